@@ -1,0 +1,8 @@
+"""MI355X (gfx950) parallel inverse fast multipole method.
+
+The compute path is the HIP library ``libifmm.so`` behind the C ABI declared
+in ``include/ifmm.h``; ``paper_1905_10602_amd.ifmm`` is a thin ctypes
+binding with the same names.  There is no CPU fallback: device calls fail
+when the library or a gfx950 device is missing.
+"""
+from .ifmm import IFMM, IfmmError, load_library, library_path  # noqa: F401

@@ -1,0 +1,218 @@
+// C ABI of the library (declared in include/ifmm.h).  Argument checking,
+// error reporting and handle life-time; the work is in engine.hip / tree.cpp.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/ifmm.h"
+#include "engine.hpp"
+
+struct ifmm_handle {
+  ifmm::Handle h;
+};
+
+namespace ifmm {
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+const char* get_error() { return g_err.c_str(); }
+
+int build_host(Handle& h, const double* pts, int64_t n, const double* w, const double* diag, double diag_scalar,
+               std::string& err) {
+  err = h.tree.build(pts, n, h.leaf_max, h.sigma);
+  if (!err.empty()) return IFMM_EINVAL;
+  h.N = n;
+  h.pts.resize((size_t)(3 * n));
+  h.w.resize((size_t)n);
+  h.diag.resize((size_t)n);
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t p = h.tree.perm[t];
+    for (int e = 0; e < 3; ++e) h.pts[3 * t + e] = pts[3 * p + e];
+    h.w[t] = w ? w[p] : 1.0;
+    h.diag[t] = diag ? diag[p] : diag_scalar;
+    if (!std::isfinite(h.w[t]) || !std::isfinite(h.diag[t])) {
+      err = "non-finite weight or diagonal entry";
+      return IFMM_ENONFINITE;
+    }
+  }
+  return IFMM_OK;
+}
+}  // namespace ifmm
+
+static ifmm_status fail(int code, const std::string& msg) {
+  ifmm::set_error(msg);
+  return (ifmm_status)code;
+}
+
+extern "C" {
+
+void ifmm_default_options(ifmm_options* opt) {
+  if (!opt) return;
+  opt->leaf_max = 64;
+  opt->cheb_order = 4;
+  opt->precision = IFMM_PREC_FP64;
+  opt->rank_cap = 0;
+  opt->max_device_bytes = 0;
+  opt->stream = nullptr;
+}
+
+ifmm_status ifmm_build(const double* points, int64_t n, const double* weights, const double* diag, double diag_scalar,
+                       int32_t kernel, double eps, int32_t sigma, const ifmm_options* opt, ifmm_handle** out) {
+  ifmm::set_error("");
+  if (!out) return fail(IFMM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!points) return fail(IFMM_EINVAL, "points is NULL");
+  if (n < 1) return fail(IFMM_EINVAL, "n must be >= 1");
+  if (kernel != IFMM_KERNEL_LAPLACE3D) return fail(IFMM_EINVAL, "unsupported kernel");
+  if (!(eps > 0.0 && eps < 1.0)) return fail(IFMM_EINVAL, "eps must lie in (0, 1)");
+  if (sigma < 3) return fail(IFMM_EINVAL, "sigma must be >= 3 (sigma <= 2 serialises every node)");
+  if (!diag && !std::isfinite(diag_scalar)) return fail(IFMM_ENONFINITE, "non-finite diag_scalar");
+  ifmm_options o;
+  ifmm_default_options(&o);
+  if (opt) o = *opt;
+  if (o.leaf_max < 1) return fail(IFMM_EINVAL, "leaf_max must be >= 1");
+  if (o.cheb_order < 2 || o.cheb_order > 6) return fail(IFMM_EINVAL, "cheb_order must lie in [2, 6]");
+  if (o.precision != IFMM_PREC_FP64) return fail(IFMM_EINVAL, "precision mode not available in this build");
+  if (o.rank_cap < 0) return fail(IFMM_EINVAL, "rank_cap must be >= 0");
+  ifmm_handle* H = new (std::nothrow) ifmm_handle();
+  if (!H) return fail(IFMM_ENOMEM, "host allocation failed");
+  ifmm::Handle& h = H->h;
+  h.eps = eps;
+  h.sigma = sigma;
+  h.leaf_max = o.leaf_max;
+  h.nc = o.cheb_order;
+  h.K = o.cheb_order * o.cheb_order * o.cheb_order;
+  h.precision = o.precision;
+  h.rank_cap = o.rank_cap;
+  h.max_bytes = o.max_device_bytes;
+  h.stream = (hipStream_t)o.stream;
+  std::string err;
+  int rc;
+  try {
+    rc = ifmm::build_host(h, points, n, weights, diag, diag_scalar, err);
+  } catch (const std::bad_alloc&) {
+    rc = IFMM_ENOMEM;
+    err = "host allocation failed";
+  }
+  if (rc) {
+    delete H;
+    return fail(rc, err);
+  }
+  *out = H;
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_factor(ifmm_handle* H) {
+  ifmm::set_error("");
+  if (!H) return fail(IFMM_EINVAL, "handle is NULL");
+  std::string err;
+  int rc;
+  try {
+    rc = ifmm::factor(H->h, err);
+  } catch (const std::bad_alloc&) {
+    rc = IFMM_ENOMEM;
+    err = "host allocation failed";
+  }
+  if (rc) return fail(rc, err);
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_solve(ifmm_handle* H, const double* rhs, double* x, int32_t nrhs, int64_t ld, int32_t on_device) {
+  ifmm::set_error("");
+  if (!H) return fail(IFMM_EINVAL, "handle is NULL");
+  if (!H->h.factored) return fail(IFMM_ESTATE, "ifmm_solve called before ifmm_factor");
+  if (!rhs || !x) return fail(IFMM_EINVAL, "rhs / x is NULL");
+  if (nrhs < 1) return fail(IFMM_EINVAL, "nrhs must be >= 1");
+  if (ld < H->h.N) return fail(IFMM_EINVAL, "ld must be >= N");
+  std::string err;
+  int rc = ifmm::solve(H->h, rhs, x, nrhs, ld, on_device ? 1 : 0, err);
+  if (rc) return fail(rc, err);
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
+  if (!H || !json || cap < 1) return fail(IFMM_EINVAL, "bad arguments");
+  const ifmm::Handle& h = H->h;
+  std::string s = "{\"N\":" + std::to_string(h.N) + ",\"depth\":" + std::to_string(h.tree.depth) +
+                  ",\"sigma\":" + std::to_string(h.sigma) + ",\"eps\":" + std::to_string(h.eps) +
+                  ",\"t_init\":" + std::to_string(h.t_init) + ",\"t_factor\":" + std::to_string(h.t_factor) +
+                  ",\"t_solve\":" + std::to_string(h.t_solve) + ",\"device_bytes\":" + std::to_string(h.dev_bytes) +
+                  ",\"store_bytes\":" + std::to_string(h.store_bytes) + ",\"top_n\":" + std::to_string(h.top_n) +
+                  ",\"t_top\":" + std::to_string(h.t_top) + ",\"far_pairs\":" + std::to_string(h.stat_far) + ",\"changed\":" + std::to_string(h.stat_changed) +
+                  ",\"levels\":[";
+  for (int l = 2; l <= h.tree.depth; ++l) {
+    const ifmm::Level& T = h.tree.levels[l];
+    long long rs = 0, rm = 0, ns = 0, nm = 0;
+    if ((int)h.lv.size() > l) {
+      const ifmm::DevLevel& L = h.lv[l];
+      for (size_t i = 0; i < L.r.size(); ++i) { rs += L.r[i]; rm = std::max<long long>(rm, L.r[i]); }
+      for (size_t i = 0; i < L.n.size(); ++i) { ns += L.n[i]; nm = std::max<long long>(nm, L.n[i]); }
+    }
+    s += std::string(l > 2 ? "," : "") + "{\"level\":" + std::to_string(l) + ",\"nodes\":" + std::to_string(T.n) +
+         ",\"colours\":" + std::to_string(T.ncolour) + ",\"rank_sum\":" + std::to_string(rs) +
+         ",\"rank_max\":" + std::to_string(rm) + ",\"n_sum\":" + std::to_string(ns) + ",\"n_max\":" + std::to_string(nm) +
+         ",\"t_setup\":" + std::to_string((int)h.t_level_setup.size() > l ? h.t_level_setup[l] : 0.0) +
+         ",\"t_elim\":" + std::to_string((int)h.t_level_elim.size() > l ? h.t_level_elim[l] : 0.0) + "}";
+  }
+  s += "]}";
+  std::snprintf(json, (size_t)cap, "%s", s.c_str());
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_tree_depth(const ifmm_handle* H, int32_t* depth) {
+  if (!H || !depth) return fail(IFMM_EINVAL, "bad arguments");
+  *depth = H->h.tree.depth;
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_tree_perm(const ifmm_handle* H, int64_t* perm) {
+  if (!H || !perm) return fail(IFMM_EINVAL, "bad arguments");
+  std::memcpy(perm, H->h.tree.perm.data(), H->h.tree.perm.size() * sizeof(int64_t));
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_tree_level(const ifmm_handle* H, int32_t level, int32_t* nnodes, int32_t* coords, int32_t* parent,
+                            int32_t* colour, int32_t* ncolour) {
+  if (!H || !nnodes) return fail(IFMM_EINVAL, "bad arguments");
+  const ifmm::Tree& T = H->h.tree;
+  if (level < 2 || level > T.depth) return fail(IFMM_EINVAL, "level out of range");
+  const ifmm::Level& L = T.levels[level];
+  *nnodes = L.n;
+  if (coords) std::memcpy(coords, L.coord.data(), L.coord.size() * 4);
+  if (parent) std::memcpy(parent, L.parent.data(), L.parent.size() * 4);
+  if (colour) std::memcpy(colour, L.colour.data(), L.colour.size() * 4);
+  if (ncolour) *ncolour = L.ncolour;
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_tree_lists(const ifmm_handle* H, int32_t level, int32_t which, int32_t* ptr, int32_t* idx) {
+  if (!H || !ptr || (which != 0 && which != 1)) return fail(IFMM_EINVAL, "bad arguments");
+  const ifmm::Tree& T = H->h.tree;
+  if (level < 2 || level > T.depth) return fail(IFMM_EINVAL, "level out of range");
+  const ifmm::Level& L = T.levels[level];
+  const std::vector<int32_t>& p = which ? L.il_ptr : L.nbr_ptr;
+  const std::vector<int32_t>& v = which ? L.il : L.nbr;
+  std::memcpy(ptr, p.data(), p.size() * 4);
+  if (idx) std::memcpy(idx, v.data(), v.size() * 4);
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_ranks(const ifmm_handle* H, int32_t level, int32_t* ranks) {
+  if (!H || !ranks) return fail(IFMM_EINVAL, "bad arguments");
+  const ifmm::Handle& h = H->h;
+  if (!h.factored) return fail(IFMM_ESTATE, "no factorisation");
+  if (level < 2 || level > h.tree.depth) return fail(IFMM_EINVAL, "level out of range");
+  std::memcpy(ranks, h.lv[level].r.data(), h.lv[level].r.size() * 4);
+  return IFMM_OK;
+}
+
+const char* ifmm_last_error(void) { return ifmm::get_error(); }
+
+void ifmm_destroy(ifmm_handle* H) {
+  if (!H) return;
+  ifmm::release(H->h);
+  delete H;
+}
+
+}  // extern "C"

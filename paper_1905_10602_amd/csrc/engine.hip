@@ -1,0 +1,881 @@
+// Host scheduler of the IFMM on one gfx950 device.
+//
+// Factorisation (Alg. 1 with the colour loops of Sec. 3.2 / 3.3):
+//   for every level, leaves first:
+//     set up the level (leaf operators, or aggregation of the finer level),
+//     initial rank reduction (square pivots), then for every colour:
+//       phase A  gather -> LU -> X = D^-1 U -> Schur update / far fill-in ->
+//                Gram -> Jacobi eigen-decomposition -> (host reads ranks) ->
+//                new bases -> projection of the far fill-in
+//       phase B  basis change pushed into the M2L blocks of the interaction
+//                lists and into M2M / L2L (owner-computes, no atomics)
+//   dense LU of the level-2 M2L system.
+// Solve (Alg. 2): per level, colours ascending (up) then descending (down).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "engine.hpp"
+#include "kernels.hpp"
+
+namespace ifmm {
+
+#define HIPCHK(x)                                                                   \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) {                                                         \
+      err = std::string(#x) + " failed: " + hipGetErrorString(e_);                  \
+      return -3;                                                                    \
+    }                                                                               \
+  } while (0)
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------ device memory
+template <class T>
+static int dalloc(Handle& h, T** p, int64_t count, std::string& err) {
+  *p = nullptr;
+  if (count <= 0) return 0;
+  const int64_t bytes = count * (int64_t)sizeof(T);
+  if (h.max_bytes > 0 && h.dev_bytes + bytes > h.max_bytes) {
+    err = "device memory limit exceeded (" + std::to_string(h.dev_bytes + bytes) + " > " +
+          std::to_string(h.max_bytes) + " bytes)";
+    return -2;
+  }
+  hipError_t e = hipMalloc((void**)p, (size_t)bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    err = "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
+    return -2;
+  }
+  h.dev_bytes += bytes;
+  h.allocs.push_back({(void*)*p, bytes});
+  return 0;
+}
+
+static void dfree(Handle& h, void* p) {
+  if (!p) return;
+  for (size_t k = 0; k < h.allocs.size(); ++k)
+    if (h.allocs[k].first == p) {
+      h.dev_bytes -= h.allocs[k].second;
+      h.allocs.erase(h.allocs.begin() + (long)k);
+      break;
+    }
+  (void)hipFree(p);
+}
+
+template <class T>
+static int upload(Handle& h, T** p, const std::vector<T>& v, std::string& err) {
+  int rc = dalloc(h, p, (int64_t)std::max<size_t>(v.size(), 1), err);
+  if (rc) return rc;
+  if (!v.empty()) {
+    HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h.stream));
+    HIPCHK(hipStreamSynchronize(h.stream));  // v may be a temporary
+  }
+  return 0;
+}
+
+// bump allocator for the persistent factor store
+static int store_take(Handle& h, int64_t doubles, double** out, std::string& err) {
+  doubles = (doubles + 31) & ~31LL;  // 256-byte alignment
+  if (doubles > h.store_left) {
+    const int64_t chunk = std::max<int64_t>(doubles, (int64_t)1 << 26);  // >= 512 MiB
+    double* p = nullptr;
+    int rc = dalloc(h, &p, chunk, err);
+    if (rc) return rc;
+    h.store_chunks.push_back(p);
+    h.store_cur = p;
+    h.store_left = chunk;
+  }
+  *out = h.store_cur;
+  h.store_cur += doubles;
+  h.store_left -= doubles;
+  h.store_bytes += doubles * 8;
+  return 0;
+}
+
+// growable scratch / meta buffers
+static int ensure(Handle& h, void** buf, int64_t* cap, int64_t bytes, std::string& err) {
+  if (bytes <= *cap) return 0;
+  HIPCHK(hipStreamSynchronize(h.stream));
+  const int64_t nb = std::max<int64_t>(bytes, (*cap) * 3 / 2);
+  dfree(h, *buf);
+  *buf = nullptr;
+  *cap = 0;
+  char* p = nullptr;
+  int rc = dalloc(h, &p, nb, err);
+  if (rc) return rc;
+  *buf = p;
+  *cap = nb;
+  return 0;
+}
+
+// ------------------------------------------------------------------ level set-up
+static LevelView view_of(DevLevel& L) {
+  LevelView V;
+  V.arena = L.arena;
+  V.n = L.d_n; V.r = L.d_r; V.rc = L.d_rc; V.coord = L.d_coord;
+  V.near_ptr = L.d_near_ptr; V.near_idx = L.d_near_idx; V.il_ptr = L.d_il_ptr; V.il_idx = L.d_il_idx;
+  V.near_off = L.d_near_off; V.il_off = L.d_il_off; V.p2m_off = L.d_p2m_off; V.l2p_off = L.d_l2p_off;
+  V.sig_off = L.d_sig_off; V.m2m_off = L.d_m2m_off; V.l2l_off = L.d_l2l_off;
+  V.cp2m_off = L.d_cp2m_off; V.cl2p_off = L.d_cl2p_off; V.T_off = L.d_T_off; V.S_off = L.d_S_off;
+  V.chg = L.d_chg;
+  return V;
+}
+
+// Allocates the working storage of level l for the node sizes L.n (exact).
+static int setup_level(Handle& h, int l, std::string& err) {
+  const Level& T = h.tree.levels[l];
+  DevLevel& L = h.lv[l];
+  const int K = h.K;
+  const int32_t nn = T.n;
+  L.nn = nn;
+  L.r.assign(nn, 0);
+  L.rc.resize(nn);
+  int32_t rcmax = 0, nmax = 0;
+  for (int32_t i = 0; i < nn; ++i) {
+    L.rc[i] = h.rank_cap > 0 ? std::min(L.n[i], h.rank_cap) : L.n[i];
+    rcmax = std::max(rcmax, L.rc[i]);
+    nmax = std::max(nmax, L.n[i]);
+  }
+  L.rcmax = rcmax;
+  L.nmax = nmax;
+  if (nmax > 2 * JAC_MAXPAIR) {
+    err = "level " + std::to_string(l) + " has a node with " + std::to_string(nmax) +
+          " unknowns, above the supported 2048 (lower eps or set rank_cap)";
+    return -1;
+  }
+  L.near_ptr.assign(1, 0);
+  L.near_idx.clear();
+  L.slot_row.clear();
+  for (int32_t i = 0; i < nn; ++i) {
+    L.near_idx.push_back(i);
+    L.slot_row.push_back(i);
+    for (int s = T.nbr_ptr[i]; s < T.nbr_ptr[i + 1]; ++s) {
+      L.near_idx.push_back(T.nbr[s]);
+      L.slot_row.push_back(i);
+    }
+    L.near_ptr.push_back((int32_t)L.near_idx.size());
+  }
+  int64_t off = 0;
+  auto take = [&](int64_t cnt) {
+    const int64_t o = off;
+    off += (cnt + 3) & ~3LL;
+    return o;
+  };
+  L.near_off.resize(L.near_idx.size());
+  for (int32_t i = 0; i < nn; ++i)
+    for (int s = L.near_ptr[i]; s < L.near_ptr[i + 1]; ++s) L.near_off[s] = take((int64_t)L.n[i] * L.n[L.near_idx[s]]);
+  L.il_off.resize(T.il.size());
+  for (int32_t i = 0; i < nn; ++i)
+    for (int s = T.il_ptr[i]; s < T.il_ptr[i + 1]; ++s) L.il_off[s] = take((int64_t)L.rc[i] * L.rc[T.il[s]]);
+  L.p2m_off.resize(nn); L.l2p_off.resize(nn); L.sig_off.resize(nn); L.m2m_off.resize(nn); L.l2l_off.resize(nn);
+  L.cp2m_off.resize(nn); L.cl2p_off.resize(nn); L.T_off.resize(nn); L.S_off.resize(nn);
+  for (int32_t i = 0; i < nn; ++i) {
+    const int64_t n = L.n[i], rc = L.rc[i];
+    L.p2m_off[i] = take(rc * n);
+    L.l2p_off[i] = take(n * rc);
+    L.sig_off[i] = take(2 * rc);
+    L.m2m_off[i] = take(K * rc);
+    L.l2l_off[i] = take(rc * K);
+    L.cp2m_off[i] = take(K * n);
+    L.cl2p_off[i] = take(n * K);
+    L.T_off[i] = take(K * rc);
+    L.S_off[i] = take(rc * K);
+  }
+  L.arena_doubles = off;
+  int rc;
+  if ((rc = dalloc(h, &L.arena, std::max<int64_t>(off, 1), err))) return rc;
+  HIPCHK(hipMemsetAsync(L.arena, 0, (size_t)std::max<int64_t>(off, 1) * 8, h.stream));
+  if ((rc = upload(h, &L.d_n, L.n, err))) return rc;
+  if ((rc = upload(h, &L.d_r, L.r, err))) return rc;
+  if ((rc = upload(h, &L.d_rc, L.rc, err))) return rc;
+  if ((rc = upload(h, &L.d_coord, T.coord, err))) return rc;
+  if ((rc = upload(h, &L.d_near_ptr, L.near_ptr, err))) return rc;
+  if ((rc = upload(h, &L.d_near_idx, L.near_idx, err))) return rc;
+  if ((rc = upload(h, &L.d_slot_row, L.slot_row, err))) return rc;
+  if ((rc = upload(h, &L.d_il_ptr, T.il_ptr, err))) return rc;
+  if ((rc = upload(h, &L.d_il_idx, T.il, err))) return rc;
+  if ((rc = upload(h, &L.d_near_off, L.near_off, err))) return rc;
+  if ((rc = upload(h, &L.d_il_off, L.il_off, err))) return rc;
+  if ((rc = upload(h, &L.d_p2m_off, L.p2m_off, err))) return rc;
+  if ((rc = upload(h, &L.d_l2p_off, L.l2p_off, err))) return rc;
+  if ((rc = upload(h, &L.d_sig_off, L.sig_off, err))) return rc;
+  if ((rc = upload(h, &L.d_m2m_off, L.m2m_off, err))) return rc;
+  if ((rc = upload(h, &L.d_l2l_off, L.l2l_off, err))) return rc;
+  if ((rc = upload(h, &L.d_cp2m_off, L.cp2m_off, err))) return rc;
+  if ((rc = upload(h, &L.d_cl2p_off, L.cl2p_off, err))) return rc;
+  if ((rc = upload(h, &L.d_T_off, L.T_off, err))) return rc;
+  if ((rc = upload(h, &L.d_S_off, L.S_off, err))) return rc;
+  std::vector<int32_t> minus(nn, -1);
+  if ((rc = upload(h, &L.d_chg, minus, err))) return rc;
+  if (l > 2) {
+    if ((rc = upload(h, &L.d_parent, T.parent, err))) return rc;
+  }
+  if (l < h.tree.depth) {
+    if ((rc = upload(h, &L.d_child_ptr, T.child_ptr, err))) return rc;
+    if ((rc = upload(h, &L.d_child, T.child, err))) return rc;
+  }
+  return 0;
+}
+
+// Frees the working storage of a level (the factor records stay).
+static void release_level_work(Handle& h, int l) {
+  DevLevel& L = h.lv[l];
+  void* ptrs[] = {L.arena, L.d_near_ptr, L.d_near_idx, L.d_slot_row, L.d_il_ptr, L.d_il_idx, L.d_near_off,
+                  L.d_il_off, L.d_p2m_off, L.d_l2p_off, L.d_sig_off, L.d_m2m_off, L.d_l2l_off, L.d_cp2m_off,
+                  L.d_cl2p_off, L.d_T_off, L.d_S_off, L.d_chg, L.d_rc, L.d_coord};
+  for (void* p : ptrs) dfree(h, p);
+  L.arena = nullptr;
+  L.d_near_ptr = L.d_near_idx = L.d_slot_row = L.d_il_ptr = L.d_il_idx = nullptr;
+  L.d_near_off = L.d_il_off = L.d_p2m_off = L.d_l2p_off = L.d_sig_off = L.d_m2m_off = L.d_l2l_off = nullptr;
+  L.d_cp2m_off = L.d_cl2p_off = L.d_T_off = L.d_S_off = nullptr;
+  L.d_chg = nullptr;
+  L.d_rc = nullptr;
+  L.d_coord = nullptr;
+}
+
+// Initial rank reduction of every node of level l (square pivots, far-field
+// weighted), then the reduced M2L / M2M / L2L of the level.
+static int reduce_level(Handle& h, int l, std::string& err) {
+  DevLevel& L = h.lv[l];
+  const int K = h.K;
+  const int32_t nn = L.nn;
+  std::vector<int64_t> woff(nn);
+  int64_t wtot = 0;
+  for (int32_t i = 0; i < nn; ++i) {
+    const int64_t n = L.n[i];
+    woff[i] = wtot;
+    wtot += 6 * n * n + (int64_t)K * n + 2 * n;
+    wtot = (wtot + 3) & ~3LL;
+  }
+  int64_t ttot = 0;
+  std::vector<int64_t> toff(nn);
+  for (int32_t i = 0; i < nn; ++i) {
+    toff[i] = ttot;
+    ttot += (int64_t)K * std::max(L.rcmax, 1);
+  }
+  int rc;
+  if ((rc = ensure(h, (void**)&h.scratch, &h.scratch_bytes, std::max(wtot, ttot) * 8 + 64, err))) return rc;
+  double* work = h.scratch;
+  std::vector<EigTask> tasks(2 * (size_t)nn);
+  for (int32_t i = 0; i < nn; ++i) {
+    const int64_t n = L.n[i];
+    double* b = work + woff[i];
+    double* gs = b;
+    double* gt = b + n * n;
+    double* vs = b + 2 * n * n + (int64_t)K * n;
+    double* vt = vs + n * n;
+    double* ws = vt + n * n;
+    double* wt = ws + n * n;
+    double* ls = wt + n * n;
+    double* lt = ls + n;
+    tasks[2 * i] = {gs, vs, ws, ls, (int32_t)n, 0};
+    tasks[2 * i + 1] = {gt, vt, wt, lt, (int32_t)n, 0};
+  }
+  const int64_t meta_bytes = (int64_t)(tasks.size() * sizeof(EigTask) + nn * sizeof(int64_t) + 2 * nn * sizeof(int32_t) + 1024);
+  if ((rc = ensure(h, (void**)&h.meta, &h.meta_bytes, meta_bytes, err))) return rc;
+  char* m = (char*)h.meta;
+  EigTask* d_tasks = (EigTask*)m;
+  int64_t* d_woff = (int64_t*)(m + ((tasks.size() * sizeof(EigTask) + 255) & ~(size_t)255));
+  int32_t* d_cnt = (int32_t*)((char*)d_woff + ((nn * sizeof(int64_t) + 255) & ~(size_t)255));
+  HIPCHK(hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
+  HIPCHK(hipMemcpyAsync(d_woff, woff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, h.stream));
+  LevelView V = view_of(L);
+  const double* G = h.weights_G[l];
+  if (nn > 0) {
+    hipLaunchKernelGGL(k_reduce_gram, dim3(nn), dim3(NT), 0, h.stream, V, K, G, work, d_woff);
+    hipLaunchKernelGGL(k_eig, dim3(2 * nn), dim3(NT), 0, h.stream, d_tasks, h.eps * h.eps, d_cnt);
+  }
+  HIPCHK(hipGetLastError());
+  std::vector<int32_t> cnt(2 * (size_t)nn);
+  if (nn > 0) HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * 4, hipMemcpyDeviceToHost, h.stream));
+  HIPCHK(hipStreamSynchronize(h.stream));
+  for (int32_t i = 0; i < nn; ++i) {
+    int r = std::max(cnt[2 * i], cnt[2 * i + 1]);
+    r = std::min(r, L.rc[i]);
+    L.r[i] = r;
+  }
+  HIPCHK(hipMemcpyAsync(L.d_r, L.r.data(), nn * 4, hipMemcpyHostToDevice, h.stream));
+  const double side = 2.0 * h.tree.H / (double)(1LL << l);
+  if (nn > 0) {
+    hipLaunchKernelGGL(k_reduce_basis, dim3(nn), dim3(NT), 0, h.stream, V, K, work, d_woff, h.d_m2m8, l > 2 ? 1 : 0);
+    HIPCHK(hipGetLastError());
+  }
+  // M2L of the interaction pairs (needs T of every node: separate launch)
+  HIPCHK(hipStreamSynchronize(h.stream));
+  std::vector<int64_t> toff2(nn);
+  for (int32_t i = 0; i < nn; ++i) toff2[i] = (int64_t)i * K * std::max(L.rcmax, 1);
+  if ((rc = ensure(h, (void**)&h.meta, &h.meta_bytes, (int64_t)nn * 8 + 256, err))) return rc;
+  int64_t* d_toff = (int64_t*)h.meta;
+  HIPCHK(hipMemcpyAsync(d_toff, toff2.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, h.stream));
+  if ((rc = ensure(h, (void**)&h.scratch, &h.scratch_bytes, (int64_t)nn * K * std::max(L.rcmax, 1) * 8 + 64, err)))
+    return rc;
+  if (nn > 0) {
+    hipLaunchKernelGGL(k_reduce_m2l, dim3(nn), dim3(NT), 0, h.stream, V, K, h.d_unit, 1.0 / side, h.scratch, d_toff);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(h.stream));
+  return 0;
+}
+
+// ------------------------------------------------------------------ one colour
+static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
+  const Level& T = h.tree.levels[l];
+  DevLevel& L = h.lv[l];
+  const int K = h.K;
+  const int g0 = T.grp_ptr[c], g1 = T.grp_ptr[c + 1];
+  const int nrec = g1 - g0;
+  if (nrec == 0) return 0;
+  // ---- records, neighbour entries, far pairs, changed nodes (host; sizes are known)
+  std::vector<ElimRec> recs(nrec);
+  std::vector<ElimNbr> nbrs;
+  std::vector<int32_t> far_idx;
+  std::vector<FarPair> far;
+  std::vector<Changed> chg;
+  std::vector<FarRef> refs;
+  std::vector<SchurTask> tasks;
+  int64_t sc = 0;  // scratch doubles
+  auto stake = [&](int64_t cnt) {
+    const int64_t o = sc;
+    sc += (std::max<int64_t>(cnt, 1) + 31) & ~31LL;
+    return o;
+  };
+  std::vector<int64_t> x_off(nrec);
+  std::vector<std::vector<int64_t>> far_off_F, far_off_D;
+  struct ChgOff { int64_t gs, gt, vs, vt, ws, wt, ls, lt, T, S, tmp; };
+  std::vector<ChgOff> coff;
+  const int nbase = (int)L.nbrs.size();
+  for (int k = 0; k < nrec; ++k) {
+    const int i = T.grp[g0 + k];
+    ElimRec& R = recs[k];
+    R.node = i;
+    R.n = L.n[i];
+    R.r = L.r[i];
+    R.d = R.n + R.r;
+    R.nnb = T.nbr_ptr[i + 1] - T.nbr_ptr[i];
+    R.nb_begin = (int)nbrs.size();
+    int off = 0;
+    for (int s = T.nbr_ptr[i]; s < T.nbr_ptr[i + 1]; ++s) {
+      const int p = T.nbr[s];
+      ElimNbr B;
+      B.p = p;
+      B.elim = T.colour[p] < c ? 1 : 0;
+      B.m = B.elim ? L.r[p] : L.n[p];
+      B.off = off;
+      off += B.m;
+      // block (p, i) in p's near list, block (i, p) in i's
+      B.blk_pi = -1;
+      for (int t = L.near_ptr[p]; t < L.near_ptr[p + 1]; ++t)
+        if (L.near_idx[t] == i) B.blk_pi = L.near_off[t];
+      B.blk_ip = -1;
+      for (int t = L.near_ptr[i]; t < L.near_ptr[i + 1]; ++t)
+        if (L.near_idx[t] == p) B.blk_ip = L.near_off[t];
+      nbrs.push_back(B);
+    }
+    R.M = off;
+    R.far_base = (int)far_idx.size();
+    x_off[k] = stake((int64_t)R.d * (R.M + R.r));
+    // persistent factor data
+    int rc;
+    double* p;
+    if ((rc = store_take(h, (int64_t)R.d * R.d, &R.lu, err))) return rc;
+    if ((rc = store_take(h, (R.d + 1) / 2 + 1, &p, err))) return rc;
+    R.piv = (int32_t*)p;
+    if ((rc = store_take(h, (int64_t)R.M * R.n, &R.L, err))) return rc;
+    if ((rc = store_take(h, (int64_t)R.n * R.M, &R.U, err))) return rc;
+    R.wv = L.wv_total;
+    L.wv_total += R.d;
+    // far pairs (a, b) with dist(p_a, p_b) >= 2
+    const ElimNbr* E = &nbrs[R.nb_begin];
+    for (int a = 0; a < R.nnb; ++a)
+      for (int b = 0; b < R.nnb; ++b) {
+        if (T.dist(E[a].p, E[b].p) <= 1) {
+          far_idx.push_back(-1);
+          continue;
+        }
+        far_idx.push_back((int32_t)far.size());
+        FarPair F;
+        F.rec = k; F.a = a; F.b = b;
+        F.direct = (E[a].elim && E[b].elim) ? 1 : 0;
+        F.F = nullptr; F.D = nullptr;
+        // M2L block (p_a, p_b): p_b is in the interaction list of p_a
+        const int pa = E[a].p, pb = E[b].p;
+        int lo = T.il_ptr[pa], hi = T.il_ptr[pa + 1] - 1, found = -1;
+        while (lo <= hi) {
+          const int mid = (lo + hi) >> 1;
+          if (T.il[mid] == pb) { found = mid; break; }
+          if (T.il[mid] < pb) lo = mid + 1; else hi = mid - 1;
+        }
+        if (found < 0) {
+          err = "internal: far neighbour pair is not in the interaction list";
+          return -1;
+        }
+        F.dst = L.il_off[found];
+        F.dst_ld = L.rc[pa];
+        F.pad = 0;
+        far.push_back(F);
+      }
+    // schur tasks: one per neighbour row block plus the row R_z_i
+    for (int a = 0; a <= R.nnb; ++a) tasks.push_back({k, a});
+  }
+  // scratch for far pairs
+  std::vector<int64_t> fF(far.size()), fD(far.size());
+  for (size_t f = 0; f < far.size(); ++f) {
+    const ElimRec& R = recs[far[f].rec];
+    const int ma = nbrs[R.nb_begin + far[f].a].m, mb = nbrs[R.nb_begin + far[f].b].m;
+    fF[f] = stake((int64_t)ma * mb);
+    fD[f] = stake((int64_t)ma * mb);
+  }
+  // changed nodes: non-eliminated neighbours with at least one far partner
+  for (int k = 0; k < nrec; ++k) {
+    const ElimRec& R = recs[k];
+    for (int a = 0; a < R.nnb; ++a) {
+      const ElimNbr& A = nbrs[R.nb_begin + a];
+      if (A.elim) continue;
+      const int fb = (int)refs.size();
+      for (int b = 0; b < R.nnb; ++b) {
+        const int ab = far_idx[R.far_base + a * R.nnb + b];
+        if (ab < 0) continue;
+        const int ba = far_idx[R.far_base + b * R.nnb + a];
+        refs.push_back({nbrs[R.nb_begin + b].p, ab, ba, 0});
+      }
+      if ((int)refs.size() == fb) continue;
+      Changed C;
+      std::memset(&C, 0, sizeof(C));
+      C.p = A.p; C.rec = k; C.a = a; C.n = L.n[A.p]; C.r = L.r[A.p]; C.rnew = 0;
+      C.far_begin = fb; C.far_count = (int)refs.size() - fb;
+      const int64_t n = C.n;
+      const int64_t big = std::max<int64_t>(std::max<int64_t>(L.rcmax, K), n);
+      ChgOff o;
+      o.gs = stake(n * n); o.gt = stake(n * n); o.vs = stake(n * n); o.vt = stake(n * n);
+      o.ws = stake(n * n); o.wt = stake(n * n); o.ls = stake(n); o.lt = stake(n);
+      o.T = stake((int64_t)std::max(C.r, 1) * n);
+      o.S = stake(n * std::max(C.r, 1));
+      o.tmp = stake(big * std::max<int64_t>(std::max<int64_t>(L.rc[A.p], n), 1));
+      coff.push_back(o);
+      chg.push_back(C);
+    }
+  }
+  int rc;
+  if ((rc = ensure(h, (void**)&h.scratch, &h.scratch_bytes, sc * 8 + 256, err))) return rc;
+  double* S0 = h.scratch;
+  for (int k = 0; k < nrec; ++k) recs[k].X = S0 + x_off[k];
+  for (size_t f = 0; f < far.size(); ++f) { far[f].F = S0 + fF[f]; far[f].D = S0 + fD[f]; }
+  std::vector<EigTask> etasks;
+  for (size_t k = 0; k < chg.size(); ++k) {
+    Changed& C = chg[k];
+    const ChgOff& o = coff[k];
+    C.gs = S0 + o.gs; C.gt = S0 + o.gt; C.vs = S0 + o.vs; C.vt = S0 + o.vt; C.ws = S0 + o.ws; C.wt = S0 + o.wt;
+    C.ls = S0 + o.ls; C.lt = S0 + o.lt; C.T = S0 + o.T; C.S = S0 + o.S; C.tmp = S0 + o.tmp;
+    etasks.push_back({C.gs, C.vs, C.ws, C.ls, C.n, 0});
+    etasks.push_back({C.gt, C.vt, C.wt, C.lt, C.n, 0});
+  }
+  // ---- pack the tables into the meta buffer
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t o_recs = 0;
+  const size_t o_nbrs = o_recs + al(recs.size() * sizeof(ElimRec));
+  const size_t o_tasks = o_nbrs + al(std::max<size_t>(nbrs.size(), 1) * sizeof(ElimNbr));
+  const size_t o_fidx = o_tasks + al(tasks.size() * sizeof(SchurTask));
+  const size_t o_far = o_fidx + al(std::max<size_t>(far_idx.size(), 1) * 4);
+  const size_t o_chg = o_far + al(std::max<size_t>(far.size(), 1) * sizeof(FarPair));
+  const size_t o_refs = o_chg + al(std::max<size_t>(chg.size(), 1) * sizeof(Changed));
+  const size_t o_et = o_refs + al(std::max<size_t>(refs.size(), 1) * sizeof(FarRef));
+  const size_t o_cnt = o_et + al(std::max<size_t>(etasks.size(), 1) * sizeof(EigTask));
+  const size_t o_info = o_cnt + al(std::max<size_t>(etasks.size(), 1) * 4);
+  const size_t total = o_info + al((size_t)nrec * 4);
+  if ((rc = ensure(h, (void**)&h.meta, &h.meta_bytes, (int64_t)total, err))) return rc;
+  char* M = (char*)h.meta;
+  h.host_meta.assign(total, 0);
+  char* Hm = h.host_meta.data();
+  std::memcpy(Hm + o_recs, recs.data(), recs.size() * sizeof(ElimRec));
+  if (!nbrs.empty()) std::memcpy(Hm + o_nbrs, nbrs.data(), nbrs.size() * sizeof(ElimNbr));
+  std::memcpy(Hm + o_tasks, tasks.data(), tasks.size() * sizeof(SchurTask));
+  if (!far_idx.empty()) std::memcpy(Hm + o_fidx, far_idx.data(), far_idx.size() * 4);
+  if (!far.empty()) std::memcpy(Hm + o_far, far.data(), far.size() * sizeof(FarPair));
+  if (!chg.empty()) std::memcpy(Hm + o_chg, chg.data(), chg.size() * sizeof(Changed));
+  if (!refs.empty()) std::memcpy(Hm + o_refs, refs.data(), refs.size() * sizeof(FarRef));
+  if (!etasks.empty()) std::memcpy(Hm + o_et, etasks.data(), etasks.size() * sizeof(EigTask));
+  HIPCHK(hipMemcpyAsync(M, Hm, o_cnt, hipMemcpyHostToDevice, h.stream));
+  const ElimRec* d_recs = (const ElimRec*)(M + o_recs);
+  const ElimNbr* d_nbrs = (const ElimNbr*)(M + o_nbrs);
+  const SchurTask* d_tasks = (const SchurTask*)(M + o_tasks);
+  const int32_t* d_fidx = (const int32_t*)(M + o_fidx);
+  const FarPair* d_far = (const FarPair*)(M + o_far);
+  Changed* d_chg = (Changed*)(M + o_chg);
+  const FarRef* d_refs = (const FarRef*)(M + o_refs);
+  const EigTask* d_et = (const EigTask*)(M + o_et);
+  int32_t* d_cnt = (int32_t*)(M + o_cnt);
+  int32_t* d_info = (int32_t*)(M + o_info);
+  LevelView V = view_of(L);
+  const int nchg = (int)chg.size();
+  // ---- phase A
+  hipLaunchKernelGGL(k_gather, dim3(nrec), dim3(NT), 0, h.stream, V, d_recs, d_nbrs);
+  hipLaunchKernelGGL(k_getrf, dim3(nrec), dim3(NT), 0, h.stream, d_recs, d_info);
+  hipLaunchKernelGGL(k_xsolve, dim3(nrec), dim3(NT), 0, h.stream, d_recs);
+  hipLaunchKernelGGL(k_schur, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks, d_fidx,
+                     d_far);
+  if (nchg) {
+    hipLaunchKernelGGL(k_set_chg, dim3((nchg + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_chg, d_chg, nchg, 0);
+    hipLaunchKernelGGL(k_gram, dim3(2 * nchg), dim3(NT), 0, h.stream, V, d_chg, d_refs, d_far, d_nbrs, d_recs);
+    hipLaunchKernelGGL(k_eig, dim3(2 * nchg), dim3(NT), 0, h.stream, d_et, h.eps * h.eps, d_cnt);
+  }
+  HIPCHK(hipGetLastError());
+  std::vector<int32_t> cnt(2 * (size_t)nchg), info(nrec);
+  if (nchg) HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * 4, hipMemcpyDeviceToHost, h.stream));
+  HIPCHK(hipMemcpyAsync(info.data(), d_info, nrec * 4, hipMemcpyDeviceToHost, h.stream));
+  HIPCHK(hipStreamSynchronize(h.stream));
+  for (int k = 0; k < nrec; ++k)
+    if (info[k]) {
+      err = "singular pivot block at level " + std::to_string(l) + ", node " + std::to_string(recs[k].node);
+      return -4;
+    }
+  if (nchg) {
+    for (int k = 0; k < nchg; ++k) {
+      Changed& C = chg[k];
+      int rn = std::max(cnt[2 * k], cnt[2 * k + 1]);
+      rn = std::min(rn, std::min(C.n, L.rc[C.p]));
+      C.rnew = rn;
+    }
+    HIPCHK(hipMemcpyAsync(d_chg, chg.data(), chg.size() * sizeof(Changed), hipMemcpyHostToDevice, h.stream));
+    hipLaunchKernelGGL(k_basis, dim3(nchg), dim3(NT), 0, h.stream, V, d_chg);
+  }
+  if (!far.empty())
+    hipLaunchKernelGGL(k_project, dim3((unsigned)far.size()), dim3(NT), 0, h.stream, V, d_far, d_recs, d_nbrs, d_chg);
+  // ---- phase B
+  if (nchg) {
+    hipLaunchKernelGGL(k_phase_b, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far, l > 2 ? 1 : 0);
+    hipLaunchKernelGGL(k_set_rank, dim3((nchg + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_r, d_chg, nchg);
+    hipLaunchKernelGGL(k_set_chg, dim3((nchg + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_chg, d_chg, nchg, 1);
+    for (const Changed& C : chg) L.r[C.p] = C.rnew;
+  }
+  HIPCHK(hipGetLastError());
+  // keep the records for the solve (neighbour entries rebased on the level table)
+  for (ElimRec R : recs) {
+    R.nb_begin += nbase;
+    R.X = nullptr;
+    L.recs.push_back(R);
+  }
+  L.nbrs.insert(L.nbrs.end(), nbrs.begin(), nbrs.end());
+  L.col_ptr.push_back((int32_t)L.recs.size());
+  h.stat_far += (int64_t)far.size();
+  h.stat_changed += nchg;
+  // the host tables above are uploaded asynchronously: wait before they go away
+  HIPCHK(hipStreamSynchronize(h.stream));
+  return 0;
+}
+
+// ------------------------------------------------------------------ factor
+static int init_leaf_level(Handle& h, std::string& err) {
+  const int l = h.tree.depth;
+  const Level& T = h.tree.levels[l];
+  DevLevel& L = h.lv[l];
+  L.n.resize(T.n);
+  for (int32_t i = 0; i < T.n; ++i) L.n[i] = (int32_t)(T.pt_end[i] - T.pt_begin[i]);
+  int rc;
+  if ((rc = setup_level(h, l, err))) return rc;
+  LevelView V = view_of(L);
+  const double side = 2.0 * h.tree.H / (double)(1LL << l);
+  hipLaunchKernelGGL(k_leaf_cheb, dim3(T.n), dim3(NT), 0, h.stream, V, h.nc, h.d_pts, h.d_w, h.d_pt_begin, h.d_lo,
+                     side);
+  hipLaunchKernelGGL(k_p2p, dim3((unsigned)L.near_idx.size()), dim3(NT), 0, h.stream, V, L.d_slot_row, h.d_pts, h.d_w,
+                     h.d_diag, h.d_pt_begin);
+  HIPCHK(hipGetLastError());
+  return reduce_level(h, l, err);
+}
+
+static int aggregate_level(Handle& h, int l, std::string& err) {
+  // level l (eliminated) -> level l - 1
+  const Level& C = h.tree.levels[l - 1];
+  DevLevel& F = h.lv[l];
+  DevLevel& P = h.lv[l - 1];
+  P.n.assign(C.n, 0);
+  for (int32_t q = 0; q < C.n; ++q)
+    for (int s = C.child_ptr[q]; s < C.child_ptr[q + 1]; ++s) P.n[q] += F.r[C.child[s]];
+  int rc;
+  if ((rc = setup_level(h, l - 1, err))) return rc;
+  LevelView VC = view_of(P), VF = view_of(F);
+  hipLaunchKernelGGL(k_agg_cheb, dim3(C.n), dim3(NT), 0, h.stream, VC, VF, h.K, P.d_child_ptr, P.d_child);
+  hipLaunchKernelGGL(k_agg_near, dim3((unsigned)P.near_idx.size()), dim3(NT), 0, h.stream, VC, VF, P.d_slot_row,
+                     P.d_child_ptr, P.d_child);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h.stream));
+  release_level_work(h, l);
+  return reduce_level(h, l - 1, err);
+}
+
+static int finish_level(Handle& h, int l, std::string& err) {
+  DevLevel& L = h.lv[l];
+  int rc;
+  dfree(h, L.d_recs);
+  dfree(h, L.d_nbrs);
+  L.d_recs = nullptr;
+  L.d_nbrs = nullptr;
+  if ((rc = upload(h, &L.d_recs, L.recs, err))) return rc;
+  if ((rc = upload(h, &L.d_nbrs, L.nbrs, err))) return rc;
+  // solve-vector offsets
+  L.vx_off.resize(L.nn);
+  L.vz_off.resize(L.nn);
+  int64_t ox = 0, oz = 0;
+  for (int32_t i = 0; i < L.nn; ++i) {
+    L.vx_off[i] = ox;
+    ox += L.n[i];
+    L.vz_off[i] = oz;
+    oz += L.r[i];
+  }
+  L.vx_total = ox;
+  L.vz_total = oz;
+  dfree(h, L.d_vx_off);
+  dfree(h, L.d_vz_off);
+  if ((rc = upload(h, &L.d_vx_off, L.vx_off, err))) return rc;
+  if ((rc = upload(h, &L.d_vz_off, L.vz_off, err))) return rc;
+  HIPCHK(hipMemcpyAsync(L.d_r, L.r.data(), L.nn * 4, hipMemcpyHostToDevice, h.stream));
+  return 0;
+}
+
+static void clear_factor(Handle& h) {
+  for (size_t l = 0; l < h.lv.size(); ++l) {
+    release_level_work(h, (int)l);
+    DevLevel& L = h.lv[l];
+    void* ptrs[] = {L.d_recs, L.d_nbrs, L.d_vx_off, L.d_vz_off, L.d_n, L.d_r, L.d_parent, L.d_child_ptr, L.d_child};
+    for (void* p : ptrs) dfree(h, p);
+    L = DevLevel();
+  }
+  for (double* p : h.store_chunks) dfree(h, p);
+  h.store_chunks.clear();
+  h.store_cur = nullptr;
+  h.store_left = 0;
+  h.store_bytes = 0;
+  dfree(h, h.d_top);
+  dfree(h, h.d_top_piv);
+  h.d_top = nullptr;
+  h.d_top_piv = nullptr;
+  h.factored = false;
+}
+
+int factor(Handle& h, std::string& err) {
+  int rc;
+  if (!h.dev_ready && (rc = device_init(h, err))) return rc;
+  HIPCHK(hipSetDevice(h.device));
+  clear_factor(h);
+  h.lv.assign((size_t)h.tree.depth + 1, DevLevel());
+  h.stat_far = 0;
+  h.stat_changed = 0;
+  const double t0 = now_s();
+  h.t_level_setup.assign((size_t)h.tree.depth + 1, 0.0);
+  h.t_level_elim.assign((size_t)h.tree.depth + 1, 0.0);
+  double ta = now_s();
+  if ((rc = init_leaf_level(h, err))) return rc;
+  h.t_level_setup[h.tree.depth] = now_s() - ta;
+  for (int l = h.tree.depth; l >= 2; --l) {
+    const Level& T = h.tree.levels[l];
+    DevLevel& L = h.lv[l];
+    L.col_ptr.assign(1, 0);
+    ta = now_s();
+    for (int c = 0; c < T.ncolour; ++c)
+      if ((rc = eliminate_colour(h, l, c, err))) return rc;
+    HIPCHK(hipStreamSynchronize(h.stream));
+    if ((rc = finish_level(h, l, err))) return rc;
+    h.t_level_elim[l] = now_s() - ta;
+    ta = now_s();
+    if (l > 2 && (rc = aggregate_level(h, l, err))) return rc;
+    if (l > 2) h.t_level_setup[l - 1] = now_s() - ta;
+  }
+  ta = now_s();
+  // top: dense LU of the level-2 system
+  DevLevel& L2 = h.lv[2];
+  h.top_off.assign(L2.nn + 1, 0);
+  for (int32_t P = 0; P < L2.nn; ++P) h.top_off[P + 1] = h.top_off[P] + L2.r[P];
+  h.top_n = (int32_t)h.top_off[L2.nn];
+  if ((rc = dalloc(h, &h.d_top, std::max<int64_t>((int64_t)h.top_n * h.top_n, 1), err))) return rc;
+  if ((rc = dalloc(h, &h.d_top_piv, std::max(h.top_n, 1), err))) return rc;
+  int64_t* d_toff = nullptr;
+  if ((rc = upload(h, &d_toff, h.top_off, err))) return rc;
+  HIPCHK(hipMemsetAsync(h.d_top, 0, (size_t)std::max<int64_t>((int64_t)h.top_n * h.top_n, 1) * 8, h.stream));
+  LevelView V2 = view_of(L2);
+  int32_t* d_info = nullptr;
+  if ((rc = dalloc(h, &d_info, 1, err))) return rc;
+  if (h.top_n > 0) {
+    hipLaunchKernelGGL(k_top_assemble, dim3(L2.nn), dim3(NT), 0, h.stream, V2, L2.nn, d_toff, h.d_top, h.top_n);
+    hipLaunchKernelGGL(k_top_getrf, dim3(1), dim3(NT), 0, h.stream, h.d_top, h.top_n, h.d_top_piv, d_info);
+  }
+  HIPCHK(hipGetLastError());
+  int32_t info = 0;
+  if (h.top_n > 0) HIPCHK(hipMemcpyAsync(&info, d_info, 4, hipMemcpyDeviceToHost, h.stream));
+  HIPCHK(hipStreamSynchronize(h.stream));
+  dfree(h, d_info);
+  h.d_top_off = d_toff;
+  release_level_work(h, 2);
+  if (info) {
+    err = "singular top-level system (column " + std::to_string(info - 1) + ")";
+    return -4;
+  }
+  h.t_top = now_s() - ta;
+  h.t_factor = now_s() - t0;
+  h.factored = true;
+  return 0;
+}
+
+// ------------------------------------------------------------------ solve
+int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_device, std::string& err) {
+  if (!h.factored) {
+    err = "ifmm_solve called before ifmm_factor";
+    return -6;
+  }
+  HIPCHK(hipSetDevice(h.device));
+  const int D = h.tree.depth;
+  const double t0 = now_s();
+  // vector storage: per level X, Z, W, tmp
+  std::vector<int64_t> ox(D + 1), oz(D + 1), ow(D + 1), ot(D + 1);
+  int64_t tot = 0;
+  for (int l = 2; l <= D; ++l) {
+    const DevLevel& L = h.lv[l];
+    ox[l] = tot; tot += L.vx_total * k + 32;
+    oz[l] = tot; tot += L.vz_total * k + 32;
+    ow[l] = tot; tot += L.wv_total * k + 32;
+    ot[l] = tot; tot += L.wv_total * k + 32;
+  }
+  const int64_t otop = tot;
+  tot += (int64_t)std::max(h.top_n, 1) * k + 32;
+  const int64_t oio = tot;
+  if (!on_device) tot += 2 * ld * k + 32;
+  int rc;
+  if ((rc = ensure(h, (void**)&h.svec, &h.svec_bytes, tot * 8, err))) return rc;
+  double* B = h.svec;
+  HIPCHK(hipMemsetAsync(B, 0, (size_t)otop * 8, h.stream));
+  const double* d_rhs = rhs;
+  double* d_x = x;
+  if (!on_device) {
+    double* io = B + oio;
+    HIPCHK(hipMemcpyAsync(io, rhs, (size_t)ld * k * 8, hipMemcpyHostToDevice, h.stream));
+    d_rhs = io;
+    d_x = io + ld * k;
+  }
+  auto sv = [&](int l) {
+    SolveView S;
+    S.X = B + ox[l]; S.Z = B + oz[l]; S.W = B + ow[l]; S.tmp = B + ot[l];
+    S.xo = h.lv[l].d_vx_off; S.zo = h.lv[l].d_vz_off; S.k = k;
+    return S;
+  };
+  const Level& TL = h.tree.levels[D];
+  hipLaunchKernelGGL(k_perm_in, dim3(TL.n), dim3(NT), 0, h.stream, d_rhs, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
+                     sv(D));
+  for (int l = D; l >= 2; --l) {
+    const DevLevel& L = h.lv[l];
+    SolveView S = sv(l);
+    for (size_t c = 0; c + 1 < L.col_ptr.size(); ++c) {
+      const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
+      if (b > a) hipLaunchKernelGGL(k_fwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S, L.d_r);
+    }
+    if (l > 2) {
+      const DevLevel& P = h.lv[l - 1];
+      hipLaunchKernelGGL(k_vec_up, dim3(P.nn), dim3(NT), 0, h.stream, S, sv(l - 1), P.d_child_ptr, P.d_child, L.d_r,
+                         P.d_n);
+    }
+  }
+  if (h.top_n > 0)
+    hipLaunchKernelGGL(k_top_solve, dim3(1), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r, h.d_top_off,
+                       h.d_top, h.top_n, h.d_top_piv, B + otop);
+  for (int l = 2; l <= D; ++l) {
+    const DevLevel& L = h.lv[l];
+    SolveView S = sv(l);
+    if (l > 2) {
+      const DevLevel& P = h.lv[l - 1];
+      hipLaunchKernelGGL(k_vec_down, dim3(P.nn), dim3(NT), 0, h.stream, S, sv(l - 1), P.d_child_ptr, P.d_child, L.d_r,
+                         P.d_n);
+    }
+    for (int c = (int)L.col_ptr.size() - 2; c >= 0; --c) {
+      const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
+      if (b > a) hipLaunchKernelGGL(k_bwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S);
+    }
+  }
+  hipLaunchKernelGGL(k_perm_out, dim3(TL.n), dim3(NT), 0, h.stream, d_x, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
+                     sv(D));
+  HIPCHK(hipGetLastError());
+  if (!on_device) HIPCHK(hipMemcpyAsync(x, d_x, (size_t)ld * k * 8, hipMemcpyDeviceToHost, h.stream));
+  HIPCHK(hipStreamSynchronize(h.stream));
+  h.t_solve = now_s() - t0;
+  return 0;
+}
+
+// ------------------------------------------------------------------ init / release
+int device_init(Handle& h, std::string& err) {
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) {
+    err = "no HIP device available";
+    return -3;
+  }
+  HIPCHK(hipGetDevice(&h.device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, h.device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    err = std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950";
+    return -3;
+  }
+  const double t0 = now_s();
+  const int K = h.K;
+  const int64_t N = h.N;
+  int rc;
+  std::vector<double> pts(h.pts), lo(h.tree.lo, h.tree.lo + 3);
+  if ((rc = upload(h, &h.d_pts, pts, err))) return rc;
+  if ((rc = upload(h, &h.d_w, h.w, err))) return rc;
+  if ((rc = upload(h, &h.d_diag, h.diag, err))) return rc;
+  if ((rc = upload(h, &h.d_perm, h.tree.perm, err))) return rc;
+  if ((rc = upload(h, &h.d_pt_begin, h.tree.levels[h.tree.depth].pt_begin, err))) return rc;
+  if ((rc = upload(h, &h.d_lo, lo, err))) return rc;
+  (void)N;
+  if ((rc = dalloc(h, &h.d_unit, 343LL * K * K, err))) return rc;
+  if ((rc = dalloc(h, &h.d_uus, 343LL * K * K, err))) return rc;
+  if ((rc = dalloc(h, &h.d_m2m8, 8LL * K * K, err))) return rc;
+  hipLaunchKernelGGL(k_unit_m2l, dim3(343), dim3(NT), 0, h.stream, h.nc, h.d_unit);
+  hipLaunchKernelGGL(k_unit_gram, dim3(343), dim3(NT), 0, h.stream, K, h.d_unit, h.d_uus);
+  hipLaunchKernelGGL(k_m2m8, dim3(8), dim3(NT), 0, h.stream, h.nc, h.d_m2m8);
+  HIPCHK(hipGetLastError());
+  // far-field weights, top-down
+  h.weights_G.assign((size_t)h.tree.depth + 1, nullptr);
+  for (int l = 2; l <= h.tree.depth; ++l) {
+    const Level& T = h.tree.levels[l];
+    int32_t *d_coord = nullptr, *d_ilp = nullptr, *d_il = nullptr, *d_par = nullptr;
+    if ((rc = upload(h, &d_coord, T.coord, err))) return rc;
+    if ((rc = upload(h, &d_ilp, T.il_ptr, err))) return rc;
+    if ((rc = upload(h, &d_il, T.il, err))) return rc;
+    if ((rc = upload(h, &d_par, T.parent, err))) return rc;
+    if ((rc = dalloc(h, &h.weights_G[l], std::max<int64_t>((int64_t)T.n * K * K, 1), err))) return rc;
+    double* tmp = nullptr;
+    if ((rc = dalloc(h, &tmp, std::max<int64_t>((int64_t)T.n * K * K, 1), err))) return rc;
+    const double side = 2.0 * h.tree.H / (double)(1LL << l);
+    if (T.n > 0)
+      hipLaunchKernelGGL(k_weights, dim3(T.n), dim3(NT), 0, h.stream, K, T.n, d_coord, d_ilp, d_il, d_par, h.d_uus,
+                         h.d_m2m8, 1.0 / (side * side), l > 2 ? h.weights_G[l - 1] : nullptr, h.weights_G[l], tmp);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h.stream));
+    dfree(h, tmp);
+    dfree(h, d_coord);
+    dfree(h, d_ilp);
+    dfree(h, d_il);
+    dfree(h, d_par);
+  }
+  h.dev_ready = true;
+  h.t_init = now_s() - t0;
+  return 0;
+}
+
+void release(Handle& h) {
+  if (!h.dev_ready) return;
+  (void)hipSetDevice(h.device);
+  (void)hipStreamSynchronize(h.stream);
+  clear_factor(h);
+  for (auto& a : h.allocs) (void)hipFree(a.first);
+  h.allocs.clear();
+  h.dev_bytes = 0;
+  h.dev_ready = false;
+}
+
+}  // namespace ifmm

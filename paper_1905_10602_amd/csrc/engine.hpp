@@ -1,0 +1,156 @@
+// Internal state of an IFMM handle: host structure, device storage, factor
+// records and the orchestration entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tree.hpp"
+
+namespace ifmm {
+
+// One elimination (node i of the current colour).  The pivot D_i (d x d) is
+// stored LU-factorised; L holds the stacked L-blocks (rows of the neighbours
+// that couple to x_i: M x n, ld M) and U the stacked U-blocks (n x W, ld n).
+// For every neighbour the row count of its block equals its column count, so
+// M == W.  All pointers are device pointers.
+struct ElimRec {
+  int32_t node, n, r, d;   // node index, |x_i|, rank, d = n + r
+  int32_t nnb, nb_begin;   // neighbour entries [nb_begin, nb_begin + nnb) of the ElimNbr table
+  int32_t M, pad0;         // total rows of L-blocks (== total columns of U-blocks)
+  double* lu;              // d x d, ld d
+  int32_t* piv;            // d
+  double* L;               // M x n, ld M
+  double* U;               // n x M, ld n
+  double* X;               // colour scratch: D^-1 [U 0; 0 I], d x (M + r), ld d
+  int64_t wv;              // offset (in doubles per right-hand side) of w_i in the solve work vector
+  int32_t far_base, pad1;  // far-pair index table: nnb * nnb entries from far_base
+};
+
+struct ElimNbr {
+  int32_t p;        // neighbour node
+  int32_t elim;     // 1 if p was eliminated before i (its row is R_z_p, its column C_y_p)
+  int32_t m;        // rows (== columns) of p's current block: r_p if elim else n_p
+  int32_t off;      // offset of p's rows in L (and of p's columns in U and X)
+  int64_t blk_pi;   // near block (p, i): m x n_i, ld n_p  (level arena offset)
+  int64_t blk_ip;   // near block (i, p): n_i x m, ld n_i
+};
+
+// Far fill-in between two neighbours a, b of an eliminated node (dist 2).
+struct FarPair {
+  int32_t rec, a, b, direct;  // direct: both eliminated, add F straight into the M2L block
+  double* F;                  // -L_a X_b, m_a x m_b (ld m_a); later the projected block
+  double* D;                  // workspace, m_a x m_b
+  int64_t dst;                // M2L block (p_a, p_b) in the level arena
+  int32_t dst_ld, pad;
+};
+
+// Far partner of a changed node: the M2L block (p, q) / (q, p) receives a
+// projected fill-in from pair ab / ba.
+struct FarRef {
+  int32_t q, ab, ba, pad;
+};
+
+// A non-eliminated neighbour whose bases change in this colour.
+struct Changed {
+  int32_t p, rec, a, n;     // node, owner record, position in its neighbour list, n_p
+  int32_t r, rnew;          // rank before / after
+  int32_t far_begin, far_count;
+  double *gs, *gt;          // Gram matrices n x n
+  double *vs, *vt;          // eigenvectors n x n
+  double *ws, *wt;          // Jacobi workspace n x n
+  double *ls, *lt;          // eigenvalues n
+  double *T, *S;            // T_p (r x rnew, ld r), S_p (rnew x r, ld rnew)
+  double* tmp;              // workspace (max(rc, n) x max(rc, n) of the level)
+};
+
+struct DevLevel {
+  int32_t nn = 0, rcmax = 0, nmax = 0;
+  // host mirrors
+  std::vector<int32_t> n, r, rc;
+  std::vector<int32_t> near_ptr, near_idx, slot_row;  // near list of i: i itself, then N_i
+  std::vector<int64_t> near_off, il_off, p2m_off, l2p_off, sig_off, m2m_off, l2l_off;
+  std::vector<int64_t> cp2m_off, cl2p_off, T_off, S_off;
+  int64_t arena_doubles = 0;
+  // device working storage of the level (freed once the level is aggregated)
+  double* arena = nullptr;
+  int32_t *d_rc = nullptr, *d_coord = nullptr, *d_near_ptr = nullptr, *d_near_idx = nullptr;
+  int32_t *d_slot_row = nullptr, *d_il_ptr = nullptr, *d_il_idx = nullptr, *d_chg = nullptr;
+  int64_t *d_near_off = nullptr, *d_il_off = nullptr, *d_p2m_off = nullptr, *d_l2p_off = nullptr;
+  int64_t *d_sig_off = nullptr, *d_m2m_off = nullptr, *d_l2l_off = nullptr;
+  int64_t *d_cp2m_off = nullptr, *d_cl2p_off = nullptr, *d_T_off = nullptr, *d_S_off = nullptr;
+  // kept for the solve
+  int32_t *d_n = nullptr, *d_r = nullptr, *d_parent = nullptr, *d_child_ptr = nullptr, *d_child = nullptr;
+  std::vector<ElimRec> recs;   // elimination order
+  std::vector<ElimNbr> nbrs;
+  std::vector<int32_t> col_ptr;  // recs of colour c: [col_ptr[c], col_ptr[c + 1])
+  ElimRec* d_recs = nullptr;
+  ElimNbr* d_nbrs = nullptr;
+  int64_t wv_total = 0;
+  std::vector<int64_t> vx_off, vz_off;
+  int64_t vx_total = 0, vz_total = 0;
+  int64_t *d_vx_off = nullptr, *d_vz_off = nullptr;
+};
+
+struct Handle {
+  // problem (points, weights and diagonal in tree order)
+  int64_t N = 0;
+  std::vector<double> pts, w, diag;
+  double eps = 0;
+  int sigma = 0, leaf_max = 64, nc = 4, K = 64, precision = 0, rank_cap = 0;
+  int64_t max_bytes = 0;
+  hipStream_t stream = nullptr;
+  Tree tree;
+  // device
+  bool dev_ready = false;
+  int device = -1;
+  std::vector<std::pair<void*, int64_t>> allocs;
+  int64_t dev_bytes = 0;
+  double *d_pts = nullptr, *d_w = nullptr, *d_diag = nullptr, *d_lo = nullptr;
+  int64_t *d_perm = nullptr, *d_pt_begin = nullptr;
+  double* d_unit = nullptr;  // 343 unit-side Chebyshev M2L matrices (offsets in [-3, 3]^3)
+  double* d_uus = nullptr;   // U_d^T U_d per offset
+  double* d_m2m8 = nullptr;  // the 8 child -> parent M2M matrices
+  std::vector<double*> weights_G;  // per level: nn * K * K far-field weights
+  std::vector<DevLevel> lv;
+  // persistent factor store (bump allocated in chunks)
+  std::vector<double*> store_chunks;
+  double* store_cur = nullptr;
+  int64_t store_left = 0, store_bytes = 0;
+  // growable buffers
+  double* scratch = nullptr;
+  int64_t scratch_bytes = 0;
+  char* meta = nullptr;
+  int64_t meta_bytes = 0;
+  std::vector<char> host_meta;
+  double* svec = nullptr;
+  int64_t svec_bytes = 0;
+  // top level
+  double* d_top = nullptr;
+  int32_t* d_top_piv = nullptr;
+  int64_t* d_top_off = nullptr;
+  int32_t top_n = 0;
+  std::vector<int64_t> top_off;
+  bool factored = false;
+  // statistics
+  double t_init = 0, t_factor = 0, t_solve = 0;
+  int64_t stat_far = 0, stat_changed = 0;
+  std::vector<double> t_level_setup, t_level_elim;  // per level: set-up + rank reduction, colour loop
+  double t_top = 0;
+};
+
+// status helpers
+void set_error(const std::string& msg);
+const char* get_error();
+
+int build_host(Handle& h, const double* pts, int64_t n, const double* w, const double* diag, double diag_scalar,
+               std::string& err);
+int device_init(Handle& h, std::string& err);
+int factor(Handle& h, std::string& err);
+int solve(Handle& h, const double* rhs, double* x, int nrhs, int64_t ld, int on_device, std::string& err);
+void release(Handle& h);
+
+}  // namespace ifmm

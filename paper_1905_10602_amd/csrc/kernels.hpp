@@ -1,0 +1,757 @@
+// HIP kernels of the IFMM factorisation and solve (gfx950, FP64).
+//
+// One workgroup (256 threads) per task: a node, a block, a neighbour row
+// block or a changed basis.  Sizes come from the task tables, so batches of
+// uneven nodes run in one launch per step and colour.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dense.hpp"
+#include "engine.hpp"
+
+namespace ifmm {
+
+// Static per-level structure as seen by the kernels.
+struct LevelView {
+  double* arena;
+  const int32_t *n, *r, *rc, *coord;
+  const int32_t *near_ptr, *near_idx, *il_ptr, *il_idx;
+  const int64_t *near_off, *il_off, *p2m_off, *l2p_off, *sig_off, *m2m_off, *l2l_off;
+  const int64_t *cp2m_off, *cl2p_off, *T_off, *S_off;  // Chebyshev-basis operators and initial transforms
+  const int32_t* chg;                                   // changed-node index per node (-1 = unchanged)
+};
+
+__device__ inline int dist3(const int32_t* coord, int a, int b) {
+  int d = abs(coord[3 * a] - coord[3 * b]);
+  d = max(d, abs(coord[3 * a + 1] - coord[3 * b + 1]));
+  return max(d, abs(coord[3 * a + 2] - coord[3 * b + 2]));
+}
+
+// near block (p, q), dist(p, q) <= 1: offset in the arena (ld = n_p)
+__device__ inline int64_t near_block(const LevelView& V, int p, int q) {
+  for (int s = V.near_ptr[p]; s < V.near_ptr[p + 1]; ++s)
+    if (V.near_idx[s] == q) return V.near_off[s];
+  return -1;
+}
+
+// M2L block (t, s), s in I_t: offset in the arena (ld = rc_t)
+__device__ inline int64_t il_block(const LevelView& V, int t, int s) {
+  int lo = V.il_ptr[t], hi = V.il_ptr[t + 1] - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int v = V.il_idx[mid];
+    if (v == s) return V.il_off[mid];
+    if (v < s) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+// ------------------------------------------------------------------ Chebyshev
+// Interpolation weight S_n(xb_m, y) = 1/n + (2/n) sum_{k=1}^{n-1} T_k(xb_m) T_k(y),
+// xb_m = cos((2m + 1) pi / (2n)), m = 0..n-1.
+__device__ inline double cheb_S(int nc, int m, double y) {
+  const double xb = cos((2.0 * m + 1.0) * M_PI / (2.0 * nc));
+  double s = 1.0 / nc;
+  double tx0 = 1.0, tx1 = xb, ty0 = 1.0, ty1 = y;
+  for (int k = 1; k < nc; ++k) {
+    s += (2.0 / nc) * tx1 * ty1;
+    const double tx2 = 2.0 * xb * tx1 - tx0, ty2 = 2.0 * y * ty1 - ty0;
+    tx0 = tx1; tx1 = tx2; ty0 = ty1; ty1 = ty2;
+  }
+  return s;
+}
+
+__device__ inline double cheb_node(int nc, int m) { return cos((2.0 * m + 1.0) * M_PI / (2.0 * nc)); }
+
+// Unit-side M2L for all 343 offsets d in [-3, 3]^3: U_d[m, m'] = K(d + xb_m / 2, xb_m' / 2).
+__global__ void k_unit_m2l(int nc, double* out) {
+  const int o = blockIdx.x;
+  const int dx = o % 7 - 3, dy = (o / 7) % 7 - 3, dz = o / 49 - 3;
+  const int K = nc * nc * nc;
+  double* U = out + (int64_t)o * K * K;
+  const bool near = abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1;
+  for (int e = threadIdx.x; e < K * K; e += NT) {
+    const int m = e % K, mp = e / K;
+    double v = 0.0;
+    if (!near) {
+      const double x = dx + 0.5 * (cheb_node(nc, m % nc) - cheb_node(nc, mp % nc));
+      const double y = dy + 0.5 * (cheb_node(nc, (m / nc) % nc) - cheb_node(nc, (mp / nc) % nc));
+      const double z = dz + 0.5 * (cheb_node(nc, m / (nc * nc)) - cheb_node(nc, mp / (nc * nc)));
+      v = 1.0 / (4.0 * M_PI * sqrt(x * x + y * y + z * z));
+    }
+    U[m + (int64_t)mp * K] = v;
+  }
+}
+
+// G_d = U_d^T U_d for every offset (source-side weight term).
+__global__ void k_unit_gram(int K, const double* unit, double* uus) {
+  const int o = blockIdx.x;
+  wg_gemm(K, K, K, 1.0, unit + (int64_t)o * K * K, K, true, unit + (int64_t)o * K * K, K, false, 0.0,
+          uus + (int64_t)o * K * K, K);
+}
+
+// M2M from a child in octant o (bit e set = upper half along axis e) to its parent.
+__global__ void k_m2m8(int nc, double* out) {
+  const int o = blockIdx.x;
+  const int K = nc * nc * nc;
+  double* M = out + (int64_t)o * K * K;
+  const double sx = (o & 1) ? 0.5 : -0.5, sy = (o & 2) ? 0.5 : -0.5, sz = (o & 4) ? 0.5 : -0.5;
+  for (int e = threadIdx.x; e < K * K; e += NT) {
+    const int m = e % K, mp = e / K;
+    const double x = sx + 0.5 * cheb_node(nc, mp % nc);
+    const double y = sy + 0.5 * cheb_node(nc, (mp / nc) % nc);
+    const double z = sz + 0.5 * cheb_node(nc, mp / (nc * nc));
+    M[m + (int64_t)mp * K] =
+        cheb_S(nc, m % nc, x) * cheb_S(nc, (m / nc) % nc, y) * cheb_S(nc, m / (nc * nc), z);
+  }
+}
+
+__device__ inline int octant_of(const int32_t* coord, int i) {
+  return (coord[3 * i] & 1) | ((coord[3 * i + 1] & 1) << 1) | ((coord[3 * i + 2] & 1) << 2);
+}
+
+__device__ inline int offset_index(const int32_t* coord, int t, int s) {
+  const int dx = coord[3 * t] - coord[3 * s], dy = coord[3 * t + 1] - coord[3 * s + 1],
+            dz = coord[3 * t + 2] - coord[3 * s + 2];
+  return (dx + 3) + 7 * ((dy + 3) + 7 * (dz + 3));
+}
+
+// Far-field weight of every node of a level (top-down):
+//   G_i = (1/L^2) sum_{l in I_i} U_{c_l - c_i}^T U_{c_l - c_i} + M2M_i^T G_parent M2M_i.
+// The Laplace kernel is symmetric, so the target weight equals G_i.
+__global__ void k_weights(int K, int nn, const int32_t* coord, const int32_t* il_ptr, const int32_t* il_idx,
+                          const int32_t* parent, const double* uus, const double* m2m8, double invL2,
+                          const double* Gpar, double* G, double* tmp) {
+  const int i = blockIdx.x;
+  double* Gi = G + (int64_t)i * K * K;
+  for (int e = threadIdx.x; e < K * K; e += NT) {
+    double acc = 0.0;
+    for (int s = il_ptr[i]; s < il_ptr[i + 1]; ++s)
+      acc += uus[(int64_t)offset_index(coord, il_idx[s], i) * K * K + e];
+    Gi[e] = acc * invL2;
+  }
+  __syncthreads();
+  if (Gpar) {
+    const double* M = m2m8 + (int64_t)octant_of(coord, i) * K * K;
+    const double* Gp = Gpar + (int64_t)parent[i] * K * K;
+    double* t = tmp + (int64_t)i * K * K;
+    wg_gemm(K, K, K, 1.0, Gp, K, false, M, K, false, 0.0, t, K);
+    wg_gemm(K, K, K, 1.0, M, K, true, t, K, false, 1.0, Gi, K);
+  }
+}
+
+// Leaf Chebyshev operators: P2Mc (K x n, ld K) and L2Pc (n x K, ld n).
+__global__ void k_leaf_cheb(LevelView V, int nc, const double* pts, const double* w, const int64_t* pt_begin,
+                            const double* lo, double side) {
+  const int i = blockIdx.x;
+  const int K = nc * nc * nc;
+  const int n = V.n[i];
+  double* P2M = V.arena + V.cp2m_off[i];
+  double* L2P = V.arena + V.cl2p_off[i];
+  const double h = 0.5 * side;
+  double c[3];
+  for (int e = 0; e < 3; ++e) c[e] = lo[e] + ((double)V.coord[3 * i + e] + 0.5) * side;
+  const int64_t b = pt_begin[i];
+  for (int e = threadIdx.x; e < K * n; e += NT) {
+    const int m = e % K, j = e / K;
+    const double* p = pts + 3 * (b + j);
+    const double s = cheb_S(nc, m % nc, (p[0] - c[0]) / h) * cheb_S(nc, (m / nc) % nc, (p[1] - c[1]) / h) *
+                     cheb_S(nc, m / (nc * nc), (p[2] - c[2]) / h);
+    P2M[m + (int64_t)j * K] = s * w[b + j];
+    L2P[j + (int64_t)m * n] = s;
+  }
+}
+
+// Near-field blocks of the leaves: P2P_pq[a, b] = K(x_a, x_b) w_b, diag on the self block.
+__global__ void k_p2p(LevelView V, const int32_t* slot_row, const double* pts, const double* w,
+                      const double* diag, const int64_t* pt_begin) {
+  const int s = blockIdx.x;
+  const int p = slot_row[s], q = V.near_idx[s];
+  const int np = V.n[p], nq = V.n[q];
+  double* B = V.arena + V.near_off[s];
+  const int64_t bp = pt_begin[p], bq = pt_begin[q];
+  for (int e = threadIdx.x; e < np * nq; e += NT) {
+    const int a = e % np, bb = e / np;
+    double v;
+    if (p == q && a == bb) {
+      v = diag[bp + a];
+    } else {
+      const double* x = pts + 3 * (bp + a);
+      const double* y = pts + 3 * (bq + bb);
+      const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+      v = w[bq + bb] / (4.0 * M_PI * sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    B[a + (int64_t)bb * np] = v;
+  }
+}
+
+// Initial rank reduction, Gram step: Gs = P2Mc^T G P2Mc, Gt = L2Pc G L2Pc^T (n x n).
+__global__ void k_reduce_gram(LevelView V, int K, const double* G, double* work, const int64_t* work_off) {
+  const int i = blockIdx.x;
+  const int n = V.n[i];
+  if (n == 0) return;
+  double* base = work + work_off[i];
+  double* gs = base;
+  double* gt = gs + (int64_t)n * n;
+  double* t = gt + (int64_t)n * n;  // K x n
+  const double* Gi = G + (int64_t)i * K * K;
+  const double* P2M = V.arena + V.cp2m_off[i];
+  const double* L2P = V.arena + V.cl2p_off[i];
+  wg_gemm(K, n, K, 1.0, Gi, K, false, P2M, K, false, 0.0, t, K);
+  wg_gemm(n, n, K, 1.0, P2M, K, true, t, K, false, 0.0, gs, n);
+  wg_gemm(K, n, K, 1.0, Gi, K, false, L2P, n, true, 0.0, t, K);
+  wg_gemm(n, n, K, 1.0, L2P, n, false, t, K, false, 0.0, gt, n);
+}
+
+// Batched symmetric eigen-decomposition; cnt[t] = #{k : lam_k > eps2 * lam_0}.
+struct EigTask {
+  double *A, *V, *W, *lam;
+  int32_t n, pad;
+};
+__global__ void k_eig(const EigTask* tasks, double eps2, int32_t* cnt) {
+  const EigTask t = tasks[blockIdx.x];
+  if (t.n == 0) {
+    if (threadIdx.x == 0) cnt[blockIdx.x] = 0;
+    return;
+  }
+  wg_syev_jacobi(t.n, t.A, t.n, t.V, t.n, t.W, t.lam);
+  if (threadIdx.x == 0) {
+    const double l0 = t.lam[0];
+    int c = 0;
+    if (l0 > 0.0)
+      for (int k = 0; k < t.n; ++k)
+        if (t.lam[k] > eps2 * l0) ++c;
+    cnt[blockIdx.x] = c;
+  }
+}
+
+// Initial rank reduction, basis step: P2M = V^T, L2P = U, sig = sqrt(lam),
+// T = P2Mc V (K x r), S = U^T L2Pc (r x K); then M2M / L2L of the node.
+__global__ void k_reduce_basis(LevelView V, int K, const double* work, const int64_t* work_off,
+                               const double* m2m8, int has_parent) {
+  const int i = blockIdx.x;
+  const int n = V.n[i], r = V.r[i], rc = V.rc[i];
+  double* T = V.arena + V.T_off[i];
+  double* S = V.arena + V.S_off[i];
+  if (n == 0 || r == 0) return;
+  const double* base = work + work_off[i];
+  // work layout per node: gs, gt (n x n), t (K x n), vs, vt, ws, wt (n x n), ls, lt (n)
+  const double* vs = base + 2 * (int64_t)n * n + (int64_t)K * n;
+  const double* vt = vs + (int64_t)n * n;
+  const double* ls = vt + 3 * (int64_t)n * n;
+  const double* lt = ls + n;
+  double* P2M = V.arena + V.p2m_off[i];
+  double* L2P = V.arena + V.l2p_off[i];
+  double* sig = V.arena + V.sig_off[i];
+  for (int e = threadIdx.x; e < r * n; e += NT) {
+    const int a = e % r, j = e / r;
+    P2M[a + (int64_t)j * rc] = vs[j + (int64_t)a * n];
+  }
+  for (int e = threadIdx.x; e < n * r; e += NT) {
+    const int j = e % n, a = e / n;
+    L2P[j + (int64_t)a * n] = vt[j + (int64_t)a * n];
+  }
+  for (int a = threadIdx.x; a < r; a += NT) {
+    sig[a] = sqrt(fmax(ls[a], 0.0));
+    sig[rc + a] = sqrt(fmax(lt[a], 0.0));
+  }
+  __syncthreads();
+  wg_gemm(K, r, n, 1.0, V.arena + V.cp2m_off[i], K, false, vs, n, false, 0.0, T, K);
+  wg_gemm(r, K, n, 1.0, vt, n, true, V.arena + V.cl2p_off[i], n, false, 0.0, S, rc);
+  if (has_parent) {
+    const double* M = m2m8 + (int64_t)octant_of(V.coord, i) * K * K;
+    wg_gemm(K, r, K, 1.0, M, K, false, T, K, false, 0.0, V.arena + V.m2m_off[i], K);
+    wg_gemm(r, K, K, 1.0, S, rc, false, M, K, true, 0.0, V.arena + V.l2l_off[i], rc);
+  }
+}
+
+// Initial M2L of every interaction pair: M2L_il = (1/L) S_i U_{c_i - c_l} T_l.
+__global__ void k_reduce_m2l(LevelView V, int K, const double* unit, double invL, double* tmp, const int64_t* tmp_off) {
+  const int i = blockIdx.x;
+  const int ri = V.r[i], rci = V.rc[i];
+  if (ri == 0) return;
+  double* t = tmp + tmp_off[i];
+  const double* S = V.arena + V.S_off[i];
+  for (int s = V.il_ptr[i]; s < V.il_ptr[i + 1]; ++s) {
+    const int l = V.il_idx[s];
+    const int rl = V.r[l];
+    if (rl == 0) continue;
+    const double* U = unit + (int64_t)offset_index(V.coord, i, l) * K * K;
+    wg_gemm(K, rl, K, invL, U, K, false, V.arena + V.T_off[l], K, false, 0.0, t, K);
+    wg_gemm(ri, rl, K, 1.0, S, rci, false, t, K, false, 0.0, V.arena + V.il_off[s], rci);
+  }
+}
+
+// ------------------------------------------------------------------ aggregation
+// Parent Chebyshev operators: P2Mc_P = [M2M_c ...] (K x n_P), L2Pc_P = [L2L_c; ...].
+__global__ void k_agg_cheb(LevelView C, LevelView F, int K, const int32_t* child_ptr, const int32_t* child) {
+  const int P = blockIdx.x;
+  const int nP = C.n[P];
+  double* P2M = C.arena + C.cp2m_off[P];
+  double* L2P = C.arena + C.cl2p_off[P];
+  int off = 0;
+  for (int s = child_ptr[P]; s < child_ptr[P + 1]; ++s) {
+    const int c = child[s];
+    const int rc = F.r[c], ldc = F.rc[c];
+    wg_copy(K, rc, F.arena + F.m2m_off[c], K, P2M + (int64_t)off * K, K);
+    wg_copy(rc, K, F.arena + F.l2l_off[c], ldc, L2P + off, nP);
+    off += rc;
+  }
+}
+
+// Parent near block (P, Q) = [M2L_cc'] over the children (near or interaction blocks).
+__global__ void k_agg_near(LevelView C, LevelView F, const int32_t* slot_row, const int32_t* child_ptr,
+                           const int32_t* child) {
+  const int s = blockIdx.x;
+  const int P = slot_row[s], Q = C.near_idx[s];
+  const int nP = C.n[P];
+  double* B = C.arena + C.near_off[s];
+  int ro = 0;
+  for (int a = child_ptr[P]; a < child_ptr[P + 1]; ++a) {
+    const int c = child[a];
+    const int rcr = F.r[c];
+    int co = 0;
+    for (int b = child_ptr[Q]; b < child_ptr[Q + 1]; ++b) {
+      const int cc = child[b];
+      const int rcc = F.r[cc];
+      if (rcr > 0 && rcc > 0) {
+        if (dist3(F.coord, c, cc) <= 1) {
+          wg_copy(rcr, rcc, F.arena + near_block(F, c, cc), F.n[c], B + ro + (int64_t)co * nP, nP);
+        } else {
+          wg_copy(rcr, rcc, F.arena + il_block(F, c, cc), F.rc[c], B + ro + (int64_t)co * nP, nP);
+        }
+      }
+      co += rcc;
+    }
+    ro += rcr;
+  }
+}
+
+// ------------------------------------------------------------------ phase A
+// Pivot D_i = [[P2P_ii, L2P_i], [P2M_i, 0]] and copies of the L- and U-blocks.
+__global__ void k_gather(LevelView V, const ElimRec* recs, const ElimNbr* nbrs) {
+  const ElimRec R = recs[blockIdx.x];
+  const int i = R.node, n = R.n, r = R.r, d = R.d;
+  const int rc = V.rc[i];
+  wg_copy(n, n, V.arena + near_block(V, i, i), n, R.lu, d);
+  wg_copy(n, r, V.arena + V.l2p_off[i], n, R.lu + (int64_t)n * d, d);
+  wg_copy(r, n, V.arena + V.p2m_off[i], rc, R.lu + n, d);
+  wg_fill(r, r, R.lu + n + (int64_t)n * d, d, 0.0);
+  for (int e = 0; e < R.nnb; ++e) {
+    const ElimNbr B = nbrs[R.nb_begin + e];
+    const int np = V.n[B.p];
+    wg_copy(B.m, n, V.arena + B.blk_pi, np, R.L + B.off, R.M);
+    wg_copy(n, B.m, V.arena + B.blk_ip, n, R.U + (int64_t)B.off * n, n);
+  }
+}
+
+__global__ void k_getrf(const ElimRec* recs, int32_t* info) {
+  const ElimRec R = recs[blockIdx.x];
+  const int inf = wg_getrf(R.d, R.lu, R.d, R.piv);
+  if (threadIdx.x == 0) info[blockIdx.x] = inf;
+}
+
+// X = D^-1 [[U, 0], [0, I]]  (d x (M + r))
+__global__ void k_xsolve(const ElimRec* recs) {
+  const ElimRec R = recs[blockIdx.x];
+  const int n = R.n, r = R.r, d = R.d, M = R.M;
+  const int nc = M + r;
+  for (int64_t e = threadIdx.x; e < (int64_t)d * nc; e += NT) {
+    const int row = (int)(e % d), col = (int)(e / d);
+    double v;
+    if (col < M) v = row < n ? R.U[row + (int64_t)col * n] : 0.0;
+    else v = (row >= n && row - n == col - M) ? 1.0 : 0.0;
+    R.X[row + (int64_t)col * d] = v;
+  }
+  __syncthreads();
+  wg_getrs(d, R.lu, d, R.piv, R.X, d, nc);
+}
+
+// Schur-complement update of one row block a of the neighbours of i (a == nnb:
+// the surviving row R_z_i of i itself).
+//   near (dist <= 1):  M[p, q] -= L_a X_top[:, q]
+//   far  (dist 2):     F_ab = -L_a X_top[:, q]          (compressed later)
+//   new blocks:        M[p, i] = L_a F,  M[i, q] = X_bot[:, q],  M[i, i] = -H
+struct SchurTask {
+  int32_t rec, a;
+};
+__global__ void k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs, const SchurTask* tasks,
+                        const int32_t* far_idx, const FarPair* far) {
+  const SchurTask T = tasks[blockIdx.x];
+  const ElimRec R = recs[T.rec];
+  const int i = R.node, n = R.n, r = R.r, d = R.d, M = R.M;
+  if (T.a < R.nnb) {
+    const ElimNbr A = nbrs[R.nb_begin + T.a];
+    const int p = A.p, np = V.n[p];
+    const double* La = R.L + A.off;
+    if (n > 0) {
+      for (int b = 0; b < R.nnb; ++b) {
+        const ElimNbr B = nbrs[R.nb_begin + b];
+        const double* Xb = R.X + (int64_t)B.off * d;
+        const int fi = far_idx[R.far_base + T.a * R.nnb + b];
+        if (fi < 0) {
+          const int64_t blk = near_block(V, p, B.p);
+          wg_gemm(A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 1.0, V.arena + blk, np);
+        } else {
+          wg_gemm(A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 0.0, far[fi].F, A.m);
+        }
+      }
+      // new block (p, i) = L_a F   with [F; H] = D^-1 [0; I]
+      wg_gemm(A.m, r, n, 1.0, La, M, false, R.X + (int64_t)M * d, d, false, 0.0, V.arena + A.blk_pi, np);
+    } else {
+      wg_fill(A.m, r, V.arena + A.blk_pi, np, 0.0);
+    }
+  } else {
+    for (int b = 0; b < R.nnb; ++b) {
+      const ElimNbr B = nbrs[R.nb_begin + b];
+      wg_copy(r, B.m, R.X + n + (int64_t)B.off * d, d, V.arena + B.blk_ip, n);
+    }
+    wg_copy(r, r, R.X + n + (int64_t)M * d, d, V.arena + near_block(V, i, i), n, -1.0);
+  }
+}
+
+// Gram matrices of a changed node p (side 0: source, side 1: target):
+//   Gs = P2M^T diag(sig_s^2) P2M + sum_q F_qp^T F_qp
+//   Gt = L2P diag(sig_t^2) L2P^T + sum_q F_pq F_pq^T
+__global__ void k_gram(LevelView V, const Changed* chg, const FarRef* refs, const FarPair* far,
+                       const ElimNbr* nbrs, const ElimRec* recs) {
+  const Changed C = chg[blockIdx.x >> 1];
+  const int side = blockIdx.x & 1;
+  const int p = C.p, n = C.n, r = C.r, rc = V.rc[p];
+  const double* sig = V.arena + V.sig_off[p];
+  double* G = side ? C.gt : C.gs;
+  double* t = C.tmp;
+  const ElimRec R = recs[C.rec];
+  if (side == 0) {
+    // t = diag(sig_s) P2M  (r x n)
+    const double* P2M = V.arena + V.p2m_off[p];
+    for (int e = threadIdx.x; e < r * n; e += NT) {
+      const int a = e % r, j = e / r;
+      t[a + (int64_t)j * r] = sig[a] * P2M[a + (int64_t)j * rc];
+    }
+    __syncthreads();
+    wg_gemm(n, n, r, 1.0, t, r, true, t, r, false, 0.0, G, n);
+    if (r == 0) wg_fill(n, n, G, n, 0.0);
+    for (int k = 0; k < C.far_count; ++k) {
+      const FarRef F = refs[C.far_begin + k];
+      const FarPair Pq = far[F.ba];  // rows of q, columns of p
+      const int mq = nbrs[R.nb_begin + Pq.a].m;
+      wg_gemm(n, n, mq, 1.0, Pq.F, mq, true, Pq.F, mq, false, 1.0, G, n);
+    }
+  } else {
+    const double* L2P = V.arena + V.l2p_off[p];
+    for (int e = threadIdx.x; e < n * r; e += NT) {
+      const int j = e % n, a = e / n;
+      t[j + (int64_t)a * n] = L2P[j + (int64_t)a * n] * sig[rc + a];
+    }
+    __syncthreads();
+    wg_gemm(n, n, r, 1.0, t, n, false, t, n, true, 0.0, G, n);
+    if (r == 0) wg_fill(n, n, G, n, 0.0);
+    for (int k = 0; k < C.far_count; ++k) {
+      const FarRef F = refs[C.far_begin + k];
+      const FarPair Pq = far[F.ab];  // rows of p, columns of q
+      const int mq = nbrs[R.nb_begin + Pq.b].m;
+      wg_gemm(n, n, mq, 1.0, Pq.F, n, false, Pq.F, n, true, 1.0, G, n);
+    }
+  }
+}
+
+// New bases of a changed node: V' = leading rnew eigenvectors of Gs, U' of Gt;
+// T_p = P2M V' (r x rnew), S_p = U'^T L2P (rnew x r); then overwrite the bases.
+__global__ void k_basis(LevelView V, const Changed* chg) {
+  const Changed C = chg[blockIdx.x];
+  const int p = C.p, n = C.n, r = C.r, rn = C.rnew, rc = V.rc[p];
+  double* P2M = V.arena + V.p2m_off[p];
+  double* L2P = V.arena + V.l2p_off[p];
+  double* sig = V.arena + V.sig_off[p];
+  wg_gemm(r, rn, n, 1.0, P2M, rc, false, C.vs, n, false, 0.0, C.T, r > 0 ? r : 1);
+  wg_gemm(rn, r, n, 1.0, C.vt, n, true, L2P, n, false, 0.0, C.S, rn > 0 ? rn : 1);
+  for (int e = threadIdx.x; e < rn * n; e += NT) {
+    const int a = e % rn, j = e / rn;
+    P2M[a + (int64_t)j * rc] = C.vs[j + (int64_t)a * n];
+  }
+  for (int e = threadIdx.x; e < n * rn; e += NT) {
+    const int j = e % n, a = e / n;
+    L2P[j + (int64_t)a * n] = C.vt[j + (int64_t)a * n];
+  }
+  for (int a = threadIdx.x; a < rn; a += NT) {
+    sig[a] = sqrt(fmax(C.ls[a], 0.0));
+    sig[rc + a] = sqrt(fmax(C.lt[a], 0.0));
+  }
+  __syncthreads();
+}
+
+// Projection of a far fill-in onto the new bases (the final block is left in
+// F with leading dimension = its row count):
+//   both changed   F <- U_a'^T F V_b'     a changed   F <- U_a'^T F
+//   b changed      F <- F V_b'            both eliminated: M2L_ab += F
+// U_a' = L2P_a (n_a x r_a', ld n_a), V_b' = P2M_b^T (P2M_b: r_b' x n_b, ld rc_b).
+__global__ void k_project(LevelView V, const FarPair* far, const ElimRec* recs, const ElimNbr* nbrs,
+                          const Changed* chg) {
+  const FarPair P = far[blockIdx.x];
+  const ElimRec R = recs[P.rec];
+  const ElimNbr A = nbrs[R.nb_begin + P.a], B = nbrs[R.nb_begin + P.b];
+  if (P.direct) {
+    double* dst = V.arena + P.dst;
+    for (int e = threadIdx.x; e < A.m * B.m; e += NT) {
+      const int x = e % A.m, y = e / A.m;
+      dst[x + (int64_t)y * P.dst_ld] += P.F[x + (int64_t)y * A.m];
+    }
+    return;
+  }
+  const int ra = A.elim ? A.m : chg[V.chg[A.p]].rnew;
+  const int rb = B.elim ? B.m : chg[V.chg[B.p]].rnew;
+  if (!A.elim && !B.elim) {
+    wg_gemm(ra, B.m, A.m, 1.0, V.arena + V.l2p_off[A.p], A.m, true, P.F, A.m, false, 0.0, P.D, ra > 0 ? ra : 1);
+    wg_gemm(ra, rb, B.m, 1.0, P.D, ra > 0 ? ra : 1, false, V.arena + V.p2m_off[B.p], V.rc[B.p], true, 0.0, P.F,
+            ra > 0 ? ra : 1);
+  } else if (!A.elim) {
+    wg_gemm(ra, B.m, A.m, 1.0, V.arena + V.l2p_off[A.p], A.m, true, P.F, A.m, false, 0.0, P.D, ra > 0 ? ra : 1);
+    wg_copy(ra, B.m, P.D, ra > 0 ? ra : 1, P.F, ra > 0 ? ra : 1);
+  } else {
+    wg_gemm(A.m, rb, B.m, 1.0, P.F, A.m, false, V.arena + V.p2m_off[B.p], V.rc[B.p], true, 0.0, P.D, A.m);
+    wg_copy(A.m, rb, P.D, A.m, P.F, A.m);
+  }
+}
+
+__device__ inline int find_ref(const FarRef* refs, int begin, int count, int q) {
+  for (int k = 0; k < count; ++k)
+    if (refs[begin + k].q == q) return begin + k;
+  return -1;
+}
+
+// Phase B: push the basis change of a changed node p into the M2L blocks of its
+// interaction list, into M2M_p and L2L_p, and add the projected fill-ins.
+// Owner rule: block (t, s) is transformed by t's workgroup when t changed,
+// else by s's, so every block is written once.
+//   (p, l):              S_p M (T_l if l changed) + D_pl
+//   (l, p), l unchanged: M T_p + D_lp
+__global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* refs, const FarPair* far,
+                          int has_parent) {
+  const Changed C = chg[blockIdx.x];
+  const int p = C.p, r = C.r, rn = C.rnew, rcp = V.rc[p];
+  double* t = C.tmp;
+  for (int s = V.il_ptr[p]; s < V.il_ptr[p + 1]; ++s) {
+    const int l = V.il_idx[s];
+    const int rl = V.r[l];
+    const int lc = V.chg[l];
+    double* M = V.arena + V.il_off[s];
+    const int rln = lc >= 0 ? chg[lc].rnew : rl;
+    // t = M (T_l)   (r x rln, ld r)
+    if (lc >= 0) wg_gemm(r, rln, rl, 1.0, M, rcp, false, chg[lc].T, rl > 0 ? rl : 1, false, 0.0, t, r > 0 ? r : 1);
+    else wg_copy(r, rl, M, rcp, t, r > 0 ? r : 1);
+    // M = S_p t   (rn x rln)
+    wg_gemm(rn, rln, r, 1.0, C.S, rn > 0 ? rn : 1, false, t, r > 0 ? r : 1, false, 0.0, M, rcp);
+    if (r == 0) wg_fill(rn, rln, M, rcp, 0.0);
+    const int k = find_ref(refs, C.far_begin, C.far_count, l);
+    if (k >= 0) {
+      const double* Dm = far[refs[k].ab].F;
+      for (int e = threadIdx.x; e < rn * rln; e += NT) {
+        const int x = e % rn, y = e / rn;
+        M[x + (int64_t)y * rcp] += Dm[x + (int64_t)y * rn];
+      }
+      __syncthreads();
+    }
+  }
+  for (int s = V.il_ptr[p]; s < V.il_ptr[p + 1]; ++s) {
+    const int l = V.il_idx[s];
+    if (V.chg[l] >= 0) continue;
+    const int rl = V.r[l], rcl = V.rc[l];
+    double* M = V.arena + il_block(V, l, p);
+    wg_gemm(rl, rn, r, 1.0, M, rcl, false, C.T, r > 0 ? r : 1, false, 0.0, t, rl > 0 ? rl : 1);
+    wg_copy(rl, rn, t, rl > 0 ? rl : 1, M, rcl);
+    const int k = find_ref(refs, C.far_begin, C.far_count, l);
+    if (k >= 0) {
+      const double* Dm = far[refs[k].ba].F;
+      for (int e = threadIdx.x; e < rl * rn; e += NT) {
+        const int x = e % rl, y = e / rl;
+        M[x + (int64_t)y * rcl] += Dm[x + (int64_t)y * rl];
+      }
+      __syncthreads();
+    }
+  }
+  if (has_parent) {
+    double* M2M = V.arena + V.m2m_off[p];
+    wg_gemm(K, rn, r, 1.0, M2M, K, false, C.T, r > 0 ? r : 1, false, 0.0, t, K);
+    wg_copy(K, rn, t, K, M2M, K);
+    double* L2L = V.arena + V.l2l_off[p];
+    wg_gemm(rn, K, r, 1.0, C.S, rn > 0 ? rn : 1, false, L2L, rcp, false, 0.0, t, rn > 0 ? rn : 1);
+    wg_copy(rn, K, t, rn > 0 ? rn : 1, L2L, rcp);
+  }
+}
+
+__global__ void k_set_rank(int32_t* r, const Changed* chg, int nchg) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k < nchg) r[chg[k].p] = chg[k].rnew;
+}
+
+__global__ void k_set_chg(int32_t* chgidx, const Changed* chg, int nchg, int clear) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k < nchg) chgidx[chg[k].p] = clear ? -1 : k;
+}
+
+// ------------------------------------------------------------------ top level
+// Dense system of all level-2 M2L blocks (near blocks for dist <= 1).
+__global__ void k_top_assemble(LevelView V, int nn, const int64_t* top_off, double* T, int ldt) {
+  const int P = blockIdx.x;
+  const int rP = V.r[P];
+  for (int Q = 0; Q < nn; ++Q) {
+    const int rQ = V.r[Q];
+    if (rP == 0 || rQ == 0) continue;
+    double* dst = T + top_off[P] + (int64_t)top_off[Q] * ldt;
+    if (dist3(V.coord, P, Q) <= 1) wg_copy(rP, rQ, V.arena + near_block(V, P, Q), V.n[P], dst, ldt);
+    else wg_copy(rP, rQ, V.arena + il_block(V, P, Q), V.rc[P], dst, ldt);
+  }
+}
+
+__global__ void k_top_getrf(double* T, int n, int32_t* piv, int32_t* info) {
+  const int inf = wg_getrf(n, T, n, piv);
+  if (threadIdx.x == 0) *info = inf;
+}
+
+// ------------------------------------------------------------------ solve
+// Node vectors per level: X (x-part, n_i x k at xo[i] * k) and Z (z-part /
+// later y-part, r_i x k at zo[i] * k); W: w_i (d x k) per elimination.
+struct SolveView {
+  double *X, *Z, *W, *tmp;
+  const int64_t *xo, *zo;
+  int k;
+};
+
+__global__ void k_perm_in(const double* b, int64_t ld, int k, const int64_t* perm, const int64_t* pt_begin,
+                          const int32_t* n, SolveView S) {
+  const int i = blockIdx.x;
+  const int ni = n[i];
+  double* Xi = S.X + S.xo[i] * S.k;
+  for (int e = threadIdx.x; e < ni * k; e += NT) {
+    const int a = e % ni, c = e / ni;
+    Xi[a + (int64_t)c * ni] = b[perm[pt_begin[i] + a] + (int64_t)c * ld];
+  }
+}
+
+__global__ void k_perm_out(double* x, int64_t ld, int k, const int64_t* perm, const int64_t* pt_begin,
+                           const int32_t* n, SolveView S) {
+  const int i = blockIdx.x;
+  const int ni = n[i];
+  const double* Xi = S.X + S.xo[i] * S.k;
+  for (int e = threadIdx.x; e < ni * k; e += NT) {
+    const int a = e % ni, c = e / ni;
+    x[perm[pt_begin[i] + a] + (int64_t)c * ld] = Xi[a + (int64_t)c * ni];
+  }
+}
+
+// Forward substitution of one elimination (Alg. 2, upward pass):
+//   w = D^-1 [x_i; 0];  rows of neighbour p -= L_p w_top;  z_i += w_bot.
+__global__ void k_fwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S, const int32_t* rnow) {
+  const ElimRec R = recs[blockIdx.x];
+  const int n = R.n, r = R.r, d = R.d, k = S.k;
+  double* w = S.W + R.wv * k;
+  const double* xi = S.X + S.xo[R.node] * k;
+  for (int e = threadIdx.x; e < d * k; e += NT) {
+    const int a = e % d, c = e / d;
+    w[a + (int64_t)c * d] = a < n ? xi[a + (int64_t)c * n] : 0.0;
+  }
+  __syncthreads();
+  if (d == 0) return;
+  wg_getrs(d, R.lu, d, R.piv, w, d, k);
+  for (int e = 0; e < R.nnb; ++e) {
+    const ElimNbr B = nbrs[R.nb_begin + e];
+    double* tgt = B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k;
+    if (B.m > 0 && n > 0) wg_gemm(B.m, k, n, -1.0, R.L + B.off, R.M, false, w, d, false, 1.0, tgt, B.m);
+  }
+  double* zi = S.Z + S.zo[R.node] * k;
+  for (int e = threadIdx.x; e < r * k; e += NT) {
+    const int a = e % r, c = e / r;
+    zi[a + (int64_t)c * r] += w[n + a + (int64_t)c * d];
+  }
+  (void)rnow;
+}
+
+// Backward substitution of one elimination (Alg. 2, downward pass):
+//   [x_i; z_i] = w - D^-1 [sum_q U_q x_q; -y_i]
+__global__ void k_bwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
+  const ElimRec R = recs[blockIdx.x];
+  const int n = R.n, r = R.r, d = R.d, k = S.k;
+  if (d == 0) return;
+  double* t = S.tmp + R.wv * k;
+  const double* w = S.W + R.wv * k;
+  const double* yi = S.Z + S.zo[R.node] * k;
+  for (int e = threadIdx.x; e < d * k; e += NT) {
+    const int a = e % d, c = e / d;
+    t[a + (int64_t)c * d] = a < n ? 0.0 : -yi[(a - n) + (int64_t)c * r];
+  }
+  __syncthreads();
+  for (int e = 0; e < R.nnb; ++e) {
+    const ElimNbr B = nbrs[R.nb_begin + e];
+    const double* xq = B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k;
+    if (B.m > 0 && n > 0) wg_gemm(n, k, B.m, 1.0, R.U + (int64_t)B.off * n, n, false, xq, B.m, false, 1.0, t, d);
+  }
+  wg_getrs(d, R.lu, d, R.piv, t, d, k);
+  double* xi = S.X + S.xo[R.node] * k;
+  for (int e = threadIdx.x; e < n * k; e += NT) {
+    const int a = e % n, c = e / n;
+    xi[a + (int64_t)c * n] = w[a + (int64_t)c * d] - t[a + (int64_t)c * d];
+  }
+}
+
+// Level change of the node vectors: x_P = [z_c ...] (up) / y_c = slices of x_P (down).
+__global__ void k_vec_up(SolveView F, SolveView C, const int32_t* child_ptr, const int32_t* child,
+                         const int32_t* rF, const int32_t* nC) {
+  const int P = blockIdx.x;
+  const int k = F.k, nP = nC[P];
+  double* xP = C.X + C.xo[P] * k;
+  int off = 0;
+  for (int s = child_ptr[P]; s < child_ptr[P + 1]; ++s) {
+    const int c = child[s], rc = rF[c];
+    const double* zc = F.Z + F.zo[c] * k;
+    for (int e = threadIdx.x; e < rc * k; e += NT) {
+      const int a = e % rc, col = e / rc;
+      xP[off + a + (int64_t)col * nP] = zc[a + (int64_t)col * rc];
+    }
+    off += rc;
+  }
+}
+
+__global__ void k_vec_down(SolveView F, SolveView C, const int32_t* child_ptr, const int32_t* child,
+                           const int32_t* rF, const int32_t* nC) {
+  const int P = blockIdx.x;
+  const int k = F.k, nP = nC[P];
+  const double* xP = C.X + C.xo[P] * k;
+  int off = 0;
+  for (int s = child_ptr[P]; s < child_ptr[P + 1]; ++s) {
+    const int c = child[s], rc = rF[c];
+    double* yc = F.Z + F.zo[c] * k;
+    for (int e = threadIdx.x; e < rc * k; e += NT) {
+      const int a = e % rc, col = e / rc;
+      yc[a + (int64_t)col * rc] = xP[off + a + (int64_t)col * nP];
+    }
+    off += rc;
+  }
+}
+
+// Dense top solve: y = T^-1 [z_P ...], written back into the z slots as y.
+__global__ void k_top_solve(SolveView S, int nn, const int32_t* r, const int64_t* top_off, const double* T,
+                            int ldt, const int32_t* piv, double* buf) {
+  const int k = S.k;
+  for (int P = 0; P < nn; ++P) {
+    const int rP = r[P];
+    const double* z = S.Z + S.zo[P] * k;
+    for (int e = threadIdx.x; e < rP * k; e += NT) {
+      const int a = e % rP, c = e / rP;
+      buf[top_off[P] + a + (int64_t)c * ldt] = z[a + (int64_t)c * rP];
+    }
+  }
+  __syncthreads();
+  wg_getrs(ldt, T, ldt, piv, buf, ldt, k);
+  for (int P = 0; P < nn; ++P) {
+    const int rP = r[P];
+    double* z = S.Z + S.zo[P] * k;
+    for (int e = threadIdx.x; e < rP * k; e += NT) {
+      const int a = e % rP, c = e / rP;
+      z[a + (int64_t)c * rP] = buf[top_off[P] + a + (int64_t)c * ldt];
+    }
+  }
+}
+
+}  // namespace ifmm

@@ -1,0 +1,245 @@
+// Host octree, lists and colouring (see tree.hpp).  Compiled with
+// -ffp-contract=off so that the box keys are reproducible bit for bit.
+#include "tree.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <numeric>
+#include <unordered_map>
+
+namespace ifmm {
+
+int Level::dist(int32_t a, int32_t b) const {
+  int d = 0;
+  for (int e = 0; e < 3; ++e) d = std::max(d, std::abs(coord[3 * a + e] - coord[3 * b + e]));
+  return d;
+}
+
+static inline int64_t lex(int32_t i, int32_t j, int32_t k, int64_t m) { return ((int64_t)k * m + j) * m + i; }
+
+int32_t colour_grid(const std::vector<uint8_t>& occ, int m, int sigma, std::vector<int32_t>& colour) {
+  const int64_t M = m;
+  colour.assign((size_t)(M * M * M), -1);
+  auto at = [&](int k, int j, int i) { return (size_t)((k * M + j) * M + i); };
+  int32_t g = 0;
+  for (int k0 = 0; k0 < m; ++k0)
+    for (int j0 = 0; j0 < m; ++j0)
+      for (int i0 = 0; i0 < m; ++i0) {
+        if (!occ[at(k0, j0, i0)] || colour[at(k0, j0, i0)] >= 0) continue;
+        colour[at(k0, j0, i0)] = g;  // first node of colour g
+        bool jstride = true, kstride = true;
+        int k = k0;
+        while (k < m) {
+          int j = (k == k0) ? j0 : 0;
+          while (j < m) {
+            int i = (j == j0 && k == k0) ? i0 + sigma : 0;
+            while (i < m) {
+              if (occ[at(k, j, i)] && colour[at(k, j, i)] < 0) {
+                colour[at(k, j, i)] = g;
+                i += sigma;
+                jstride = true;
+                kstride = true;
+              } else {
+                i += 1;
+              }
+            }
+            j = jstride ? j + sigma : j + 1;
+            jstride = false;
+          }
+          k = kstride ? k + sigma : k + 1;
+          kstride = false;
+        }
+        ++g;
+      }
+  return g;
+}
+
+void Tree::box(int l, int32_t i, double c[3], double* half) const {
+  const double side = 2.0 * H / (double)(1LL << l);
+  const Level& L = levels[l];
+  for (int e = 0; e < 3; ++e) c[e] = lo[e] + ((double)L.coord[3 * i + e] + 0.5) * side;
+  *half = side / 2.0;
+}
+
+static void point_keys(const double* pts, int64_t n, const double lo[3], double H, int level,
+                       std::vector<int32_t>& key) {
+  const int64_t m = 1LL << level;
+  const double s = (double)m / (2.0 * H);
+  key.resize((size_t)(3 * n));
+  for (int64_t p = 0; p < n; ++p)
+    for (int e = 0; e < 3; ++e) {
+      const double t = (pts[3 * p + e] - lo[e]) * s;
+      double f = std::floor(t);
+      if (f < 0.0) f = 0.0;
+      if (f > (double)(m - 1)) f = (double)(m - 1);
+      key[3 * p + e] = (int32_t)f;
+    }
+}
+
+std::string Tree::build(const double* pts, int64_t n, int leaf_max, int sig) {
+  if (n < 1) return "need at least one point";
+  if (leaf_max < 1) return "leaf_max must be positive";
+  sigma = sig;
+  double pmin[3], pmax[3];
+  for (int e = 0; e < 3; ++e) {
+    pmin[e] = pts[e];
+    pmax[e] = pts[e];
+  }
+  for (int64_t p = 0; p < n; ++p)
+    for (int e = 0; e < 3; ++e) {
+      const double v = pts[3 * p + e];
+      if (!std::isfinite(v)) return "non-finite coordinate";
+      pmin[e] = std::min(pmin[e], v);
+      pmax[e] = std::max(pmax[e], v);
+    }
+  double ext = 0.0;
+  for (int e = 0; e < 3; ++e) ext = std::max(ext, pmax[e] - pmin[e]);
+  H = ext / 2.0;
+  if (!(H > 0.0)) return "all points coincide";
+  for (int e = 0; e < 3; ++e) {
+    const double centre = (pmin[e] + pmax[e]) / 2.0;
+    lo[e] = centre - H;
+  }
+  // depth: smallest level >= 2 whose fullest leaf holds <= leaf_max points
+  std::vector<int32_t> key;
+  std::vector<int64_t> code((size_t)n);
+  int L = 2;
+  for (;; ++L) {
+    if (L > 10) return "leaf size not reachable (too many coincident points)";
+    point_keys(pts, n, lo, H, L, key);
+    const int64_t m = 1LL << L;
+    for (int64_t p = 0; p < n; ++p) code[p] = lex(key[3 * p], key[3 * p + 1], key[3 * p + 2], m);
+    std::vector<int64_t> sorted(code);
+    std::sort(sorted.begin(), sorted.end());
+    int64_t best = 0;
+    for (int64_t a = 0; a < n;) {
+      int64_t b = a;
+      while (b < n && sorted[b] == sorted[a]) ++b;
+      best = std::max(best, b - a);
+      a = b;
+    }
+    if (best <= leaf_max) break;
+  }
+  depth = L;
+  perm.resize((size_t)n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return code[a] < code[b]; });
+  levels.assign((size_t)L + 1, Level());
+  // leaf level
+  {
+    Level& lv = levels[L];
+    lv.level = L;
+    for (int64_t t = 0; t < n;) {
+      int64_t u = t;
+      const int64_t c = code[perm[t]];
+      while (u < n && code[perm[u]] == c) ++u;
+      const int64_t p = perm[t];
+      lv.coord.push_back(key[3 * p]);
+      lv.coord.push_back(key[3 * p + 1]);
+      lv.coord.push_back(key[3 * p + 2]);
+      lv.pt_begin.push_back(t);
+      lv.pt_end.push_back(u);
+      t = u;
+    }
+    lv.n = (int32_t)lv.pt_begin.size();
+  }
+  // coarser levels by shifting coordinates
+  for (int l = L - 1; l >= 2; --l) {
+    const Level& f = levels[l + 1];
+    Level& c = levels[l];
+    c.level = l;
+    const int64_t m = 1LL << l;
+    std::vector<std::pair<int64_t, int32_t>> codes;
+    codes.reserve(f.n);
+    for (int32_t i = 0; i < f.n; ++i)
+      codes.push_back({lex(f.coord[3 * i] >> 1, f.coord[3 * i + 1] >> 1, f.coord[3 * i + 2] >> 1, m), i});
+    std::sort(codes.begin(), codes.end());
+    for (size_t a = 0; a < codes.size(); ++a) {
+      if (a > 0 && codes[a].first == codes[a - 1].first) continue;
+      const int32_t i = codes[a].second;
+      c.coord.push_back(f.coord[3 * i] >> 1);
+      c.coord.push_back(f.coord[3 * i + 1] >> 1);
+      c.coord.push_back(f.coord[3 * i + 2] >> 1);
+    }
+    c.n = (int32_t)(c.coord.size() / 3);
+  }
+  // parent / children and lists
+  for (int l = 2; l <= L; ++l) {
+    Level& lv = levels[l];
+    const int64_t m = 1LL << l;
+    std::unordered_map<int64_t, int32_t> index;
+    index.reserve((size_t)lv.n * 2);
+    for (int32_t i = 0; i < lv.n; ++i) index[lex(lv.coord[3 * i], lv.coord[3 * i + 1], lv.coord[3 * i + 2], m)] = i;
+    auto find = [&](int i, int j, int k) -> int32_t {
+      if (i < 0 || j < 0 || k < 0 || i >= m || j >= m || k >= m) return -1;
+      auto it = index.find(lex(i, j, k, m));
+      return it == index.end() ? -1 : it->second;
+    };
+    lv.parent.assign((size_t)lv.n, -1);
+    if (l > 2) {
+      const Level& pc = levels[l - 1];
+      const int64_t mp = 1LL << (l - 1);
+      std::unordered_map<int64_t, int32_t> pidx;
+      pidx.reserve((size_t)pc.n * 2);
+      for (int32_t i = 0; i < pc.n; ++i) pidx[lex(pc.coord[3 * i], pc.coord[3 * i + 1], pc.coord[3 * i + 2], mp)] = i;
+      for (int32_t i = 0; i < lv.n; ++i)
+        lv.parent[i] = pidx.at(lex(lv.coord[3 * i] >> 1, lv.coord[3 * i + 1] >> 1, lv.coord[3 * i + 2] >> 1, mp));
+    }
+    lv.nbr_ptr.assign(1, 0);
+    lv.il_ptr.assign(1, 0);
+    for (int32_t a = 0; a < lv.n; ++a) {
+      const int x = lv.coord[3 * a], y = lv.coord[3 * a + 1], z = lv.coord[3 * a + 2];
+      for (int dk = -1; dk <= 1; ++dk)
+        for (int dj = -1; dj <= 1; ++dj)
+          for (int di = -1; di <= 1; ++di) {
+            if (!di && !dj && !dk) continue;
+            const int32_t v = find(x + di, y + dj, z + dk);
+            if (v >= 0) lv.nbr.push_back(v);
+          }
+      lv.nbr_ptr.push_back((int32_t)lv.nbr.size());
+      // interaction list: children of the parent's neighbours (the whole
+      // 6 x 6 x 6 block around the parent) at distance >= 2
+      const int bx = 2 * (x >> 1) - 2, by = 2 * (y >> 1) - 2, bz = 2 * (z >> 1) - 2;
+      for (int k = bz; k < bz + 6; ++k)
+        for (int j = by; j < by + 6; ++j)
+          for (int i = bx; i < bx + 6; ++i) {
+            const int d = std::max(std::abs(i - x), std::max(std::abs(j - y), std::abs(k - z)));
+            if (d < 2) continue;
+            const int32_t v = find(i, j, k);
+            if (v >= 0) lv.il.push_back(v);
+          }
+      lv.il_ptr.push_back((int32_t)lv.il.size());
+    }
+    // colouring (Alg. 3)
+    std::vector<uint8_t> occ((size_t)(m * m * m), 0);
+    for (int32_t i = 0; i < lv.n; ++i) occ[(size_t)lex(lv.coord[3 * i], lv.coord[3 * i + 1], lv.coord[3 * i + 2], m)] = 1;
+    std::vector<int32_t> grid;
+    lv.ncolour = colour_grid(occ, (int)m, sigma, grid);
+    lv.colour.resize((size_t)lv.n);
+    std::vector<int32_t> cnt((size_t)lv.ncolour + 1, 0);
+    for (int32_t i = 0; i < lv.n; ++i) {
+      lv.colour[i] = grid[(size_t)lex(lv.coord[3 * i], lv.coord[3 * i + 1], lv.coord[3 * i + 2], m)];
+      cnt[lv.colour[i] + 1]++;
+    }
+    for (int32_t c = 0; c < lv.ncolour; ++c) cnt[c + 1] += cnt[c];
+    lv.grp_ptr = cnt;
+    lv.grp.resize((size_t)lv.n);
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int32_t i = 0; i < lv.n; ++i) lv.grp[fill[lv.colour[i]]++] = i;
+  }
+  for (int l = 2; l < L; ++l) {
+    Level& c = levels[l];
+    const Level& f = levels[l + 1];
+    std::vector<int32_t> cnt((size_t)c.n + 1, 0);
+    for (int32_t i = 0; i < f.n; ++i) cnt[f.parent[i] + 1]++;
+    for (int32_t i = 0; i < c.n; ++i) cnt[i + 1] += cnt[i];
+    c.child_ptr = cnt;
+    c.child.resize((size_t)f.n);
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int32_t i = 0; i < f.n; ++i) c.child[fill[f.parent[i]]++] = i;
+  }
+  return std::string();
+}
+
+}  // namespace ifmm

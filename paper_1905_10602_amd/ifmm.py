@@ -1,0 +1,195 @@
+"""ctypes binding of the C ABI in include/ifmm.h (argument marshalling only).
+
+Host arrays are numpy; device arrays are torch tensors on the GPU (PyTorch is
+used for device memory and streams only).  Every entry point maps to one C
+call; no step of the method runs in Python.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+STATUS = {0: "IFMM_OK", -1: "IFMM_EINVAL", -2: "IFMM_ENOMEM", -3: "IFMM_EDEVICE", -4: "IFMM_ESINGULAR",
+          -5: "IFMM_ENONFINITE", -6: "IFMM_ESTATE", -7: "IFMM_ENOCONV"}
+
+
+class IfmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Options(C.Structure):
+    _fields_ = [("leaf_max", C.c_int32), ("cheb_order", C.c_int32), ("precision", C.c_int32),
+                ("rank_cap", C.c_int32), ("max_device_bytes", C.c_int64), ("stream", C.c_void_p)]
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libifmm.so")
+
+
+def load_library():
+    """Loads libifmm.so from the package directory (raises if it is not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() or paper_1905_10602_amd/build.py")
+    lib = C.CDLL(path)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "ifmm_default_options": (None, [C.POINTER(Options)]),
+        "ifmm_build": (I32, [P, I64, P, P, D, I32, D, I32, C.POINTER(Options), C.POINTER(P)]),
+        "ifmm_factor": (I32, [P]),
+        "ifmm_solve": (I32, [P, P, P, I32, I64, I32]),
+        "ifmm_stats": (I32, [P, C.c_char_p, I64]),
+        "ifmm_tree_depth": (I32, [P, C.POINTER(I32)]),
+        "ifmm_tree_perm": (I32, [P, P]),
+        "ifmm_tree_level": (I32, [P, I32, C.POINTER(I32), P, P, P, C.POINTER(I32)]),
+        "ifmm_tree_lists": (I32, [P, I32, I32, P, P]),
+        "ifmm_ranks": (I32, [P, I32, P]),
+        "ifmm_last_error": (C.c_char_p, []),
+        "ifmm_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _check(code):
+    if code != 0:
+        msg = load_library().ifmm_last_error().decode(errors="replace")
+        raise IfmmError(code, msg)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class IFMM:
+    """Handle of one factorisation (ifmm_build / ifmm_factor / ifmm_solve)."""
+
+    def __init__(self, points, eps, sigma, diag=None, weights=None, leaf_max=64, cheb_order=4, rank_cap=0,
+                 max_device_bytes=0, stream=None):
+        lib = load_library()
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        if pts.ndim != 2 or pts.shape[1] != 3:
+            raise ValueError("points must be (N, 3)")
+        self.N = pts.shape[0]
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        dvec, dsc = None, 0.0
+        if diag is None:
+            raise ValueError("diag (scalar or array) is required")
+        if np.isscalar(diag):
+            dsc = float(diag)
+        else:
+            dvec = np.ascontiguousarray(diag, dtype=np.float64)
+        opt = Options()
+        lib.ifmm_default_options(C.byref(opt))
+        opt.leaf_max = leaf_max
+        opt.cheb_order = cheb_order
+        opt.rank_cap = rank_cap
+        opt.max_device_bytes = max_device_bytes
+        opt.stream = None if stream is None else C.c_void_p(stream)
+        h = C.c_void_p()
+        _check(lib.ifmm_build(_ptr(pts), self.N, _ptr(w), _ptr(dvec), dsc, 0, float(eps), int(sigma),
+                              C.byref(opt), C.byref(h)))
+        self._h = h
+        self.eps = eps
+        self.sigma = sigma
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ifmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- method
+    def factor(self):
+        _check(load_library().ifmm_factor(self._h))
+        return self
+
+    def solve(self, b):
+        """b: numpy (N,) / (N, k) on the host, or a torch tensor on the GPU
+        (column-major (N, k) is taken as b.T contiguous (k, N))."""
+        lib = load_library()
+        if hasattr(b, "is_cuda") and b.is_cuda:
+            import torch
+            vec = b.dim() == 1
+            B = b.reshape(-1, 1) if vec else b
+            k = B.shape[1]
+            Bc = B.t().contiguous()  # (k, N) row-major == (N, k) column-major
+            X = torch.empty_like(Bc)
+            _check(lib.ifmm_solve(self._h, _ptr(Bc), _ptr(X), k, self.N, 1))
+            out = X.t()
+            return out[:, 0] if vec else out
+        B = np.asarray(b, dtype=np.float64)
+        vec = B.ndim == 1
+        Bf = np.asfortranarray(B.reshape(self.N, -1))
+        X = np.empty_like(Bf, order="F")
+        _check(lib.ifmm_solve(self._h, _ptr(Bf), _ptr(X), Bf.shape[1], self.N, 0))
+        return X[:, 0] if vec else X
+
+    def stats(self):
+        buf = C.create_string_buffer(1 << 16)
+        _check(load_library().ifmm_stats(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    # -- structure queries
+    def depth(self):
+        d = C.c_int32()
+        _check(load_library().ifmm_tree_depth(self._h, C.byref(d)))
+        return d.value
+
+    def perm(self):
+        p = np.empty(self.N, dtype=np.int64)
+        _check(load_library().ifmm_tree_perm(self._h, _ptr(p)))
+        return p
+
+    def level(self, lvl):
+        lib = load_library()
+        nn = C.c_int32()
+        _check(lib.ifmm_tree_level(self._h, lvl, C.byref(nn), None, None, None, None))
+        n = nn.value
+        coords = np.empty((n, 3), dtype=np.int32)
+        parent = np.empty(n, dtype=np.int32)
+        colour = np.empty(n, dtype=np.int32)
+        nc = C.c_int32()
+        _check(lib.ifmm_tree_level(self._h, lvl, C.byref(nn), _ptr(coords), _ptr(parent), _ptr(colour),
+                                   C.byref(nc)))
+        return {"coords": coords, "parent": parent, "colour": colour, "ncolour": nc.value}
+
+    def lists(self, lvl, which):
+        lib = load_library()
+        n = self.level(lvl)["coords"].shape[0]
+        ptr = np.empty(n + 1, dtype=np.int32)
+        _check(lib.ifmm_tree_lists(self._h, lvl, which, _ptr(ptr), None))
+        idx = np.empty(int(ptr[-1]), dtype=np.int32)
+        _check(lib.ifmm_tree_lists(self._h, lvl, which, _ptr(ptr), _ptr(idx)))
+        return ptr, idx
+
+    def ranks(self, lvl):
+        n = self.level(lvl)["coords"].shape[0]
+        r = np.empty(n, dtype=np.int32)
+        _check(load_library().ifmm_ranks(self._h, lvl, _ptr(r)))
+        return r

@@ -1,0 +1,113 @@
+"""Parity of the HIP factorisation and solve with the CPU oracle.
+
+All device work goes through the C ABI (paper_1905_10602_amd.ifmm).  Expected
+values come from the oracle (oracle/) run on the same seeded inputs.
+Tolerances:
+  * eps -> 0: both reproduce the dense LU solve of the represented matrix,
+    so they must agree with it to 1e-10 (relative forward error);
+  * eps = 1e-6: the two implementations take the same truncation decisions
+    except at ties (Gram eigenvalues on the GPU vs an SVD in the oracle), so
+    the solutions agree to well within 10 eps relative, and the GPU solution
+    has a normwise backward error <= 10 eps.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.ifmm import IFMM as Oracle, dense_tilde
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(shape, N, seed):
+    kw = {"jitter": 0.05} if shape == "ellipsoid" else {}
+    pts = synth.geometry_points(shape, N, seed, **kw)
+    area = {"sphere": 4 * np.pi, "ellipsoid": 2.6, "cube": 24.0}[shape]
+    return pts, synth.laplace_self_term(N, area)
+
+
+def _gpu(pts, eps, sigma, dg, leaf, **kw):
+    from paper_1905_10602_amd import IFMM
+    return IFMM(pts, eps, sigma, diag=dg, leaf_max=leaf, **kw).factor()
+
+
+@pytest.mark.parametrize("shape,N,leaf,sigma", [("sphere", 500, 8, 3), ("cube", 600, 12, 6)])
+def test_exact_limit_matches_dense_lu(shape, N, leaf, sigma):
+    print(f"case exact {shape} N={N} leaf={leaf} sigma={sigma}", flush=True)
+    pts, dg = _case(shape, N, 21)
+    b = synth.uniform_rhs(N, 2, 101)
+    At = dense_tilde(pts, None, dg, leaf_max=leaf)
+    xd = np.linalg.solve(At, b)
+    h = _gpu(pts, 1e-14, sigma, dg, leaf)
+    assert h.depth() >= 3
+    x = h.solve(b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
+
+
+@pytest.mark.parametrize("shape,N,leaf,sigma,eps", [
+    ("sphere", 4096, 64, 6, 1e-6),      # the N = 4096 sphere workload
+    ("sphere", 1500, 24, 3, 1e-4),      # strong compression, depth 3
+    ("ellipsoid", 3000, 32, 3, 1e-6),
+    ("cube", 2000, 20, 6, 1e-5),
+])
+def test_matches_oracle(shape, N, leaf, sigma, eps):
+    print(f"case oracle {shape} N={N} leaf={leaf} sigma={sigma} eps={eps}", flush=True)
+    pts, dg = _case(shape, N, 1)
+    b = synth.uniform_rhs(N, 3, 101)
+    ref = Oracle(pts, eps=eps, sigma=sigma, diag=dg, leaf_max=leaf).factor()
+    xo = ref.solve(b)
+    h = _gpu(pts, eps, sigma, dg, leaf)
+    x = h.solve(b)
+    rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    assert rel <= 10 * eps, rel
+    # ranks agree except at truncation ties
+    for lvl in range(2, ref.depth + 1):
+        ro = ref.state[lvl]["r"]
+        rg = h.ranks(lvl)
+        assert np.mean(ro != rg) <= 0.02
+        assert np.abs(ro - rg).max() <= 2
+
+
+def test_weighted_columns_and_diag_vector():
+    N = 1200
+    pts = synth.sphere_points(N, 4)
+    rng = np.random.default_rng(4)
+    w = rng.uniform(0.5, 2.0, N) * (4 * np.pi / N)
+    dg = w * synth.laplace_self_term(N) * (N / (4 * np.pi))
+    b = synth.uniform_rhs(N, 1, 7)[:, 0]
+    eps = 1e-6
+    ref = Oracle(pts, eps=eps, sigma=3, diag=dg, weights=w, leaf_max=20).factor()
+    h = _gpu(pts, eps, 3, dg, 20, weights=w)
+    x, xo = h.solve(b), ref.solve(b)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 10 * eps
+
+
+def test_multi_rhs_device_pointers_and_determinism():
+    import torch
+    N = 2500
+    pts, dg = _case("sphere", N, 3)
+    h = _gpu(pts, 1e-6, 3, dg, 32)
+    b = synth.uniform_rhs(N, 4, 11)
+    x = h.solve(b)
+    for k in range(4):
+        xk = h.solve(b[:, k])
+        assert np.allclose(xk, x[:, k], rtol=0, atol=1e-12 * np.abs(x).max())
+    bt = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    xt = h.solve(bt).cpu().numpy()
+    assert np.array_equal(xt, x)
+    # refactorisation and a second handle give bitwise-identical results
+    x2 = h.factor().solve(b)
+    assert np.array_equal(x2, x)
+    x3 = _gpu(pts, 1e-6, 3, dg, 32).solve(b)
+    assert np.array_equal(x3, x)
+
+
+def test_backward_error_at_eps():
+    N = 3000
+    pts, dg = _case("sphere", N, 8)
+    b = synth.uniform_rhs(N, 1, 5)[:, 0]
+    At = dense_tilde(pts, None, dg, leaf_max=40)
+    for eps in (1e-3, 1e-6):
+        x = _gpu(pts, eps, 3, dg, 40).solve(b)
+        r = np.linalg.norm(At @ x - b)
+        assert r / (np.linalg.norm(At, 2) * np.linalg.norm(x) + np.linalg.norm(b)) <= 10 * eps
