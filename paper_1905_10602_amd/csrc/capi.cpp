@@ -23,6 +23,7 @@ int build_host(Handle& h, const double* pts, int64_t n, const double* w, const d
   err = h.tree.build(pts, n, h.leaf_max, h.sigma);
   if (!err.empty()) return IFMM_EINVAL;
   h.N = n;
+  h.symmetric = (w == nullptr);
   h.pts.resize((size_t)(3 * n));
   h.w.resize((size_t)n);
   h.diag.resize((size_t)n);

@@ -13,7 +13,14 @@
 namespace ifmm {
 
 constexpr int NT = 256;           // threads per workgroup
-constexpr int JAC_MAXPAIR = 1024;  // Jacobi eigen-solver handles n <= 2048
+
+// Workgroup-strided loop over an R x C index range, rows fastest (coalesced
+// for column-major data).  One 32-bit division at entry, none per step.
+// Requires R > 0.
+#define WG_FOR2(R, C, i, c)                                                                          \
+  for (int i = (int)(threadIdx.x % (unsigned)(R)), c = (int)(threadIdx.x / (unsigned)(R)),           \
+           i##_di = (int)((unsigned)NT % (unsigned)(R)), i##_dc = (int)((unsigned)NT / (unsigned)(R)); \
+       c < (C); i += i##_di, c += i##_dc, (i >= (R) ? (i -= (R), ++c) : 0))
 
 // C(m x n) = alpha * op(A) * op(B) + beta * C, op = transpose if tA / tB.
 // op(A) is m x k, op(B) is k x n.  beta == 0 overwrites C (NaNs in C ignored).
@@ -84,19 +91,15 @@ __device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* 
 
 // dst(m x n) = alpha * src
 __device__ inline void wg_copy(int m, int n, const double* src, int lds, double* dst, int ldd, double alpha = 1.0) {
-  const int64_t tot = (int64_t)m * n;
-  for (int64_t e = threadIdx.x; e < tot; e += NT) {
-    const int i = (int)(e % m), j = (int)(e / m);
-    dst[i + (int64_t)j * ldd] = alpha * src[i + (int64_t)j * lds];
+  if (m > 0) {
+    WG_FOR2(m, n, i, j) dst[i + (int64_t)j * ldd] = alpha * src[i + (int64_t)j * lds];
   }
   __syncthreads();
 }
 
 __device__ inline void wg_fill(int m, int n, double* dst, int ldd, double v) {
-  const int64_t tot = (int64_t)m * n;
-  for (int64_t e = threadIdx.x; e < tot; e += NT) {
-    const int i = (int)(e % m), j = (int)(e / m);
-    dst[i + (int64_t)j * ldd] = v;
+  if (m > 0) {
+    WG_FOR2(m, n, i, j) dst[i + (int64_t)j * ldd] = v;
   }
   __syncthreads();
 }
@@ -113,8 +116,10 @@ __device__ inline int wg_getrf(int d, double* A, int lda, int32_t* piv) {
   __syncthreads();
   const int tid = threadIdx.x;
   for (int j = 0; j < d; ++j) {
+    // start at the diagonal so that the pivot index stays in range even for a
+    // column of NaNs (no comparison below succeeds then)
     double best = -1.0;
-    int bi = d;
+    int bi = j;
     for (int i = j + tid; i < d; i += NT) {
       const double v = fabs(A[i + (int64_t)j * lda]);
       if (v > best) { best = v; bi = i; }
@@ -152,10 +157,12 @@ __device__ inline int wg_getrf(int d, double* A, int lda, int32_t* piv) {
     }
     __syncthreads();
     const int rem = d - j - 1;
-    const int64_t tot = (int64_t)rem * rem;
-    for (int64_t e = tid; e < tot; e += NT) {
-      const int i = j + 1 + (int)(e % rem), c = j + 1 + (int)(e / rem);
-      A[i + (int64_t)c * lda] -= A[i + (int64_t)j * lda] * A[j + (int64_t)c * lda];
+    if (rem > 0) {
+      const double* colj = A + j + 1 + (int64_t)j * lda;
+      WG_FOR2(rem, rem, ii, cc) {
+        double* a = A + (j + 1 + ii) + (int64_t)(j + 1 + cc) * lda;
+        *a -= colj[ii] * A[j + (int64_t)(j + 1 + cc) * lda];
+      }
     }
     __syncthreads();
   }
@@ -182,11 +189,8 @@ __device__ inline void wg_getrs(int d, const double* LU, int lda, const int32_t*
   // forward: unit lower
   for (int j = 0; j < d - 1; ++j) {
     const int rem = d - j - 1;
-    const int64_t tot = (int64_t)rem * nc;
-    for (int64_t e = tid; e < tot; e += NT) {
-      const int i = j + 1 + (int)(e % rem), c = (int)(e / rem);
-      B[i + (int64_t)c * ldb] -= LU[i + (int64_t)j * lda] * B[j + (int64_t)c * ldb];
-    }
+    const double* lj = LU + j + 1 + (int64_t)j * lda;
+    WG_FOR2(rem, nc, ii, c) B[j + 1 + ii + (int64_t)c * ldb] -= lj[ii] * B[j + (int64_t)c * ldb];
     __syncthreads();
   }
   // backward: upper
@@ -194,10 +198,268 @@ __device__ inline void wg_getrs(int d, const double* LU, int lda, const int32_t*
     const double djj = LU[j + (int64_t)j * lda];
     for (int c = tid; c < nc; c += NT) B[j + (int64_t)c * ldb] /= djj;
     __syncthreads();
-    const int64_t tot = (int64_t)j * nc;
-    for (int64_t e = tid; e < tot; e += NT) {
-      const int i = (int)(e % j), c = (int)(e / j);
-      B[i + (int64_t)c * ldb] -= LU[i + (int64_t)j * lda] * B[j + (int64_t)c * ldb];
+    if (j > 0) {
+      const double* uj = LU + (int64_t)j * lda;
+      WG_FOR2(j, nc, i, c) B[i + (int64_t)c * ldb] -= uj[i] * B[j + (int64_t)c * ldb];
+    }
+    __syncthreads();
+  }
+}
+
+// Sum over the workgroup (every thread gets the total).
+__device__ inline double wg_sum(double v) {
+  __shared__ double s_part[NT / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_part[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) t += s_part[w];
+  return t;
+}
+
+constexpr int TRD_MAXN = 2048;  // largest matrix the tridiagonal eigen-solver takes
+
+// Number of eigenvalues of the tridiagonal (d, e) below x (Sturm sequence).
+__device__ inline int sturm_count(int n, const double* d, const double* e, double x, double tiny) {
+  double q = d[0] - x;
+  int c = q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    if (q == 0.0) q = tiny;
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+// Eigenvalues of a symmetric A (n x n, overwritten): Householder reduction to
+// tridiagonal form (the reflectors v_k are left in A[k+1:, k], tau[k] = 1 if
+// reflector k is applied), then bisection on Sturm counts.  W holds d, e and
+// tau (3n); lam receives the eigenvalues in descending order.
+__device__ inline void wg_syev_values(int n, double* A, int lda, double* W, double* lam) {
+  __shared__ double sv[TRD_MAXN], sw[TRD_MAXN];
+  __shared__ double s_lo, s_hi;
+  double* d = W;
+  double* e = W + n;
+  double* tau = W + 2 * n;
+  const int tid = threadIdx.x;
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double* x = A + (k + 1) + (int64_t)k * lda;
+    double part = 0.0;
+    for (int i = 1 + tid; i < m; i += NT) part += x[i] * x[i];
+    const double sig = wg_sum(part);
+    const double x0 = x[0];
+    if (sig == 0.0) {
+      if (tid == 0) { e[k] = x0; tau[k] = 0.0; }
+      __syncthreads();
+      continue;
+    }
+    const double alpha = -copysign(sqrt(x0 * x0 + sig), x0);
+    const double v0 = x0 - alpha;
+    const double inv = 1.0 / sqrt(sig + v0 * v0);
+    for (int i = tid; i < m; i += NT) sv[i] = (i == 0 ? v0 : x[i]) * inv;
+    __syncthreads();
+    if (tid == 0) { e[k] = alpha; tau[k] = 1.0; }
+    for (int i = tid; i < m; i += NT) x[i] = sv[i];
+    // p = S v, S = A[k+1:, k+1:]
+    double* S = A + (k + 1) + (int64_t)(k + 1) * lda;
+    double kp = 0.0;
+    for (int i = tid; i < m; i += NT) {
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += S[i + (int64_t)j * lda] * sv[j];
+      sw[i] = acc;
+      kp += acc * sv[i];
+    }
+    const double K = wg_sum(kp);
+    for (int i = tid; i < m; i += NT) sw[i] -= K * sv[i];  // w = p - K v
+    __syncthreads();
+    WG_FOR2(m, m, ii, jj) S[ii + (int64_t)jj * lda] -= 2.0 * (sv[ii] * sw[jj] + sw[ii] * sv[jj]);
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += NT) d[i] = A[i + (int64_t)i * lda];
+  if (tid == 0 && n >= 2) e[n - 2] = A[(n - 1) + (int64_t)(n - 2) * lda];
+  __syncthreads();
+  // Gershgorin interval
+  if (tid == 0) {
+    double lo = 0.0, hi = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double rad = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+      if (i == 0 || d[i] - rad < lo) lo = d[i] - rad;
+      if (i == 0 || d[i] + rad > hi) hi = d[i] + rad;
+    }
+    s_lo = lo;
+    s_hi = hi;
+  }
+  __syncthreads();
+  const double lo = s_lo, hi = s_hi;
+  const double nrm = fmax(fabs(lo), fabs(hi));
+  const double tiny = 2.2e-16 * nrm + 1e-300;
+  for (int j = tid; j < n; j += NT) {
+    const int target = n - 1 - j;  // the j-th largest has n-1-j eigenvalues below it
+    double a = lo, b = hi;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (b - a <= 4.4e-16 * nrm || mid <= a || mid >= b) break;
+      if (sturm_count(n, d, e, mid, tiny) > target) b = mid;
+      else a = mid;
+    }
+    lam[j] = 0.5 * (a + b);
+  }
+  __syncthreads();
+}
+
+// Eigenvectors of the k largest eigenvalues (after wg_syev_values): inverse
+// iteration on the tridiagonal (one thread per vector, pivoted LU of T - lam I),
+// two passes of modified Gram-Schmidt, then the Householder back-transform.
+// X (n x k, ld ldx) receives the vectors; IW holds 5 n k doubles.
+__device__ inline void wg_syev_vectors(int n, const double* A, int lda, const double* W, const double* lam, int k,
+                                       double* X, int ldx, double* IW) {
+  __shared__ double s_c[NT];
+  const double* d = W;
+  const double* e = W + n;
+  const double* tau = W + 2 * n;
+  const int tid = threadIdx.x;
+  if (k <= 0) return;
+  if (n == 1) {
+    if (tid == 0) X[0] = 1.0;
+    __syncthreads();
+    return;
+  }
+  const double nrm = fmax(fabs(lam[0]), fabs(lam[n - 1])) + 1e-300;
+  const double tiny = 2.2e-16 * nrm;
+  for (int j = tid; j < k; j += NT) {
+    // interleaved per-thread arrays: element i of vector j at [i * k + j]
+    double* u0 = IW;
+    double* u1 = IW + (int64_t)n * k;
+    double* u2 = IW + 2 * (int64_t)n * k;
+    double* ll = IW + 3 * (int64_t)n * k;
+    double* pv = IW + 4 * (int64_t)n * k;
+    const double mu = lam[j];
+    double cd = d[0] - mu, cs = e[0];
+    for (int i = 0; i + 1 < n; ++i) {
+      const double ns = e[i], nd = d[i + 1] - mu, nsp = (i + 2 < n) ? e[i + 1] : 0.0;
+      const int64_t o = (int64_t)i * k + j;
+      if (fabs(cd) >= fabs(ns)) {
+        if (cd == 0.0) cd = tiny;
+        const double mlt = ns / cd;
+        u0[o] = cd; u1[o] = cs; u2[o] = 0.0; ll[o] = mlt; pv[o] = 0.0;
+        cd = nd - mlt * cs;
+        cs = nsp;
+      } else {
+        const double mlt = cd / ns;
+        u0[o] = ns; u1[o] = nd; u2[o] = nsp; ll[o] = mlt; pv[o] = 1.0;
+        cd = cs - mlt * nd;
+        cs = -mlt * nsp;
+      }
+    }
+    {
+      const int64_t o = (int64_t)(n - 1) * k + j;  // last row: only the diagonal is non-zero
+      u0[o] = cd; u1[o] = 0.0; u2[o] = 0.0; ll[o] = 0.0; pv[o] = 0.0;
+    }
+    for (int i = 0; i < n; ++i) {
+      double& u = u0[(int64_t)i * k + j];
+      if (fabs(u) < tiny) u = (u < 0.0) ? -tiny : tiny;
+    }
+    double* x = X + (int64_t)j * ldx;
+    // distinct pseudo-random start per vector: within a (near-)degenerate
+    // cluster the iterates then span the cluster's eigenspace
+    for (int i = 0; i < n; ++i) {
+      uint32_t hsh = (uint32_t)i * 2654435761u ^ ((uint32_t)j * 2246822519u + 0x9E3779B9u);
+      hsh = hsh * 747796405u + 2891336453u;
+      hsh ^= hsh >> 16;
+      hsh *= 2246822519u;
+      hsh ^= hsh >> 13;
+      x[i] = 0.25 + (double)(hsh >> 8) * (1.0 / 16777216.0);
+    }
+    for (int it = 0; it < 3; ++it) {
+      // apply L (with the row interchanges), carrying b_i in a register
+      double bi = x[0];
+      for (int i = 0; i + 1 < n; ++i) {
+        const int64_t o = (int64_t)i * k + j;
+        double bn = x[i + 1];
+        if (pv[o] != 0.0) { const double t = bi; bi = bn; bn = t; }
+        x[i] = bi;
+        bi = bn - ll[o] * bi;
+      }
+      x[n - 1] = bi;
+      // back substitution with U (three diagonals)
+      double x1 = 0.0, x2 = 0.0, ss = 0.0;
+      for (int i = n - 1; i >= 0; --i) {
+        const int64_t o = (int64_t)i * k + j;
+        const double xi = (x[i] - u1[o] * x1 - u2[o] * x2) / u0[o];
+        x[i] = xi;
+        x2 = x1;
+        x1 = xi;
+        ss += xi * xi;
+      }
+      const double sc = 1.0 / sqrt(ss);
+      for (int i = 0; i < n; ++i) x[i] *= sc;
+    }
+  }
+  __syncthreads();
+  // two passes of modified Gram-Schmidt, largest eigenvalue first
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int j = 1; j < k; ++j) {
+      double* xj = X + (int64_t)j * ldx;
+      for (int i = tid; i < j; i += NT) {
+        const double* xi = X + (int64_t)i * ldx;
+        double c = 0.0;
+        for (int r = 0; r < n; ++r) c += xi[r] * xj[r];
+        s_c[i % NT] = c;
+      }
+      __syncthreads();
+      // (j <= NT keeps s_c valid; larger j fall back to one vector at a time)
+      if (j <= NT) {
+        for (int r = tid; r < n; r += NT) {
+          double v = xj[r];
+          for (int i = 0; i < j; ++i) v -= s_c[i] * X[r + (int64_t)i * ldx];
+          xj[r] = v;
+        }
+      } else {
+        for (int i = 0; i < j; ++i) {
+          const double* xi = X + (int64_t)i * ldx;
+          double part = 0.0;
+          for (int r = tid; r < n; r += NT) part += xi[r] * xj[r];
+          const double c = wg_sum(part);
+          for (int r = tid; r < n; r += NT) xj[r] -= c * xi[r];
+          __syncthreads();
+        }
+      }
+      __syncthreads();
+      double part = 0.0;
+      for (int r = tid; r < n; r += NT) part += xj[r] * xj[r];
+      const double nn = wg_sum(part);
+      const double sc = 1.0 / sqrt(nn);
+      for (int r = tid; r < n; r += NT) xj[r] *= sc;
+      __syncthreads();
+    }
+  }
+  // back-transform: X <- H_0 H_1 ... H_{n-3} X
+  for (int kk = n - 3; kk >= 0; --kk) {
+    if (tau[kk] == 0.0) continue;
+    const int m = n - kk - 1;
+    const double* v = A + (kk + 1) + (int64_t)kk * lda;
+    for (int j = tid; j < k; j += NT) {
+      const double* xj = X + (kk + 1) + (int64_t)j * ldx;
+      double c = 0.0;
+      for (int r = 0; r < m; ++r) c += v[r] * xj[r];
+      s_c[j % NT] = c;
+    }
+    __syncthreads();
+    if (k <= NT) {
+      WG_FOR2(m, k, r, j) X[(kk + 1 + r) + (int64_t)j * ldx] -= 2.0 * s_c[j] * v[r];
+    } else {
+      for (int j = 0; j < k; ++j) {
+        double* xj = X + (kk + 1) + (int64_t)j * ldx;
+        double part = 0.0;
+        for (int r = tid; r < m; r += NT) part += v[r] * xj[r];
+        const double c = wg_sum(part);
+        for (int r = tid; r < m; r += NT) xj[r] -= 2.0 * c * v[r];
+        __syncthreads();
+      }
     }
     __syncthreads();
   }
@@ -209,8 +471,8 @@ __device__ inline void wg_getrs(int d, const double* LU, int lda, const int32_t*
 // Vtmp (n x n) is workspace.
 __device__ inline void wg_syev_jacobi(int n, double* A, int lda, double* V, int ldv, double* Vtmp, double* lam) {
   // one entry per rotation pair of a round: n <= 2 * JAC_MAXPAIR
-  __shared__ double s_c[JAC_MAXPAIR], s_s[JAC_MAXPAIR];
-  __shared__ int s_p[JAC_MAXPAIR], s_q[JAC_MAXPAIR];
+  __shared__ double s_c[1024], s_s[1024];
+  __shared__ int s_p[1024], s_q[1024];
   __shared__ double s_red[NT];
   __shared__ int s_stop;
   const int tid = threadIdx.x;

@@ -17,6 +17,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 #include "engine.hpp"
@@ -56,6 +58,8 @@ static int dalloc(Handle& h, T** p, int64_t count, std::string& err) {
   }
   h.dev_bytes += bytes;
   h.allocs.push_back({(void*)*p, bytes});
+  // debugging: fill with a huge finite value, which exposes reads of unset memory
+  if (h.poison) (void)hipMemsetD32Async((hipDeviceptr_t)*p, 0x7FEFFFFF, (size_t)(bytes / 4), h.stream);
   return 0;
 }
 
@@ -116,6 +120,27 @@ static int ensure(Handle& h, void** buf, int64_t* cap, int64_t bytes, std::strin
   return 0;
 }
 
+// IFMM_CHECK: after a step, scan the level arena for non-finite / huge values.
+static int check_arena(Handle& h, int l, const char* step, int c, std::string& err) {
+  if (!h.check) return 0;
+  DevLevel& L = h.lv[l];
+  if (!L.arena || L.arena_doubles == 0) return 0;
+  if (!h.d_flag) {
+    HIPCHK(hipMalloc((void**)&h.d_flag, 4));
+  }
+  HIPCHK(hipMemsetAsync(h.d_flag, 0, 4, h.stream));
+  hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(NT), 0, h.stream, L.arena, L.arena_doubles, h.d_flag);
+  int32_t f = 0;
+  HIPCHK(hipMemcpyAsync(&f, h.d_flag, 4, hipMemcpyDeviceToHost, h.stream));
+  HIPCHK(hipStreamSynchronize(h.stream));
+  if (f) {
+    err = std::string("check: non-finite or huge value in the level arena after ") + step + " at level " +
+          std::to_string(l) + " colour " + std::to_string(c);
+    return -5;
+  }
+  return 0;
+}
+
 // ------------------------------------------------------------------ level set-up
 static LevelView view_of(DevLevel& L) {
   LevelView V;
@@ -146,7 +171,7 @@ static int setup_level(Handle& h, int l, std::string& err) {
   }
   L.rcmax = rcmax;
   L.nmax = nmax;
-  if (nmax > 2 * JAC_MAXPAIR) {
+  if (nmax > TRD_MAXN) {
     err = "level " + std::to_string(l) + " has a node with " + std::to_string(nmax) +
           " unknowns, above the supported 2048 (lower eps or set rank_cap)";
     return -1;
@@ -247,24 +272,20 @@ static int reduce_level(Handle& h, int l, std::string& err) {
   DevLevel& L = h.lv[l];
   const int K = h.K;
   const int32_t nn = L.nn;
+  const bool sym = h.symmetric;
   std::vector<int64_t> woff(nn);
   int64_t wtot = 0;
   for (int32_t i = 0; i < nn; ++i) {
     const int64_t n = L.n[i];
     woff[i] = wtot;
-    wtot += 6 * n * n + (int64_t)K * n + 2 * n;
-    wtot = (wtot + 3) & ~3LL;
-  }
-  int64_t ttot = 0;
-  std::vector<int64_t> toff(nn);
-  for (int32_t i = 0; i < nn; ++i) {
-    toff[i] = ttot;
-    ttot += (int64_t)K * std::max(L.rcmax, 1);
+    wtot += 4 * n * n + (int64_t)K * n + 8 * n + (h.eig_jacobi ? 2 * n * n : 0);
+    wtot = (wtot + 31) & ~31LL;
   }
   int rc;
-  if ((rc = ensure(h, (void**)&h.scratch, &h.scratch_bytes, std::max(wtot, ttot) * 8 + 64, err))) return rc;
+  if ((rc = ensure(h, (void**)&h.scratch, &h.scratch_bytes, wtot * 8 + 64, err))) return rc;
   double* work = h.scratch;
-  std::vector<EigTask> tasks(2 * (size_t)nn);
+  const int sides = sym ? 1 : 2;
+  std::vector<EigTask> tasks((size_t)sides * nn);
   for (int32_t i = 0; i < nn; ++i) {
     const int64_t n = L.n[i];
     double* b = work + woff[i];
@@ -272,40 +293,56 @@ static int reduce_level(Handle& h, int l, std::string& err) {
     double* gt = b + n * n;
     double* vs = b + 2 * n * n + (int64_t)K * n;
     double* vt = vs + n * n;
-    double* ws = vt + n * n;
-    double* wt = ws + n * n;
-    double* ls = wt + n * n;
+    double* ls = vt + n * n;
     double* lt = ls + n;
-    tasks[2 * i] = {gs, vs, ws, ls, (int32_t)n, 0};
-    tasks[2 * i + 1] = {gt, vt, wt, lt, (int32_t)n, 0};
+    double* ws = lt + n;
+    double* wt = ws + (h.eig_jacobi ? n * n : 3 * n);
+    tasks[(size_t)sides * i] = {gs, vs, ws, ls, nullptr, (int32_t)n, 0};
+    if (!sym) tasks[(size_t)sides * i + 1] = {gt, vt, wt, lt, nullptr, (int32_t)n, 0};
   }
-  const int64_t meta_bytes = (int64_t)(tasks.size() * sizeof(EigTask) + nn * sizeof(int64_t) + 2 * nn * sizeof(int32_t) + 1024);
-  if ((rc = ensure(h, (void**)&h.meta, &h.meta_bytes, meta_bytes, err))) return rc;
-  char* m = (char*)h.meta;
-  EigTask* d_tasks = (EigTask*)m;
-  int64_t* d_woff = (int64_t*)(m + ((tasks.size() * sizeof(EigTask) + 255) & ~(size_t)255));
-  int32_t* d_cnt = (int32_t*)((char*)d_woff + ((nn * sizeof(int64_t) + 255) & ~(size_t)255));
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t o_t = 0, o_w = al(tasks.size() * sizeof(EigTask)), o_c = o_w + al(nn * sizeof(int64_t));
+  const size_t mtot = o_c + al(tasks.size() * 4 + 4);
+  if ((rc = ensure(h, (void**)&h.meta, &h.meta_bytes, (int64_t)mtot, err))) return rc;
+  EigTask* d_tasks = (EigTask*)(h.meta + o_t);
+  int64_t* d_woff = (int64_t*)(h.meta + o_w);
+  int32_t* d_cnt = (int32_t*)(h.meta + o_c);
   HIPCHK(hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
   HIPCHK(hipMemcpyAsync(d_woff, woff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, h.stream));
   LevelView V = view_of(L);
   const double* G = h.weights_G[l];
   if (nn > 0) {
     hipLaunchKernelGGL(k_reduce_gram, dim3(nn), dim3(NT), 0, h.stream, V, K, G, work, d_woff);
-    hipLaunchKernelGGL(k_eig, dim3(2 * nn), dim3(NT), 0, h.stream, d_tasks, h.eps * h.eps, d_cnt);
+    hipLaunchKernelGGL(k_eig_values, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, d_tasks, h.eps * h.eps,
+                       d_cnt, h.eig_jacobi ? 1 : 0);
   }
   HIPCHK(hipGetLastError());
-  std::vector<int32_t> cnt(2 * (size_t)nn);
+  std::vector<int32_t> cnt(tasks.size());
   if (nn > 0) HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * 4, hipMemcpyDeviceToHost, h.stream));
   HIPCHK(hipStreamSynchronize(h.stream));
+  int64_t iw = 0;
   for (int32_t i = 0; i < nn; ++i) {
-    int r = std::max(cnt[2 * i], cnt[2 * i + 1]);
+    int r = sym ? cnt[i] : std::max(cnt[2 * i], cnt[2 * i + 1]);
     r = std::min(r, L.rc[i]);
     L.r[i] = r;
+    for (int s2 = 0; s2 < sides; ++s2) iw += 5LL * L.n[i] * r + 32;
   }
+  if ((rc = ensure(h, (void**)&h.scratch2, &h.scratch2_bytes, iw * 8 + 64, err))) return rc;
+  iw = 0;
+  for (int32_t i = 0; i < nn; ++i)
+    for (int s2 = 0; s2 < sides; ++s2) {
+      EigTask& t = tasks[(size_t)sides * i + s2];
+      t.k = L.r[i];
+      t.IW = h.scratch2 + iw;
+      iw += 5LL * L.n[i] * L.r[i] + 32;
+    }
+  HIPCHK(hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
   HIPCHK(hipMemcpyAsync(L.d_r, L.r.data(), nn * 4, hipMemcpyHostToDevice, h.stream));
   const double side = 2.0 * h.tree.H / (double)(1LL << l);
   if (nn > 0) {
-    hipLaunchKernelGGL(k_reduce_basis, dim3(nn), dim3(NT), 0, h.stream, V, K, work, d_woff, h.d_m2m8, l > 2 ? 1 : 0);
+    if (!h.eig_jacobi) hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, d_tasks);
+    hipLaunchKernelGGL(k_reduce_basis, dim3(nn), dim3(NT), 0, h.stream, V, K, work, d_woff, h.d_m2m8, l > 2 ? 1 : 0,
+                       sym ? 1 : 0);
     HIPCHK(hipGetLastError());
   }
   // M2L of the interaction pairs (needs T of every node: separate launch)
@@ -341,6 +378,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   std::vector<Changed> chg;
   std::vector<FarRef> refs;
   std::vector<SchurTask> tasks;
+  std::vector<XTask> xtasks;
   int64_t sc = 0;  // scratch doubles
   auto stake = [&](int64_t cnt) {
     const int64_t o = sc;
@@ -350,6 +388,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   std::vector<int64_t> x_off(nrec);
   std::vector<std::vector<int64_t>> far_off_F, far_off_D;
   struct ChgOff { int64_t gs, gt, vs, vt, ws, wt, ls, lt, T, S, tmp; };
+  const bool sym = h.symmetric;
+  const int sides = sym ? 1 : 2;
   std::vector<ChgOff> coff;
   const int nbase = (int)L.nbrs.size();
   for (int k = 0; k < nrec; ++k) {
@@ -424,6 +464,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       }
     // schur tasks: one per neighbour row block plus the row R_z_i
     for (int a = 0; a <= R.nnb; ++a) tasks.push_back({k, a});
+    for (int c0 = 0; c0 < R.M + R.r; c0 += 64) xtasks.push_back({k, c0});
   }
   // scratch for far pairs
   std::vector<int64_t> fF(far.size()), fD(far.size());
@@ -454,8 +495,13 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       const int64_t n = C.n;
       const int64_t big = std::max<int64_t>(std::max<int64_t>(L.rcmax, K), n);
       ChgOff o;
-      o.gs = stake(n * n); o.gt = stake(n * n); o.vs = stake(n * n); o.vt = stake(n * n);
-      o.ws = stake(n * n); o.wt = stake(n * n); o.ls = stake(n); o.lt = stake(n);
+      const int64_t wsz = h.eig_jacobi ? n * n : 3 * n;
+      o.gs = stake(n * n); o.vs = stake(n * n); o.ws = stake(wsz); o.ls = stake(n);
+      if (sym) {
+        o.gt = o.gs; o.vt = o.vs; o.wt = o.ws; o.lt = o.ls;
+      } else {
+        o.gt = stake(n * n); o.vt = stake(n * n); o.wt = stake(wsz); o.lt = stake(n);
+      }
       o.T = stake((int64_t)std::max(C.r, 1) * n);
       o.S = stake(n * std::max(C.r, 1));
       o.tmp = stake(big * std::max<int64_t>(std::max<int64_t>(L.rc[A.p], n), 1));
@@ -474,8 +520,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     const ChgOff& o = coff[k];
     C.gs = S0 + o.gs; C.gt = S0 + o.gt; C.vs = S0 + o.vs; C.vt = S0 + o.vt; C.ws = S0 + o.ws; C.wt = S0 + o.wt;
     C.ls = S0 + o.ls; C.lt = S0 + o.lt; C.T = S0 + o.T; C.S = S0 + o.S; C.tmp = S0 + o.tmp;
-    etasks.push_back({C.gs, C.vs, C.ws, C.ls, C.n, 0});
-    etasks.push_back({C.gt, C.vt, C.wt, C.lt, C.n, 0});
+    etasks.push_back({C.gs, C.vs, C.ws, C.ls, nullptr, C.n, 0});
+    if (!sym) etasks.push_back({C.gt, C.vt, C.wt, C.lt, nullptr, C.n, 0});
   }
   // ---- pack the tables into the meta buffer
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -488,7 +534,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   const size_t o_refs = o_chg + al(std::max<size_t>(chg.size(), 1) * sizeof(Changed));
   const size_t o_et = o_refs + al(std::max<size_t>(refs.size(), 1) * sizeof(FarRef));
   const size_t o_cnt = o_et + al(std::max<size_t>(etasks.size(), 1) * sizeof(EigTask));
-  const size_t o_info = o_cnt + al(std::max<size_t>(etasks.size(), 1) * 4);
+  const size_t o_xt = o_cnt + al(std::max<size_t>(etasks.size(), 1) * 4);
+  const size_t o_info = o_xt + al(std::max<size_t>(xtasks.size(), 1) * sizeof(XTask));
   const size_t total = o_info + al((size_t)nrec * 4);
   if ((rc = ensure(h, (void**)&h.meta, &h.meta_bytes, (int64_t)total, err))) return rc;
   char* M = (char*)h.meta;
@@ -502,7 +549,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   if (!chg.empty()) std::memcpy(Hm + o_chg, chg.data(), chg.size() * sizeof(Changed));
   if (!refs.empty()) std::memcpy(Hm + o_refs, refs.data(), refs.size() * sizeof(FarRef));
   if (!etasks.empty()) std::memcpy(Hm + o_et, etasks.data(), etasks.size() * sizeof(EigTask));
-  HIPCHK(hipMemcpyAsync(M, Hm, o_cnt, hipMemcpyHostToDevice, h.stream));
+  if (!xtasks.empty()) std::memcpy(Hm + o_xt, xtasks.data(), xtasks.size() * sizeof(XTask));
+  HIPCHK(hipMemcpyAsync(M, Hm, o_info, hipMemcpyHostToDevice, h.stream));
   const ElimRec* d_recs = (const ElimRec*)(M + o_recs);
   const ElimNbr* d_nbrs = (const ElimNbr*)(M + o_nbrs);
   const SchurTask* d_tasks = (const SchurTask*)(M + o_tasks);
@@ -513,21 +561,27 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   const EigTask* d_et = (const EigTask*)(M + o_et);
   int32_t* d_cnt = (int32_t*)(M + o_cnt);
   int32_t* d_info = (int32_t*)(M + o_info);
+  const XTask* d_xt = (const XTask*)(M + o_xt);
   LevelView V = view_of(L);
   const int nchg = (int)chg.size();
   // ---- phase A
   hipLaunchKernelGGL(k_gather, dim3(nrec), dim3(NT), 0, h.stream, V, d_recs, d_nbrs);
+  if ((rc = check_arena(h, l, "gather", c, err))) return rc;
   hipLaunchKernelGGL(k_getrf, dim3(nrec), dim3(NT), 0, h.stream, d_recs, d_info);
-  hipLaunchKernelGGL(k_xsolve, dim3(nrec), dim3(NT), 0, h.stream, d_recs);
+  if (!xtasks.empty())
+    hipLaunchKernelGGL(k_xsolve, dim3((unsigned)xtasks.size()), dim3(NT), 0, h.stream, d_recs, d_xt);
   hipLaunchKernelGGL(k_schur, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks, d_fidx,
                      d_far);
+  if ((rc = check_arena(h, l, "schur", c, err))) return rc;
   if (nchg) {
     hipLaunchKernelGGL(k_set_chg, dim3((nchg + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_chg, d_chg, nchg, 0);
-    hipLaunchKernelGGL(k_gram, dim3(2 * nchg), dim3(NT), 0, h.stream, V, d_chg, d_refs, d_far, d_nbrs, d_recs);
-    hipLaunchKernelGGL(k_eig, dim3(2 * nchg), dim3(NT), 0, h.stream, d_et, h.eps * h.eps, d_cnt);
+    hipLaunchKernelGGL(k_gram, dim3(sides * nchg), dim3(NT), 0, h.stream, V, d_chg, d_refs, d_far, d_nbrs, d_recs,
+                       sides);
+    hipLaunchKernelGGL(k_eig_values, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et, h.eps * h.eps,
+                       d_cnt, h.eig_jacobi ? 1 : 0);
   }
   HIPCHK(hipGetLastError());
-  std::vector<int32_t> cnt(2 * (size_t)nchg), info(nrec);
+  std::vector<int32_t> cnt(etasks.size()), info(nrec);
   if (nchg) HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * 4, hipMemcpyDeviceToHost, h.stream));
   HIPCHK(hipMemcpyAsync(info.data(), d_info, nrec * 4, hipMemcpyDeviceToHost, h.stream));
   HIPCHK(hipStreamSynchronize(h.stream));
@@ -537,20 +591,37 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       return -4;
     }
   if (nchg) {
+    int64_t iw = 0;
     for (int k = 0; k < nchg; ++k) {
       Changed& C = chg[k];
-      int rn = std::max(cnt[2 * k], cnt[2 * k + 1]);
+      int rn = sym ? cnt[k] : std::max(cnt[2 * k], cnt[2 * k + 1]);
       rn = std::min(rn, std::min(C.n, L.rc[C.p]));
       C.rnew = rn;
+      iw += sides * (5LL * C.n * rn + 32);
     }
+    if ((rc = ensure(h, (void**)&h.scratch2, &h.scratch2_bytes, iw * 8 + 64, err))) return rc;
+    iw = 0;
+    for (int k = 0; k < nchg; ++k)
+      for (int s2 = 0; s2 < sides; ++s2) {
+        EigTask& t = etasks[(size_t)sides * k + s2];
+        t.k = chg[k].rnew;
+        t.IW = h.scratch2 + iw;
+        iw += 5LL * chg[k].n * chg[k].rnew + 32;
+      }
+    HIPCHK(hipMemcpyAsync((void*)d_et, etasks.data(), etasks.size() * sizeof(EigTask), hipMemcpyHostToDevice,
+                          h.stream));
     HIPCHK(hipMemcpyAsync(d_chg, chg.data(), chg.size() * sizeof(Changed), hipMemcpyHostToDevice, h.stream));
+    if (!h.eig_jacobi) hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et);
     hipLaunchKernelGGL(k_basis, dim3(nchg), dim3(NT), 0, h.stream, V, d_chg);
+    if ((rc = check_arena(h, l, "basis", c, err))) return rc;
   }
   if (!far.empty())
     hipLaunchKernelGGL(k_project, dim3((unsigned)far.size()), dim3(NT), 0, h.stream, V, d_far, d_recs, d_nbrs, d_chg);
+  if ((rc = check_arena(h, l, "project", c, err))) return rc;
   // ---- phase B
   if (nchg) {
     hipLaunchKernelGGL(k_phase_b, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far, l > 2 ? 1 : 0);
+    if ((rc = check_arena(h, l, "phase_b", c, err))) return rc;
     hipLaunchKernelGGL(k_set_rank, dim3((nchg + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_r, d_chg, nchg);
     hipLaunchKernelGGL(k_set_chg, dim3((nchg + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_chg, d_chg, nchg, 1);
     for (const Changed& C : chg) L.r[C.p] = C.rnew;
@@ -587,7 +658,9 @@ static int init_leaf_level(Handle& h, std::string& err) {
   hipLaunchKernelGGL(k_p2p, dim3((unsigned)L.near_idx.size()), dim3(NT), 0, h.stream, V, L.d_slot_row, h.d_pts, h.d_w,
                      h.d_diag, h.d_pt_begin);
   HIPCHK(hipGetLastError());
-  return reduce_level(h, l, err);
+  if ((rc = check_arena(h, l, "leaf operators", -1, err))) return rc;
+  if ((rc = reduce_level(h, l, err))) return rc;
+  return check_arena(h, l, "rank reduction", -1, err);
 }
 
 static int aggregate_level(Handle& h, int l, std::string& err) {
@@ -606,8 +679,10 @@ static int aggregate_level(Handle& h, int l, std::string& err) {
                      P.d_child_ptr, P.d_child);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(h.stream));
+  if ((rc = check_arena(h, l - 1, "aggregation", -1, err))) return rc;
   release_level_work(h, l);
-  return reduce_level(h, l - 1, err);
+  if ((rc = reduce_level(h, l - 1, err))) return rc;
+  return check_arena(h, l - 1, "rank reduction", -1, err);
 }
 
 static int finish_level(Handle& h, int l, std::string& err) {
@@ -654,8 +729,10 @@ static void clear_factor(Handle& h) {
   h.store_bytes = 0;
   dfree(h, h.d_top);
   dfree(h, h.d_top_piv);
+  dfree(h, h.d_top_inv);
   h.d_top = nullptr;
   h.d_top_piv = nullptr;
+  h.d_top_inv = nullptr;
   h.factored = false;
 }
 
@@ -665,6 +742,13 @@ int factor(Handle& h, std::string& err) {
   HIPCHK(hipSetDevice(h.device));
   clear_factor(h);
   h.lv.assign((size_t)h.tree.depth + 1, DevLevel());
+  h.log = std::getenv("IFMM_LOG") != nullptr;
+  h.poison = std::getenv("IFMM_POISON") != nullptr;
+  h.check = std::getenv("IFMM_CHECK") != nullptr;
+  {
+    const char* ev = std::getenv("IFMM_EIG");
+    h.eig_jacobi = ev && std::strcmp(ev, "jacobi") == 0;
+  }
   h.stat_far = 0;
   h.stat_changed = 0;
   const double t0 = now_s();
@@ -683,6 +767,9 @@ int factor(Handle& h, std::string& err) {
     HIPCHK(hipStreamSynchronize(h.stream));
     if ((rc = finish_level(h, l, err))) return rc;
     h.t_level_elim[l] = now_s() - ta;
+    if (h.log)
+      std::fprintf(stderr, "[ifmm] level %d: %d nodes, %d colours eliminated in %.3f s (set-up %.3f s)\n", l, T.n,
+                   T.ncolour, h.t_level_elim[l], h.t_level_setup[l]);
     ta = now_s();
     if (l > 2 && (rc = aggregate_level(h, l, err))) return rc;
     if (l > 2) h.t_level_setup[l - 1] = now_s() - ta;
@@ -702,8 +789,25 @@ int factor(Handle& h, std::string& err) {
   int32_t* d_info = nullptr;
   if ((rc = dalloc(h, &d_info, 1, err))) return rc;
   if (h.top_n > 0) {
-    hipLaunchKernelGGL(k_top_assemble, dim3(L2.nn), dim3(NT), 0, h.stream, V2, L2.nn, d_toff, h.d_top, h.top_n);
-    hipLaunchKernelGGL(k_top_getrf, dim3(1), dim3(NT), 0, h.stream, h.d_top, h.top_n, h.d_top_piv, d_info);
+    const int n = h.top_n;
+    HIPCHK(hipMemsetAsync(d_info, 0, 4, h.stream));
+    hipLaunchKernelGGL(k_top_assemble, dim3(L2.nn), dim3(NT), 0, h.stream, V2, L2.nn, d_toff, h.d_top, n);
+    // blocked LU: panel, swaps, triangular solve, trailing update
+    for (int j0 = 0; j0 < n; j0 += TOP_NB) {
+      const int nb = std::min(TOP_NB, n - j0);
+      hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(NT), 0, h.stream, h.d_top, n, j0, nb, h.d_top_piv, d_info);
+      hipLaunchKernelGGL(k_lu_swap, dim3((n + NT - 1) / NT), dim3(NT), 0, h.stream, h.d_top, n, j0, nb, h.d_top_piv);
+      const int rest = n - j0 - nb;
+      if (rest > 0) {
+        hipLaunchKernelGGL(k_lu_trsm, dim3((rest + 63) / 64), dim3(NT), 0, h.stream, h.d_top, n, j0, nb);
+        hipLaunchKernelGGL(k_gemm_tiles, dim3((rest + 63) / 64, (rest + 63) / 64), dim3(NT), 0, h.stream, rest, rest,
+                           nb, -1.0, h.d_top + (j0 + nb) + (int64_t)j0 * n, n, h.d_top + j0 + (int64_t)(j0 + nb) * n,
+                           n, 1.0, h.d_top + (j0 + nb) + (int64_t)(j0 + nb) * n, n);
+      }
+    }
+    if ((rc = dalloc(h, &h.d_top_inv, (int64_t)n * n, err))) return rc;
+    hipLaunchKernelGGL(k_lu_inverse, dim3((n + 63) / 64), dim3(NT), 0, h.stream, h.d_top, n, h.d_top_piv,
+                       h.d_top_inv);
   }
   HIPCHK(hipGetLastError());
   int32_t info = 0;
@@ -742,7 +846,7 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
     ot[l] = tot; tot += L.wv_total * k + 32;
   }
   const int64_t otop = tot;
-  tot += (int64_t)std::max(h.top_n, 1) * k + 32;
+  tot += 2 * (int64_t)std::max(h.top_n, 1) * k + 32;
   const int64_t oio = tot;
   if (!on_device) tot += 2 * ld * k + 32;
   int rc;
@@ -779,9 +883,17 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
                          P.d_n);
     }
   }
-  if (h.top_n > 0)
-    hipLaunchKernelGGL(k_top_solve, dim3(1), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r, h.d_top_off,
-                       h.d_top, h.top_n, h.d_top_piv, B + otop);
+  if (h.top_n > 0) {
+    const int n = h.top_n;
+    double* f = B + otop;
+    double* y = f + (int64_t)n * k;
+    hipLaunchKernelGGL(k_top_gather, dim3(h.lv[2].nn), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r,
+                       h.d_top_off, f, n);
+    hipLaunchKernelGGL(k_gemm_tiles, dim3((n + 63) / 64, (k + 63) / 64), dim3(NT), 0, h.stream, n, k, n, 1.0,
+                       h.d_top_inv, n, f, n, 0.0, y, n);
+    hipLaunchKernelGGL(k_top_scatter, dim3(h.lv[2].nn), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r,
+                       h.d_top_off, y, n);
+  }
   for (int l = 2; l <= D; ++l) {
     const DevLevel& L = h.lv[l];
     SolveView S = sv(l);
@@ -822,6 +934,7 @@ int device_init(Handle& h, std::string& err) {
   const double t0 = now_s();
   const int K = h.K;
   const int64_t N = h.N;
+  h.poison = std::getenv("IFMM_POISON") != nullptr;
   int rc;
   std::vector<double> pts(h.pts), lo(h.tree.lo, h.tree.lo + 3);
   if ((rc = upload(h, &h.d_pts, pts, err))) return rc;
@@ -874,8 +987,45 @@ void release(Handle& h) {
   clear_factor(h);
   for (auto& a : h.allocs) (void)hipFree(a.first);
   h.allocs.clear();
+  if (h.d_flag) (void)hipFree(h.d_flag);
+  h.d_flag = nullptr;
   h.dev_bytes = 0;
   h.dev_ready = false;
 }
 
 }  // namespace ifmm
+
+// Internal test hook (not part of the public header): eigen-decomposition of
+// `count` symmetric n x n matrices (host, column-major, back to back) with the
+// device solver; lam (count x n, descending) and the k leading vectors
+// (count x n x k).  Returns 0 or a negative status.
+extern "C" int ifmm_internal_syev(const double* A, int count, int n, int k, double* lam, double* V, int jacobi) {
+  using namespace ifmm;
+  if (count < 1 || n < 1 || n > TRD_MAXN || k < 0 || k > n) return -1;
+  const int64_t nn = (int64_t)n * n;
+  double *dA = nullptr, *dV = nullptr, *dW = nullptr, *dL = nullptr, *dI = nullptr;
+  EigTask* dT = nullptr;
+  int32_t* dC = nullptr;
+  const int64_t wsz = jacobi ? nn : 3LL * n;
+  if (hipMalloc((void**)&dA, count * nn * 8) != hipSuccess) return -3;
+  (void)hipMalloc((void**)&dV, count * nn * 8);
+  (void)hipMalloc((void**)&dW, count * wsz * 8);
+  (void)hipMalloc((void**)&dL, count * (int64_t)n * 8);
+  (void)hipMalloc((void**)&dI, count * (5LL * n * std::max(k, 1)) * 8);
+  (void)hipMalloc((void**)&dT, count * sizeof(EigTask));
+  (void)hipMalloc((void**)&dC, count * 4);
+  std::vector<EigTask> t(count);
+  for (int c = 0; c < count; ++c)
+    t[c] = {dA + c * nn, dV + c * nn, dW + c * wsz, dL + (int64_t)c * n, dI + c * (5LL * n * std::max(k, 1)), n, k};
+  (void)hipMemcpy(dA, A, count * nn * 8, hipMemcpyHostToDevice);
+  (void)hipMemcpy(dT, t.data(), count * sizeof(EigTask), hipMemcpyHostToDevice);
+  hipLaunchKernelGGL(k_eig_values, dim3(count), dim3(NT), 0, nullptr, dT, 0.0, dC, jacobi);
+  if (!jacobi) hipLaunchKernelGGL(k_eig_vectors, dim3(count), dim3(NT), 0, nullptr, dT);
+  int rc = hipDeviceSynchronize() == hipSuccess ? 0 : -3;
+  (void)hipMemcpy(lam, dL, count * (int64_t)n * 8, hipMemcpyDeviceToHost);
+  for (int c = 0; c < count; ++c)
+    (void)hipMemcpy(V + c * (int64_t)n * k, dV + c * nn, (int64_t)n * k * 8, hipMemcpyDeviceToHost);
+  (void)hipFree(dA); (void)hipFree(dV); (void)hipFree(dW); (void)hipFree(dL); (void)hipFree(dI);
+  (void)hipFree(dT); (void)hipFree(dC);
+  return rc;
+}

@@ -128,8 +128,12 @@ struct Handle {
   std::vector<char> host_meta;
   double* svec = nullptr;
   int64_t svec_bytes = 0;
+  double* scratch2 = nullptr;  // eigenvector workspace, sized after the rank decision
+  int64_t scratch2_bytes = 0;
+  bool symmetric = false;      // unit weights: source and target sides coincide
   // top level
-  double* d_top = nullptr;
+  double* d_top = nullptr;      // LU factors of the level-2 system
+  double* d_top_inv = nullptr;  // its inverse (the solve applies it as a GEMM)
   int32_t* d_top_piv = nullptr;
   int64_t* d_top_off = nullptr;
   int32_t top_n = 0;
@@ -140,6 +144,11 @@ struct Handle {
   int64_t stat_far = 0, stat_changed = 0;
   std::vector<double> t_level_setup, t_level_elim;  // per level: set-up + rank reduction, colour loop
   double t_top = 0;
+  bool log = false;         // IFMM_LOG set: one progress line per level on stderr
+  bool poison = false;      // IFMM_POISON set: fill new device allocations with a huge value (debugging)
+  bool check = false;       // IFMM_CHECK set: scan the level arena after every step (debugging)
+  int32_t* d_flag = nullptr;
+  bool eig_jacobi = false;  // IFMM_EIG=jacobi: cyclic Jacobi instead of tridiagonal + bisection
 };
 
 // status helpers

@@ -71,8 +71,7 @@ __global__ void k_unit_m2l(int nc, double* out) {
   const int K = nc * nc * nc;
   double* U = out + (int64_t)o * K * K;
   const bool near = abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1;
-  for (int e = threadIdx.x; e < K * K; e += NT) {
-    const int m = e % K, mp = e / K;
+  if (K > 0) WG_FOR2(K, K, m, mp) {
     double v = 0.0;
     if (!near) {
       const double x = dx + 0.5 * (cheb_node(nc, m % nc) - cheb_node(nc, mp % nc));
@@ -97,8 +96,7 @@ __global__ void k_m2m8(int nc, double* out) {
   const int K = nc * nc * nc;
   double* M = out + (int64_t)o * K * K;
   const double sx = (o & 1) ? 0.5 : -0.5, sy = (o & 2) ? 0.5 : -0.5, sz = (o & 4) ? 0.5 : -0.5;
-  for (int e = threadIdx.x; e < K * K; e += NT) {
-    const int m = e % K, mp = e / K;
+  if (K > 0) WG_FOR2(K, K, m, mp) {
     const double x = sx + 0.5 * cheb_node(nc, mp % nc);
     const double y = sy + 0.5 * cheb_node(nc, (mp / nc) % nc);
     const double z = sz + 0.5 * cheb_node(nc, mp / (nc * nc));
@@ -153,8 +151,7 @@ __global__ void k_leaf_cheb(LevelView V, int nc, const double* pts, const double
   double c[3];
   for (int e = 0; e < 3; ++e) c[e] = lo[e] + ((double)V.coord[3 * i + e] + 0.5) * side;
   const int64_t b = pt_begin[i];
-  for (int e = threadIdx.x; e < K * n; e += NT) {
-    const int m = e % K, j = e / K;
+  if (K > 0) WG_FOR2(K, n, m, j) {
     const double* p = pts + 3 * (b + j);
     const double s = cheb_S(nc, m % nc, (p[0] - c[0]) / h) * cheb_S(nc, (m / nc) % nc, (p[1] - c[1]) / h) *
                      cheb_S(nc, m / (nc * nc), (p[2] - c[2]) / h);
@@ -171,8 +168,7 @@ __global__ void k_p2p(LevelView V, const int32_t* slot_row, const double* pts, c
   const int np = V.n[p], nq = V.n[q];
   double* B = V.arena + V.near_off[s];
   const int64_t bp = pt_begin[p], bq = pt_begin[q];
-  for (int e = threadIdx.x; e < np * nq; e += NT) {
-    const int a = e % np, bb = e / np;
+  if (np > 0) WG_FOR2(np, nq, a, bb) {
     double v;
     if (p == q && a == bb) {
       v = diag[bp + a];
@@ -204,18 +200,21 @@ __global__ void k_reduce_gram(LevelView V, int K, const double* G, double* work,
   wg_gemm(n, n, K, 1.0, L2P, n, false, t, K, false, 0.0, gt, n);
 }
 
-// Batched symmetric eigen-decomposition; cnt[t] = #{k : lam_k > eps2 * lam_0}.
+// Batched symmetric eigen-decomposition in two launches around the host's
+// rank decision: values (tridiagonalisation + bisection; cnt[t] = #{k :
+// lam_k > eps2 * lam_0}) and then the k leading vectors.
 struct EigTask {
-  double *A, *V, *W, *lam;
-  int32_t n, pad;
+  double *A, *V, *W, *lam, *IW;  // A n x n (destroyed), V n x k, W 3n, lam n, IW 5 n k
+  int32_t n, k;
 };
-__global__ void k_eig(const EigTask* tasks, double eps2, int32_t* cnt) {
+__global__ void k_eig_values(const EigTask* tasks, double eps2, int32_t* cnt, int jacobi) {
   const EigTask t = tasks[blockIdx.x];
   if (t.n == 0) {
     if (threadIdx.x == 0) cnt[blockIdx.x] = 0;
     return;
   }
-  wg_syev_jacobi(t.n, t.A, t.n, t.V, t.n, t.W, t.lam);
+  if (jacobi) wg_syev_jacobi(t.n, t.A, t.n, t.V, t.n, t.W, t.lam);  // all vectors; W holds n x n
+  else wg_syev_values(t.n, t.A, t.n, t.W, t.lam);
   if (threadIdx.x == 0) {
     const double l0 = t.lam[0];
     int c = 0;
@@ -226,30 +225,34 @@ __global__ void k_eig(const EigTask* tasks, double eps2, int32_t* cnt) {
   }
 }
 
+__global__ void k_eig_vectors(const EigTask* tasks) {
+  const EigTask t = tasks[blockIdx.x];
+  if (t.n == 0 || t.k == 0) return;
+  wg_syev_vectors(t.n, t.A, t.n, t.W, t.lam, t.k, t.V, t.n, t.IW);
+}
+
 // Initial rank reduction, basis step: P2M = V^T, L2P = U, sig = sqrt(lam),
 // T = P2Mc V (K x r), S = U^T L2Pc (r x K); then M2M / L2L of the node.
 __global__ void k_reduce_basis(LevelView V, int K, const double* work, const int64_t* work_off,
-                               const double* m2m8, int has_parent) {
+                               const double* m2m8, int has_parent, int sym) {
   const int i = blockIdx.x;
   const int n = V.n[i], r = V.r[i], rc = V.rc[i];
   double* T = V.arena + V.T_off[i];
   double* S = V.arena + V.S_off[i];
   if (n == 0 || r == 0) return;
   const double* base = work + work_off[i];
-  // work layout per node: gs, gt (n x n), t (K x n), vs, vt, ws, wt (n x n), ls, lt (n)
+  // work layout per node: gs, gt (n x n), t (K x n), vs, vt (n x n), ls, lt (n), ws, wt (3n)
   const double* vs = base + 2 * (int64_t)n * n + (int64_t)K * n;
-  const double* vt = vs + (int64_t)n * n;
-  const double* ls = vt + 3 * (int64_t)n * n;
-  const double* lt = ls + n;
+  const double* vt = sym ? vs : vs + (int64_t)n * n;
+  const double* ls = vs + 2 * (int64_t)n * n;
+  const double* lt = sym ? ls : ls + n;
   double* P2M = V.arena + V.p2m_off[i];
   double* L2P = V.arena + V.l2p_off[i];
   double* sig = V.arena + V.sig_off[i];
-  for (int e = threadIdx.x; e < r * n; e += NT) {
-    const int a = e % r, j = e / r;
+  if (r > 0) WG_FOR2(r, n, a, j) {
     P2M[a + (int64_t)j * rc] = vs[j + (int64_t)a * n];
   }
-  for (int e = threadIdx.x; e < n * r; e += NT) {
-    const int j = e % n, a = e / n;
+  if (n > 0) WG_FOR2(n, r, j, a) {
     L2P[j + (int64_t)a * n] = vt[j + (int64_t)a * n];
   }
   for (int a = threadIdx.x; a < r; a += NT) {
@@ -352,20 +355,26 @@ __global__ void k_getrf(const ElimRec* recs, int32_t* info) {
   if (threadIdx.x == 0) info[blockIdx.x] = inf;
 }
 
-// X = D^-1 [[U, 0], [0, I]]  (d x (M + r))
-__global__ void k_xsolve(const ElimRec* recs) {
-  const ElimRec R = recs[blockIdx.x];
-  const int n = R.n, r = R.r, d = R.d, M = R.M;
-  const int nc = M + r;
-  for (int64_t e = threadIdx.x; e < (int64_t)d * nc; e += NT) {
-    const int row = (int)(e % d), col = (int)(e / d);
+// X = D^-1 [[U, 0], [0, I]]  (d x (M + r)), 64 columns per workgroup.
+struct XTask {
+  int32_t rec, c0;
+};
+__global__ void k_xsolve(const ElimRec* recs, const XTask* xt) {
+  const XTask t = xt[blockIdx.x];
+  const ElimRec R = recs[t.rec];
+  const int n = R.n, d = R.d, M = R.M;
+  const int nc = min(64, M + R.r - t.c0);
+  if (d == 0 || nc <= 0) return;
+  double* X = R.X + (int64_t)t.c0 * d;
+  WG_FOR2(d, nc, row, cl) {
+    const int col = t.c0 + cl;
     double v;
     if (col < M) v = row < n ? R.U[row + (int64_t)col * n] : 0.0;
     else v = (row >= n && row - n == col - M) ? 1.0 : 0.0;
-    R.X[row + (int64_t)col * d] = v;
+    X[row + (int64_t)cl * d] = v;
   }
   __syncthreads();
-  wg_getrs(d, R.lu, d, R.piv, R.X, d, nc);
+  wg_getrs(d, R.lu, d, R.piv, X, d, nc);
 }
 
 // Schur-complement update of one row block a of the neighbours of i (a == nnb:
@@ -385,7 +394,9 @@ __global__ void k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs, c
     const ElimNbr A = nbrs[R.nb_begin + T.a];
     const int p = A.p, np = V.n[p];
     const double* La = R.L + A.off;
-    if (n > 0) {
+    {
+      // (with n == 0 the products are empty: far blocks become zero, near
+      // blocks stay, the new block is zero)
       for (int b = 0; b < R.nnb; ++b) {
         const ElimNbr B = nbrs[R.nb_begin + b];
         const double* Xb = R.X + (int64_t)B.off * d;
@@ -399,8 +410,6 @@ __global__ void k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs, c
       }
       // new block (p, i) = L_a F   with [F; H] = D^-1 [0; I]
       wg_gemm(A.m, r, n, 1.0, La, M, false, R.X + (int64_t)M * d, d, false, 0.0, V.arena + A.blk_pi, np);
-    } else {
-      wg_fill(A.m, r, V.arena + A.blk_pi, np, 0.0);
     }
   } else {
     for (int b = 0; b < R.nnb; ++b) {
@@ -415,9 +424,9 @@ __global__ void k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs, c
 //   Gs = P2M^T diag(sig_s^2) P2M + sum_q F_qp^T F_qp
 //   Gt = L2P diag(sig_t^2) L2P^T + sum_q F_pq F_pq^T
 __global__ void k_gram(LevelView V, const Changed* chg, const FarRef* refs, const FarPair* far,
-                       const ElimNbr* nbrs, const ElimRec* recs) {
-  const Changed C = chg[blockIdx.x >> 1];
-  const int side = blockIdx.x & 1;
+                       const ElimNbr* nbrs, const ElimRec* recs, int sides) {
+  const Changed C = chg[sides == 2 ? blockIdx.x >> 1 : blockIdx.x];
+  const int side = sides == 2 ? (int)(blockIdx.x & 1) : 0;
   const int p = C.p, n = C.n, r = C.r, rc = V.rc[p];
   const double* sig = V.arena + V.sig_off[p];
   double* G = side ? C.gt : C.gs;
@@ -426,8 +435,7 @@ __global__ void k_gram(LevelView V, const Changed* chg, const FarRef* refs, cons
   if (side == 0) {
     // t = diag(sig_s) P2M  (r x n)
     const double* P2M = V.arena + V.p2m_off[p];
-    for (int e = threadIdx.x; e < r * n; e += NT) {
-      const int a = e % r, j = e / r;
+    if (r > 0) WG_FOR2(r, n, a, j) {
       t[a + (int64_t)j * r] = sig[a] * P2M[a + (int64_t)j * rc];
     }
     __syncthreads();
@@ -441,8 +449,7 @@ __global__ void k_gram(LevelView V, const Changed* chg, const FarRef* refs, cons
     }
   } else {
     const double* L2P = V.arena + V.l2p_off[p];
-    for (int e = threadIdx.x; e < n * r; e += NT) {
-      const int j = e % n, a = e / n;
+    if (n > 0) WG_FOR2(n, r, j, a) {
       t[j + (int64_t)a * n] = L2P[j + (int64_t)a * n] * sig[rc + a];
     }
     __syncthreads();
@@ -467,12 +474,10 @@ __global__ void k_basis(LevelView V, const Changed* chg) {
   double* sig = V.arena + V.sig_off[p];
   wg_gemm(r, rn, n, 1.0, P2M, rc, false, C.vs, n, false, 0.0, C.T, r > 0 ? r : 1);
   wg_gemm(rn, r, n, 1.0, C.vt, n, true, L2P, n, false, 0.0, C.S, rn > 0 ? rn : 1);
-  for (int e = threadIdx.x; e < rn * n; e += NT) {
-    const int a = e % rn, j = e / rn;
+  if (rn > 0) WG_FOR2(rn, n, a, j) {
     P2M[a + (int64_t)j * rc] = C.vs[j + (int64_t)a * n];
   }
-  for (int e = threadIdx.x; e < n * rn; e += NT) {
-    const int j = e % n, a = e / n;
+  if (n > 0) WG_FOR2(n, rn, j, a) {
     L2P[j + (int64_t)a * n] = C.vt[j + (int64_t)a * n];
   }
   for (int a = threadIdx.x; a < rn; a += NT) {
@@ -494,8 +499,7 @@ __global__ void k_project(LevelView V, const FarPair* far, const ElimRec* recs, 
   const ElimNbr A = nbrs[R.nb_begin + P.a], B = nbrs[R.nb_begin + P.b];
   if (P.direct) {
     double* dst = V.arena + P.dst;
-    for (int e = threadIdx.x; e < A.m * B.m; e += NT) {
-      const int x = e % A.m, y = e / A.m;
+    if (A.m > 0) WG_FOR2(A.m, B.m, x, y) {
       dst[x + (int64_t)y * P.dst_ld] += P.F[x + (int64_t)y * A.m];
     }
     return;
@@ -547,8 +551,7 @@ __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* 
     const int k = find_ref(refs, C.far_begin, C.far_count, l);
     if (k >= 0) {
       const double* Dm = far[refs[k].ab].F;
-      for (int e = threadIdx.x; e < rn * rln; e += NT) {
-        const int x = e % rn, y = e / rn;
+      if (rn > 0) WG_FOR2(rn, rln, x, y) {
         M[x + (int64_t)y * rcp] += Dm[x + (int64_t)y * rn];
       }
       __syncthreads();
@@ -564,8 +567,7 @@ __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* 
     const int k = find_ref(refs, C.far_begin, C.far_count, l);
     if (k >= 0) {
       const double* Dm = far[refs[k].ba].F;
-      for (int e = threadIdx.x; e < rl * rn; e += NT) {
-        const int x = e % rl, y = e / rl;
+      if (rl > 0) WG_FOR2(rl, rn, x, y) {
         M[x + (int64_t)y * rcl] += Dm[x + (int64_t)y * rl];
       }
       __syncthreads();
@@ -578,6 +580,14 @@ __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* 
     double* L2L = V.arena + V.l2l_off[p];
     wg_gemm(rn, K, r, 1.0, C.S, rn > 0 ? rn : 1, false, L2L, rcp, false, 0.0, t, rn > 0 ? rn : 1);
     wg_copy(rn, K, t, rn > 0 ? rn : 1, L2L, rcp);
+  }
+}
+
+// Debug: flag any non-finite or huge (> 1e300) value in a buffer.
+__global__ void k_check_finite(const double* p, int64_t n, int32_t* flag) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) {
+    const double v = p[e];
+    if (!(fabs(v) <= 1e300)) flag[0] = 1;
   }
 }
 
@@ -605,9 +615,114 @@ __global__ void k_top_assemble(LevelView V, int nn, const int64_t* top_off, doub
   }
 }
 
-__global__ void k_top_getrf(double* T, int n, int32_t* piv, int32_t* info) {
-  const int inf = wg_getrf(n, T, n, piv);
-  if (threadIdx.x == 0) *info = inf;
+// ---- blocked right-looking LU of the dense top matrix (many workgroups)
+constexpr int TOP_NB = 64;
+
+// C tile (64 x 64 at blockIdx) of C = alpha A B + beta C.
+__global__ void k_gemm_tiles(int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
+                             double beta, double* C, int ldc) {
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int mm = min(64, m - i0), nn = min(64, n - j0);
+  if (mm <= 0 || nn <= 0) return;
+  wg_gemm(mm, nn, k, alpha, A + i0, lda, false, B + (int64_t)j0 * ldb, ldb, false, beta, C + i0 + (int64_t)j0 * ldc,
+          ldc);
+}
+
+// Panel T[j0:n, j0:j0+nb]: unblocked LU with partial pivoting over rows j0..n-1
+// (swaps applied inside the panel only); piv[j] = global row swapped with j.
+__global__ void k_lu_panel(double* T, int n, int j0, int nb, int32_t* piv, int32_t* info) {
+  __shared__ double sv[NT];
+  __shared__ int si[NT];
+  const int tid = threadIdx.x;
+  for (int j = j0; j < j0 + nb; ++j) {
+    double best = -1.0;
+    int bi = j;  // in range even for a NaN column
+    for (int i = j + tid; i < n; i += NT) {
+      const double v = fabs(T[i + (int64_t)j * n]);
+      if (v > best) { best = v; bi = i; }
+    }
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double v2 = sv[tid + s];
+        const int i2 = si[tid + s];
+        if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
+      }
+      __syncthreads();
+    }
+    const int p = si[0];
+    const double pv = sv[0];
+    __syncthreads();
+    if (tid == 0) {
+      piv[j] = p;
+      if (pv == 0.0 && *info == 0) *info = j + 1;
+    }
+    if (p != j)
+      for (int c = j0 + tid; c < j0 + nb; c += NT) {
+        const double t = T[j + (int64_t)c * n];
+        T[j + (int64_t)c * n] = T[p + (int64_t)c * n];
+        T[p + (int64_t)c * n] = t;
+      }
+    __syncthreads();
+    const double dj = T[j + (int64_t)j * n];
+    if (dj != 0.0)
+      for (int i = j + 1 + tid; i < n; i += NT) T[i + (int64_t)j * n] /= dj;
+    __syncthreads();
+    const int rem = n - j - 1, w = j0 + nb - j - 1;
+    if (rem > 0 && w > 0) {
+      WG_FOR2(rem, w, ii, cc) T[j + 1 + ii + (int64_t)(j + 1 + cc) * n] -=
+          T[j + 1 + ii + (int64_t)j * n] * T[j + (int64_t)(j + 1 + cc) * n];
+    }
+    __syncthreads();
+  }
+}
+
+// Row interchanges of the panel applied to the columns outside it.
+__global__ void k_lu_swap(double* T, int n, int j0, int nb, const int32_t* piv) {
+  const int c = blockIdx.x * NT + threadIdx.x;
+  if (c >= n || (c >= j0 && c < j0 + nb)) return;
+  for (int j = j0; j < j0 + nb; ++j) {
+    const int p = piv[j];
+    if (p != j) {
+      const double t = T[j + (int64_t)c * n];
+      T[j + (int64_t)c * n] = T[p + (int64_t)c * n];
+      T[p + (int64_t)c * n] = t;
+    }
+  }
+}
+
+// U12 = L11^-1 A12 for 64 columns per workgroup (L11 unit lower, in LDS).
+__global__ void k_lu_trsm(double* T, int n, int j0, int nb) {
+  __shared__ double L[TOP_NB][TOP_NB + 1];
+  const int c0 = j0 + nb + blockIdx.x * 64;
+  for (int e = threadIdx.x; e < nb * nb; e += NT) L[e % nb][e / nb] = T[j0 + e % nb + (int64_t)(j0 + e / nb) * n];
+  __syncthreads();
+  const int c = c0 + (threadIdx.x & 63);
+  const int part = threadIdx.x >> 6;  // 4 threads share a column: rows split by 4
+  const bool act = c < n;
+  double* col = T + j0 + (int64_t)(act ? c : 0) * n;
+  for (int j = 0; j < nb; ++j) {
+    if (act) {
+      const double xj = col[j];
+      for (int i = j + 1 + part; i < nb; i += 4) col[i] -= L[i][j] * xj;
+    }
+    // row j + 1 must be final before the next step reads it (uniform barrier)
+    __syncthreads();
+  }
+}
+
+// Inverse columns: X[:, c0:c0+64] = T^-1 I[:, c0:c0+64] with the LU factors.
+__global__ void k_lu_inverse(const double* T, int n, const int32_t* piv, double* X) {
+  const int c0 = blockIdx.x * 64;
+  const int nc = min(64, n - c0);
+  double* B = X + (int64_t)c0 * n;
+  if (n > 0) {
+    WG_FOR2(n, nc, i, c) B[i + (int64_t)c * n] = (i == c0 + c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  wg_getrs(n, T, n, piv, B, n, nc);
 }
 
 // ------------------------------------------------------------------ solve
@@ -624,8 +739,7 @@ __global__ void k_perm_in(const double* b, int64_t ld, int k, const int64_t* per
   const int i = blockIdx.x;
   const int ni = n[i];
   double* Xi = S.X + S.xo[i] * S.k;
-  for (int e = threadIdx.x; e < ni * k; e += NT) {
-    const int a = e % ni, c = e / ni;
+  if (ni > 0) WG_FOR2(ni, k, a, c) {
     Xi[a + (int64_t)c * ni] = b[perm[pt_begin[i] + a] + (int64_t)c * ld];
   }
 }
@@ -635,8 +749,7 @@ __global__ void k_perm_out(double* x, int64_t ld, int k, const int64_t* perm, co
   const int i = blockIdx.x;
   const int ni = n[i];
   const double* Xi = S.X + S.xo[i] * S.k;
-  for (int e = threadIdx.x; e < ni * k; e += NT) {
-    const int a = e % ni, c = e / ni;
+  if (ni > 0) WG_FOR2(ni, k, a, c) {
     x[perm[pt_begin[i] + a] + (int64_t)c * ld] = Xi[a + (int64_t)c * ni];
   }
 }
@@ -648,8 +761,7 @@ __global__ void k_fwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S, con
   const int n = R.n, r = R.r, d = R.d, k = S.k;
   double* w = S.W + R.wv * k;
   const double* xi = S.X + S.xo[R.node] * k;
-  for (int e = threadIdx.x; e < d * k; e += NT) {
-    const int a = e % d, c = e / d;
+  if (d > 0) WG_FOR2(d, k, a, c) {
     w[a + (int64_t)c * d] = a < n ? xi[a + (int64_t)c * n] : 0.0;
   }
   __syncthreads();
@@ -661,8 +773,7 @@ __global__ void k_fwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S, con
     if (B.m > 0 && n > 0) wg_gemm(B.m, k, n, -1.0, R.L + B.off, R.M, false, w, d, false, 1.0, tgt, B.m);
   }
   double* zi = S.Z + S.zo[R.node] * k;
-  for (int e = threadIdx.x; e < r * k; e += NT) {
-    const int a = e % r, c = e / r;
+  if (r > 0) WG_FOR2(r, k, a, c) {
     zi[a + (int64_t)c * r] += w[n + a + (int64_t)c * d];
   }
   (void)rnow;
@@ -677,8 +788,7 @@ __global__ void k_bwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
   double* t = S.tmp + R.wv * k;
   const double* w = S.W + R.wv * k;
   const double* yi = S.Z + S.zo[R.node] * k;
-  for (int e = threadIdx.x; e < d * k; e += NT) {
-    const int a = e % d, c = e / d;
+  if (d > 0) WG_FOR2(d, k, a, c) {
     t[a + (int64_t)c * d] = a < n ? 0.0 : -yi[(a - n) + (int64_t)c * r];
   }
   __syncthreads();
@@ -689,8 +799,7 @@ __global__ void k_bwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
   }
   wg_getrs(d, R.lu, d, R.piv, t, d, k);
   double* xi = S.X + S.xo[R.node] * k;
-  for (int e = threadIdx.x; e < n * k; e += NT) {
-    const int a = e % n, c = e / n;
+  if (n > 0) WG_FOR2(n, k, a, c) {
     xi[a + (int64_t)c * n] = w[a + (int64_t)c * d] - t[a + (int64_t)c * d];
   }
 }
@@ -705,8 +814,7 @@ __global__ void k_vec_up(SolveView F, SolveView C, const int32_t* child_ptr, con
   for (int s = child_ptr[P]; s < child_ptr[P + 1]; ++s) {
     const int c = child[s], rc = rF[c];
     const double* zc = F.Z + F.zo[c] * k;
-    for (int e = threadIdx.x; e < rc * k; e += NT) {
-      const int a = e % rc, col = e / rc;
+    if (rc > 0) WG_FOR2(rc, k, a, col) {
       xP[off + a + (int64_t)col * nP] = zc[a + (int64_t)col * rc];
     }
     off += rc;
@@ -722,36 +830,28 @@ __global__ void k_vec_down(SolveView F, SolveView C, const int32_t* child_ptr, c
   for (int s = child_ptr[P]; s < child_ptr[P + 1]; ++s) {
     const int c = child[s], rc = rF[c];
     double* yc = F.Z + F.zo[c] * k;
-    for (int e = threadIdx.x; e < rc * k; e += NT) {
-      const int a = e % rc, col = e / rc;
+    if (rc > 0) WG_FOR2(rc, k, a, col) {
       yc[a + (int64_t)col * rc] = xP[off + a + (int64_t)col * nP];
     }
     off += rc;
   }
 }
 
-// Dense top solve: y = T^-1 [z_P ...], written back into the z slots as y.
-__global__ void k_top_solve(SolveView S, int nn, const int32_t* r, const int64_t* top_off, const double* T,
-                            int ldt, const int32_t* piv, double* buf) {
-  const int k = S.k;
-  for (int P = 0; P < nn; ++P) {
-    const int rP = r[P];
-    const double* z = S.Z + S.zo[P] * k;
-    for (int e = threadIdx.x; e < rP * k; e += NT) {
-      const int a = e % rP, c = e / rP;
-      buf[top_off[P] + a + (int64_t)c * ldt] = z[a + (int64_t)c * rP];
-    }
-  }
-  __syncthreads();
-  wg_getrs(ldt, T, ldt, piv, buf, ldt, k);
-  for (int P = 0; P < nn; ++P) {
-    const int rP = r[P];
-    double* z = S.Z + S.zo[P] * k;
-    for (int e = threadIdx.x; e < rP * k; e += NT) {
-      const int a = e % rP, c = e / rP;
-      z[a + (int64_t)c * rP] = buf[top_off[P] + a + (int64_t)c * ldt];
-    }
-  }
+// Top solve with the explicit inverse: gather f = [z_P ...], y = Tinv f (tiled
+// GEMM, separate launch), scatter y back into the z slots.
+__global__ void k_top_gather(SolveView S, int nn, const int32_t* r, const int64_t* top_off, double* buf, int ldt) {
+  const int P = blockIdx.x;
+  const int k = S.k, rP = r[P];
+  const double* z = S.Z + S.zo[P] * k;
+  if (rP > 0) WG_FOR2(rP, k, a, c) buf[top_off[P] + a + (int64_t)c * ldt] = z[a + (int64_t)c * rP];
+}
+
+__global__ void k_top_scatter(SolveView S, int nn, const int32_t* r, const int64_t* top_off, const double* buf,
+                              int ldt) {
+  const int P = blockIdx.x;
+  const int k = S.k, rP = r[P];
+  double* z = S.Z + S.zo[P] * k;
+  if (rP > 0) WG_FOR2(rP, k, a, c) z[a + (int64_t)c * rP] = buf[top_off[P] + a + (int64_t)c * ldt];
 }
 
 }  // namespace ifmm

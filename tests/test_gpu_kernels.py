@@ -1,0 +1,101 @@
+"""Unit tests of individual device routines against numpy (through an
+internal, undeclared test symbol of the library)."""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _syev(mats, k, jacobi):
+    lib = C.CDLL(os.path.join(ROOT, "paper_1905_10602_amd", "libifmm.so"))
+    f = lib.ifmm_internal_syev
+    f.restype = C.c_int
+    f.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
+    cnt, n = len(mats), mats[0].shape[0]
+    A = np.ascontiguousarray(np.stack([np.asfortranarray(m).ravel(order="F") for m in mats]))
+    lam = np.zeros((cnt, n))
+    V = np.zeros((cnt, k * n))
+    rc = f(A.ctypes.data, cnt, n, k, lam.ctypes.data, V.ctypes.data, int(jacobi))
+    assert rc == 0
+    return lam, [V[c].reshape((n, k), order="F") for c in range(cnt)]
+
+
+def _mats(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for kind in range(4):
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        if kind == 0:
+            lam = np.logspace(0, -16, n)
+        elif kind == 1:   # degenerate top eigenvalues
+            lam = np.logspace(0, -12, n)
+            lam[1:4] = lam[0]
+        elif kind == 2:   # rank deficient Gram
+            Z = rng.standard_normal((n, max(1, n // 3)))
+            out.append(Z @ Z.T)
+            continue
+        else:
+            lam = rng.uniform(0, 1, n)
+        out.append((Q * lam) @ Q.T)
+    return [0.5 * (m + m.T) for m in out]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 40, 131, 300])
+@pytest.mark.parametrize("jacobi", [0, 1])
+def test_syev_matches_numpy(n, jacobi):
+    mats = _mats(n, n)
+    k = max(1, min(n, 24))
+    lam, V = _syev(mats, k, jacobi)
+    for G, l, X in zip(mats, lam, V):
+        ref = np.linalg.eigvalsh(G)[::-1]
+        s = max(abs(ref[0]), 1e-300)
+        assert np.abs(l - ref).max() <= 1e-13 * s * max(1, n / 10)
+        lk = l[:k]
+        # eigen-residual and orthonormality of the k leading vectors
+        assert np.linalg.norm(G @ X - X * lk) <= 1e-12 * s * max(1, n / 10)
+        assert np.linalg.norm(X.T @ X - np.eye(k)) <= 1e-10
+
+
+def test_syev_on_ifmm_gram_matrices():
+    # the Gram matrices W^T W of the recompressions of a strongly compressing
+    # case (sphere, N = 1500, leaf 24, eps = 1e-4), taken from the oracle
+    import synth
+    import oracle.ifmm as OI
+    grams = []
+    orig = OI._right_svd
+
+    def spy(W):
+        grams.append(W.T @ W)
+        return orig(W)
+
+    OI._right_svd = spy
+    try:
+        N = 1500
+        pts = synth.sphere_points(N, 1)
+        OI.IFMM(pts, eps=1e-4, sigma=3, diag=synth.laplace_self_term(N), leaf_max=24).factor()
+    finally:
+        OI._right_svd = orig
+    by_n = {}
+    for G in grams:
+        by_n.setdefault(G.shape[0], []).append(0.5 * (G + G.T))
+    worst = 0.0
+    for n, mats in sorted(by_n.items()):
+        ks = []
+        for G in mats:
+            lam = np.linalg.eigvalsh(G)[::-1]
+            ks.append(int(np.sum(lam > 1e-8 * lam[0])) if lam[0] > 0 else 0)
+        k = max(max(ks), 1)
+        lam, V = _syev(mats, k, 0)
+        for G, l, X, kk in zip(mats, lam, V, ks):
+            if kk == 0:
+                continue
+            w, Q = np.linalg.eigh(G)
+            Q = Q[:, ::-1][:, :kk]
+            Xk = X[:, :kk]
+            err = np.linalg.norm(Xk @ Xk.T - Q @ Q.T)
+            worst = max(worst, err)
+            assert err < 1e-6, (n, kk, err)
