@@ -1,0 +1,172 @@
+"""Benchmark of the IFMM hot path on one MI355X.
+
+One step = ifmm_build (host octree, lists, colouring) + ifmm_factor (device
+operators, colour-by-colour elimination, top LU) + ifmm_solve of 8
+right-hand sides, all inputs resident before the timed region (the solve
+takes device pointers).  Workload: the learned-rank configuration's geometry
+at full size - N = 1,048,576 points on the ellipsoid with semi-axes
+(1, 0.7, 0.3) plus 5 % uniform jitter, Laplace kernel, eps = 1e-6, sigma = 3,
+leaves of at most 64 points, Chebyshev 4^3 operators, FP64.
+
+Prints one JSON line (see the keys below).  `roofline` covers the kernel
+class with the largest device time in the timed steps, timed with HIP events
+on its own launch stream inside the library; `cpu_baseline` times the CPU
+oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "IFMM factor s + solve ms/RHS at eps=1e-6, N=1M; mixed vs FP64 on same GPU"
+FP64_VECTOR_PEAK = 78.6e12      # 256 CUs x 2.4 GHz x 128 FP64 flop/clk
+HBM_PEAK = 8.0e12               # bytes/s
+BOUND = {"k_fwd": "hbm", "k_bwd": "hbm", "k_gather": "hbm"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(N, seed=5):
+    import synth
+    axes = (1.0, 0.7, 0.3)
+    pts = synth.ellipsoid_points(N, seed, axes=axes, jitter=0.05)
+    dg = synth.laplace_self_term(N, synth.ellipsoid_area(axes))
+    return pts, dg
+
+
+def cpu_baseline(eps, sigma, nrhs, N_full, budget_s=25.0):
+    """The oracle, untuned, on a bounded sample: the same workload at a
+    reduced N, scaled linearly in N (the IFMM is O(N))."""
+    import numpy as np
+    import synth
+    from oracle.ifmm import IFMM as Oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    N = 4096
+    pts, dg = workload(N)
+    b = synth.uniform_rhs(N, nrhs, 201)
+    t0 = time.perf_counter()
+    F = Oracle(pts, eps=eps, sigma=sigma, diag=dg, leaf_max=64).factor()
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    F.solve(b)
+    ts = time.perf_counter() - t0
+    scale = N_full / N
+    return {"value": tf * scale, "unit": "s (factor, extrapolated)", "cores": int(cores), "kind": "oracle",
+            "sample": f"oracle factor {tf:.2f} s + solve of {nrhs} RHS {ts:.2f} s on the same workload at "
+                      f"N={N}, scaled linearly to N={N_full}; solve {1e3 * ts * scale / nrhs:.1f} ms/RHS"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--eps", type=float, default=1e-6)
+    ap.add_argument("--sigma", type=int, default=3)
+    ap.add_argument("--nrhs", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md, "
+              "not implemented", file=sys.stderr)
+        sys.exit(2)
+    os.environ["IFMM_PROF"] = "1"
+    os.environ.setdefault("IFMM_LOG", "1")
+    import numpy as np
+    import torch
+    import synth
+    from paper_1905_10602_amd import IFMM
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    N = args.n
+    log(f"workload: ellipsoid N={N}")
+    pts, dg = workload(N)
+    b = synth.uniform_rhs(N, args.nrhs, 201)
+    bt = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()  # (nrhs, N) row-major = (N, nrhs) col-major
+    xt = torch.empty_like(bt)
+
+    def step():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = IFMM(pts, args.eps, args.sigma, diag=dg, leaf_max=64)
+        t1 = time.perf_counter()
+        h.factor()
+        t2 = time.perf_counter()
+        from paper_1905_10602_amd.ifmm import load_library, _check, _ptr
+        _check(load_library().ifmm_solve(h._h, _ptr(bt), _ptr(xt), args.nrhs, N, 1))
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        return h, {"build_s": t1 - t0, "factor_s": t2 - t1, "solve_s": t3 - t2, "step_s": t3 - t0}
+
+    for w in range(args.warmup):
+        h, t = step()
+        log(f"warmup {w}: {json.dumps(t)}")
+        del h
+    times = []
+    stats = None
+    torch.cuda.synchronize()
+    for k in range(args.steps):
+        h, t = step()
+        stats = h.stats()
+        times.append(t)
+        log(f"step {k}: {json.dumps(t)}")
+        if k + 1 < args.steps:
+            del h
+    torch.cuda.synchronize()
+    fac = statistics.median(t["factor_s"] for t in times)
+    sol = statistics.median(t["solve_s"] for t in times)
+    stp = statistics.median(t["step_s"] for t in times)
+    # roofline of the kernel class with the largest device time
+    ks = stats.get("kernels", {})
+    dom = max(ks.items(), key=lambda kv: kv[1]["ms"]) if ks else None
+    roof = None
+    if dom:
+        name, k = dom
+        avg_s = k["ms"] / 1e3 / max(k["launches"], 1)
+        if BOUND.get(name) == "hbm":
+            ach = k["bytes"] / max(k["launches"], 1) / avg_s
+            roof = {"kernel": name, "bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK, "traffic": None, "launches": k["launches"], "avg_launch_ms": avg_s * 1e3}
+        else:
+            ach = k["flops"] / max(k["launches"], 1) / avg_s
+            roof = {"kernel": name, "bound": "alu", "achieved": ach / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
+                    "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK, "traffic": None,
+                    "launches": k["launches"], "avg_launch_ms": avg_s * 1e3}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        cpu = cpu_baseline(args.eps, args.sigma, args.nrhs, N)
+    out = {
+        "metric": METRIC, "value": fac, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": stp * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"ellipsoid (1,0.7,0.3) + 5% jitter, N={N}, Laplace 1/(4 pi r), eps={args.eps}, "
+                               f"sigma={args.sigma}, leaf<=64, Chebyshev 4^3, FP64, {args.nrhs} RHS",
+                   "parallelism": "single GPU"},
+        "factor_s": fac, "solve_ms_per_rhs": sol * 1e3 / args.nrhs, "solve_ms": sol * 1e3,
+        "build_s": statistics.median(t["build_s"] for t in times),
+        "depth": stats.get("depth"), "top_n": stats.get("top_n"), "device_GB": stats.get("device_bytes", 0) / 1e9,
+        "factor_store_GB": stats.get("store_bytes", 0) / 1e9,
+        "levels": [{k2: L[k2] for k2 in ("level", "nodes", "colours", "rank_sum", "rank_max", "n_max", "t_elim")}
+                   for L in stats.get("levels", [])],
+        "kernels_ms": {n: round(k["ms"], 3) for n, k in ks.items()},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,5 +1,6 @@
 // C ABI of the library (declared in include/ifmm.h).  Argument checking,
 // error reporting and handle life-time; the work is in engine.hip / tree.cpp.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -140,7 +141,7 @@ ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
                   ",\"t_init\":" + std::to_string(h.t_init) + ",\"t_factor\":" + std::to_string(h.t_factor) +
                   ",\"t_solve\":" + std::to_string(h.t_solve) + ",\"device_bytes\":" + std::to_string(h.dev_bytes) +
                   ",\"store_bytes\":" + std::to_string(h.store_bytes) + ",\"top_n\":" + std::to_string(h.top_n) +
-                  ",\"t_top\":" + std::to_string(h.t_top) + ",\"far_pairs\":" + std::to_string(h.stat_far) + ",\"changed\":" + std::to_string(h.stat_changed) +
+                  ",\"t_top\":" + std::to_string(h.t_top) + ",\"far_pairs\":" + std::to_string(h.stat_far) + ",\"changed\":" + std::to_string(h.stat_changed) + ",\"grown\":" + std::to_string(h.stat_grown) +
                   ",\"levels\":[";
   for (int l = 2; l <= h.tree.depth; ++l) {
     const ifmm::Level& T = h.tree.levels[l];
@@ -156,7 +157,17 @@ ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
          ",\"t_setup\":" + std::to_string((int)h.t_level_setup.size() > l ? h.t_level_setup[l] : 0.0) +
          ",\"t_elim\":" + std::to_string((int)h.t_level_elim.size() > l ? h.t_level_elim[l] : 0.0) + "}";
   }
-  s += "]}";
+  s += "],\"kernels\":{";
+  bool first = true;
+  for (const auto& kv : h.kstat) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s\"%s\":{\"launches\":%lld,\"ms\":%.6f,\"flops\":%.6e,\"bytes\":%.6e}",
+                  first ? "" : ",", kv.first.c_str(), (long long)kv.second.launches, kv.second.ms, kv.second.flops,
+                  kv.second.bytes);
+    s += buf;
+    first = false;
+  }
+  s += "}}";
   std::snprintf(json, (size_t)cap, "%s", s.c_str());
   return IFMM_OK;
 }

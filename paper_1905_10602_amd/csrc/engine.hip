@@ -120,6 +120,53 @@ static int ensure(Handle& h, void** buf, int64_t* cap, int64_t bytes, std::strin
   return 0;
 }
 
+// ---- per-kernel-class timing (IFMM_PROF)
+static hipEvent_t take_event(Handle& h) {
+  if (!h.event_pool.empty()) {
+    hipEvent_t e = h.event_pool.back();
+    h.event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+struct ProfScope {
+  Handle& h;
+  Handle::Pending p;
+  bool on;
+  ProfScope(Handle& hh, const char* name, double flops, double bytes) : h(hh), on(hh.prof) {
+    if (!on) return;
+    p.a = take_event(h);
+    p.b = take_event(h);
+    p.name = name;
+    p.flops = flops;
+    p.bytes = bytes;
+    (void)hipEventRecord(p.a, h.stream);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(p.b, h.stream);
+    h.pending.push_back(p);
+  }
+};
+// called after a stream synchronisation
+static void prof_collect(Handle& h) {
+  for (auto& p : h.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      auto& k = h.kstat[p.name];
+      k.launches += 1;
+      k.ms += ms;
+      k.flops += p.flops;
+      k.bytes += p.bytes;
+    }
+    h.event_pool.push_back(p.a);
+    h.event_pool.push_back(p.b);
+  }
+  h.pending.clear();
+}
+
 // IFMM_CHECK: after a step, scan the level arena for non-finite / huge values.
 static int check_arena(Handle& h, int l, const char* step, int c, std::string& err) {
   if (!h.check) return 0;
@@ -147,7 +194,8 @@ static LevelView view_of(DevLevel& L) {
   V.arena = L.arena;
   V.n = L.d_n; V.r = L.d_r; V.rc = L.d_rc; V.coord = L.d_coord;
   V.near_ptr = L.d_near_ptr; V.near_idx = L.d_near_idx; V.il_ptr = L.d_il_ptr; V.il_idx = L.d_il_idx;
-  V.near_off = L.d_near_off; V.il_off = L.d_il_off; V.p2m_off = L.d_p2m_off; V.l2p_off = L.d_l2p_off;
+  V.near_off = L.d_near_off; V.p2m_off = L.d_p2m_off; V.l2p_off = L.d_l2p_off;
+  V.il_blk = L.d_il_blk; V.ilcap = L.d_ilcap;
   V.sig_off = L.d_sig_off; V.m2m_off = L.d_m2m_off; V.l2l_off = L.d_l2l_off;
   V.cp2m_off = L.d_cp2m_off; V.cl2p_off = L.d_cl2p_off; V.T_off = L.d_T_off; V.S_off = L.d_S_off;
   V.chg = L.d_chg;
@@ -197,9 +245,9 @@ static int setup_level(Handle& h, int l, std::string& err) {
   L.near_off.resize(L.near_idx.size());
   for (int32_t i = 0; i < nn; ++i)
     for (int s = L.near_ptr[i]; s < L.near_ptr[i + 1]; ++s) L.near_off[s] = take((int64_t)L.n[i] * L.n[L.near_idx[s]]);
-  L.il_off.resize(T.il.size());
-  for (int32_t i = 0; i < nn; ++i)
-    for (int s = T.il_ptr[i]; s < T.il_ptr[i + 1]; ++s) L.il_off[s] = take((int64_t)L.rc[i] * L.rc[T.il[s]]);
+  // M2L blocks are allocated once the ranks are known (reduce_level)
+  L.il_blk.assign(T.il.size(), nullptr);
+  L.ilcap.assign(nn, 0);
   L.p2m_off.resize(nn); L.l2p_off.resize(nn); L.sig_off.resize(nn); L.m2m_off.resize(nn); L.l2l_off.resize(nn);
   L.cp2m_off.resize(nn); L.cl2p_off.resize(nn); L.T_off.resize(nn); L.S_off.resize(nn);
   for (int32_t i = 0; i < nn; ++i) {
@@ -228,7 +276,6 @@ static int setup_level(Handle& h, int l, std::string& err) {
   if ((rc = upload(h, &L.d_il_ptr, T.il_ptr, err))) return rc;
   if ((rc = upload(h, &L.d_il_idx, T.il, err))) return rc;
   if ((rc = upload(h, &L.d_near_off, L.near_off, err))) return rc;
-  if ((rc = upload(h, &L.d_il_off, L.il_off, err))) return rc;
   if ((rc = upload(h, &L.d_p2m_off, L.p2m_off, err))) return rc;
   if ((rc = upload(h, &L.d_l2p_off, L.l2p_off, err))) return rc;
   if ((rc = upload(h, &L.d_sig_off, L.sig_off, err))) return rc;
@@ -254,16 +301,48 @@ static int setup_level(Handle& h, int l, std::string& err) {
 static void release_level_work(Handle& h, int l) {
   DevLevel& L = h.lv[l];
   void* ptrs[] = {L.arena, L.d_near_ptr, L.d_near_idx, L.d_slot_row, L.d_il_ptr, L.d_il_idx, L.d_near_off,
-                  L.d_il_off, L.d_p2m_off, L.d_l2p_off, L.d_sig_off, L.d_m2m_off, L.d_l2l_off, L.d_cp2m_off,
-                  L.d_cl2p_off, L.d_T_off, L.d_S_off, L.d_chg, L.d_rc, L.d_coord};
+                  L.d_p2m_off, L.d_l2p_off, L.d_sig_off, L.d_m2m_off, L.d_l2l_off, L.d_cp2m_off,
+                  L.d_cl2p_off, L.d_T_off, L.d_S_off, L.d_chg, L.d_rc, L.d_coord,
+                  (void*)L.d_il_blk, (void*)L.d_il_blk_old, L.d_ilcap, L.d_ilcap_old};
   for (void* p : ptrs) dfree(h, p);
+  for (double* c : L.il_chunks) dfree(h, c);
+  L.il_chunks.clear();
+  L.il_cur = nullptr;
+  L.il_left = 0;
+  L.d_il_blk = L.d_il_blk_old = nullptr;
+  L.d_ilcap = L.d_ilcap_old = nullptr;
   L.arena = nullptr;
   L.d_near_ptr = L.d_near_idx = L.d_slot_row = L.d_il_ptr = L.d_il_idx = nullptr;
-  L.d_near_off = L.d_il_off = L.d_p2m_off = L.d_l2p_off = L.d_sig_off = L.d_m2m_off = L.d_l2l_off = nullptr;
+  L.d_near_off = L.d_p2m_off = L.d_l2p_off = L.d_sig_off = L.d_m2m_off = L.d_l2l_off = nullptr;
   L.d_cp2m_off = L.d_cl2p_off = L.d_T_off = L.d_S_off = nullptr;
   L.d_chg = nullptr;
   L.d_rc = nullptr;
   L.d_coord = nullptr;
+}
+
+// Bump allocator of the level's M2L block pool (chunks of >= 256 MiB).
+static int il_take(Handle& h, DevLevel& L, int64_t doubles, double** out, std::string& err) {
+  doubles = (std::max<int64_t>(doubles, 1) + 7) & ~7LL;
+  if (doubles > L.il_left) {
+    const int64_t chunk = std::max<int64_t>(doubles, (int64_t)1 << 25);
+    double* p = nullptr;
+    int rc = dalloc(h, &p, chunk, err);
+    if (rc) return rc;
+    L.il_chunks.push_back(p);
+    L.il_cur = p;
+    L.il_left = chunk;
+  }
+  *out = L.il_cur;
+  L.il_cur += doubles;
+  L.il_left -= doubles;
+  L.il_bytes += doubles * 8;
+  return 0;
+}
+
+// Capacity of a node's M2L rows / columns for rank r: headroom for the growth
+// that later recompressions bring, never above rc.
+static int32_t il_capacity(const Handle& h, int32_t r, int32_t rc) {
+  return h.il_tight ? std::min(rc, r) : std::min(rc, r + std::max(8, r / 2));
 }
 
 // Initial rank reduction of every node of level l (square pivots, far-field
@@ -338,6 +417,19 @@ static int reduce_level(Handle& h, int l, std::string& err) {
     }
   HIPCHK(hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
   HIPCHK(hipMemcpyAsync(L.d_r, L.r.data(), nn * 4, hipMemcpyHostToDevice, h.stream));
+  // M2L block pool sized from the ranks just found
+  {
+    const Level& T = h.tree.levels[l];
+    for (int32_t i = 0; i < nn; ++i) L.ilcap[i] = il_capacity(h, L.r[i], L.rc[i]);
+    for (int32_t i = 0; i < nn; ++i)
+      for (int s2 = T.il_ptr[i]; s2 < T.il_ptr[i + 1]; ++s2)
+        if ((rc = il_take(h, L, (int64_t)L.ilcap[i] * L.ilcap[T.il[s2]], &L.il_blk[s2], err))) return rc;
+    if ((rc = upload(h, &L.d_il_blk, L.il_blk, err))) return rc;
+    if ((rc = upload(h, &L.d_il_blk_old, L.il_blk, err))) return rc;
+    if ((rc = upload(h, &L.d_ilcap, L.ilcap, err))) return rc;
+    if ((rc = upload(h, &L.d_ilcap_old, L.ilcap, err))) return rc;
+  }
+  V = view_of(L);
   const double side = 2.0 * h.tree.H / (double)(1LL << l);
   if (nn > 0) {
     if (!h.eig_jacobi) hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, d_tasks);
@@ -457,8 +549,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
           err = "internal: far neighbour pair is not in the interaction list";
           return -1;
         }
-        F.dst = L.il_off[found];
-        F.dst_ld = L.rc[pa];
+        F.dst = L.il_blk[found];
+        F.dst_ld = L.ilcap[pa];
         F.pad = 0;
         far.push_back(F);
       }
@@ -564,27 +656,64 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   const XTask* d_xt = (const XTask*)(M + o_xt);
   LevelView V = view_of(L);
   const int nchg = (int)chg.size();
+  // algorithmic work of the phase-A steps (counted from the block sizes)
+  double fl_lu = 0, fl_x = 0, fl_schur = 0, by_gather = 0;
+  for (const ElimRec& R : recs) {
+    const double d = R.d, n = R.n, M = R.M, r = R.r;
+    fl_lu += 2.0 / 3.0 * d * d * d;
+    fl_x += 2.0 * d * d * (M + r);
+    fl_schur += 2.0 * M * n * (M + r);
+    by_gather += 8.0 * (d * d + 2.0 * M * n) * 2.0;
+  }
+  double fl_gram = 0, fl_ev = 0, fl_evec = 0;
+  for (const Changed& C : chg) {
+    double sm = C.r;
+    for (int q = 0; q < C.far_count; ++q) {
+      const FarPair& F = far[refs[C.far_begin + q].ba];
+      sm += nbrs[recs[F.rec].nb_begin + F.a].m;
+    }
+    fl_gram += sides * 2.0 * C.n * C.n * sm;
+    fl_ev += sides * 4.0 / 3.0 * (double)C.n * C.n * C.n;
+  }
   // ---- phase A
-  hipLaunchKernelGGL(k_gather, dim3(nrec), dim3(NT), 0, h.stream, V, d_recs, d_nbrs);
+  {
+    ProfScope ps(h, "k_gather", 0, by_gather);
+    hipLaunchKernelGGL(k_gather, dim3(nrec), dim3(NT), 0, h.stream, V, d_recs, d_nbrs);
+  }
   if ((rc = check_arena(h, l, "gather", c, err))) return rc;
-  hipLaunchKernelGGL(k_getrf, dim3(nrec), dim3(NT), 0, h.stream, d_recs, d_info);
-  if (!xtasks.empty())
+  {
+    ProfScope ps(h, "k_getrf", fl_lu, 0);
+    hipLaunchKernelGGL(k_getrf, dim3(nrec), dim3(NT), 0, h.stream, d_recs, d_info);
+  }
+  if (!xtasks.empty()) {
+    ProfScope ps(h, "k_xsolve", fl_x, 0);
     hipLaunchKernelGGL(k_xsolve, dim3((unsigned)xtasks.size()), dim3(NT), 0, h.stream, d_recs, d_xt);
-  hipLaunchKernelGGL(k_schur, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks, d_fidx,
-                     d_far);
+  }
+  {
+    ProfScope ps(h, "k_schur", fl_schur, 0);
+    hipLaunchKernelGGL(k_schur, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks, d_fidx,
+                       d_far);
+  }
   if ((rc = check_arena(h, l, "schur", c, err))) return rc;
   if (nchg) {
     hipLaunchKernelGGL(k_set_chg, dim3((nchg + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_chg, d_chg, nchg, 0);
-    hipLaunchKernelGGL(k_gram, dim3(sides * nchg), dim3(NT), 0, h.stream, V, d_chg, d_refs, d_far, d_nbrs, d_recs,
-                       sides);
-    hipLaunchKernelGGL(k_eig_values, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et, h.eps * h.eps,
-                       d_cnt, h.eig_jacobi ? 1 : 0);
+    {
+      ProfScope ps(h, "k_gram", fl_gram, 0);
+      hipLaunchKernelGGL(k_gram, dim3(sides * nchg), dim3(NT), 0, h.stream, V, d_chg, d_refs, d_far, d_nbrs, d_recs,
+                         sides);
+    }
+    {
+      ProfScope ps(h, "k_eig_values", fl_ev, 0);
+      hipLaunchKernelGGL(k_eig_values, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et, h.eps * h.eps,
+                         d_cnt, h.eig_jacobi ? 1 : 0);
+    }
   }
   HIPCHK(hipGetLastError());
   std::vector<int32_t> cnt(etasks.size()), info(nrec);
   if (nchg) HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * 4, hipMemcpyDeviceToHost, h.stream));
   HIPCHK(hipMemcpyAsync(info.data(), d_info, nrec * 4, hipMemcpyDeviceToHost, h.stream));
   HIPCHK(hipStreamSynchronize(h.stream));
+  prof_collect(h);
   for (int k = 0; k < nrec; ++k)
     if (info[k]) {
       err = "singular pivot block at level " + std::to_string(l) + ", node " + std::to_string(recs[k].node);
@@ -611,16 +740,99 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     HIPCHK(hipMemcpyAsync((void*)d_et, etasks.data(), etasks.size() * sizeof(EigTask), hipMemcpyHostToDevice,
                           h.stream));
     HIPCHK(hipMemcpyAsync(d_chg, chg.data(), chg.size() * sizeof(Changed), hipMemcpyHostToDevice, h.stream));
-    if (!h.eig_jacobi) hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et);
+    for (int k = 0; k < nchg; ++k) fl_evec += sides * 2.0 * (double)chg[k].n * chg[k].n * chg[k].rnew;
+    if (!h.eig_jacobi) {
+      ProfScope ps(h, "k_eig_vectors", fl_evec, 0);
+      hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et);
+    }
     hipLaunchKernelGGL(k_basis, dim3(nchg), dim3(NT), 0, h.stream, V, d_chg);
     if ((rc = check_arena(h, l, "basis", c, err))) return rc;
+  }
+  // capacity growth of the M2L blocks of nodes whose new rank exceeds it
+  std::vector<SlotMove> moves;
+  std::vector<int32_t> capset;
+  if (nchg) {
+    const Level& TL = h.tree.levels[l];
+    std::vector<int32_t> newcap(chg.size(), 0);
+    std::vector<char> grown_mark;
+    bool any = false;
+    for (size_t k = 0; k < chg.size(); ++k) {
+      const int p = chg[k].p;
+      if (chg[k].rnew > L.ilcap[p]) {
+        newcap[k] = h.il_tight ? chg[k].rnew
+                               : std::min(L.rc[p], std::max(chg[k].rnew, L.ilcap[p] + L.ilcap[p] / 2 + 8));
+        any = true;
+      }
+    }
+    if (any) {
+      std::vector<int32_t> cap_now(L.ilcap);  // capacities after growth
+      for (size_t k = 0; k < chg.size(); ++k)
+        if (newcap[k]) cap_now[chg[k].p] = newcap[k];
+      for (size_t k = 0; k < chg.size(); ++k) {
+        if (!newcap[k]) continue;
+        const int p = chg[k].p;
+        for (int s2 = TL.il_ptr[p]; s2 < TL.il_ptr[p + 1]; ++s2) {
+          const int lq = TL.il[s2];
+          double* ptr = nullptr;
+          if ((rc = il_take(h, L, (int64_t)cap_now[p] * cap_now[lq], &ptr, err))) return rc;
+          moves.push_back({s2, 0, ptr});
+          L.il_blk[s2] = ptr;
+          if (cap_now[lq] == L.ilcap[lq]) {  // l keeps its capacity: move its column block too
+            int lo = TL.il_ptr[lq], hi = TL.il_ptr[lq + 1] - 1, f = -1;
+            while (lo <= hi) {
+              const int mid = (lo + hi) >> 1;
+              if (TL.il[mid] == p) { f = mid; break; }
+              if (TL.il[mid] < p) lo = mid + 1; else hi = mid - 1;
+            }
+            double* ptr2 = nullptr;
+            if ((rc = il_take(h, L, (int64_t)cap_now[lq] * cap_now[p], &ptr2, err))) return rc;
+            moves.push_back({f, 0, ptr2});
+            L.il_blk[f] = ptr2;
+          }
+        }
+      }
+      for (size_t k = 0; k < chg.size(); ++k)
+        if (newcap[k]) {
+          capset.push_back(chg[k].p);
+          capset.push_back(newcap[k]);
+        }
+      const int64_t need = (int64_t)(moves.size() * sizeof(SlotMove) + capset.size() * 4 + 512);
+      if ((rc = ensure(h, (void**)&h.meta2, &h.meta2_bytes, need, err))) return rc;
+      SlotMove* d_mv = (SlotMove*)h.meta2;
+      int32_t* d_cs = (int32_t*)(h.meta2 + ((moves.size() * sizeof(SlotMove) + 255) & ~(size_t)255));
+      HIPCHK(hipMemcpyAsync(d_mv, moves.data(), moves.size() * sizeof(SlotMove), hipMemcpyHostToDevice, h.stream));
+      HIPCHK(hipMemcpyAsync(d_cs, capset.data(), capset.size() * 4, hipMemcpyHostToDevice, h.stream));
+      const int nm = (int)moves.size(), nc2 = (int)capset.size() / 2;
+      hipLaunchKernelGGL(k_slot_moves, dim3((nm + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_il_blk, d_mv, nm);
+      hipLaunchKernelGGL(k_set_caps, dim3((nc2 + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_ilcap, d_cs, nc2);
+      for (size_t k = 0; k < chg.size(); ++k)
+        if (newcap[k]) L.ilcap[chg[k].p] = newcap[k];
+      h.stat_grown += nc2;
+    }
   }
   if (!far.empty())
     hipLaunchKernelGGL(k_project, dim3((unsigned)far.size()), dim3(NT), 0, h.stream, V, d_far, d_recs, d_nbrs, d_chg);
   if ((rc = check_arena(h, l, "project", c, err))) return rc;
   // ---- phase B
   if (nchg) {
-    hipLaunchKernelGGL(k_phase_b, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far, l > 2 ? 1 : 0);
+    {
+      double fl_b = 0;
+      for (const Changed& C : chg) {
+        const Level& TL = h.tree.levels[l];
+        const double nil = TL.il_ptr[C.p + 1] - TL.il_ptr[C.p];
+        fl_b += 2.0 * nil * 2.0 * (double)C.r * C.rnew * std::max(C.r, C.rnew) + 4.0 * K * C.r * C.rnew;
+      }
+      ProfScope ps(h, "k_phase_b", fl_b, 0);
+      hipLaunchKernelGGL(k_phase_b, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far, l > 2 ? 1 : 0,
+                         L.d_il_blk_old, L.d_ilcap_old);
+    }
+    if (!moves.empty()) {  // old tables follow the new ones again
+      SlotMove* d_mv = (SlotMove*)h.meta2;
+      int32_t* d_cs = (int32_t*)(h.meta2 + ((moves.size() * sizeof(SlotMove) + 255) & ~(size_t)255));
+      const int nm = (int)moves.size(), nc2 = (int)capset.size() / 2;
+      hipLaunchKernelGGL(k_slot_moves, dim3((nm + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_il_blk_old, d_mv, nm);
+      hipLaunchKernelGGL(k_set_caps, dim3((nc2 + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_ilcap_old, d_cs, nc2);
+    }
     if ((rc = check_arena(h, l, "phase_b", c, err))) return rc;
     hipLaunchKernelGGL(k_set_rank, dim3((nchg + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_r, d_chg, nchg);
     hipLaunchKernelGGL(k_set_chg, dim3((nchg + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_chg, d_chg, nchg, 1);
@@ -639,6 +851,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   h.stat_changed += nchg;
   // the host tables above are uploaded asynchronously: wait before they go away
   HIPCHK(hipStreamSynchronize(h.stream));
+  prof_collect(h);
   return 0;
 }
 
@@ -749,8 +962,12 @@ int factor(Handle& h, std::string& err) {
     const char* ev = std::getenv("IFMM_EIG");
     h.eig_jacobi = ev && std::strcmp(ev, "jacobi") == 0;
   }
+  h.prof = std::getenv("IFMM_PROF") != nullptr;
+  h.il_tight = std::getenv("IFMM_IL_TIGHT") != nullptr;
+  h.kstat.clear();
   h.stat_far = 0;
   h.stat_changed = 0;
+  h.stat_grown = 0;
   const double t0 = now_s();
   h.t_level_setup.assign((size_t)h.tree.depth + 1, 0.0);
   h.t_level_elim.assign((size_t)h.tree.depth + 1, 0.0);
@@ -875,7 +1092,16 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
     SolveView S = sv(l);
     for (size_t c = 0; c + 1 < L.col_ptr.size(); ++c) {
       const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
-      if (b > a) hipLaunchKernelGGL(k_fwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S, L.d_r);
+      if (b > a) {
+        double by = 0;
+        if (h.prof)
+          for (int e = a; e < b; ++e) {
+            const ElimRec& R = L.recs[e];
+            by += 8.0 * ((double)R.d * R.d + (double)R.M * R.n + k * (2.0 * R.n + 2.0 * R.M + 2.0 * R.d));
+          }
+        ProfScope ps(h, "k_fwd", 0, by);
+        hipLaunchKernelGGL(k_fwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S, L.d_r);
+      }
     }
     if (l > 2) {
       const DevLevel& P = h.lv[l - 1];
@@ -904,7 +1130,16 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
     }
     for (int c = (int)L.col_ptr.size() - 2; c >= 0; --c) {
       const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
-      if (b > a) hipLaunchKernelGGL(k_bwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S);
+      if (b > a) {
+        double by = 0;
+        if (h.prof)
+          for (int e = a; e < b; ++e) {
+            const ElimRec& R = L.recs[e];
+            by += 8.0 * ((double)R.d * R.d + (double)R.M * R.n + k * (2.0 * R.n + 2.0 * R.M + 3.0 * R.d));
+          }
+        ProfScope ps(h, "k_bwd", 0, by);
+        hipLaunchKernelGGL(k_bwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S);
+      }
     }
   }
   hipLaunchKernelGGL(k_perm_out, dim3(TL.n), dim3(NT), 0, h.stream, d_x, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
@@ -912,6 +1147,7 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
   HIPCHK(hipGetLastError());
   if (!on_device) HIPCHK(hipMemcpyAsync(x, d_x, (size_t)ld * k * 8, hipMemcpyDeviceToHost, h.stream));
   HIPCHK(hipStreamSynchronize(h.stream));
+  prof_collect(h);
   h.t_solve = now_s() - t0;
   return 0;
 }
@@ -989,6 +1225,13 @@ void release(Handle& h) {
   h.allocs.clear();
   if (h.d_flag) (void)hipFree(h.d_flag);
   h.d_flag = nullptr;
+  for (auto& p : h.pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  h.pending.clear();
+  for (hipEvent_t e : h.event_pool) (void)hipEventDestroy(e);
+  h.event_pool.clear();
   h.dev_bytes = 0;
   h.dev_ready = false;
 }

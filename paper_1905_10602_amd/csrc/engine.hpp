@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -44,7 +45,7 @@ struct FarPair {
   int32_t rec, a, b, direct;  // direct: both eliminated, add F straight into the M2L block
   double* F;                  // -L_a X_b, m_a x m_b (ld m_a); later the projected block
   double* D;                  // workspace, m_a x m_b
-  int64_t dst;                // M2L block (p_a, p_b) in the level arena
+  double* dst;                // M2L block (p_a, p_b)
   int32_t dst_ld, pad;
 };
 
@@ -72,14 +73,24 @@ struct DevLevel {
   // host mirrors
   std::vector<int32_t> n, r, rc;
   std::vector<int32_t> near_ptr, near_idx, slot_row;  // near list of i: i itself, then N_i
-  std::vector<int64_t> near_off, il_off, p2m_off, l2p_off, sig_off, m2m_off, l2l_off;
+  std::vector<int64_t> near_off, p2m_off, l2p_off, sig_off, m2m_off, l2l_off;
+  // M2L blocks of the interaction lists: per slot a pointer into the level's
+  // block pool, capacity ilcap[t] x ilcap[s], leading dimension ilcap[t]
+  std::vector<double*> il_blk;
+  std::vector<int32_t> ilcap;
+  std::vector<double*> il_chunks;
+  double* il_cur = nullptr;
+  int64_t il_left = 0, il_bytes = 0;
+  double** d_il_blk = nullptr;
+  double** d_il_blk_old = nullptr;
+  int32_t *d_ilcap = nullptr, *d_ilcap_old = nullptr;
   std::vector<int64_t> cp2m_off, cl2p_off, T_off, S_off;
   int64_t arena_doubles = 0;
   // device working storage of the level (freed once the level is aggregated)
   double* arena = nullptr;
   int32_t *d_rc = nullptr, *d_coord = nullptr, *d_near_ptr = nullptr, *d_near_idx = nullptr;
   int32_t *d_slot_row = nullptr, *d_il_ptr = nullptr, *d_il_idx = nullptr, *d_chg = nullptr;
-  int64_t *d_near_off = nullptr, *d_il_off = nullptr, *d_p2m_off = nullptr, *d_l2p_off = nullptr;
+  int64_t *d_near_off = nullptr, *d_p2m_off = nullptr, *d_l2p_off = nullptr;
   int64_t *d_sig_off = nullptr, *d_m2m_off = nullptr, *d_l2l_off = nullptr;
   int64_t *d_cp2m_off = nullptr, *d_cl2p_off = nullptr, *d_T_off = nullptr, *d_S_off = nullptr;
   // kept for the solve
@@ -125,6 +136,8 @@ struct Handle {
   int64_t scratch_bytes = 0;
   char* meta = nullptr;
   int64_t meta_bytes = 0;
+  char* meta2 = nullptr;  // slot moves of grown M2L blocks
+  int64_t meta2_bytes = 0;
   std::vector<char> host_meta;
   double* svec = nullptr;
   int64_t svec_bytes = 0;
@@ -141,12 +154,28 @@ struct Handle {
   bool factored = false;
   // statistics
   double t_init = 0, t_factor = 0, t_solve = 0;
-  int64_t stat_far = 0, stat_changed = 0;
+  int64_t stat_far = 0, stat_changed = 0, stat_grown = 0;
   std::vector<double> t_level_setup, t_level_elim;  // per level: set-up + rank reduction, colour loop
   double t_top = 0;
   bool log = false;         // IFMM_LOG set: one progress line per level on stderr
   bool poison = false;      // IFMM_POISON set: fill new device allocations with a huge value (debugging)
   bool check = false;       // IFMM_CHECK set: scan the level arena after every step (debugging)
+  // IFMM_PROF set: per kernel class, launches / time (hipEvents on the launch
+  // stream) / algorithmic flops and bytes of the instrumented launches
+  bool prof = false;
+  bool il_tight = false;    // IFMM_IL_TIGHT set: no capacity headroom for M2L blocks (tests the growth path)
+  struct KStat {
+    int64_t launches = 0;
+    double ms = 0, flops = 0, bytes = 0;
+  };
+  std::map<std::string, KStat> kstat;
+  struct Pending {
+    hipEvent_t a, b;
+    std::string name;
+    double flops, bytes;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
   int32_t* d_flag = nullptr;
   bool eig_jacobi = false;  // IFMM_EIG=jacobi: cyclic Jacobi instead of tridiagonal + bisection
 };

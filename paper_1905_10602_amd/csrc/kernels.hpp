@@ -17,7 +17,9 @@ struct LevelView {
   double* arena;
   const int32_t *n, *r, *rc, *coord;
   const int32_t *near_ptr, *near_idx, *il_ptr, *il_idx;
-  const int64_t *near_off, *il_off, *p2m_off, *l2p_off, *sig_off, *m2m_off, *l2l_off;
+  const int64_t *near_off, *p2m_off, *l2p_off, *sig_off, *m2m_off, *l2l_off;
+  double* const* il_blk;  // M2L block (t, il_idx[s]) of slot s; leading dimension ilcap[t]
+  const int32_t* ilcap;
   const int64_t *cp2m_off, *cl2p_off, *T_off, *S_off;  // Chebyshev-basis operators and initial transforms
   const int32_t* chg;                                   // changed-node index per node (-1 = unchanged)
 };
@@ -35,13 +37,13 @@ __device__ inline int64_t near_block(const LevelView& V, int p, int q) {
   return -1;
 }
 
-// M2L block (t, s), s in I_t: offset in the arena (ld = rc_t)
-__device__ inline int64_t il_block(const LevelView& V, int t, int s) {
+// slot of the M2L block (t, s), s in I_t (binary search in the sorted list)
+__device__ inline int il_slot(const LevelView& V, int t, int s) {
   int lo = V.il_ptr[t], hi = V.il_ptr[t + 1] - 1;
   while (lo <= hi) {
     const int mid = (lo + hi) >> 1;
     const int v = V.il_idx[mid];
-    if (v == s) return V.il_off[mid];
+    if (v == s) return mid;
     if (v < s) lo = mid + 1; else hi = mid - 1;
   }
   return -1;
@@ -282,7 +284,7 @@ __global__ void k_reduce_m2l(LevelView V, int K, const double* unit, double invL
     if (rl == 0) continue;
     const double* U = unit + (int64_t)offset_index(V.coord, i, l) * K * K;
     wg_gemm(K, rl, K, invL, U, K, false, V.arena + V.T_off[l], K, false, 0.0, t, K);
-    wg_gemm(ri, rl, K, 1.0, S, rci, false, t, K, false, 0.0, V.arena + V.il_off[s], rci);
+    wg_gemm(ri, rl, K, 1.0, S, rci, false, t, K, false, 0.0, V.il_blk[s], V.ilcap[i]);
   }
 }
 
@@ -322,7 +324,7 @@ __global__ void k_agg_near(LevelView C, LevelView F, const int32_t* slot_row, co
         if (dist3(F.coord, c, cc) <= 1) {
           wg_copy(rcr, rcc, F.arena + near_block(F, c, cc), F.n[c], B + ro + (int64_t)co * nP, nP);
         } else {
-          wg_copy(rcr, rcc, F.arena + il_block(F, c, cc), F.rc[c], B + ro + (int64_t)co * nP, nP);
+          wg_copy(rcr, rcc, F.il_blk[il_slot(F, c, cc)], F.ilcap[c], B + ro + (int64_t)co * nP, nP);
         }
       }
       co += rcc;
@@ -498,7 +500,7 @@ __global__ void k_project(LevelView V, const FarPair* far, const ElimRec* recs, 
   const ElimRec R = recs[P.rec];
   const ElimNbr A = nbrs[R.nb_begin + P.a], B = nbrs[R.nb_begin + P.b];
   if (P.direct) {
-    double* dst = V.arena + P.dst;
+    double* dst = P.dst;
     if (A.m > 0) WG_FOR2(A.m, B.m, x, y) {
       dst[x + (int64_t)y * P.dst_ld] += P.F[x + (int64_t)y * A.m];
     }
@@ -531,8 +533,10 @@ __device__ inline int find_ref(const FarRef* refs, int begin, int count, int q) 
 // else by s's, so every block is written once.
 //   (p, l):              S_p M (T_l if l changed) + D_pl
 //   (l, p), l unchanged: M T_p + D_lp
+// A block whose capacity grew is read from its old storage (blk_old, ld
+// cap_old) and written to its new one (V.il_blk, ld V.ilcap).
 __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* refs, const FarPair* far,
-                          int has_parent) {
+                          int has_parent, double* const* blk_old, const int32_t* cap_old) {
   const Changed C = chg[blockIdx.x];
   const int p = C.p, r = C.r, rn = C.rnew, rcp = V.rc[p];
   double* t = C.tmp;
@@ -540,19 +544,20 @@ __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* 
     const int l = V.il_idx[s];
     const int rl = V.r[l];
     const int lc = V.chg[l];
-    double* M = V.arena + V.il_off[s];
+    const double* Mo = blk_old[s];
+    double* M = V.il_blk[s];
+    const int ldo = cap_old[p], ldn = V.ilcap[p];
     const int rln = lc >= 0 ? chg[lc].rnew : rl;
     // t = M (T_l)   (r x rln, ld r)
-    if (lc >= 0) wg_gemm(r, rln, rl, 1.0, M, rcp, false, chg[lc].T, rl > 0 ? rl : 1, false, 0.0, t, r > 0 ? r : 1);
-    else wg_copy(r, rl, M, rcp, t, r > 0 ? r : 1);
+    if (lc >= 0) wg_gemm(r, rln, rl, 1.0, Mo, ldo, false, chg[lc].T, rl > 0 ? rl : 1, false, 0.0, t, r > 0 ? r : 1);
+    else wg_copy(r, rl, Mo, ldo, t, r > 0 ? r : 1);
     // M = S_p t   (rn x rln)
-    wg_gemm(rn, rln, r, 1.0, C.S, rn > 0 ? rn : 1, false, t, r > 0 ? r : 1, false, 0.0, M, rcp);
-    if (r == 0) wg_fill(rn, rln, M, rcp, 0.0);
+    wg_gemm(rn, rln, r, 1.0, C.S, rn > 0 ? rn : 1, false, t, r > 0 ? r : 1, false, 0.0, M, ldn);
     const int k = find_ref(refs, C.far_begin, C.far_count, l);
     if (k >= 0) {
       const double* Dm = far[refs[k].ab].F;
       if (rn > 0) WG_FOR2(rn, rln, x, y) {
-        M[x + (int64_t)y * rcp] += Dm[x + (int64_t)y * rn];
+        M[x + (int64_t)y * ldn] += Dm[x + (int64_t)y * rn];
       }
       __syncthreads();
     }
@@ -560,15 +565,18 @@ __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* 
   for (int s = V.il_ptr[p]; s < V.il_ptr[p + 1]; ++s) {
     const int l = V.il_idx[s];
     if (V.chg[l] >= 0) continue;
-    const int rl = V.r[l], rcl = V.rc[l];
-    double* M = V.arena + il_block(V, l, p);
-    wg_gemm(rl, rn, r, 1.0, M, rcl, false, C.T, r > 0 ? r : 1, false, 0.0, t, rl > 0 ? rl : 1);
-    wg_copy(rl, rn, t, rl > 0 ? rl : 1, M, rcl);
+    const int rl = V.r[l];
+    const int s2 = il_slot(V, l, p);
+    const double* Mo = blk_old[s2];
+    double* M = V.il_blk[s2];
+    const int ldo = cap_old[l], ldn = V.ilcap[l];
+    wg_gemm(rl, rn, r, 1.0, Mo, ldo, false, C.T, r > 0 ? r : 1, false, 0.0, t, rl > 0 ? rl : 1);
+    wg_copy(rl, rn, t, rl > 0 ? rl : 1, M, ldn);
     const int k = find_ref(refs, C.far_begin, C.far_count, l);
     if (k >= 0) {
       const double* Dm = far[refs[k].ba].F;
       if (rl > 0) WG_FOR2(rl, rn, x, y) {
-        M[x + (int64_t)y * rcl] += Dm[x + (int64_t)y * rl];
+        M[x + (int64_t)y * ldn] += Dm[x + (int64_t)y * rl];
       }
       __syncthreads();
     }
@@ -581,6 +589,21 @@ __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* 
     wg_gemm(rn, K, r, 1.0, C.S, rn > 0 ? rn : 1, false, L2L, rcp, false, 0.0, t, rn > 0 ? rn : 1);
     wg_copy(rn, K, t, rn > 0 ? rn : 1, L2L, rcp);
   }
+}
+
+// Pointer-table updates of grown M2L blocks: before phase B the old table
+// keeps the old pointer; after it both tables agree again.
+struct SlotMove {
+  int32_t slot, pad;
+  double* ptr;
+};
+__global__ void k_slot_moves(double** tab, const SlotMove* mv, int count) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k < count) tab[mv[k].slot] = mv[k].ptr;
+}
+__global__ void k_set_caps(int32_t* cap, const int32_t* node_cap, int count) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k < count) cap[node_cap[2 * k]] = node_cap[2 * k + 1];
 }
 
 // Debug: flag any non-finite or huge (> 1e300) value in a buffer.
@@ -611,7 +634,7 @@ __global__ void k_top_assemble(LevelView V, int nn, const int64_t* top_off, doub
     if (rP == 0 || rQ == 0) continue;
     double* dst = T + top_off[P] + (int64_t)top_off[Q] * ldt;
     if (dist3(V.coord, P, Q) <= 1) wg_copy(rP, rQ, V.arena + near_block(V, P, Q), V.n[P], dst, ldt);
-    else wg_copy(rP, rQ, V.arena + il_block(V, P, Q), V.rc[P], dst, ldt);
+    else wg_copy(rP, rQ, V.il_blk[il_slot(V, P, Q)], V.ilcap[P], dst, ldt);
   }
 }
 

@@ -20,6 +20,7 @@ __all__ = [
     "uniform_rhs",
     "icosphere",
     "laplace_self_term",
+    "ellipsoid_area",
     "batch_geometries",
 ]
 
@@ -91,6 +92,14 @@ def uniform_rhs(n: int, nrhs: int, seed: int) -> np.ndarray:
     semantics (column k is right-hand side k)."""
     rng = np.random.default_rng(seed)
     return np.asfortranarray(rng.uniform(-1.0, 1.0, size=(n, nrhs)))
+
+
+def ellipsoid_area(axes=(1.0, 0.7, 0.3)) -> float:
+    """Surface area of an ellipsoid (Knud Thomsen's approximation, relative
+    error below 1.1 %)."""
+    a, b, c = (float(x) for x in axes)
+    p = 1.6075
+    return 4.0 * np.pi * (((a * b) ** p + (a * c) ** p + (b * c) ** p) / 3.0) ** (1.0 / p)
 
 
 def laplace_self_term(n: int, area: float = 4.0 * np.pi) -> float:

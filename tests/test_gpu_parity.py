@@ -114,3 +114,16 @@ def test_backward_error_at_eps():
         x = _gpu(pts, eps, 3, dg, 40).solve(b)
         r = np.linalg.norm(At @ x - b)
         assert r / (np.linalg.norm(At, 2) * np.linalg.norm(x) + np.linalg.norm(b)) <= 10 * eps
+
+
+def test_m2l_capacity_growth_path(monkeypatch):
+    # without headroom every rank increase reallocates the node's M2L blocks
+    monkeypatch.setenv("IFMM_IL_TIGHT", "1")
+    N, eps = 3000, 1e-6
+    pts, dg = _case("ellipsoid", N, 2)
+    b = synth.uniform_rhs(N, 2, 3)
+    h = _gpu(pts, eps, 3, dg, 32)
+    assert h.stats()["grown"] > 0
+    x = h.solve(b)
+    xo = Oracle(pts, eps=eps, sigma=3, diag=dg, leaf_max=32).factor().solve(b)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 10 * eps
