@@ -238,13 +238,17 @@ __device__ inline int sturm_count(int n, const double* d, const double* e, doubl
 // tridiagonal form (the reflectors v_k are left in A[k+1:, k], tau[k] = 1 if
 // reflector k is applied), then bisection on Sturm counts.  W holds d, e and
 // tau (3n); lam receives the eigenvalues in descending order.
+// The rank-2 update of step k and the product S v of step k + 1 share one
+// pass over the trailing matrix.
 __device__ inline void wg_syev_values(int n, double* A, int lda, double* W, double* lam) {
-  __shared__ double sv[TRD_MAXN], sw[TRD_MAXN];
+  __shared__ double sv[TRD_MAXN], sw[TRD_MAXN], sp[TRD_MAXN];  // 48 KiB
   __shared__ double s_lo, s_hi;
   double* d = W;
   double* e = W + n;
   double* tau = W + 2 * n;
   const int tid = threadIdx.x;
+  // sp holds p = S v for the current step once `have_p` is set
+  bool have_p = false;
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
     double* x = A + (k + 1) + (int64_t)k * lda;
@@ -254,6 +258,7 @@ __device__ inline void wg_syev_values(int n, double* A, int lda, double* W, doub
     const double x0 = x[0];
     if (sig == 0.0) {
       if (tid == 0) { e[k] = x0; tau[k] = 0.0; }
+      have_p = false;
       __syncthreads();
       continue;
     }
@@ -264,20 +269,99 @@ __device__ inline void wg_syev_values(int n, double* A, int lda, double* W, doub
     __syncthreads();
     if (tid == 0) { e[k] = alpha; tau[k] = 1.0; }
     for (int i = tid; i < m; i += NT) x[i] = sv[i];
-    // p = S v, S = A[k+1:, k+1:]
     double* S = A + (k + 1) + (int64_t)(k + 1) * lda;
-    double kp = 0.0;
-    for (int i = tid; i < m; i += NT) {
-      double acc = 0.0;
-      for (int j = 0; j < m; ++j) acc += S[i + (int64_t)j * lda] * sv[j];
-      sw[i] = acc;
-      kp += acc * sv[i];
+    if (!have_p) {
+      // p = S v  (four independent partial sums pipeline the loads)
+      for (int i = tid; i < m; i += NT) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int j = 0;
+        for (; j + 3 < m; j += 4) {
+          a0 += S[i + (int64_t)j * lda] * sv[j];
+          a1 += S[i + (int64_t)(j + 1) * lda] * sv[j + 1];
+          a2 += S[i + (int64_t)(j + 2) * lda] * sv[j + 2];
+          a3 += S[i + (int64_t)(j + 3) * lda] * sv[j + 3];
+        }
+        for (; j < m; ++j) a0 += S[i + (int64_t)j * lda] * sv[j];
+        sp[i] = (a0 + a1) + (a2 + a3);
+      }
+      __syncthreads();
     }
+    double kp = 0.0;
+    for (int i = tid; i < m; i += NT) kp += sp[i] * sv[i];
     const double K = wg_sum(kp);
-    for (int i = tid; i < m; i += NT) sw[i] -= K * sv[i];  // w = p - K v
+    for (int i = tid; i < m; i += NT) sw[i] = sp[i] - K * sv[i];  // w = p - K v
     __syncthreads();
-    WG_FOR2(m, m, ii, jj) S[ii + (int64_t)jj * lda] -= 2.0 * (sv[ii] * sw[jj] + sw[ii] * sv[jj]);
+    // S -= 2 (v w^T + w v^T): first the leading column (the next x), then the
+    // rest fused with the next product S' v'
+    for (int i = tid; i < m; i += NT) S[i] -= 2.0 * (sv[i] * sw[0] + sw[i] * sv[0]);
     __syncthreads();
+    const int m2 = m - 1;
+    if (k + 3 < n && m2 > 0) {
+      // next reflector from the updated column
+      double* x2 = S + 1;  // A[k+2:, k+1]
+      double part2 = 0.0;
+      for (int i = 1 + tid; i < m2; i += NT) part2 += x2[i] * x2[i];
+      const double sig2 = wg_sum(part2);
+      const double y0 = x2[0];
+      double inv2 = 0.0, v02 = 0.0;
+      if (sig2 != 0.0) {
+        const double alpha2 = -copysign(sqrt(y0 * y0 + sig2), y0);
+        v02 = y0 - alpha2;
+        inv2 = 1.0 / sqrt(sig2 + v02 * v02);
+      }
+      // sp <- v' (next reflector), kept aside in registers of the pass below
+      double* vn = sp;  // reuse: p of this step is no longer needed
+      for (int i = tid; i < m2; i += NT) vn[i] = sig2 != 0.0 ? (i == 0 ? v02 : x2[i]) * inv2 : 0.0;
+      __syncthreads();
+      // fused pass over S[1:, 1:]: update and accumulate S' v' (rows of this
+      // thread: i = tid + NT t, at most TRD_MAXN / NT of them)
+      double* S2 = S + 1 + lda;
+      double pacc[TRD_MAXN / NT];
+#pragma unroll
+      for (int t = 0; t < TRD_MAXN / NT; ++t) {
+        pacc[t] = 0.0;
+        const int i = tid + NT * t;
+        if (i >= m2) continue;
+        const double vi = sv[i + 1], wi = sw[i + 1];
+        double a0 = 0.0, a1 = 0.0;
+        int j = 0;
+        for (; j + 1 < m2; j += 2) {
+          double* c0 = S2 + i + (int64_t)j * lda;
+          double* c1 = S2 + i + (int64_t)(j + 1) * lda;
+          const double s0 = *c0 - 2.0 * (vi * sw[j + 1] + wi * sv[j + 1]);
+          const double s1 = *c1 - 2.0 * (vi * sw[j + 2] + wi * sv[j + 2]);
+          *c0 = s0;
+          *c1 = s1;
+          a0 += s0 * vn[j];
+          a1 += s1 * vn[j + 1];
+        }
+        for (; j < m2; ++j) {
+          double* c0 = S2 + i + (int64_t)j * lda;
+          const double s0 = *c0 - 2.0 * (vi * sw[j + 1] + wi * sv[j + 1]);
+          *c0 = s0;
+          a0 += s0 * vn[j];
+        }
+        pacc[t] = a0 + a1;
+      }
+      __syncthreads();
+      // the next step recomputes its v from the same column; its p is S'' v'
+      // (only when that reflector is non-trivial)
+      if (sig2 != 0.0) {
+#pragma unroll
+        for (int t = 0; t < TRD_MAXN / NT; ++t) {
+          const int i = tid + NT * t;
+          if (i < m2) sp[i] = pacc[t];
+        }
+        have_p = true;
+      } else {
+        have_p = false;
+      }
+      __syncthreads();
+    } else {
+      WG_FOR2(m, m, ii, jj) if (jj > 0) S[ii + (int64_t)jj * lda] -= 2.0 * (sv[ii] * sw[jj] + sw[ii] * sv[jj]);
+      have_p = false;
+      __syncthreads();
+    }
   }
   for (int i = tid; i < n; i += NT) d[i] = A[i + (int64_t)i * lda];
   if (tid == 0 && n >= 2) e[n - 2] = A[(n - 1) + (int64_t)(n - 2) * lda];
@@ -400,35 +484,29 @@ __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const do
     }
   }
   __syncthreads();
-  // two passes of modified Gram-Schmidt, largest eigenvalue first
+  // two passes of modified Gram-Schmidt, largest eigenvalue first; dot
+  // products one wave per vector (lanes along the rows: coalesced)
+  const int wave = tid >> 6, lane = tid & 63;
   for (int pass = 0; pass < 2; ++pass) {
     for (int j = 1; j < k; ++j) {
       double* xj = X + (int64_t)j * ldx;
-      for (int i = tid; i < j; i += NT) {
-        const double* xi = X + (int64_t)i * ldx;
-        double c = 0.0;
-        for (int r = 0; r < n; ++r) c += xi[r] * xj[r];
-        s_c[i % NT] = c;
-      }
-      __syncthreads();
-      // (j <= NT keeps s_c valid; larger j fall back to one vector at a time)
-      if (j <= NT) {
+      for (int i0 = 0; i0 < j; i0 += NT) {
+        const int cnt = min(NT, j - i0);
+        for (int i = i0 + wave; i < i0 + cnt; i += NT / 64) {
+          const double* xi = X + (int64_t)i * ldx;
+          double c = 0.0;
+          for (int r = lane; r < n; r += 64) c += xi[r] * xj[r];
+          for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+          if (lane == 0) s_c[i - i0] = c;
+        }
+        __syncthreads();
         for (int r = tid; r < n; r += NT) {
           double v = xj[r];
-          for (int i = 0; i < j; ++i) v -= s_c[i] * X[r + (int64_t)i * ldx];
+          for (int i = 0; i < cnt; ++i) v -= s_c[i] * X[r + (int64_t)(i0 + i) * ldx];
           xj[r] = v;
         }
-      } else {
-        for (int i = 0; i < j; ++i) {
-          const double* xi = X + (int64_t)i * ldx;
-          double part = 0.0;
-          for (int r = tid; r < n; r += NT) part += xi[r] * xj[r];
-          const double c = wg_sum(part);
-          for (int r = tid; r < n; r += NT) xj[r] -= c * xi[r];
-          __syncthreads();
-        }
+        __syncthreads();
       }
-      __syncthreads();
       double part = 0.0;
       for (int r = tid; r < n; r += NT) part += xj[r] * xj[r];
       const double nn = wg_sum(part);
@@ -442,26 +520,19 @@ __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const do
     if (tau[kk] == 0.0) continue;
     const int m = n - kk - 1;
     const double* v = A + (kk + 1) + (int64_t)kk * lda;
-    for (int j = tid; j < k; j += NT) {
-      const double* xj = X + (kk + 1) + (int64_t)j * ldx;
-      double c = 0.0;
-      for (int r = 0; r < m; ++r) c += v[r] * xj[r];
-      s_c[j % NT] = c;
-    }
-    __syncthreads();
-    if (k <= NT) {
-      WG_FOR2(m, k, r, j) X[(kk + 1 + r) + (int64_t)j * ldx] -= 2.0 * s_c[j] * v[r];
-    } else {
-      for (int j = 0; j < k; ++j) {
-        double* xj = X + (kk + 1) + (int64_t)j * ldx;
-        double part = 0.0;
-        for (int r = tid; r < m; r += NT) part += v[r] * xj[r];
-        const double c = wg_sum(part);
-        for (int r = tid; r < m; r += NT) xj[r] -= 2.0 * c * v[r];
-        __syncthreads();
+    for (int j0 = 0; j0 < k; j0 += NT) {
+      const int cnt = min(NT, k - j0);
+      for (int j = j0 + wave; j < j0 + cnt; j += NT / 64) {
+        const double* xj = X + (kk + 1) + (int64_t)j * ldx;
+        double c = 0.0;
+        for (int r = lane; r < m; r += 64) c += v[r] * xj[r];
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+        if (lane == 0) s_c[j - j0] = c;
       }
+      __syncthreads();
+      WG_FOR2(m, cnt, r, j) X[(kk + 1 + r) + (int64_t)(j0 + j) * ldx] -= 2.0 * s_c[j] * v[r];
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 

@@ -392,8 +392,12 @@ static int reduce_level(Handle& h, int l, std::string& err) {
   const double* G = h.weights_G[l];
   if (nn > 0) {
     hipLaunchKernelGGL(k_reduce_gram, dim3(nn), dim3(NT), 0, h.stream, V, K, G, work, d_woff);
-    hipLaunchKernelGGL(k_eig_values, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, d_tasks, h.eps * h.eps,
-                       d_cnt, h.eig_jacobi ? 1 : 0);
+    if (h.eig_jacobi)
+      hipLaunchKernelGGL(k_eig_jacobi, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, d_tasks, h.eps * h.eps,
+                         d_cnt);
+    else
+      hipLaunchKernelGGL(k_eig_values, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, d_tasks, h.eps * h.eps,
+                         d_cnt, 0);
   }
   HIPCHK(hipGetLastError());
   std::vector<int32_t> cnt(tasks.size());
@@ -554,8 +558,16 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         F.pad = 0;
         far.push_back(F);
       }
-    // schur tasks: one per neighbour row block plus the row R_z_i
-    for (int a = 0; a <= R.nnb; ++a) tasks.push_back({k, a});
+    // schur tasks: one per neighbour row block plus the row R_z_i; large
+    // nodes get one task per (row block, column block) pair
+    const bool split = (int64_t)R.n * R.M >= (int64_t)64 * 1024;
+    for (int a = 0; a <= R.nnb; ++a) {
+      if (!split) {
+        tasks.push_back({k, a, -2, 0});
+      } else {
+        for (int b = -1; b < R.nnb; ++b) tasks.push_back({k, a, b, 0});
+      }
+    }
     for (int c0 = 0; c0 < R.M + R.r; c0 += 64) xtasks.push_back({k, c0});
   }
   // scratch for far pairs
@@ -704,8 +716,12 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     }
     {
       ProfScope ps(h, "k_eig_values", fl_ev, 0);
-      hipLaunchKernelGGL(k_eig_values, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et, h.eps * h.eps,
-                         d_cnt, h.eig_jacobi ? 1 : 0);
+      if (h.eig_jacobi)
+        hipLaunchKernelGGL(k_eig_jacobi, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et, h.eps * h.eps,
+                           d_cnt);
+      else
+        hipLaunchKernelGGL(k_eig_values, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et, h.eps * h.eps,
+                           d_cnt, 0);
     }
   }
   HIPCHK(hipGetLastError());
@@ -1262,7 +1278,8 @@ extern "C" int ifmm_internal_syev(const double* A, int count, int n, int k, doub
     t[c] = {dA + c * nn, dV + c * nn, dW + c * wsz, dL + (int64_t)c * n, dI + c * (5LL * n * std::max(k, 1)), n, k};
   (void)hipMemcpy(dA, A, count * nn * 8, hipMemcpyHostToDevice);
   (void)hipMemcpy(dT, t.data(), count * sizeof(EigTask), hipMemcpyHostToDevice);
-  hipLaunchKernelGGL(k_eig_values, dim3(count), dim3(NT), 0, nullptr, dT, 0.0, dC, jacobi);
+  if (jacobi) hipLaunchKernelGGL(k_eig_jacobi, dim3(count), dim3(NT), 0, nullptr, dT, 0.0, dC);
+  else hipLaunchKernelGGL(k_eig_values, dim3(count), dim3(NT), 0, nullptr, dT, 0.0, dC, 0);
   if (!jacobi) hipLaunchKernelGGL(k_eig_vectors, dim3(count), dim3(NT), 0, nullptr, dT);
   int rc = hipDeviceSynchronize() == hipSuccess ? 0 : -3;
   (void)hipMemcpy(lam, dL, count * (int64_t)n * 8, hipMemcpyDeviceToHost);

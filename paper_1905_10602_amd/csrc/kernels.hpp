@@ -209,14 +209,35 @@ struct EigTask {
   double *A, *V, *W, *lam, *IW;  // A n x n (destroyed), V n x k, W 3n, lam n, IW 5 n k
   int32_t n, k;
 };
-__global__ void k_eig_values(const EigTask* tasks, double eps2, int32_t* cnt, int jacobi) {
+__device__ inline void eig_count(const EigTask& t, double eps2, int32_t* cnt) {
+  if (threadIdx.x == 0) {
+    const double l0 = t.lam[0];
+    int c = 0;
+    if (l0 > 0.0)
+      for (int k = 0; k < t.n; ++k)
+        if (t.lam[k] > eps2 * l0) ++c;
+    cnt[blockIdx.x] = c;
+  }
+}
+
+// cyclic Jacobi alternative (all vectors at once; W holds n x n)
+__global__ void k_eig_jacobi(const EigTask* tasks, double eps2, int32_t* cnt) {
   const EigTask t = tasks[blockIdx.x];
   if (t.n == 0) {
     if (threadIdx.x == 0) cnt[blockIdx.x] = 0;
     return;
   }
-  if (jacobi) wg_syev_jacobi(t.n, t.A, t.n, t.V, t.n, t.W, t.lam);  // all vectors; W holds n x n
-  else wg_syev_values(t.n, t.A, t.n, t.W, t.lam);
+  wg_syev_jacobi(t.n, t.A, t.n, t.V, t.n, t.W, t.lam);
+  eig_count(t, eps2, cnt);
+}
+
+__global__ void k_eig_values(const EigTask* tasks, double eps2, int32_t* cnt, int unused) {
+  const EigTask t = tasks[blockIdx.x];
+  if (t.n == 0) {
+    if (threadIdx.x == 0) cnt[blockIdx.x] = 0;
+    return;
+  }
+  wg_syev_values(t.n, t.A, t.n, t.W, t.lam);
   if (threadIdx.x == 0) {
     const double l0 = t.lam[0];
     int c = 0;
@@ -380,45 +401,51 @@ __global__ void k_xsolve(const ElimRec* recs, const XTask* xt) {
 }
 
 // Schur-complement update of one row block a of the neighbours of i (a == nnb:
-// the surviving row R_z_i of i itself).
+// the surviving row R_z_i of i itself), for one column block b (b == -1: the
+// new column C_y_i; b == -2: every column block, the small-node form).
 //   near (dist <= 1):  M[p, q] -= L_a X_top[:, q]
 //   far  (dist 2):     F_ab = -L_a X_top[:, q]          (compressed later)
 //   new blocks:        M[p, i] = L_a F,  M[i, q] = X_bot[:, q],  M[i, i] = -H
+// (with n == 0 the products are empty: far blocks become zero, near blocks
+// stay, the new block is zero)
 struct SchurTask {
-  int32_t rec, a;
+  int32_t rec, a, b, pad;
 };
-__global__ void k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs, const SchurTask* tasks,
-                        const int32_t* far_idx, const FarPair* far) {
-  const SchurTask T = tasks[blockIdx.x];
-  const ElimRec R = recs[T.rec];
+__device__ inline void schur_block(const LevelView& V, const ElimRec& R, const ElimNbr* nbrs, const int32_t* far_idx,
+                                   const FarPair* far, int a, int b) {
   const int i = R.node, n = R.n, r = R.r, d = R.d, M = R.M;
-  if (T.a < R.nnb) {
-    const ElimNbr A = nbrs[R.nb_begin + T.a];
-    const int p = A.p, np = V.n[p];
+  if (a < R.nnb) {
+    const ElimNbr A = nbrs[R.nb_begin + a];
+    const int np = V.n[A.p];
     const double* La = R.L + A.off;
-    {
-      // (with n == 0 the products are empty: far blocks become zero, near
-      // blocks stay, the new block is zero)
-      for (int b = 0; b < R.nnb; ++b) {
-        const ElimNbr B = nbrs[R.nb_begin + b];
-        const double* Xb = R.X + (int64_t)B.off * d;
-        const int fi = far_idx[R.far_base + T.a * R.nnb + b];
-        if (fi < 0) {
-          const int64_t blk = near_block(V, p, B.p);
-          wg_gemm(A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 1.0, V.arena + blk, np);
-        } else {
-          wg_gemm(A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 0.0, far[fi].F, A.m);
-        }
-      }
+    if (b >= 0) {
+      const ElimNbr B = nbrs[R.nb_begin + b];
+      const double* Xb = R.X + (int64_t)B.off * d;
+      const int fi = far_idx[R.far_base + a * R.nnb + b];
+      if (fi < 0) wg_gemm(A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 1.0, V.arena + near_block(V, A.p, B.p), np);
+      else wg_gemm(A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 0.0, far[fi].F, A.m);
+    } else {
       // new block (p, i) = L_a F   with [F; H] = D^-1 [0; I]
       wg_gemm(A.m, r, n, 1.0, La, M, false, R.X + (int64_t)M * d, d, false, 0.0, V.arena + A.blk_pi, np);
     }
   } else {
-    for (int b = 0; b < R.nnb; ++b) {
+    if (b >= 0) {
       const ElimNbr B = nbrs[R.nb_begin + b];
       wg_copy(r, B.m, R.X + n + (int64_t)B.off * d, d, V.arena + B.blk_ip, n);
+    } else {
+      wg_copy(r, r, R.X + n + (int64_t)M * d, d, V.arena + near_block(V, i, i), n, -1.0);
     }
-    wg_copy(r, r, R.X + n + (int64_t)M * d, d, V.arena + near_block(V, i, i), n, -1.0);
+  }
+}
+__global__ void k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs, const SchurTask* tasks,
+                        const int32_t* far_idx, const FarPair* far) {
+  const SchurTask T = tasks[blockIdx.x];
+  const ElimRec R = recs[T.rec];
+  if (T.b == -2) {
+    for (int b = 0; b < R.nnb; ++b) schur_block(V, R, nbrs, far_idx, far, T.a, b);
+    schur_block(V, R, nbrs, far_idx, far, T.a, -1);
+  } else {
+    schur_block(V, R, nbrs, far_idx, far, T.a, T.b);
   }
 }
 
