@@ -568,7 +568,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         for (int b = -1; b < R.nnb; ++b) tasks.push_back({k, a, b, 0});
       }
     }
-    for (int c0 = 0; c0 < R.M + R.r; c0 += 64) xtasks.push_back({k, c0});
+    if (R.d < h.big_d)
+      for (int c0 = 0; c0 < R.M + R.r; c0 += 64) xtasks.push_back({k, c0});
   }
   // scratch for far pairs
   std::vector<int64_t> fF(far.size()), fD(far.size());
@@ -639,8 +640,21 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   const size_t o_et = o_refs + al(std::max<size_t>(refs.size(), 1) * sizeof(FarRef));
   const size_t o_cnt = o_et + al(std::max<size_t>(etasks.size(), 1) * sizeof(EigTask));
   const size_t o_xt = o_cnt + al(std::max<size_t>(etasks.size(), 1) * 4);
+  // large pivots (blocked LU of the augmented matrix, many workgroups each)
+  std::vector<BluTask> blu;
+  std::vector<int32_t> blu_rec;
+  int blu_dmax = 0, blu_wmax = 0;
+  for (int k = 0; k < nrec; ++k)
+    if (recs[k].d >= h.big_d) {
+      blu.push_back({recs[k].lu, recs[k].X, recs[k].piv, nullptr, recs[k].d, recs[k].M + recs[k].r});
+      blu_rec.push_back(k);
+      blu_dmax = std::max(blu_dmax, recs[k].d);
+      blu_wmax = std::max(blu_wmax, recs[k].M + recs[k].r);
+    }
   const size_t o_info = o_xt + al(std::max<size_t>(xtasks.size(), 1) * sizeof(XTask));
-  const size_t total = o_info + al((size_t)nrec * 4);
+  const size_t o_blu = o_info + al((size_t)nrec * 4);
+  const size_t o_blur = o_blu + al(std::max<size_t>(blu.size(), 1) * sizeof(BluTask));
+  const size_t total = o_blur + al(std::max<size_t>(blu_rec.size(), 1) * 4);
   if ((rc = ensure(h, (void**)&h.meta, &h.meta_bytes, (int64_t)total, err))) return rc;
   char* M = (char*)h.meta;
   h.host_meta.assign(total, 0);
@@ -654,7 +668,14 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   if (!refs.empty()) std::memcpy(Hm + o_refs, refs.data(), refs.size() * sizeof(FarRef));
   if (!etasks.empty()) std::memcpy(Hm + o_et, etasks.data(), etasks.size() * sizeof(EigTask));
   if (!xtasks.empty()) std::memcpy(Hm + o_xt, xtasks.data(), xtasks.size() * sizeof(XTask));
+  for (size_t b = 0; b < blu.size(); ++b) blu[b].info = (int32_t*)(M + o_info) + blu_rec[b];
+  if (!blu.empty()) {
+    std::memcpy(Hm + o_blu, blu.data(), blu.size() * sizeof(BluTask));
+    std::memcpy(Hm + o_blur, blu_rec.data(), blu_rec.size() * 4);
+  }
   HIPCHK(hipMemcpyAsync(M, Hm, o_info, hipMemcpyHostToDevice, h.stream));
+  if (!blu.empty())
+    HIPCHK(hipMemcpyAsync(M + o_blu, Hm + o_blu, total - o_blu, hipMemcpyHostToDevice, h.stream));
   const ElimRec* d_recs = (const ElimRec*)(M + o_recs);
   const ElimNbr* d_nbrs = (const ElimNbr*)(M + o_nbrs);
   const SchurTask* d_tasks = (const SchurTask*)(M + o_tasks);
@@ -695,7 +716,35 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   if ((rc = check_arena(h, l, "gather", c, err))) return rc;
   {
     ProfScope ps(h, "k_getrf", fl_lu, 0);
-    hipLaunchKernelGGL(k_getrf, dim3(nrec), dim3(NT), 0, h.stream, d_recs, d_info);
+    hipLaunchKernelGGL(k_getrf, dim3(nrec), dim3(NT), 0, h.stream, d_recs, d_info, h.big_d);
+  }
+  if (!blu.empty()) {
+    const BluTask* d_blu = (const BluTask*)(M + o_blu);
+    const int32_t* d_blur = (const int32_t*)(M + o_blur);
+    const unsigned nb = (unsigned)blu.size();
+    double fl_blu = 0;
+    for (const BluTask& b : blu) fl_blu += 2.0 / 3.0 * b.d * (double)b.d * b.d + 2.0 * (double)b.d * b.d * b.W;
+    ProfScope ps(h, "k_blu", fl_blu, 0);
+    const unsigned wch = (unsigned)std::max(1, (blu_wmax + 63) / 64);
+    hipLaunchKernelGGL(k_blu_xinit, dim3(wch, nb), dim3(NT), 0, h.stream, d_blu, d_recs, d_blur);
+    const int nsteps = (blu_dmax + BLU_NB - 1) / BLU_NB;
+    for (int st = 0; st < nsteps; ++st) {
+      const int j0 = st * BLU_NB;
+      const unsigned rows = (unsigned)std::max(1, (blu_dmax - j0 - BLU_NB + 63) / 64);
+      const unsigned cols = (unsigned)((std::max(0, blu_dmax - j0 - BLU_NB) + 63) / 64 + (blu_wmax + 63) / 64 + 1);
+      const unsigned swp = (unsigned)((blu_dmax + blu_wmax + NT - 1) / NT);
+      hipLaunchKernelGGL(k_blu_panel, dim3(nb), dim3(NT), 0, h.stream, d_blu, j0);
+      hipLaunchKernelGGL(k_blu_swap, dim3(swp, nb), dim3(NT), 0, h.stream, d_blu, j0);
+      hipLaunchKernelGGL(k_blu_trsm, dim3(cols, nb), dim3(NT), 0, h.stream, d_blu, j0);
+      if (blu_dmax - j0 - BLU_NB > 0)
+        hipLaunchKernelGGL(k_blu_gemm, dim3(rows, cols, nb), dim3(NT), 0, h.stream, d_blu, j0);
+    }
+    for (int st = nsteps - 1; st >= 0; --st) {
+      const int j0 = st * BLU_NB;
+      hipLaunchKernelGGL(k_bu_trsm, dim3(wch, nb), dim3(NT), 0, h.stream, d_blu, st);
+      if (j0 > 0)
+        hipLaunchKernelGGL(k_bu_gemm, dim3((unsigned)((j0 + 63) / 64), wch, nb), dim3(NT), 0, h.stream, d_blu, st);
+    }
   }
   if (!xtasks.empty()) {
     ProfScope ps(h, "k_xsolve", fl_x, 0);
@@ -980,6 +1029,7 @@ int factor(Handle& h, std::string& err) {
   }
   h.prof = std::getenv("IFMM_PROF") != nullptr;
   h.il_tight = std::getenv("IFMM_IL_TIGHT") != nullptr;
+  if (const char* e = std::getenv("IFMM_BIG_D")) h.big_d = std::max(1, std::atoi(e));
   h.kstat.clear();
   h.stat_far = 0;
   h.stat_changed = 0;

@@ -163,6 +163,7 @@ struct Handle {
   // IFMM_PROF set: per kernel class, launches / time (hipEvents on the launch
   // stream) / algorithmic flops and bytes of the instrumented launches
   bool prof = false;
+  int big_d = 256;          // pivots of at least this order take the blocked multi-workgroup path (IFMM_BIG_D)
   bool il_tight = false;    // IFMM_IL_TIGHT set: no capacity headroom for M2L blocks (tests the growth path)
   struct KStat {
     int64_t launches = 0;

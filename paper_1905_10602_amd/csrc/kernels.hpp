@@ -372,8 +372,9 @@ __global__ void k_gather(LevelView V, const ElimRec* recs, const ElimNbr* nbrs) 
   }
 }
 
-__global__ void k_getrf(const ElimRec* recs, int32_t* info) {
+__global__ void k_getrf(const ElimRec* recs, int32_t* info, int big_d) {
   const ElimRec R = recs[blockIdx.x];
+  if (R.d >= big_d) return;  // blocked path
   const int inf = wg_getrf(R.d, R.lu, R.d, R.piv);
   if (threadIdx.x == 0) info[blockIdx.x] = inf;
 }
@@ -398,6 +399,219 @@ __global__ void k_xsolve(const ElimRec* recs, const XTask* xt) {
   }
   __syncthreads();
   wg_getrs(d, R.lu, d, R.piv, X, d, nc);
+}
+
+// ---- large pivots: right-looking blocked LU of the augmented matrix
+// [D | X0] (d x (d + W)), X0 = [[U, 0], [0, I]], pivoting over the columns of
+// D only.  The trailing updates carry L^-1 P X0 along in the X columns; a
+// blocked backward substitution with U then leaves X = D^-1 X0.  Every step
+// is one launch over all large pivots of a colour, many workgroups each, so
+// a colour with a handful of big nodes still fills the device.  Panel width
+// 64; the panel itself is factorised by one workgroup.  piv follows the
+// convention of wg_getrf, so the solve phase reads the factors unchanged.
+struct BluTask {
+  double* lu;
+  double* X;
+  int32_t* piv;
+  int32_t* info;
+  int32_t d, W;
+};
+constexpr int BLU_NB = 64;
+
+__global__ void k_blu_xinit(const BluTask* tasks, const ElimRec* recs, const int32_t* rec_of) {
+  const BluTask t = tasks[blockIdx.y];
+  const ElimRec R = recs[rec_of[blockIdx.y]];
+  const int c0 = blockIdx.x * 64;
+  const int nc = min(64, t.W - c0);
+  if (threadIdx.x == 0 && blockIdx.x == 0) *t.info = 0;
+  if (nc <= 0 || t.d == 0) return;
+  const int n = R.n, M = R.M;
+  WG_FOR2(t.d, nc, row, cl) {
+    const int col = c0 + cl;
+    double v;
+    if (col < M) v = row < n ? R.U[row + (int64_t)col * n] : 0.0;
+    else v = (row >= n && row - n == col - M) ? 1.0 : 0.0;
+    t.X[row + (int64_t)col * t.d] = v;
+  }
+}
+
+__global__ void k_blu_panel(const BluTask* tasks, int j0) {
+  const BluTask t = tasks[blockIdx.x];
+  const int d = t.d;
+  if (j0 >= d) return;
+  const int nb = min(BLU_NB, d - j0);
+  double* T = t.lu;
+  __shared__ double sv[NT];
+  __shared__ int si[NT];
+  const int tid = threadIdx.x;
+  for (int j = j0; j < j0 + nb; ++j) {
+    double best = -1.0;
+    int bi = j;  // in range even for a NaN column
+    for (int i = j + tid; i < d; i += NT) {
+      const double v = fabs(T[i + (int64_t)j * d]);
+      if (v > best) { best = v; bi = i; }
+    }
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double v2 = sv[tid + s];
+        const int i2 = si[tid + s];
+        if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
+      }
+      __syncthreads();
+    }
+    const int p = si[0];
+    const double pv = sv[0];
+    __syncthreads();
+    if (tid == 0) {
+      t.piv[j] = p;
+      if (pv == 0.0 && *t.info == 0) *t.info = j + 1;
+    }
+    if (p != j)
+      for (int c = j0 + tid; c < j0 + nb; c += NT) {
+        const double x = T[j + (int64_t)c * d];
+        T[j + (int64_t)c * d] = T[p + (int64_t)c * d];
+        T[p + (int64_t)c * d] = x;
+      }
+    __syncthreads();
+    const double dj = T[j + (int64_t)j * d];
+    if (dj != 0.0)
+      for (int i = j + 1 + tid; i < d; i += NT) T[i + (int64_t)j * d] /= dj;
+    __syncthreads();
+    const int rem = d - j - 1, w = j0 + nb - j - 1;
+    if (rem > 0 && w > 0) {
+      WG_FOR2(rem, w, ii, cc) T[j + 1 + ii + (int64_t)(j + 1 + cc) * d] -=
+          T[j + 1 + ii + (int64_t)j * d] * T[j + (int64_t)(j + 1 + cc) * d];
+    }
+    __syncthreads();
+  }
+}
+
+// columns outside the panel: c < d in lu, c >= d in X (both leading dim d)
+__device__ inline double* blu_col(const BluTask& t, int c) {
+  return c < t.d ? t.lu + (int64_t)c * t.d : t.X + (int64_t)(c - t.d) * t.d;
+}
+
+__global__ void k_blu_swap(const BluTask* tasks, int j0) {
+  const BluTask t = tasks[blockIdx.y];
+  const int d = t.d;
+  if (j0 >= d) return;
+  const int nb = min(BLU_NB, d - j0);
+  const int c = blockIdx.x * NT + threadIdx.x;
+  if (c >= d + t.W || (c >= j0 && c < j0 + nb)) return;
+  double* col = blu_col(t, c);
+  for (int j = j0; j < j0 + nb; ++j) {
+    const int p = t.piv[j];
+    if (p != j) {
+      const double x = col[j];
+      col[j] = col[p];
+      col[p] = x;
+    }
+  }
+}
+
+// column chunks right of the panel: first the lu columns j0+nb..d-1, then the
+// X columns, each split into chunks of 64 that never straddle the two
+__device__ inline int blu_chunks_lu(const BluTask& t, int j0, int nb) { return (t.d - j0 - nb + 63) / 64; }
+
+__global__ void k_blu_trsm(const BluTask* tasks, int j0) {
+  __shared__ double L[BLU_NB][BLU_NB + 1];
+  const BluTask t = tasks[blockIdx.y];
+  const int d = t.d;
+  if (j0 >= d) return;
+  const int nb = min(BLU_NB, d - j0);
+  const int clu = blu_chunks_lu(t, j0, nb);
+  const int cx = (t.W + 63) / 64;
+  const int ch = blockIdx.x;
+  if (ch >= clu + cx) return;
+  int c0, cend;
+  double* base;
+  if (ch < clu) {
+    c0 = j0 + nb + ch * 64; cend = d; base = t.lu;
+  } else {
+    c0 = (ch - clu) * 64; cend = t.W; base = t.X;
+  }
+  for (int e = threadIdx.x; e < nb * nb; e += NT) L[e % nb][e / nb] = t.lu[j0 + e % nb + (int64_t)(j0 + e / nb) * d];
+  __syncthreads();
+  const int c = c0 + (threadIdx.x & 63);
+  const int part = threadIdx.x >> 6;
+  const bool act = c < cend;
+  double* col = base + j0 + (int64_t)(act ? c : 0) * d;
+  for (int j = 0; j < nb; ++j) {
+    if (act) {
+      const double xj = col[j];
+      for (int i = j + 1 + part; i < nb; i += 4) col[i] -= L[i][j] * xj;
+    }
+    __syncthreads();
+  }
+}
+
+// trailing update A22 -= L21 U12 over the lu columns right of the panel and
+// all X columns; grid (row tiles, column chunks, task)
+__global__ void k_blu_gemm(const BluTask* tasks, int j0) {
+  const BluTask t = tasks[blockIdx.z];
+  const int d = t.d;
+  if (j0 >= d) return;
+  const int nb = min(BLU_NB, d - j0);
+  const int r0 = j0 + nb + blockIdx.x * 64;
+  if (r0 >= d) return;
+  const int clu = blu_chunks_lu(t, j0, nb);
+  const int cx = (t.W + 63) / 64;
+  const int ch = blockIdx.y;
+  if (ch >= clu + cx) return;
+  int c0, nc;
+  double* base;
+  if (ch < clu) {
+    c0 = j0 + nb + ch * 64; nc = min(64, d - c0); base = t.lu;
+  } else {
+    c0 = (ch - clu) * 64; nc = min(64, t.W - c0); base = t.X;
+  }
+  const int mr = min(64, d - r0);
+  wg_gemm(mr, nc, nb, -1.0, t.lu + r0 + (int64_t)j0 * d, d, false, base + j0 + (int64_t)c0 * d, d, false, 1.0,
+          base + r0 + (int64_t)c0 * d, d);
+}
+
+// backward substitution, block row jb: X_jb = U_jb,jb^-1 X_jb (per 64 columns)
+__global__ void k_bu_trsm(const BluTask* tasks, int jb) {
+  __shared__ double U[BLU_NB][BLU_NB + 1];
+  const BluTask t = tasks[blockIdx.y];
+  const int d = t.d, j0 = jb * BLU_NB;
+  if (j0 >= d) return;
+  const int nb = min(BLU_NB, d - j0);
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= t.W) return;
+  for (int e = threadIdx.x; e < nb * nb; e += NT) U[e % nb][e / nb] = t.lu[j0 + e % nb + (int64_t)(j0 + e / nb) * d];
+  __syncthreads();
+  const int c = c0 + (threadIdx.x & 63);
+  const int part = threadIdx.x >> 6;
+  const bool act = c < t.W;
+  double* col = t.X + j0 + (int64_t)(act ? c : 0) * d;
+  for (int j = nb - 1; j >= 0; --j) {
+    // x_j is final once rows > j have been subtracted; thread part 0 scales it
+    if (act && part == 0) col[j] = col[j] / U[j][j];
+    __syncthreads();
+    if (act) {
+      const double xj = col[j];
+      for (int i = part; i < j; i += 4) col[i] -= U[i][j] * xj;
+    }
+    __syncthreads();
+  }
+}
+
+// X[0:j0, :] -= U[0:j0, j0:j0+nb] X[j0:j0+nb, :]; grid (row tiles, column chunks, task)
+__global__ void k_bu_gemm(const BluTask* tasks, int jb) {
+  const BluTask t = tasks[blockIdx.z];
+  const int d = t.d, j0 = jb * BLU_NB;
+  if (j0 >= d) return;
+  const int nb = min(BLU_NB, d - j0);
+  const int r0 = blockIdx.x * 64;
+  const int c0 = blockIdx.y * 64;
+  if (r0 >= j0 || c0 >= t.W) return;
+  const int mr = min(64, j0 - r0), nc = min(64, t.W - c0);
+  wg_gemm(mr, nc, nb, -1.0, t.lu + r0 + (int64_t)j0 * d, d, false, t.X + j0 + (int64_t)c0 * d, d, false, 1.0,
+          t.X + r0 + (int64_t)c0 * d, d);
 }
 
 // Schur-complement update of one row block a of the neighbours of i (a == nnb:

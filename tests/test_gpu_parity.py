@@ -127,3 +127,27 @@ def test_m2l_capacity_growth_path(monkeypatch):
     x = h.solve(b)
     xo = Oracle(pts, eps=eps, sigma=3, diag=dg, leaf_max=32).factor().solve(b)
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 10 * eps
+
+
+@pytest.mark.parametrize("big_d", [1, 40, 100])
+def test_blocked_pivot_path_exact_limit(monkeypatch, big_d):
+    # every pivot of order >= big_d takes the blocked multi-workgroup LU of the
+    # augmented matrix; orders of 1..~400 cover partial panels and ragged tails
+    monkeypatch.setenv("IFMM_BIG_D", str(big_d))
+    print(f"case blocked exact big_d={big_d}", flush=True)
+    pts, dg = _case("sphere", 900, 21)
+    b = synth.uniform_rhs(900, 2, 101)
+    At = dense_tilde(pts, None, dg, leaf_max=16)
+    xd = np.linalg.solve(At, b)
+    x = _gpu(pts, 1e-14, 3, dg, 16).solve(b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
+
+
+def test_blocked_pivot_path_matches_oracle(monkeypatch):
+    monkeypatch.setenv("IFMM_BIG_D", "64")
+    N, eps = 3000, 1e-6
+    pts, dg = _case("ellipsoid", N, 2)
+    b = synth.uniform_rhs(N, 2, 3)
+    x = _gpu(pts, eps, 3, dg, 32).solve(b)
+    xo = Oracle(pts, eps=eps, sigma=3, diag=dg, leaf_max=32).factor().solve(b)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 10 * eps
