@@ -149,6 +149,59 @@ const char* ifmm_last_error(void);
 /* Releases the handle and all its device memory.  NULL is ignored. */
 void ifmm_destroy(ifmm_handle* h);
 
+/* ---- FMM matrix-vector product and the preconditioned FMBEM driver ---------
+ * Alg. 4 builds an FMM tree, precomputes the FMM operators and runs GMRES from
+ * x = 0; Alg. 5 is its preconditioner (the IFMM solve).  Sec. 4.2 allows the
+ * matrix-vector FMM to differ from the one the IFMM uses: here it is the
+ * Chebyshev FMM with its own interpolation order (5 by default) on the same
+ * uniform octree rule.  The product computed is y = A~ x, A~ the FMM
+ * representation of A (A on neighbouring leaves, interpolated elsewhere).
+ */
+typedef struct fmm_handle fmm_handle;
+
+/*
+ * Builds the FMM of A (same arguments and meaning as ifmm_build).
+ *   cheb_order  2..6 (interpolation points per axis; K = cheb_order^3)
+ *   leaf_max    >= 1, the octree depth is the smallest with <= leaf_max points per leaf
+ *   stream      hipStream_t for all device work, or NULL (a library-owned stream)
+ * Errors: IFMM_EINVAL, IFMM_ENONFINITE, IFMM_ENOMEM, IFMM_EDEVICE.
+ */
+ifmm_status fmm_build(const double* points, int64_t n, const double* weights, const double* diag,
+                      double diag_scalar, int32_t cheb_order, int32_t leaf_max, void* stream, fmm_handle** out);
+
+/* y = A~ x for one vector of length N (host or device pointers as on_device says). */
+ifmm_status fmm_matvec(fmm_handle* h, const double* x, double* y, int32_t on_device);
+
+/*
+ * Right-preconditioned flexible GMRES(restart) for A~ x = b from x = 0 (Alg. 4),
+ * classical Gram-Schmidt applied twice, stopping when the relative residual
+ * estimate falls to tol or after maxit inner iterations.
+ *   precond   a factored IFMM handle over the same N points in the same order
+ *             (Alg. 5), or NULL for no preconditioner
+ *   restart   1..1000
+ *   b, x      length N, host or device pointers (on_device); may not alias
+ *   iters     receives the number of inner iterations; relres the final
+ *             relative residual estimate
+ * Returns IFMM_ENOCONV (x and the counters still written) when tol is not met.
+ */
+ifmm_status fmm_gmres(fmm_handle* h, const double* b, ifmm_handle* precond, double tol, int32_t restart,
+                      int32_t maxit, double* x, int32_t on_device, int32_t* iters, double* relres);
+
+/* JSON: N, depth, K, M2L pairs and flops per product, products so far and their time. */
+ifmm_status fmm_stats(const fmm_handle* h, char* json, int64_t cap);
+
+void fmm_destroy(fmm_handle* h);
+
+/*
+ * The FMBEM driver in one call (Alg. 4): piecewise-constant collocation,
+ * A_ij = areas_j / (4 pi |c_i - c_j|), A_ii = self_terms_i, solved by
+ * fmm_gmres with an FMM of order fmm_cheb_order (leaf_max 64) and the given
+ * preconditioner (NULL = none).  Host arrays of length n; sol is written.
+ */
+ifmm_status fmbem_gmres(const double* centroids, const double* areas, const double* self_terms, int64_t n,
+                        const double* f, ifmm_handle* precond, int32_t fmm_cheb_order, double tol, int32_t restart,
+                        int32_t maxit, double* sol, int32_t* iters, double* relres);
+
 #ifdef __cplusplus
 }
 #endif

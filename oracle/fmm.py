@@ -55,12 +55,24 @@ class FMM:
             self.p2m.append(cheb.p2m(self.nc, c, h, self.points[ip], self.w[ip]))
             self.l2p.append(cheb.l2p(self.nc, c, h, self.points[ip]))
         self._m2m = {}
+        self._m2l = {}
 
     def m2m(self, lvl, i):
         key = tuple(int(v) & 1 for v in self.tree.levels[lvl].coords[i])
         if key not in self._m2m:
             self._m2m[key] = cheb.m2m(self.nc, _octant(self.tree.levels[lvl].coords[i]))
         return self._m2m[key]
+
+    def m2l(self, lvl, t, s):
+        """M2L of the pair; it depends only on the level and the box offset, so
+        the first pair of each (level, offset) is evaluated and reused."""
+        T = self.tree
+        key = (lvl,) + tuple(int(v) for v in (T.levels[lvl].coords[s] - T.levels[lvl].coords[t]))
+        if key not in self._m2l:
+            ct, h = T.box(lvl, t)
+            cs, _ = T.box(lvl, s)
+            self._m2l[key] = cheb.m2l(self.nc, ct, cs, h)
+        return self._m2l[key]
 
     def matvec(self, x):
         T = self.tree
@@ -83,11 +95,9 @@ class FMM:
             lev = T.levels[lvl]
             loc[lvl] = []
             for i in range(lev.n):
-                ci, h = T.box(lvl, i)
                 acc = np.zeros((K, X.shape[1]))
                 for s in lev.il[i]:
-                    cs, _ = T.box(lvl, s)
-                    acc += cheb.m2l(self.nc, ci, cs, h) @ mult[lvl][s]
+                    acc += self.m2l(lvl, i, s) @ mult[lvl][s]
                 if lvl > 2:
                     p = lev.parent[i]
                     acc += self.m2m(lvl, i).T @ loc[lvl - 1][p]

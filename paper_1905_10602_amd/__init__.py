@@ -5,4 +5,4 @@ in ``include/ifmm.h``; ``paper_1905_10602_amd.ifmm`` is a thin ctypes
 binding with the same names.  There is no CPU fallback: device calls fail
 when the library or a gfx950 device is missing.
 """
-from .ifmm import IFMM, IfmmError, load_library, library_path  # noqa: F401
+from .ifmm import FMM, IFMM, IfmmError, fmbem_gmres, load_library, library_path  # noqa: F401

@@ -36,6 +36,8 @@ def build(verbose: bool = False) -> str:
         ("capi.cpp", ["-x", "c++", "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"]),
         ("engine.hip", ["-x", "hip", "--offload-arch=gfx950", "-ffp-contract=fast",
                         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]),
+        ("fmm.hip", ["-x", "hip", "--offload-arch=gfx950", "-ffp-contract=fast",
+                     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]),
     ]
     procs = []
     for src, extra in jobs:

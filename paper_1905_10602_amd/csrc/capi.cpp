@@ -9,9 +9,14 @@
 
 #include "../../include/ifmm.h"
 #include "engine.hpp"
+#include "fmm.hpp"
 
 struct ifmm_handle {
   ifmm::Handle h;
+};
+
+struct fmm_handle {
+  ifmm::FmmHandle h;
 };
 
 namespace ifmm {
@@ -225,6 +230,134 @@ void ifmm_destroy(ifmm_handle* H) {
   if (!H) return;
   ifmm::release(H->h);
   delete H;
+}
+
+ifmm_status fmm_build(const double* points, int64_t n, const double* weights, const double* diag, double diag_scalar,
+                      int32_t cheb_order, int32_t leaf_max, void* stream, fmm_handle** out) {
+  ifmm::set_error("");
+  if (!out) return fail(IFMM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!points) return fail(IFMM_EINVAL, "points is NULL");
+  if (n < 1) return fail(IFMM_EINVAL, "n must be >= 1");
+  if (cheb_order < 2 || cheb_order > 6) return fail(IFMM_EINVAL, "cheb_order must lie in [2, 6]");
+  if (leaf_max < 1) return fail(IFMM_EINVAL, "leaf_max must be >= 1");
+  if (!diag && !std::isfinite(diag_scalar)) return fail(IFMM_ENONFINITE, "non-finite diag_scalar");
+  fmm_handle* F = new (std::nothrow) fmm_handle();
+  if (!F) return fail(IFMM_ENOMEM, "host allocation failed");
+  F->h.nc = cheb_order;
+  F->h.leaf_max = leaf_max;
+  F->h.stream = (hipStream_t)stream;
+  std::string err;
+  int rc;
+  try {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+      rc = IFMM_EDEVICE;
+      err = "no HIP device";
+    } else {
+      rc = ifmm::fmm_setup(F->h, points, n, weights, diag, diag_scalar, err);
+    }
+  } catch (const std::bad_alloc&) {
+    rc = IFMM_ENOMEM;
+    err = "host allocation failed";
+  }
+  if (rc) {
+    ifmm::fmm_release(F->h);
+    delete F;
+    return fail(rc, err);
+  }
+  *out = F;
+  return IFMM_OK;
+}
+
+// host <-> device staging for the vector calls
+struct Staged {
+  double* d = nullptr;
+  ~Staged() {
+    if (d) (void)hipFree(d);
+  }
+};
+
+ifmm_status fmm_matvec(fmm_handle* F, const double* x, double* y, int32_t on_device) {
+  ifmm::set_error("");
+  if (!F || !x || !y) return fail(IFMM_EINVAL, "bad arguments");
+  ifmm::FmmHandle& h = F->h;
+  std::string err;
+  int rc;
+  if (on_device) {
+    rc = ifmm::fmm_apply(h, x, y, err);
+  } else {
+    Staged st;
+    if (hipMalloc((void**)&st.d, (size_t)(2 * h.N) * 8) != hipSuccess) return fail(IFMM_ENOMEM, "device allocation failed");
+    if (hipMemcpy(st.d, x, (size_t)h.N * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(IFMM_EDEVICE, "copy failed");
+    rc = ifmm::fmm_apply(h, st.d, st.d + h.N, err);
+    if (!rc && hipMemcpy(y, st.d + h.N, (size_t)h.N * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(IFMM_EDEVICE, "copy failed");
+  }
+  if (rc) return fail(rc, err);
+  return IFMM_OK;
+}
+
+ifmm_status fmm_gmres(fmm_handle* F, const double* b, ifmm_handle* P, double tol, int32_t restart, int32_t maxit,
+                      double* x, int32_t on_device, int32_t* iters, double* relres) {
+  ifmm::set_error("");
+  if (!F || !b || !x || !iters || !relres) return fail(IFMM_EINVAL, "bad arguments");
+  if (restart < 1 || restart > 1000) return fail(IFMM_EINVAL, "restart must lie in [1, 1000]");
+  if (maxit < 0) return fail(IFMM_EINVAL, "maxit must be >= 0");
+  if (!(tol > 0.0)) return fail(IFMM_EINVAL, "tol must be > 0");
+  if (b == x) return fail(IFMM_EINVAL, "b and x may not alias");
+  ifmm::FmmHandle& h = F->h;
+  if (P) {
+    if (!P->h.factored) return fail(IFMM_ESTATE, "preconditioner is not factored");
+    if (P->h.N != h.N) return fail(IFMM_EINVAL, "preconditioner size differs from the FMM's");
+  }
+  std::string err;
+  int rc;
+  if (on_device) {
+    rc = ifmm::fmm_gmres(h, P ? &P->h : nullptr, b, x, tol, restart, maxit, iters, relres, err);
+  } else {
+    Staged st;
+    if (hipMalloc((void**)&st.d, (size_t)(2 * h.N) * 8) != hipSuccess) return fail(IFMM_ENOMEM, "device allocation failed");
+    if (hipMemcpy(st.d, b, (size_t)h.N * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(IFMM_EDEVICE, "copy failed");
+    rc = ifmm::fmm_gmres(h, P ? &P->h : nullptr, st.d, st.d + h.N, tol, restart, maxit, iters, relres, err);
+    if (!rc && hipMemcpy(x, st.d + h.N, (size_t)h.N * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(IFMM_EDEVICE, "copy failed");
+  }
+  if (rc) return fail(rc, err);
+  if (!(*relres <= tol)) return fail(IFMM_ENOCONV, "GMRES did not reach the tolerance");
+  return IFMM_OK;
+}
+
+ifmm_status fmm_stats(const fmm_handle* F, char* json, int64_t cap) {
+  if (!F || !json || cap < 1) return fail(IFMM_EINVAL, "bad arguments");
+  const ifmm::FmmHandle& h = F->h;
+  char buf[512];
+  std::snprintf(buf, sizeof buf,
+                "{\"N\":%lld,\"depth\":%d,\"K\":%d,\"m2l_pairs\":%lld,\"m2l_flops\":%.6e,\"matvecs\":%lld,"
+                "\"t_matvec\":%.6f}",
+                (long long)h.N, h.tree.depth, h.K, (long long)h.npairs, h.flops_m2l, (long long)h.matvecs, h.t_matvec);
+  std::snprintf(json, (size_t)cap, "%s", buf);
+  return IFMM_OK;
+}
+
+void fmm_destroy(fmm_handle* F) {
+  if (!F) return;
+  ifmm::fmm_release(F->h);
+  delete F;
+}
+
+ifmm_status fmbem_gmres(const double* centroids, const double* areas, const double* self_terms, int64_t n,
+                        const double* f, ifmm_handle* P, int32_t fmm_cheb_order, double tol, int32_t restart,
+                        int32_t maxit, double* sol, int32_t* iters, double* relres) {
+  if (!centroids || !areas || !self_terms || !f || !sol) return fail(IFMM_EINVAL, "bad arguments");
+  fmm_handle* F = nullptr;
+  ifmm_status st = fmm_build(centroids, n, areas, self_terms, 0.0, fmm_cheb_order, 64, nullptr, &F);
+  if (st != IFMM_OK) return st;
+  st = fmm_gmres(F, f, P, tol, restart, maxit, sol, 0, iters, relres);
+  const std::string msg = ifmm::get_error();
+  fmm_destroy(F);
+  if (st != IFMM_OK) ifmm::set_error(msg);
+  return st;
 }
 
 }  // extern "C"

@@ -609,7 +609,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       }
       o.T = stake((int64_t)std::max(C.r, 1) * n);
       o.S = stake(n * std::max(C.r, 1));
-      o.tmp = stake(big * std::max<int64_t>(std::max<int64_t>(L.rc[A.p], n), 1));
+      o.tmp = stake(std::max<int64_t>(big * std::max<int64_t>(std::max<int64_t>(L.rc[A.p], n), 1),
+                                      (int64_t)sides * C.r * n));
       coff.push_back(o);
       chg.push_back(C);
     }
@@ -705,7 +706,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       const FarPair& F = far[refs[C.far_begin + q].ba];
       sm += nbrs[recs[F.rec].nb_begin + F.a].m;
     }
-    fl_gram += sides * 2.0 * C.n * C.n * sm;
+    fl_gram += sides * (double)C.n * (C.n + 1) * sm;  // symmetric product: lower triangle
     fl_ev += sides * 4.0 / 3.0 * (double)C.n * C.n * C.n;
   }
   // ---- phase A
@@ -760,8 +761,12 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     hipLaunchKernelGGL(k_set_chg, dim3((nchg + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_chg, d_chg, nchg, 0);
     {
       ProfScope ps(h, "k_gram", fl_gram, 0);
-      hipLaunchKernelGGL(k_gram, dim3(sides * nchg), dim3(NT), 0, h.stream, V, d_chg, d_refs, d_far, d_nbrs, d_recs,
-                         sides);
+      int nmax = 0;
+      for (const Changed& C : chg) nmax = std::max(nmax, C.n);
+      const int nbt = (nmax + 63) / 64;
+      hipLaunchKernelGGL(k_gram_prep, dim3(sides * nchg), dim3(NT), 0, h.stream, V, d_chg, sides);
+      hipLaunchKernelGGL(k_gram, dim3((unsigned)std::max(1, nbt * (nbt + 1) / 2), sides * nchg), dim3(NT), 0,
+                         h.stream, V, d_chg, d_refs, d_far, d_nbrs, d_recs, sides);
     }
     {
       ProfScope ps(h, "k_eig_values", fl_ev, 0);
@@ -888,8 +893,70 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         fl_b += 2.0 * nil * 2.0 * (double)C.r * C.rnew * std::max(C.r, C.rnew) + 4.0 * K * C.r * C.rnew;
       }
       ProfScope ps(h, "k_phase_b", fl_b, 0);
-      hipLaunchKernelGGL(k_phase_b, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far, l > 2 ? 1 : 0,
-                         L.d_il_blk_old, L.d_ilcap_old);
+      int rmax = 0;
+      for (const Changed& C : chg) rmax = std::max(rmax, std::max(C.r, C.rnew));
+      if (rmax <= 48) {  // small blocks: one workgroup per changed node
+        hipLaunchKernelGGL(k_phase_b, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far, l > 2 ? 1 : 0,
+                           L.d_il_blk_old, L.d_ilcap_old);
+      } else {
+      // one task per transformed block, each with its own temporary; launched
+      // in chunks whose temporaries fit a bounded buffer
+      const Level& TL = h.tree.levels[l];
+      std::vector<int32_t> chg_of(TL.n, -1);
+      for (int k = 0; k < nchg; ++k) chg_of[chg[k].p] = k;
+      std::vector<PBTask> pb;
+      std::vector<int64_t> pbsz;
+      for (int k = 0; k < nchg; ++k) {
+        const Changed& C = chg[k];
+        const int p = C.p;
+        for (int s2 = TL.il_ptr[p]; s2 < TL.il_ptr[p + 1]; ++s2) {
+          const int lq = TL.il[s2];
+          const int lc = chg_of[lq];
+          const int rln = lc >= 0 ? chg[lc].rnew : L.r[lq];
+          pb.push_back({k, s2, 0, 0, nullptr});
+          pbsz.push_back((int64_t)std::max(C.r, 1) * std::max(rln, 1));
+          if (lc < 0) {
+            int lo = TL.il_ptr[lq], hi = TL.il_ptr[lq + 1] - 1, f = -1;
+            while (lo <= hi) {
+              const int mid = (lo + hi) >> 1;
+              if (TL.il[mid] == p) { f = mid; break; }
+              if (TL.il[mid] < p) lo = mid + 1; else hi = mid - 1;
+            }
+            if (f < 0) { err = "interaction lists not symmetric"; return -6; }
+            pb.push_back({k, f, 1, lq, nullptr});
+            pbsz.push_back((int64_t)std::max(L.r[lq], 1) * std::max(C.rnew, 1));
+          }
+        }
+        if (l > 2) {
+          pb.push_back({k, 0, 2, 0, nullptr});
+          pbsz.push_back((int64_t)K * std::max(C.rnew, 1) + (int64_t)std::max(C.rnew, 1) * K);
+        }
+      }
+      const int64_t budget = (int64_t)256 << 20;  // doubles (2 GiB)
+      size_t b0 = 0;
+      while (b0 < pb.size()) {
+        int64_t used = 0;
+        size_t b1 = b0;
+        while (b1 < pb.size() && (b1 == b0 || used + ((pbsz[b1] + 31) & ~31LL) <= budget)) {
+          used += (pbsz[b1] + 31) & ~31LL;
+          ++b1;
+        }
+        const int64_t tbytes = (int64_t)((b1 - b0) * sizeof(PBTask) + 255) & ~255LL;
+        if ((rc = ensure(h, (void**)&h.scratch2, &h.scratch2_bytes, used * 8 + tbytes + 256, err))) return rc;
+        double* T0 = (double*)((char*)h.scratch2 + tbytes);
+        int64_t o = 0;
+        for (size_t b = b0; b < b1; ++b) {
+          pb[b].t = T0 + o;
+          o += (pbsz[b] + 31) & ~31LL;
+        }
+        HIPCHK(hipMemcpyAsync(h.scratch2, pb.data() + b0, (b1 - b0) * sizeof(PBTask), hipMemcpyHostToDevice,
+                              h.stream));
+        hipLaunchKernelGGL(k_phase_b_blocks, dim3((unsigned)(b1 - b0)), dim3(NT), 0, h.stream, V, K, d_chg, d_refs,
+                           d_far, (const PBTask*)h.scratch2, L.d_il_blk_old, L.d_ilcap_old);
+        b0 = b1;
+        HIPCHK(hipStreamSynchronize(h.stream));  // the task table and buffer are reused / freed after this
+      }
+      }
     }
     if (!moves.empty()) {  // old tables follow the new ones again
       SlotMove* d_mv = (SlotMove*)h.meta2;

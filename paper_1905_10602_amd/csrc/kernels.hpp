@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "cheb.hpp"
 #include "dense.hpp"
 #include "engine.hpp"
 
@@ -49,22 +50,6 @@ __device__ inline int il_slot(const LevelView& V, int t, int s) {
   return -1;
 }
 
-// ------------------------------------------------------------------ Chebyshev
-// Interpolation weight S_n(xb_m, y) = 1/n + (2/n) sum_{k=1}^{n-1} T_k(xb_m) T_k(y),
-// xb_m = cos((2m + 1) pi / (2n)), m = 0..n-1.
-__device__ inline double cheb_S(int nc, int m, double y) {
-  const double xb = cos((2.0 * m + 1.0) * M_PI / (2.0 * nc));
-  double s = 1.0 / nc;
-  double tx0 = 1.0, tx1 = xb, ty0 = 1.0, ty1 = y;
-  for (int k = 1; k < nc; ++k) {
-    s += (2.0 / nc) * tx1 * ty1;
-    const double tx2 = 2.0 * xb * tx1 - tx0, ty2 = 2.0 * y * ty1 - ty0;
-    tx0 = tx1; tx1 = tx2; ty0 = ty1; ty1 = ty2;
-  }
-  return s;
-}
-
-__device__ inline double cheb_node(int nc, int m) { return cos((2.0 * m + 1.0) * M_PI / (2.0 * nc)); }
 
 // Unit-side M2L for all 343 offsets d in [-3, 3]^3: U_d[m, m'] = K(d + xb_m / 2, xb_m' / 2).
 __global__ void k_unit_m2l(int nc, double* out) {
@@ -666,44 +651,64 @@ __global__ void k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs, c
 // Gram matrices of a changed node p (side 0: source, side 1: target):
 //   Gs = P2M^T diag(sig_s^2) P2M + sum_q F_qp^T F_qp
 //   Gt = L2P diag(sig_t^2) L2P^T + sum_q F_pq F_pq^T
-__global__ void k_gram(LevelView V, const Changed* chg, const FarRef* refs, const FarPair* far,
-                       const ElimNbr* nbrs, const ElimRec* recs, int sides) {
+// Scaled bases of a changed node, one workgroup per (node, side):
+//   side 0: t0 = diag(sig_s) P2M (r x n);  side 1: t1 = L2P diag(sig_t) (n x r)
+// (the two sides use disjoint halves of the node's tmp buffer)
+__global__ void k_gram_prep(LevelView V, const Changed* chg, int sides) {
   const Changed C = chg[sides == 2 ? blockIdx.x >> 1 : blockIdx.x];
   const int side = sides == 2 ? (int)(blockIdx.x & 1) : 0;
   const int p = C.p, n = C.n, r = C.r, rc = V.rc[p];
   const double* sig = V.arena + V.sig_off[p];
-  double* G = side ? C.gt : C.gs;
-  double* t = C.tmp;
-  const ElimRec R = recs[C.rec];
+  double* t = C.tmp + (int64_t)side * r * n;
+  if (r == 0 || n == 0) return;
   if (side == 0) {
-    // t = diag(sig_s) P2M  (r x n)
     const double* P2M = V.arena + V.p2m_off[p];
-    if (r > 0) WG_FOR2(r, n, a, j) {
-      t[a + (int64_t)j * r] = sig[a] * P2M[a + (int64_t)j * rc];
-    }
-    __syncthreads();
-    wg_gemm(n, n, r, 1.0, t, r, true, t, r, false, 0.0, G, n);
-    if (r == 0) wg_fill(n, n, G, n, 0.0);
-    for (int k = 0; k < C.far_count; ++k) {
-      const FarRef F = refs[C.far_begin + k];
-      const FarPair Pq = far[F.ba];  // rows of q, columns of p
-      const int mq = nbrs[R.nb_begin + Pq.a].m;
-      wg_gemm(n, n, mq, 1.0, Pq.F, mq, true, Pq.F, mq, false, 1.0, G, n);
-    }
+    WG_FOR2(r, n, a, j) { t[a + (int64_t)j * r] = sig[a] * P2M[a + (int64_t)j * rc]; }
   } else {
     const double* L2P = V.arena + V.l2p_off[p];
-    if (n > 0) WG_FOR2(n, r, j, a) {
-      t[j + (int64_t)a * n] = L2P[j + (int64_t)a * n] * sig[rc + a];
-    }
-    __syncthreads();
-    wg_gemm(n, n, r, 1.0, t, n, false, t, n, true, 0.0, G, n);
-    if (r == 0) wg_fill(n, n, G, n, 0.0);
+    WG_FOR2(n, r, j, a) { t[j + (int64_t)a * n] = L2P[j + (int64_t)a * n] * sig[rc + a]; }
+  }
+}
+
+// Gram matrices of a changed node p (side 0: source, side 1: target):
+//   Gs = t0^T t0 + sum_q F_qp^T F_qp,   Gt = t1 t1^T + sum_q F_pq F_pq^T
+// One workgroup per 64 x 64 tile of the lower triangle (grid.x), mirrored
+// into the upper one; grid.y = (node, side).
+__global__ void k_gram(LevelView V, const Changed* chg, const FarRef* refs, const FarPair* far,
+                       const ElimNbr* nbrs, const ElimRec* recs, int sides) {
+  const Changed C = chg[sides == 2 ? blockIdx.y >> 1 : blockIdx.y];
+  const int side = sides == 2 ? (int)(blockIdx.y & 1) : 0;
+  const int n = C.n, r = C.r;
+  const int nb = (n + 63) / 64;
+  const int tile = blockIdx.x;
+  if (tile >= nb * (nb + 1) / 2) return;
+  int ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > tile) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+  const int tj = tile - ti * (ti + 1) / 2;
+  const int I = ti * 64, J = tj * 64;
+  const int mi = min(64, n - I), mj = min(64, n - J);
+  double* G = side ? C.gt : C.gs;
+  const double* t = C.tmp + (int64_t)side * r * n;
+  const ElimRec R = recs[C.rec];
+  if (side == 0) {
+    wg_gemm(mi, mj, r, 1.0, t + (int64_t)I * r, r, true, t + (int64_t)J * r, r, false, 0.0, G + I + (int64_t)J * n, n);
     for (int k = 0; k < C.far_count; ++k) {
-      const FarRef F = refs[C.far_begin + k];
-      const FarPair Pq = far[F.ab];  // rows of p, columns of q
-      const int mq = nbrs[R.nb_begin + Pq.b].m;
-      wg_gemm(n, n, mq, 1.0, Pq.F, n, false, Pq.F, n, true, 1.0, G, n);
+      const FarPair Pq = far[refs[C.far_begin + k].ba];  // rows of q, columns of p
+      const int mq = nbrs[R.nb_begin + Pq.a].m;
+      wg_gemm(mi, mj, mq, 1.0, Pq.F + (int64_t)I * mq, mq, true, Pq.F + (int64_t)J * mq, mq, false, 1.0,
+              G + I + (int64_t)J * n, n);
     }
+  } else {
+    wg_gemm(mi, mj, r, 1.0, t + I, n, false, t + J, n, true, 0.0, G + I + (int64_t)J * n, n);
+    for (int k = 0; k < C.far_count; ++k) {
+      const FarPair Pq = far[refs[C.far_begin + k].ab];  // rows of p, columns of q
+      const int mq = nbrs[R.nb_begin + Pq.b].m;
+      wg_gemm(mi, mj, mq, 1.0, Pq.F + I, n, false, Pq.F + J, n, true, 1.0, G + I + (int64_t)J * n, n);
+    }
+  }
+  if (ti != tj) {
+    WG_FOR2(mi, mj, a, b) { G[J + b + (int64_t)(I + a) * n] = G[I + a + (int64_t)(J + b) * n]; }
   }
 }
 
@@ -776,6 +781,7 @@ __device__ inline int find_ref(const FarRef* refs, int begin, int count, int q) 
 //   (l, p), l unchanged: M T_p + D_lp
 // A block whose capacity grew is read from its old storage (blk_old, ld
 // cap_old) and written to its new one (V.il_blk, ld V.ilcap).
+// k_phase_b: one workgroup per changed node (small ranks).
 __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* refs, const FarPair* far,
                           int has_parent, double* const* blk_old, const int32_t* cap_old) {
   const Changed C = chg[blockIdx.x];
@@ -823,6 +829,60 @@ __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* 
     }
   }
   if (has_parent) {
+    double* M2M = V.arena + V.m2m_off[p];
+    wg_gemm(K, rn, r, 1.0, M2M, K, false, C.T, r > 0 ? r : 1, false, 0.0, t, K);
+    wg_copy(K, rn, t, K, M2M, K);
+    double* L2L = V.arena + V.l2l_off[p];
+    wg_gemm(rn, K, r, 1.0, C.S, rn > 0 ? rn : 1, false, L2L, rcp, false, 0.0, t, rn > 0 ? rn : 1);
+    wg_copy(rn, K, t, rn > 0 ? rn : 1, L2L, rcp);
+  }
+}
+
+// One workgroup per transformed block: kind 0 = block (p, l) of changed p, kind 1 = block
+// (l, p) with l unchanged, kind 2 = M2M_p and L2L_p.  Each task brings its
+// own temporary.
+struct PBTask {
+  int32_t chg, slot, kind, pad;
+  double* t;
+};
+__global__ void k_phase_b_blocks(LevelView V, int K, const Changed* chg, const FarRef* refs, const FarPair* far,
+                                 const PBTask* tasks, double* const* blk_old, const int32_t* cap_old) {
+  const PBTask task = tasks[blockIdx.x];
+  const Changed C = chg[task.chg];
+  const int p = C.p, r = C.r, rn = C.rnew, rcp = V.rc[p];
+  double* t = task.t;
+  if (task.kind == 0) {
+    const int s = task.slot;
+    const int l = V.il_idx[s];
+    const int rl = V.r[l];
+    const int lc = V.chg[l];
+    const double* Mo = blk_old[s];
+    double* M = V.il_blk[s];
+    const int ldo = cap_old[p], ldn = V.ilcap[p];
+    const int rln = lc >= 0 ? chg[lc].rnew : rl;
+    if (lc >= 0) wg_gemm(r, rln, rl, 1.0, Mo, ldo, false, chg[lc].T, rl > 0 ? rl : 1, false, 0.0, t, r > 0 ? r : 1);
+    else wg_copy(r, rl, Mo, ldo, t, r > 0 ? r : 1);
+    wg_gemm(rn, rln, r, 1.0, C.S, rn > 0 ? rn : 1, false, t, r > 0 ? r : 1, false, 0.0, M, ldn);
+    const int k = find_ref(refs, C.far_begin, C.far_count, l);
+    if (k >= 0) {
+      const double* Dm = far[refs[k].ab].F;
+      if (rn > 0) WG_FOR2(rn, rln, x, y) { M[x + (int64_t)y * ldn] += Dm[x + (int64_t)y * rn]; }
+    }
+  } else if (task.kind == 1) {
+    const int s = task.slot;  // slot of p in I_l
+    const int ln = task.pad;  // the row node l of that slot
+    const int rl = V.r[ln];
+    const double* Mo = blk_old[s];
+    double* M = V.il_blk[s];
+    const int ldo = cap_old[ln], ldn = V.ilcap[ln];
+    wg_gemm(rl, rn, r, 1.0, Mo, ldo, false, C.T, r > 0 ? r : 1, false, 0.0, t, rl > 0 ? rl : 1);
+    wg_copy(rl, rn, t, rl > 0 ? rl : 1, M, ldn);
+    const int k = find_ref(refs, C.far_begin, C.far_count, ln);
+    if (k >= 0) {
+      const double* Dm = far[refs[k].ba].F;
+      if (rl > 0) WG_FOR2(rl, rn, x, y) { M[x + (int64_t)y * ldn] += Dm[x + (int64_t)y * rl]; }
+    }
+  } else {
     double* M2M = V.arena + V.m2m_off[p];
     wg_gemm(K, rn, r, 1.0, M2M, K, false, C.T, r > 0 ? r : 1, false, 0.0, t, K);
     wg_copy(K, rn, t, K, M2M, K);

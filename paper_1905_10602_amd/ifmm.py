@@ -58,6 +58,12 @@ def load_library():
         "ifmm_ranks": (I32, [P, I32, P]),
         "ifmm_last_error": (C.c_char_p, []),
         "ifmm_destroy": (None, [P]),
+        "fmm_build": (I32, [P, I64, P, P, D, I32, I32, P, C.POINTER(P)]),
+        "fmm_matvec": (I32, [P, P, P, I32]),
+        "fmm_gmres": (I32, [P, P, P, D, I32, I32, P, I32, C.POINTER(I32), C.POINTER(D)]),
+        "fmm_stats": (I32, [P, C.c_char_p, I64]),
+        "fmm_destroy": (None, [P]),
+        "fmbem_gmres": (I32, [P, P, P, I64, P, P, I32, D, I32, I32, P, C.POINTER(I32), C.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -193,3 +199,88 @@ class IFMM:
         r = np.empty(n, dtype=np.int32)
         _check(load_library().ifmm_ranks(self._h, lvl, _ptr(r)))
         return r
+
+
+def _is_dev(a):
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+class FMM:
+    """Handle of the Chebyshev FMM product y = A~ x (fmm_build / fmm_matvec / fmm_gmres)."""
+
+    def __init__(self, points, diag, weights=None, cheb_order=5, leaf_max=64, stream=None):
+        lib = load_library()
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        if pts.ndim != 2 or pts.shape[1] != 3:
+            raise ValueError("points must be (N, 3)")
+        self.N = pts.shape[0]
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        dvec, dsc = (None, float(diag)) if np.isscalar(diag) else (np.ascontiguousarray(diag, dtype=np.float64), 0.0)
+        h = C.c_void_p()
+        _check(lib.fmm_build(_ptr(pts), self.N, _ptr(w), _ptr(dvec), dsc, int(cheb_order), int(leaf_max),
+                             None if stream is None else C.c_void_p(stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().fmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matvec(self, x):
+        """x: numpy (N,) on the host or a contiguous torch (N,) float64 tensor on the GPU."""
+        lib = load_library()
+        if _is_dev(x):
+            import torch
+            y = torch.empty_like(x)
+            _check(lib.fmm_matvec(self._h, _ptr(x.contiguous()), _ptr(y), 1))
+            return y
+        xv = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.empty_like(xv)
+        _check(lib.fmm_matvec(self._h, _ptr(xv), _ptr(y), 0))
+        return y
+
+    def gmres(self, b, precond=None, tol=1e-8, restart=50, maxit=1000, allow_noconv=False):
+        """Returns (x, iterations, relative residual).  precond: a factored IFMM or None."""
+        lib = load_library()
+        it, rr = C.c_int32(), C.c_double()
+        ph = None if precond is None else precond._h
+        if _is_dev(b):
+            import torch
+            bc = b.contiguous()
+            x = torch.empty_like(bc)
+            code = lib.fmm_gmres(self._h, _ptr(bc), ph, float(tol), int(restart), int(maxit), _ptr(x), 1,
+                                 C.byref(it), C.byref(rr))
+        else:
+            bc = np.ascontiguousarray(b, dtype=np.float64)
+            x = np.empty_like(bc)
+            code = lib.fmm_gmres(self._h, _ptr(bc), ph, float(tol), int(restart), int(maxit), _ptr(x), 0,
+                                 C.byref(it), C.byref(rr))
+        if not (allow_noconv and code == -7):
+            _check(code)
+        return x, it.value, rr.value
+
+    def stats(self):
+        buf = C.create_string_buffer(4096)
+        _check(load_library().fmm_stats(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+
+def fmbem_gmres(centroids, areas, self_terms, f, precond=None, fmm_cheb_order=5, tol=1e-8, restart=50, maxit=1000):
+    """The one-call FMBEM driver (host arrays).  Returns (sol, iterations, relres)."""
+    lib = load_library()
+    c = np.ascontiguousarray(centroids, dtype=np.float64)
+    a = np.ascontiguousarray(areas, dtype=np.float64)
+    st = np.ascontiguousarray(self_terms, dtype=np.float64)
+    fv = np.ascontiguousarray(f, dtype=np.float64)
+    sol = np.empty_like(fv)
+    it, rr = C.c_int32(), C.c_double()
+    _check(lib.fmbem_gmres(_ptr(c), _ptr(a), _ptr(st), c.shape[0], _ptr(fv), None if precond is None else precond._h,
+                           int(fmm_cheb_order), float(tol), int(restart), int(maxit), _ptr(sol), C.byref(it),
+                           C.byref(rr)))
+    return sol, it.value, rr.value

@@ -22,13 +22,14 @@ def _lib():
 def declared_functions():
     text = open(os.path.join(ROOT, "include", "ifmm.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ifmm_\w+|fmbem_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(ifmm_\w+|fmbem_\w+|fmm_\w+)\s*\(", text)))
 
 
 def test_exports_every_declared_symbol():
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1905_10602_amd", "libifmm.so"))
     names = declared_functions()
     assert "ifmm_build" in names and "ifmm_solve" in names
+    assert "fmbem_gmres" in names and "fmm_gmres" in names and "fmm_matvec" in names
     for name in names:
         assert hasattr(lib, name), name
 
@@ -90,3 +91,20 @@ def test_no_cpu_fallback_without_device():
     with pytest.raises(IfmmError) as e:
         h.factor()
     assert e.value.status == "IFMM_EDEVICE"
+
+
+def test_fmm_rejects_bad_arguments_and_needs_a_device():
+    import torch
+    from paper_1905_10602_amd import FMM, IfmmError
+    pts = synth.sphere_points(100, 1)
+    for kw in ({"cheb_order": 9}, {"cheb_order": 1}, {"leaf_max": 0}):
+        with pytest.raises(IfmmError) as e:
+            FMM(pts, 1.0, **kw)
+        assert e.value.status == "IFMM_EINVAL"
+    with pytest.raises(IfmmError) as e:
+        FMM(np.zeros((0, 3)), 1.0)
+    assert e.value.status == "IFMM_EINVAL"
+    if not torch.cuda.is_available():
+        with pytest.raises(IfmmError) as e:
+            FMM(pts, 1.0)
+        assert e.value.status == "IFMM_EDEVICE"
