@@ -56,6 +56,15 @@ typedef enum {
 
 typedef enum { IFMM_KERNEL_LAPLACE3D = 0 } ifmm_kernel;
 
+/*
+ * IFMM_PREC_FP64: every step in FP64.
+ * IFMM_PREC_MIXED: the Schur-complement products of the elimination and the
+ * basis-change products of phase B run on FP32 matrix cores (operands
+ * rounded to FP32, FP32 accumulation, results combined in FP64); the pivot
+ * LU and its triangular solves, the recompression (Gram matrices and their
+ * eigen-decomposition, which must resolve eps^2 relative to the largest
+ * eigenvalue), the top-level LU and the solve stay FP64.
+ */
 typedef enum { IFMM_PREC_FP64 = 0, IFMM_PREC_MIXED = 1 } ifmm_precision;
 
 typedef struct {

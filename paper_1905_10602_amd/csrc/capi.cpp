@@ -80,7 +80,7 @@ ifmm_status ifmm_build(const double* points, int64_t n, const double* weights, c
   if (opt) o = *opt;
   if (o.leaf_max < 1) return fail(IFMM_EINVAL, "leaf_max must be >= 1");
   if (o.cheb_order < 2 || o.cheb_order > 6) return fail(IFMM_EINVAL, "cheb_order must lie in [2, 6]");
-  if (o.precision != IFMM_PREC_FP64) return fail(IFMM_EINVAL, "precision mode not available in this build");
+  if (o.precision != IFMM_PREC_FP64 && o.precision != IFMM_PREC_MIXED) return fail(IFMM_EINVAL, "unknown precision mode");
   if (o.rank_cap < 0) return fail(IFMM_EINVAL, "rank_cap must be >= 0");
   ifmm_handle* H = new (std::nothrow) ifmm_handle();
   if (!H) return fail(IFMM_ENOMEM, "host allocation failed");

@@ -89,6 +89,72 @@ __device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* 
   __syncthreads();
 }
 
+// The same product with FP32 matrix cores: operands rounded to FP32 on their
+// way into LDS, FP32 accumulation (v_mfma_f32_32x32x2f32), the result
+// combined with C in FP64.  Each of the four waves owns a 32 x 32 quadrant of
+// the 64 x 64 output tile.  Operand lane layout of the 32x32x2 instruction:
+// lane l holds A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator register
+// v of lane l holds D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+__device__ inline void wg_gemm_f32(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
+                                   const double* B, int ldb, bool tB, double beta, double* C, int ldc) {
+  __shared__ float fA[16][68];
+  __shared__ float fB[16][68];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  for (int i0 = 0; i0 < m; i0 += 64) {
+    for (int j0 = 0; j0 < n; j0 += 64) {
+      f32x16 acc;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+      for (int k0 = 0; k0 < k; k0 += 16) {
+        for (int e = tid; e < 1024; e += NT) {
+          int ii, kk;
+          if (!tA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
+          const int gi = i0 + ii, gk = k0 + kk;
+          double v = 0.0;
+          if (gi < m && gk < k) v = tA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
+          fA[kk][ii] = (float)v;
+        }
+        for (int e = tid; e < 1024; e += NT) {
+          int kk, jj;
+          if (!tB) { kk = e & 15; jj = e >> 4; } else { jj = e & 63; kk = e >> 6; }
+          const int gk = k0 + kk, gj = j0 + jj;
+          double v = 0.0;
+          if (gk < k && gj < n) v = tB ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb];
+          fB[kk][jj] = (float)v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 2) {
+          const float a = fA[kk + (lane >> 5)][wr + (lane & 31)];
+          const float b = fB[kk + (lane >> 5)][wc + (lane & 31)];
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int gi = i0 + wr + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int gj = j0 + wc + (lane & 31);
+        if (gi < m && gj < n) {
+          double* c = C + gi + (int64_t)gj * ldc;
+          *c = (beta == 0.0) ? alpha * (double)acc[v] : fma(alpha, (double)acc[v], beta * (*c));
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// precision switch of the Schur-complement and basis-change products
+__device__ inline void wg_gemm_p(bool f32, int m, int n, int k, double alpha, const double* A, int lda, bool tA,
+                                 const double* B, int ldb, bool tB, double beta, double* C, int ldc) {
+  if (f32) wg_gemm_f32(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc);
+  else wg_gemm(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc);
+}
+
 // dst(m x n) = alpha * src
 __device__ inline void wg_copy(int m, int n, const double* src, int lds, double* dst, int ldd, double alpha = 1.0) {
   if (m > 0) {

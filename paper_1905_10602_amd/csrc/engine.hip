@@ -754,7 +754,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   {
     ProfScope ps(h, "k_schur", fl_schur, 0);
     hipLaunchKernelGGL(k_schur, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks, d_fidx,
-                       d_far);
+                       d_far, h.precision == 1 ? 1 : 0);
   }
   if ((rc = check_arena(h, l, "schur", c, err))) return rc;
   if (nchg) {
@@ -897,7 +897,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       for (const Changed& C : chg) rmax = std::max(rmax, std::max(C.r, C.rnew));
       if (rmax <= 48) {  // small blocks: one workgroup per changed node
         hipLaunchKernelGGL(k_phase_b, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far, l > 2 ? 1 : 0,
-                           L.d_il_blk_old, L.d_ilcap_old);
+                           L.d_il_blk_old, L.d_ilcap_old, h.precision == 1 ? 1 : 0);
       } else {
       // one task per transformed block, each with its own temporary; launched
       // in chunks whose temporaries fit a bounded buffer
@@ -952,7 +952,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         HIPCHK(hipMemcpyAsync(h.scratch2, pb.data() + b0, (b1 - b0) * sizeof(PBTask), hipMemcpyHostToDevice,
                               h.stream));
         hipLaunchKernelGGL(k_phase_b_blocks, dim3((unsigned)(b1 - b0)), dim3(NT), 0, h.stream, V, K, d_chg, d_refs,
-                           d_far, (const PBTask*)h.scratch2, L.d_il_blk_old, L.d_ilcap_old);
+                           d_far, (const PBTask*)h.scratch2, L.d_il_blk_old, L.d_ilcap_old,
+                           h.precision == 1 ? 1 : 0);
         b0 = b1;
         HIPCHK(hipStreamSynchronize(h.stream));  // the task table and buffer are reused / freed after this
       }
@@ -1404,5 +1405,41 @@ extern "C" int ifmm_internal_syev(const double* A, int count, int n, int k, doub
     (void)hipMemcpy(V + c * (int64_t)n * k, dV + c * nn, (int64_t)n * k * 8, hipMemcpyDeviceToHost);
   (void)hipFree(dA); (void)hipFree(dV); (void)hipFree(dW); (void)hipFree(dL); (void)hipFree(dI);
   (void)hipFree(dT); (void)hipFree(dC);
+  return rc;
+}
+
+namespace ifmm {
+__global__ void k_internal_gemm(int m, int n, int k, double alpha, const double* A, int lda, int tA, const double* B,
+                                int ldb, int tB, double beta, double* C, int ldc, int f32) {
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int mm = min(64, m - i0), nn = min(64, n - j0);
+  if (mm <= 0 || nn <= 0) return;
+  const double* Ab = tA ? A + (int64_t)i0 * lda : A + i0;
+  const double* Bb = tB ? B + j0 : B + (int64_t)j0 * ldb;
+  wg_gemm_p(f32 != 0, mm, nn, k, alpha, Ab, lda, tA != 0, Bb, ldb, tB != 0, beta, C + i0 + (int64_t)j0 * ldc, ldc);
+}
+}  // namespace ifmm
+
+// Test hook (not part of the declared ABI): C = alpha op(A) op(B) + beta C on
+// host arrays (column-major, tight leading dimensions) with the FP64 (f32 = 0)
+// or FP32 matrix-core (f32 = 1) workgroup product, one workgroup per 64 x 64 tile.
+extern "C" int ifmm_internal_gemm(int m, int n, int k, double alpha, const double* A, int tA, const double* B, int tB,
+                                  double beta, double* C, int f32) {
+  using namespace ifmm;
+  if (m < 1 || n < 1 || k < 0) return -1;
+  const int lda = tA ? std::max(k, 1) : m, ldb = tB ? n : std::max(k, 1);
+  const int64_t sa = (int64_t)m * k, sb = (int64_t)k * n, sc = (int64_t)m * n;
+  double *dA = nullptr, *dB = nullptr, *dC = nullptr;
+  if (hipMalloc((void**)&dA, std::max<int64_t>(sa, 1) * 8) != hipSuccess) return -3;
+  if (hipMalloc((void**)&dB, std::max<int64_t>(sb, 1) * 8) != hipSuccess) return -3;
+  if (hipMalloc((void**)&dC, sc * 8) != hipSuccess) return -3;
+  if (sa) (void)hipMemcpy(dA, A, sa * 8, hipMemcpyHostToDevice);
+  if (sb) (void)hipMemcpy(dB, B, sb * 8, hipMemcpyHostToDevice);
+  (void)hipMemcpy(dC, C, sc * 8, hipMemcpyHostToDevice);
+  hipLaunchKernelGGL(k_internal_gemm, dim3((m + 63) / 64, (n + 63) / 64), dim3(NT), 0, nullptr, m, n, k, alpha, dA, lda,
+                     tA, dB, ldb, tB, beta, dC, m, f32);
+  int rc = hipDeviceSynchronize() == hipSuccess ? 0 : -3;
+  (void)hipMemcpy(C, dC, sc * 8, hipMemcpyDeviceToHost);
+  (void)hipFree(dA); (void)hipFree(dB); (void)hipFree(dC);
   return rc;
 }

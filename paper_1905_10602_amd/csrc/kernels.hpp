@@ -611,7 +611,7 @@ struct SchurTask {
   int32_t rec, a, b, pad;
 };
 __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const ElimNbr* nbrs, const int32_t* far_idx,
-                                   const FarPair* far, int a, int b) {
+                                   const FarPair* far, int a, int b, bool f32) {
   const int i = R.node, n = R.n, r = R.r, d = R.d, M = R.M;
   if (a < R.nnb) {
     const ElimNbr A = nbrs[R.nb_begin + a];
@@ -621,11 +621,12 @@ __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const E
       const ElimNbr B = nbrs[R.nb_begin + b];
       const double* Xb = R.X + (int64_t)B.off * d;
       const int fi = far_idx[R.far_base + a * R.nnb + b];
-      if (fi < 0) wg_gemm(A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 1.0, V.arena + near_block(V, A.p, B.p), np);
-      else wg_gemm(A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 0.0, far[fi].F, A.m);
+      if (fi < 0)
+        wg_gemm_p(f32, A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 1.0, V.arena + near_block(V, A.p, B.p), np);
+      else wg_gemm_p(f32, A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 0.0, far[fi].F, A.m);
     } else {
       // new block (p, i) = L_a F   with [F; H] = D^-1 [0; I]
-      wg_gemm(A.m, r, n, 1.0, La, M, false, R.X + (int64_t)M * d, d, false, 0.0, V.arena + A.blk_pi, np);
+      wg_gemm_p(f32, A.m, r, n, 1.0, La, M, false, R.X + (int64_t)M * d, d, false, 0.0, V.arena + A.blk_pi, np);
     }
   } else {
     if (b >= 0) {
@@ -637,14 +638,14 @@ __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const E
   }
 }
 __global__ void k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs, const SchurTask* tasks,
-                        const int32_t* far_idx, const FarPair* far) {
+                        const int32_t* far_idx, const FarPair* far, int f32) {
   const SchurTask T = tasks[blockIdx.x];
   const ElimRec R = recs[T.rec];
   if (T.b == -2) {
-    for (int b = 0; b < R.nnb; ++b) schur_block(V, R, nbrs, far_idx, far, T.a, b);
-    schur_block(V, R, nbrs, far_idx, far, T.a, -1);
+    for (int b = 0; b < R.nnb; ++b) schur_block(V, R, nbrs, far_idx, far, T.a, b, f32);
+    schur_block(V, R, nbrs, far_idx, far, T.a, -1, f32);
   } else {
-    schur_block(V, R, nbrs, far_idx, far, T.a, T.b);
+    schur_block(V, R, nbrs, far_idx, far, T.a, T.b, f32);
   }
 }
 
@@ -783,7 +784,7 @@ __device__ inline int find_ref(const FarRef* refs, int begin, int count, int q) 
 // cap_old) and written to its new one (V.il_blk, ld V.ilcap).
 // k_phase_b: one workgroup per changed node (small ranks).
 __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* refs, const FarPair* far,
-                          int has_parent, double* const* blk_old, const int32_t* cap_old) {
+                          int has_parent, double* const* blk_old, const int32_t* cap_old, int f32) {
   const Changed C = chg[blockIdx.x];
   const int p = C.p, r = C.r, rn = C.rnew, rcp = V.rc[p];
   double* t = C.tmp;
@@ -796,10 +797,10 @@ __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* 
     const int ldo = cap_old[p], ldn = V.ilcap[p];
     const int rln = lc >= 0 ? chg[lc].rnew : rl;
     // t = M (T_l)   (r x rln, ld r)
-    if (lc >= 0) wg_gemm(r, rln, rl, 1.0, Mo, ldo, false, chg[lc].T, rl > 0 ? rl : 1, false, 0.0, t, r > 0 ? r : 1);
+    if (lc >= 0) wg_gemm_p(f32, r, rln, rl, 1.0, Mo, ldo, false, chg[lc].T, rl > 0 ? rl : 1, false, 0.0, t, r > 0 ? r : 1);
     else wg_copy(r, rl, Mo, ldo, t, r > 0 ? r : 1);
     // M = S_p t   (rn x rln)
-    wg_gemm(rn, rln, r, 1.0, C.S, rn > 0 ? rn : 1, false, t, r > 0 ? r : 1, false, 0.0, M, ldn);
+    wg_gemm_p(f32, rn, rln, r, 1.0, C.S, rn > 0 ? rn : 1, false, t, r > 0 ? r : 1, false, 0.0, M, ldn);
     const int k = find_ref(refs, C.far_begin, C.far_count, l);
     if (k >= 0) {
       const double* Dm = far[refs[k].ab].F;
@@ -817,7 +818,7 @@ __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* 
     const double* Mo = blk_old[s2];
     double* M = V.il_blk[s2];
     const int ldo = cap_old[l], ldn = V.ilcap[l];
-    wg_gemm(rl, rn, r, 1.0, Mo, ldo, false, C.T, r > 0 ? r : 1, false, 0.0, t, rl > 0 ? rl : 1);
+    wg_gemm_p(f32, rl, rn, r, 1.0, Mo, ldo, false, C.T, r > 0 ? r : 1, false, 0.0, t, rl > 0 ? rl : 1);
     wg_copy(rl, rn, t, rl > 0 ? rl : 1, M, ldn);
     const int k = find_ref(refs, C.far_begin, C.far_count, l);
     if (k >= 0) {
@@ -830,10 +831,10 @@ __global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* 
   }
   if (has_parent) {
     double* M2M = V.arena + V.m2m_off[p];
-    wg_gemm(K, rn, r, 1.0, M2M, K, false, C.T, r > 0 ? r : 1, false, 0.0, t, K);
+    wg_gemm_p(f32, K, rn, r, 1.0, M2M, K, false, C.T, r > 0 ? r : 1, false, 0.0, t, K);
     wg_copy(K, rn, t, K, M2M, K);
     double* L2L = V.arena + V.l2l_off[p];
-    wg_gemm(rn, K, r, 1.0, C.S, rn > 0 ? rn : 1, false, L2L, rcp, false, 0.0, t, rn > 0 ? rn : 1);
+    wg_gemm_p(f32, rn, K, r, 1.0, C.S, rn > 0 ? rn : 1, false, L2L, rcp, false, 0.0, t, rn > 0 ? rn : 1);
     wg_copy(rn, K, t, rn > 0 ? rn : 1, L2L, rcp);
   }
 }
@@ -846,7 +847,7 @@ struct PBTask {
   double* t;
 };
 __global__ void k_phase_b_blocks(LevelView V, int K, const Changed* chg, const FarRef* refs, const FarPair* far,
-                                 const PBTask* tasks, double* const* blk_old, const int32_t* cap_old) {
+                                 const PBTask* tasks, double* const* blk_old, const int32_t* cap_old, int f32) {
   const PBTask task = tasks[blockIdx.x];
   const Changed C = chg[task.chg];
   const int p = C.p, r = C.r, rn = C.rnew, rcp = V.rc[p];
@@ -860,9 +861,9 @@ __global__ void k_phase_b_blocks(LevelView V, int K, const Changed* chg, const F
     double* M = V.il_blk[s];
     const int ldo = cap_old[p], ldn = V.ilcap[p];
     const int rln = lc >= 0 ? chg[lc].rnew : rl;
-    if (lc >= 0) wg_gemm(r, rln, rl, 1.0, Mo, ldo, false, chg[lc].T, rl > 0 ? rl : 1, false, 0.0, t, r > 0 ? r : 1);
+    if (lc >= 0) wg_gemm_p(f32, r, rln, rl, 1.0, Mo, ldo, false, chg[lc].T, rl > 0 ? rl : 1, false, 0.0, t, r > 0 ? r : 1);
     else wg_copy(r, rl, Mo, ldo, t, r > 0 ? r : 1);
-    wg_gemm(rn, rln, r, 1.0, C.S, rn > 0 ? rn : 1, false, t, r > 0 ? r : 1, false, 0.0, M, ldn);
+    wg_gemm_p(f32, rn, rln, r, 1.0, C.S, rn > 0 ? rn : 1, false, t, r > 0 ? r : 1, false, 0.0, M, ldn);
     const int k = find_ref(refs, C.far_begin, C.far_count, l);
     if (k >= 0) {
       const double* Dm = far[refs[k].ab].F;
@@ -875,7 +876,7 @@ __global__ void k_phase_b_blocks(LevelView V, int K, const Changed* chg, const F
     const double* Mo = blk_old[s];
     double* M = V.il_blk[s];
     const int ldo = cap_old[ln], ldn = V.ilcap[ln];
-    wg_gemm(rl, rn, r, 1.0, Mo, ldo, false, C.T, r > 0 ? r : 1, false, 0.0, t, rl > 0 ? rl : 1);
+    wg_gemm_p(f32, rl, rn, r, 1.0, Mo, ldo, false, C.T, r > 0 ? r : 1, false, 0.0, t, rl > 0 ? rl : 1);
     wg_copy(rl, rn, t, rl > 0 ? rl : 1, M, ldn);
     const int k = find_ref(refs, C.far_begin, C.far_count, ln);
     if (k >= 0) {
@@ -884,10 +885,10 @@ __global__ void k_phase_b_blocks(LevelView V, int K, const Changed* chg, const F
     }
   } else {
     double* M2M = V.arena + V.m2m_off[p];
-    wg_gemm(K, rn, r, 1.0, M2M, K, false, C.T, r > 0 ? r : 1, false, 0.0, t, K);
+    wg_gemm_p(f32, K, rn, r, 1.0, M2M, K, false, C.T, r > 0 ? r : 1, false, 0.0, t, K);
     wg_copy(K, rn, t, K, M2M, K);
     double* L2L = V.arena + V.l2l_off[p];
-    wg_gemm(rn, K, r, 1.0, C.S, rn > 0 ? rn : 1, false, L2L, rcp, false, 0.0, t, rn > 0 ? rn : 1);
+    wg_gemm_p(f32, rn, K, r, 1.0, C.S, rn > 0 ? rn : 1, false, L2L, rcp, false, 0.0, t, rn > 0 ? rn : 1);
     wg_copy(rn, K, t, rn > 0 ? rn : 1, L2L, rcp);
   }
 }

@@ -91,7 +91,7 @@ class IFMM:
     """Handle of one factorisation (ifmm_build / ifmm_factor / ifmm_solve)."""
 
     def __init__(self, points, eps, sigma, diag=None, weights=None, leaf_max=64, cheb_order=4, rank_cap=0,
-                 max_device_bytes=0, stream=None):
+                 max_device_bytes=0, stream=None, precision="fp64"):
         lib = load_library()
         pts = np.ascontiguousarray(points, dtype=np.float64)
         if pts.ndim != 2 or pts.shape[1] != 3:
@@ -110,6 +110,7 @@ class IFMM:
         opt.leaf_max = leaf_max
         opt.cheb_order = cheb_order
         opt.rank_cap = rank_cap
+        opt.precision = {"fp64": 0, "mixed": 1}[precision]
         opt.max_device_bytes = max_device_bytes
         opt.stream = None if stream is None else C.c_void_p(stream)
         h = C.c_void_p()

@@ -99,3 +99,31 @@ def test_syev_on_ifmm_gram_matrices():
             err = np.linalg.norm(Xk @ Xk.T - Q @ Q.T)
             worst = max(worst, err)
             assert err < 1e-6, (n, kk, err)
+
+
+@pytest.mark.parametrize("m,n,k,tA,tB", [(64, 64, 64, 0, 0), (130, 70, 33, 0, 0), (5, 200, 300, 1, 0),
+                                         (77, 9, 1, 0, 1), (100, 100, 0, 1, 1)])
+@pytest.mark.parametrize("f32", [0, 1])
+def test_workgroup_gemm_fp64_and_fp32_matrix_cores(m, n, k, tA, tB, f32):
+    lib = C.CDLL(os.path.join(ROOT, "paper_1905_10602_amd", "libifmm.so"))
+    f = lib.ifmm_internal_gemm
+    f.restype = C.c_int
+    f.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_double,
+                  C.c_void_p, C.c_int]
+    rng = np.random.default_rng(m + n + k)
+    A = rng.standard_normal((k, m) if tA else (m, k))
+    B = rng.standard_normal((n, k) if tB else (k, n))
+    Cm = rng.standard_normal((m, n))
+    Af, Bf, Cf = np.asfortranarray(A), np.asfortranarray(B), np.asfortranarray(Cm.copy())
+    assert f(m, n, k, -1.5, Af.ctypes.data, tA, Bf.ctypes.data, tB, 0.5, Cf.ctypes.data, f32) == 0
+    opA = A.T if tA else A
+    opB = B.T if tB else B
+    ref = -1.5 * opA @ opB + 0.5 * Cm
+    if f32:
+        # operands rounded to FP32 and FP32 accumulation: |error| <= c k u32 |A||B|
+        bound = 1.5 * (k + 2) * 2.0 ** -23 * (np.abs(opA) @ np.abs(opB)) + 1e-300
+        assert np.all(np.abs(Cf - ref) <= bound)
+        if k > 1:
+            assert not np.allclose(Cf, ref, rtol=0, atol=1e-12)  # really FP32
+    else:
+        assert np.allclose(Cf, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())

@@ -151,3 +151,24 @@ def test_blocked_pivot_path_matches_oracle(monkeypatch):
     x = _gpu(pts, eps, 3, dg, 32).solve(b)
     xo = Oracle(pts, eps=eps, sigma=3, diag=dg, leaf_max=32).factor().solve(b)
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 10 * eps
+
+
+@pytest.mark.parametrize("shape,N,leaf,sigma,eps", [("sphere", 4096, 64, 6, 1e-6), ("ellipsoid", 3000, 32, 3, 1e-6),
+                                                    ("sphere", 1500, 24, 3, 1e-4)])
+def test_mixed_precision_error_vs_oracle(shape, N, leaf, sigma, eps):
+    # FP32 matrix cores for the Schur and basis-change products: the solution
+    # stays within 100 eps of the FP64 oracle (FP32 rounding, 6e-8, enters the
+    # updated blocks at about the level of the truncation itself) and its
+    # backward error on A~ within 100 eps
+    print(f"case mixed {shape} N={N} eps={eps}", flush=True)
+    pts, dg = _case(shape, N, 1)
+    b = synth.uniform_rhs(N, 2, 101)
+    xo = Oracle(pts, eps=eps, sigma=sigma, diag=dg, leaf_max=leaf).factor().solve(b)
+    h = _gpu(pts, eps, sigma, dg, leaf, precision="mixed")
+    x = h.solve(b)
+    rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    x64 = _gpu(pts, eps, sigma, dg, leaf).solve(b)
+    rel64 = np.linalg.norm(x64 - xo) / np.linalg.norm(xo)
+    print(f"mixed error vs oracle {rel:.3e} (fp64 {rel64:.3e})", flush=True)
+    assert rel <= 100 * eps
+    assert not np.array_equal(x, x64)  # the FP32 path really ran
