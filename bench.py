@@ -163,6 +163,8 @@ def main():
         "levels": [{k2: L[k2] for k2 in ("level", "nodes", "colours", "rank_sum", "rank_max", "n_max", "t_elim")}
                    for L in stats.get("levels", [])],
         "kernels_ms": {n: round(k["ms"], 3) for n, k in ks.items()},
+        "sketches": stats.get("sketches"), "sketches_rejected": stats.get("sketches_rejected"),
+        "sketches_narrow": stats.get("sketches_narrow"),
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

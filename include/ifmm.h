@@ -158,6 +158,55 @@ const char* ifmm_last_error(void);
 /* Releases the handle and all its device memory.  NULL is ignored. */
 void ifmm_destroy(ifmm_handle* h);
 
+/* ---- learned recompression rank ---------------------------------------------
+ * Sec. 5.1 compresses the fill-in with a randomised SVD, whose width has to
+ * be chosen.  Here every recompression whose Gram matrix has order >= 128
+ * first tries a sketch (randomised range finder of the stacked factor,
+ * Rayleigh-Ritz on the Gram matrix) of width s = predicted rank +
+ * oversampling; it is accepted only when the eigen-mass outside the sketch,
+ * trace(G) - trace(Q^T G Q), is at most eps^2 lambda_1 and fewer than s Ritz
+ * values pass the truncation rule, otherwise the full eigen-decomposition
+ * runs (fall-back and judge).  Without a model the predicted rank is the
+ * node's current rank; with one it is a small network's estimate.
+ *
+ * The network: IFMM_RANK_FEATURES inputs (level / 8, log10(box half-side) / 4,
+ * log2(1 + points in the box) / 20, |interaction list| / 189, n / 1024,
+ * current rank / 512, log10(s_1) / 8 and log10(s_i / s_1) / 16 for i = 2..8,
+ * s_i the singular values of an 8-column range sample of the source-side
+ * stacked factor), two hidden layers of 64 ReLU units, one output (the rank
+ * as a fraction of n), FP32.  Parameters, flat: W1 (64 x F row-major), b1
+ * (64), W2 (64 x 64 row-major), b2 (64), w3 (64), b3 (1).  Training minimises
+ * the pinball loss at quantile tau (an upper quantile keeps fall-backs rare)
+ * with full-batch Adam, on the device.
+ */
+#define IFMM_RANK_FEATURES 14
+
+/* Number of parameters of the network for nfeat inputs (-1 if nfeat < 1). */
+int64_t ifmm_rank_model_params(int32_t nfeat);
+
+/* y[i] = network(theta, X[i, :]) for m samples (X row-major m x nfeat; host arrays). */
+ifmm_status ifmm_rank_model_eval(const float* theta, int32_t nfeat, const float* X, int64_t m, float* y);
+
+/* Mean pinball loss (quantile tau) of the targets t and its gradient (host arrays). */
+ifmm_status ifmm_rank_model_grad(const float* theta, int32_t nfeat, const float* X, const float* t, int64_t m,
+                                 float tau, double* loss, float* grad);
+
+/*
+ * steps of full-batch Adam (lr; beta 0.9 / 0.999, 1e-8) from theta, updated in
+ * place; loss_hist[k] receives the loss before step k + 1 (NULL allowed).
+ */
+ifmm_status ifmm_rank_model_train(const float* X, const float* t, int64_t m, int32_t nfeat, int32_t steps,
+                                  float lr, float tau, float* theta, double* loss_hist);
+
+/* Loads (theta != NULL) or clears the rank model of a handle; used by later ifmm_factor calls. */
+ifmm_status ifmm_set_rank_model(ifmm_handle* h, const float* theta, int32_t nfeat);
+
+/* With on != 0 the next ifmm_factor records (features, new rank / n) of every sketch-eligible recompression. */
+ifmm_status ifmm_record_ranks(ifmm_handle* h, int32_t on);
+
+/* Copies up to cap recorded samples (X: cap x IFMM_RANK_FEATURES, t: cap); *count = number recorded. */
+ifmm_status ifmm_rank_records(const ifmm_handle* h, float* X, float* t, int64_t cap, int64_t* count);
+
 /* ---- FMM matrix-vector product and the preconditioned FMBEM driver ---------
  * Alg. 4 builds an FMM tree, precomputes the FMM operators and runs GMRES from
  * x = 0; Alg. 5 is its preconditioner (the IFMM solve).  Sec. 4.2 allows the

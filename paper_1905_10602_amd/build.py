@@ -38,6 +38,8 @@ def build(verbose: bool = False) -> str:
                         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]),
         ("fmm.hip", ["-x", "hip", "--offload-arch=gfx950", "-ffp-contract=fast",
                      "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]),
+        ("mlp.hip", ["-x", "hip", "--offload-arch=gfx950", "-ffp-contract=fast",
+                     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]),
     ]
     procs = []
     for src, extra in jobs:

@@ -30,6 +30,20 @@ int build_host(Handle& h, const double* pts, int64_t n, const double* w, const d
   if (!err.empty()) return IFMM_EINVAL;
   h.N = n;
   h.symmetric = (w == nullptr);
+  // points inside every node's box (leaf ranges summed up the tree)
+  const int D = h.tree.depth;
+  h.pt_count.assign((size_t)D + 1, {});
+  for (int l = D; l >= 2; --l) {
+    const Level& L = h.tree.levels[l];
+    h.pt_count[l].assign((size_t)L.n, 0);
+    for (int i = 0; i < L.n; ++i) {
+      if (l == D) {
+        h.pt_count[l][i] = L.pt_end[i] - L.pt_begin[i];
+      } else {
+        for (int e = L.child_ptr[i]; e < L.child_ptr[i + 1]; ++e) h.pt_count[l][i] += h.pt_count[l + 1][L.child[e]];
+      }
+    }
+  }
   h.pts.resize((size_t)(3 * n));
   h.w.resize((size_t)n);
   h.diag.resize((size_t)n);
@@ -147,6 +161,10 @@ ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
                   ",\"t_solve\":" + std::to_string(h.t_solve) + ",\"device_bytes\":" + std::to_string(h.dev_bytes) +
                   ",\"store_bytes\":" + std::to_string(h.store_bytes) + ",\"top_n\":" + std::to_string(h.top_n) +
                   ",\"t_top\":" + std::to_string(h.t_top) + ",\"far_pairs\":" + std::to_string(h.stat_far) + ",\"changed\":" + std::to_string(h.stat_changed) + ",\"grown\":" + std::to_string(h.stat_grown) +
+                  ",\"sketches\":" + std::to_string(h.stat_sketch) +
+                  ",\"sketches_rejected\":" + std::to_string(h.stat_sketch_rejected) +
+                  ",\"sketches_narrow\":" + std::to_string(h.stat_sketch_narrow) +
+                  ",\"rank_predictions\":" + std::to_string(h.stat_predicted) +
                   ",\"levels\":[";
   for (int l = 2; l <= h.tree.depth; ++l) {
     const ifmm::Level& T = h.tree.levels[l];
@@ -224,10 +242,49 @@ ifmm_status ifmm_ranks(const ifmm_handle* H, int32_t level, int32_t* ranks) {
   return IFMM_OK;
 }
 
+ifmm_status ifmm_set_rank_model(ifmm_handle* H, const float* theta, int32_t nfeat) {
+  ifmm::set_error("");
+  if (!H) return fail(IFMM_EINVAL, "handle is NULL");
+  ifmm::Handle& h = H->h;
+  if (h.d_model) {
+    (void)hipFree(h.d_model);
+    h.d_model = nullptr;
+  }
+  if (!theta) return IFMM_OK;
+  if (nfeat != IFMM_RANK_FEATURES) return fail(IFMM_EINVAL, "the rank model takes IFMM_RANK_FEATURES inputs");
+  const int64_t np = ifmm_rank_model_params(nfeat);
+  for (int64_t i = 0; i < np; ++i)
+    if (!std::isfinite(theta[i])) return fail(IFMM_ENONFINITE, "non-finite model parameter");
+  if (hipMalloc((void**)&h.d_model, (size_t)np * 4) != hipSuccess) return fail(IFMM_EDEVICE, "device allocation failed");
+  if (hipMemcpy(h.d_model, theta, (size_t)np * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(IFMM_EDEVICE, "copy failed");
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_record_ranks(ifmm_handle* H, int32_t on) {
+  if (!H) return fail(IFMM_EINVAL, "handle is NULL");
+  H->h.record_ranks = on != 0;
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_rank_records(const ifmm_handle* H, float* X, float* t, int64_t cap, int64_t* count) {
+  if (!H || !count) return fail(IFMM_EINVAL, "bad arguments");
+  const ifmm::Handle& h = H->h;
+  const int64_t m = (int64_t)h.rec_t.size();
+  *count = m;
+  if (!X || !t) return IFMM_OK;
+  const int64_t k = std::min(m, cap);
+  std::memcpy(X, h.rec_X.data(), (size_t)k * IFMM_RANK_FEATURES * 4);
+  std::memcpy(t, h.rec_t.data(), (size_t)k * 4);
+  return IFMM_OK;
+}
+
 const char* ifmm_last_error(void) { return ifmm::get_error(); }
 
 void ifmm_destroy(ifmm_handle* H) {
   if (!H) return;
+  if (H->h.d_model) (void)hipFree(H->h.d_model);
+  H->h.d_model = nullptr;
   ifmm::release(H->h);
   delete H;
 }

@@ -23,6 +23,7 @@
 
 #include "engine.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 
 namespace ifmm {
 
@@ -139,7 +140,7 @@ struct ProfScope {
     if (!on) return;
     p.a = take_event(h);
     p.b = take_event(h);
-    p.name = name;
+    p.name = h.prof_level && h.cur_level > 0 ? std::string(name) + "@" + std::to_string(h.cur_level) : name;
     p.flops = flops;
     p.bytes = bytes;
     (void)hipEventRecord(p.a, h.stream);
@@ -459,6 +460,92 @@ static int reduce_level(Handle& h, int l, std::string& err) {
 }
 
 // ------------------------------------------------------------------ one colour
+// Rank guess that sizes a sketch when no learned model is loaded: the node's
+// current rank.
+static int predict_rank(const Handle& h, int l, const Changed& C, int side) {
+  (void)h;
+  (void)l;
+  (void)side;
+  return std::max(1, C.r);
+}
+
+constexpr int RANK_NF = 14;
+
+// Features of the rank predictor for changed nodes `ids` (level, box size,
+// points in the box, interaction-list size, n, current rank and the top-8
+// singular values of an 8-column range sample of the source-side stacked
+// factor), and, when a model is loaded, its predictions (fraction of n).
+static int rank_features(Handle& h, int l, std::vector<Changed>& chg, const std::vector<int32_t>& ids,
+                         const std::vector<int64_t>& wrows, const Changed* d_chg, const FarRef* d_refs,
+                         const FarPair* d_far, const ElimNbr* d_nbrs, const ElimRec* d_recs, std::vector<float>& feats,
+                         std::vector<float>& pred, std::string& err) {
+  const size_t nf = ids.size();
+  feats.assign(nf * RANK_NF, 0.f);
+  pred.assign(nf, -1.f);
+  if (!nf) return 0;
+  const Level& T = h.tree.levels[l];
+  int64_t need = 0;
+  int nmax = 1;
+  for (int32_t k : ids) {
+    need += (std::max<int64_t>(wrows[k], chg[k].n) + chg[k].n) * 8 + 64;
+    nmax = std::max(nmax, chg[k].n);
+  }
+  const size_t tb = (nf * sizeof(SkTask) + nf * 8 * 8 + nf * RANK_NF * 4 + nf * 4 + 1024 + 255) & ~(size_t)255;
+  const int64_t mlpw = mlp_work_floats((int64_t)nf);
+  int rc;
+  if ((rc = ensure(h, (void**)&h.fbuf, &h.fbuf_bytes, (int64_t)tb + need * 8 + mlpw * 4 + 512, err))) return rc;
+  char* base = (char*)h.fbuf;
+  SkTask* d_t = (SkTask*)base;
+  double* d_sv = (double*)(d_t + nf);
+  float* d_X = (float*)(d_sv + 8 * nf);
+  float* d_y = d_X + nf * RANK_NF;
+  double* W0 = (double*)(base + tb);
+  float* d_mw = (float*)(W0 + need);
+  std::vector<SkTask> tt(nf);
+  int64_t o = 0;
+  for (size_t a = 0; a < nf; ++a) {
+    const Changed& C = chg[ids[a]];
+    SkTask& t = tt[a];
+    std::memset(&t, 0, sizeof t);
+    t.O = W0 + o; o += std::max<int64_t>(wrows[ids[a]], C.n) * 8;
+    t.Y = W0 + o; o += (int64_t)C.n * 8 + 64;
+    t.n = C.n; t.s = 8; t.R = (int32_t)wrows[ids[a]]; t.chg = ids[a];
+    t.seed = (uint32_t)(0x51ED + 2 * C.p); t.side = 0;
+  }
+  HIPCHK(hipMemcpyAsync(d_t, tt.data(), nf * sizeof(SkTask), hipMemcpyHostToDevice, h.stream));
+  hipLaunchKernelGGL(k_sk_omega, dim3(16, (unsigned)nf), dim3(NT), 0, h.stream, d_t);
+  hipLaunchKernelGGL(k_sk_range, dim3((unsigned)((nmax + 63) / 64), 1, (unsigned)nf), dim3(NT), 0, h.stream, d_chg,
+                     d_refs, d_far, d_nbrs, d_recs, d_t);
+  hipLaunchKernelGGL(k_feat_sv, dim3((unsigned)nf), dim3(NT), 0, h.stream, d_t, d_sv);
+  std::vector<double> sv(8 * nf);
+  HIPCHK(hipMemcpyAsync(sv.data(), d_sv, sv.size() * 8, hipMemcpyDeviceToHost, h.stream));
+  HIPCHK(hipStreamSynchronize(h.stream));
+  const double half = h.tree.H / (double)(1 << l);
+  for (size_t a = 0; a < nf; ++a) {
+    const Changed& C = chg[ids[a]];
+    float* f = &feats[a * RANK_NF];
+    const double s1 = std::max(sv[8 * a], 1e-300);
+    f[0] = (float)(l / 8.0);
+    f[1] = (float)(std::log10(half) / 4.0);
+    f[2] = (float)(std::log2(1.0 + (double)h.pt_count[l][C.p]) / 20.0);
+    f[3] = (float)((T.il_ptr[C.p + 1] - T.il_ptr[C.p]) / 189.0);
+    f[4] = (float)(C.n / 1024.0);
+    f[5] = (float)(C.r / 512.0);
+    f[6] = (float)(std::log10(s1) / 8.0);
+    for (int i = 1; i < 8; ++i) f[6 + i] = (float)(std::log10(std::max(sv[8 * a + i], 1e-300) / s1) / 16.0);
+  }
+  if (h.d_model) {
+    HIPCHK(hipMemcpyAsync(d_X, feats.data(), feats.size() * 4, hipMemcpyHostToDevice, h.stream));
+    if (mlp_forward_dev(h.d_model, RANK_NF, d_X, (int64_t)nf, d_y, d_mw, h.stream)) {
+      err = "rank model forward failed";
+      return -3;
+    }
+    HIPCHK(hipMemcpyAsync(pred.data(), d_y, nf * 4, hipMemcpyDeviceToHost, h.stream));
+    HIPCHK(hipStreamSynchronize(h.stream));
+  }
+  return 0;
+}
+
 static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   const Level& T = h.tree.levels[l];
   DevLevel& L = h.lv[l];
@@ -768,21 +855,202 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       hipLaunchKernelGGL(k_gram, dim3((unsigned)std::max(1, nbt * (nbt + 1) / 2), sides * nchg), dim3(NT), 0,
                          h.stream, V, d_chg, d_refs, d_far, d_nbrs, d_recs, sides);
     }
-    {
+  }
+  // ---- recompression: per changed node and side, either a sketch of width s
+  // (predicted rank plus oversampling) or the full eigen-decomposition
+  const int ne = (int)etasks.size();
+  std::vector<int32_t> skw(ne, 0), cnt(ne, 0), info(nrec);
+  std::vector<int32_t> full_ids, sk_ids;
+  std::vector<EigTask> fullT, skE;
+  std::vector<SkTask> skT;
+  std::vector<GemmTask> gT;
+  std::vector<int32_t> cnt_full, cnt_sk, ok_sk;
+  std::vector<float> rfeat, rpred;
+  std::vector<int32_t> fe_ids, fe_of;
+  if (nchg) {
+    // rows of the stacked factor of each changed node's Gram matrix
+    std::vector<int64_t> wrows(nchg, 0);
+    for (int k = 0; k < nchg; ++k) {
+      const Changed& C = chg[k];
+      int64_t rr = C.r;
+      for (int q = 0; q < C.far_count; ++q) {
+        const FarPair& F = far[refs[C.far_begin + q].ba];
+        rr += nbrs[recs[F.rec].nb_begin + F.a].m;
+      }
+      wrows[k] = rr;
+    }
+    // learned rank: features and predictions of the sketch-eligible nodes
+    fe_of.assign(nchg, -1);
+    if ((h.d_model || h.record_ranks) && h.sketch && !h.eig_jacobi)
+      for (int k = 0; k < nchg; ++k)
+        if (chg[k].n >= h.sketch_min) {
+          fe_of[k] = (int32_t)fe_ids.size();
+          fe_ids.push_back(k);
+        }
+    if (!fe_ids.empty() &&
+        (rc = rank_features(h, l, chg, fe_ids, wrows, d_chg, d_refs, d_far, d_nbrs, d_recs, rfeat, rpred, err)))
+      return rc;
+    for (int e = 0; e < ne; ++e) {
+      const int k = e / sides;
+      const Changed& C = chg[k];
+      int s = 0;
+      if (h.sketch && !h.eig_jacobi && C.n >= h.sketch_min) {
+        int pred;
+        if (h.d_model && fe_of[k] >= 0) {
+          const float fr = std::min(1.f, std::max(0.f, rpred[fe_of[k]]));
+          pred = std::max(1, (int)std::ceil(fr * C.n));
+          ++h.stat_predicted;
+          s = std::min(C.n, pred + std::max(8, pred / 8));
+        } else {
+          pred = predict_rank(h, l, C, e % sides);
+          s = std::min(C.n, pred + std::max(16, pred / 4));
+        }
+        if (s < 1 || s > (int)(0.6 * C.n)) s = 0;
+      }
+      skw[e] = s;
+      (s ? sk_ids : full_ids).push_back(e);
+    }
+    // device tables and buffers of the sketches
+    int64_t need = 0;
+    for (int e : sk_ids) {
+      const int64_t n = chg[e / sides].n, sw = skw[e];
+      need += std::max<int64_t>(wrows[e / sides], n) * sw + n * sw + 2 * sw * sw + 3 * sw + 64;
+    }
+    const size_t nsk = sk_ids.size(), nfull = full_ids.size();
+    const size_t tb = ((nfull + 2 * nsk) * sizeof(EigTask) + nsk * sizeof(SkTask) + 4 * nsk * sizeof(GemmTask) +
+                       (nfull + 3 * nsk) * 4 + 4096 + 255) & ~(size_t)255;
+    if ((rc = ensure(h, (void**)&h.skbuf, &h.skbuf_bytes, (int64_t)tb + need * 8 + 256, err))) return rc;
+    char* base = (char*)h.skbuf;
+    EigTask* d_fullT = (EigTask*)base;
+    EigTask* d_skE = d_fullT + nfull;
+    EigTask* d_fbT = d_skE + nsk;  // fall-back full tasks of rejected sketches
+    SkTask* d_skT = (SkTask*)(d_fbT + nsk);
+    GemmTask* d_gT = (GemmTask*)(d_skT + nsk);
+    int32_t* d_cf = (int32_t*)(d_gT + 4 * nsk);
+    int32_t* d_cs = d_cf + nfull;
+    int32_t* d_ok = d_cs + nsk;
+    int32_t* d_cfb = d_ok + nsk;
+    double* W0 = (double*)(base + tb);
+    int64_t o = 0;
+    for (int e : full_ids) fullT.push_back(etasks[e]);
+    int smax = 1, nmax = 1;
+    for (int e : sk_ids) {
+      const Changed& C = chg[e / sides];
+      const int side = e % sides;
+      const int n = C.n, sw = skw[e];
+      SkTask t;
+      t.G = side ? C.gt : C.gs;
+      t.O = W0 + o; o += std::max<int64_t>(wrows[e / sides], n) * sw;
+      t.Y = W0 + o; o += (int64_t)n * sw;
+      t.B = W0 + o; o += (int64_t)sw * sw;
+      double* U = W0 + o; o += (int64_t)sw * sw;
+      double* Wk = W0 + o; o += 3LL * sw;
+      t.tr = W0 + o; o += 64;
+      t.n = n; t.s = sw;
+      t.R = (int32_t)wrows[e / sides];
+      t.chg = e / sides;
+      t.seed = (uint32_t)(C.p * 2 + side + 1);
+      t.side = (uint32_t)side;
+      skT.push_back(t);
+      skE.push_back({t.B, U, Wk, side ? C.lt : C.ls, nullptr, sw, 0});
+      smax = std::max(smax, sw);
+      nmax = std::max(nmax, n);
+    }
+    // Z = G Q (into O), B = Q^T Z
+    for (const SkTask& t : skT) gT.push_back({t.G, t.Y, t.O, t.n, t.s, t.n, t.n, t.n, t.n, 0, 0, 1.0, 0.0});
+    for (const SkTask& t : skT) gT.push_back({t.Y, t.O, t.B, t.s, t.s, t.n, t.n, t.n, t.s, 1, 0, 1.0, 0.0});
+    if (nfull) HIPCHK(hipMemcpyAsync(d_fullT, fullT.data(), nfull * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
+    if (nsk) {
+      HIPCHK(hipMemcpyAsync(d_skE, skE.data(), nsk * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
+      HIPCHK(hipMemcpyAsync(d_skT, skT.data(), nsk * sizeof(SkTask), hipMemcpyHostToDevice, h.stream));
+      HIPCHK(hipMemcpyAsync(d_gT, gT.data(), 2 * nsk * sizeof(GemmTask), hipMemcpyHostToDevice, h.stream));
+    }
+    const double eps2 = h.eps * h.eps;
+    if (nsk) {
+      double fl_sk = 0;
+      for (const SkTask& t : skT)
+        fl_sk += 2.0 * t.n * (double)t.R * t.s + 2.0 * t.n * (double)t.n * t.s + 6.0 * t.n * (double)t.s * t.s;
+      ProfScope ps(h, "k_sketch", fl_sk, 0);
+      const unsigned tn = (unsigned)((nmax + 63) / 64), ts = (unsigned)((smax + 63) / 64);
+      const double drop = std::max(1e-13, std::min(1e-9, 1e-3 * h.eps));
+      hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
+      hipLaunchKernelGGL(k_sk_range, dim3(tn, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_chg, d_refs, d_far, d_nbrs,
+                         d_recs, d_skT);
+      hipLaunchKernelGGL(k_sk_orth, dim3((unsigned)nsk), dim3(NT), 0, h.stream, d_skT, drop);
+      hipLaunchKernelGGL(k_gemm_batch, dim3(tn, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_gT);
+      hipLaunchKernelGGL(k_gemm_batch, dim3(ts, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_gT + nsk);
+      hipLaunchKernelGGL(k_sk_trace, dim3((unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
+      hipLaunchKernelGGL(k_eig_values, dim3((unsigned)nsk), dim3(NT), 0, h.stream, d_skE, eps2, d_cs, 0);
+      hipLaunchKernelGGL(k_sk_check, dim3((unsigned)((nsk + NT - 1) / NT)), dim3(NT), 0, h.stream, d_skT, d_skE, d_cs,
+                         eps2, d_ok, (int)nsk);
+    }
+    if (nfull) {
       ProfScope ps(h, "k_eig_values", fl_ev, 0);
       if (h.eig_jacobi)
-        hipLaunchKernelGGL(k_eig_jacobi, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et, h.eps * h.eps,
-                           d_cnt);
+        hipLaunchKernelGGL(k_eig_jacobi, dim3((unsigned)nfull), dim3(NT), 0, h.stream, d_fullT, eps2, d_cf);
       else
-        hipLaunchKernelGGL(k_eig_values, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et, h.eps * h.eps,
-                           d_cnt, 0);
+        hipLaunchKernelGGL(k_eig_values, dim3((unsigned)nfull), dim3(NT), 0, h.stream, d_fullT, eps2, d_cf, 0);
     }
+    HIPCHK(hipGetLastError());
+    cnt_full.assign(nfull, 0);
+    cnt_sk.assign(nsk, 0);
+    ok_sk.assign(nsk, 0);
+    if (nfull) HIPCHK(hipMemcpyAsync(cnt_full.data(), d_cf, nfull * 4, hipMemcpyDeviceToHost, h.stream));
+    if (nsk) {
+      HIPCHK(hipMemcpyAsync(cnt_sk.data(), d_cs, nsk * 4, hipMemcpyDeviceToHost, h.stream));
+      HIPCHK(hipMemcpyAsync(ok_sk.data(), d_ok, nsk * 4, hipMemcpyDeviceToHost, h.stream));
+    }
+    HIPCHK(hipMemcpyAsync(info.data(), d_info, nrec * 4, hipMemcpyDeviceToHost, h.stream));
+    HIPCHK(hipStreamSynchronize(h.stream));
+    for (size_t a = 0; a < nfull; ++a) cnt[full_ids[a]] = cnt_full[a];
+    // rejected sketches: full eigen-decomposition of their Gram matrices
+    std::vector<EigTask> fb;
+    std::vector<int32_t> fb_of;
+    for (size_t a = 0; a < nsk; ++a) {
+      const int e = sk_ids[a];
+      if (ok_sk[a] == 0) ++h.stat_sketch_narrow;
+      if (ok_sk[a] > 0) {
+        cnt[e] = cnt_sk[a];
+      } else {
+        fb.push_back(etasks[e]);
+        fb_of.push_back((int32_t)a);
+      }
+    }
+    h.stat_sketch += (int64_t)nsk;
+    h.stat_sketch_rejected += (int64_t)fb.size();
+    if (!fb.empty()) {
+      HIPCHK(hipMemcpyAsync(d_fbT, fb.data(), fb.size() * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
+      {
+        ProfScope ps(h, "k_eig_values", 0, 0);
+        hipLaunchKernelGGL(k_eig_values, dim3((unsigned)fb.size()), dim3(NT), 0, h.stream, d_fbT, eps2, d_cfb, 0);
+      }
+      std::vector<int32_t> cfb(fb.size());
+      HIPCHK(hipMemcpyAsync(cfb.data(), d_cfb, fb.size() * 4, hipMemcpyDeviceToHost, h.stream));
+      HIPCHK(hipStreamSynchronize(h.stream));
+      for (size_t a = 0; a < fb.size(); ++a) cnt[sk_ids[fb_of[a]]] = cfb[a];
+    }
+    // the full-path task list now holds every non-accepted task
+    for (size_t a = 0; a < fb.size(); ++a) {
+      full_ids.push_back(sk_ids[fb_of[a]]);
+      fullT.push_back(fb[a]);
+    }
+    std::vector<int32_t> keep_ids;
+    std::vector<EigTask> keepE;
+    std::vector<SkTask> keepT;
+    for (size_t a = 0; a < nsk; ++a)
+      if (ok_sk[a] > 0) {
+        keep_ids.push_back(sk_ids[a]);
+        keepE.push_back(skE[a]);
+        keepT.push_back(skT[a]);
+      }
+    sk_ids.swap(keep_ids);
+    skE.swap(keepE);
+    skT.swap(keepT);
+  } else {
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(info.data(), d_info, nrec * 4, hipMemcpyDeviceToHost, h.stream));
+    HIPCHK(hipStreamSynchronize(h.stream));
   }
-  HIPCHK(hipGetLastError());
-  std::vector<int32_t> cnt(etasks.size()), info(nrec);
-  if (nchg) HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * 4, hipMemcpyDeviceToHost, h.stream));
-  HIPCHK(hipMemcpyAsync(info.data(), d_info, nrec * 4, hipMemcpyDeviceToHost, h.stream));
-  HIPCHK(hipStreamSynchronize(h.stream));
   prof_collect(h);
   for (int k = 0; k < nrec; ++k)
     if (info[k]) {
@@ -796,25 +1064,76 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       int rn = sym ? cnt[k] : std::max(cnt[2 * k], cnt[2 * k + 1]);
       rn = std::min(rn, std::min(C.n, L.rc[C.p]));
       C.rnew = rn;
-      iw += sides * (5LL * C.n * rn + 32);
     }
+    if (h.record_ranks)
+      for (size_t a = 0; a < fe_ids.size(); ++a) {
+        const Changed& C = chg[fe_ids[a]];
+        h.rec_X.insert(h.rec_X.end(), rfeat.begin() + a * RANK_NF, rfeat.begin() + (a + 1) * RANK_NF);
+        h.rec_t.push_back((float)C.rnew / (float)C.n);
+      }
+    // every accepted sketch can supply rn vectors: rn <= max count < s on both sides
+    for (size_t a = 0; a < sk_ids.size(); ++a) {
+      const Changed& C = chg[sk_ids[a] / sides];
+      if (C.rnew >= skT[a].s) {
+        err = "sketch narrower than the selected rank";
+        return -6;
+      }
+    }
+    for (int e : full_ids) iw += 5LL * chg[e / sides].n * chg[e / sides].rnew + 32;
+    for (size_t a = 0; a < sk_ids.size(); ++a) iw += 5LL * skT[a].s * chg[sk_ids[a] / sides].rnew + 32;
     if ((rc = ensure(h, (void**)&h.scratch2, &h.scratch2_bytes, iw * 8 + 64, err))) return rc;
     iw = 0;
-    for (int k = 0; k < nchg; ++k)
-      for (int s2 = 0; s2 < sides; ++s2) {
-        EigTask& t = etasks[(size_t)sides * k + s2];
-        t.k = chg[k].rnew;
-        t.IW = h.scratch2 + iw;
-        iw += 5LL * chg[k].n * chg[k].rnew + 32;
-      }
-    HIPCHK(hipMemcpyAsync((void*)d_et, etasks.data(), etasks.size() * sizeof(EigTask), hipMemcpyHostToDevice,
-                          h.stream));
-    HIPCHK(hipMemcpyAsync(d_chg, chg.data(), chg.size() * sizeof(Changed), hipMemcpyHostToDevice, h.stream));
-    for (int k = 0; k < nchg; ++k) fl_evec += sides * 2.0 * (double)chg[k].n * chg[k].n * chg[k].rnew;
-    if (!h.eig_jacobi) {
-      ProfScope ps(h, "k_eig_vectors", fl_evec, 0);
-      hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)etasks.size()), dim3(NT), 0, h.stream, d_et);
+    for (size_t a = 0; a < full_ids.size(); ++a) {
+      const Changed& C = chg[full_ids[a] / sides];
+      fullT[a].k = C.rnew;
+      fullT[a].IW = h.scratch2 + iw;
+      iw += 5LL * C.n * C.rnew + 32;
     }
+    for (size_t a = 0; a < sk_ids.size(); ++a) {
+      const Changed& C = chg[sk_ids[a] / sides];
+      skE[a].k = C.rnew;
+      skE[a].IW = h.scratch2 + iw;
+      iw += 5LL * skT[a].s * C.rnew + 32;
+    }
+    const size_t nf2 = fullT.size(), ns2 = sk_ids.size();
+    std::vector<GemmTask> vT;
+    for (size_t a = 0; a < ns2; ++a) {
+      const int e = sk_ids[a];
+      const Changed& C = chg[e / sides];
+      double* Vout = (e % sides) ? C.vt : C.vs;
+      vT.push_back({skT[a].Y, skE[a].V, Vout, C.n, C.rnew, skT[a].s, C.n, skT[a].s, C.n, 0, 0, 1.0, 0.0});
+    }
+    const size_t need_tab = (nf2 + ns2) * sizeof(EigTask) + ns2 * sizeof(GemmTask) + 1024;
+    if ((rc = ensure(h, (void**)&h.meta2b, &h.meta2b_bytes, (int64_t)need_tab, err))) return rc;
+    EigTask* d_vf = (EigTask*)h.meta2b;
+    EigTask* d_vs = d_vf + nf2;
+    GemmTask* d_vg = (GemmTask*)(d_vs + ns2);
+    if (nf2) HIPCHK(hipMemcpyAsync(d_vf, fullT.data(), nf2 * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
+    if (ns2) {
+      HIPCHK(hipMemcpyAsync(d_vs, skE.data(), ns2 * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
+      HIPCHK(hipMemcpyAsync(d_vg, vT.data(), ns2 * sizeof(GemmTask), hipMemcpyHostToDevice, h.stream));
+    }
+    HIPCHK(hipMemcpyAsync(d_chg, chg.data(), chg.size() * sizeof(Changed), hipMemcpyHostToDevice, h.stream));
+    for (int e : full_ids) fl_evec += 2.0 * (double)chg[e / sides].n * chg[e / sides].n * chg[e / sides].rnew;
+    if (!h.eig_jacobi && nf2) {
+      ProfScope ps(h, "k_eig_vectors", fl_evec, 0);
+      hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)nf2), dim3(NT), 0, h.stream, d_vf);
+    }
+    if (ns2) {
+      double fl = 0;
+      int rmax = 1, nmx = 1;
+      for (size_t a = 0; a < ns2; ++a) {
+        const Changed& C = chg[sk_ids[a] / sides];
+        fl += 2.0 * (double)skT[a].s * skT[a].s * C.rnew + 2.0 * (double)C.n * skT[a].s * C.rnew;
+        rmax = std::max(rmax, C.rnew);
+        nmx = std::max(nmx, C.n);
+      }
+      ProfScope ps(h, "k_sketch", fl, 0);
+      hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)ns2), dim3(NT), 0, h.stream, d_vs);
+      hipLaunchKernelGGL(k_gemm_batch, dim3((unsigned)((nmx + 63) / 64), (unsigned)((rmax + 63) / 64), (unsigned)ns2),
+                         dim3(NT), 0, h.stream, d_vg);
+    }
+    HIPCHK(hipStreamSynchronize(h.stream));  // host task tables above are temporaries
     hipLaunchKernelGGL(k_basis, dim3(nchg), dim3(NT), 0, h.stream, V, d_chg);
     if ((rc = check_arena(h, l, "basis", c, err))) return rc;
   }
@@ -1098,6 +1417,13 @@ int factor(Handle& h, std::string& err) {
   h.prof = std::getenv("IFMM_PROF") != nullptr;
   h.il_tight = std::getenv("IFMM_IL_TIGHT") != nullptr;
   if (const char* e = std::getenv("IFMM_BIG_D")) h.big_d = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("IFMM_SKETCH")) h.sketch = std::atoi(e) != 0;
+  h.prof_level = std::getenv("IFMM_PROF_LEVEL") != nullptr;
+  if (const char* e = std::getenv("IFMM_SKETCH_MIN")) h.sketch_min = std::max(1, std::atoi(e));
+  h.stat_sketch = h.stat_sketch_rejected = h.stat_sketch_narrow = 0;
+  h.rec_X.clear();
+  h.rec_t.clear();
+  h.stat_predicted = 0;
   h.kstat.clear();
   h.stat_far = 0;
   h.stat_changed = 0;
@@ -1113,6 +1439,7 @@ int factor(Handle& h, std::string& err) {
     DevLevel& L = h.lv[l];
     L.col_ptr.assign(1, 0);
     ta = now_s();
+    h.cur_level = l;
     for (int c = 0; c < T.ncolour; ++c)
       if ((rc = eliminate_colour(h, l, c, err))) return rc;
     HIPCHK(hipStreamSynchronize(h.stream));
@@ -1125,6 +1452,7 @@ int factor(Handle& h, std::string& err) {
     if (l > 2 && (rc = aggregate_level(h, l, err))) return rc;
     if (l > 2) h.t_level_setup[l - 1] = now_s() - ta;
   }
+  h.cur_level = 0;
   ta = now_s();
   // top: dense LU of the level-2 system
   DevLevel& L2 = h.lv[2];

@@ -163,6 +163,25 @@ struct Handle {
   // IFMM_PROF set: per kernel class, launches / time (hipEvents on the launch
   // stream) / algorithmic flops and bytes of the instrumented launches
   bool prof = false;
+  // sketched recompression (randomised range finder with a rank guess; the
+  // full eigen-decomposition remains the fall-back and the judge)
+  bool sketch = true;       // IFMM_SKETCH=0 disables
+  int sketch_min = 128;     // Gram order from which a sketch is tried (IFMM_SKETCH_MIN)
+  double* skbuf = nullptr;
+  int64_t skbuf_bytes = 0;
+  char* meta2b = nullptr;
+  int64_t meta2b_bytes = 0;
+  int64_t stat_sketch = 0, stat_sketch_rejected = 0, stat_sketch_narrow = 0;
+  bool record_ranks = false;
+  bool prof_level = false;  // IFMM_PROF_LEVEL: profile classes keyed "name@level"
+  int cur_level = 0;
+  // learned rank model (FP32 parameters on the device) and recorded samples
+  float* d_model = nullptr;
+  double* fbuf = nullptr;
+  int64_t fbuf_bytes = 0;
+  std::vector<float> rec_X, rec_t;                   // features (14 per row) and r_new / n
+  std::vector<std::vector<int64_t>> pt_count;        // points in each node's box, per level
+  int64_t stat_predicted = 0;
   int big_d = 256;          // pivots of at least this order take the blocked multi-workgroup path (IFMM_BIG_D)
   bool il_tight = false;    // IFMM_IL_TIGHT set: no capacity headroom for M2L blocks (tests the growth path)
   struct KStat {

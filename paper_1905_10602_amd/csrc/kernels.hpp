@@ -239,6 +239,222 @@ __global__ void k_eig_vectors(const EigTask* tasks) {
   wg_syev_vectors(t.n, t.A, t.n, t.W, t.lam, t.k, t.V, t.n, t.IW);
 }
 
+// ------------------------------------------------------------------ batched tiled GEMM
+// C = alpha op(A) op(B) + beta C for many independent problems; grid
+// (row tiles, column tiles, task), one 64 x 64 output tile per workgroup.
+struct GemmTask {
+  const double* A;
+  const double* B;
+  double* C;
+  int32_t m, n, k, lda, ldb, ldc, tA, tB;
+  double alpha, beta;
+};
+__global__ void k_gemm_batch(const GemmTask* tasks) {
+  const GemmTask t = tasks[blockIdx.z];
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  if (i0 >= t.m || j0 >= t.n) return;
+  const int mm = min(64, t.m - i0), nn = min(64, t.n - j0);
+  const double* Ab = t.tA ? t.A + (int64_t)i0 * t.lda : t.A + i0;
+  const double* Bb = t.tB ? t.B + j0 : t.B + (int64_t)j0 * t.ldb;
+  wg_gemm(mm, nn, t.k, t.alpha, Ab, t.lda, t.tA != 0, Bb, t.ldb, t.tB != 0, t.beta, t.C + i0 + (int64_t)j0 * t.ldc,
+          t.ldc);
+}
+
+// ------------------------------------------------------------------ sketched recompression
+// Randomised range finder on a Gram matrix G (n x n, PSD) with s columns
+// (the predicted rank plus oversampling): Y = G Omega, Q = orth(Y),
+// B = Q^T G Q, eigen-pairs of B (Rayleigh-Ritz).  Every direction outside
+// span(Q) carries at most trace(G) - trace(B) of G's eigenvalue mass, so the
+// sketch is accepted when that tail is <= eps^2 lambda_1 (no eigenvalue
+// above the truncation threshold was missed) and fewer than s Ritz values
+// pass the threshold; otherwise the full eigen-decomposition runs.
+struct SkTask {
+  const double* G;  // n x n
+  double *O, *Y;    // O: Omega (R x s), later G Q (n x s);  Y (n x s), then Q
+  double* B;        // s x s
+  double* tr;       // trace(G), trace(B)
+  int32_t n, s, R, chg;  // R = rows of the stacked factor W (G = W^T W); changed-node index
+  uint32_t seed, side;
+};
+
+__device__ inline double sk_uniform(uint32_t seed, uint64_t idx) {
+  uint64_t z = ((uint64_t)seed << 40) ^ (idx + 0x9E3779B97F4A7C15ULL);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;  // [-1, 1)
+}
+
+__global__ void k_sk_omega(const SkTask* tasks) {
+  const SkTask t = tasks[blockIdx.y];
+  const int64_t tot = (int64_t)t.R * t.s;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT)
+    t.O[e] = sk_uniform(t.seed, (uint64_t)e);
+}
+
+// Range sample of the stacked factor instead of the Gram matrix itself, so the
+// sampled directions carry singular values, not their squares:
+//   side 0:  Y = W^T Omega,  W = [diag(sig_s) P2M ; F_qp ...]   (rows: r, then m_q each)
+//   side 1:  Y = W Omega,    W = [L2P diag(sig_t) , F_pq ...]   (columns likewise)
+// grid (row tiles of n, column tiles of s, sketch task).
+__global__ void k_sk_range(const Changed* chg, const FarRef* refs, const FarPair* far, const ElimNbr* nbrs,
+                           const ElimRec* recs, const SkTask* tasks) {
+  const SkTask t = tasks[blockIdx.z];
+  const int I = blockIdx.x * 64, J = blockIdx.y * 64;
+  if (I >= t.n || J >= t.s) return;
+  const Changed C = chg[t.chg];
+  const int n = C.n, r = C.r, s = t.s;
+  const int mi = min(64, n - I), sj = min(64, s - J);
+  const ElimRec R = recs[C.rec];
+  const double* tb = C.tmp + (int64_t)t.side * r * n;  // scaled bases from k_gram_prep
+  double* Y = t.Y + I + (int64_t)J * n;
+  const double* Om = t.O + (int64_t)J * t.R;
+  if (t.side == 0) {
+    wg_gemm(mi, sj, r, 1.0, tb + (int64_t)I * r, r, true, Om, t.R, false, 0.0, Y, n);
+    int off = r;
+    for (int k = 0; k < C.far_count; ++k) {
+      const FarPair Pq = far[refs[C.far_begin + k].ba];
+      const int mq = nbrs[R.nb_begin + Pq.a].m;
+      wg_gemm(mi, sj, mq, 1.0, Pq.F + (int64_t)I * mq, mq, true, Om + off, t.R, false, 1.0, Y, n);
+      off += mq;
+    }
+  } else {
+    wg_gemm(mi, sj, r, 1.0, tb + I, n, false, Om, t.R, false, 0.0, Y, n);
+    int off = r;
+    for (int k = 0; k < C.far_count; ++k) {
+      const FarPair Pq = far[refs[C.far_begin + k].ab];
+      const int mq = nbrs[R.nb_begin + Pq.b].m;
+      wg_gemm(mi, sj, mq, 1.0, Pq.F + I, n, false, Om + off, t.R, false, 1.0, Y, n);
+      off += mq;
+    }
+  }
+}
+
+// Column-by-column Gram-Schmidt with one reorthogonalisation pass; a column
+// whose norm collapses below `drop` times its original norm only adds
+// directions with singular values far below the truncation threshold and is
+// set to zero (keeping Q orthonormal).  One workgroup per task.
+__global__ void k_sk_orth(const SkTask* tasks, double drop) {
+  __shared__ double s_c[NT];
+  const SkTask t = tasks[blockIdx.x];
+  const int n = t.n, k = t.s;
+  double* X = t.Y;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int j = 0; j < k; ++j) {
+    double* xj = X + (int64_t)j * n;
+    double part = 0.0;
+    for (int r = tid; r < n; r += NT) part += xj[r] * xj[r];
+    const double n0 = sqrt(wg_sum(part));
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i0 = 0; i0 < j; i0 += NT) {
+        const int cnt = min(NT, j - i0);
+        for (int i = i0 + wave; i < i0 + cnt; i += NT / 64) {
+          const double* xi = X + (int64_t)i * n;
+          double c = 0.0;
+          for (int r = lane; r < n; r += 64) c += xi[r] * xj[r];
+          for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+          if (lane == 0) s_c[i - i0] = c;
+        }
+        __syncthreads();
+        for (int r = tid; r < n; r += NT) {
+          double v = xj[r];
+          for (int i = 0; i < cnt; ++i) v -= s_c[i] * X[r + (int64_t)(i0 + i) * n];
+          xj[r] = v;
+        }
+        __syncthreads();
+      }
+    }
+    part = 0.0;
+    for (int r = tid; r < n; r += NT) part += xj[r] * xj[r];
+    const double n2 = sqrt(wg_sum(part));
+    const double sc = (n2 > drop * n0 && n2 > 0.0) ? 1.0 / n2 : 0.0;
+    for (int r = tid; r < n; r += NT) xj[r] *= sc;
+    __syncthreads();
+  }
+}
+
+// Top singular values of an 8-column range sample Y (n x 8): sqrt of the
+// eigenvalues of Y^T Y (cyclic Jacobi on the 8 x 8 matrix), descending.
+// These are the "sketched singular values" fed to the rank predictor.
+__global__ void k_feat_sv(const SkTask* tasks, double* out) {
+  __shared__ double g[8][8];
+  const SkTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int pr = wave; pr < 64; pr += NT / 64) {
+    const int a = pr >> 3, b = pr & 7;
+    double c = 0.0;
+    if (a <= b)
+      for (int r = lane; r < n; r += 64) c += t.Y[r + (int64_t)a * n] * t.Y[r + (int64_t)b * n];
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0 && a <= b) {
+      g[a][b] = c;
+      g[b][a] = c;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      double off = 0.0;
+      for (int p = 0; p < 8; ++p)
+        for (int q = p + 1; q < 8; ++q) off += g[p][q] * g[p][q];
+      if (off == 0.0) break;
+      for (int p = 0; p < 8; ++p)
+        for (int q = p + 1; q < 8; ++q) {
+          if (g[p][q] == 0.0) continue;
+          const double th = (g[q][q] - g[p][p]) / (2.0 * g[p][q]);
+          const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          const double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
+          for (int k = 0; k < 8; ++k) {
+            const double gp = g[k][p], gq = g[k][q];
+            g[k][p] = cs * gp - sn * gq;
+            g[k][q] = sn * gp + cs * gq;
+          }
+          for (int k = 0; k < 8; ++k) {
+            const double gp = g[p][k], gq = g[q][k];
+            g[p][k] = cs * gp - sn * gq;
+            g[q][k] = sn * gp + cs * gq;
+          }
+        }
+    }
+    double ev[8];
+    for (int k = 0; k < 8; ++k) ev[k] = fmax(g[k][k], 0.0);
+    for (int a = 0; a < 8; ++a)
+      for (int b = a + 1; b < 8; ++b)
+        if (ev[b] > ev[a]) {
+          const double x = ev[a];
+          ev[a] = ev[b];
+          ev[b] = x;
+        }
+    for (int k = 0; k < 8; ++k) out[8 * blockIdx.x + k] = sqrt(ev[k]);
+  }
+}
+
+__global__ void k_sk_trace(const SkTask* tasks) {
+  const SkTask t = tasks[blockIdx.x];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < t.n; i += NT) a += t.G[i + (int64_t)i * t.n];
+  for (int i = threadIdx.x; i < t.s; i += NT) b += t.B[i + (int64_t)i * t.s];
+  const double ta = wg_sum(a);
+  const double tb = wg_sum(b);
+  if (threadIdx.x == 0) {
+    t.tr[0] = ta;
+    t.tr[1] = tb;
+  }
+}
+
+// ok[i] = 1 when sketch i is accepted (see above); cnt from the Ritz values
+__global__ void k_sk_check(const SkTask* tasks, const EigTask* et, const int32_t* cnt, double eps2, int32_t* ok,
+                           int count) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= count) return;
+  const SkTask t = tasks[i];
+  const double l0 = et[i].lam[0];
+  const double tail = t.tr[0] - t.tr[1];
+  // 1 accepted, 0 too narrow (every Ritz value passed), -1 tail too large
+  ok[i] = cnt[i] >= t.s ? 0 : ((l0 > 0.0 && tail <= eps2 * l0) ? 1 : -1);
+}
+
 // Initial rank reduction, basis step: P2M = V^T, L2P = U, sig = sqrt(lam),
 // T = P2Mc V (K x r), S = U^T L2Pc (r x K); then M2M / L2L of the node.
 __global__ void k_reduce_basis(LevelView V, int K, const double* work, const int64_t* work_off,

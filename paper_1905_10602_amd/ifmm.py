@@ -19,6 +19,9 @@ STATUS = {0: "IFMM_OK", -1: "IFMM_EINVAL", -2: "IFMM_ENOMEM", -3: "IFMM_EDEVICE"
           -5: "IFMM_ENONFINITE", -6: "IFMM_ESTATE", -7: "IFMM_ENOCONV"}
 
 
+RANK_FEATURES = 14
+
+
 class IfmmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -58,6 +61,13 @@ def load_library():
         "ifmm_ranks": (I32, [P, I32, P]),
         "ifmm_last_error": (C.c_char_p, []),
         "ifmm_destroy": (None, [P]),
+        "ifmm_rank_model_params": (I64, [I32]),
+        "ifmm_rank_model_eval": (I32, [P, I32, P, I64, P]),
+        "ifmm_rank_model_grad": (I32, [P, I32, P, P, I64, C.c_float, C.POINTER(D), P]),
+        "ifmm_rank_model_train": (I32, [P, P, I64, I32, I32, C.c_float, C.c_float, P, P]),
+        "ifmm_set_rank_model": (I32, [P, P, I32]),
+        "ifmm_record_ranks": (I32, [P, I32]),
+        "ifmm_rank_records": (I32, [P, P, P, I64, C.POINTER(I64)]),
         "fmm_build": (I32, [P, I64, P, P, D, I32, I32, P, C.POINTER(P)]),
         "fmm_matvec": (I32, [P, P, P, I32]),
         "fmm_gmres": (I32, [P, P, P, D, I32, I32, P, I32, C.POINTER(I32), C.POINTER(D)]),
@@ -195,6 +205,30 @@ class IFMM:
         _check(lib.ifmm_tree_lists(self._h, lvl, which, _ptr(ptr), _ptr(idx)))
         return ptr, idx
 
+    # -- learned recompression rank
+    def set_rank_model(self, theta):
+        """theta: flat float32 parameters (None clears the model)."""
+        lib = load_library()
+        if theta is None:
+            _check(lib.ifmm_set_rank_model(self._h, None, RANK_FEATURES))
+            return self
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(lib.ifmm_set_rank_model(self._h, _ptr(th), RANK_FEATURES))
+        return self
+
+    def record_ranks(self, on=True):
+        _check(load_library().ifmm_record_ranks(self._h, 1 if on else 0))
+        return self
+
+    def rank_records(self):
+        lib = load_library()
+        cnt = C.c_int64()
+        _check(lib.ifmm_rank_records(self._h, None, None, 0, C.byref(cnt)))
+        X = np.zeros((cnt.value, RANK_FEATURES), dtype=np.float32)
+        t = np.zeros(cnt.value, dtype=np.float32)
+        _check(lib.ifmm_rank_records(self._h, _ptr(X), _ptr(t), cnt.value, C.byref(cnt)))
+        return X, t
+
     def ranks(self, lvl):
         n = self.level(lvl)["coords"].shape[0]
         r = np.empty(n, dtype=np.int32)
@@ -285,3 +319,38 @@ def fmbem_gmres(centroids, areas, self_terms, f, precond=None, fmm_cheb_order=5,
                            int(fmm_cheb_order), float(tol), int(restart), int(maxit), _ptr(sol), C.byref(it),
                            C.byref(rr)))
     return sol, it.value, rr.value
+
+
+# -- the rank network (device forward / gradient / training)
+def rank_model_params(nfeat=RANK_FEATURES):
+    return int(load_library().ifmm_rank_model_params(nfeat))
+
+
+def rank_model_eval(theta, X):
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    y = np.zeros(X.shape[0], dtype=np.float32)
+    _check(load_library().ifmm_rank_model_eval(_ptr(th), X.shape[1], _ptr(X), X.shape[0], _ptr(y)))
+    return y
+
+
+def rank_model_grad(theta, X, t, tau):
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    tt = np.ascontiguousarray(t, dtype=np.float32)
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    g = np.zeros_like(th)
+    L = C.c_double()
+    _check(load_library().ifmm_rank_model_grad(_ptr(th), X.shape[1], _ptr(X), _ptr(tt), X.shape[0], float(tau),
+                                               C.byref(L), _ptr(g)))
+    return L.value, g
+
+
+def rank_model_train(X, t, theta, steps, lr=1e-3, tau=0.9):
+    """Returns (trained theta, loss history)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    tt = np.ascontiguousarray(t, dtype=np.float32)
+    th = np.array(theta, dtype=np.float32, copy=True)
+    hist = np.zeros(max(int(steps), 1))
+    _check(load_library().ifmm_rank_model_train(_ptr(X), _ptr(tt), X.shape[0], X.shape[1], int(steps), float(lr),
+                                                float(tau), _ptr(th), _ptr(hist)))
+    return th, hist[:int(steps)]

@@ -172,3 +172,26 @@ def test_mixed_precision_error_vs_oracle(shape, N, leaf, sigma, eps):
     print(f"mixed error vs oracle {rel:.3e} (fp64 {rel64:.3e})", flush=True)
     assert rel <= 100 * eps
     assert not np.array_equal(x, x64)  # the FP32 path really ran
+
+
+@pytest.mark.parametrize("shape,N,leaf,sigma,eps", [("sphere", 4096, 64, 6, 1e-6), ("ellipsoid", 3000, 32, 3, 1e-6)])
+def test_sketched_recompression(monkeypatch, shape, N, leaf, sigma, eps):
+    # Gram matrices of order >= 64 first try the randomised range finder with
+    # the node's current rank plus oversampling; accepted sketches must give the
+    # same solution quality as the full eigen-decomposition (IFMM_SKETCH=0)
+    monkeypatch.setenv("IFMM_SKETCH_MIN", "64")
+    print(f"case sketch {shape} N={N}", flush=True)
+    pts, dg = _case(shape, N, 1)
+    b = synth.uniform_rhs(N, 2, 101)
+    xo = Oracle(pts, eps=eps, sigma=sigma, diag=dg, leaf_max=leaf).factor().solve(b)
+    h = _gpu(pts, eps, sigma, dg, leaf)
+    st = h.stats()
+    print(f"sketches {st['sketches']} rejected {st['sketches_rejected']} narrow {st['sketches_narrow']}", flush=True)
+    assert st["sketches"] > st["sketches_rejected"]
+    x = h.solve(b)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 10 * eps
+    monkeypatch.setenv("IFMM_SKETCH", "0")
+    h0 = _gpu(pts, eps, sigma, dg, leaf)
+    assert h0.stats()["sketches"] == 0
+    x0 = h0.solve(b)
+    assert np.linalg.norm(x0 - xo) / np.linalg.norm(xo) <= 10 * eps
