@@ -3,10 +3,16 @@
 One step = ifmm_build (host octree, lists, colouring) + ifmm_factor (device
 operators, colour-by-colour elimination, top LU) + ifmm_solve of 8
 right-hand sides, all inputs resident before the timed region (the solve
-takes device pointers).  Workload: the learned-rank configuration's geometry
-at full size - N = 1,048,576 points on the ellipsoid with semi-axes
-(1, 0.7, 0.3) plus 5 % uniform jitter, Laplace kernel, eps = 1e-6, sigma = 3,
-leaves of at most 64 points, Chebyshev 4^3 operators, FP64.
+takes device pointers).  Workload: N = 1,048,576 points on the ellipsoid with
+semi-axes (1, 0.7, 0.3) plus 5 % uniform jitter, Laplace kernel, eps = 1e-6,
+sigma = 3, leaves of at most 64 points, Chebyshev 4^3 operators.
+
+Two forms run on the same GPU: "mixed" (FP32 matrix-core Schur and basis
+products, sketched recompression sized by the trained rank network) gives
+`value`; "fp64" (every step FP64, full eigen-decompositions) is reported
+beside it.  For each form, FGMRES(50) on the Chebyshev 5^3 FMM operator with
+the form's factorisation as right preconditioner gives the iteration count
+at the same tolerance (1e-8).
 
 Prints one JSON line (see the keys below).  `roofline` covers the kernel
 class with the largest device time in the timed steps, timed with HIP events
@@ -69,6 +75,97 @@ def cpu_baseline(eps, sigma, nrhs, N_full, budget_s=25.0):
                       f"N={N}, scaled linearly to N={N_full}; solve {1e3 * ts * scale / nrhs:.1f} ms/RHS"}
 
 
+def run_form(name, pts, dg, args, bt, xt, F, f_dev):
+    """One form of the path: `steps` timed steps (build + factor + solve of the
+    RHS block), then FGMRES(50) to 1e-8 on the FMM operator with this form's
+    factorisation as the right preconditioner (untimed against the metric)."""
+    import numpy as np
+    import torch
+    from paper_1905_10602_amd import IFMM
+    from paper_1905_10602_amd.ifmm import _check, _ptr, load_library
+    N = pts.shape[0]
+    mixed = name != "fp64"
+    os.environ["IFMM_SKETCH"] = "1" if mixed else "0"
+    theta = None
+    if mixed:
+        from paper_1905_10602_amd.rank_model import load
+        theta, _ = load()
+
+    def step():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = IFMM(pts, args.eps, args.sigma, diag=dg, leaf_max=64, precision="mixed" if mixed else "fp64")
+        if theta is not None:
+            h.set_rank_model(theta)
+        t1 = time.perf_counter()
+        h.factor()
+        t2 = time.perf_counter()
+        _check(load_library().ifmm_solve(h._h, _ptr(bt), _ptr(xt), args.nrhs, N, 1))
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        return h, {"build_s": t1 - t0, "factor_s": t2 - t1, "solve_s": t3 - t2, "step_s": t3 - t0}
+
+    for w in range(args.warmup):
+        h, t = step()
+        log(f"{name} warmup {w}: {json.dumps(t)}")
+        h.close()
+    times = []
+    h = None
+    for k in range(args.steps):
+        if h is not None:
+            h.close()
+        torch.cuda.synchronize()
+        h, t = step()
+        torch.cuda.synchronize()
+        times.append(t)
+        log(f"{name} step {k}: {json.dumps(t)}")
+    stats = h.stats()
+    x_first = xt[0].cpu().numpy().copy()
+    # accuracy of the IFMM solve on the FMM operator, and preconditioned FGMRES
+    res = None
+    gm = {}
+    if F is not None:
+        y = F.matvec(xt[0].contiguous())
+        res = float(torch.linalg.norm(y - bt[0]) / torch.linalg.norm(bt[0]))
+        t0 = time.perf_counter()
+        xg, its, rr = F.gmres(f_dev, precond=h, tol=1e-8, restart=50, maxit=200, allow_noconv=True)
+        torch.cuda.synchronize()
+        gm = {"gmres_iters": its, "gmres_relres": rr, "gmres_s": time.perf_counter() - t0}
+        t0 = time.perf_counter()
+        xg0, its0, rr0 = F.gmres(f_dev, precond=None, tol=1e-8, restart=50, maxit=400, allow_noconv=True)
+        torch.cuda.synchronize()
+        gm.update({"gmres_unpreconditioned_iters": its0, "gmres_unpreconditioned_s": time.perf_counter() - t0})
+        del xg, xg0
+    h.close()
+    med = lambda key: statistics.median(t[key] for t in times)
+    out = {"factor_s": med("factor_s"), "solve_ms_per_rhs": med("solve_s") * 1e3 / args.nrhs,
+           "build_s": med("build_s"), "step_s": med("step_s"), "solve_residual_on_fmm": res, **gm,
+           "sketches": stats.get("sketches"), "sketches_rejected": stats.get("sketches_rejected"),
+           "rank_predictions": stats.get("rank_predictions"),
+           "depth": stats.get("depth"), "top_n": stats.get("top_n"), "device_GB": stats.get("device_bytes", 0) / 1e9,
+           "factor_store_GB": stats.get("store_bytes", 0) / 1e9,
+           "levels": [{k2: L[k2] for k2 in ("level", "nodes", "colours", "rank_sum", "rank_max", "n_max", "t_elim")}
+                      for L in stats.get("levels", [])],
+           "kernels_ms": {n: round(k["ms"], 3) for n, k in stats.get("kernels", {}).items()}}
+    return out, stats, x_first
+
+
+def roofline_of(stats):
+    ks = stats.get("kernels", {})
+    if not ks:
+        return None
+    name, k = max(ks.items(), key=lambda kv: kv[1]["ms"])
+    avg_s = k["ms"] / 1e3 / max(k["launches"], 1)
+    if BOUND.get(name) == "hbm":
+        ach = k["bytes"] / max(k["launches"], 1) / avg_s
+        return {"kernel": name, "bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": ach / HBM_PEAK, "traffic": None, "launches": k["launches"], "avg_launch_ms": avg_s * 1e3}
+    ach = k["flops"] / max(k["launches"], 1) / avg_s
+    return {"kernel": name, "bound": "alu", "achieved": ach / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK, "traffic": None, "launches": k["launches"],
+            "avg_launch_ms": avg_s * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +175,8 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--sigma", type=int, default=3)
     ap.add_argument("--nrhs", type=int, default=8)
+    ap.add_argument("--form", choices=("both", "mixed", "fp64"), default="both")
+    ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -89,7 +188,7 @@ def main():
     import numpy as np
     import torch
     import synth
-    from paper_1905_10602_amd import IFMM
+    from paper_1905_10602_amd import FMM
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     N = args.n
     log(f"workload: ellipsoid N={N}")
@@ -97,76 +196,42 @@ def main():
     b = synth.uniform_rhs(N, args.nrhs, 201)
     bt = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()  # (nrhs, N) row-major = (N, nrhs) col-major
     xt = torch.empty_like(bt)
-
-    def step():
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        h = IFMM(pts, args.eps, args.sigma, diag=dg, leaf_max=64)
-        t1 = time.perf_counter()
-        h.factor()
-        t2 = time.perf_counter()
-        from paper_1905_10602_amd.ifmm import load_library, _check, _ptr
-        _check(load_library().ifmm_solve(h._h, _ptr(bt), _ptr(xt), args.nrhs, N, 1))
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        return h, {"build_s": t1 - t0, "factor_s": t2 - t1, "solve_s": t3 - t2, "step_s": t3 - t0}
-
-    for w in range(args.warmup):
-        h, t = step()
-        log(f"warmup {w}: {json.dumps(t)}")
-        del h
-    times = []
-    stats = None
-    torch.cuda.synchronize()
-    for k in range(args.steps):
-        h, t = step()
-        stats = h.stats()
-        times.append(t)
-        log(f"step {k}: {json.dumps(t)}")
-        if k + 1 < args.steps:
-            del h
-    torch.cuda.synchronize()
-    fac = statistics.median(t["factor_s"] for t in times)
-    sol = statistics.median(t["solve_s"] for t in times)
-    stp = statistics.median(t["step_s"] for t in times)
-    # roofline of the kernel class with the largest device time
-    ks = stats.get("kernels", {})
-    dom = max(ks.items(), key=lambda kv: kv[1]["ms"]) if ks else None
-    roof = None
-    if dom:
-        name, k = dom
-        avg_s = k["ms"] / 1e3 / max(k["launches"], 1)
-        if BOUND.get(name) == "hbm":
-            ach = k["bytes"] / max(k["launches"], 1) / avg_s
-            roof = {"kernel": name, "bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK, "traffic": None, "launches": k["launches"], "avg_launch_ms": avg_s * 1e3}
-        else:
-            ach = k["flops"] / max(k["launches"], 1) / avg_s
-            roof = {"kernel": name, "bound": "alu", "achieved": ach / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
-                    "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK, "traffic": None,
-                    "launches": k["launches"], "avg_launch_ms": avg_s * 1e3}
+    F, f_dev = None, None
+    if not args.no_gmres:
+        F = FMM(pts, dg, cheb_order=5, leaf_max=256)  # FMM depth for ~30 points per leaf (not the IFMM's)
+        f_dev = bt[0].contiguous()
+        log(f"FMM matvec operator built: {json.dumps(F.stats())}")
+    forms = {"both": ["mixed", "fp64"], "mixed": ["mixed"], "fp64": ["fp64"]}[args.form]
+    res, stats0, xs = {}, None, {}
+    for fm in forms:
+        log(f"form {fm}")
+        out, st, x0 = run_form(fm, pts, dg, args, bt, xt, F, f_dev)
+        res[fm] = out
+        xs[fm] = x0
+        if stats0 is None:
+            stats0 = st
+    lead = forms[0]
+    R = res[lead]
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         cpu = cpu_baseline(args.eps, args.sigma, args.nrhs, N)
     out = {
-        "metric": METRIC, "value": fac, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": stp * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "metric": METRIC, "value": R["factor_s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": R["step_s"] * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32mfma" if lead == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": f"ellipsoid (1,0.7,0.3) + 5% jitter, N={N}, Laplace 1/(4 pi r), eps={args.eps}, "
-                               f"sigma={args.sigma}, leaf<=64, Chebyshev 4^3, FP64, {args.nrhs} RHS",
+                               f"sigma={args.sigma}, leaf<=64, Chebyshev 4^3, {args.nrhs} RHS; value = "
+                               f"{'mixed-precision learned-rank' if lead == 'mixed' else 'plain FP64'} form",
                    "parallelism": "single GPU"},
-        "factor_s": fac, "solve_ms_per_rhs": sol * 1e3 / args.nrhs, "solve_ms": sol * 1e3,
-        "build_s": statistics.median(t["build_s"] for t in times),
-        "depth": stats.get("depth"), "top_n": stats.get("top_n"), "device_GB": stats.get("device_bytes", 0) / 1e9,
-        "factor_store_GB": stats.get("store_bytes", 0) / 1e9,
-        "levels": [{k2: L[k2] for k2 in ("level", "nodes", "colours", "rank_sum", "rank_max", "n_max", "t_elim")}
-                   for L in stats.get("levels", [])],
-        "kernels_ms": {n: round(k["ms"], 3) for n, k in ks.items()},
-        "sketches": stats.get("sketches"), "sketches_rejected": stats.get("sketches_rejected"),
-        "sketches_narrow": stats.get("sketches_narrow"),
-        "roofline": roof, "cpu_baseline": cpu,
+        "factor_s": R["factor_s"], "solve_ms_per_rhs": R["solve_ms_per_rhs"],
+        "forms": res,
+        "roofline": roofline_of(stats0), "cpu_baseline": cpu,
     }
+    if "mixed" in res and "fp64" in res:
+        out["factor_speedup_mixed_vs_fp64"] = res["fp64"]["factor_s"] / res["mixed"]["factor_s"]
+        xm, x6 = xs["mixed"], xs["fp64"]
+        out["mixed_vs_fp64_solution_rel_diff"] = float(np.linalg.norm(xm - x6) / np.linalg.norm(x6))
     print(json.dumps(out), flush=True)
 
 

@@ -158,6 +158,18 @@ const char* ifmm_last_error(void);
 /* Releases the handle and all its device memory.  NULL is ignored. */
 void ifmm_destroy(ifmm_handle* h);
 
+/* ---- many independent geometries -------------------------------------------
+ * The factorisations (solves) of `count` handles run concurrently: every
+ * handle without a stream of its own gets a library-owned one, and `threads`
+ * host threads (0 = up to 8) drive the colour-by-colour schedules, so the
+ * small per-colour launches of different geometries overlap on the device.
+ * On failure *failed (if not NULL) receives the index of the first failing
+ * handle and its status is returned; other handles may have completed.
+ */
+ifmm_status ifmm_factor_batch(ifmm_handle** hs, int32_t count, int32_t threads, int32_t* failed);
+ifmm_status ifmm_solve_batch(ifmm_handle** hs, int32_t count, const double* const* rhs, double* const* x,
+                             int32_t nrhs, const int64_t* ld, int32_t on_device, int32_t threads, int32_t* failed);
+
 /* ---- learned recompression rank ---------------------------------------------
  * Sec. 5.1 compresses the fill-in with a randomised SVD, whose width has to
  * be chosen.  Here every recompression whose Gram matrix has order >= 128

@@ -6,6 +6,10 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <atomic>
+#include <functional>
+#include <thread>
+#include <vector>
 
 #include "../../include/ifmm.h"
 #include "engine.hpp"
@@ -240,6 +244,73 @@ ifmm_status ifmm_ranks(const ifmm_handle* H, int32_t level, int32_t* ranks) {
   if (level < 2 || level > h.tree.depth) return fail(IFMM_EINVAL, "level out of range");
   std::memcpy(ranks, h.lv[level].r.data(), h.lv[level].r.size() * 4);
   return IFMM_OK;
+}
+
+// Many independent handles at once: each gets a stream of its own (a
+// library-owned one if it has none) and a host thread drives its
+// colour-by-colour schedule, so the small per-colour launches of different
+// geometries overlap on the device.
+static ifmm_status run_batch(ifmm_handle** hs, int32_t count, int32_t threads,
+                             const std::function<int(ifmm_handle*, int32_t, std::string&)>& work, int32_t* failed) {
+  ifmm::set_error("");
+  if (!hs || count < 1) return fail(IFMM_EINVAL, "bad arguments");
+  for (int32_t g = 0; g < count; ++g) {
+    if (!hs[g]) return fail(IFMM_EINVAL, "NULL handle in the batch");
+    for (int32_t q = 0; q < g; ++q)
+      if (hs[q] == hs[g]) return fail(IFMM_EINVAL, "a handle appears twice in the batch");
+  }
+  for (int32_t g = 0; g < count; ++g) {
+    ifmm::Handle& h = hs[g]->h;
+    if (!h.stream && !h.batch_stream) {
+      if (hipStreamCreateWithFlags(&h.batch_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(IFMM_EDEVICE, "stream creation failed");
+    }
+    if (!h.stream) h.stream = h.batch_stream;
+  }
+  const int nt = std::max(1, std::min<int>(threads > 0 ? threads : 8, count));
+  std::vector<int> rcs(count, 0);
+  std::vector<std::string> errs(count);
+  std::vector<std::thread> pool;
+  std::atomic<int> next{0};
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&]() {
+      for (int g = next++; g < count; g = next++) {
+        try {
+          rcs[g] = work(hs[g], g, errs[g]);
+        } catch (const std::bad_alloc&) {
+          rcs[g] = IFMM_ENOMEM;
+          errs[g] = "host allocation failed";
+        }
+      }
+    });
+  for (auto& th : pool) th.join();
+  for (int32_t g = 0; g < count; ++g)
+    if (rcs[g]) {
+      if (failed) *failed = g;
+      return fail(rcs[g], "geometry " + std::to_string(g) + ": " + errs[g]);
+    }
+  if (failed) *failed = -1;
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_factor_batch(ifmm_handle** hs, int32_t count, int32_t threads, int32_t* failed) {
+  return run_batch(hs, count, threads, [](ifmm_handle* H, int32_t, std::string& e) { return ifmm::factor(H->h, e); },
+                   failed);
+}
+
+ifmm_status ifmm_solve_batch(ifmm_handle** hs, int32_t count, const double* const* rhs, double* const* x,
+                             int32_t nrhs, const int64_t* ld, int32_t on_device, int32_t threads, int32_t* failed) {
+  if (!hs || !rhs || !x || !ld || nrhs < 1 || count < 1) return fail(IFMM_EINVAL, "bad arguments");
+  for (int32_t g = 0; g < count; ++g) {
+    if (!hs[g] || !hs[g]->h.factored) return fail(IFMM_ESTATE, "a handle of the batch is not factored");
+    if (!rhs[g] || !x[g] || ld[g] < hs[g]->h.N) return fail(IFMM_EINVAL, "bad vectors in the batch");
+  }
+  return run_batch(
+      hs, count, threads,
+      [&](ifmm_handle* H, int32_t g, std::string& e) {
+        return ifmm::solve(H->h, rhs[g], x[g], nrhs, ld[g], on_device ? 1 : 0, e);
+      },
+      failed);
 }
 
 ifmm_status ifmm_set_rank_model(ifmm_handle* H, const float* theta, int32_t nfeat) {

@@ -604,7 +604,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     }
     R.M = off;
     R.far_base = (int)far_idx.size();
-    x_off[k] = stake((int64_t)R.d * (R.M + R.r));
+    R.inv = R.d >= h.big_d ? 1 : 0;  // blocked path: X also carries the x-columns of D^-1
+    x_off[k] = stake((int64_t)R.d * (R.M + R.r + (R.inv ? R.n : 0)));
     // persistent factor data
     int rc;
     double* p;
@@ -733,11 +734,12 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   std::vector<int32_t> blu_rec;
   int blu_dmax = 0, blu_wmax = 0;
   for (int k = 0; k < nrec; ++k)
-    if (recs[k].d >= h.big_d) {
-      blu.push_back({recs[k].lu, recs[k].X, recs[k].piv, nullptr, recs[k].d, recs[k].M + recs[k].r});
+    if (recs[k].inv) {
+      const int W = recs[k].M + recs[k].r + recs[k].n;
+      blu.push_back({recs[k].lu, recs[k].X, recs[k].piv, nullptr, recs[k].d, W});
       blu_rec.push_back(k);
       blu_dmax = std::max(blu_dmax, recs[k].d);
-      blu_wmax = std::max(blu_wmax, recs[k].M + recs[k].r);
+      blu_wmax = std::max(blu_wmax, W);
     }
   const size_t o_info = o_xt + al(std::max<size_t>(xtasks.size(), 1) * sizeof(XTask));
   const size_t o_blu = o_info + al((size_t)nrec * 4);
@@ -811,7 +813,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     const int32_t* d_blur = (const int32_t*)(M + o_blur);
     const unsigned nb = (unsigned)blu.size();
     double fl_blu = 0;
-    for (const BluTask& b : blu) fl_blu += 2.0 / 3.0 * b.d * (double)b.d * b.d + 2.0 * (double)b.d * b.d * b.W;
+    for (const BluTask& b : blu) fl_blu += 2.0 / 3.0 * b.d * (double)b.d * b.d + 2.0 * (double)b.d * b.d * b.W;  // LU + both triangular solves
     ProfScope ps(h, "k_blu", fl_blu, 0);
     const unsigned wch = (unsigned)std::max(1, (blu_wmax + 63) / 64);
     hipLaunchKernelGGL(k_blu_xinit, dim3(wch, nb), dim3(NT), 0, h.stream, d_blu, d_recs, d_blur);
@@ -833,6 +835,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       if (j0 > 0)
         hipLaunchKernelGGL(k_bu_gemm, dim3((unsigned)((j0 + 63) / 64), wch, nb), dim3(NT), 0, h.stream, d_blu, st);
     }
+    hipLaunchKernelGGL(k_blu_store_inv, dim3((unsigned)((blu_dmax + 63) / 64), nb), dim3(NT), 0, h.stream, d_blu,
+                       d_recs, d_blur);
   }
   if (!xtasks.empty()) {
     ProfScope ps(h, "k_xsolve", fl_x, 0);
@@ -1299,6 +1303,15 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   }
   L.nbrs.insert(L.nbrs.end(), nbrs.begin(), nbrs.end());
   L.col_ptr.push_back((int32_t)L.recs.size());
+  ColourInv ci;
+  for (const ElimRec& R : recs)
+    if (R.inv) {
+      ++ci.count;
+      ci.dmax = std::max(ci.dmax, R.d);
+      ci.nmax = std::max(ci.nmax, R.n);
+      ci.Mmax = std::max(ci.Mmax, R.M);
+    }
+  L.cinv.push_back(ci);
   h.stat_far += (int64_t)far.size();
   h.stat_changed += nchg;
   // the host tables above are uploaded asynchronously: wait before they go away
@@ -1379,7 +1392,9 @@ static int finish_level(Handle& h, int l, std::string& err) {
   return 0;
 }
 
+static void release_graph(Handle& h);
 static void clear_factor(Handle& h) {
+  release_graph(h);
   for (size_t l = 0; l < h.lv.size(); ++l) {
     release_level_work(h, (int)l);
     DevLevel& L = h.lv[l];
@@ -1416,6 +1431,7 @@ int factor(Handle& h, std::string& err) {
   }
   h.prof = std::getenv("IFMM_PROF") != nullptr;
   h.il_tight = std::getenv("IFMM_IL_TIGHT") != nullptr;
+  if (const char* e = std::getenv("IFMM_GRAPH")) h.graph_solve = std::atoi(e) != 0;
   if (const char* e = std::getenv("IFMM_BIG_D")) h.big_d = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("IFMM_SKETCH")) h.sketch = std::atoi(e) != 0;
   h.prof_level = std::getenv("IFMM_PROF_LEVEL") != nullptr;
@@ -1438,6 +1454,7 @@ int factor(Handle& h, std::string& err) {
     const Level& T = h.tree.levels[l];
     DevLevel& L = h.lv[l];
     L.col_ptr.assign(1, 0);
+    L.cinv.clear();
     ta = now_s();
     h.cur_level = l;
     for (int c = 0; c < T.ncolour; ++c)
@@ -1506,6 +1523,19 @@ int factor(Handle& h, std::string& err) {
 }
 
 // ------------------------------------------------------------------ solve
+// Fill kernel (graph-safe replacement of a memset)
+__global__ void k_zero(double* p, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) p[e] = 0.0;
+}
+
+static void release_graph(Handle& h) {
+  if (h.g_exec) (void)hipGraphExecDestroy(h.g_exec);
+  if (h.g_graph) (void)hipGraphDestroy(h.g_graph);
+  h.g_exec = nullptr;
+  h.g_graph = nullptr;
+  h.g_key_k = -1;
+}
+
 int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_device, std::string& err) {
   if (!h.factored) {
     err = "ifmm_solve called before ifmm_factor";
@@ -1527,11 +1557,12 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
   const int64_t otop = tot;
   tot += 2 * (int64_t)std::max(h.top_n, 1) * k + 32;
   const int64_t oio = tot;
-  if (!on_device) tot += 2 * ld * k + 32;
+  tot += 2 * ld * k + 32;  // staging of host vectors (used when on_device == 0)
   int rc;
+  double* before = h.svec;
   if ((rc = ensure(h, (void**)&h.svec, &h.svec_bytes, tot * 8, err))) return rc;
+  if (h.svec != before) release_graph(h);  // the captured graph refers to the old buffer
   double* B = h.svec;
-  HIPCHK(hipMemsetAsync(B, 0, (size_t)otop * 8, h.stream));
   const double* d_rhs = rhs;
   double* d_x = x;
   if (!on_device) {
@@ -1546,66 +1577,120 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
     S.xo = h.lv[l].d_vx_off; S.zo = h.lv[l].d_vz_off; S.k = k;
     return S;
   };
-  const Level& TL = h.tree.levels[D];
-  hipLaunchKernelGGL(k_perm_in, dim3(TL.n), dim3(NT), 0, h.stream, d_rhs, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
-                     sv(D));
-  for (int l = D; l >= 2; --l) {
-    const DevLevel& L = h.lv[l];
-    SolveView S = sv(l);
-    for (size_t c = 0; c + 1 < L.col_ptr.size(); ++c) {
-      const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
-      if (b > a) {
-        double by = 0;
-        if (h.prof)
-          for (int e = a; e < b; ++e) {
-            const ElimRec& R = L.recs[e];
-            by += 8.0 * ((double)R.d * R.d + (double)R.M * R.n + k * (2.0 * R.n + 2.0 * R.M + 2.0 * R.d));
+  // the substitution as one stream of launches (captured once per (k, ld, rhs, x) into a HIP graph)
+  auto enqueue = [&]() {
+    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(NT), 0, h.stream, B, otop);
+    const Level& TL = h.tree.levels[D];
+    hipLaunchKernelGGL(k_perm_in, dim3(TL.n), dim3(NT), 0, h.stream, d_rhs, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
+                       sv(D));
+    for (int l = D; l >= 2; --l) {
+      const DevLevel& L = h.lv[l];
+      SolveView S = sv(l);
+      for (size_t c = 0; c + 1 < L.col_ptr.size(); ++c) {
+        const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
+        if (b > a) {
+          double by = 0;
+          if (h.prof)
+            for (int e = a; e < b; ++e) {
+              const ElimRec& R = L.recs[e];
+              by += 8.0 * ((double)R.d * R.d + (double)R.M * R.n + k * (2.0 * R.n + 2.0 * R.M + 2.0 * R.d));
+            }
+          ProfScope ps(h, "k_fwd", 0, by);
+          hipLaunchKernelGGL(k_fwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S, L.d_r);
+          const ColourInv& ci = L.cinv[c];
+          if (ci.count) {
+            hipLaunchKernelGGL(k_fwd_inv_w, dim3((unsigned)((ci.dmax + 63) / 64), b - a), dim3(NT), 0, h.stream,
+                               L.d_recs + a, S);
+            hipLaunchKernelGGL(k_fwd_inv_upd, dim3((unsigned)((ci.Mmax + 63) / 64 + 1), b - a), dim3(NT), 0, h.stream,
+                               L.d_recs + a, L.d_nbrs, S);
           }
-        ProfScope ps(h, "k_fwd", 0, by);
-        hipLaunchKernelGGL(k_fwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S, L.d_r);
+        }
+      }
+      if (l > 2) {
+        const DevLevel& P = h.lv[l - 1];
+        hipLaunchKernelGGL(k_vec_up, dim3(P.nn), dim3(NT), 0, h.stream, S, sv(l - 1), P.d_child_ptr, P.d_child, L.d_r,
+                           P.d_n);
       }
     }
-    if (l > 2) {
-      const DevLevel& P = h.lv[l - 1];
-      hipLaunchKernelGGL(k_vec_up, dim3(P.nn), dim3(NT), 0, h.stream, S, sv(l - 1), P.d_child_ptr, P.d_child, L.d_r,
-                         P.d_n);
+    if (h.top_n > 0) {
+      const int n = h.top_n;
+      double* f = B + otop;
+      double* y = f + (int64_t)n * k;
+      hipLaunchKernelGGL(k_top_gather, dim3(h.lv[2].nn), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r,
+                         h.d_top_off, f, n);
+      hipLaunchKernelGGL(k_gemm_tiles, dim3((n + 63) / 64, (k + 63) / 64), dim3(NT), 0, h.stream, n, k, n, 1.0,
+                         h.d_top_inv, n, f, n, 0.0, y, n);
+      hipLaunchKernelGGL(k_top_scatter, dim3(h.lv[2].nn), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r,
+                         h.d_top_off, y, n);
     }
-  }
-  if (h.top_n > 0) {
-    const int n = h.top_n;
-    double* f = B + otop;
-    double* y = f + (int64_t)n * k;
-    hipLaunchKernelGGL(k_top_gather, dim3(h.lv[2].nn), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r,
-                       h.d_top_off, f, n);
-    hipLaunchKernelGGL(k_gemm_tiles, dim3((n + 63) / 64, (k + 63) / 64), dim3(NT), 0, h.stream, n, k, n, 1.0,
-                       h.d_top_inv, n, f, n, 0.0, y, n);
-    hipLaunchKernelGGL(k_top_scatter, dim3(h.lv[2].nn), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r,
-                       h.d_top_off, y, n);
-  }
-  for (int l = 2; l <= D; ++l) {
-    const DevLevel& L = h.lv[l];
-    SolveView S = sv(l);
-    if (l > 2) {
-      const DevLevel& P = h.lv[l - 1];
-      hipLaunchKernelGGL(k_vec_down, dim3(P.nn), dim3(NT), 0, h.stream, S, sv(l - 1), P.d_child_ptr, P.d_child, L.d_r,
-                         P.d_n);
-    }
-    for (int c = (int)L.col_ptr.size() - 2; c >= 0; --c) {
-      const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
-      if (b > a) {
-        double by = 0;
-        if (h.prof)
-          for (int e = a; e < b; ++e) {
-            const ElimRec& R = L.recs[e];
-            by += 8.0 * ((double)R.d * R.d + (double)R.M * R.n + k * (2.0 * R.n + 2.0 * R.M + 3.0 * R.d));
+    for (int l = 2; l <= D; ++l) {
+      const DevLevel& L = h.lv[l];
+      SolveView S = sv(l);
+      if (l > 2) {
+        const DevLevel& P = h.lv[l - 1];
+        hipLaunchKernelGGL(k_vec_down, dim3(P.nn), dim3(NT), 0, h.stream, S, sv(l - 1), P.d_child_ptr, P.d_child, L.d_r,
+                           P.d_n);
+      }
+      for (int c = (int)L.col_ptr.size() - 2; c >= 0; --c) {
+        const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
+        if (b > a) {
+          double by = 0;
+          if (h.prof)
+            for (int e = a; e < b; ++e) {
+              const ElimRec& R = L.recs[e];
+              by += 8.0 * ((double)R.d * R.d + (double)R.M * R.n + k * (2.0 * R.n + 2.0 * R.M + 3.0 * R.d));
+            }
+          ProfScope ps(h, "k_bwd", 0, by);
+          hipLaunchKernelGGL(k_bwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S);
+          const ColourInv& ci = L.cinv[c];
+          if (ci.count) {
+            hipLaunchKernelGGL(k_bwd_inv_t, dim3((unsigned)((ci.nmax + 63) / 64 + 1), b - a), dim3(NT), 0, h.stream,
+                               L.d_recs + a, L.d_nbrs, S);
+            hipLaunchKernelGGL(k_bwd_inv_x, dim3((unsigned)((ci.nmax + 63) / 64), b - a), dim3(NT), 0, h.stream,
+                               L.d_recs + a, S);
           }
-        ProfScope ps(h, "k_bwd", 0, by);
-        hipLaunchKernelGGL(k_bwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S);
+        }
       }
     }
+    hipLaunchKernelGGL(k_perm_out, dim3(TL.n), dim3(NT), 0, h.stream, d_x, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
+                       sv(D));
+  };
+  const bool use_graph = h.graph_solve;
+  if (!use_graph) {
+    enqueue();
+  } else {
+    const bool hit = h.g_exec && h.g_key_k == k && h.g_key_ld == ld && h.g_key_rhs == d_rhs && h.g_key_x == d_x;
+    if (!hit) {
+      release_graph(h);
+      if (!h.cap_stream) HIPCHK(hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking));
+      HIPCHK(hipStreamSynchronize(h.stream));
+      hipStream_t keep = h.stream;
+      const bool prof = h.prof;
+      h.stream = h.cap_stream;
+      h.prof = false;  // no timing events inside the graph
+      hipError_t e = hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        enqueue();
+        e = hipStreamEndCapture(h.stream, &h.g_graph);
+      }
+      h.stream = keep;
+      h.prof = prof;
+      if (e == hipSuccess) e = hipGraphInstantiate(&h.g_exec, h.g_graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        release_graph(h);
+        err = std::string("capturing the solve into a HIP graph failed: ") + hipGetErrorString(e);
+        return -3;
+      }
+      h.g_key_k = k;
+      h.g_key_ld = ld;
+      h.g_key_rhs = d_rhs;
+      h.g_key_x = d_x;
+    }
+    {
+      ProfScope ps(h, "solve_graph", 0, 0);
+      HIPCHK(hipGraphLaunch(h.g_exec, h.stream));
+    }
   }
-  hipLaunchKernelGGL(k_perm_out, dim3(TL.n), dim3(NT), 0, h.stream, d_x, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
-                     sv(D));
   HIPCHK(hipGetLastError());
   if (!on_device) HIPCHK(hipMemcpyAsync(x, d_x, (size_t)ld * k * 8, hipMemcpyDeviceToHost, h.stream));
   HIPCHK(hipStreamSynchronize(h.stream));
@@ -1694,6 +1779,13 @@ void release(Handle& h) {
   h.pending.clear();
   for (hipEvent_t e : h.event_pool) (void)hipEventDestroy(e);
   h.event_pool.clear();
+  if (h.cap_stream) (void)hipStreamDestroy(h.cap_stream);
+  h.cap_stream = nullptr;
+  if (h.batch_stream) {
+    if (h.stream == h.batch_stream) h.stream = nullptr;
+    (void)hipStreamDestroy(h.batch_stream);
+  }
+  h.batch_stream = nullptr;
   h.dev_bytes = 0;
   h.dev_ready = false;
 }

@@ -21,8 +21,8 @@ namespace ifmm {
 struct ElimRec {
   int32_t node, n, r, d;   // node index, |x_i|, rank, d = n + r
   int32_t nnb, nb_begin;   // neighbour entries [nb_begin, nb_begin + nnb) of the ElimNbr table
-  int32_t M, pad0;         // total rows of L-blocks (== total columns of U-blocks)
-  double* lu;              // d x d, ld d
+  int32_t M, inv;          // total rows of L-blocks (== total columns of U-blocks); inv: lu holds D^-1
+  double* lu;              // d x d, ld d: LU factors with piv, or the explicit inverse (inv = 1)
   int32_t* piv;            // d
   double* L;               // M x n, ld M
   double* U;               // n x M, ld n
@@ -68,6 +68,10 @@ struct Changed {
   double* tmp;              // workspace (max(rc, n) x max(rc, n) of the level)
 };
 
+struct ColourInv {
+  int32_t count = 0, dmax = 0, nmax = 0, Mmax = 0;
+};
+
 struct DevLevel {
   int32_t nn = 0, rcmax = 0, nmax = 0;
   // host mirrors
@@ -98,6 +102,7 @@ struct DevLevel {
   std::vector<ElimRec> recs;   // elimination order
   std::vector<ElimNbr> nbrs;
   std::vector<int32_t> col_ptr;  // recs of colour c: [col_ptr[c], col_ptr[c + 1])
+  std::vector<ColourInv> cinv;   // per colour: records solved with an explicit inverse
   ElimRec* d_recs = nullptr;
   ElimNbr* d_nbrs = nullptr;
   int64_t wv_total = 0;
@@ -182,6 +187,16 @@ struct Handle {
   std::vector<float> rec_X, rec_t;                   // features (14 per row) and r_new / n
   std::vector<std::vector<int64_t>> pt_count;        // points in each node's box, per level
   int64_t stat_predicted = 0;
+  // solve captured into a HIP graph, replayed while (nrhs, ld, rhs, x) repeat (IFMM_GRAPH=0 disables)
+  bool graph_solve = true;
+  hipStream_t batch_stream = nullptr;  // library-owned stream given by the batch calls
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t g_graph = nullptr;
+  hipGraphExec_t g_exec = nullptr;
+  int g_key_k = -1;
+  int64_t g_key_ld = 0;
+  const double* g_key_rhs = nullptr;
+  double* g_key_x = nullptr;
   int big_d = 256;          // pivots of at least this order take the blocked multi-workgroup path (IFMM_BIG_D)
   bool il_tight = false;    // IFMM_IL_TIGHT set: no capacity headroom for M2L blocks (tests the growth path)
   struct KStat {

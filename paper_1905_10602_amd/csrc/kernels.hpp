@@ -626,13 +626,29 @@ __global__ void k_blu_xinit(const BluTask* tasks, const ElimRec* recs, const int
   const int nc = min(64, t.W - c0);
   if (threadIdx.x == 0 && blockIdx.x == 0) *t.info = 0;
   if (nc <= 0 || t.d == 0) return;
-  const int n = R.n, M = R.M;
+  const int n = R.n, M = R.M, r = R.r;
   WG_FOR2(t.d, nc, row, cl) {
     const int col = c0 + cl;
     double v;
     if (col < M) v = row < n ? R.U[row + (int64_t)col * n] : 0.0;
-    else v = (row >= n && row - n == col - M) ? 1.0 : 0.0;
+    else if (col < M + r) v = (row >= n && row - n == col - M) ? 1.0 : 0.0;
+    else v = (row == col - M - r) ? 1.0 : 0.0;  // [I_n; 0]: the x-columns of D^-1
     t.X[row + (int64_t)col * t.d] = v;
+  }
+}
+
+// After the solve, D^-1 = [X[:, M+r : M+r+n], X[:, M : M+r]] replaces the LU
+// factors (the solve of a large pivot multiplies by the explicit inverse).
+__global__ void k_blu_store_inv(const BluTask* tasks, const ElimRec* recs, const int32_t* rec_of) {
+  const BluTask t = tasks[blockIdx.y];
+  const ElimRec R = recs[rec_of[blockIdx.y]];
+  const int c0 = blockIdx.x * 64, d = t.d;
+  const int nc = min(64, d - c0);
+  if (nc <= 0) return;
+  WG_FOR2(d, nc, row, cl) {
+    const int c = c0 + cl;
+    const int src = c < R.n ? R.M + R.r + c : R.M + (c - R.n);
+    t.lu[row + (int64_t)c * d] = t.X[row + (int64_t)src * d];
   }
 }
 
@@ -1299,6 +1315,7 @@ __global__ void k_perm_out(double* x, int64_t ld, int k, const int64_t* perm, co
 //   w = D^-1 [x_i; 0];  rows of neighbour p -= L_p w_top;  z_i += w_bot.
 __global__ void k_fwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S, const int32_t* rnow) {
   const ElimRec R = recs[blockIdx.x];
+  if (R.inv) return;  // explicit-inverse path
   const int n = R.n, r = R.r, d = R.d, k = S.k;
   double* w = S.W + R.wv * k;
   const double* xi = S.X + S.xo[R.node] * k;
@@ -1324,6 +1341,7 @@ __global__ void k_fwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S, con
 //   [x_i; z_i] = w - D^-1 [sum_q U_q x_q; -y_i]
 __global__ void k_bwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
   const ElimRec R = recs[blockIdx.x];
+  if (R.inv) return;  // explicit-inverse path
   const int n = R.n, r = R.r, d = R.d, k = S.k;
   if (d == 0) return;
   double* t = S.tmp + R.wv * k;
@@ -1343,6 +1361,79 @@ __global__ void k_bwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
   if (n > 0) WG_FOR2(n, k, a, c) {
     xi[a + (int64_t)c * n] = w[a + (int64_t)c * d] - t[a + (int64_t)c * d];
   }
+}
+
+// Large pivots with an explicit inverse: the substitution steps of one node
+// spread over many workgroups (64-row tiles), grid (tiles, records of the colour).
+//   forward:  w = D^-1[:, 0:n] x_i;  rows of neighbour p -= L_p w_top;  z_i += w_bot
+//   backward: t = [sum_q U_q x_q; -y_i];  x_i = w_top - D^-1[0:n, :] t
+__global__ void k_fwd_inv_w(const ElimRec* recs, SolveView S) {
+  const ElimRec R = recs[blockIdx.y];
+  if (!R.inv) return;
+  const int r0 = blockIdx.x * 64, k = S.k;
+  if (r0 >= R.d || R.n == 0) return;
+  double* w = S.W + R.wv * k;
+  const double* xi = S.X + S.xo[R.node] * k;
+  wg_gemm(min(64, R.d - r0), k, R.n, 1.0, R.lu + r0, R.d, false, xi, R.n, false, 0.0, w + r0, R.d);
+}
+
+__global__ void k_fwd_inv_upd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
+  const ElimRec R = recs[blockIdx.y];
+  if (!R.inv) return;
+  const int k = S.k, n = R.n, d = R.d;
+  const int ntile = (R.M + 63) / 64;
+  const double* w = S.W + R.wv * k;
+  if ((int)blockIdx.x == ntile) {  // z_i += w_bot
+    double* zi = S.Z + S.zo[R.node] * k;
+    if (R.r > 0) WG_FOR2(R.r, k, a, c) { zi[a + (int64_t)c * R.r] += w[n + a + (int64_t)c * d]; }
+    return;
+  }
+  if ((int)blockIdx.x > ntile || n == 0) return;
+  const int t0 = blockIdx.x * 64, t1 = min(R.M, t0 + 64);
+  for (int e = 0; e < R.nnb; ++e) {
+    const ElimNbr B = nbrs[R.nb_begin + e];
+    const int a = max(t0, B.off), b = min(t1, B.off + B.m);
+    if (a >= b) continue;
+    double* tgt = B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k;
+    wg_gemm(b - a, k, n, -1.0, R.L + a, R.M, false, w, d, false, 1.0, tgt + (a - B.off), B.m);
+  }
+}
+
+__global__ void k_bwd_inv_t(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
+  const ElimRec R = recs[blockIdx.y];
+  if (!R.inv) return;
+  const int k = S.k, n = R.n, d = R.d;
+  const int ntile = (n + 63) / 64;
+  double* t = S.tmp + R.wv * k;
+  if ((int)blockIdx.x == ntile) {  // t_bot = -y_i
+    const double* yi = S.Z + S.zo[R.node] * k;
+    if (R.r > 0) WG_FOR2(R.r, k, a, c) { t[n + a + (int64_t)c * d] = -yi[a + (int64_t)c * R.r]; }
+    return;
+  }
+  if ((int)blockIdx.x > ntile) return;
+  const int r0 = blockIdx.x * 64, mr = min(64, n - r0);
+  wg_fill(mr, k, t + r0, d, 0.0);
+  for (int e = 0; e < R.nnb; ++e) {
+    const ElimNbr B = nbrs[R.nb_begin + e];
+    if (B.m == 0) continue;
+    const double* xq = B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k;
+    wg_gemm(mr, k, B.m, 1.0, R.U + r0 + (int64_t)B.off * n, n, false, xq, B.m, false, 1.0, t + r0, d);
+  }
+}
+
+__global__ void k_bwd_inv_x(const ElimRec* recs, SolveView S) {
+  const ElimRec R = recs[blockIdx.y];
+  if (!R.inv) return;
+  const int k = S.k, n = R.n, d = R.d;
+  const int r0 = blockIdx.x * 64;
+  if (r0 >= n) return;
+  const int mr = min(64, n - r0);
+  const double* w = S.W + R.wv * k;
+  const double* t = S.tmp + R.wv * k;
+  double* xi = S.X + S.xo[R.node] * k;
+  WG_FOR2(mr, k, a, c) { xi[r0 + a + (int64_t)c * n] = w[r0 + a + (int64_t)c * d]; }
+  __syncthreads();
+  wg_gemm(mr, k, d, -1.0, R.lu + r0, d, false, t, d, false, 1.0, xi + r0, n);
 }
 
 // Level change of the node vectors: x_P = [z_c ...] (up) / y_c = slices of x_P (down).

@@ -68,6 +68,8 @@ def load_library():
         "ifmm_set_rank_model": (I32, [P, P, I32]),
         "ifmm_record_ranks": (I32, [P, I32]),
         "ifmm_rank_records": (I32, [P, P, P, I64, C.POINTER(I64)]),
+        "ifmm_factor_batch": (I32, [P, I32, I32, C.POINTER(I32)]),
+        "ifmm_solve_batch": (I32, [P, I32, P, P, I32, P, I32, I32, C.POINTER(I32)]),
         "fmm_build": (I32, [P, I64, P, P, D, I32, I32, P, C.POINTER(P)]),
         "fmm_matvec": (I32, [P, P, P, I32]),
         "fmm_gmres": (I32, [P, P, P, D, I32, I32, P, I32, C.POINTER(I32), C.POINTER(D)]),
@@ -354,3 +356,29 @@ def rank_model_train(X, t, theta, steps, lr=1e-3, tau=0.9):
     _check(load_library().ifmm_rank_model_train(_ptr(X), _ptr(tt), X.shape[0], X.shape[1], int(steps), float(lr),
                                                 float(tau), _ptr(th), _ptr(hist)))
     return th, hist[:int(steps)]
+
+
+def factor_batch(handles, threads=0):
+    """ifmm_factor_batch over IFMM handles; returns the handles."""
+    lib = load_library()
+    arr = (C.c_void_p * len(handles))(*[h._h.value for h in handles])
+    failed = C.c_int32(-1)
+    _check(lib.ifmm_factor_batch(C.cast(arr, C.c_void_p), len(handles), int(threads), C.byref(failed)))
+    return handles
+
+
+def solve_batch(handles, rhs, threads=0):
+    """ifmm_solve_batch: rhs is a list of host (N_g, k) arrays (same k); returns the solutions."""
+    lib = load_library()
+    G = len(handles)
+    Bs = [np.asfortranarray(np.asarray(b, dtype=np.float64).reshape(h.N, -1)) for h, b in zip(handles, rhs)]
+    k = Bs[0].shape[1]
+    Xs = [np.empty_like(b, order="F") for b in Bs]
+    hp = (C.c_void_p * G)(*[h._h.value for h in handles])
+    rp = (C.c_void_p * G)(*[b.ctypes.data for b in Bs])
+    xp = (C.c_void_p * G)(*[x.ctypes.data for x in Xs])
+    ld = (C.c_int64 * G)(*[h.N for h in handles])
+    failed = C.c_int32(-1)
+    _check(lib.ifmm_solve_batch(C.cast(hp, C.c_void_p), G, C.cast(rp, C.c_void_p), C.cast(xp, C.c_void_p), k,
+                                C.cast(ld, C.c_void_p), 0, int(threads), C.byref(failed)))
+    return Xs

@@ -195,3 +195,62 @@ def test_sketched_recompression(monkeypatch, shape, N, leaf, sigma, eps):
     assert h0.stats()["sketches"] == 0
     x0 = h0.solve(b)
     assert np.linalg.norm(x0 - xo) / np.linalg.norm(xo) <= 10 * eps
+
+
+def test_batched_geometries_match_individual_runs():
+    # many independent geometries factorised and solved concurrently (one
+    # stream and host thread each): bitwise the results of separate runs
+    from paper_1905_10602_amd import factor_batch, solve_batch
+    geoms = synth.batch_geometries(6, 4000, nmin=1500, nmax=4000)
+    eps = 1e-4
+    hs, refs, rhs = [], [], []
+    for g, (shape, pts) in enumerate(geoms):
+        dg = synth.laplace_self_term(pts.shape[0], 4 * np.pi)
+        hs.append(_gpu_unfactored(pts, eps, 3, dg, 32))
+        refs.append(_gpu(pts, eps, 3, dg, 32))
+        rhs.append(synth.uniform_rhs(pts.shape[0], 4, 300 + g))
+    factor_batch(hs, threads=4)
+    xs = solve_batch(hs, rhs, threads=4)
+    for h, r, b, x in zip(hs, refs, rhs, xs):
+        assert np.array_equal(x, r.solve(b))
+        assert np.array_equal(h.solve(b), x)
+    # one of them against the oracle
+    shape, pts = geoms[0]
+    dg = synth.laplace_self_term(pts.shape[0], 4 * np.pi)
+    xo = Oracle(pts, eps=eps, sigma=3, diag=dg, leaf_max=32).factor().solve(rhs[0])
+    assert np.linalg.norm(xs[0] - xo) / np.linalg.norm(xo) <= 10 * eps
+
+
+def _gpu_unfactored(pts, eps, sigma, dg, leaf, **kw):
+    from paper_1905_10602_amd import IFMM
+    return IFMM(pts, eps, sigma, diag=dg, leaf_max=leaf, **kw)
+
+
+def test_graph_captured_solve_replays(monkeypatch):
+    # the solve is captured into a HIP graph and replayed while the vectors
+    # repeat; every replay, with eager work and synchronisations in between,
+    # must equal the eager (uncaptured) solve bitwise
+    import torch
+    N = 3000
+    pts, dg = _case("ellipsoid", N, 4)
+    b = synth.uniform_rhs(N, 3, 9)
+    bt = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    monkeypatch.setenv("IFMM_GRAPH", "0")
+    he = _gpu(pts, 1e-6, 3, dg, 32)
+    ref = he.solve(bt).cpu().numpy()
+    monkeypatch.setenv("IFMM_GRAPH", "1")
+    hg = _gpu(pts, 1e-6, 3, dg, 32)
+    from paper_1905_10602_amd.ifmm import _check, _ptr, load_library
+    Bc = bt.t().contiguous()
+    X = torch.empty_like(Bc)
+    for rep in range(4):
+        _check(load_library().ifmm_solve(hg._h, _ptr(Bc), _ptr(X), 3, N, 1))
+        assert np.array_equal(X.t().cpu().numpy(), ref), rep
+        junk = torch.randn(1000, 1000, device="cuda", dtype=torch.float64) @ torch.randn(1000, 1000, device="cuda",
+                                                                                          dtype=torch.float64)
+        torch.cuda.synchronize()
+        del junk
+    # a different right-hand-side count recaptures; host vectors use the staging buffer
+    x1 = hg.solve(b[:, 0])
+    assert np.array_equal(x1, he.solve(b[:, 0]))
+    assert np.array_equal(hg.solve(b), ref)
