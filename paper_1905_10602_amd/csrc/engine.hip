@@ -546,6 +546,68 @@ static int rank_features(Handle& h, int l, std::vector<Changed>& chg, const std:
   return 0;
 }
 
+// Orthonormalises the range samples of a batch of sketches (BCGS2 over
+// 64-column blocks): per block two passes of C = Q_prev^T Y_blk,
+// Y_blk -= Q_prev C as batched GEMMs, then the in-block Gram-Schmidt.
+static int sk_orthonormalise(Handle& h, const std::vector<SkTask>& T, const SkTask* d_T, double drop,
+                             std::string& err) {
+  const size_t nt = T.size();
+  if (!nt) return 0;
+  int smax = 1, nmax = 1;
+  for (const SkTask& t : T) {
+    smax = std::max(smax, t.s);
+    nmax = std::max(nmax, t.n);
+  }
+  const int nblk = (smax + 63) / 64;
+  const int ldn0 = smax;
+  int64_t cdoubles = 0;
+  for (const SkTask& t : T) cdoubles += (int64_t)t.s * 64 + 64;
+  const size_t gtab = ((size_t)nblk * 4 * nt * sizeof(GemmTask) + 255) & ~(size_t)255;
+  const int64_t bytes = (int64_t)gtab + (cdoubles + (int64_t)nt * ldn0 + 64) * 8;
+  int rc;
+  if ((rc = ensure(h, (void**)&h.orthbuf, &h.orthbuf_bytes, bytes, err))) return rc;
+  GemmTask* d_g = (GemmTask*)h.orthbuf;
+  double* Cb = (double*)((char*)h.orthbuf + gtab);
+  double* n0 = Cb + cdoubles;
+  std::vector<double*> cptr(nt);
+  int64_t o = 0;
+  for (size_t a = 0; a < nt; ++a) {
+    cptr[a] = Cb + o;
+    o += (int64_t)T[a].s * 64 + 64;
+  }
+  // tables: for block b, [proj C (nt)] [update Y (nt)], twice (the same tables serve both passes)
+  std::vector<GemmTask> g((size_t)nblk * 2 * nt);
+  for (int b = 0; b < nblk; ++b)
+    for (size_t a = 0; a < nt; ++a) {
+      const SkTask& t = T[a];
+      const int j0 = b * 64;
+      const int bs = j0 < t.s ? std::min(64, t.s - j0) : 0;
+      const int J0 = bs > 0 ? j0 : 0;
+      // C (J0 x bs, ld s) = Y[:, :J0]^T Y[:, j0:j0+bs]
+      g[((size_t)b * 2 + 0) * nt + a] = {t.Y, t.Y + (int64_t)j0 * t.n, cptr[a], J0, bs, t.n, t.n, t.n, t.s, 1, 0, 1.0,
+                                         0.0};
+      // Y[:, j0:j0+bs] -= Y[:, :J0] C
+      g[((size_t)b * 2 + 1) * nt + a] = {t.Y, cptr[a], t.Y + (int64_t)j0 * t.n, t.n, bs, J0, t.n, t.s, t.n, 0, 0, -1.0,
+                                         1.0};
+    }
+  HIPCHK(hipMemcpyAsync(d_g, g.data(), g.size() * sizeof(GemmTask), hipMemcpyHostToDevice, h.stream));
+  hipLaunchKernelGGL(k_sk_colnorm, dim3((unsigned)std::max(1, std::min(64, (smax + 3) / 4)), (unsigned)nt), dim3(NT), 0,
+                     h.stream, d_T, n0, ldn0);
+  for (int b = 0; b < nblk; ++b) {
+    if (b > 0) {
+      const unsigned tj = (unsigned)((b * 64 + 63) / 64), tn = (unsigned)((nmax + 63) / 64);
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_gemm_batch, dim3(tj, 1, (unsigned)nt), dim3(NT), 0, h.stream, d_g + ((size_t)b * 2) * nt);
+        hipLaunchKernelGGL(k_gemm_batch, dim3(tn, 1, (unsigned)nt), dim3(NT), 0, h.stream,
+                           d_g + ((size_t)b * 2 + 1) * nt);
+      }
+    }
+    hipLaunchKernelGGL(k_sk_orth_block, dim3((unsigned)nt), dim3(NT), 0, h.stream, d_T, b * 64, drop, n0, ldn0);
+  }
+  HIPCHK(hipStreamSynchronize(h.stream));  // the host table above is a temporary
+  return 0;
+}
+
 static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   const Level& T = h.tree.levels[l];
   DevLevel& L = h.lv[l];
@@ -980,7 +1042,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
       hipLaunchKernelGGL(k_sk_range, dim3(tn, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_chg, d_refs, d_far, d_nbrs,
                          d_recs, d_skT);
-      hipLaunchKernelGGL(k_sk_orth, dim3((unsigned)nsk), dim3(NT), 0, h.stream, d_skT, drop);
+      if ((rc = sk_orthonormalise(h, skT, d_skT, drop, err))) return rc;
       hipLaunchKernelGGL(k_gemm_batch, dim3(tn, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_gT);
       hipLaunchKernelGGL(k_gemm_batch, dim3(ts, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_gT + nsk);
       hipLaunchKernelGGL(k_sk_trace, dim3((unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
@@ -1022,6 +1084,111 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     }
     h.stat_sketch += (int64_t)nsk;
     h.stat_sketch_rejected += (int64_t)fb.size();
+    // second chance: a rejected sketch is retried once at about twice the width
+    // (still far cheaper than the full decomposition of a large Gram matrix)
+    std::vector<int32_t> r2_ids, r2_w;
+    {
+      std::vector<EigTask> fb_keep;
+      std::vector<int32_t> fbof_keep;
+      for (size_t q = 0; q < fb.size(); ++q) {
+        const int a = fb_of[q], e = sk_ids[a];
+        const int n = chg[e / sides].n;
+        const int s2 = std::min(n, 2 * skw[e] + 16);
+        if (s2 <= (int)(0.8 * n)) {
+          r2_ids.push_back(e);
+          r2_w.push_back(s2);
+        } else {
+          fb_keep.push_back(fb[q]);
+          fbof_keep.push_back(a);
+        }
+      }
+      fb.swap(fb_keep);
+      fb_of.swap(fbof_keep);
+    }
+    std::vector<int32_t> r2_ok;
+    std::vector<SkTask> r2T;
+    std::vector<EigTask> r2E;
+    if (!r2_ids.empty()) {
+      const size_t n2 = r2_ids.size();
+      int64_t need2 = 0;
+      for (size_t q = 0; q < n2; ++q) {
+        const int64_t n = chg[r2_ids[q] / sides].n, sw = r2_w[q];
+        need2 += std::max<int64_t>(wrows[r2_ids[q] / sides], n) * sw + n * sw + 2 * sw * sw + 3 * sw + 64;
+      }
+      const size_t tb2 = (n2 * (sizeof(EigTask) + sizeof(SkTask) + 2 * sizeof(GemmTask) + 8) + 4096 + 255) &
+                         ~(size_t)255;
+      if ((rc = ensure(h, (void**)&h.skbuf2, &h.skbuf2_bytes, (int64_t)tb2 + need2 * 8 + 256, err))) return rc;
+      char* b2 = (char*)h.skbuf2;
+      EigTask* d_E2 = (EigTask*)b2;
+      SkTask* d_T2 = (SkTask*)(d_E2 + n2);
+      GemmTask* d_G2 = (GemmTask*)(d_T2 + n2);
+      int32_t* d_c2 = (int32_t*)(d_G2 + 2 * n2);
+      int32_t* d_o2 = d_c2 + n2;
+      double* V0 = (double*)(b2 + tb2);
+      int64_t o2 = 0;
+      int smax2 = 1, nmax2 = 1;
+      std::vector<GemmTask> g2;
+      for (size_t q = 0; q < n2; ++q) {
+        const int e = r2_ids[q];
+        const Changed& C = chg[e / sides];
+        const int side = e % sides, n = C.n, sw = r2_w[q];
+        SkTask t;
+        t.G = side ? C.gt : C.gs;
+        t.O = V0 + o2; o2 += std::max<int64_t>(wrows[e / sides], n) * sw;
+        t.Y = V0 + o2; o2 += (int64_t)n * sw;
+        t.B = V0 + o2; o2 += (int64_t)sw * sw;
+        double* U = V0 + o2; o2 += (int64_t)sw * sw;
+        double* Wk = V0 + o2; o2 += 3LL * sw;
+        t.tr = V0 + o2; o2 += 64;
+        t.n = n; t.s = sw;
+        t.R = (int32_t)wrows[e / sides];
+        t.chg = e / sides;
+        t.seed = (uint32_t)(C.p * 2 + side + 0x9E37);
+        t.side = (uint32_t)side;
+        r2T.push_back(t);
+        r2E.push_back({t.B, U, Wk, side ? C.lt : C.ls, nullptr, sw, 0});
+        smax2 = std::max(smax2, sw);
+        nmax2 = std::max(nmax2, n);
+      }
+      for (const SkTask& t : r2T) g2.push_back({t.G, t.Y, t.O, t.n, t.s, t.n, t.n, t.n, t.n, 0, 0, 1.0, 0.0});
+      for (const SkTask& t : r2T) g2.push_back({t.Y, t.O, t.B, t.s, t.s, t.n, t.n, t.n, t.s, 1, 0, 1.0, 0.0});
+      HIPCHK(hipMemcpyAsync(d_E2, r2E.data(), n2 * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
+      HIPCHK(hipMemcpyAsync(d_T2, r2T.data(), n2 * sizeof(SkTask), hipMemcpyHostToDevice, h.stream));
+      HIPCHK(hipMemcpyAsync(d_G2, g2.data(), 2 * n2 * sizeof(GemmTask), hipMemcpyHostToDevice, h.stream));
+      {
+        double fl2 = 0;
+        for (const SkTask& t : r2T)
+          fl2 += 2.0 * t.n * (double)t.R * t.s + 2.0 * t.n * (double)t.n * t.s + 6.0 * t.n * (double)t.s * t.s;
+        ProfScope ps(h, "k_sketch", fl2, 0);
+        const unsigned tn = (unsigned)((nmax2 + 63) / 64), ts = (unsigned)((smax2 + 63) / 64);
+        const double drop = std::max(1e-13, std::min(1e-9, 1e-3 * h.eps));
+        hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)n2), dim3(NT), 0, h.stream, d_T2);
+        hipLaunchKernelGGL(k_sk_range, dim3(tn, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_chg, d_refs, d_far, d_nbrs,
+                           d_recs, d_T2);
+        if ((rc = sk_orthonormalise(h, r2T, d_T2, drop, err))) return rc;
+        hipLaunchKernelGGL(k_gemm_batch, dim3(tn, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_G2);
+        hipLaunchKernelGGL(k_gemm_batch, dim3(ts, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_G2 + n2);
+        hipLaunchKernelGGL(k_sk_trace, dim3((unsigned)n2), dim3(NT), 0, h.stream, d_T2);
+        hipLaunchKernelGGL(k_eig_values, dim3((unsigned)n2), dim3(NT), 0, h.stream, d_E2, eps2, d_c2, 0);
+        hipLaunchKernelGGL(k_sk_check, dim3((unsigned)((n2 + NT - 1) / NT)), dim3(NT), 0, h.stream, d_T2, d_E2, d_c2,
+                           eps2, d_o2, (int)n2);
+      }
+      std::vector<int32_t> c2(n2);
+      r2_ok.assign(n2, 0);
+      HIPCHK(hipMemcpyAsync(c2.data(), d_c2, n2 * 4, hipMemcpyDeviceToHost, h.stream));
+      HIPCHK(hipMemcpyAsync(r2_ok.data(), d_o2, n2 * 4, hipMemcpyDeviceToHost, h.stream));
+      HIPCHK(hipStreamSynchronize(h.stream));
+      h.stat_sketch += (int64_t)n2;
+      for (size_t q = 0; q < n2; ++q) {
+        if (r2_ok[q] > 0) {
+          cnt[r2_ids[q]] = c2[q];
+          --h.stat_sketch_rejected;  // recovered by the wider sketch
+        } else {
+          fb.push_back(etasks[r2_ids[q]]);
+          fb_of.push_back(-1 - (int32_t)q);  // marks a second-round task
+        }
+      }
+    }
     if (!fb.empty()) {
       HIPCHK(hipMemcpyAsync(d_fbT, fb.data(), fb.size() * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
       {
@@ -1031,11 +1198,11 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       std::vector<int32_t> cfb(fb.size());
       HIPCHK(hipMemcpyAsync(cfb.data(), d_cfb, fb.size() * 4, hipMemcpyDeviceToHost, h.stream));
       HIPCHK(hipStreamSynchronize(h.stream));
-      for (size_t a = 0; a < fb.size(); ++a) cnt[sk_ids[fb_of[a]]] = cfb[a];
+      for (size_t a = 0; a < fb.size(); ++a) cnt[fb_of[a] >= 0 ? sk_ids[fb_of[a]] : r2_ids[-1 - fb_of[a]]] = cfb[a];
     }
     // the full-path task list now holds every non-accepted task
     for (size_t a = 0; a < fb.size(); ++a) {
-      full_ids.push_back(sk_ids[fb_of[a]]);
+      full_ids.push_back(fb_of[a] >= 0 ? sk_ids[fb_of[a]] : r2_ids[-1 - fb_of[a]]);
       fullT.push_back(fb[a]);
     }
     std::vector<int32_t> keep_ids;
@@ -1046,6 +1213,12 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         keep_ids.push_back(sk_ids[a]);
         keepE.push_back(skE[a]);
         keepT.push_back(skT[a]);
+      }
+    for (size_t q = 0; q < r2_ids.size(); ++q)
+      if (r2_ok[q] > 0) {
+        keep_ids.push_back(r2_ids[q]);
+        keepE.push_back(r2E[q]);
+        keepT.push_back(r2T[q]);
       }
     sk_ids.swap(keep_ids);
     skE.swap(keepE);

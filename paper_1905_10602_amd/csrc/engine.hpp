@@ -174,6 +174,10 @@ struct Handle {
   int sketch_min = 128;     // Gram order from which a sketch is tried (IFMM_SKETCH_MIN)
   double* skbuf = nullptr;
   int64_t skbuf_bytes = 0;
+  double* skbuf2 = nullptr;  // second-round (wider) sketches
+  double* orthbuf = nullptr;  // block Gram-Schmidt tables and coefficients
+  int64_t orthbuf_bytes = 0;
+  int64_t skbuf2_bytes = 0;
   char* meta2b = nullptr;
   int64_t meta2b_bytes = 0;
   int64_t stat_sketch = 0, stat_sketch_rejected = 0, stat_sketch_narrow = 0;

@@ -430,6 +430,61 @@ __global__ void k_feat_sv(const SkTask* tasks, double* out) {
   }
 }
 
+// Blocked classical Gram-Schmidt with reorthogonalisation (BCGS2) of the
+// range sample, 64 columns per block: the projections against the earlier
+// blocks are batched GEMMs on many workgroups (k_gemm_batch); these two
+// kernels give the column norms before any projection and orthonormalise the
+// columns inside a block (same dependence rule as k_sk_orth).
+__global__ void k_sk_colnorm(const SkTask* tasks, double* n0, int ldn0) {
+  const SkTask t = tasks[blockIdx.y];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int j = blockIdx.x * 4 + wave; j < t.s; j += gridDim.x * 4) {
+    const double* y = t.Y + (int64_t)j * t.n;
+    double c = 0.0;
+    for (int r = lane; r < t.n; r += 64) c += y[r] * y[r];
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0) n0[(int64_t)blockIdx.y * ldn0 + j] = sqrt(c);
+  }
+}
+
+__global__ void k_sk_orth_block(const SkTask* tasks, int j0, double drop, const double* n0, int ldn0) {
+  __shared__ double s_c[64];
+  const SkTask t = tasks[blockIdx.x];
+  const int n = t.n, j1 = min(t.s, j0 + 64);
+  if (j0 >= t.s) return;
+  double* X = t.Y;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int j = j0; j < j1; ++j) {
+    double* xj = X + (int64_t)j * n;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int cnt = j - j0;
+      if (cnt > 0) {
+        for (int i = wave; i < cnt; i += NT / 64) {
+          const double* xi = X + (int64_t)(j0 + i) * n;
+          double c = 0.0;
+          for (int r = lane; r < n; r += 64) c += xi[r] * xj[r];
+          for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+          if (lane == 0) s_c[i] = c;
+        }
+        __syncthreads();
+        for (int r = tid; r < n; r += NT) {
+          double v = xj[r];
+          for (int i = 0; i < cnt; ++i) v -= s_c[i] * X[r + (int64_t)(j0 + i) * n];
+          xj[r] = v;
+        }
+        __syncthreads();
+      }
+    }
+    double part = 0.0;
+    for (int r = tid; r < n; r += NT) part += xj[r] * xj[r];
+    const double n2 = sqrt(wg_sum(part));
+    const double nn0 = n0[(int64_t)blockIdx.x * ldn0 + j];
+    const double sc = (n2 > drop * nn0 && n2 > 0.0) ? 1.0 / n2 : 0.0;
+    for (int r = tid; r < n; r += NT) xj[r] *= sc;
+    __syncthreads();
+  }
+}
+
 __global__ void k_sk_trace(const SkTask* tasks) {
   const SkTask t = tasks[blockIdx.x];
   double a = 0.0, b = 0.0;
