@@ -630,7 +630,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     sc += (std::max<int64_t>(cnt, 1) + 31) & ~31LL;
     return o;
   };
-  std::vector<int64_t> x_off(nrec);
+  std::vector<int64_t> x_off(nrec), dinv_off(nrec, 0);
   std::vector<std::vector<int64_t>> far_off_F, far_off_D;
   struct ChgOff { int64_t gs, gt, vs, vt, ws, wt, ls, lt, T, S, tmp; };
   const bool sym = h.symmetric;
@@ -668,6 +668,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     R.far_base = (int)far_idx.size();
     R.inv = R.d >= h.big_d ? 1 : 0;  // blocked path: X also carries the x-columns of D^-1
     x_off[k] = stake((int64_t)R.d * (R.M + R.r + (R.inv ? R.n : 0)));
+    dinv_off[k] = R.inv ? stake((int64_t)((R.d + BLU_NB - 1) / BLU_NB) * 2 * 4096) : 0;
     // persistent factor data
     int rc;
     double* p;
@@ -798,7 +799,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   for (int k = 0; k < nrec; ++k)
     if (recs[k].inv) {
       const int W = recs[k].M + recs[k].r + recs[k].n;
-      blu.push_back({recs[k].lu, recs[k].X, recs[k].piv, nullptr, recs[k].d, W});
+      blu.push_back({recs[k].lu, recs[k].X, recs[k].piv, nullptr, S0 + dinv_off[k], recs[k].d, W});
       blu_rec.push_back(k);
       blu_dmax = std::max(blu_dmax, recs[k].d);
       blu_wmax = std::max(blu_wmax, W);
@@ -876,7 +877,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     const unsigned nb = (unsigned)blu.size();
     double fl_blu = 0;
     for (const BluTask& b : blu) fl_blu += 2.0 / 3.0 * b.d * (double)b.d * b.d + 2.0 * (double)b.d * b.d * b.W;  // LU + both triangular solves
-    ProfScope ps(h, "k_blu", fl_blu, 0);
+    ProfScope ps(h, "group:blocked_lu", fl_blu, 0);
     const unsigned wch = (unsigned)std::max(1, (blu_wmax + 63) / 64);
     hipLaunchKernelGGL(k_blu_xinit, dim3(wch, nb), dim3(NT), 0, h.stream, d_blu, d_recs, d_blur);
     const int nsteps = (blu_dmax + BLU_NB - 1) / BLU_NB;
@@ -891,6 +892,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       if (blu_dmax - j0 - BLU_NB > 0)
         hipLaunchKernelGGL(k_blu_gemm, dim3(rows, cols, nb), dim3(NT), 0, h.stream, d_blu, j0);
     }
+    hipLaunchKernelGGL(k_blu_uinv, dim3((unsigned)nsteps, nb), dim3(NT), 0, h.stream, d_blu);
     for (int st = nsteps - 1; st >= 0; --st) {
       const int j0 = st * BLU_NB;
       hipLaunchKernelGGL(k_bu_trsm, dim3(wch, nb), dim3(NT), 0, h.stream, d_blu, st);
@@ -913,11 +915,11 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   if (nchg) {
     hipLaunchKernelGGL(k_set_chg, dim3((nchg + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_chg, d_chg, nchg, 0);
     {
-      ProfScope ps(h, "k_gram", fl_gram, 0);
       int nmax = 0;
       for (const Changed& C : chg) nmax = std::max(nmax, C.n);
       const int nbt = (nmax + 63) / 64;
       hipLaunchKernelGGL(k_gram_prep, dim3(sides * nchg), dim3(NT), 0, h.stream, V, d_chg, sides);
+      ProfScope ps(h, "k_gram", fl_gram, 0);
       hipLaunchKernelGGL(k_gram, dim3((unsigned)std::max(1, nbt * (nbt + 1) / 2), sides * nchg), dim3(NT), 0,
                          h.stream, V, d_chg, d_refs, d_far, d_nbrs, d_recs, sides);
     }
@@ -1036,7 +1038,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       double fl_sk = 0;
       for (const SkTask& t : skT)
         fl_sk += 2.0 * t.n * (double)t.R * t.s + 2.0 * t.n * (double)t.n * t.s + 6.0 * t.n * (double)t.s * t.s;
-      ProfScope ps(h, "k_sketch", fl_sk, 0);
+      ProfScope ps(h, "group:sketch", fl_sk, 0);
       const unsigned tn = (unsigned)((nmax + 63) / 64), ts = (unsigned)((smax + 63) / 64);
       const double drop = std::max(1e-13, std::min(1e-9, 1e-3 * h.eps));
       hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
@@ -1159,7 +1161,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         double fl2 = 0;
         for (const SkTask& t : r2T)
           fl2 += 2.0 * t.n * (double)t.R * t.s + 2.0 * t.n * (double)t.n * t.s + 6.0 * t.n * (double)t.s * t.s;
-        ProfScope ps(h, "k_sketch", fl2, 0);
+        ProfScope ps(h, "group:sketch", fl2, 0);
         const unsigned tn = (unsigned)((nmax2 + 63) / 64), ts = (unsigned)((smax2 + 63) / 64);
         const double drop = std::max(1e-13, std::min(1e-9, 1e-3 * h.eps));
         hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)n2), dim3(NT), 0, h.stream, d_T2);
@@ -1305,7 +1307,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         rmax = std::max(rmax, C.rnew);
         nmx = std::max(nmx, C.n);
       }
-      ProfScope ps(h, "k_sketch", fl, 0);
+      ProfScope ps(h, "group:sketch", fl, 0);
       hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)ns2), dim3(NT), 0, h.stream, d_vs);
       hipLaunchKernelGGL(k_gemm_batch, dim3((unsigned)((nmx + 63) / 64), (unsigned)((rmax + 63) / 64), (unsigned)ns2),
                          dim3(NT), 0, h.stream, d_vg);
@@ -1388,10 +1390,10 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         const double nil = TL.il_ptr[C.p + 1] - TL.il_ptr[C.p];
         fl_b += 2.0 * nil * 2.0 * (double)C.r * C.rnew * std::max(C.r, C.rnew) + 4.0 * K * C.r * C.rnew;
       }
-      ProfScope ps(h, "k_phase_b", fl_b, 0);
+      ProfScope ps(h, "group:phase_b", fl_b, 0);
       int rmax = 0;
       for (const Changed& C : chg) rmax = std::max(rmax, std::max(C.r, C.rnew));
-      if (rmax <= 48) {  // small blocks: one workgroup per changed node
+      if (rmax <= 48) {  // one workgroup per changed node
         hipLaunchKernelGGL(k_phase_b, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far, l > 2 ? 1 : 0,
                            L.d_il_blk_old, L.d_ilcap_old, h.precision == 1 ? 1 : 0);
       } else {
@@ -1860,7 +1862,7 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
       h.g_key_x = d_x;
     }
     {
-      ProfScope ps(h, "solve_graph", 0, 0);
+      ProfScope ps(h, "group:solve_graph", 0, 0);
       HIPCHK(hipGraphLaunch(h.g_exec, h.stream));
     }
   }

@@ -665,14 +665,52 @@ __global__ void k_xsolve(const ElimRec* recs, const XTask* xt) {
 // a colour with a handful of big nodes still fills the device.  Panel width
 // 64; the panel itself is factorised by one workgroup.  piv follows the
 // convention of wg_getrf, so the solve phase reads the factors unchanged.
+constexpr int BLU_NB = 64;
+constexpr int BLU_NB_PAD = BLU_NB + 1;
+
 struct BluTask {
   double* lu;
   double* X;
   int32_t* piv;
   int32_t* info;
+  double* dinv;  // inverses of the 64 x 64 diagonal blocks: L11^-1 (unit lower) / U11^-1 per panel, 64 x 64 each
   int32_t d, W;
 };
-constexpr int BLU_NB = 64;
+
+// Inverse of a triangular nb x nb diagonal block T (in LDS) into Inv (global,
+// ld 64): lower = 1: unit lower triangular; lower = 0: upper triangular with
+// its diagonal.  Column c of the inverse solves T x = e_c by substitution, one
+// thread per column, the columns held in LDS.
+__device__ inline void wg_tri_inverse(const double (*T)[BLU_NB_PAD], int nb, int lower, double* Inv) {
+  __shared__ double Xs[BLU_NB][BLU_NB_PAD];
+  const int c = threadIdx.x;
+  if (c < nb) {
+    if (lower) {
+      for (int i = 0; i < nb; ++i) {
+        double v = (i == c) ? 1.0 : 0.0;
+        for (int q = c; q < i; ++q) v -= T[i][q] * Xs[q][c];
+        Xs[i][c] = i < c ? 0.0 : v;
+      }
+    } else {
+      for (int i = nb - 1; i >= 0; --i) {
+        double v = (i == c) ? 1.0 : 0.0;
+        if (i <= c) {
+          for (int q = i + 1; q <= c; ++q) v -= T[i][q] * Xs[q][c];
+          v /= T[i][i];
+        } else {
+          v = 0.0;
+        }
+        Xs[i][c] = v;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = e & 63, j = e >> 6;
+    Inv[i + 64 * j] = (i < nb && j < nb) ? Xs[i][j] : 0.0;
+  }
+  __syncthreads();
+}
 
 __global__ void k_blu_xinit(const BluTask* tasks, const ElimRec* recs, const int32_t* rec_of) {
   const BluTask t = tasks[blockIdx.y];
@@ -759,6 +797,23 @@ __global__ void k_blu_panel(const BluTask* tasks, int j0) {
     }
     __syncthreads();
   }
+  // L11^-1 of this panel for the block triangular solve of the columns to its right
+  __shared__ double Ls[BLU_NB][BLU_NB_PAD];
+  for (int e = tid; e < nb * nb; e += NT) Ls[e % nb][e / nb] = T[j0 + e % nb + (int64_t)(j0 + e / nb) * d];
+  __syncthreads();
+  wg_tri_inverse(Ls, nb, 1, t.dinv + (int64_t)(j0 / BLU_NB) * 2 * 4096);
+}
+
+// U_jj^-1 of every diagonal block (after the factorisation), grid (blocks, tasks)
+__global__ void k_blu_uinv(const BluTask* tasks) {
+  __shared__ double Us[BLU_NB][BLU_NB_PAD];
+  const BluTask t = tasks[blockIdx.y];
+  const int j0 = blockIdx.x * BLU_NB;
+  if (j0 >= t.d) return;
+  const int nb = min(BLU_NB, t.d - j0);
+  for (int e = threadIdx.x; e < nb * nb; e += NT) Us[e % nb][e / nb] = t.lu[j0 + e % nb + (int64_t)(j0 + e / nb) * t.d];
+  __syncthreads();
+  wg_tri_inverse(Us, nb, 0, t.dinv + (int64_t)blockIdx.x * 2 * 4096 + 4096);
 }
 
 // columns outside the panel: c < d in lu, c >= d in X (both leading dim d)
@@ -789,7 +844,6 @@ __global__ void k_blu_swap(const BluTask* tasks, int j0) {
 __device__ inline int blu_chunks_lu(const BluTask& t, int j0, int nb) { return (t.d - j0 - nb + 63) / 64; }
 
 __global__ void k_blu_trsm(const BluTask* tasks, int j0) {
-  __shared__ double L[BLU_NB][BLU_NB + 1];
   const BluTask t = tasks[blockIdx.y];
   const int d = t.d;
   if (j0 >= d) return;
@@ -798,26 +852,17 @@ __global__ void k_blu_trsm(const BluTask* tasks, int j0) {
   const int cx = (t.W + 63) / 64;
   const int ch = blockIdx.x;
   if (ch >= clu + cx) return;
-  int c0, cend;
+  int c0, nc;
   double* base;
   if (ch < clu) {
-    c0 = j0 + nb + ch * 64; cend = d; base = t.lu;
+    c0 = j0 + nb + ch * 64; nc = min(64, d - c0); base = t.lu;
   } else {
-    c0 = (ch - clu) * 64; cend = t.W; base = t.X;
+    c0 = (ch - clu) * 64; nc = min(64, t.W - c0); base = t.X;
   }
-  for (int e = threadIdx.x; e < nb * nb; e += NT) L[e % nb][e / nb] = t.lu[j0 + e % nb + (int64_t)(j0 + e / nb) * d];
-  __syncthreads();
-  const int c = c0 + (threadIdx.x & 63);
-  const int part = threadIdx.x >> 6;
-  const bool act = c < cend;
-  double* col = base + j0 + (int64_t)(act ? c : 0) * d;
-  for (int j = 0; j < nb; ++j) {
-    if (act) {
-      const double xj = col[j];
-      for (int i = j + 1 + part; i < nb; i += 4) col[i] -= L[i][j] * xj;
-    }
-    __syncthreads();
-  }
+  // U12 = L11^-1 A12 in place: one 64 x 64 output tile whose operand is read
+  // completely before the tile is written
+  wg_gemm(nb, nc, nb, 1.0, t.dinv + (int64_t)(j0 / BLU_NB) * 2 * 4096, 64, false, base + j0 + (int64_t)c0 * d, d,
+          false, 0.0, base + j0 + (int64_t)c0 * d, d);
 }
 
 // trailing update A22 -= L21 U12 over the lu columns right of the panel and
@@ -845,31 +890,17 @@ __global__ void k_blu_gemm(const BluTask* tasks, int j0) {
           base + r0 + (int64_t)c0 * d, d);
 }
 
-// backward substitution, block row jb: X_jb = U_jb,jb^-1 X_jb (per 64 columns)
+// backward substitution, block row jb: X_jb = U_jb,jb^-1 X_jb (per 64 columns, in place)
 __global__ void k_bu_trsm(const BluTask* tasks, int jb) {
-  __shared__ double U[BLU_NB][BLU_NB + 1];
   const BluTask t = tasks[blockIdx.y];
   const int d = t.d, j0 = jb * BLU_NB;
   if (j0 >= d) return;
   const int nb = min(BLU_NB, d - j0);
   const int c0 = blockIdx.x * 64;
   if (c0 >= t.W) return;
-  for (int e = threadIdx.x; e < nb * nb; e += NT) U[e % nb][e / nb] = t.lu[j0 + e % nb + (int64_t)(j0 + e / nb) * d];
-  __syncthreads();
-  const int c = c0 + (threadIdx.x & 63);
-  const int part = threadIdx.x >> 6;
-  const bool act = c < t.W;
-  double* col = t.X + j0 + (int64_t)(act ? c : 0) * d;
-  for (int j = nb - 1; j >= 0; --j) {
-    // x_j is final once rows > j have been subtracted; thread part 0 scales it
-    if (act && part == 0) col[j] = col[j] / U[j][j];
-    __syncthreads();
-    if (act) {
-      const double xj = col[j];
-      for (int i = part; i < j; i += 4) col[i] -= U[i][j] * xj;
-    }
-    __syncthreads();
-  }
+  const int nc = min(64, t.W - c0);
+  wg_gemm(nb, nc, nb, 1.0, t.dinv + (int64_t)jb * 2 * 4096 + 4096, 64, false, t.X + j0 + (int64_t)c0 * d, d, false,
+          0.0, t.X + j0 + (int64_t)c0 * d, d);
 }
 
 // X[0:j0, :] -= U[0:j0, j0:j0+nb] X[j0:j0+nb, :]; grid (row tiles, column chunks, task)
