@@ -39,25 +39,43 @@ __device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* 
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-      for (int k0 = 0; k0 < k; k0 += 16) {
-        // load A tile: rows i0..i0+63, cols k0..k0+15  (64*16 = 1024 values, 4 per thread)
-        for (int e = tid; e < 1024; e += NT) {
+      // the next k-chunk is fetched into registers while the current one is
+      // multiplied out of LDS (4 A and 4 B values per thread)
+      double ra[4], rb[4];
+      auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = tid + q * NT;
           int ii, kk;
           if (!tA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
           const int gi = i0 + ii, gk = k0 + kk;
-          double v = 0.0;
-          if (gi < m && gk < k) v = tA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
-          sA[kk][ii] = v;
+          ra[q] = (gi < m && gk < k) ? (tA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda]) : 0.0;
+          int kb, jb;
+          if (!tB) { kb = e & 15; jb = e >> 4; } else { jb = e & 63; kb = e >> 6; }
+          const int gk2 = k0 + kb, gj = j0 + jb;
+          rb[q] = (gk2 < k && gj < n) ? (tB ? B[gj + (int64_t)gk2 * ldb] : B[gk2 + (int64_t)gj * ldb]) : 0.0;
         }
-        for (int e = tid; e < 1024; e += NT) {
-          int kk, jj;
-          if (!tB) { kk = e & 15; jj = e >> 4; } else { jj = e & 63; kk = e >> 6; }
-          const int gk = k0 + kk, gj = j0 + jj;
-          double v = 0.0;
-          if (gk < k && gj < n) v = tB ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb];
-          sB[kk][jj] = v;
+      };
+      auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = tid + q * NT;
+          int ii, kk;
+          if (!tA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
+          sA[kk][ii] = ra[q];
+          int kb, jb;
+          if (!tB) { kb = e & 15; jb = e >> 4; } else { jb = e & 63; kb = e >> 6; }
+          sB[kb][jb] = rb[q];
         }
-        __syncthreads();
+      };
+      if (k > 0) {
+        fetch(0);
+        stash();
+      }
+      __syncthreads();
+      for (int k0 = 0; k0 < k; k0 += 16) {
+        const bool more = k0 + 16 < k;
+        if (more) fetch(k0 + 16);
 #pragma unroll 4
         for (int kk = 0; kk < 16; ++kk) {
           double av[4], bv[4];
@@ -70,6 +88,8 @@ __device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* 
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
         }
+        __syncthreads();
+        if (more) stash();
         __syncthreads();
       }
 #pragma unroll
@@ -108,30 +128,49 @@ __device__ inline void wg_gemm_f32(int m, int n, int k, double alpha, const doub
       f32x16 acc;
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-      for (int k0 = 0; k0 < k; k0 += 16) {
-        for (int e = tid; e < 1024; e += NT) {
+      float ra[4], rb[4];
+      auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = tid + q * NT;
           int ii, kk;
           if (!tA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
           const int gi = i0 + ii, gk = k0 + kk;
-          double v = 0.0;
-          if (gi < m && gk < k) v = tA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
-          fA[kk][ii] = (float)v;
+          ra[q] = (gi < m && gk < k) ? (float)(tA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda]) : 0.0f;
+          int kb, jb;
+          if (!tB) { kb = e & 15; jb = e >> 4; } else { jb = e & 63; kb = e >> 6; }
+          const int gk2 = k0 + kb, gj = j0 + jb;
+          rb[q] = (gk2 < k && gj < n) ? (float)(tB ? B[gj + (int64_t)gk2 * ldb] : B[gk2 + (int64_t)gj * ldb]) : 0.0f;
         }
-        for (int e = tid; e < 1024; e += NT) {
-          int kk, jj;
-          if (!tB) { kk = e & 15; jj = e >> 4; } else { jj = e & 63; kk = e >> 6; }
-          const int gk = k0 + kk, gj = j0 + jj;
-          double v = 0.0;
-          if (gk < k && gj < n) v = tB ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb];
-          fB[kk][jj] = (float)v;
+      };
+      auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = tid + q * NT;
+          int ii, kk;
+          if (!tA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
+          fA[kk][ii] = ra[q];
+          int kb, jb;
+          if (!tB) { kb = e & 15; jb = e >> 4; } else { jb = e & 63; kb = e >> 6; }
+          fB[kb][jb] = rb[q];
         }
-        __syncthreads();
+      };
+      if (k > 0) {
+        fetch(0);
+        stash();
+      }
+      __syncthreads();
+      for (int k0 = 0; k0 < k; k0 += 16) {
+        const bool more = k0 + 16 < k;
+        if (more) fetch(k0 + 16);
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 2) {
           const float a = fA[kk + (lane >> 5)][wr + (lane & 31)];
           const float b = fB[kk + (lane >> 5)][wc + (lane & 31)];
           acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
         }
+        __syncthreads();
+        if (more) stash();
         __syncthreads();
       }
 #pragma unroll

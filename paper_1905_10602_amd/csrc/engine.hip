@@ -908,8 +908,12 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   }
   {
     ProfScope ps(h, "k_schur", fl_schur, 0);
-    hipLaunchKernelGGL(k_schur, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks, d_fidx,
-                       d_far, h.precision == 1 ? 1 : 0);
+    if (h.precision == 1)
+      hipLaunchKernelGGL(k_schur<true>, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks,
+                         d_fidx, d_far);
+    else
+      hipLaunchKernelGGL(k_schur<false>, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs,
+                         d_tasks, d_fidx, d_far);
   }
   if ((rc = check_arena(h, l, "schur", c, err))) return rc;
   if (nchg) {
@@ -1038,13 +1042,19 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       double fl_sk = 0;
       for (const SkTask& t : skT)
         fl_sk += 2.0 * t.n * (double)t.R * t.s + 2.0 * t.n * (double)t.n * t.s + 6.0 * t.n * (double)t.s * t.s;
-      ProfScope ps(h, "group:sketch", fl_sk, 0);
       const unsigned tn = (unsigned)((nmax + 63) / 64), ts = (unsigned)((smax + 63) / 64);
       const double drop = std::max(1e-13, std::min(1e-9, 1e-3 * h.eps));
-      hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
-      hipLaunchKernelGGL(k_sk_range, dim3(tn, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_chg, d_refs, d_far, d_nbrs,
-                         d_recs, d_skT);
-      if ((rc = sk_orthonormalise(h, skT, d_skT, drop, err))) return rc;
+      {
+        ProfScope ps(h, "group:sketch_range", fl_sk, 0);
+        hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
+        hipLaunchKernelGGL(k_sk_range, dim3(tn, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_chg, d_refs, d_far,
+                           d_nbrs, d_recs, d_skT);
+      }
+      {
+        ProfScope ps(h, "group:sketch_orth", 0, 0);
+        if ((rc = sk_orthonormalise(h, skT, d_skT, drop, err))) return rc;
+      }
+      ProfScope ps(h, "group:sketch_rr", 0, 0);
       hipLaunchKernelGGL(k_gemm_batch, dim3(tn, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_gT);
       hipLaunchKernelGGL(k_gemm_batch, dim3(ts, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_gT + nsk);
       hipLaunchKernelGGL(k_sk_trace, dim3((unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
@@ -1161,13 +1171,19 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         double fl2 = 0;
         for (const SkTask& t : r2T)
           fl2 += 2.0 * t.n * (double)t.R * t.s + 2.0 * t.n * (double)t.n * t.s + 6.0 * t.n * (double)t.s * t.s;
-        ProfScope ps(h, "group:sketch", fl2, 0);
         const unsigned tn = (unsigned)((nmax2 + 63) / 64), ts = (unsigned)((smax2 + 63) / 64);
         const double drop = std::max(1e-13, std::min(1e-9, 1e-3 * h.eps));
-        hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)n2), dim3(NT), 0, h.stream, d_T2);
-        hipLaunchKernelGGL(k_sk_range, dim3(tn, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_chg, d_refs, d_far, d_nbrs,
-                           d_recs, d_T2);
-        if ((rc = sk_orthonormalise(h, r2T, d_T2, drop, err))) return rc;
+        {
+          ProfScope ps(h, "group:sketch_range", fl2, 0);
+          hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)n2), dim3(NT), 0, h.stream, d_T2);
+          hipLaunchKernelGGL(k_sk_range, dim3(tn, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_chg, d_refs, d_far,
+                             d_nbrs, d_recs, d_T2);
+        }
+        {
+          ProfScope ps(h, "group:sketch_orth", 0, 0);
+          if ((rc = sk_orthonormalise(h, r2T, d_T2, drop, err))) return rc;
+        }
+        ProfScope ps(h, "group:sketch_rr", 0, 0);
         hipLaunchKernelGGL(k_gemm_batch, dim3(tn, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_G2);
         hipLaunchKernelGGL(k_gemm_batch, dim3(ts, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_G2 + n2);
         hipLaunchKernelGGL(k_sk_trace, dim3((unsigned)n2), dim3(NT), 0, h.stream, d_T2);
@@ -1307,7 +1323,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         rmax = std::max(rmax, C.rnew);
         nmx = std::max(nmx, C.n);
       }
-      ProfScope ps(h, "group:sketch", fl, 0);
+      ProfScope ps(h, "group:sketch_vectors", fl, 0);
       hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)ns2), dim3(NT), 0, h.stream, d_vs);
       hipLaunchKernelGGL(k_gemm_batch, dim3((unsigned)((nmx + 63) / 64), (unsigned)((rmax + 63) / 64), (unsigned)ns2),
                          dim3(NT), 0, h.stream, d_vg);
@@ -1394,8 +1410,12 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       int rmax = 0;
       for (const Changed& C : chg) rmax = std::max(rmax, std::max(C.r, C.rnew));
       if (rmax <= 48) {  // one workgroup per changed node
-        hipLaunchKernelGGL(k_phase_b, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far, l > 2 ? 1 : 0,
-                           L.d_il_blk_old, L.d_ilcap_old, h.precision == 1 ? 1 : 0);
+        if (h.precision == 1)
+          hipLaunchKernelGGL(k_phase_b<true>, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far,
+                             l > 2 ? 1 : 0, L.d_il_blk_old, L.d_ilcap_old);
+        else
+          hipLaunchKernelGGL(k_phase_b<false>, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far,
+                             l > 2 ? 1 : 0, L.d_il_blk_old, L.d_ilcap_old);
       } else {
       // one task per transformed block, each with its own temporary; launched
       // in chunks whose temporaries fit a bounded buffer
@@ -1449,9 +1469,12 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         }
         HIPCHK(hipMemcpyAsync(h.scratch2, pb.data() + b0, (b1 - b0) * sizeof(PBTask), hipMemcpyHostToDevice,
                               h.stream));
-        hipLaunchKernelGGL(k_phase_b_blocks, dim3((unsigned)(b1 - b0)), dim3(NT), 0, h.stream, V, K, d_chg, d_refs,
-                           d_far, (const PBTask*)h.scratch2, L.d_il_blk_old, L.d_ilcap_old,
-                           h.precision == 1 ? 1 : 0);
+        if (h.precision == 1)
+          hipLaunchKernelGGL(k_phase_b_blocks<true>, dim3((unsigned)(b1 - b0)), dim3(NT), 0, h.stream, V, K, d_chg,
+                             d_refs, d_far, (const PBTask*)h.scratch2, L.d_il_blk_old, L.d_ilcap_old);
+        else
+          hipLaunchKernelGGL(k_phase_b_blocks<false>, dim3((unsigned)(b1 - b0)), dim3(NT), 0, h.stream, V, K, d_chg,
+                             d_refs, d_far, (const PBTask*)h.scratch2, L.d_il_blk_old, L.d_ilcap_old);
         b0 = b1;
         HIPCHK(hipStreamSynchronize(h.stream));  // the task table and buffer are reused / freed after this
       }
@@ -1699,7 +1722,7 @@ int factor(Handle& h, std::string& err) {
 
 // ------------------------------------------------------------------ solve
 // Fill kernel (graph-safe replacement of a memset)
-__global__ void k_zero(double* p, int64_t n) {
+__global__ void __launch_bounds__(NT) k_zero(double* p, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) p[e] = 0.0;
 }
 
@@ -2004,7 +2027,7 @@ extern "C" int ifmm_internal_syev(const double* A, int count, int n, int k, doub
 }
 
 namespace ifmm {
-__global__ void k_internal_gemm(int m, int n, int k, double alpha, const double* A, int lda, int tA, const double* B,
+__global__ void __launch_bounds__(NT) k_internal_gemm(int m, int n, int k, double alpha, const double* A, int lda, int tA, const double* B,
                                 int ldb, int tB, double beta, double* C, int ldc, int f32) {
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   const int mm = min(64, m - i0), nn = min(64, n - j0);

@@ -54,7 +54,7 @@ static double fnow() {
 // ------------------------------------------------------------------ operators
 // Unit-side M2L for box offsets d in [-3, 3]^3 (d = source - target):
 //   U_d[m, m'] = 1 / (4 pi |xb_m / 2 - d - xb_m' / 2|) for side 1 (scaled by 1/side).
-__global__ void k_fmm_m2l_ops(int nc, double* out) {
+__global__ void __launch_bounds__(NT) k_fmm_m2l_ops(int nc, double* out) {
   const int o = blockIdx.x;
   const int dx = o % 7 - 3, dy = (o / 7) % 7 - 3, dz = o / 49 - 3;
   const int K = nc * nc * nc;
@@ -73,7 +73,7 @@ __global__ void k_fmm_m2l_ops(int nc, double* out) {
 }
 
 // M2M of a child in octant o (bit e set: upper half along axis e), parent frame.
-__global__ void k_fmm_m2m_ops(int nc, double* out) {
+__global__ void __launch_bounds__(NT) k_fmm_m2m_ops(int nc, double* out) {
   const int o = blockIdx.x;
   const int K = nc * nc * nc;
   double* M = out + (int64_t)o * K * K;
@@ -87,7 +87,7 @@ __global__ void k_fmm_m2m_ops(int nc, double* out) {
 }
 
 // Leaf interpolation weights S[m, j] = S(xb_m, y_j) (K x n_leaf per leaf, at pt_begin * K).
-__global__ void k_fmm_leaf_S(int nc, const double* pts, const int64_t* pt_begin, const int32_t* coord,
+__global__ void __launch_bounds__(NT) k_fmm_leaf_S(int nc, const double* pts, const int64_t* pt_begin, const int32_t* coord,
                              const double* lo, double side, double* S) {
   const int i = blockIdx.x;
   const int K = nc * nc * nc;
@@ -105,18 +105,18 @@ __global__ void k_fmm_leaf_S(int nc, const double* pts, const int64_t* pt_begin,
 }
 
 // ------------------------------------------------------------------ matvec
-__global__ void k_fmm_perm_in(const double* x, const int64_t* perm, double* xs, int64_t n) {
+__global__ void __launch_bounds__(NT) k_fmm_perm_in(const double* x, const int64_t* perm, double* xs, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (t < n) xs[t] = x[perm[t]];
 }
 
-__global__ void k_fmm_perm_out(const double* ys, const int64_t* perm, double* y, int64_t n) {
+__global__ void __launch_bounds__(NT) k_fmm_perm_out(const double* ys, const int64_t* perm, double* y, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (t < n) y[perm[t]] = ys[t];
 }
 
 // m_leaf = S diag(w) x_leaf; one workgroup per leaf, leaf_base = global index of leaf 0
-__global__ void k_fmm_p2m(int K, const double* S, const int64_t* pt_begin, const double* w, const double* xs,
+__global__ void __launch_bounds__(NT) k_fmm_p2m(int K, const double* S, const int64_t* pt_begin, const double* w, const double* xs,
                           double* mult, int64_t leaf_base) {
   const int i = blockIdx.x;
   const int64_t b = pt_begin[i];
@@ -131,7 +131,7 @@ __global__ void k_fmm_p2m(int K, const double* S, const int64_t* pt_begin, const
 }
 
 // m_P = sum_c M2M_oct(c) m_c; one workgroup per parent (global index base + blockIdx.x)
-__global__ void k_fmm_m2m(int K, const double* m2m, const int32_t* child_ptr, const int32_t* child,
+__global__ void __launch_bounds__(NT) k_fmm_m2m(int K, const double* m2m, const int32_t* child_ptr, const int32_t* child,
                           const int32_t* oct, double* mult, int64_t base) {
   __shared__ double sm[216];  // K <= 216, one output row per thread
   const int64_t P = base + blockIdx.x;
@@ -150,7 +150,7 @@ __global__ void k_fmm_m2m(int K, const double* m2m, const int32_t* child_ptr, co
 }
 
 // gathered source multipoles of the pairs: G[:, p] = m_{src(p)}
-__global__ void k_fmm_gather(int K, const int32_t* src, const double* mult, double* G, int64_t npairs) {
+__global__ void __launch_bounds__(NT) k_fmm_gather(int K, const int32_t* src, const double* mult, double* G, int64_t npairs) {
   const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (e >= npairs * K) return;
   const int64_t p = e / K;
@@ -159,7 +159,7 @@ __global__ void k_fmm_gather(int K, const int32_t* src, const double* mult, doub
 }
 
 // partial[:, start:start+count] = U_off G[:, start:start+count]
-__global__ void k_fmm_m2l(int K, const FmmHandle::GemmTask* tasks, const double* m2l, const double* G,
+__global__ void __launch_bounds__(NT) k_fmm_m2l(int K, const FmmHandle::GemmTask* tasks, const double* m2l, const double* G,
                           double* part) {
   const FmmHandle::GemmTask t = tasks[blockIdx.x];
   wg_gemm(K, t.count, K, 1.0, m2l + (int64_t)t.off * K * K, K, false, G + t.start * K, K, false, 0.0,
@@ -168,7 +168,7 @@ __global__ void k_fmm_m2l(int K, const FmmHandle::GemmTask* tasks, const double*
 
 // l_t = (1/h) sum_pairs partial + M2M_oct(t)^T l_parent (levels > 2); one
 // workgroup per target node of the level (global index base + blockIdx.x)
-__global__ void k_fmm_local(int K, const int64_t* tp_ptr, const int64_t* tp, const double* part, double inv_h,
+__global__ void __launch_bounds__(NT) k_fmm_local(int K, const int64_t* tp_ptr, const int64_t* tp, const double* part, double inv_h,
                             const double* m2m, const int32_t* oct, const int32_t* par, double* loc, int64_t base,
                             int has_parent) {
   __shared__ double sl[216];
@@ -194,7 +194,7 @@ __global__ void k_fmm_local(int K, const int64_t* tp_ptr, const int64_t* tp, con
 
 // y_leaf = S^T l_leaf + near field; one workgroup per leaf, 4 lanes per target
 // point split the sources; sources staged through LDS one neighbour at a time
-__global__ void k_fmm_leaf_eval(int K, const double* S, const int64_t* pt_begin, const int32_t* nbr_ptr,
+__global__ void __launch_bounds__(NT) k_fmm_leaf_eval(int K, const double* S, const int64_t* pt_begin, const int32_t* nbr_ptr,
                                 const int32_t* nbr, const double* pts, const double* w, const double* diag,
                                 const double* xs, const double* loc, int64_t leaf_base, double* ys) {
   __shared__ double sl[216];
@@ -248,7 +248,7 @@ __global__ void k_fmm_leaf_eval(int K, const double* S, const int64_t* pt_begin,
 
 // ------------------------------------------------------------------ GMRES vector kernels
 // partial dot products of w with columns 0..nv-1 of V (ld n): grid (chunks, nv)
-__global__ void k_gm_dots(const double* V, int64_t n, const double* w, int64_t chunk, double* part) {
+__global__ void __launch_bounds__(NT) k_gm_dots(const double* V, int64_t n, const double* w, int64_t chunk, double* part) {
   const int64_t a = (int64_t)blockIdx.x * chunk, bnd = (n < a + chunk) ? n : a + chunk;
   const double* v = V + (int64_t)blockIdx.y * n;
   double s = 0.0;
@@ -257,7 +257,7 @@ __global__ void k_gm_dots(const double* V, int64_t n, const double* w, int64_t c
   if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
 }
 
-__global__ void k_gm_dots_fin(const double* part, int nchunk, double* out) {
+__global__ void __launch_bounds__(NT) k_gm_dots_fin(const double* part, int nchunk, double* out) {
   double s = 0.0;
   for (int e = threadIdx.x; e < nchunk; e += NT) s += part[(int64_t)blockIdx.x * nchunk + e];
   const double tot = wg_sum(s);
@@ -265,7 +265,7 @@ __global__ void k_gm_dots_fin(const double* part, int nchunk, double* out) {
 }
 
 // w -= V[:, 0:nv] h  (h on device, nv <= 1024)
-__global__ void k_gm_sub(const double* V, int64_t n, int nv, const double* h, double* w) {
+__global__ void __launch_bounds__(NT) k_gm_sub(const double* V, int64_t n, int nv, const double* h, double* w) {
   __shared__ double sh[1024];
   for (int e = threadIdx.x; e < nv; e += NT) sh[e] = h[e];
   __syncthreads();
@@ -277,7 +277,7 @@ __global__ void k_gm_sub(const double* V, int64_t n, int nv, const double* h, do
 }
 
 // y = a x + b y
-__global__ void k_gm_axpby(int64_t n, double a, const double* x, double b, double* y) {
+__global__ void __launch_bounds__(NT) k_gm_axpby(int64_t n, double a, const double* x, double b, double* y) {
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (i < n) y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
 }

@@ -52,7 +52,7 @@ __device__ inline int il_slot(const LevelView& V, int t, int s) {
 
 
 // Unit-side M2L for all 343 offsets d in [-3, 3]^3: U_d[m, m'] = K(d + xb_m / 2, xb_m' / 2).
-__global__ void k_unit_m2l(int nc, double* out) {
+__global__ void __launch_bounds__(NT) k_unit_m2l(int nc, double* out) {
   const int o = blockIdx.x;
   const int dx = o % 7 - 3, dy = (o / 7) % 7 - 3, dz = o / 49 - 3;
   const int K = nc * nc * nc;
@@ -71,14 +71,14 @@ __global__ void k_unit_m2l(int nc, double* out) {
 }
 
 // G_d = U_d^T U_d for every offset (source-side weight term).
-__global__ void k_unit_gram(int K, const double* unit, double* uus) {
+__global__ void __launch_bounds__(NT) k_unit_gram(int K, const double* unit, double* uus) {
   const int o = blockIdx.x;
   wg_gemm(K, K, K, 1.0, unit + (int64_t)o * K * K, K, true, unit + (int64_t)o * K * K, K, false, 0.0,
           uus + (int64_t)o * K * K, K);
 }
 
 // M2M from a child in octant o (bit e set = upper half along axis e) to its parent.
-__global__ void k_m2m8(int nc, double* out) {
+__global__ void __launch_bounds__(NT) k_m2m8(int nc, double* out) {
   const int o = blockIdx.x;
   const int K = nc * nc * nc;
   double* M = out + (int64_t)o * K * K;
@@ -105,7 +105,7 @@ __device__ inline int offset_index(const int32_t* coord, int t, int s) {
 // Far-field weight of every node of a level (top-down):
 //   G_i = (1/L^2) sum_{l in I_i} U_{c_l - c_i}^T U_{c_l - c_i} + M2M_i^T G_parent M2M_i.
 // The Laplace kernel is symmetric, so the target weight equals G_i.
-__global__ void k_weights(int K, int nn, const int32_t* coord, const int32_t* il_ptr, const int32_t* il_idx,
+__global__ void __launch_bounds__(NT) k_weights(int K, int nn, const int32_t* coord, const int32_t* il_ptr, const int32_t* il_idx,
                           const int32_t* parent, const double* uus, const double* m2m8, double invL2,
                           const double* Gpar, double* G, double* tmp) {
   const int i = blockIdx.x;
@@ -127,7 +127,7 @@ __global__ void k_weights(int K, int nn, const int32_t* coord, const int32_t* il
 }
 
 // Leaf Chebyshev operators: P2Mc (K x n, ld K) and L2Pc (n x K, ld n).
-__global__ void k_leaf_cheb(LevelView V, int nc, const double* pts, const double* w, const int64_t* pt_begin,
+__global__ void __launch_bounds__(NT) k_leaf_cheb(LevelView V, int nc, const double* pts, const double* w, const int64_t* pt_begin,
                             const double* lo, double side) {
   const int i = blockIdx.x;
   const int K = nc * nc * nc;
@@ -148,7 +148,7 @@ __global__ void k_leaf_cheb(LevelView V, int nc, const double* pts, const double
 }
 
 // Near-field blocks of the leaves: P2P_pq[a, b] = K(x_a, x_b) w_b, diag on the self block.
-__global__ void k_p2p(LevelView V, const int32_t* slot_row, const double* pts, const double* w,
+__global__ void __launch_bounds__(NT) k_p2p(LevelView V, const int32_t* slot_row, const double* pts, const double* w,
                       const double* diag, const int64_t* pt_begin) {
   const int s = blockIdx.x;
   const int p = slot_row[s], q = V.near_idx[s];
@@ -170,7 +170,7 @@ __global__ void k_p2p(LevelView V, const int32_t* slot_row, const double* pts, c
 }
 
 // Initial rank reduction, Gram step: Gs = P2Mc^T G P2Mc, Gt = L2Pc G L2Pc^T (n x n).
-__global__ void k_reduce_gram(LevelView V, int K, const double* G, double* work, const int64_t* work_off) {
+__global__ void __launch_bounds__(NT) k_reduce_gram(LevelView V, int K, const double* G, double* work, const int64_t* work_off) {
   const int i = blockIdx.x;
   const int n = V.n[i];
   if (n == 0) return;
@@ -206,7 +206,7 @@ __device__ inline void eig_count(const EigTask& t, double eps2, int32_t* cnt) {
 }
 
 // cyclic Jacobi alternative (all vectors at once; W holds n x n)
-__global__ void k_eig_jacobi(const EigTask* tasks, double eps2, int32_t* cnt) {
+__global__ void __launch_bounds__(NT) k_eig_jacobi(const EigTask* tasks, double eps2, int32_t* cnt) {
   const EigTask t = tasks[blockIdx.x];
   if (t.n == 0) {
     if (threadIdx.x == 0) cnt[blockIdx.x] = 0;
@@ -216,7 +216,7 @@ __global__ void k_eig_jacobi(const EigTask* tasks, double eps2, int32_t* cnt) {
   eig_count(t, eps2, cnt);
 }
 
-__global__ void k_eig_values(const EigTask* tasks, double eps2, int32_t* cnt, int unused) {
+__global__ void __launch_bounds__(NT) k_eig_values(const EigTask* tasks, double eps2, int32_t* cnt, int unused) {
   const EigTask t = tasks[blockIdx.x];
   if (t.n == 0) {
     if (threadIdx.x == 0) cnt[blockIdx.x] = 0;
@@ -233,7 +233,7 @@ __global__ void k_eig_values(const EigTask* tasks, double eps2, int32_t* cnt, in
   }
 }
 
-__global__ void k_eig_vectors(const EigTask* tasks) {
+__global__ void __launch_bounds__(NT) k_eig_vectors(const EigTask* tasks) {
   const EigTask t = tasks[blockIdx.x];
   if (t.n == 0 || t.k == 0) return;
   wg_syev_vectors(t.n, t.A, t.n, t.W, t.lam, t.k, t.V, t.n, t.IW);
@@ -249,7 +249,7 @@ struct GemmTask {
   int32_t m, n, k, lda, ldb, ldc, tA, tB;
   double alpha, beta;
 };
-__global__ void k_gemm_batch(const GemmTask* tasks) {
+__global__ void __launch_bounds__(NT) k_gemm_batch(const GemmTask* tasks) {
   const GemmTask t = tasks[blockIdx.z];
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   if (i0 >= t.m || j0 >= t.n) return;
@@ -285,7 +285,7 @@ __device__ inline double sk_uniform(uint32_t seed, uint64_t idx) {
   return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;  // [-1, 1)
 }
 
-__global__ void k_sk_omega(const SkTask* tasks) {
+__global__ void __launch_bounds__(NT) k_sk_omega(const SkTask* tasks) {
   const SkTask t = tasks[blockIdx.y];
   const int64_t tot = (int64_t)t.R * t.s;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT)
@@ -297,7 +297,7 @@ __global__ void k_sk_omega(const SkTask* tasks) {
 //   side 0:  Y = W^T Omega,  W = [diag(sig_s) P2M ; F_qp ...]   (rows: r, then m_q each)
 //   side 1:  Y = W Omega,    W = [L2P diag(sig_t) , F_pq ...]   (columns likewise)
 // grid (row tiles of n, column tiles of s, sketch task).
-__global__ void k_sk_range(const Changed* chg, const FarRef* refs, const FarPair* far, const ElimNbr* nbrs,
+__global__ void __launch_bounds__(NT) k_sk_range(const Changed* chg, const FarRef* refs, const FarPair* far, const ElimNbr* nbrs,
                            const ElimRec* recs, const SkTask* tasks) {
   const SkTask t = tasks[blockIdx.z];
   const int I = blockIdx.x * 64, J = blockIdx.y * 64;
@@ -334,7 +334,7 @@ __global__ void k_sk_range(const Changed* chg, const FarRef* refs, const FarPair
 // whose norm collapses below `drop` times its original norm only adds
 // directions with singular values far below the truncation threshold and is
 // set to zero (keeping Q orthonormal).  One workgroup per task.
-__global__ void k_sk_orth(const SkTask* tasks, double drop) {
+__global__ void __launch_bounds__(NT) k_sk_orth(const SkTask* tasks, double drop) {
   __shared__ double s_c[NT];
   const SkTask t = tasks[blockIdx.x];
   const int n = t.n, k = t.s;
@@ -376,7 +376,7 @@ __global__ void k_sk_orth(const SkTask* tasks, double drop) {
 // Top singular values of an 8-column range sample Y (n x 8): sqrt of the
 // eigenvalues of Y^T Y (cyclic Jacobi on the 8 x 8 matrix), descending.
 // These are the "sketched singular values" fed to the rank predictor.
-__global__ void k_feat_sv(const SkTask* tasks, double* out) {
+__global__ void __launch_bounds__(NT) k_feat_sv(const SkTask* tasks, double* out) {
   __shared__ double g[8][8];
   const SkTask t = tasks[blockIdx.x];
   const int n = t.n;
@@ -435,7 +435,7 @@ __global__ void k_feat_sv(const SkTask* tasks, double* out) {
 // blocks are batched GEMMs on many workgroups (k_gemm_batch); these two
 // kernels give the column norms before any projection and orthonormalise the
 // columns inside a block (same dependence rule as k_sk_orth).
-__global__ void k_sk_colnorm(const SkTask* tasks, double* n0, int ldn0) {
+__global__ void __launch_bounds__(NT) k_sk_colnorm(const SkTask* tasks, double* n0, int ldn0) {
   const SkTask t = tasks[blockIdx.y];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int j = blockIdx.x * 4 + wave; j < t.s; j += gridDim.x * 4) {
@@ -447,7 +447,7 @@ __global__ void k_sk_colnorm(const SkTask* tasks, double* n0, int ldn0) {
   }
 }
 
-__global__ void k_sk_orth_block(const SkTask* tasks, int j0, double drop, const double* n0, int ldn0) {
+__global__ void __launch_bounds__(NT) k_sk_orth_block(const SkTask* tasks, int j0, double drop, const double* n0, int ldn0) {
   __shared__ double s_c[64];
   const SkTask t = tasks[blockIdx.x];
   const int n = t.n, j1 = min(t.s, j0 + 64);
@@ -485,7 +485,7 @@ __global__ void k_sk_orth_block(const SkTask* tasks, int j0, double drop, const 
   }
 }
 
-__global__ void k_sk_trace(const SkTask* tasks) {
+__global__ void __launch_bounds__(NT) k_sk_trace(const SkTask* tasks) {
   const SkTask t = tasks[blockIdx.x];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < t.n; i += NT) a += t.G[i + (int64_t)i * t.n];
@@ -499,7 +499,7 @@ __global__ void k_sk_trace(const SkTask* tasks) {
 }
 
 // ok[i] = 1 when sketch i is accepted (see above); cnt from the Ritz values
-__global__ void k_sk_check(const SkTask* tasks, const EigTask* et, const int32_t* cnt, double eps2, int32_t* ok,
+__global__ void __launch_bounds__(NT) k_sk_check(const SkTask* tasks, const EigTask* et, const int32_t* cnt, double eps2, int32_t* ok,
                            int count) {
   const int i = blockIdx.x * NT + threadIdx.x;
   if (i >= count) return;
@@ -512,7 +512,7 @@ __global__ void k_sk_check(const SkTask* tasks, const EigTask* et, const int32_t
 
 // Initial rank reduction, basis step: P2M = V^T, L2P = U, sig = sqrt(lam),
 // T = P2Mc V (K x r), S = U^T L2Pc (r x K); then M2M / L2L of the node.
-__global__ void k_reduce_basis(LevelView V, int K, const double* work, const int64_t* work_off,
+__global__ void __launch_bounds__(NT) k_reduce_basis(LevelView V, int K, const double* work, const int64_t* work_off,
                                const double* m2m8, int has_parent, int sym) {
   const int i = blockIdx.x;
   const int n = V.n[i], r = V.r[i], rc = V.rc[i];
@@ -549,7 +549,7 @@ __global__ void k_reduce_basis(LevelView V, int K, const double* work, const int
 }
 
 // Initial M2L of every interaction pair: M2L_il = (1/L) S_i U_{c_i - c_l} T_l.
-__global__ void k_reduce_m2l(LevelView V, int K, const double* unit, double invL, double* tmp, const int64_t* tmp_off) {
+__global__ void __launch_bounds__(NT) k_reduce_m2l(LevelView V, int K, const double* unit, double invL, double* tmp, const int64_t* tmp_off) {
   const int i = blockIdx.x;
   const int ri = V.r[i], rci = V.rc[i];
   if (ri == 0) return;
@@ -567,7 +567,7 @@ __global__ void k_reduce_m2l(LevelView V, int K, const double* unit, double invL
 
 // ------------------------------------------------------------------ aggregation
 // Parent Chebyshev operators: P2Mc_P = [M2M_c ...] (K x n_P), L2Pc_P = [L2L_c; ...].
-__global__ void k_agg_cheb(LevelView C, LevelView F, int K, const int32_t* child_ptr, const int32_t* child) {
+__global__ void __launch_bounds__(NT) k_agg_cheb(LevelView C, LevelView F, int K, const int32_t* child_ptr, const int32_t* child) {
   const int P = blockIdx.x;
   const int nP = C.n[P];
   double* P2M = C.arena + C.cp2m_off[P];
@@ -583,7 +583,7 @@ __global__ void k_agg_cheb(LevelView C, LevelView F, int K, const int32_t* child
 }
 
 // Parent near block (P, Q) = [M2L_cc'] over the children (near or interaction blocks).
-__global__ void k_agg_near(LevelView C, LevelView F, const int32_t* slot_row, const int32_t* child_ptr,
+__global__ void __launch_bounds__(NT) k_agg_near(LevelView C, LevelView F, const int32_t* slot_row, const int32_t* child_ptr,
                            const int32_t* child) {
   const int s = blockIdx.x;
   const int P = slot_row[s], Q = C.near_idx[s];
@@ -612,7 +612,7 @@ __global__ void k_agg_near(LevelView C, LevelView F, const int32_t* slot_row, co
 
 // ------------------------------------------------------------------ phase A
 // Pivot D_i = [[P2P_ii, L2P_i], [P2M_i, 0]] and copies of the L- and U-blocks.
-__global__ void k_gather(LevelView V, const ElimRec* recs, const ElimNbr* nbrs) {
+__global__ void __launch_bounds__(NT) k_gather(LevelView V, const ElimRec* recs, const ElimNbr* nbrs) {
   const ElimRec R = recs[blockIdx.x];
   const int i = R.node, n = R.n, r = R.r, d = R.d;
   const int rc = V.rc[i];
@@ -628,7 +628,7 @@ __global__ void k_gather(LevelView V, const ElimRec* recs, const ElimNbr* nbrs) 
   }
 }
 
-__global__ void k_getrf(const ElimRec* recs, int32_t* info, int big_d) {
+__global__ void __launch_bounds__(NT) k_getrf(const ElimRec* recs, int32_t* info, int big_d) {
   const ElimRec R = recs[blockIdx.x];
   if (R.d >= big_d) return;  // blocked path
   const int inf = wg_getrf(R.d, R.lu, R.d, R.piv);
@@ -639,7 +639,7 @@ __global__ void k_getrf(const ElimRec* recs, int32_t* info, int big_d) {
 struct XTask {
   int32_t rec, c0;
 };
-__global__ void k_xsolve(const ElimRec* recs, const XTask* xt) {
+__global__ void __launch_bounds__(NT) k_xsolve(const ElimRec* recs, const XTask* xt) {
   const XTask t = xt[blockIdx.x];
   const ElimRec R = recs[t.rec];
   const int n = R.n, d = R.d, M = R.M;
@@ -712,7 +712,7 @@ __device__ inline void wg_tri_inverse(const double (*T)[BLU_NB_PAD], int nb, int
   __syncthreads();
 }
 
-__global__ void k_blu_xinit(const BluTask* tasks, const ElimRec* recs, const int32_t* rec_of) {
+__global__ void __launch_bounds__(NT) k_blu_xinit(const BluTask* tasks, const ElimRec* recs, const int32_t* rec_of) {
   const BluTask t = tasks[blockIdx.y];
   const ElimRec R = recs[rec_of[blockIdx.y]];
   const int c0 = blockIdx.x * 64;
@@ -732,7 +732,7 @@ __global__ void k_blu_xinit(const BluTask* tasks, const ElimRec* recs, const int
 
 // After the solve, D^-1 = [X[:, M+r : M+r+n], X[:, M : M+r]] replaces the LU
 // factors (the solve of a large pivot multiplies by the explicit inverse).
-__global__ void k_blu_store_inv(const BluTask* tasks, const ElimRec* recs, const int32_t* rec_of) {
+__global__ void __launch_bounds__(NT) k_blu_store_inv(const BluTask* tasks, const ElimRec* recs, const int32_t* rec_of) {
   const BluTask t = tasks[blockIdx.y];
   const ElimRec R = recs[rec_of[blockIdx.y]];
   const int c0 = blockIdx.x * 64, d = t.d;
@@ -745,7 +745,7 @@ __global__ void k_blu_store_inv(const BluTask* tasks, const ElimRec* recs, const
   }
 }
 
-__global__ void k_blu_panel(const BluTask* tasks, int j0) {
+__global__ void __launch_bounds__(NT) k_blu_panel(const BluTask* tasks, int j0) {
   const BluTask t = tasks[blockIdx.x];
   const int d = t.d;
   if (j0 >= d) return;
@@ -805,7 +805,7 @@ __global__ void k_blu_panel(const BluTask* tasks, int j0) {
 }
 
 // U_jj^-1 of every diagonal block (after the factorisation), grid (blocks, tasks)
-__global__ void k_blu_uinv(const BluTask* tasks) {
+__global__ void __launch_bounds__(NT) k_blu_uinv(const BluTask* tasks) {
   __shared__ double Us[BLU_NB][BLU_NB_PAD];
   const BluTask t = tasks[blockIdx.y];
   const int j0 = blockIdx.x * BLU_NB;
@@ -821,7 +821,7 @@ __device__ inline double* blu_col(const BluTask& t, int c) {
   return c < t.d ? t.lu + (int64_t)c * t.d : t.X + (int64_t)(c - t.d) * t.d;
 }
 
-__global__ void k_blu_swap(const BluTask* tasks, int j0) {
+__global__ void __launch_bounds__(NT) k_blu_swap(const BluTask* tasks, int j0) {
   const BluTask t = tasks[blockIdx.y];
   const int d = t.d;
   if (j0 >= d) return;
@@ -843,7 +843,7 @@ __global__ void k_blu_swap(const BluTask* tasks, int j0) {
 // X columns, each split into chunks of 64 that never straddle the two
 __device__ inline int blu_chunks_lu(const BluTask& t, int j0, int nb) { return (t.d - j0 - nb + 63) / 64; }
 
-__global__ void k_blu_trsm(const BluTask* tasks, int j0) {
+__global__ void __launch_bounds__(NT) k_blu_trsm(const BluTask* tasks, int j0) {
   const BluTask t = tasks[blockIdx.y];
   const int d = t.d;
   if (j0 >= d) return;
@@ -867,7 +867,7 @@ __global__ void k_blu_trsm(const BluTask* tasks, int j0) {
 
 // trailing update A22 -= L21 U12 over the lu columns right of the panel and
 // all X columns; grid (row tiles, column chunks, task)
-__global__ void k_blu_gemm(const BluTask* tasks, int j0) {
+__global__ void __launch_bounds__(NT) k_blu_gemm(const BluTask* tasks, int j0) {
   const BluTask t = tasks[blockIdx.z];
   const int d = t.d;
   if (j0 >= d) return;
@@ -891,7 +891,7 @@ __global__ void k_blu_gemm(const BluTask* tasks, int j0) {
 }
 
 // backward substitution, block row jb: X_jb = U_jb,jb^-1 X_jb (per 64 columns, in place)
-__global__ void k_bu_trsm(const BluTask* tasks, int jb) {
+__global__ void __launch_bounds__(NT) k_bu_trsm(const BluTask* tasks, int jb) {
   const BluTask t = tasks[blockIdx.y];
   const int d = t.d, j0 = jb * BLU_NB;
   if (j0 >= d) return;
@@ -904,7 +904,7 @@ __global__ void k_bu_trsm(const BluTask* tasks, int jb) {
 }
 
 // X[0:j0, :] -= U[0:j0, j0:j0+nb] X[j0:j0+nb, :]; grid (row tiles, column chunks, task)
-__global__ void k_bu_gemm(const BluTask* tasks, int jb) {
+__global__ void __launch_bounds__(NT) k_bu_gemm(const BluTask* tasks, int jb) {
   const BluTask t = tasks[blockIdx.z];
   const int d = t.d, j0 = jb * BLU_NB;
   if (j0 >= d) return;
@@ -928,8 +928,9 @@ __global__ void k_bu_gemm(const BluTask* tasks, int jb) {
 struct SchurTask {
   int32_t rec, a, b, pad;
 };
+template <bool f32>
 __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const ElimNbr* nbrs, const int32_t* far_idx,
-                                   const FarPair* far, int a, int b, bool f32) {
+                                   const FarPair* far, int a, int b) {
   const int i = R.node, n = R.n, r = R.r, d = R.d, M = R.M;
   if (a < R.nnb) {
     const ElimNbr A = nbrs[R.nb_begin + a];
@@ -955,15 +956,16 @@ __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const E
     }
   }
 }
-__global__ void k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs, const SchurTask* tasks,
-                        const int32_t* far_idx, const FarPair* far, int f32) {
+template <bool f32>
+__global__ void __launch_bounds__(NT) k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs,
+                                              const SchurTask* tasks, const int32_t* far_idx, const FarPair* far) {
   const SchurTask T = tasks[blockIdx.x];
   const ElimRec R = recs[T.rec];
   if (T.b == -2) {
-    for (int b = 0; b < R.nnb; ++b) schur_block(V, R, nbrs, far_idx, far, T.a, b, f32);
-    schur_block(V, R, nbrs, far_idx, far, T.a, -1, f32);
+    for (int b = 0; b < R.nnb; ++b) schur_block<f32>(V, R, nbrs, far_idx, far, T.a, b);
+    schur_block<f32>(V, R, nbrs, far_idx, far, T.a, -1);
   } else {
-    schur_block(V, R, nbrs, far_idx, far, T.a, T.b, f32);
+    schur_block<f32>(V, R, nbrs, far_idx, far, T.a, T.b);
   }
 }
 
@@ -973,7 +975,7 @@ __global__ void k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs, c
 // Scaled bases of a changed node, one workgroup per (node, side):
 //   side 0: t0 = diag(sig_s) P2M (r x n);  side 1: t1 = L2P diag(sig_t) (n x r)
 // (the two sides use disjoint halves of the node's tmp buffer)
-__global__ void k_gram_prep(LevelView V, const Changed* chg, int sides) {
+__global__ void __launch_bounds__(NT) k_gram_prep(LevelView V, const Changed* chg, int sides) {
   const Changed C = chg[sides == 2 ? blockIdx.x >> 1 : blockIdx.x];
   const int side = sides == 2 ? (int)(blockIdx.x & 1) : 0;
   const int p = C.p, n = C.n, r = C.r, rc = V.rc[p];
@@ -993,7 +995,7 @@ __global__ void k_gram_prep(LevelView V, const Changed* chg, int sides) {
 //   Gs = t0^T t0 + sum_q F_qp^T F_qp,   Gt = t1 t1^T + sum_q F_pq F_pq^T
 // One workgroup per 64 x 64 tile of the lower triangle (grid.x), mirrored
 // into the upper one; grid.y = (node, side).
-__global__ void k_gram(LevelView V, const Changed* chg, const FarRef* refs, const FarPair* far,
+__global__ void __launch_bounds__(NT) k_gram(LevelView V, const Changed* chg, const FarRef* refs, const FarPair* far,
                        const ElimNbr* nbrs, const ElimRec* recs, int sides) {
   const Changed C = chg[sides == 2 ? blockIdx.y >> 1 : blockIdx.y];
   const int side = sides == 2 ? (int)(blockIdx.y & 1) : 0;
@@ -1033,7 +1035,7 @@ __global__ void k_gram(LevelView V, const Changed* chg, const FarRef* refs, cons
 
 // New bases of a changed node: V' = leading rnew eigenvectors of Gs, U' of Gt;
 // T_p = P2M V' (r x rnew), S_p = U'^T L2P (rnew x r); then overwrite the bases.
-__global__ void k_basis(LevelView V, const Changed* chg) {
+__global__ void __launch_bounds__(NT) k_basis(LevelView V, const Changed* chg) {
   const Changed C = chg[blockIdx.x];
   const int p = C.p, n = C.n, r = C.r, rn = C.rnew, rc = V.rc[p];
   double* P2M = V.arena + V.p2m_off[p];
@@ -1059,7 +1061,7 @@ __global__ void k_basis(LevelView V, const Changed* chg) {
 //   both changed   F <- U_a'^T F V_b'     a changed   F <- U_a'^T F
 //   b changed      F <- F V_b'            both eliminated: M2L_ab += F
 // U_a' = L2P_a (n_a x r_a', ld n_a), V_b' = P2M_b^T (P2M_b: r_b' x n_b, ld rc_b).
-__global__ void k_project(LevelView V, const FarPair* far, const ElimRec* recs, const ElimNbr* nbrs,
+__global__ void __launch_bounds__(NT) k_project(LevelView V, const FarPair* far, const ElimRec* recs, const ElimNbr* nbrs,
                           const Changed* chg) {
   const FarPair P = far[blockIdx.x];
   const ElimRec R = recs[P.rec];
@@ -1101,8 +1103,10 @@ __device__ inline int find_ref(const FarRef* refs, int begin, int count, int q) 
 // A block whose capacity grew is read from its old storage (blk_old, ld
 // cap_old) and written to its new one (V.il_blk, ld V.ilcap).
 // k_phase_b: one workgroup per changed node (small ranks).
-__global__ void k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* refs, const FarPair* far,
-                          int has_parent, double* const* blk_old, const int32_t* cap_old, int f32) {
+template <bool f32>
+__global__ void __launch_bounds__(NT) k_phase_b(LevelView V, int K, const Changed* chg, const FarRef* refs,
+                                                const FarPair* far, int has_parent, double* const* blk_old,
+                                                const int32_t* cap_old) {
   const Changed C = chg[blockIdx.x];
   const int p = C.p, r = C.r, rn = C.rnew, rcp = V.rc[p];
   double* t = C.tmp;
@@ -1164,8 +1168,10 @@ struct PBTask {
   int32_t chg, slot, kind, pad;
   double* t;
 };
-__global__ void k_phase_b_blocks(LevelView V, int K, const Changed* chg, const FarRef* refs, const FarPair* far,
-                                 const PBTask* tasks, double* const* blk_old, const int32_t* cap_old, int f32) {
+template <bool f32>
+__global__ void __launch_bounds__(NT) k_phase_b_blocks(LevelView V, int K, const Changed* chg, const FarRef* refs,
+                                                       const FarPair* far, const PBTask* tasks, double* const* blk_old,
+                                                       const int32_t* cap_old) {
   const PBTask task = tasks[blockIdx.x];
   const Changed C = chg[task.chg];
   const int p = C.p, r = C.r, rn = C.rnew, rcp = V.rc[p];
@@ -1217,36 +1223,36 @@ struct SlotMove {
   int32_t slot, pad;
   double* ptr;
 };
-__global__ void k_slot_moves(double** tab, const SlotMove* mv, int count) {
+__global__ void __launch_bounds__(NT) k_slot_moves(double** tab, const SlotMove* mv, int count) {
   const int k = blockIdx.x * NT + threadIdx.x;
   if (k < count) tab[mv[k].slot] = mv[k].ptr;
 }
-__global__ void k_set_caps(int32_t* cap, const int32_t* node_cap, int count) {
+__global__ void __launch_bounds__(NT) k_set_caps(int32_t* cap, const int32_t* node_cap, int count) {
   const int k = blockIdx.x * NT + threadIdx.x;
   if (k < count) cap[node_cap[2 * k]] = node_cap[2 * k + 1];
 }
 
 // Debug: flag any non-finite or huge (> 1e300) value in a buffer.
-__global__ void k_check_finite(const double* p, int64_t n, int32_t* flag) {
+__global__ void __launch_bounds__(NT) k_check_finite(const double* p, int64_t n, int32_t* flag) {
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) {
     const double v = p[e];
     if (!(fabs(v) <= 1e300)) flag[0] = 1;
   }
 }
 
-__global__ void k_set_rank(int32_t* r, const Changed* chg, int nchg) {
+__global__ void __launch_bounds__(NT) k_set_rank(int32_t* r, const Changed* chg, int nchg) {
   const int k = blockIdx.x * NT + threadIdx.x;
   if (k < nchg) r[chg[k].p] = chg[k].rnew;
 }
 
-__global__ void k_set_chg(int32_t* chgidx, const Changed* chg, int nchg, int clear) {
+__global__ void __launch_bounds__(NT) k_set_chg(int32_t* chgidx, const Changed* chg, int nchg, int clear) {
   const int k = blockIdx.x * NT + threadIdx.x;
   if (k < nchg) chgidx[chg[k].p] = clear ? -1 : k;
 }
 
 // ------------------------------------------------------------------ top level
 // Dense system of all level-2 M2L blocks (near blocks for dist <= 1).
-__global__ void k_top_assemble(LevelView V, int nn, const int64_t* top_off, double* T, int ldt) {
+__global__ void __launch_bounds__(NT) k_top_assemble(LevelView V, int nn, const int64_t* top_off, double* T, int ldt) {
   const int P = blockIdx.x;
   const int rP = V.r[P];
   for (int Q = 0; Q < nn; ++Q) {
@@ -1262,7 +1268,7 @@ __global__ void k_top_assemble(LevelView V, int nn, const int64_t* top_off, doub
 constexpr int TOP_NB = 64;
 
 // C tile (64 x 64 at blockIdx) of C = alpha A B + beta C.
-__global__ void k_gemm_tiles(int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
+__global__ void __launch_bounds__(NT) k_gemm_tiles(int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
                              double beta, double* C, int ldc) {
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   const int mm = min(64, m - i0), nn = min(64, n - j0);
@@ -1273,7 +1279,7 @@ __global__ void k_gemm_tiles(int m, int n, int k, double alpha, const double* A,
 
 // Panel T[j0:n, j0:j0+nb]: unblocked LU with partial pivoting over rows j0..n-1
 // (swaps applied inside the panel only); piv[j] = global row swapped with j.
-__global__ void k_lu_panel(double* T, int n, int j0, int nb, int32_t* piv, int32_t* info) {
+__global__ void __launch_bounds__(NT) k_lu_panel(double* T, int n, int j0, int nb, int32_t* piv, int32_t* info) {
   __shared__ double sv[NT];
   __shared__ int si[NT];
   const int tid = threadIdx.x;
@@ -1323,7 +1329,7 @@ __global__ void k_lu_panel(double* T, int n, int j0, int nb, int32_t* piv, int32
 }
 
 // Row interchanges of the panel applied to the columns outside it.
-__global__ void k_lu_swap(double* T, int n, int j0, int nb, const int32_t* piv) {
+__global__ void __launch_bounds__(NT) k_lu_swap(double* T, int n, int j0, int nb, const int32_t* piv) {
   const int c = blockIdx.x * NT + threadIdx.x;
   if (c >= n || (c >= j0 && c < j0 + nb)) return;
   for (int j = j0; j < j0 + nb; ++j) {
@@ -1337,7 +1343,7 @@ __global__ void k_lu_swap(double* T, int n, int j0, int nb, const int32_t* piv) 
 }
 
 // U12 = L11^-1 A12 for 64 columns per workgroup (L11 unit lower, in LDS).
-__global__ void k_lu_trsm(double* T, int n, int j0, int nb) {
+__global__ void __launch_bounds__(NT) k_lu_trsm(double* T, int n, int j0, int nb) {
   __shared__ double L[TOP_NB][TOP_NB + 1];
   const int c0 = j0 + nb + blockIdx.x * 64;
   for (int e = threadIdx.x; e < nb * nb; e += NT) L[e % nb][e / nb] = T[j0 + e % nb + (int64_t)(j0 + e / nb) * n];
@@ -1357,7 +1363,7 @@ __global__ void k_lu_trsm(double* T, int n, int j0, int nb) {
 }
 
 // Inverse columns: X[:, c0:c0+64] = T^-1 I[:, c0:c0+64] with the LU factors.
-__global__ void k_lu_inverse(const double* T, int n, const int32_t* piv, double* X) {
+__global__ void __launch_bounds__(NT) k_lu_inverse(const double* T, int n, const int32_t* piv, double* X) {
   const int c0 = blockIdx.x * 64;
   const int nc = min(64, n - c0);
   double* B = X + (int64_t)c0 * n;
@@ -1377,7 +1383,7 @@ struct SolveView {
   int k;
 };
 
-__global__ void k_perm_in(const double* b, int64_t ld, int k, const int64_t* perm, const int64_t* pt_begin,
+__global__ void __launch_bounds__(NT) k_perm_in(const double* b, int64_t ld, int k, const int64_t* perm, const int64_t* pt_begin,
                           const int32_t* n, SolveView S) {
   const int i = blockIdx.x;
   const int ni = n[i];
@@ -1387,7 +1393,7 @@ __global__ void k_perm_in(const double* b, int64_t ld, int k, const int64_t* per
   }
 }
 
-__global__ void k_perm_out(double* x, int64_t ld, int k, const int64_t* perm, const int64_t* pt_begin,
+__global__ void __launch_bounds__(NT) k_perm_out(double* x, int64_t ld, int k, const int64_t* perm, const int64_t* pt_begin,
                            const int32_t* n, SolveView S) {
   const int i = blockIdx.x;
   const int ni = n[i];
@@ -1399,7 +1405,7 @@ __global__ void k_perm_out(double* x, int64_t ld, int k, const int64_t* perm, co
 
 // Forward substitution of one elimination (Alg. 2, upward pass):
 //   w = D^-1 [x_i; 0];  rows of neighbour p -= L_p w_top;  z_i += w_bot.
-__global__ void k_fwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S, const int32_t* rnow) {
+__global__ void __launch_bounds__(NT) k_fwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S, const int32_t* rnow) {
   const ElimRec R = recs[blockIdx.x];
   if (R.inv) return;  // explicit-inverse path
   const int n = R.n, r = R.r, d = R.d, k = S.k;
@@ -1425,7 +1431,7 @@ __global__ void k_fwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S, con
 
 // Backward substitution of one elimination (Alg. 2, downward pass):
 //   [x_i; z_i] = w - D^-1 [sum_q U_q x_q; -y_i]
-__global__ void k_bwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
+__global__ void __launch_bounds__(NT) k_bwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
   const ElimRec R = recs[blockIdx.x];
   if (R.inv) return;  // explicit-inverse path
   const int n = R.n, r = R.r, d = R.d, k = S.k;
@@ -1453,7 +1459,7 @@ __global__ void k_bwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
 // spread over many workgroups (64-row tiles), grid (tiles, records of the colour).
 //   forward:  w = D^-1[:, 0:n] x_i;  rows of neighbour p -= L_p w_top;  z_i += w_bot
 //   backward: t = [sum_q U_q x_q; -y_i];  x_i = w_top - D^-1[0:n, :] t
-__global__ void k_fwd_inv_w(const ElimRec* recs, SolveView S) {
+__global__ void __launch_bounds__(NT) k_fwd_inv_w(const ElimRec* recs, SolveView S) {
   const ElimRec R = recs[blockIdx.y];
   if (!R.inv) return;
   const int r0 = blockIdx.x * 64, k = S.k;
@@ -1463,7 +1469,7 @@ __global__ void k_fwd_inv_w(const ElimRec* recs, SolveView S) {
   wg_gemm(min(64, R.d - r0), k, R.n, 1.0, R.lu + r0, R.d, false, xi, R.n, false, 0.0, w + r0, R.d);
 }
 
-__global__ void k_fwd_inv_upd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
+__global__ void __launch_bounds__(NT) k_fwd_inv_upd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
   const ElimRec R = recs[blockIdx.y];
   if (!R.inv) return;
   const int k = S.k, n = R.n, d = R.d;
@@ -1485,7 +1491,7 @@ __global__ void k_fwd_inv_upd(const ElimRec* recs, const ElimNbr* nbrs, SolveVie
   }
 }
 
-__global__ void k_bwd_inv_t(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
+__global__ void __launch_bounds__(NT) k_bwd_inv_t(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
   const ElimRec R = recs[blockIdx.y];
   if (!R.inv) return;
   const int k = S.k, n = R.n, d = R.d;
@@ -1507,7 +1513,7 @@ __global__ void k_bwd_inv_t(const ElimRec* recs, const ElimNbr* nbrs, SolveView 
   }
 }
 
-__global__ void k_bwd_inv_x(const ElimRec* recs, SolveView S) {
+__global__ void __launch_bounds__(NT) k_bwd_inv_x(const ElimRec* recs, SolveView S) {
   const ElimRec R = recs[blockIdx.y];
   if (!R.inv) return;
   const int k = S.k, n = R.n, d = R.d;
@@ -1523,7 +1529,7 @@ __global__ void k_bwd_inv_x(const ElimRec* recs, SolveView S) {
 }
 
 // Level change of the node vectors: x_P = [z_c ...] (up) / y_c = slices of x_P (down).
-__global__ void k_vec_up(SolveView F, SolveView C, const int32_t* child_ptr, const int32_t* child,
+__global__ void __launch_bounds__(NT) k_vec_up(SolveView F, SolveView C, const int32_t* child_ptr, const int32_t* child,
                          const int32_t* rF, const int32_t* nC) {
   const int P = blockIdx.x;
   const int k = F.k, nP = nC[P];
@@ -1539,7 +1545,7 @@ __global__ void k_vec_up(SolveView F, SolveView C, const int32_t* child_ptr, con
   }
 }
 
-__global__ void k_vec_down(SolveView F, SolveView C, const int32_t* child_ptr, const int32_t* child,
+__global__ void __launch_bounds__(NT) k_vec_down(SolveView F, SolveView C, const int32_t* child_ptr, const int32_t* child,
                            const int32_t* rF, const int32_t* nC) {
   const int P = blockIdx.x;
   const int k = F.k, nP = nC[P];
@@ -1557,14 +1563,14 @@ __global__ void k_vec_down(SolveView F, SolveView C, const int32_t* child_ptr, c
 
 // Top solve with the explicit inverse: gather f = [z_P ...], y = Tinv f (tiled
 // GEMM, separate launch), scatter y back into the z slots.
-__global__ void k_top_gather(SolveView S, int nn, const int32_t* r, const int64_t* top_off, double* buf, int ldt) {
+__global__ void __launch_bounds__(NT) k_top_gather(SolveView S, int nn, const int32_t* r, const int64_t* top_off, double* buf, int ldt) {
   const int P = blockIdx.x;
   const int k = S.k, rP = r[P];
   const double* z = S.Z + S.zo[P] * k;
   if (rP > 0) WG_FOR2(rP, k, a, c) buf[top_off[P] + a + (int64_t)c * ldt] = z[a + (int64_t)c * rP];
 }
 
-__global__ void k_top_scatter(SolveView S, int nn, const int32_t* r, const int64_t* top_off, const double* buf,
+__global__ void __launch_bounds__(NT) k_top_scatter(SolveView S, int nn, const int32_t* r, const int64_t* top_off, const double* buf,
                               int ldt) {
   const int P = blockIdx.x;
   const int k = S.k, rP = r[P];

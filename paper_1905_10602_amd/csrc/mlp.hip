@@ -23,7 +23,7 @@ constexpr int MNT = 256;
 
 static inline int64_t mlp_np(int F) { return (int64_t)MH * F + MH + MH * MH + MH + MH + 1; }
 
-__global__ void k_mlp_layer1(const float* th, int F, const float* X, int64_t m, float* Z1, float* H1) {
+__global__ void __launch_bounds__(MNT) k_mlp_layer1(const float* th, int F, const float* X, int64_t m, float* Z1, float* H1) {
   const int64_t e = (int64_t)blockIdx.x * MNT + threadIdx.x;
   if (e >= m * MH) return;
   const int64_t i = e / MH;
@@ -36,7 +36,7 @@ __global__ void k_mlp_layer1(const float* th, int F, const float* X, int64_t m, 
   H1[e] = z > 0.f ? z : 0.f;
 }
 
-__global__ void k_mlp_layer2(const float* th, int F, const float* H1, int64_t m, float* Z2, float* H2) {
+__global__ void __launch_bounds__(MNT) k_mlp_layer2(const float* th, int F, const float* H1, int64_t m, float* Z2, float* H2) {
   const int64_t e = (int64_t)blockIdx.x * MNT + threadIdx.x;
   if (e >= m * MH) return;
   const int64_t i = e / MH;
@@ -49,7 +49,7 @@ __global__ void k_mlp_layer2(const float* th, int F, const float* H1, int64_t m,
   H2[e] = z > 0.f ? z : 0.f;
 }
 
-__global__ void k_mlp_out(const float* th, int F, const float* H2, int64_t m, float* Y) {
+__global__ void __launch_bounds__(MNT) k_mlp_out(const float* th, int F, const float* H2, int64_t m, float* Y) {
   const int64_t i = (int64_t)blockIdx.x * MNT + threadIdx.x;
   if (i >= m) return;
   const float* w3 = th + (int64_t)MH * F + MH + MH * MH + MH;
@@ -59,7 +59,7 @@ __global__ void k_mlp_out(const float* th, int F, const float* H2, int64_t m, fl
 }
 
 // dL/dy (sample i) and the per-sample loss
-__global__ void k_mlp_dy(const float* Y, const float* T, int64_t m, float tau, float* DY, float* Lterm) {
+__global__ void __launch_bounds__(MNT) k_mlp_dy(const float* Y, const float* T, int64_t m, float tau, float* DY, float* Lterm) {
   const int64_t i = (int64_t)blockIdx.x * MNT + threadIdx.x;
   if (i >= m) return;
   const float u = T[i] - Y[i];
@@ -67,7 +67,7 @@ __global__ void k_mlp_dy(const float* Y, const float* T, int64_t m, float tau, f
   Lterm[i] = u >= 0.f ? tau * u : (tau - 1.f) * u;
 }
 
-__global__ void k_mlp_dz2(const float* th, int F, const float* DY, const float* Z2, int64_t m, float* DZ2) {
+__global__ void __launch_bounds__(MNT) k_mlp_dz2(const float* th, int F, const float* DY, const float* Z2, int64_t m, float* DZ2) {
   const int64_t e = (int64_t)blockIdx.x * MNT + threadIdx.x;
   if (e >= m * MH) return;
   const int64_t i = e / MH;
@@ -76,7 +76,7 @@ __global__ void k_mlp_dz2(const float* th, int F, const float* DY, const float* 
   DZ2[e] = Z2[e] > 0.f ? DY[i] * w3[j] : 0.f;
 }
 
-__global__ void k_mlp_dz1(const float* th, int F, const float* DZ2, const float* Z1, int64_t m, float* DZ1) {
+__global__ void __launch_bounds__(MNT) k_mlp_dz1(const float* th, int F, const float* DZ2, const float* Z1, int64_t m, float* DZ1) {
   const int64_t e = (int64_t)blockIdx.x * MNT + threadIdx.x;
   if (e >= m * MH) return;
   const int64_t i = e / MH;
@@ -88,7 +88,7 @@ __global__ void k_mlp_dz1(const float* th, int F, const float* DZ2, const float*
 }
 
 // one thread per parameter: sum over the samples in FP64
-__global__ void k_mlp_pgrad(int F, const float* X, const float* H1, const float* H2, const float* DY, const float* DZ1,
+__global__ void __launch_bounds__(MNT) k_mlp_pgrad(int F, const float* X, const float* H1, const float* H2, const float* DY, const float* DZ1,
                             const float* DZ2, int64_t m, float* G) {
   const int64_t p = (int64_t)blockIdx.x * MNT + threadIdx.x;
   const int64_t o1 = (int64_t)MH * F, o2 = o1 + MH, o3 = o2 + MH * MH, o4 = o3 + MH, o5 = o4 + MH, o6 = o5 + 1;
@@ -115,7 +115,7 @@ __global__ void k_mlp_pgrad(int F, const float* X, const float* H1, const float*
   G[p] = (float)s;
 }
 
-__global__ void k_mlp_adam(float* th, const float* g, float* m1, float* m2, int64_t n, float lr, float c1, float c2) {
+__global__ void __launch_bounds__(MNT) k_mlp_adam(float* th, const float* g, float* m1, float* m2, int64_t n, float lr, float c1, float c2) {
   const int64_t p = (int64_t)blockIdx.x * MNT + threadIdx.x;
   if (p >= n) return;
   const float a = 0.9f * m1[p] + 0.1f * g[p];
@@ -125,7 +125,7 @@ __global__ void k_mlp_adam(float* th, const float* g, float* m1, float* m2, int6
   th[p] -= lr * (a / c1) / (sqrtf(b / c2) + 1e-8f);
 }
 
-__global__ void k_mlp_sum(const float* v, int64_t m, double* out) {
+__global__ void __launch_bounds__(MNT) k_mlp_sum(const float* v, int64_t m, double* out) {
   __shared__ double red[MNT];
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < m; i += MNT) s += v[i];
