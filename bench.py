@@ -143,7 +143,7 @@ def run_form(name, pts, dg, args, bt, xt, F, f_dev):
     out = {"factor_s": med("factor_s"), "solve_ms_per_rhs": med("solve_s") * 1e3 / args.nrhs,
            "build_s": med("build_s"), "step_s": med("step_s"), "solve_residual_on_fmm": res, **gm,
            "sketches": stats.get("sketches"), "sketches_rejected": stats.get("sketches_rejected"),
-           "rank_predictions": stats.get("rank_predictions"),
+           "rank_predictions": stats.get("rank_predictions"), "t_sync": stats.get("t_sync"),
            "depth": stats.get("depth"), "top_n": stats.get("top_n"), "device_GB": stats.get("device_bytes", 0) / 1e9,
            "factor_store_GB": stats.get("store_bytes", 0) / 1e9,
            "levels": [{k2: L[k2] for k2 in ("level", "nodes", "colours", "rank_sum", "rank_max", "n_max", "t_elim")}

@@ -169,6 +169,7 @@ ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
                   ",\"sketches_rejected\":" + std::to_string(h.stat_sketch_rejected) +
                   ",\"sketches_narrow\":" + std::to_string(h.stat_sketch_narrow) +
                   ",\"rank_predictions\":" + std::to_string(h.stat_predicted) +
+                  ",\"t_sync\":" + std::to_string(h.t_sync) +
                   ",\"levels\":[";
   for (int l = 2; l <= h.tree.depth; ++l) {
     const ifmm::Level& T = h.tree.levels[l];

@@ -28,9 +28,33 @@ constexpr int NT = 256;           // threads per workgroup
 // of the 64 x 64 output tile, rows strided by 16 for coalesced stores.
 __device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
                                const double* B, int ldb, bool tB, double beta, double* C, int ldc) {
-  __shared__ double sA[16][65];
-  __shared__ double sB[16][65];
+  __shared__ double smem[2 * 16 * 65 + 64];
+  double (*sA)[65] = reinterpret_cast<double (*)[65]>(smem);
+  double (*sB)[65] = reinterpret_cast<double (*)[65]>(smem + 16 * 65);
   const int tid = threadIdx.x;
+  if (m <= 32 && n <= 32 && k <= 32) {
+    // small product: both operands staged whole in LDS, one pass, no k-chunks
+    double (*As)[33] = reinterpret_cast<double (*)[33]>(smem);
+    double (*Bs)[33] = reinterpret_cast<double (*)[33]>(smem + 32 * 33);
+    for (int e = tid; e < m * k; e += NT) {
+      const int i = e % m, q = e / m;
+      As[i][q] = tA ? A[q + (int64_t)i * lda] : A[i + (int64_t)q * lda];
+    }
+    for (int e = tid; e < k * n; e += NT) {
+      const int q = e % k, j = e / k;
+      Bs[q][j] = tB ? B[j + (int64_t)q * ldb] : B[q + (int64_t)j * ldb];
+    }
+    __syncthreads();
+    for (int e = tid; e < m * n; e += NT) {
+      const int i = e % m, j = e / m;
+      double acc = 0.0;
+      for (int q = 0; q < k; ++q) acc = fma(As[i][q], Bs[q][j], acc);
+      double* c = C + i + (int64_t)j * ldc;
+      *c = (beta == 0.0) ? alpha * acc : fma(alpha, acc, beta * (*c));
+    }
+    __syncthreads();
+    return;
+  }
   const int tr = tid & 15, tc = tid >> 4;
   for (int i0 = 0; i0 < m; i0 += 64) {
     for (int j0 = 0; j0 < n; j0 += 64) {
@@ -118,6 +142,10 @@ __device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 __device__ inline void wg_gemm_f32(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
                                    const double* B, int ldb, bool tB, double beta, double* C, int ldc) {
+  if (m <= 32 && n <= 32 && k <= 32) {  // too small for matrix cores: the FP64 one-pass product
+    wg_gemm(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc);
+    return;
+  }
   __shared__ float fA[16][68];
   __shared__ float fB[16][68];
   const int tid = threadIdx.x;

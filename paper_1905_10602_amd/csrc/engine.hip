@@ -36,6 +36,14 @@ namespace ifmm {
     }                                                                               \
   } while (0)
 
+// stream synchronisation of the factorisation, its waiting time accounted
+#define HSYNC(hh)                                                     \
+  do {                                                                \
+    const double t_s0_ = now_s();                                     \
+    HIPCHK(hipStreamSynchronize((hh).stream));                        \
+    (hh).t_sync += now_s() - t_s0_;                                   \
+  } while (0)
+
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -604,7 +612,7 @@ static int sk_orthonormalise(Handle& h, const std::vector<SkTask>& T, const SkTa
     }
     hipLaunchKernelGGL(k_sk_orth_block, dim3((unsigned)nt), dim3(NT), 0, h.stream, d_T, b * 64, drop, n0, ldn0);
   }
-  HIPCHK(hipStreamSynchronize(h.stream));  // the host table above is a temporary
+  HSYNC(h);  // the host table above is a temporary
   return 0;
 }
 
@@ -1079,7 +1087,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       HIPCHK(hipMemcpyAsync(ok_sk.data(), d_ok, nsk * 4, hipMemcpyDeviceToHost, h.stream));
     }
     HIPCHK(hipMemcpyAsync(info.data(), d_info, nrec * 4, hipMemcpyDeviceToHost, h.stream));
-    HIPCHK(hipStreamSynchronize(h.stream));
+    HSYNC(h);
     for (size_t a = 0; a < nfull; ++a) cnt[full_ids[a]] = cnt_full[a];
     // rejected sketches: full eigen-decomposition of their Gram matrices
     std::vector<EigTask> fb;
@@ -1195,7 +1203,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       r2_ok.assign(n2, 0);
       HIPCHK(hipMemcpyAsync(c2.data(), d_c2, n2 * 4, hipMemcpyDeviceToHost, h.stream));
       HIPCHK(hipMemcpyAsync(r2_ok.data(), d_o2, n2 * 4, hipMemcpyDeviceToHost, h.stream));
-      HIPCHK(hipStreamSynchronize(h.stream));
+      HSYNC(h);
       h.stat_sketch += (int64_t)n2;
       for (size_t q = 0; q < n2; ++q) {
         if (r2_ok[q] > 0) {
@@ -1215,7 +1223,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       }
       std::vector<int32_t> cfb(fb.size());
       HIPCHK(hipMemcpyAsync(cfb.data(), d_cfb, fb.size() * 4, hipMemcpyDeviceToHost, h.stream));
-      HIPCHK(hipStreamSynchronize(h.stream));
+      HSYNC(h);
       for (size_t a = 0; a < fb.size(); ++a) cnt[fb_of[a] >= 0 ? sk_ids[fb_of[a]] : r2_ids[-1 - fb_of[a]]] = cfb[a];
     }
     // the full-path task list now holds every non-accepted task
@@ -1244,7 +1252,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   } else {
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(info.data(), d_info, nrec * 4, hipMemcpyDeviceToHost, h.stream));
-    HIPCHK(hipStreamSynchronize(h.stream));
+    HSYNC(h);
   }
   prof_collect(h);
   for (int k = 0; k < nrec; ++k)
@@ -1328,7 +1336,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       hipLaunchKernelGGL(k_gemm_batch, dim3((unsigned)((nmx + 63) / 64), (unsigned)((rmax + 63) / 64), (unsigned)ns2),
                          dim3(NT), 0, h.stream, d_vg);
     }
-    HIPCHK(hipStreamSynchronize(h.stream));  // host task tables above are temporaries
+    HSYNC(h);  // host task tables above are temporaries
     hipLaunchKernelGGL(k_basis, dim3(nchg), dim3(NT), 0, h.stream, V, d_chg);
     if ((rc = check_arena(h, l, "basis", c, err))) return rc;
   }
@@ -1476,7 +1484,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
           hipLaunchKernelGGL(k_phase_b_blocks<false>, dim3((unsigned)(b1 - b0)), dim3(NT), 0, h.stream, V, K, d_chg,
                              d_refs, d_far, (const PBTask*)h.scratch2, L.d_il_blk_old, L.d_ilcap_old);
         b0 = b1;
-        HIPCHK(hipStreamSynchronize(h.stream));  // the task table and buffer are reused / freed after this
+        HSYNC(h);  // the task table and buffer are reused / freed after this
       }
       }
     }
@@ -1513,7 +1521,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   h.stat_far += (int64_t)far.size();
   h.stat_changed += nchg;
   // the host tables above are uploaded asynchronously: wait before they go away
-  HIPCHK(hipStreamSynchronize(h.stream));
+  HSYNC(h);
   prof_collect(h);
   return 0;
 }
@@ -1635,6 +1643,7 @@ int factor(Handle& h, std::string& err) {
   h.prof_level = std::getenv("IFMM_PROF_LEVEL") != nullptr;
   if (const char* e = std::getenv("IFMM_SKETCH_MIN")) h.sketch_min = std::max(1, std::atoi(e));
   h.stat_sketch = h.stat_sketch_rejected = h.stat_sketch_narrow = 0;
+  h.t_sync = 0;
   h.rec_X.clear();
   h.rec_t.clear();
   h.stat_predicted = 0;

@@ -191,6 +191,7 @@ struct Handle {
   std::vector<float> rec_X, rec_t;                   // features (14 per row) and r_new / n
   std::vector<std::vector<int64_t>> pt_count;        // points in each node's box, per level
   int64_t stat_predicted = 0;
+  double t_sync = 0;  // time the host waited in stream synchronisations of the elimination
   // solve captured into a HIP graph, replayed while (nrhs, ld, rhs, x) repeat (IFMM_GRAPH=0 disables)
   bool graph_solve = true;
   hipStream_t batch_stream = nullptr;  // library-owned stream given by the batch calls
