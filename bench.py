@@ -152,6 +152,26 @@ def run_form(name, pts, dg, args, bt, xt, F, f_dev):
     return out, stats, x_first
 
 
+def measured_traffic(kernel, form):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    record (FETCH_SIZE / WRITE_SIZE scaled by the copy calibration), or None
+    when there is none or the kernel sources changed since it was taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1905_10602_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("dense.hpp", "kernels.hpp"):
+        with open(os.path.join(src, f), "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_hbm_traffic_*.json")):
+        with open(path) as fh:
+            rec = json.load(fh)
+        if rec.get("form") == form and rec.get("kernel_sources_sha256_16") == digest:
+            return rec["traffic_bytes_per_launch"]
+    return None
+
+
 def roofline_of(stats, mixed):
     """Roofline of the single kernel with the largest device time (profiler
     classes named "group:..." span several kernels and are skipped)."""
@@ -160,8 +180,10 @@ def roofline_of(stats, mixed):
         return None
     name, k = max(ks.items(), key=lambda kv: kv[1]["ms"])
     avg_s = k["ms"] / 1e3 / max(k["launches"], 1)
-    common = {"kernel": name, "traffic": None, "launches": k["launches"], "avg_launch_ms": avg_s * 1e3,
-              "algorithmic_per_launch": (k["bytes"] if BOUND.get(name) == "hbm" else k["flops"]) / max(k["launches"], 1)}
+    common = {"kernel": name, "traffic": measured_traffic(name, "mixed" if mixed else "fp64"),
+              "launches": k["launches"], "avg_launch_ms": avg_s * 1e3,
+              "algorithmic_per_launch": (k["bytes"] if BOUND.get(name) == "hbm" else k["flops"]) / max(k["launches"], 1),
+              "algorithmic_bytes_per_launch": k["bytes"] / max(k["launches"], 1)}
     if BOUND.get(name) == "hbm":
         ach = k["bytes"] / max(k["launches"], 1) / avg_s
         return {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",

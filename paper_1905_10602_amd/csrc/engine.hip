@@ -851,12 +851,13 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   LevelView V = view_of(L);
   const int nchg = (int)chg.size();
   // algorithmic work of the phase-A steps (counted from the block sizes)
-  double fl_lu = 0, fl_x = 0, fl_schur = 0, by_gather = 0;
+  double fl_lu = 0, fl_x = 0, fl_schur = 0, by_gather = 0, by_schur = 0;
   for (const ElimRec& R : recs) {
     const double d = R.d, n = R.n, M = R.M, r = R.r;
     fl_lu += 2.0 / 3.0 * d * d * d;
     fl_x += 2.0 * d * d * (M + r);
     fl_schur += 2.0 * M * n * (M + r);
+    by_schur += 8.0 * (M * n + (double)R.d * (M + r) + 2.0 * M * (M + r));  // L, X once; blocks read + written
     by_gather += 8.0 * (d * d + 2.0 * M * n) * 2.0;
   }
   double fl_gram = 0, fl_ev = 0, fl_evec = 0;
@@ -915,7 +916,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     hipLaunchKernelGGL(k_xsolve, dim3((unsigned)xtasks.size()), dim3(NT), 0, h.stream, d_recs, d_xt);
   }
   {
-    ProfScope ps(h, "k_schur", fl_schur, 0);
+    ProfScope ps(h, "k_schur", fl_schur, by_schur);
     if (h.precision == 1)
       hipLaunchKernelGGL(k_schur<true>, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks,
                          d_fidx, d_far);
