@@ -617,28 +617,41 @@ __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const do
     }
   }
   __syncthreads();
-  // two passes of modified Gram-Schmidt, largest eigenvalue first; dot
-  // products one wave per vector (lanes along the rows: coalesced)
+  // Orthonormalisation, largest eigenvalue first: block classical Gram-Schmidt
+  // with reorthogonalisation (blocks of 32 vectors projected against all
+  // earlier ones by two in-workgroup GEMMs, twice), then Gram-Schmidt inside
+  // the block.  IW (free after the inverse iteration) holds the coefficients.
   const int wave = tid >> 6, lane = tid & 63;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int j = 1; j < k; ++j) {
+  const bool blocked = (int64_t)n * k * 5 >= (int64_t)32 * k + (int64_t)n * 32 + 32 * 32 + 64;
+  for (int j0 = 0; j0 < k; j0 += 32) {
+    const int jb = min(32, k - j0);
+    if (j0 > 0 && blocked) {
+      for (int pass = 0; pass < 2; ++pass) {
+        wg_gemm(j0, jb, n, 1.0, X, ldx, true, X + (int64_t)j0 * ldx, ldx, false, 0.0, IW, j0);
+        wg_gemm(n, jb, j0, -1.0, X, ldx, false, IW, j0, false, 1.0, X + (int64_t)j0 * ldx, ldx);
+      }
+    }
+    const int jlo = blocked ? j0 : 0;
+    for (int j = j0; j < j0 + jb; ++j) {
       double* xj = X + (int64_t)j * ldx;
-      for (int i0 = 0; i0 < j; i0 += NT) {
-        const int cnt = min(NT, j - i0);
-        for (int i = i0 + wave; i < i0 + cnt; i += NT / 64) {
-          const double* xi = X + (int64_t)i * ldx;
-          double c = 0.0;
-          for (int r = lane; r < n; r += 64) c += xi[r] * xj[r];
-          for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-          if (lane == 0) s_c[i - i0] = c;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int i0 = jlo; i0 < j; i0 += NT) {
+          const int cnt = min(NT, j - i0);
+          for (int i = i0 + wave; i < i0 + cnt; i += NT / 64) {
+            const double* xi = X + (int64_t)i * ldx;
+            double c = 0.0;
+            for (int r = lane; r < n; r += 64) c += xi[r] * xj[r];
+            for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+            if (lane == 0) s_c[i - i0] = c;
+          }
+          __syncthreads();
+          for (int r = tid; r < n; r += NT) {
+            double v = xj[r];
+            for (int i = 0; i < cnt; ++i) v -= s_c[i] * X[r + (int64_t)(i0 + i) * ldx];
+            xj[r] = v;
+          }
+          __syncthreads();
         }
-        __syncthreads();
-        for (int r = tid; r < n; r += NT) {
-          double v = xj[r];
-          for (int i = 0; i < cnt; ++i) v -= s_c[i] * X[r + (int64_t)(i0 + i) * ldx];
-          xj[r] = v;
-        }
-        __syncthreads();
       }
       double part = 0.0;
       for (int r = tid; r < n; r += NT) part += xj[r] * xj[r];
@@ -648,23 +661,71 @@ __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const do
       __syncthreads();
     }
   }
-  // back-transform: X <- H_0 H_1 ... H_{n-3} X
-  for (int kk = n - 3; kk >= 0; --kk) {
-    if (tau[kk] == 0.0) continue;
-    const int m = n - kk - 1;
-    const double* v = A + (kk + 1) + (int64_t)kk * lda;
-    for (int j0 = 0; j0 < k; j0 += NT) {
-      const int cnt = min(NT, k - j0);
-      for (int j = j0 + wave; j < j0 + cnt; j += NT / 64) {
-        const double* xj = X + (kk + 1) + (int64_t)j * ldx;
-        double c = 0.0;
-        for (int r = lane; r < m; r += 64) c += v[r] * xj[r];
-        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-        if (lane == 0) s_c[j - j0] = c;
+  // back-transform X <- H_0 H_1 ... H_{n-3} X, H_q = I - tq vq vq^T (tq = 2 or 0):
+  // 32 reflectors at a time in compact WY form H_b0 ... H_b1-1 = I - V T V^T
+  // (T upper triangular), applied as W = V^T X, W = T W, X -= V W.
+  const int nref = n - 2;
+  if (blocked && nref >= 32) {
+    double* Vb = IW;                          // n x 32
+    double* Tb = IW + (int64_t)n * 32;         // 32 x 32
+    double* Wb = Tb + 32 * 32;                 // 32 x k
+    for (int b1 = nref; b1 > 0; b1 -= 32) {
+      const int b0 = max(0, b1 - 32), nb = b1 - b0;
+      // V: column q - b0 holds v_q in rows q+1..n-1, zeros above
+      WG_FOR2(n, nb, r, c) {
+        const int q = b0 + c;
+        Vb[r + (int64_t)c * n] = (r > q && tau[q] != 0.0) ? A[r + (int64_t)q * lda] : 0.0;
       }
       __syncthreads();
-      WG_FOR2(m, cnt, r, j) X[(kk + 1 + r) + (int64_t)(j0 + j) * ldx] -= 2.0 * s_c[j] * v[r];
+      // T: column c = -t_c T[0:c, 0:c] (V[:, 0:c]^T v_c), T[c][c] = t_c
+      for (int c = 0; c < nb; ++c) {
+        const double tc = tau[b0 + c] != 0.0 ? 2.0 : 0.0;
+        for (int i = wave; i < c; i += NT / 64) {
+          double g = 0.0;
+          for (int r = lane; r < n; r += 64) g += Vb[r + (int64_t)i * n] * Vb[r + (int64_t)c * n];
+          for (int off = 32; off > 0; off >>= 1) g += __shfl_xor(g, off, 64);
+          if (lane == 0) s_c[i] = g;
+        }
+        __syncthreads();
+        if (tid < c) {
+          double acc = 0.0;
+          for (int q = tid; q < c; ++q) acc += Tb[tid + q * 32] * s_c[q];
+          Tb[tid + c * 32] = -tc * acc;
+        }
+        if (tid == c) Tb[c + c * 32] = tc;
+        if (tid > c && tid < 32) Tb[tid + c * 32] = 0.0;
+        __syncthreads();
+      }
+      wg_gemm(nb, k, n, 1.0, Vb, n, true, X, ldx, false, 0.0, Wb, 32);          // W = V^T X
+      // W = T W (T upper triangular, in place by rows top-down)
+      for (int j = tid; j < k; j += NT) {
+        for (int i = 0; i < nb; ++i) {
+          double acc = 0.0;
+          for (int q = i; q < nb; ++q) acc += Tb[i + q * 32] * Wb[q + (int64_t)j * 32];
+          Wb[i + (int64_t)j * 32] = acc;
+        }
+      }
       __syncthreads();
+      wg_gemm(n, k, nb, -1.0, Vb, n, false, Wb, 32, false, 1.0, X, ldx);         // X -= V W
+    }
+  } else {
+    for (int kk = n - 3; kk >= 0; --kk) {
+      if (tau[kk] == 0.0) continue;
+      const int m = n - kk - 1;
+      const double* v = A + (kk + 1) + (int64_t)kk * lda;
+      for (int j0 = 0; j0 < k; j0 += NT) {
+        const int cnt = min(NT, k - j0);
+        for (int j = j0 + wave; j < j0 + cnt; j += NT / 64) {
+          const double* xj = X + (kk + 1) + (int64_t)j * ldx;
+          double c = 0.0;
+          for (int r = lane; r < m; r += 64) c += v[r] * xj[r];
+          for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+          if (lane == 0) s_c[j - j0] = c;
+        }
+        __syncthreads();
+        WG_FOR2(m, cnt, r, j) X[(kk + 1 + r) + (int64_t)(j0 + j) * ldx] -= 2.0 * s_c[j] * v[r];
+        __syncthreads();
+      }
     }
   }
 }
