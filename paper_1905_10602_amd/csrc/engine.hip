@@ -1418,7 +1418,13 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       ProfScope ps(h, "group:phase_b", fl_b, 0);
       int rmax = 0;
       for (const Changed& C : chg) rmax = std::max(rmax, std::max(C.r, C.rnew));
-      if (rmax <= 48) {  // one workgroup per changed node
+      int rlev = 0;
+      if (h.precision == 1 && rmax <= 32)
+        for (int32_t rv : L.r) rlev = std::max(rlev, rv);
+      if (h.precision == 1 && rmax <= 32 && rlev <= 32) {  // waves of one workgroup on separate blocks
+        hipLaunchKernelGGL(k_phase_b_wave, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far,
+                           l > 2 ? 1 : 0, L.d_il_blk_old, L.d_ilcap_old);
+      } else if (rmax <= 48) {  // one workgroup per changed node
         if (h.precision == 1)
           hipLaunchKernelGGL(k_phase_b<true>, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far,
                              l > 2 ? 1 : 0, L.d_il_blk_old, L.d_ilcap_old);

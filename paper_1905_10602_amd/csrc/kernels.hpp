@@ -1161,6 +1161,111 @@ __global__ void __launch_bounds__(NT) k_phase_b(LevelView V, int K, const Change
   }
 }
 
+// Mixed form, every rank of the level <= 32: one workgroup per changed node,
+// its four waves transform the blocks of the interaction list independently
+// (slot w, w + 4, ...) with FP32 matrix-core products of one 32 x 32 tile
+// (v_mfma_f32_32x32x2f32; lane l holds A[l % 32][k + l / 32] and
+// B[k + l / 32][l % 32], accumulator v holds D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]);
+// the intermediate S_p-side operand goes through a wave-private LDS tile.
+// Same arithmetic and owner rule as k_phase_b; M2M_p / L2L_p afterwards with
+// the workgroup products.
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// acc += A (m x k, global FP64) B (k x n, global FP64), one wave, m, n, k <= 32
+__device__ inline void wave_mm_gg(f32x16& acc, int m, int n, int k, const double* A, int lda, const double* B,
+                                  int ldb) {
+  const int lane = threadIdx.x & 63, i = lane & 31, kh = lane >> 5;
+  for (int k0 = 0; k0 < k; k0 += 2) {
+    const int kk = k0 + kh;
+    const float a = (i < m && kk < k) ? (float)A[i + (int64_t)kk * lda] : 0.0f;
+    const float b = (i < n && kk < k) ? (float)B[kk + (int64_t)i * ldb] : 0.0f;
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+  }
+}
+// acc += A (m x k, global FP64) Bl (k x n, wave LDS tile)
+__device__ inline void wave_mm_gl(f32x16& acc, int m, int n, int k, const double* A, int lda, const float (*Bl)[33]) {
+  const int lane = threadIdx.x & 63, i = lane & 31, kh = lane >> 5;
+  for (int k0 = 0; k0 < k; k0 += 2) {
+    const int kk = k0 + kh;
+    const float a = (i < m && kk < k) ? (float)A[i + (int64_t)kk * lda] : 0.0f;
+    const float b = (kk < k) ? Bl[kk][i] : 0.0f;
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+  }
+}
+__device__ inline void wave_acc_to_lds(const f32x16& acc, float (*Tl)[33]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) Tl[8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)][lane & 31] = acc[v];
+}
+// M (m x n, ld ldm) = acc + D (m x n, ld m; may be null)
+__device__ inline void wave_store(const f32x16& acc, int m, int n, double* M, int ldm, const double* D) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), j = lane & 31;
+    if (i < m && j < n) M[i + (int64_t)j * ldm] = (double)acc[v] + (D ? D[i + (int64_t)j * m] : 0.0);
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_phase_b_wave(LevelView V, int K, const Changed* chg, const FarRef* refs,
+                                                     const FarPair* far, int has_parent, double* const* blk_old,
+                                                     const int32_t* cap_old) {
+  __shared__ float tl[4][32][33];
+  const Changed C = chg[blockIdx.x];
+  const int p = C.p, r = C.r, rn = C.rnew, rcp = V.rc[p];
+  const int wave = threadIdx.x >> 6;
+  float (*Tl)[33] = tl[wave];
+  for (int s = V.il_ptr[p] + wave; s < V.il_ptr[p + 1]; s += NT / 64) {
+    const int l = V.il_idx[s];
+    const int rl = V.r[l], lc = V.chg[l];
+    const double* Mo = blk_old[s];
+    double* M = V.il_blk[s];
+    const int ldo = cap_old[p], ldn = V.ilcap[p];
+    const int rln = lc >= 0 ? chg[lc].rnew : rl;
+    // t = M (T_l), then M = S_p t (+ D)
+    f32x16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    if (lc >= 0) {
+      wave_mm_gg(acc, r, rln, rl, Mo, ldo, chg[lc].T, rl > 0 ? rl : 1);
+      wave_acc_to_lds(acc, Tl);
+    } else {
+      const int lane = threadIdx.x & 63;
+      for (int e = lane; e < 32 * 32; e += 64) {
+        const int i = e & 31, j = e >> 5;
+        Tl[i][j] = (i < r && j < rl) ? (float)Mo[i + (int64_t)j * ldo] : 0.0f;
+      }
+    }
+    wave_sync_lds();
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    wave_mm_gl(acc, rn, rln, r, C.S, rn > 0 ? rn : 1, Tl);
+    const int k = find_ref(refs, C.far_begin, C.far_count, l);
+    wave_store(acc, rn, rln, M, ldn, k >= 0 ? far[refs[k].ab].F : nullptr);
+    wave_sync_lds();
+    if (lc >= 0) continue;
+    // block (l, p) of the unchanged l: M T_p (+ D)
+    const int s2 = il_slot(V, l, p);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    wave_mm_gg(acc, rl, rn, r, blk_old[s2], cap_old[l], C.T, r > 0 ? r : 1);
+    wave_store(acc, rl, rn, V.il_blk[s2], V.ilcap[l], k >= 0 ? far[refs[k].ba].F : nullptr);
+  }
+  __syncthreads();
+  if (has_parent) {
+    double* t = C.tmp;
+    double* M2M = V.arena + V.m2m_off[p];
+    wg_gemm_f32(K, rn, r, 1.0, M2M, K, false, C.T, r > 0 ? r : 1, false, 0.0, t, K);
+    wg_copy(K, rn, t, K, M2M, K);
+    double* L2L = V.arena + V.l2l_off[p];
+    wg_gemm_f32(rn, K, r, 1.0, C.S, rn > 0 ? rn : 1, false, L2L, rcp, false, 0.0, t, rn > 0 ? rn : 1);
+    wg_copy(rn, K, t, rn > 0 ? rn : 1, L2L, rcp);
+  }
+}
+
 // One workgroup per transformed block: kind 0 = block (p, l) of changed p, kind 1 = block
 // (l, p) with l unchanged, kind 2 = M2M_p and L2L_p.  Each task brings its
 // own temporary.
