@@ -143,12 +143,13 @@ def run_form(name, pts, dg, args, bt, xt, F, f_dev):
     out = {"factor_s": med("factor_s"), "solve_ms_per_rhs": med("solve_s") * 1e3 / args.nrhs,
            "build_s": med("build_s"), "step_s": med("step_s"), "solve_residual_on_fmm": res, **gm,
            "sketches": stats.get("sketches"), "sketches_rejected": stats.get("sketches_rejected"),
-           "rank_predictions": stats.get("rank_predictions"), "t_sync": stats.get("t_sync"),
+           "rank_predictions": stats.get("rank_predictions"), "t_sync": stats.get("t_sync"), "t_h2d": stats.get("t_h2d"),
            "depth": stats.get("depth"), "top_n": stats.get("top_n"), "device_GB": stats.get("device_bytes", 0) / 1e9,
            "factor_store_GB": stats.get("store_bytes", 0) / 1e9,
            "levels": [{k2: L[k2] for k2 in ("level", "nodes", "colours", "rank_sum", "rank_max", "n_max", "t_elim")}
                       for L in stats.get("levels", [])],
-           "kernels_ms": {n: round(k["ms"], 3) for n, k in stats.get("kernels", {}).items()}}
+           "kernels_ms": {n: round(k["ms"], 3) for n, k in stats.get("kernels", {}).items()},
+           "host_ms": {n: round(v, 1) for n, v in stats.get("host_ms", {}).items()}}
     return out, stats, x_first
 
 

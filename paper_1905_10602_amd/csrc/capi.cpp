@@ -170,6 +170,7 @@ ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
                   ",\"sketches_narrow\":" + std::to_string(h.stat_sketch_narrow) +
                   ",\"rank_predictions\":" + std::to_string(h.stat_predicted) +
                   ",\"t_sync\":" + std::to_string(h.t_sync) +
+                  ",\"t_h2d\":" + std::to_string(h.t_h2d) +
                   ",\"levels\":[";
   for (int l = 2; l <= h.tree.depth; ++l) {
     const ifmm::Level& T = h.tree.levels[l];
@@ -192,6 +193,14 @@ ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
     std::snprintf(buf, sizeof buf, "%s\"%s\":{\"launches\":%lld,\"ms\":%.6f,\"flops\":%.6e,\"bytes\":%.6e}",
                   first ? "" : ",", kv.first.c_str(), (long long)kv.second.launches, kv.second.ms, kv.second.flops,
                   kv.second.bytes);
+    s += buf;
+    first = false;
+  }
+  s += "},\"host_ms\":{";
+  first = true;
+  for (const auto& kv : h.host_ms) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s\"%s\":%.3f", first ? "" : ",", kv.first.c_str(), kv.second);
     s += buf;
     first = false;
   }

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <numeric>
+#include <thread>
 
 #include "engine.hpp"
 #include "kernels.hpp"
@@ -44,9 +45,57 @@ namespace ifmm {
     (hh).t_sync += now_s() - t_s0_;                                   \
   } while (0)
 
+static double now_s();
+// host worker threads for table building: IFMM_HOST_THREADS, else the
+// hardware's count, at most 16
+static int host_threads() {
+  static const int n = [] {
+    int t = (int)std::thread::hardware_concurrency();
+    if (const char* e = std::getenv("IFMM_HOST_THREADS")) t = std::atoi(e);
+    return std::max(1, std::min(t > 0 ? t : 1, 16));
+  }();
+  return n;
+}
+// fn(chunk, begin, end) over [0, n) split into `chunks` contiguous ranges, in parallel
+template <class F>
+static void parallel_chunks(int n, int chunks, F&& fn) {
+  if (chunks <= 1) {
+    fn(0, 0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(chunks - 1);
+  for (int c = 1; c < chunks; ++c) {
+    const int b = (int)((int64_t)n * c / chunks), e = (int)((int64_t)n * (c + 1) / chunks);
+    th.emplace_back([&fn, c, b, e] { fn(c, b, e); });
+  }
+  fn(0, 0, (int)((int64_t)n / chunks));
+  for (auto& t : th) t.join();
+}
+// upload of a host table; the time the call holds the host is booked apart
+#define H2D(hh, dst, src, bytes)                                                          \
+  do {                                                                                   \
+    const double t_h0_ = now_s();                                                        \
+    HIPCHK(hipMemcpyAsync((dst), (src), (bytes), hipMemcpyHostToDevice, (hh).stream));   \
+    (hh).t_h2d += now_s() - t_h0_;                                                       \
+  } while (0)
+
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+// Host time of the factorisation split by phase: mark() books the time since
+// the previous mark, less the stream waits and table uploads in between.
+struct HostLap {
+  Handle& h;
+  double t, s;
+  explicit HostLap(Handle& hh) : h(hh), t(now_s()), s(hh.t_sync + hh.t_h2d) {}
+  void mark(const char* name) {
+    const double t1 = now_s();
+    h.host_ms[name] += 1e3 * ((t1 - t) - (h.t_sync + h.t_h2d - s));
+    t = t1;
+    s = h.t_sync + h.t_h2d;
+  }
+};
 
 // ------------------------------------------------------------------ device memory
 template <class T>
@@ -88,8 +137,8 @@ static int upload(Handle& h, T** p, const std::vector<T>& v, std::string& err) {
   int rc = dalloc(h, p, (int64_t)std::max<size_t>(v.size(), 1), err);
   if (rc) return rc;
   if (!v.empty()) {
-    HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h.stream));
-    HIPCHK(hipStreamSynchronize(h.stream));  // v may be a temporary
+    H2D(h, *p, v.data(), v.size() * sizeof(T));
+    HSYNC(h);  // v may be a temporary
   }
   return 0;
 }
@@ -116,7 +165,7 @@ static int store_take(Handle& h, int64_t doubles, double** out, std::string& err
 // growable scratch / meta buffers
 static int ensure(Handle& h, void** buf, int64_t* cap, int64_t bytes, std::string& err) {
   if (bytes <= *cap) return 0;
-  HIPCHK(hipStreamSynchronize(h.stream));
+  HSYNC(h);
   const int64_t nb = std::max<int64_t>(bytes, (*cap) * 3 / 2);
   dfree(h, *buf);
   *buf = nullptr;
@@ -395,8 +444,8 @@ static int reduce_level(Handle& h, int l, std::string& err) {
   EigTask* d_tasks = (EigTask*)(h.meta + o_t);
   int64_t* d_woff = (int64_t*)(h.meta + o_w);
   int32_t* d_cnt = (int32_t*)(h.meta + o_c);
-  HIPCHK(hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
-  HIPCHK(hipMemcpyAsync(d_woff, woff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, h.stream));
+  H2D(h, d_tasks, tasks.data(), tasks.size() * sizeof(EigTask));
+  H2D(h, d_woff, woff.data(), nn * sizeof(int64_t));
   LevelView V = view_of(L);
   const double* G = h.weights_G[l];
   if (nn > 0) {
@@ -410,8 +459,9 @@ static int reduce_level(Handle& h, int l, std::string& err) {
   }
   HIPCHK(hipGetLastError());
   std::vector<int32_t> cnt(tasks.size());
+  HSYNC(h);  // the copy below waits for the queue: accounted here
   if (nn > 0) HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * 4, hipMemcpyDeviceToHost, h.stream));
-  HIPCHK(hipStreamSynchronize(h.stream));
+  HSYNC(h);
   int64_t iw = 0;
   for (int32_t i = 0; i < nn; ++i) {
     int r = sym ? cnt[i] : std::max(cnt[2 * i], cnt[2 * i + 1]);
@@ -428,8 +478,8 @@ static int reduce_level(Handle& h, int l, std::string& err) {
       t.IW = h.scratch2 + iw;
       iw += 5LL * L.n[i] * L.r[i] + 32;
     }
-  HIPCHK(hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
-  HIPCHK(hipMemcpyAsync(L.d_r, L.r.data(), nn * 4, hipMemcpyHostToDevice, h.stream));
+  H2D(h, d_tasks, tasks.data(), tasks.size() * sizeof(EigTask));
+  H2D(h, L.d_r, L.r.data(), nn * 4);
   // M2L block pool sized from the ranks just found
   {
     const Level& T = h.tree.levels[l];
@@ -451,19 +501,19 @@ static int reduce_level(Handle& h, int l, std::string& err) {
     HIPCHK(hipGetLastError());
   }
   // M2L of the interaction pairs (needs T of every node: separate launch)
-  HIPCHK(hipStreamSynchronize(h.stream));
+  HSYNC(h);
   std::vector<int64_t> toff2(nn);
   for (int32_t i = 0; i < nn; ++i) toff2[i] = (int64_t)i * K * std::max(L.rcmax, 1);
   if ((rc = ensure(h, (void**)&h.meta, &h.meta_bytes, (int64_t)nn * 8 + 256, err))) return rc;
   int64_t* d_toff = (int64_t*)h.meta;
-  HIPCHK(hipMemcpyAsync(d_toff, toff2.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, h.stream));
+  H2D(h, d_toff, toff2.data(), nn * sizeof(int64_t));
   if ((rc = ensure(h, (void**)&h.scratch, &h.scratch_bytes, (int64_t)nn * K * std::max(L.rcmax, 1) * 8 + 64, err)))
     return rc;
   if (nn > 0) {
     hipLaunchKernelGGL(k_reduce_m2l, dim3(nn), dim3(NT), 0, h.stream, V, K, h.d_unit, 1.0 / side, h.scratch, d_toff);
     HIPCHK(hipGetLastError());
   }
-  HIPCHK(hipStreamSynchronize(h.stream));
+  HSYNC(h);
   return 0;
 }
 
@@ -520,14 +570,15 @@ static int rank_features(Handle& h, int l, std::vector<Changed>& chg, const std:
     t.n = C.n; t.s = 8; t.R = (int32_t)wrows[ids[a]]; t.chg = ids[a];
     t.seed = (uint32_t)(0x51ED + 2 * C.p); t.side = 0;
   }
-  HIPCHK(hipMemcpyAsync(d_t, tt.data(), nf * sizeof(SkTask), hipMemcpyHostToDevice, h.stream));
+  H2D(h, d_t, tt.data(), nf * sizeof(SkTask));
   hipLaunchKernelGGL(k_sk_omega, dim3(16, (unsigned)nf), dim3(NT), 0, h.stream, d_t);
   hipLaunchKernelGGL(k_sk_range, dim3((unsigned)((nmax + 63) / 64), 1, (unsigned)nf), dim3(NT), 0, h.stream, d_chg,
                      d_refs, d_far, d_nbrs, d_recs, d_t);
   hipLaunchKernelGGL(k_feat_sv, dim3((unsigned)nf), dim3(NT), 0, h.stream, d_t, d_sv);
   std::vector<double> sv(8 * nf);
+  HSYNC(h);  // the copy below waits for the queue: accounted here
   HIPCHK(hipMemcpyAsync(sv.data(), d_sv, sv.size() * 8, hipMemcpyDeviceToHost, h.stream));
-  HIPCHK(hipStreamSynchronize(h.stream));
+  HSYNC(h);
   const double half = h.tree.H / (double)(1 << l);
   for (size_t a = 0; a < nf; ++a) {
     const Changed& C = chg[ids[a]];
@@ -543,13 +594,14 @@ static int rank_features(Handle& h, int l, std::vector<Changed>& chg, const std:
     for (int i = 1; i < 8; ++i) f[6 + i] = (float)(std::log10(std::max(sv[8 * a + i], 1e-300) / s1) / 16.0);
   }
   if (h.d_model) {
-    HIPCHK(hipMemcpyAsync(d_X, feats.data(), feats.size() * 4, hipMemcpyHostToDevice, h.stream));
+    H2D(h, d_X, feats.data(), feats.size() * 4);
     if (mlp_forward_dev(h.d_model, RANK_NF, d_X, (int64_t)nf, d_y, d_mw, h.stream)) {
       err = "rank model forward failed";
       return -3;
     }
+    HSYNC(h);
     HIPCHK(hipMemcpyAsync(pred.data(), d_y, nf * 4, hipMemcpyDeviceToHost, h.stream));
-    HIPCHK(hipStreamSynchronize(h.stream));
+    HSYNC(h);
   }
   return 0;
 }
@@ -598,7 +650,7 @@ static int sk_orthonormalise(Handle& h, const std::vector<SkTask>& T, const SkTa
       g[((size_t)b * 2 + 1) * nt + a] = {t.Y, cptr[a], t.Y + (int64_t)j0 * t.n, t.n, bs, J0, t.n, t.s, t.n, 0, 0, -1.0,
                                          1.0};
     }
-  HIPCHK(hipMemcpyAsync(d_g, g.data(), g.size() * sizeof(GemmTask), hipMemcpyHostToDevice, h.stream));
+  H2D(h, d_g, g.data(), g.size() * sizeof(GemmTask));
   hipLaunchKernelGGL(k_sk_colnorm, dim3((unsigned)std::max(1, std::min(64, (smax + 3) / 4)), (unsigned)nt), dim3(NT), 0,
                      h.stream, d_T, n0, ldn0);
   for (int b = 0; b < nblk; ++b) {
@@ -623,6 +675,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   const int g0 = T.grp_ptr[c], g1 = T.grp_ptr[c + 1];
   const int nrec = g1 - g0;
   if (nrec == 0) return 0;
+  HostLap lap(h);
   // ---- records, neighbour entries, far pairs, changed nodes (host; sizes are known)
   std::vector<ElimRec> recs(nrec);
   std::vector<ElimNbr> nbrs;
@@ -645,39 +698,127 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   const int sides = sym ? 1 : 2;
   std::vector<ChgOff> coff;
   const int nbase = (int)L.nbrs.size();
-  for (int k = 0; k < nrec; ++k) {
-    const int i = T.grp[g0 + k];
-    ElimRec& R = recs[k];
-    R.node = i;
-    R.n = L.n[i];
-    R.r = L.r[i];
-    R.d = R.n + R.r;
-    R.nnb = T.nbr_ptr[i + 1] - T.nbr_ptr[i];
-    R.nb_begin = (int)nbrs.size();
-    int off = 0;
-    for (int s = T.nbr_ptr[i]; s < T.nbr_ptr[i + 1]; ++s) {
-      const int p = T.nbr[s];
-      ElimNbr B;
-      B.p = p;
-      B.elim = T.colour[p] < c ? 1 : 0;
-      B.m = B.elim ? L.r[p] : L.n[p];
-      B.off = off;
-      off += B.m;
-      // block (p, i) in p's near list, block (i, p) in i's
-      B.blk_pi = -1;
-      for (int t = L.near_ptr[p]; t < L.near_ptr[p + 1]; ++t)
-        if (L.near_idx[t] == i) B.blk_pi = L.near_off[t];
-      B.blk_ip = -1;
-      for (int t = L.near_ptr[i]; t < L.near_ptr[i + 1]; ++t)
-        if (L.near_idx[t] == p) B.blk_ip = L.near_off[t];
-      nbrs.push_back(B);
+  // topology and sizes per record, in parallel over contiguous record chunks
+  // (each chunk's entries are local; they are concatenated in record order)
+  struct Part {
+    std::vector<ElimNbr> nbrs;
+    std::vector<int32_t> far_idx;  // chunk-local far indices
+    std::vector<FarPair> far;
+    std::vector<SchurTask> tasks;
+    std::vector<XTask> xtasks;
+    bool bad = false;
+  };
+  const int nparts = std::max(1, std::min(host_threads(), nrec / 64));
+  std::vector<Part> parts(nparts);
+  std::vector<int> part_end(nparts);
+  parallel_chunks(nrec, nparts, [&](int pc, int k0, int k1) {
+    Part& P = parts[pc];
+    part_end[pc] = k1;
+    for (int k = k0; k < k1; ++k) {
+      const int i = T.grp[g0 + k];
+      ElimRec& R = recs[k];
+      R.node = i;
+      R.n = L.n[i];
+      R.r = L.r[i];
+      R.d = R.n + R.r;
+      R.nnb = T.nbr_ptr[i + 1] - T.nbr_ptr[i];
+      R.nb_begin = (int)P.nbrs.size();
+      int off = 0;
+      for (int s = T.nbr_ptr[i]; s < T.nbr_ptr[i + 1]; ++s) {
+        const int p = T.nbr[s];
+        ElimNbr B;
+        B.p = p;
+        B.elim = T.colour[p] < c ? 1 : 0;
+        B.m = B.elim ? L.r[p] : L.n[p];
+        B.off = off;
+        off += B.m;
+        // block (p, i) in p's near list, block (i, p) in i's
+        B.blk_pi = -1;
+        for (int t = L.near_ptr[p]; t < L.near_ptr[p + 1]; ++t)
+          if (L.near_idx[t] == i) B.blk_pi = L.near_off[t];
+        B.blk_ip = -1;
+        for (int t = L.near_ptr[i]; t < L.near_ptr[i + 1]; ++t)
+          if (L.near_idx[t] == p) B.blk_ip = L.near_off[t];
+        P.nbrs.push_back(B);
+      }
+      R.M = off;
+      R.far_base = (int)P.far_idx.size();
+      R.inv = R.d >= h.big_d ? 1 : 0;  // blocked path: X also carries the x-columns of D^-1
+      // far pairs (a, b) with dist(p_a, p_b) >= 2
+      const ElimNbr* E = &P.nbrs[R.nb_begin];
+      for (int a = 0; a < R.nnb; ++a)
+        for (int b = 0; b < R.nnb; ++b) {
+          if (T.dist(E[a].p, E[b].p) <= 1) {
+            P.far_idx.push_back(-1);
+            continue;
+          }
+          P.far_idx.push_back((int32_t)P.far.size());
+          FarPair F;
+          F.rec = k; F.a = a; F.b = b;
+          F.direct = (E[a].elim && E[b].elim) ? 1 : 0;
+          F.F = nullptr; F.D = nullptr;
+          // M2L block (p_a, p_b): p_b is in the interaction list of p_a
+          const int pa = E[a].p, pb = E[b].p;
+          int lo = T.il_ptr[pa], hi = T.il_ptr[pa + 1] - 1, found = -1;
+          while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            if (T.il[mid] == pb) { found = mid; break; }
+            if (T.il[mid] < pb) lo = mid + 1; else hi = mid - 1;
+          }
+          if (found < 0) {
+            P.bad = true;
+            return;
+          }
+          F.dst = L.il_blk[found];
+          F.dst_ld = L.ilcap[pa];
+          F.pad = 0;
+          P.far.push_back(F);
+        }
+      // schur tasks: one per neighbour row block plus the row R_z_i; large
+      // nodes get one task per (row block, column block) pair
+      const bool split = (int64_t)R.n * R.M >= (int64_t)64 * 1024;
+      for (int a = 0; a <= R.nnb; ++a) {
+        if (!split) {
+          P.tasks.push_back({k, a, -2, 0});
+        } else {
+          for (int b = -1; b < R.nnb; ++b) P.tasks.push_back({k, a, b, 0});
+        }
+      }
+      if (R.d < h.big_d)
+        for (int c0 = 0; c0 < R.M + R.r; c0 += 64) P.xtasks.push_back({k, c0});
     }
-    R.M = off;
-    R.far_base = (int)far_idx.size();
-    R.inv = R.d >= h.big_d ? 1 : 0;  // blocked path: X also carries the x-columns of D^-1
+  });
+  {
+    size_t nn = 0, nf = 0, nfi = 0, nt = 0, nx = 0;
+    for (const Part& P : parts) {
+      if (P.bad) {
+        err = "internal: far neighbour pair is not in the interaction list";
+        return -1;
+      }
+      nn += P.nbrs.size(); nf += P.far.size(); nfi += P.far_idx.size(); nt += P.tasks.size(); nx += P.xtasks.size();
+    }
+    nbrs.reserve(nn); far.reserve(nf); far_idx.reserve(nfi); tasks.reserve(nt); xtasks.reserve(nx);
+    int k0 = 0;
+    for (int pc = 0; pc < nparts; ++pc) {
+      Part& P = parts[pc];
+      const int nb0 = (int)nbrs.size(), fi0 = (int)far_idx.size(), f0 = (int)far.size();
+      for (int k = k0; k < part_end[pc]; ++k) {
+        recs[k].nb_begin += nb0;
+        recs[k].far_base += fi0;
+      }
+      k0 = part_end[pc];
+      nbrs.insert(nbrs.end(), P.nbrs.begin(), P.nbrs.end());
+      for (int32_t v : P.far_idx) far_idx.push_back(v < 0 ? v : v + f0);
+      far.insert(far.end(), P.far.begin(), P.far.end());
+      tasks.insert(tasks.end(), P.tasks.begin(), P.tasks.end());
+      xtasks.insert(xtasks.end(), P.xtasks.begin(), P.xtasks.end());
+    }
+  }
+  // scratch and persistent factor storage, in record order
+  for (int k = 0; k < nrec; ++k) {
+    ElimRec& R = recs[k];
     x_off[k] = stake((int64_t)R.d * (R.M + R.r + (R.inv ? R.n : 0)));
     dinv_off[k] = R.inv ? stake((int64_t)((R.d + BLU_NB - 1) / BLU_NB) * 2 * 4096) : 0;
-    // persistent factor data
     int rc;
     double* p;
     if ((rc = store_take(h, (int64_t)R.d * R.d, &R.lu, err))) return rc;
@@ -687,48 +828,6 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     if ((rc = store_take(h, (int64_t)R.n * R.M, &R.U, err))) return rc;
     R.wv = L.wv_total;
     L.wv_total += R.d;
-    // far pairs (a, b) with dist(p_a, p_b) >= 2
-    const ElimNbr* E = &nbrs[R.nb_begin];
-    for (int a = 0; a < R.nnb; ++a)
-      for (int b = 0; b < R.nnb; ++b) {
-        if (T.dist(E[a].p, E[b].p) <= 1) {
-          far_idx.push_back(-1);
-          continue;
-        }
-        far_idx.push_back((int32_t)far.size());
-        FarPair F;
-        F.rec = k; F.a = a; F.b = b;
-        F.direct = (E[a].elim && E[b].elim) ? 1 : 0;
-        F.F = nullptr; F.D = nullptr;
-        // M2L block (p_a, p_b): p_b is in the interaction list of p_a
-        const int pa = E[a].p, pb = E[b].p;
-        int lo = T.il_ptr[pa], hi = T.il_ptr[pa + 1] - 1, found = -1;
-        while (lo <= hi) {
-          const int mid = (lo + hi) >> 1;
-          if (T.il[mid] == pb) { found = mid; break; }
-          if (T.il[mid] < pb) lo = mid + 1; else hi = mid - 1;
-        }
-        if (found < 0) {
-          err = "internal: far neighbour pair is not in the interaction list";
-          return -1;
-        }
-        F.dst = L.il_blk[found];
-        F.dst_ld = L.ilcap[pa];
-        F.pad = 0;
-        far.push_back(F);
-      }
-    // schur tasks: one per neighbour row block plus the row R_z_i; large
-    // nodes get one task per (row block, column block) pair
-    const bool split = (int64_t)R.n * R.M >= (int64_t)64 * 1024;
-    for (int a = 0; a <= R.nnb; ++a) {
-      if (!split) {
-        tasks.push_back({k, a, -2, 0});
-      } else {
-        for (int b = -1; b < R.nnb; ++b) tasks.push_back({k, a, b, 0});
-      }
-    }
-    if (R.d < h.big_d)
-      for (int c0 = 0; c0 < R.M + R.r; c0 += 64) xtasks.push_back({k, c0});
   }
   // scratch for far pairs
   std::vector<int64_t> fF(far.size()), fD(far.size());
@@ -788,6 +887,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     etasks.push_back({C.gs, C.vs, C.ws, C.ls, nullptr, C.n, 0});
     if (!sym) etasks.push_back({C.gt, C.vt, C.wt, C.lt, nullptr, C.n, 0});
   }
+  lap.mark("tables");
   // ---- pack the tables into the meta buffer
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t o_recs = 0;
@@ -834,9 +934,9 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     std::memcpy(Hm + o_blu, blu.data(), blu.size() * sizeof(BluTask));
     std::memcpy(Hm + o_blur, blu_rec.data(), blu_rec.size() * 4);
   }
-  HIPCHK(hipMemcpyAsync(M, Hm, o_info, hipMemcpyHostToDevice, h.stream));
+  H2D(h, M, Hm, o_info);
   if (!blu.empty())
-    HIPCHK(hipMemcpyAsync(M + o_blu, Hm + o_blu, total - o_blu, hipMemcpyHostToDevice, h.stream));
+    H2D(h, M + o_blu, Hm + o_blu, total - o_blu);
   const ElimRec* d_recs = (const ElimRec*)(M + o_recs);
   const ElimNbr* d_nbrs = (const ElimNbr*)(M + o_nbrs);
   const SchurTask* d_tasks = (const SchurTask*)(M + o_tasks);
@@ -870,6 +970,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     fl_gram += sides * (double)C.n * (C.n + 1) * sm;  // symmetric product: lower triangle
     fl_ev += sides * 4.0 / 3.0 * (double)C.n * C.n * C.n;
   }
+  lap.mark("pack");
   // ---- phase A
   {
     ProfScope ps(h, "k_gather", 0, by_gather);
@@ -937,6 +1038,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
                          h.stream, V, d_chg, d_refs, d_far, d_nbrs, d_recs, sides);
     }
   }
+  lap.mark("launch_a");
   // ---- recompression: per changed node and side, either a sketch of width s
   // (predicted rank plus oversampling) or the full eigen-decomposition
   const int ne = (int)etasks.size();
@@ -1040,11 +1142,11 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     // Z = G Q (into O), B = Q^T Z
     for (const SkTask& t : skT) gT.push_back({t.G, t.Y, t.O, t.n, t.s, t.n, t.n, t.n, t.n, 0, 0, 1.0, 0.0});
     for (const SkTask& t : skT) gT.push_back({t.Y, t.O, t.B, t.s, t.s, t.n, t.n, t.n, t.s, 1, 0, 1.0, 0.0});
-    if (nfull) HIPCHK(hipMemcpyAsync(d_fullT, fullT.data(), nfull * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
+    if (nfull) H2D(h, d_fullT, fullT.data(), nfull * sizeof(EigTask));
     if (nsk) {
-      HIPCHK(hipMemcpyAsync(d_skE, skE.data(), nsk * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
-      HIPCHK(hipMemcpyAsync(d_skT, skT.data(), nsk * sizeof(SkTask), hipMemcpyHostToDevice, h.stream));
-      HIPCHK(hipMemcpyAsync(d_gT, gT.data(), 2 * nsk * sizeof(GemmTask), hipMemcpyHostToDevice, h.stream));
+      H2D(h, d_skE, skE.data(), nsk * sizeof(EigTask));
+      H2D(h, d_skT, skT.data(), nsk * sizeof(SkTask));
+      H2D(h, d_gT, gT.data(), 2 * nsk * sizeof(GemmTask));
     }
     const double eps2 = h.eps * h.eps;
     if (nsk) {
@@ -1082,6 +1184,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     cnt_full.assign(nfull, 0);
     cnt_sk.assign(nsk, 0);
     ok_sk.assign(nsk, 0);
+    lap.mark("plan_recomp");
+    HSYNC(h);  // the copies below wait for the queue: accounted here
     if (nfull) HIPCHK(hipMemcpyAsync(cnt_full.data(), d_cf, nfull * 4, hipMemcpyDeviceToHost, h.stream));
     if (nsk) {
       HIPCHK(hipMemcpyAsync(cnt_sk.data(), d_cs, nsk * 4, hipMemcpyDeviceToHost, h.stream));
@@ -1173,9 +1277,9 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       }
       for (const SkTask& t : r2T) g2.push_back({t.G, t.Y, t.O, t.n, t.s, t.n, t.n, t.n, t.n, 0, 0, 1.0, 0.0});
       for (const SkTask& t : r2T) g2.push_back({t.Y, t.O, t.B, t.s, t.s, t.n, t.n, t.n, t.s, 1, 0, 1.0, 0.0});
-      HIPCHK(hipMemcpyAsync(d_E2, r2E.data(), n2 * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
-      HIPCHK(hipMemcpyAsync(d_T2, r2T.data(), n2 * sizeof(SkTask), hipMemcpyHostToDevice, h.stream));
-      HIPCHK(hipMemcpyAsync(d_G2, g2.data(), 2 * n2 * sizeof(GemmTask), hipMemcpyHostToDevice, h.stream));
+      H2D(h, d_E2, r2E.data(), n2 * sizeof(EigTask));
+      H2D(h, d_T2, r2T.data(), n2 * sizeof(SkTask));
+      H2D(h, d_G2, g2.data(), 2 * n2 * sizeof(GemmTask));
       {
         double fl2 = 0;
         for (const SkTask& t : r2T)
@@ -1202,6 +1306,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       }
       std::vector<int32_t> c2(n2);
       r2_ok.assign(n2, 0);
+      HSYNC(h);
       HIPCHK(hipMemcpyAsync(c2.data(), d_c2, n2 * 4, hipMemcpyDeviceToHost, h.stream));
       HIPCHK(hipMemcpyAsync(r2_ok.data(), d_o2, n2 * 4, hipMemcpyDeviceToHost, h.stream));
       HSYNC(h);
@@ -1217,12 +1322,13 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       }
     }
     if (!fb.empty()) {
-      HIPCHK(hipMemcpyAsync(d_fbT, fb.data(), fb.size() * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
+      H2D(h, d_fbT, fb.data(), fb.size() * sizeof(EigTask));
       {
         ProfScope ps(h, "k_eig_values", 0, 0);
         hipLaunchKernelGGL(k_eig_values, dim3((unsigned)fb.size()), dim3(NT), 0, h.stream, d_fbT, eps2, d_cfb, 0);
       }
       std::vector<int32_t> cfb(fb.size());
+      HSYNC(h);
       HIPCHK(hipMemcpyAsync(cfb.data(), d_cfb, fb.size() * 4, hipMemcpyDeviceToHost, h.stream));
       HSYNC(h);
       for (size_t a = 0; a < fb.size(); ++a) cnt[fb_of[a] >= 0 ? sk_ids[fb_of[a]] : r2_ids[-1 - fb_of[a]]] = cfb[a];
@@ -1252,10 +1358,12 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     skT.swap(keepT);
   } else {
     HIPCHK(hipGetLastError());
+    HSYNC(h);
     HIPCHK(hipMemcpyAsync(info.data(), d_info, nrec * 4, hipMemcpyDeviceToHost, h.stream));
     HSYNC(h);
   }
   prof_collect(h);
+  lap.mark("select");
   for (int k = 0; k < nrec; ++k)
     if (info[k]) {
       err = "singular pivot block at level " + std::to_string(l) + ", node " + std::to_string(recs[k].node);
@@ -1312,12 +1420,12 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     EigTask* d_vf = (EigTask*)h.meta2b;
     EigTask* d_vs = d_vf + nf2;
     GemmTask* d_vg = (GemmTask*)(d_vs + ns2);
-    if (nf2) HIPCHK(hipMemcpyAsync(d_vf, fullT.data(), nf2 * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
+    if (nf2) H2D(h, d_vf, fullT.data(), nf2 * sizeof(EigTask));
     if (ns2) {
-      HIPCHK(hipMemcpyAsync(d_vs, skE.data(), ns2 * sizeof(EigTask), hipMemcpyHostToDevice, h.stream));
-      HIPCHK(hipMemcpyAsync(d_vg, vT.data(), ns2 * sizeof(GemmTask), hipMemcpyHostToDevice, h.stream));
+      H2D(h, d_vs, skE.data(), ns2 * sizeof(EigTask));
+      H2D(h, d_vg, vT.data(), ns2 * sizeof(GemmTask));
     }
-    HIPCHK(hipMemcpyAsync(d_chg, chg.data(), chg.size() * sizeof(Changed), hipMemcpyHostToDevice, h.stream));
+    H2D(h, d_chg, chg.data(), chg.size() * sizeof(Changed));
     for (int e : full_ids) fl_evec += 2.0 * (double)chg[e / sides].n * chg[e / sides].n * chg[e / sides].rnew;
     if (!h.eig_jacobi && nf2) {
       ProfScope ps(h, "k_eig_vectors", fl_evec, 0);
@@ -1337,6 +1445,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       hipLaunchKernelGGL(k_gemm_batch, dim3((unsigned)((nmx + 63) / 64), (unsigned)((rmax + 63) / 64), (unsigned)ns2),
                          dim3(NT), 0, h.stream, d_vg);
     }
+    lap.mark("plan_vectors");
     HSYNC(h);  // host task tables above are temporaries
     hipLaunchKernelGGL(k_basis, dim3(nchg), dim3(NT), 0, h.stream, V, d_chg);
     if ((rc = check_arena(h, l, "basis", c, err))) return rc;
@@ -1393,8 +1502,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       if ((rc = ensure(h, (void**)&h.meta2, &h.meta2_bytes, need, err))) return rc;
       SlotMove* d_mv = (SlotMove*)h.meta2;
       int32_t* d_cs = (int32_t*)(h.meta2 + ((moves.size() * sizeof(SlotMove) + 255) & ~(size_t)255));
-      HIPCHK(hipMemcpyAsync(d_mv, moves.data(), moves.size() * sizeof(SlotMove), hipMemcpyHostToDevice, h.stream));
-      HIPCHK(hipMemcpyAsync(d_cs, capset.data(), capset.size() * 4, hipMemcpyHostToDevice, h.stream));
+      H2D(h, d_mv, moves.data(), moves.size() * sizeof(SlotMove));
+      H2D(h, d_cs, capset.data(), capset.size() * 4);
       const int nm = (int)moves.size(), nc2 = (int)capset.size() / 2;
       hipLaunchKernelGGL(k_slot_moves, dim3((nm + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_il_blk, d_mv, nm);
       hipLaunchKernelGGL(k_set_caps, dim3((nc2 + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_ilcap, d_cs, nc2);
@@ -1406,6 +1515,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   if (!far.empty())
     hipLaunchKernelGGL(k_project, dim3((unsigned)far.size()), dim3(NT), 0, h.stream, V, d_far, d_recs, d_nbrs, d_chg);
   if ((rc = check_arena(h, l, "project", c, err))) return rc;
+  lap.mark("moves_project");
   // ---- phase B
   if (nchg) {
     {
@@ -1482,8 +1592,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
           pb[b].t = T0 + o;
           o += (pbsz[b] + 31) & ~31LL;
         }
-        HIPCHK(hipMemcpyAsync(h.scratch2, pb.data() + b0, (b1 - b0) * sizeof(PBTask), hipMemcpyHostToDevice,
-                              h.stream));
+        H2D(h, h.scratch2, pb.data() + b0, (b1 - b0) * sizeof(PBTask));
         if (h.precision == 1)
           hipLaunchKernelGGL(k_phase_b_blocks<true>, dim3((unsigned)(b1 - b0)), dim3(NT), 0, h.stream, V, K, d_chg,
                              d_refs, d_far, (const PBTask*)h.scratch2, L.d_il_blk_old, L.d_ilcap_old);
@@ -1508,6 +1617,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     for (const Changed& C : chg) L.r[C.p] = C.rnew;
   }
   HIPCHK(hipGetLastError());
+  lap.mark("phase_b");
   // keep the records for the solve (neighbour entries rebased on the level table)
   for (ElimRec R : recs) {
     R.nb_begin += nbase;
@@ -1527,9 +1637,11 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   L.cinv.push_back(ci);
   h.stat_far += (int64_t)far.size();
   h.stat_changed += nchg;
+  lap.mark("keep");
   // the host tables above are uploaded asynchronously: wait before they go away
   HSYNC(h);
   prof_collect(h);
+  lap.mark("tail");
   return 0;
 }
 
@@ -1569,7 +1681,7 @@ static int aggregate_level(Handle& h, int l, std::string& err) {
   hipLaunchKernelGGL(k_agg_near, dim3((unsigned)P.near_idx.size()), dim3(NT), 0, h.stream, VC, VF, P.d_slot_row,
                      P.d_child_ptr, P.d_child);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(h.stream));
+  HSYNC(h);
   if ((rc = check_arena(h, l - 1, "aggregation", -1, err))) return rc;
   release_level_work(h, l);
   if ((rc = reduce_level(h, l - 1, err))) return rc;
@@ -1601,7 +1713,7 @@ static int finish_level(Handle& h, int l, std::string& err) {
   dfree(h, L.d_vz_off);
   if ((rc = upload(h, &L.d_vx_off, L.vx_off, err))) return rc;
   if ((rc = upload(h, &L.d_vz_off, L.vz_off, err))) return rc;
-  HIPCHK(hipMemcpyAsync(L.d_r, L.r.data(), L.nn * 4, hipMemcpyHostToDevice, h.stream));
+  H2D(h, L.d_r, L.r.data(), L.nn * 4);
   return 0;
 }
 
@@ -1651,10 +1763,12 @@ int factor(Handle& h, std::string& err) {
   if (const char* e = std::getenv("IFMM_SKETCH_MIN")) h.sketch_min = std::max(1, std::atoi(e));
   h.stat_sketch = h.stat_sketch_rejected = h.stat_sketch_narrow = 0;
   h.t_sync = 0;
+  h.t_h2d = 0;
   h.rec_X.clear();
   h.rec_t.clear();
   h.stat_predicted = 0;
   h.kstat.clear();
+  h.host_ms.clear();
   h.stat_far = 0;
   h.stat_changed = 0;
   h.stat_grown = 0;
@@ -1662,7 +1776,11 @@ int factor(Handle& h, std::string& err) {
   h.t_level_setup.assign((size_t)h.tree.depth + 1, 0.0);
   h.t_level_elim.assign((size_t)h.tree.depth + 1, 0.0);
   double ta = now_s();
-  if ((rc = init_leaf_level(h, err))) return rc;
+  {
+    HostLap lp(h);
+    if ((rc = init_leaf_level(h, err))) return rc;
+    lp.mark("level_setup");
+  }
   h.t_level_setup[h.tree.depth] = now_s() - ta;
   for (int l = h.tree.depth; l >= 2; --l) {
     const Level& T = h.tree.levels[l];
@@ -1673,14 +1791,22 @@ int factor(Handle& h, std::string& err) {
     h.cur_level = l;
     for (int c = 0; c < T.ncolour; ++c)
       if ((rc = eliminate_colour(h, l, c, err))) return rc;
-    HIPCHK(hipStreamSynchronize(h.stream));
-    if ((rc = finish_level(h, l, err))) return rc;
+    HSYNC(h);
+    {
+      HostLap lp(h);
+      if ((rc = finish_level(h, l, err))) return rc;
+      lp.mark("finish_level");
+    }
     h.t_level_elim[l] = now_s() - ta;
     if (h.log)
       std::fprintf(stderr, "[ifmm] level %d: %d nodes, %d colours eliminated in %.3f s (set-up %.3f s)\n", l, T.n,
                    T.ncolour, h.t_level_elim[l], h.t_level_setup[l]);
     ta = now_s();
-    if (l > 2 && (rc = aggregate_level(h, l, err))) return rc;
+    {
+      HostLap lp(h);
+      if (l > 2 && (rc = aggregate_level(h, l, err))) return rc;
+      lp.mark("level_setup");
+    }
     if (l > 2) h.t_level_setup[l - 1] = now_s() - ta;
   }
   h.cur_level = 0;
@@ -1722,7 +1848,7 @@ int factor(Handle& h, std::string& err) {
   HIPCHK(hipGetLastError());
   int32_t info = 0;
   if (h.top_n > 0) HIPCHK(hipMemcpyAsync(&info, d_info, 4, hipMemcpyDeviceToHost, h.stream));
-  HIPCHK(hipStreamSynchronize(h.stream));
+  HSYNC(h);
   dfree(h, d_info);
   h.d_top_off = d_toff;
   release_level_work(h, 2);
@@ -1781,7 +1907,7 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
   double* d_x = x;
   if (!on_device) {
     double* io = B + oio;
-    HIPCHK(hipMemcpyAsync(io, rhs, (size_t)ld * k * 8, hipMemcpyHostToDevice, h.stream));
+    H2D(h, io, rhs, (size_t)ld * k * 8);
     d_rhs = io;
     d_x = io + ld * k;
   }

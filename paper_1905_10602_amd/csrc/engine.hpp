@@ -191,7 +191,8 @@ struct Handle {
   std::vector<float> rec_X, rec_t;                   // features (14 per row) and r_new / n
   std::vector<std::vector<int64_t>> pt_count;        // points in each node's box, per level
   int64_t stat_predicted = 0;
-  double t_sync = 0;  // time the host waited in stream synchronisations of the elimination
+  double t_sync = 0;
+  double t_h2d = 0;   // time the host spent inside table uploads of the factorisation  // time the host waited in stream synchronisations of the elimination
   // solve captured into a HIP graph, replayed while (nrhs, ld, rhs, x) repeat (IFMM_GRAPH=0 disables)
   bool graph_solve = true;
   hipStream_t batch_stream = nullptr;  // library-owned stream given by the batch calls
@@ -209,6 +210,7 @@ struct Handle {
     double ms = 0, flops = 0, bytes = 0;
   };
   std::map<std::string, KStat> kstat;
+  std::map<std::string, double> host_ms;  // host time of the factorisation by phase, stream waits excluded
   struct Pending {
     hipEvent_t a, b;
     std::string name;
