@@ -1528,10 +1528,12 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       ProfScope ps(h, "group:phase_b", fl_b, 0);
       int rmax = 0;
       for (const Changed& C : chg) rmax = std::max(rmax, std::max(C.r, C.rnew));
+      // wave form: every block a single 32 x 32 tile (all ranks involved <= 32),
+      // so each wave reads a block completely before it overwrites it in place
       int rlev = 0;
-      if (h.precision == 1 && rmax <= 32)
+      if (h.precision == 1 && h.pb_wave && rmax <= 32)
         for (int32_t rv : L.r) rlev = std::max(rlev, rv);
-      if (h.precision == 1 && rmax <= 32 && rlev <= 32) {  // waves of one workgroup on separate blocks
+      if (h.precision == 1 && h.pb_wave && rmax <= 32 && rlev <= 32) {
         hipLaunchKernelGGL(k_phase_b_wave, dim3(nchg), dim3(NT), 0, h.stream, V, K, d_chg, d_refs, d_far,
                            l > 2 ? 1 : 0, L.d_il_blk_old, L.d_ilcap_old);
       } else if (rmax <= 48) {  // one workgroup per changed node
@@ -1547,32 +1549,60 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       const Level& TL = h.tree.levels[l];
       std::vector<int32_t> chg_of(TL.n, -1);
       for (int k = 0; k < nchg; ++k) chg_of[chg[k].p] = k;
-      std::vector<PBTask> pb;
-      std::vector<int64_t> pbsz;
-      for (int k = 0; k < nchg; ++k) {
-        const Changed& C = chg[k];
-        const int p = C.p;
-        for (int s2 = TL.il_ptr[p]; s2 < TL.il_ptr[p + 1]; ++s2) {
-          const int lq = TL.il[s2];
-          const int lc = chg_of[lq];
-          const int rln = lc >= 0 ? chg[lc].rnew : L.r[lq];
-          pb.push_back({k, s2, 0, 0, nullptr});
-          pbsz.push_back((int64_t)std::max(C.r, 1) * std::max(rln, 1));
-          if (lc < 0) {
-            int lo = TL.il_ptr[lq], hi = TL.il_ptr[lq + 1] - 1, f = -1;
-            while (lo <= hi) {
-              const int mid = (lo + hi) >> 1;
-              if (TL.il[mid] == p) { f = mid; break; }
-              if (TL.il[mid] < p) lo = mid + 1; else hi = mid - 1;
+      // task table built on worker threads over changed-node ranges, joined in order
+      const int nparts = std::max(1, std::min(host_threads(), nchg / 32));
+      std::vector<std::vector<PBTask>> pbp(nparts);
+      std::vector<std::vector<int64_t>> pbszp(nparts);
+      std::vector<char> pbbad(nparts, 0);
+      parallel_chunks(nchg, nparts, [&](int pc, int k0, int k1) {
+        std::vector<PBTask>& pb = pbp[pc];
+        std::vector<int64_t>& pbsz = pbszp[pc];
+        for (int k = k0; k < k1; ++k) {
+          const Changed& C = chg[k];
+          const int p = C.p;
+          for (int s2 = TL.il_ptr[p]; s2 < TL.il_ptr[p + 1]; ++s2) {
+            const int lq = TL.il[s2];
+            const int lc = chg_of[lq];
+            const int rln = lc >= 0 ? chg[lc].rnew : L.r[lq];
+            pb.push_back({k, s2, 0, 0, nullptr});
+            pbsz.push_back((int64_t)std::max(C.r, 1) * std::max(rln, 1));
+            if (lc < 0) {
+              int lo = TL.il_ptr[lq], hi = TL.il_ptr[lq + 1] - 1, f = -1;
+              while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                if (TL.il[mid] == p) { f = mid; break; }
+                if (TL.il[mid] < p) lo = mid + 1; else hi = mid - 1;
+              }
+              if (f < 0) {
+                pbbad[pc] = 1;
+                return;
+              }
+              pb.push_back({k, f, 1, lq, nullptr});
+              pbsz.push_back((int64_t)std::max(L.r[lq], 1) * std::max(C.rnew, 1));
             }
-            if (f < 0) { err = "interaction lists not symmetric"; return -6; }
-            pb.push_back({k, f, 1, lq, nullptr});
-            pbsz.push_back((int64_t)std::max(L.r[lq], 1) * std::max(C.rnew, 1));
+          }
+          if (l > 2) {
+            pb.push_back({k, 0, 2, 0, nullptr});
+            pbsz.push_back((int64_t)K * std::max(C.rnew, 1) + (int64_t)std::max(C.rnew, 1) * K);
           }
         }
-        if (l > 2) {
-          pb.push_back({k, 0, 2, 0, nullptr});
-          pbsz.push_back((int64_t)K * std::max(C.rnew, 1) + (int64_t)std::max(C.rnew, 1) * K);
+      });
+      std::vector<PBTask> pb;
+      std::vector<int64_t> pbsz;
+      {
+        size_t tot = 0;
+        for (int pc = 0; pc < nparts; ++pc) {
+          if (pbbad[pc]) {
+            err = "interaction lists not symmetric";
+            return -6;
+          }
+          tot += pbp[pc].size();
+        }
+        pb.reserve(tot);
+        pbsz.reserve(tot);
+        for (int pc = 0; pc < nparts; ++pc) {
+          pb.insert(pb.end(), pbp[pc].begin(), pbp[pc].end());
+          pbsz.insert(pbsz.end(), pbszp[pc].begin(), pbszp[pc].end());
         }
       }
       const int64_t budget = (int64_t)256 << 20;  // doubles (2 GiB)
@@ -1759,6 +1789,7 @@ int factor(Handle& h, std::string& err) {
   if (const char* e = std::getenv("IFMM_GRAPH")) h.graph_solve = std::atoi(e) != 0;
   if (const char* e = std::getenv("IFMM_BIG_D")) h.big_d = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("IFMM_SKETCH")) h.sketch = std::atoi(e) != 0;
+  if (const char* e = std::getenv("IFMM_PB_WAVE")) h.pb_wave = std::atoi(e) != 0;
   h.prof_level = std::getenv("IFMM_PROF_LEVEL") != nullptr;
   if (const char* e = std::getenv("IFMM_SKETCH_MIN")) h.sketch_min = std::max(1, std::atoi(e));
   h.stat_sketch = h.stat_sketch_rejected = h.stat_sketch_narrow = 0;

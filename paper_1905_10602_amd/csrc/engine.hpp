@@ -171,6 +171,7 @@ struct Handle {
   // sketched recompression (randomised range finder with a rank guess; the
   // full eigen-decomposition remains the fall-back and the judge)
   bool sketch = true;       // IFMM_SKETCH=0 disables
+  bool pb_wave = true;      // IFMM_PB_WAVE=0: mixed-form phase B without the wave form
   int sketch_min = 128;     // Gram order from which a sketch is tried (IFMM_SKETCH_MIN)
   double* skbuf = nullptr;
   int64_t skbuf_bytes = 0;

@@ -1167,6 +1167,8 @@ __global__ void __launch_bounds__(NT) k_phase_b(LevelView V, int K, const Change
 // (v_mfma_f32_32x32x2f32; lane l holds A[l % 32][k + l / 32] and
 // B[k + l / 32][l % 32], accumulator v holds D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]);
 // the intermediate S_p-side operand goes through a wave-private LDS tile.
+// Every block is one tile and is read completely before it is written, which
+// keeps the update correct where a block is transformed in place.
 // Same arithmetic and owner rule as k_phase_b; M2M_p / L2L_p afterwards with
 // the workgroup products.
 __device__ inline void wave_sync_lds() {

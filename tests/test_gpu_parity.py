@@ -174,6 +174,30 @@ def test_mixed_precision_error_vs_oracle(shape, N, leaf, sigma, eps):
     assert not np.array_equal(x, x64)  # the FP32 path really ran
 
 
+def test_phase_b_wave_form_matches_workgroup_form(monkeypatch):
+    # mixed form: where every rank of a level is <= 32 the basis change of the
+    # M2L blocks runs one block per wave; with leaves of <= 32 points that is
+    # the case on the leaf level.  Against the one-workgroup-per-node form the
+    # solution differs only by FP32 rounding and the ranks chosen on every
+    # level stay the same (a block updated from stale data would shift them)
+    N, eps = 3000, 1e-6
+    print(f"case phase-B wave form ellipsoid N={N}", flush=True)
+    pts, dg = _case("ellipsoid", N, 7)
+    b = synth.uniform_rhs(N, 2, 17)
+    out = {}
+    for w in ("1", "0"):
+        monkeypatch.setenv("IFMM_PB_WAVE", w)
+        h = _gpu(pts, eps, 3, dg, 32, precision="mixed")
+        out[w] = (h.solve(b), [lv["rank_sum"] for lv in h.stats()["levels"]])
+    (x1, r1), (x0, r0) = out["1"], out["0"]
+    rel = np.linalg.norm(x1 - x0) / np.linalg.norm(x0)
+    print(f"wave vs workgroup: rel diff {rel:.3e}, rank sums {r1} vs {r0}", flush=True)
+    assert not np.array_equal(x1, x0)  # the wave form really ran
+    assert rel <= 20 * eps
+    for a, c in zip(r1, r0):
+        assert abs(a - c) <= 0.01 * c + 2
+
+
 @pytest.mark.parametrize("shape,N,leaf,sigma,eps", [("sphere", 4096, 64, 6, 1e-6), ("ellipsoid", 3000, 32, 3, 1e-6)])
 def test_sketched_recompression(monkeypatch, shape, N, leaf, sigma, eps):
     # Gram matrices of order >= 64 first try the randomised range finder with
