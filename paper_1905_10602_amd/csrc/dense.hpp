@@ -22,6 +22,33 @@ constexpr int NT = 256;           // threads per workgroup
            i##_di = (int)((unsigned)NT % (unsigned)(R)), i##_dc = (int)((unsigned)NT / (unsigned)(R)); \
        c < (C); i += i##_di, c += i##_dc, (i >= (R) ? (i -= (R), ++c) : 0))
 
+// Small product (m, n, k <= 32): both operands staged whole in LDS (the
+// caller's buffer of at least 2 * 32 * 33 doubles), one pass, no k-chunks.
+__device__ inline void wg_gemm_small(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
+                                     const double* B, int ldb, bool tB, double beta, double* C, int ldc,
+                                     double* smem) {
+  const int tid = threadIdx.x;
+  double (*As)[33] = reinterpret_cast<double (*)[33]>(smem);
+  double (*Bs)[33] = reinterpret_cast<double (*)[33]>(smem + 32 * 33);
+  for (int e = tid; e < m * k; e += NT) {
+    const int i = e % m, q = e / m;
+    As[i][q] = tA ? A[q + (int64_t)i * lda] : A[i + (int64_t)q * lda];
+  }
+  for (int e = tid; e < k * n; e += NT) {
+    const int q = e % k, j = e / k;
+    Bs[q][j] = tB ? B[j + (int64_t)q * ldb] : B[q + (int64_t)j * ldb];
+  }
+  __syncthreads();
+  for (int e = tid; e < m * n; e += NT) {
+    const int i = e % m, j = e / m;
+    double acc = 0.0;
+    for (int q = 0; q < k; ++q) acc = fma(As[i][q], Bs[q][j], acc);
+    double* c = C + i + (int64_t)j * ldc;
+    *c = (beta == 0.0) ? alpha * acc : fma(alpha, acc, beta * (*c));
+  }
+  __syncthreads();
+}
+
 // C(m x n) = alpha * op(A) * op(B) + beta * C, op = transpose if tA / tB.
 // op(A) is m x k, op(B) is k x n.  beta == 0 overwrites C (NaNs in C ignored).
 // LDS tiles of 64 x 16 (A) and 16 x 64 (B); each thread owns a 4 x 4 block
@@ -33,26 +60,7 @@ __device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* 
   double (*sB)[65] = reinterpret_cast<double (*)[65]>(smem + 16 * 65);
   const int tid = threadIdx.x;
   if (m <= 32 && n <= 32 && k <= 32) {
-    // small product: both operands staged whole in LDS, one pass, no k-chunks
-    double (*As)[33] = reinterpret_cast<double (*)[33]>(smem);
-    double (*Bs)[33] = reinterpret_cast<double (*)[33]>(smem + 32 * 33);
-    for (int e = tid; e < m * k; e += NT) {
-      const int i = e % m, q = e / m;
-      As[i][q] = tA ? A[q + (int64_t)i * lda] : A[i + (int64_t)q * lda];
-    }
-    for (int e = tid; e < k * n; e += NT) {
-      const int q = e % k, j = e / k;
-      Bs[q][j] = tB ? B[j + (int64_t)q * ldb] : B[q + (int64_t)j * ldb];
-    }
-    __syncthreads();
-    for (int e = tid; e < m * n; e += NT) {
-      const int i = e % m, j = e / m;
-      double acc = 0.0;
-      for (int q = 0; q < k; ++q) acc = fma(As[i][q], Bs[q][j], acc);
-      double* c = C + i + (int64_t)j * ldc;
-      *c = (beta == 0.0) ? alpha * acc : fma(alpha, acc, beta * (*c));
-    }
-    __syncthreads();
+    wg_gemm_small(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc, smem);
     return;
   }
   const int tr = tid & 15, tc = tid >> 4;
@@ -136,18 +144,18 @@ __device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* 
 // The same product with FP32 matrix cores: operands rounded to FP32 on their
 // way into LDS, FP32 accumulation (v_mfma_f32_32x32x2f32), the result
 // combined with C in FP64.  Each of the four waves owns a 32 x 32 quadrant of
-// the 64 x 64 output tile.  Operand lane layout of the 32x32x2 instruction:
+// the 64 x 64 output tile (formed transposed, B^T A^T, so that each lane owns
+// rows of C).  Operand lane layout of the 32x32x2 instruction:
 // lane l holds A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator register
 // v of lane l holds D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-__device__ inline void wg_gemm_f32(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
-                                   const double* B, int ldb, bool tB, double beta, double* C, int ldc) {
-  if (m <= 32 && n <= 32 && k <= 32) {  // too small for matrix cores: the FP64 one-pass product
-    wg_gemm(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc);
-    return;
-  }
-  __shared__ float fA[16][68];
-  __shared__ float fB[16][68];
+// 64 x 64 tiles, k-chunks of 16 through one LDS buffer pair (lds: at least
+// 2 x 16 x 68 floats), the next chunk prefetched into registers.
+__device__ inline void wg_gemm_f32_lite(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
+                                        const double* B, int ldb, bool tB, double beta, double* C, int ldc,
+                                        float* lds) {
+  float (*fA)[68] = reinterpret_cast<float (*)[68]>(lds);
+  float (*fB)[68] = reinterpret_cast<float (*)[68]>(lds + 16 * 68);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
@@ -191,28 +199,137 @@ __device__ inline void wg_gemm_f32(int m, int n, int k, double alpha, const doub
       for (int k0 = 0; k0 < k; k0 += 16) {
         const bool more = k0 + 16 < k;
         if (more) fetch(k0 + 16);
+        // transposed product (B^T A^T): lane l holds rows l % 32 of C
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 2) {
           const float a = fA[kk + (lane >> 5)][wr + (lane & 31)];
           const float b = fB[kk + (lane >> 5)][wc + (lane & 31)];
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b, a, acc, 0, 0, 0);
         }
         __syncthreads();
         if (more) stash();
         __syncthreads();
       }
+      const int gi = i0 + wr + (lane & 31);
+      if (gi < m) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int gi = i0 + wr + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int gj = j0 + wc + (lane & 31);
-        if (gi < m && gj < n) {
-          double* c = C + gi + (int64_t)gj * ldc;
-          *c = (beta == 0.0) ? alpha * (double)acc[v] : fma(alpha, (double)acc[v], beta * (*c));
+        for (int v = 0; v < 16; ++v) {
+          const int gj = j0 + wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          if (gj < n) {
+            double* c = C + gi + (int64_t)gj * ldc;
+            *c = (beta == 0.0) ? alpha * (double)acc[v] : fma(alpha, (double)acc[v], beta * (*c));
+          }
         }
       }
     }
   }
   __syncthreads();
+}
+
+// 64 x 64 tiles, k-chunks of 32 through two LDS buffer pairs (lds: at least
+// 2 x 2 x 32 x 65 floats): chunk c + 1 is loaded into registers while chunk c
+// is multiplied, then written to the other pair; one barrier per chunk.  Rows
+// padded to 65 floats (conflict-free column writes).  For long inner dimensions.
+__device__ inline void wg_gemm_f32_kc32(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
+                                        const double* B, int ldb, bool tB, double beta, double* C, int ldc,
+                                        float* lds) {
+  constexpr int KC = 32;
+  float (*fA)[KC][65] = reinterpret_cast<float (*)[KC][65]>(lds);
+  float (*fB)[KC][65] = reinterpret_cast<float (*)[KC][65]>(lds + 2 * KC * 65);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  for (int i0 = 0; i0 < m; i0 += 64) {
+    for (int j0 = 0; j0 < n; j0 += 64) {
+      f32x16 acc;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+      double ra[8], rb[8];
+      auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int e = tid + q * NT;
+          int ii, kk;
+          if (!tA) { ii = e & 63; kk = e >> 6; } else { kk = e & 31; ii = e >> 5; }
+          const int gi = i0 + ii, gk = k0 + kk;
+          ra[q] = (gi < m && gk < k) ? (tA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda]) : 0.0;
+          int kb, jb;
+          if (!tB) { kb = e & 31; jb = e >> 5; } else { jb = e & 63; kb = e >> 6; }
+          const int gk2 = k0 + kb, gj = j0 + jb;
+          rb[q] = (gk2 < k && gj < n) ? (tB ? B[gj + (int64_t)gk2 * ldb] : B[gk2 + (int64_t)gj * ldb]) : 0.0;
+        }
+      };
+      auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int e = tid + q * NT;
+          int ii, kk;
+          if (!tA) { ii = e & 63; kk = e >> 6; } else { kk = e & 31; ii = e >> 5; }
+          fA[buf][kk][ii] = (float)ra[q];
+          int kb, jb;
+          if (!tB) { kb = e & 31; jb = e >> 5; } else { jb = e & 63; kb = e >> 6; }
+          fB[buf][kb][jb] = (float)rb[q];
+        }
+      };
+      if (k > 0) {
+        fetch(0);
+        stash(0);
+      }
+      __syncthreads();
+      int buf = 0;
+      for (int k0 = 0; k0 < k; k0 += KC) {
+        const bool more = k0 + KC < k;
+        if (more) fetch(k0 + KC);
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 2) {
+          const float a = fA[buf][kk + (lane >> 5)][wr + (lane & 31)];
+          const float b = fB[buf][kk + (lane >> 5)][wc + (lane & 31)];
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b, a, acc, 0, 0, 0);
+        }
+        if (more) stash(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      }
+      const int gi = i0 + wr + (lane & 31);
+      if (gi < m) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int gj = j0 + wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          if (gj < n) {
+            double* c = C + gi + (int64_t)gj * ldc;
+            *c = (beta == 0.0) ? alpha * (double)acc[v] : fma(alpha, (double)acc[v], beta * (*c));
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// FP32 matrix-core product with the lite tile; one LDS buffer serves it and
+// the small FP64 product.
+__device__ inline void wg_gemm_f32(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
+                                   const double* B, int ldb, bool tB, double beta, double* C, int ldc) {
+  __shared__ double lbuf[2 * 32 * 33];  // >= 2 x 16 x 68 floats
+  if (m <= 32 && n <= 32 && k <= 32) {  // too small for matrix cores: the FP64 one-pass product
+    wg_gemm_small(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc, lbuf);
+    return;
+  }
+  wg_gemm_f32_lite(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc, reinterpret_cast<float*>(lbuf));
+}
+
+// The same for kernels whose products have long inner dimensions: k >= 96
+// takes the double-buffered tile (more LDS and registers, hence its own
+// kernel instances), shorter ones the lite tile in the same buffer.
+__device__ inline void wg_gemm_f32_deep(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
+                                        const double* B, int ldb, bool tB, double beta, double* C, int ldc) {
+  __shared__ double lbuf[2 * 32 * 65];  // 2 x 2 x 32 x 65 floats
+  if (m <= 32 && n <= 32 && k <= 32) {
+    wg_gemm_small(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc, lbuf);
+    return;
+  }
+  if (k < 96) wg_gemm_f32_lite(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc, reinterpret_cast<float*>(lbuf));
+  else wg_gemm_f32_kc32(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc, reinterpret_cast<float*>(lbuf));
 }
 
 // precision switch of the Schur-complement and basis-change products

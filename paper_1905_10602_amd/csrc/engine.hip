@@ -1018,12 +1018,13 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   }
   {
     ProfScope ps(h, "k_schur", fl_schur, by_schur);
-    if (h.precision == 1)
-      hipLaunchKernelGGL(k_schur<true>, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks,
-                         d_fidx, d_far);
-    else
-      hipLaunchKernelGGL(k_schur<false>, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs,
-                         d_tasks, d_fidx, d_far);
+    // inner dimension of the products = n of the pivot: the double-buffered
+    // FP32 tile where some pivot of the colour is large
+    int nmx = 0;
+    for (const ElimRec& R : recs) nmx = std::max(nmx, R.n);
+    auto ks = h.precision != 1 ? k_schur<false, false> : nmx >= 128 ? k_schur<true, true> : k_schur<true, false>;
+    hipLaunchKernelGGL(ks, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks, d_fidx,
+                       d_far);
   }
   if ((rc = check_arena(h, l, "schur", c, err))) return rc;
   if (nchg) {
@@ -2207,13 +2208,15 @@ __global__ void __launch_bounds__(NT) k_internal_gemm(int m, int n, int k, doubl
   if (mm <= 0 || nn <= 0) return;
   const double* Ab = tA ? A + (int64_t)i0 * lda : A + i0;
   const double* Bb = tB ? B + j0 : B + (int64_t)j0 * ldb;
-  wg_gemm_p(f32 != 0, mm, nn, k, alpha, Ab, lda, tA != 0, Bb, ldb, tB != 0, beta, C + i0 + (int64_t)j0 * ldc, ldc);
+  if (f32 == 2) wg_gemm_f32_deep(mm, nn, k, alpha, Ab, lda, tA != 0, Bb, ldb, tB != 0, beta, C + i0 + (int64_t)j0 * ldc, ldc);
+  else wg_gemm_p(f32 != 0, mm, nn, k, alpha, Ab, lda, tA != 0, Bb, ldb, tB != 0, beta, C + i0 + (int64_t)j0 * ldc, ldc);
 }
 }  // namespace ifmm
 
 // Test hook (not part of the declared ABI): C = alpha op(A) op(B) + beta C on
 // host arrays (column-major, tight leading dimensions) with the FP64 (f32 = 0)
-// or FP32 matrix-core (f32 = 1) workgroup product, one workgroup per 64 x 64 tile.
+// or FP32 matrix-core workgroup product (f32 = 1: the lite tile; f32 = 2: the
+// double-buffered tile from inner dimension 96 on), one workgroup per 64 x 64 tile.
 extern "C" int ifmm_internal_gemm(int m, int n, int k, double alpha, const double* A, int tA, const double* B, int tB,
                                   double beta, double* C, int f32) {
   using namespace ifmm;

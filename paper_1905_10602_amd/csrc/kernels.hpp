@@ -928,7 +928,16 @@ __global__ void __launch_bounds__(NT) k_bu_gemm(const BluTask* tasks, int jb) {
 struct SchurTask {
   int32_t rec, a, b, pad;
 };
-template <bool f32>
+// product of the Schur update: FP64, FP32 lite tile, or FP32 with the
+// double-buffered tile for long inner dimensions (own kernel instances)
+template <bool f32, bool deep>
+__device__ inline void schur_gemm(int m, int n, int k, double alpha, const double* A, int lda, const double* B,
+                                  int ldb, double beta, double* C, int ldc) {
+  if (!f32) wg_gemm(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc);
+  else if (deep) wg_gemm_f32_deep(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc);
+  else wg_gemm_f32(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc);
+}
+template <bool f32, bool deep>
 __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const ElimNbr* nbrs, const int32_t* far_idx,
                                    const FarPair* far, int a, int b) {
   const int i = R.node, n = R.n, r = R.r, d = R.d, M = R.M;
@@ -941,11 +950,11 @@ __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const E
       const double* Xb = R.X + (int64_t)B.off * d;
       const int fi = far_idx[R.far_base + a * R.nnb + b];
       if (fi < 0)
-        wg_gemm_p(f32, A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 1.0, V.arena + near_block(V, A.p, B.p), np);
-      else wg_gemm_p(f32, A.m, B.m, n, -1.0, La, M, false, Xb, d, false, 0.0, far[fi].F, A.m);
+        schur_gemm<f32, deep>(A.m, B.m, n, -1.0, La, M, Xb, d, 1.0, V.arena + near_block(V, A.p, B.p), np);
+      else schur_gemm<f32, deep>(A.m, B.m, n, -1.0, La, M, Xb, d, 0.0, far[fi].F, A.m);
     } else {
       // new block (p, i) = L_a F   with [F; H] = D^-1 [0; I]
-      wg_gemm_p(f32, A.m, r, n, 1.0, La, M, false, R.X + (int64_t)M * d, d, false, 0.0, V.arena + A.blk_pi, np);
+      schur_gemm<f32, deep>(A.m, r, n, 1.0, La, M, R.X + (int64_t)M * d, d, 0.0, V.arena + A.blk_pi, np);
     }
   } else {
     if (b >= 0) {
@@ -956,16 +965,16 @@ __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const E
     }
   }
 }
-template <bool f32>
+template <bool f32, bool deep>
 __global__ void __launch_bounds__(NT) k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs,
                                               const SchurTask* tasks, const int32_t* far_idx, const FarPair* far) {
   const SchurTask T = tasks[blockIdx.x];
   const ElimRec R = recs[T.rec];
   if (T.b == -2) {
-    for (int b = 0; b < R.nnb; ++b) schur_block<f32>(V, R, nbrs, far_idx, far, T.a, b);
-    schur_block<f32>(V, R, nbrs, far_idx, far, T.a, -1);
+    for (int b = 0; b < R.nnb; ++b) schur_block<f32, deep>(V, R, nbrs, far_idx, far, T.a, b);
+    schur_block<f32, deep>(V, R, nbrs, far_idx, far, T.a, -1);
   } else {
-    schur_block<f32>(V, R, nbrs, far_idx, far, T.a, T.b);
+    schur_block<f32, deep>(V, R, nbrs, far_idx, far, T.a, T.b);
   }
 }
 

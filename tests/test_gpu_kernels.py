@@ -103,8 +103,9 @@ def test_syev_on_ifmm_gram_matrices():
 
 @pytest.mark.parametrize("m,n,k,tA,tB", [(64, 64, 64, 0, 0), (130, 70, 33, 0, 0), (5, 200, 300, 1, 0),
                                          (77, 9, 1, 0, 1), (100, 100, 0, 1, 1), (20, 30, 7, 0, 0),
-                                         (32, 32, 32, 1, 1), (9, 3, 32, 1, 0)])
-@pytest.mark.parametrize("f32", [0, 1])
+                                         (32, 32, 32, 1, 1), (9, 3, 32, 1, 0), (100, 90, 129, 0, 1),
+                                         (70, 130, 96, 1, 0), (64, 64, 95, 0, 0)])
+@pytest.mark.parametrize("f32", [0, 1, 2])
 def test_workgroup_gemm_fp64_and_fp32_matrix_cores(m, n, k, tA, tB, f32):
     lib = C.CDLL(os.path.join(ROOT, "paper_1905_10602_amd", "libifmm.so"))
     f = lib.ifmm_internal_gemm
