@@ -43,6 +43,7 @@ namespace ifmm {
     const double t_s0_ = now_s();                                     \
     HIPCHK(hipStreamSynchronize((hh).stream));                        \
     (hh).t_sync += now_s() - t_s0_;                                   \
+    (hh).hold.clear();                                                \
   } while (0)
 
 static double now_s();
@@ -160,6 +161,16 @@ static int store_take(Handle& h, int64_t doubles, double** out, std::string& err
   h.store_left -= doubles;
   h.store_bytes += doubles * 8;
   return 0;
+}
+
+// A copy of a host table that stays alive until the next stream
+// synchronisation: the source of an upload that the host does not wait for.
+template <class T>
+static const T* held(Handle& h, const std::vector<T>& v) {
+  auto c = std::make_shared<std::vector<T>>(v);
+  const T* p = c->data();
+  h.hold.push_back(std::move(c));
+  return p;
 }
 
 // growable scratch / meta buffers
@@ -1421,12 +1432,13 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     EigTask* d_vf = (EigTask*)h.meta2b;
     EigTask* d_vs = d_vf + nf2;
     GemmTask* d_vg = (GemmTask*)(d_vs + ns2);
-    if (nf2) H2D(h, d_vf, fullT.data(), nf2 * sizeof(EigTask));
+    // uploads the host does not wait for (the sources are held)
+    if (nf2) H2D(h, d_vf, held(h, fullT), nf2 * sizeof(EigTask));
     if (ns2) {
-      H2D(h, d_vs, skE.data(), ns2 * sizeof(EigTask));
-      H2D(h, d_vg, vT.data(), ns2 * sizeof(GemmTask));
+      H2D(h, d_vs, held(h, skE), ns2 * sizeof(EigTask));
+      H2D(h, d_vg, held(h, vT), ns2 * sizeof(GemmTask));
     }
-    H2D(h, d_chg, chg.data(), chg.size() * sizeof(Changed));
+    H2D(h, d_chg, held(h, chg), chg.size() * sizeof(Changed));
     for (int e : full_ids) fl_evec += 2.0 * (double)chg[e / sides].n * chg[e / sides].n * chg[e / sides].rnew;
     if (!h.eig_jacobi && nf2) {
       ProfScope ps(h, "k_eig_vectors", fl_evec, 0);
@@ -1447,7 +1459,6 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
                          dim3(NT), 0, h.stream, d_vg);
     }
     lap.mark("plan_vectors");
-    HSYNC(h);  // host task tables above are temporaries
     hipLaunchKernelGGL(k_basis, dim3(nchg), dim3(NT), 0, h.stream, V, d_chg);
     if ((rc = check_arena(h, l, "basis", c, err))) return rc;
   }
@@ -1503,8 +1514,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       if ((rc = ensure(h, (void**)&h.meta2, &h.meta2_bytes, need, err))) return rc;
       SlotMove* d_mv = (SlotMove*)h.meta2;
       int32_t* d_cs = (int32_t*)(h.meta2 + ((moves.size() * sizeof(SlotMove) + 255) & ~(size_t)255));
-      H2D(h, d_mv, moves.data(), moves.size() * sizeof(SlotMove));
-      H2D(h, d_cs, capset.data(), capset.size() * 4);
+      H2D(h, d_mv, held(h, moves), moves.size() * sizeof(SlotMove));
+      H2D(h, d_cs, held(h, capset), capset.size() * 4);
       const int nm = (int)moves.size(), nc2 = (int)capset.size() / 2;
       hipLaunchKernelGGL(k_slot_moves, dim3((nm + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_il_blk, d_mv, nm);
       hipLaunchKernelGGL(k_set_caps, dim3((nc2 + NT - 1) / NT), dim3(NT), 0, h.stream, L.d_ilcap, d_cs, nc2);
@@ -1623,7 +1634,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
           pb[b].t = T0 + o;
           o += (pbsz[b] + 31) & ~31LL;
         }
-        H2D(h, h.scratch2, pb.data() + b0, (b1 - b0) * sizeof(PBTask));
+        const bool last = b1 == pb.size();
+        H2D(h, h.scratch2, last ? held(h, pb) + b0 : pb.data() + b0, (b1 - b0) * sizeof(PBTask));
         if (h.precision == 1)
           hipLaunchKernelGGL(k_phase_b_blocks<true>, dim3((unsigned)(b1 - b0)), dim3(NT), 0, h.stream, V, K, d_chg,
                              d_refs, d_far, (const PBTask*)h.scratch2, L.d_il_blk_old, L.d_ilcap_old);
@@ -1631,7 +1643,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
           hipLaunchKernelGGL(k_phase_b_blocks<false>, dim3((unsigned)(b1 - b0)), dim3(NT), 0, h.stream, V, K, d_chg,
                              d_refs, d_far, (const PBTask*)h.scratch2, L.d_il_blk_old, L.d_ilcap_old);
         b0 = b1;
-        HSYNC(h);  // the task table and buffer are reused / freed after this
+        if (!last) HSYNC(h);  // the next chunk reuses the task table and buffer
       }
       }
     }
@@ -1669,10 +1681,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   h.stat_far += (int64_t)far.size();
   h.stat_changed += nchg;
   lap.mark("keep");
-  // the host tables above are uploaded asynchronously: wait before they go away
-  HSYNC(h);
-  prof_collect(h);
-  lap.mark("tail");
+  // no wait here: the host goes on to the next colour's tables while the
+  // device finishes this one (pending uploads read held copies)
   return 0;
 }
 
@@ -1824,6 +1834,7 @@ int factor(Handle& h, std::string& err) {
     for (int c = 0; c < T.ncolour; ++c)
       if ((rc = eliminate_colour(h, l, c, err))) return rc;
     HSYNC(h);
+    prof_collect(h);
     {
       HostLap lp(h);
       if ((rc = finish_level(h, l, err))) return rc;

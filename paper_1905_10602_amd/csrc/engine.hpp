@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -193,7 +194,10 @@ struct Handle {
   std::vector<std::vector<int64_t>> pt_count;        // points in each node's box, per level
   int64_t stat_predicted = 0;
   double t_sync = 0;
-  double t_h2d = 0;   // time the host spent inside table uploads of the factorisation  // time the host waited in stream synchronisations of the elimination
+  double t_h2d = 0;
+  // host copies of tables whose uploads may still be in flight: released at
+  // the next stream synchronisation of the factorisation
+  std::vector<std::shared_ptr<void>> hold;   // time the host spent inside table uploads of the factorisation  // time the host waited in stream synchronisations of the elimination
   // solve captured into a HIP graph, replayed while (nrhs, ld, rhs, x) repeat (IFMM_GRAPH=0 disables)
   bool graph_solve = true;
   hipStream_t batch_stream = nullptr;  // library-owned stream given by the batch calls
