@@ -149,6 +149,9 @@ def run_form(name, pts, dg, args, bt, xt, F, f_dev):
            "levels": [{k2: L[k2] for k2 in ("level", "nodes", "colours", "rank_sum", "rank_max", "n_max", "t_elim")}
                       for L in stats.get("levels", [])],
            "kernels_ms": {n: round(k["ms"], 3) for n, k in stats.get("kernels", {}).items()},
+           "kernels_rate": {n: {"TFLOP/s": round(k["flops"] / k["ms"] / 1e9, 2) if k["flops"] else None,
+                                "GB/s": round(k["bytes"] / k["ms"] / 1e6, 1) if k["bytes"] else None}
+                            for n, k in stats.get("kernels", {}).items() if k["ms"] > 0},
            "host_ms": {n: round(v, 1) for n, v in stats.get("host_ms", {}).items()}}
     return out, stats, x_first
 

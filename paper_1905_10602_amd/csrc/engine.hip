@@ -661,7 +661,7 @@ static int sk_orthonormalise(Handle& h, const std::vector<SkTask>& T, const SkTa
       g[((size_t)b * 2 + 1) * nt + a] = {t.Y, cptr[a], t.Y + (int64_t)j0 * t.n, t.n, bs, J0, t.n, t.s, t.n, 0, 0, -1.0,
                                          1.0};
     }
-  H2D(h, d_g, g.data(), g.size() * sizeof(GemmTask));
+  H2D(h, d_g, held(h, g), g.size() * sizeof(GemmTask));
   hipLaunchKernelGGL(k_sk_colnorm, dim3((unsigned)std::max(1, std::min(64, (smax + 3) / 4)), (unsigned)nt), dim3(NT), 0,
                      h.stream, d_T, n0, ldn0);
   for (int b = 0; b < nblk; ++b) {
@@ -675,7 +675,6 @@ static int sk_orthonormalise(Handle& h, const std::vector<SkTask>& T, const SkTa
     }
     hipLaunchKernelGGL(k_sk_orth_block, dim3((unsigned)nt), dim3(NT), 0, h.stream, d_T, b * 64, drop, n0, ldn0);
   }
-  HSYNC(h);  // the host table above is a temporary
   return 0;
 }
 
@@ -786,13 +785,22 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
           P.far.push_back(F);
         }
       // schur tasks: one per neighbour row block plus the row R_z_i; large
-      // nodes get one task per (row block, column block) pair
+      // nodes get one task per (row block, column block) pair, and those
+      // with long products (n >= 128) one per 64 x 64 output tile of each
+      // pair (the blocks of the row R_z_i stay whole)
       const bool split = (int64_t)R.n * R.M >= (int64_t)64 * 1024;
       for (int a = 0; a <= R.nnb; ++a) {
         if (!split) {
-          P.tasks.push_back({k, a, -2, 0});
+          P.tasks.push_back({k, a, -2, -1});
+        } else if (a == R.nnb || R.n < 128) {
+          for (int b = -1; b < R.nnb; ++b) P.tasks.push_back({k, a, b, -1});
         } else {
-          for (int b = -1; b < R.nnb; ++b) P.tasks.push_back({k, a, b, 0});
+          const int mt = (E[a].m + 63) / 64;
+          for (int b = -1; b < R.nnb; ++b) {
+            const int nt = ((b >= 0 ? E[b].m : R.r) + 63) / 64;
+            for (int tj = 0; tj < nt; ++tj)
+              for (int ti = 0; ti < mt; ++ti) P.tasks.push_back({k, a, b, ti | (tj << 16)});
+          }
         }
       }
       if (R.d < h.big_d)
@@ -985,7 +993,14 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   // ---- phase A
   {
     ProfScope ps(h, "k_gather", 0, by_gather);
-    hipLaunchKernelGGL(k_gather, dim3(nrec), dim3(NT), 0, h.stream, V, d_recs, d_nbrs);
+    int wmax = 1, pmax = 1;
+    for (const ElimRec& R : recs) {
+      wmax = std::max(wmax, R.d);
+      pmax = std::max(pmax, 1 + R.nnb);
+    }
+    for (const ElimNbr& B : nbrs) wmax = std::max(wmax, B.m);
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)nrec, (unsigned)pmax, (unsigned)((wmax + GATHER_COLS - 1) / GATHER_COLS)),
+                       dim3(NT), 0, h.stream, V, d_recs, d_nbrs);
   }
   if ((rc = check_arena(h, l, "gather", c, err))) return rc;
   {
@@ -1459,7 +1474,10 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
                          dim3(NT), 0, h.stream, d_vg);
     }
     lap.mark("plan_vectors");
-    hipLaunchKernelGGL(k_basis, dim3(nchg), dim3(NT), 0, h.stream, V, d_chg);
+    {
+      ProfScope ps(h, "k_basis", 0, 0);
+      hipLaunchKernelGGL(k_basis, dim3(nchg), dim3(NT), 0, h.stream, V, d_chg);
+    }
     if ((rc = check_arena(h, l, "basis", c, err))) return rc;
   }
   // capacity growth of the M2L blocks of nodes whose new rank exceeds it
@@ -1524,8 +1542,10 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       h.stat_grown += nc2;
     }
   }
-  if (!far.empty())
+  if (!far.empty()) {
+    ProfScope ps(h, "k_project", 0, 0);
     hipLaunchKernelGGL(k_project, dim3((unsigned)far.size()), dim3(NT), 0, h.stream, V, d_far, d_recs, d_nbrs, d_chg);
+  }
   if ((rc = check_arena(h, l, "project", c, err))) return rc;
   lap.mark("moves_project");
   // ---- phase B

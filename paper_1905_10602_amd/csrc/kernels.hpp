@@ -612,20 +612,35 @@ __global__ void __launch_bounds__(NT) k_agg_near(LevelView C, LevelView F, const
 
 // ------------------------------------------------------------------ phase A
 // Pivot D_i = [[P2P_ii, L2P_i], [P2M_i, 0]] and copies of the L- and U-blocks.
+// Grid (records, 1 + neighbours, column chunks of GATHER_COLS): part 0 forms
+// columns [c0, c0 + GATHER_COLS) of D_i, part 1 + e those of the e-th L- and
+// U-blocks, so a few large records still spread over many workgroups.
+constexpr int GATHER_COLS = 32;
+__device__ inline void wg_copy_cols(int m, int c0, int c1, const double* src, int lds, double* dst, int ldd) {
+  if (m > 0 && c1 > c0) wg_copy(m, c1 - c0, src + (int64_t)c0 * lds, lds, dst + (int64_t)c0 * ldd, ldd);
+}
 __global__ void __launch_bounds__(NT) k_gather(LevelView V, const ElimRec* recs, const ElimNbr* nbrs) {
   const ElimRec R = recs[blockIdx.x];
   const int i = R.node, n = R.n, r = R.r, d = R.d;
-  const int rc = V.rc[i];
-  wg_copy(n, n, V.arena + near_block(V, i, i), n, R.lu, d);
-  wg_copy(n, r, V.arena + V.l2p_off[i], n, R.lu + (int64_t)n * d, d);
-  wg_copy(r, n, V.arena + V.p2m_off[i], rc, R.lu + n, d);
-  wg_fill(r, r, R.lu + n + (int64_t)n * d, d, 0.0);
-  for (int e = 0; e < R.nnb; ++e) {
-    const ElimNbr B = nbrs[R.nb_begin + e];
-    const int np = V.n[B.p];
-    wg_copy(B.m, n, V.arena + B.blk_pi, np, R.L + B.off, R.M);
-    wg_copy(n, B.m, V.arena + B.blk_ip, n, R.U + (int64_t)B.off * n, n);
+  const int c0 = blockIdx.z * GATHER_COLS, c1 = c0 + GATHER_COLS;
+  const int part = blockIdx.y;
+  if (part == 0) {
+    if (c0 >= d) return;
+    const int rc = V.rc[i];
+    // columns [0, n): P2P_ii over P2M_i; columns [n, d): L2P_i over zeros
+    const int a = c0, b = min(c1, n);
+    wg_copy_cols(n, a, b, V.arena + near_block(V, i, i), n, R.lu, d);
+    wg_copy_cols(r, a, b, V.arena + V.p2m_off[i], rc, R.lu + n, d);
+    const int a2 = max(c0, n) - n, b2 = min(c1, d) - n;
+    wg_copy_cols(n, a2, b2, V.arena + V.l2p_off[i], n, R.lu + (int64_t)n * d, d);
+    if (r > 0 && b2 > a2) wg_fill(r, b2 - a2, R.lu + n + (int64_t)(n + a2) * d, d, 0.0);
+    return;
   }
+  if (part > R.nnb) return;
+  const ElimNbr B = nbrs[R.nb_begin + part - 1];
+  const int np = V.n[B.p];
+  wg_copy_cols(B.m, c0, min(c1, n), V.arena + B.blk_pi, np, R.L + B.off, R.M);
+  wg_copy_cols(n, c0, min(c1, B.m), V.arena + B.blk_ip, n, R.U + (int64_t)B.off * n, n);
 }
 
 __global__ void __launch_bounds__(NT) k_getrf(const ElimRec* recs, int32_t* info, int big_d) {
@@ -925,8 +940,10 @@ __global__ void __launch_bounds__(NT) k_bu_gemm(const BluTask* tasks, int jb) {
 //   new blocks:        M[p, i] = L_a F,  M[i, q] = X_bot[:, q],  M[i, i] = -H
 // (with n == 0 the products are empty: far blocks become zero, near blocks
 // stay, the new block is zero)
+// tile: -1 = the whole block; else ti | tj << 16, the 64 x 64 output tile
+// (rows 64 ti, columns 64 tj) of block (a, b), a < nnb, b >= -1
 struct SchurTask {
-  int32_t rec, a, b, pad;
+  int32_t rec, a, b, tile;
 };
 // product of the Schur update: FP64, FP32 lite tile, or FP32 with the
 // double-buffered tile for long inner dimensions (own kernel instances)
@@ -965,12 +982,40 @@ __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const E
     }
   }
 }
+// one 64 x 64 output tile of the update of block (a, b), a < nnb
+template <bool f32, bool deep>
+__device__ inline void schur_tile(const LevelView& V, const ElimRec& R, const ElimNbr* nbrs, const int32_t* far_idx,
+                                  const FarPair* far, int a, int b, int ti, int tj) {
+  const int n = R.n, d = R.d, M = R.M;
+  const ElimNbr A = nbrs[R.nb_begin + a];
+  const int np = V.n[A.p];
+  const int i0 = 64 * ti, j0 = 64 * tj;
+  const int mt = min(64, A.m - i0);
+  const double* La = R.L + A.off + i0;
+  if (b >= 0) {
+    const ElimNbr B = nbrs[R.nb_begin + b];
+    const int nt = min(64, B.m - j0);
+    const double* Xb = R.X + (int64_t)(B.off + j0) * d;
+    const int fi = far_idx[R.far_base + a * R.nnb + b];
+    if (fi < 0)
+      schur_gemm<f32, deep>(mt, nt, n, -1.0, La, M, Xb, d, 1.0,
+                            V.arena + near_block(V, A.p, B.p) + i0 + (int64_t)j0 * np, np);
+    else schur_gemm<f32, deep>(mt, nt, n, -1.0, La, M, Xb, d, 0.0, far[fi].F + i0 + (int64_t)j0 * A.m, A.m);
+  } else {
+    const int nt = min(64, R.r - j0);
+    schur_gemm<f32, deep>(mt, nt, n, 1.0, La, M, R.X + (int64_t)(M + j0) * d, d, 0.0,
+                          V.arena + A.blk_pi + i0 + (int64_t)j0 * np, np);
+  }
+}
+
 template <bool f32, bool deep>
 __global__ void __launch_bounds__(NT) k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs,
                                               const SchurTask* tasks, const int32_t* far_idx, const FarPair* far) {
   const SchurTask T = tasks[blockIdx.x];
   const ElimRec R = recs[T.rec];
-  if (T.b == -2) {
+  if (T.tile >= 0) {
+    schur_tile<f32, deep>(V, R, nbrs, far_idx, far, T.a, T.b, T.tile & 0xffff, T.tile >> 16);
+  } else if (T.b == -2) {
     for (int b = 0; b < R.nnb; ++b) schur_block<f32, deep>(V, R, nbrs, far_idx, far, T.a, b);
     schur_block<f32, deep>(V, R, nbrs, far_idx, far, T.a, -1);
   } else {
