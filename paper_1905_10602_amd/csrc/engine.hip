@@ -804,7 +804,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         }
       }
       if (R.d < h.big_d)
-        for (int c0 = 0; c0 < R.M + R.r; c0 += 64) P.xtasks.push_back({k, c0});
+        for (int c0 = 0; c0 < R.M + R.r; c0 += XCOLS) P.xtasks.push_back({k, c0});
     }
   });
   {
@@ -1040,7 +1040,11 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   }
   if (!xtasks.empty()) {
     ProfScope ps(h, "k_xsolve", fl_x, 0);
-    hipLaunchKernelGGL(k_xsolve, dim3((unsigned)xtasks.size()), dim3(NT), 0, h.stream, d_recs, d_xt);
+    int dmx = 0;
+    for (const ElimRec& R : recs)
+      if (R.d < h.big_d) dmx = std::max(dmx, R.d);
+    hipLaunchKernelGGL(dmx <= 64 ? k_xsolve<64> : k_xsolve<256>, dim3((unsigned)xtasks.size()), dim3(NT), 0, h.stream,
+                       d_recs, d_xt);
   }
   {
     ProfScope ps(h, "k_schur", fl_schur, by_schur);

@@ -650,26 +650,38 @@ __global__ void __launch_bounds__(NT) k_getrf(const ElimRec* recs, int32_t* info
   if (threadIdx.x == 0) info[blockIdx.x] = inf;
 }
 
-// X = D^-1 [[U, 0], [0, I]]  (d x (M + r)), 64 columns per workgroup.
+// X = D^-1 [[U, 0], [0, I]]  (d x (M + r)), XCOLS columns per workgroup.
+// Pivots of order <= DMAX keep their slice of X in LDS through the row
+// interchanges and both substitutions (2 d barrier steps, all on LDS); larger
+// ones solve in place in global memory.  DMAX sizes the LDS (occupancy).
+constexpr int XCOLS = 32;
 struct XTask {
   int32_t rec, c0;
 };
+template <int DMAX>
 __global__ void __launch_bounds__(NT) k_xsolve(const ElimRec* recs, const XTask* xt) {
+  __shared__ double xs[DMAX * XCOLS];
   const XTask t = xt[blockIdx.x];
   const ElimRec R = recs[t.rec];
   const int n = R.n, d = R.d, M = R.M;
-  const int nc = min(64, M + R.r - t.c0);
+  const int nc = min(XCOLS, M + R.r - t.c0);
   if (d == 0 || nc <= 0) return;
   double* X = R.X + (int64_t)t.c0 * d;
+  const bool lds = d <= DMAX;
+  double* B = lds ? xs : X;  // ld d either way
   WG_FOR2(d, nc, row, cl) {
     const int col = t.c0 + cl;
     double v;
     if (col < M) v = row < n ? R.U[row + (int64_t)col * n] : 0.0;
     else v = (row >= n && row - n == col - M) ? 1.0 : 0.0;
-    X[row + (int64_t)cl * d] = v;
+    B[row + cl * d] = v;
   }
   __syncthreads();
-  wg_getrs(d, R.lu, d, R.piv, X, d, nc);
+  wg_getrs(d, R.lu, d, R.piv, B, d, nc);
+  if (lds) {
+    WG_FOR2(d, nc, row, cl) X[row + (int64_t)cl * d] = xs[row + cl * d];
+    __syncthreads();
+  }
 }
 
 // ---- large pivots: right-looking blocked LU of the augmented matrix
