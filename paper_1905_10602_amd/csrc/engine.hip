@@ -204,21 +204,42 @@ struct ProfScope {
   Handle& h;
   Handle::Pending p;
   bool on;
-  ProfScope(Handle& hh, const char* name, double flops, double bytes) : h(hh), on(hh.prof) {
+  hipStream_t st;
+  ProfScope(Handle& hh, const char* name, double flops, double bytes, bool side = false)
+      : h(hh), on(hh.prof), st(side ? hh.side_stream : hh.stream) {
     if (!on) return;
     p.a = take_event(h);
     p.b = take_event(h);
     p.name = h.prof_level && h.cur_level > 0 ? std::string(name) + "@" + std::to_string(h.cur_level) : name;
     p.flops = flops;
     p.bytes = bytes;
-    (void)hipEventRecord(p.a, h.stream);
+    (void)hipEventRecord(p.a, st);
   }
   ~ProfScope() {
     if (!on) return;
-    (void)hipEventRecord(p.b, h.stream);
+    (void)hipEventRecord(p.b, st);
     h.pending.push_back(p);
   }
 };
+
+// Fork: work launched on h.side_stream after this waits for everything
+// queued on the main stream so far.  Join: the main stream waits for the
+// side stream's work so far.  Both streams have the default priority.
+static int fork_side(Handle& h, std::string& err) {
+  if (!h.side_stream) {
+    HIPCHK(hipStreamCreateWithFlags(&h.side_stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h.ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h.ev_join, hipEventDisableTiming));
+  }
+  HIPCHK(hipEventRecord(h.ev_fork, h.stream));
+  HIPCHK(hipStreamWaitEvent(h.side_stream, h.ev_fork, 0));
+  return 0;
+}
+static int join_side(Handle& h, std::string& err) {
+  HIPCHK(hipEventRecord(h.ev_join, h.side_stream));
+  HIPCHK(hipStreamWaitEvent(h.stream, h.ev_join, 0));
+  return 0;
+}
 // called after a stream synchronisation
 static void prof_collect(Handle& h) {
   for (auto& p : h.pending) {
@@ -1180,6 +1201,18 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       H2D(h, d_gT, gT.data(), 2 * nsk * sizeof(GemmTask));
     }
     const double eps2 = h.eps * h.eps;
+    // the full decompositions (their own Gram matrices and work space) run on
+    // the side stream while the sketches run on the main stream
+    const bool side = nfull && nsk;
+    if (side && (rc = fork_side(h, err))) return rc;
+    if (nfull) {
+      ProfScope ps(h, "k_eig_values", fl_ev, 0, side);
+      const hipStream_t st = side ? h.side_stream : h.stream;
+      if (h.eig_jacobi)
+        hipLaunchKernelGGL(k_eig_jacobi, dim3((unsigned)nfull), dim3(NT), 0, st, d_fullT, eps2, d_cf);
+      else
+        hipLaunchKernelGGL(k_eig_values, dim3((unsigned)nfull), dim3(NT), 0, st, d_fullT, eps2, d_cf, 0);
+    }
     if (nsk) {
       double fl_sk = 0;
       for (const SkTask& t : skT)
@@ -1204,13 +1237,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       hipLaunchKernelGGL(k_sk_check, dim3((unsigned)((nsk + NT - 1) / NT)), dim3(NT), 0, h.stream, d_skT, d_skE, d_cs,
                          eps2, d_ok, (int)nsk);
     }
-    if (nfull) {
-      ProfScope ps(h, "k_eig_values", fl_ev, 0);
-      if (h.eig_jacobi)
-        hipLaunchKernelGGL(k_eig_jacobi, dim3((unsigned)nfull), dim3(NT), 0, h.stream, d_fullT, eps2, d_cf);
-      else
-        hipLaunchKernelGGL(k_eig_values, dim3((unsigned)nfull), dim3(NT), 0, h.stream, d_fullT, eps2, d_cf, 0);
-    }
+    if (side && (rc = join_side(h, err))) return rc;
     HIPCHK(hipGetLastError());
     cnt_full.assign(nfull, 0);
     cnt_sk.assign(nsk, 0);
@@ -1459,9 +1486,13 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     }
     H2D(h, d_chg, held(h, chg), chg.size() * sizeof(Changed));
     for (int e : full_ids) fl_evec += 2.0 * (double)chg[e / sides].n * chg[e / sides].n * chg[e / sides].rnew;
+    // eigenvectors of the full decompositions on the side stream, those of
+    // the sketches on the main stream
+    const bool vside = !h.eig_jacobi && nf2 && ns2;
+    if (vside && (rc = fork_side(h, err))) return rc;
     if (!h.eig_jacobi && nf2) {
-      ProfScope ps(h, "k_eig_vectors", fl_evec, 0);
-      hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)nf2), dim3(NT), 0, h.stream, d_vf);
+      ProfScope ps(h, "k_eig_vectors", fl_evec, 0, vside);
+      hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)nf2), dim3(NT), 0, vside ? h.side_stream : h.stream, d_vf);
     }
     if (ns2) {
       double fl = 0;
@@ -1477,6 +1508,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       hipLaunchKernelGGL(k_gemm_batch, dim3((unsigned)((nmx + 63) / 64), (unsigned)((rmax + 63) / 64), (unsigned)ns2),
                          dim3(NT), 0, h.stream, d_vg);
     }
+    if (vside && (rc = join_side(h, err))) return rc;
     lap.mark("plan_vectors");
     {
       ProfScope ps(h, "k_basis", 0, 0);
@@ -2188,6 +2220,11 @@ void release(Handle& h) {
   h.event_pool.clear();
   if (h.cap_stream) (void)hipStreamDestroy(h.cap_stream);
   h.cap_stream = nullptr;
+  if (h.side_stream) (void)hipStreamDestroy(h.side_stream);
+  h.side_stream = nullptr;
+  if (h.ev_fork) (void)hipEventDestroy(h.ev_fork);
+  if (h.ev_join) (void)hipEventDestroy(h.ev_join);
+  h.ev_fork = h.ev_join = nullptr;
   if (h.batch_stream) {
     if (h.stream == h.batch_stream) h.stream = nullptr;
     (void)hipStreamDestroy(h.batch_stream);

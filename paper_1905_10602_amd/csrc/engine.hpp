@@ -202,6 +202,10 @@ struct Handle {
   bool graph_solve = true;
   hipStream_t batch_stream = nullptr;  // library-owned stream given by the batch calls
   hipStream_t cap_stream = nullptr;
+  // second stream of the factorisation (default priority): independent work of
+  // a colour runs there between a fork and a join event on the main stream
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t g_graph = nullptr;
   hipGraphExec_t g_exec = nullptr;
   int g_key_k = -1;
