@@ -447,8 +447,15 @@ __global__ void __launch_bounds__(NT) k_sk_colnorm(const SkTask* tasks, double* 
   }
 }
 
+// Classical Gram-Schmidt with one reorthogonalisation inside a block of 64
+// columns of Y (earlier blocks are already projected out).  Column j keeps
+// its raw values and a scale sc_j in LDS (q_j = sc_j y_j, sc_j = 0 for a
+// dropped column); the scales are applied in one sweep at the end of the
+// block.  Per column: dots, update, dots, update fused with the norm, i.e.
+// four barriers.  A column whose remaining norm is <= drop times its
+// original norm is dropped.
 __global__ void __launch_bounds__(NT) k_sk_orth_block(const SkTask* tasks, int j0, double drop, const double* n0, int ldn0) {
-  __shared__ double s_c[64];
+  __shared__ double s_c[64], s_sc[64], s_part[NT / 64];
   const SkTask t = tasks[blockIdx.x];
   const int n = t.n, j1 = min(t.s, j0 + 64);
   if (j0 >= t.s) return;
@@ -456,33 +463,54 @@ __global__ void __launch_bounds__(NT) k_sk_orth_block(const SkTask* tasks, int j
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int j = j0; j < j1; ++j) {
     double* xj = X + (int64_t)j * n;
+    const int cnt = j - j0;
+    double part = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
-      const int cnt = j - j0;
       if (cnt > 0) {
-        for (int i = wave; i < cnt; i += NT / 64) {
-          const double* xi = X + (int64_t)(j0 + i) * n;
-          double c = 0.0;
-          for (int r = lane; r < n; r += 64) c += xi[r] * xj[r];
-          for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-          if (lane == 0) s_c[i] = c;
-        }
-        __syncthreads();
-        for (int r = tid; r < n; r += NT) {
-          double v = xj[r];
-          for (int i = 0; i < cnt; ++i) v -= s_c[i] * X[r + (int64_t)(j0 + i) * n];
-          xj[r] = v;
+        // c_i = q_i^T x_j, four columns per wave at a time
+        for (int i0 = 4 * wave; i0 < cnt; i0 += NT / 16) {
+          double c[4] = {0.0, 0.0, 0.0, 0.0};
+          const double* xi[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) xi[u] = X + (int64_t)(j0 + min(i0 + u, cnt - 1)) * n;
+          for (int r = lane; r < n; r += 64) {
+            const double v = xj[r];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c[u] += xi[u][r] * v;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            double cu = c[u];
+            for (int off = 32; off > 0; off >>= 1) cu += __shfl_xor(cu, off, 64);
+            if (lane == 0 && i0 + u < cnt) s_c[i0 + u] = cu * s_sc[i0 + u];
+          }
         }
         __syncthreads();
       }
+      // x_j -= sum_i c_i q_i (and, on the second pass, the squared norm)
+      for (int r = tid; r < n; r += NT) {
+        double v = xj[r];
+        for (int i = 0; i < cnt; ++i) v -= s_c[i] * s_sc[i] * X[r + (int64_t)(j0 + i) * n];
+        if (cnt > 0) xj[r] = v;
+        if (pass == 1) part += v * v;
+      }
+      if (pass == 0 && cnt > 0) __syncthreads();
     }
-    double part = 0.0;
-    for (int r = tid; r < n; r += NT) part += xj[r] * xj[r];
-    const double n2 = sqrt(wg_sum(part));
-    const double nn0 = n0[(int64_t)blockIdx.x * ldn0 + j];
-    const double sc = (n2 > drop * nn0 && n2 > 0.0) ? 1.0 / n2 : 0.0;
-    for (int r = tid; r < n; r += NT) xj[r] *= sc;
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+    if (lane == 0) s_part[wave] = part;
     __syncthreads();
+    double tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) tot += s_part[w];
+    const double n2 = sqrt(tot);
+    const double nn0 = n0[(int64_t)blockIdx.x * ldn0 + j];
+    // every thread computes the same value; read by others after the next barrier
+    s_sc[cnt] = (n2 > drop * nn0 && n2 > 0.0) ? 1.0 / n2 : 0.0;
   }
+  __syncthreads();
+  const int nb = j1 - j0;
+  if (n > 0) WG_FOR2(n, nb, r, jj) X[r + (int64_t)(j0 + jj) * n] *= s_sc[jj];
+  __syncthreads();
 }
 
 __global__ void __launch_bounds__(NT) k_sk_trace(const SkTask* tasks) {
