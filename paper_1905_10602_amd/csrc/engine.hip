@@ -1024,9 +1024,22 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
                        dim3(NT), 0, h.stream, V, d_recs, d_nbrs);
   }
   if ((rc = check_arena(h, l, "gather", c, err))) return rc;
+  // small pivots (unblocked LU and solve) on the side stream while the large
+  // ones go through the blocked LU on the main stream (different records)
+  const bool aside = !blu.empty() && !xtasks.empty();
+  if (aside && (rc = fork_side(h, err))) return rc;
+  const hipStream_t sa = aside ? h.side_stream : h.stream;
   {
-    ProfScope ps(h, "k_getrf", fl_lu, 0);
-    hipLaunchKernelGGL(k_getrf, dim3(nrec), dim3(NT), 0, h.stream, d_recs, d_info, h.big_d);
+    ProfScope ps(h, "k_getrf", fl_lu, 0, aside);
+    hipLaunchKernelGGL(k_getrf, dim3(nrec), dim3(NT), 0, sa, d_recs, d_info, h.big_d);
+  }
+  if (!xtasks.empty()) {
+    ProfScope ps(h, "k_xsolve", fl_x, 0, aside);
+    int dmx = 0;
+    for (const ElimRec& R : recs)
+      if (R.d < h.big_d) dmx = std::max(dmx, R.d);
+    hipLaunchKernelGGL(dmx <= 64 ? k_xsolve<64> : k_xsolve<256>, dim3((unsigned)xtasks.size()), dim3(NT), 0, sa, d_recs,
+                       d_xt);
   }
   if (!blu.empty()) {
     const BluTask* d_blu = (const BluTask*)(M + o_blu);
@@ -1059,14 +1072,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     hipLaunchKernelGGL(k_blu_store_inv, dim3((unsigned)((blu_dmax + 63) / 64), nb), dim3(NT), 0, h.stream, d_blu,
                        d_recs, d_blur);
   }
-  if (!xtasks.empty()) {
-    ProfScope ps(h, "k_xsolve", fl_x, 0);
-    int dmx = 0;
-    for (const ElimRec& R : recs)
-      if (R.d < h.big_d) dmx = std::max(dmx, R.d);
-    hipLaunchKernelGGL(dmx <= 64 ? k_xsolve<64> : k_xsolve<256>, dim3((unsigned)xtasks.size()), dim3(NT), 0, h.stream,
-                       d_recs, d_xt);
-  }
+  if (aside && (rc = join_side(h, err))) return rc;
   {
     ProfScope ps(h, "k_schur", fl_schur, by_schur);
     // inner dimension of the products = n of the pivot: the double-buffered
