@@ -1079,7 +1079,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     // FP32 tile where some pivot of the colour is large
     int nmx = 0;
     for (const ElimRec& R : recs) nmx = std::max(nmx, R.n);
-    auto ks = h.precision != 1 ? k_schur<false, false> : nmx >= 128 ? k_schur<true, true> : k_schur<true, false>;
+    auto ks = h.precision != 1 ? k_schur<false, false> : nmx >= h.deep_n ? k_schur<true, true> : k_schur<true, false>;
     hipLaunchKernelGGL(ks, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks, d_fidx,
                        d_far);
   }
@@ -1863,6 +1863,7 @@ int factor(Handle& h, std::string& err) {
   if (const char* e = std::getenv("IFMM_BIG_D")) h.big_d = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("IFMM_SKETCH")) h.sketch = std::atoi(e) != 0;
   if (const char* e = std::getenv("IFMM_PB_WAVE")) h.pb_wave = std::atoi(e) != 0;
+  if (const char* e = std::getenv("IFMM_DEEP_N")) h.deep_n = std::max(1, std::atoi(e));
   h.prof_level = std::getenv("IFMM_PROF_LEVEL") != nullptr;
   if (const char* e = std::getenv("IFMM_SKETCH_MIN")) h.sketch_min = std::max(1, std::atoi(e));
   h.stat_sketch = h.stat_sketch_rejected = h.stat_sketch_narrow = 0;
