@@ -173,7 +173,9 @@ struct Handle {
   // full eigen-decomposition remains the fall-back and the judge)
   bool sketch = true;       // IFMM_SKETCH=0 disables
   bool pb_wave = true;      // IFMM_PB_WAVE=0: mixed-form phase B without the wave form
-  int deep_n = 128;         // IFMM_DEEP_N: pivot order from which the Schur update takes the deep FP32 tile
+  // IFMM_DEEP_N: pivot order from which the Schur update takes the deep FP32
+  // tile; off by default (the lite tile's occupancy wins at every level measured)
+  int deep_n = 1 << 30;
   int sketch_min = 128;     // Gram order from which a sketch is tried (IFMM_SKETCH_MIN)
   double* skbuf = nullptr;
   int64_t skbuf_bytes = 0;
