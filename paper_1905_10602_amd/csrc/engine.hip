@@ -534,14 +534,21 @@ static int reduce_level(Handle& h, int l, std::string& err) {
   }
   // M2L of the interaction pairs (needs T of every node: separate launch)
   HSYNC(h);
-  std::vector<int64_t> toff2(nn);
-  for (int32_t i = 0; i < nn; ++i) toff2[i] = (int64_t)i * K * std::max(L.rcmax, 1);
-  if ((rc = ensure(h, (void**)&h.meta, &h.meta_bytes, (int64_t)nn * 8 + 256, err))) return rc;
-  int64_t* d_toff = (int64_t*)h.meta;
-  H2D(h, d_toff, toff2.data(), nn * sizeof(int64_t));
-  if ((rc = ensure(h, (void**)&h.scratch, &h.scratch_bytes, (int64_t)nn * K * std::max(L.rcmax, 1) * 8 + 64, err)))
-    return rc;
-  if (nn > 0) {
+  if (nn > 0 && K <= 64) {
+    const Level& TL = h.tree.levels[l];
+    int ilmax = 1;
+    for (int32_t i = 0; i < nn; ++i) ilmax = std::max(ilmax, TL.il_ptr[i + 1] - TL.il_ptr[i]);
+    hipLaunchKernelGGL(k_reduce_m2l_lds, dim3(nn, (unsigned)((ilmax + RM2L_SLOTS - 1) / RM2L_SLOTS)), dim3(NT), 0,
+                       h.stream, V, K, h.d_unit, 1.0 / side);
+    HIPCHK(hipGetLastError());
+  } else if (nn > 0) {
+    std::vector<int64_t> toff2(nn);
+    for (int32_t i = 0; i < nn; ++i) toff2[i] = (int64_t)i * K * std::max(L.rcmax, 1);
+    if ((rc = ensure(h, (void**)&h.meta, &h.meta_bytes, (int64_t)nn * 8 + 256, err))) return rc;
+    int64_t* d_toff = (int64_t*)h.meta;
+    H2D(h, d_toff, toff2.data(), nn * sizeof(int64_t));
+    if ((rc = ensure(h, (void**)&h.scratch, &h.scratch_bytes, (int64_t)nn * K * std::max(L.rcmax, 1) * 8 + 64, err)))
+      return rc;
     hipLaunchKernelGGL(k_reduce_m2l, dim3(nn), dim3(NT), 0, h.stream, V, K, h.d_unit, 1.0 / side, h.scratch, d_toff);
     HIPCHK(hipGetLastError());
   }

@@ -593,6 +593,30 @@ __global__ void __launch_bounds__(NT) k_reduce_m2l(LevelView V, int K, const dou
   }
 }
 
+// The same for K <= 64, one workgroup per (node, group of RM2L_SLOTS
+// interaction blocks): U T_l is formed 64 columns at a time in LDS, so no
+// global temporary is needed and a few nodes with long lists still fill the chip.
+constexpr int RM2L_SLOTS = 4;
+__global__ void __launch_bounds__(NT) k_reduce_m2l_lds(LevelView V, int K, const double* unit, double invL) {
+  __shared__ double tl[64 * 64];
+  const int i = blockIdx.x;
+  const int ri = V.r[i], rci = V.rc[i];
+  const int s0 = V.il_ptr[i] + blockIdx.y * RM2L_SLOTS, s1 = min(V.il_ptr[i + 1], s0 + RM2L_SLOTS);
+  if (ri == 0 || s0 >= s1) return;
+  const double* S = V.arena + V.S_off[i];
+  for (int s = s0; s < s1; ++s) {
+    const int l = V.il_idx[s];
+    const int rl = V.r[l];
+    const double* U = unit + (int64_t)offset_index(V.coord, i, l) * K * K;
+    const double* Tl = V.arena + V.T_off[l];
+    for (int c0 = 0; c0 < rl; c0 += 64) {
+      const int nc = min(64, rl - c0);
+      wg_gemm(K, nc, K, invL, U, K, false, Tl + (int64_t)c0 * K, K, false, 0.0, tl, K);
+      wg_gemm(ri, nc, K, 1.0, S, rci, false, tl, K, false, 0.0, V.il_blk[s] + (int64_t)c0 * V.ilcap[i], V.ilcap[i]);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ aggregation
 // Parent Chebyshev operators: P2Mc_P = [M2M_c ...] (K x n_P), L2Pc_P = [L2L_c; ...].
 __global__ void __launch_bounds__(NT) k_agg_cheb(LevelView C, LevelView F, int K, const int32_t* child_ptr, const int32_t* child) {
