@@ -354,13 +354,35 @@ __device__ inline void wg_fill(int m, int n, double* dst, int ldd, double v) {
   __syncthreads();
 }
 
+// Pivot choice over the workgroup: every thread brings its best (|value|,
+// row); all threads return the largest |value|, the smallest row on ties.
+// Wave shuffles, then the four wave results through LDS (one barrier); the
+// caller separates consecutive calls by at least one barrier.
+__device__ inline void wg_argmax(double& v, int& idx) {
+  __shared__ double wv[NT / 64];
+  __shared__ int wi[NT / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    const double v2 = __shfl_xor(v, off, 64);
+    const int i2 = __shfl_xor(idx, off, 64);
+    if (v2 > v || (v2 == v && i2 < idx)) { v = v2; idx = i2; }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    wv[threadIdx.x >> 6] = v;
+    wi[threadIdx.x >> 6] = idx;
+  }
+  __syncthreads();
+  v = wv[0];
+  idx = wi[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w)
+    if (wv[w] > v || (wv[w] == v && wi[w] < idx)) { v = wv[w]; idx = wi[w]; }
+}
+
 // In-place LU with partial pivoting (row interchanges), A = P L U, L unit
 // lower.  piv[j] = row swapped with row j at step j (0-based).  The pivot is
 // the entry of largest magnitude, the first one on ties.  Returns (to every
 // thread) the first step with an exactly zero pivot + 1, or 0.
 __device__ inline int wg_getrf(int d, double* A, int lda, int32_t* piv) {
-  __shared__ double sv[NT];
-  __shared__ int si[NT];
   __shared__ int s_info;
   if (threadIdx.x == 0) s_info = 0;
   __syncthreads();
@@ -374,20 +396,9 @@ __device__ inline int wg_getrf(int d, double* A, int lda, int32_t* piv) {
       const double v = fabs(A[i + (int64_t)j * lda]);
       if (v > best) { best = v; bi = i; }
     }
-    sv[tid] = best;
-    si[tid] = bi;
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double v2 = sv[tid + s];
-        const int i2 = si[tid + s];
-        if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
-      }
-      __syncthreads();
-    }
-    const int p = si[0];
-    const double pv = sv[0];
-    __syncthreads();
+    wg_argmax(best, bi);
+    const int p = bi;
+    const double pv = best;
     if (tid == 0) {
       piv[j] = p;
       if (pv == 0.0 && s_info == 0) s_info = j + 1;

@@ -830,8 +830,6 @@ __global__ void __launch_bounds__(NT) k_blu_panel(const BluTask* tasks, int j0) 
   if (j0 >= d) return;
   const int nb = min(BLU_NB, d - j0);
   double* T = t.lu;
-  __shared__ double sv[NT];
-  __shared__ int si[NT];
   const int tid = threadIdx.x;
   for (int j = j0; j < j0 + nb; ++j) {
     double best = -1.0;
@@ -840,20 +838,9 @@ __global__ void __launch_bounds__(NT) k_blu_panel(const BluTask* tasks, int j0) 
       const double v = fabs(T[i + (int64_t)j * d]);
       if (v > best) { best = v; bi = i; }
     }
-    sv[tid] = best;
-    si[tid] = bi;
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double v2 = sv[tid + s];
-        const int i2 = si[tid + s];
-        if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
-      }
-      __syncthreads();
-    }
-    const int p = si[0];
-    const double pv = sv[0];
-    __syncthreads();
+    wg_argmax(best, bi);
+    const int p = bi;
+    const double pv = best;
     if (tid == 0) {
       t.piv[j] = p;
       if (pv == 0.0 && *t.info == 0) *t.info = j + 1;
@@ -1505,8 +1492,6 @@ __global__ void __launch_bounds__(NT) k_gemm_tiles(int m, int n, int k, double a
 // Panel T[j0:n, j0:j0+nb]: unblocked LU with partial pivoting over rows j0..n-1
 // (swaps applied inside the panel only); piv[j] = global row swapped with j.
 __global__ void __launch_bounds__(NT) k_lu_panel(double* T, int n, int j0, int nb, int32_t* piv, int32_t* info) {
-  __shared__ double sv[NT];
-  __shared__ int si[NT];
   const int tid = threadIdx.x;
   for (int j = j0; j < j0 + nb; ++j) {
     double best = -1.0;
@@ -1515,20 +1500,9 @@ __global__ void __launch_bounds__(NT) k_lu_panel(double* T, int n, int j0, int n
       const double v = fabs(T[i + (int64_t)j * n]);
       if (v > best) { best = v; bi = i; }
     }
-    sv[tid] = best;
-    si[tid] = bi;
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double v2 = sv[tid + s];
-        const int i2 = si[tid + s];
-        if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
-      }
-      __syncthreads();
-    }
-    const int p = si[0];
-    const double pv = sv[0];
-    __syncthreads();
+    wg_argmax(best, bi);
+    const int p = bi;
+    const double pv = best;
     if (tid == 0) {
       piv[j] = p;
       if (pv == 0.0 && *info == 0) *info = j + 1;
