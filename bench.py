@@ -214,8 +214,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md, "
-              "not implemented", file=sys.stderr)
+        print("bench.py: one GPU only (--gpus 1); sharding a factorisation across GPUs is not implemented",
+              file=sys.stderr)
         sys.exit(2)
     os.environ["IFMM_PROF"] = "1"
     os.environ.setdefault("IFMM_LOG", "1")
