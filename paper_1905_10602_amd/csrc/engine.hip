@@ -1082,8 +1082,9 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   if (aside && (rc = join_side(h, err))) return rc;
   {
     ProfScope ps(h, "k_schur", fl_schur, by_schur);
-    // inner dimension of the products = n of the pivot: the double-buffered
-    // FP32 tile where some pivot of the colour is large
+    // inner dimension of the products = n of the pivot; the double-buffered
+    // FP32 tile only from pivot order h.deep_n on (off unless set: the lite
+    // tile keeps more workgroups resident and measured faster at every level)
     int nmx = 0;
     for (const ElimRec& R : recs) nmx = std::max(nmx, R.n);
     auto ks = h.precision != 1 ? k_schur<false, false> : nmx >= h.deep_n ? k_schur<true, true> : k_schur<true, false>;
