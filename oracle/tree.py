@@ -103,43 +103,60 @@ def choose_depth(points: np.ndarray, lo, H, leaf_max: int) -> int:
 
 
 def colour_grid(occupied: np.ndarray, sigma: int) -> np.ndarray:
-    """Alg. 3, written as the paper states it.
+    """Greedy sigma-stride colouring of one level (Sec. 3.4, Alg. 3).
 
-    occupied[k, j, i] marks the non-empty boxes of an m x m x m level.  Returns
-    colour[k, j, i] (-1 for empty boxes).  The scan starts every colour at the
-    first uncoloured box in (k, j, i) order and then walks the rest of the
-    grid, jumping sigma boxes along i after a hit, sigma rows along j after a
-    row that had a hit, and sigma planes along k after a plane that had a hit.
+    occupied[k, j, i] marks the non-empty boxes of an m x m x m level; the
+    result holds colour[k, j, i] (-1 for empty boxes).
+
+    The rule, as Sec. 3.4 states it: a colour starts at the first box, in
+    (k, j, i) scan order, that is non-empty and not yet coloured (the seed).
+    The rest of the grid is then walked in scan order from the seed.  A
+    non-empty uncoloured box on the walk takes the colour, and the walk then
+    jumps sigma boxes ahead along i instead of one.  Likewise a row (fixed k, j)
+    in which the colour was placed is followed by the row sigma further on,
+    and a plane (fixed k) in which it was placed by the plane sigma further on;
+    otherwise the walk moves to the next row / plane.  The seed counts as a
+    placement in its row and plane.  Colours are numbered in the order their
+    seeds are found.
     """
     m = occupied.shape[0]
     colour = np.full(occupied.shape, -1, dtype=np.int64)
+
+    def free(k, j, i):
+        return bool(occupied[k, j, i]) and colour[k, j, i] < 0
+
+    def walk_row(k, j, i, g):
+        """Places colour g along row (k, j) from box i on; True if it placed any."""
+        placed = False
+        while i < m:
+            if free(k, j, i):
+                colour[k, j, i] = g
+                placed = True
+                i += sigma
+            else:
+                i += 1
+        return placed
+
     g = 0
-    for k0 in range(m):
-        for j0 in range(m):
-            for i0 in range(m):
-                if not (occupied[k0, j0, i0] and colour[k0, j0, i0] < 0):
-                    continue
-                colour[k0, j0, i0] = g
-                j_stride = True
-                k_stride = True
-                k = k0
-                while k < m:
-                    j = j0 if k == k0 else 0
-                    while j < m:
-                        i = i0 + sigma if (j == j0 and k == k0) else 0
-                        while i < m:
-                            if occupied[k, j, i] and colour[k, j, i] < 0:
-                                colour[k, j, i] = g
-                                i += sigma
-                                j_stride = True
-                                k_stride = True
-                            else:
-                                i += 1
-                        j = j + sigma if j_stride else j + 1
-                        j_stride = False
-                    k = k + sigma if k_stride else k + 1
-                    k_stride = False
-                g += 1
+    for seed in range(m * m * m):  # scan order: i fastest, then j, then k
+        k0, j0, i0 = seed // (m * m), (seed // m) % m, seed % m
+        if not free(k0, j0, i0):
+            continue
+        colour[k0, j0, i0] = g
+        k = k0
+        while k < m:
+            in_seed_plane = k == k0
+            plane_placed = in_seed_plane
+            j = j0 if in_seed_plane else 0
+            while j < m:
+                if in_seed_plane and j == j0:
+                    row_placed = walk_row(k, j, i0 + sigma, g) or True  # the seed's row
+                else:
+                    row_placed = walk_row(k, j, 0, g)
+                plane_placed = plane_placed or row_placed
+                j += sigma if row_placed else 1
+            k += sigma if plane_placed else 1
+        g += 1
     return colour
 
 

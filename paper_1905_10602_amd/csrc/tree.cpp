@@ -18,40 +18,68 @@ int Level::dist(int32_t a, int32_t b) const {
 
 static inline int64_t lex(int32_t i, int32_t j, int32_t k, int64_t m) { return ((int64_t)k * m + j) * m + i; }
 
+// Greedy sigma-stride colouring of one level (Sec. 3.4, Alg. 3).  The rule:
+// a colour starts at the first non-empty uncoloured box in (k, j, i) scan
+// order and walks the rest of the grid in scan order; a box it colours makes
+// the walk continue sigma boxes further along i, a row in which it coloured a
+// box is followed by the row sigma further on, a plane likewise by the plane
+// sigma further on (otherwise the next row / plane); the seed counts as a
+// placement in its row and plane.
+//
+// Only occupied boxes are stored: every row (k, j) keeps its uncoloured boxes
+// as an ascending list of i.  Walking a row from i = start takes the first
+// listed box at or after start, then the first at or after that box + sigma,
+// and so on, which is what the box-by-box walk does.
 int32_t colour_grid(const std::vector<uint8_t>& occ, int m, int sigma, std::vector<int32_t>& colour) {
   const int64_t M = m;
   colour.assign((size_t)(M * M * M), -1);
-  auto at = [&](int k, int j, int i) { return (size_t)((k * M + j) * M + i); };
-  int32_t g = 0;
-  for (int k0 = 0; k0 < m; ++k0)
-    for (int j0 = 0; j0 < m; ++j0)
-      for (int i0 = 0; i0 < m; ++i0) {
-        if (!occ[at(k0, j0, i0)] || colour[at(k0, j0, i0)] >= 0) continue;
-        colour[at(k0, j0, i0)] = g;  // first node of colour g
-        bool jstride = true, kstride = true;
-        int k = k0;
-        while (k < m) {
-          int j = (k == k0) ? j0 : 0;
-          while (j < m) {
-            int i = (j == j0 && k == k0) ? i0 + sigma : 0;
-            while (i < m) {
-              if (occ[at(k, j, i)] && colour[at(k, j, i)] < 0) {
-                colour[at(k, j, i)] = g;
-                i += sigma;
-                jstride = true;
-                kstride = true;
-              } else {
-                i += 1;
-              }
-            }
-            j = jstride ? j + sigma : j + 1;
-            jstride = false;
-          }
-          k = kstride ? k + sigma : k + 1;
-          kstride = false;
-        }
-        ++g;
+  std::vector<std::vector<int32_t>> row_free((size_t)(M * M));
+  for (int64_t r = 0; r < M * M; ++r)
+    for (int32_t i = 0; i < m; ++i)
+      if (occ[(size_t)(r * M + i)]) row_free[(size_t)r].push_back(i);
+  // colours row r = k m + j from i = start on; returns whether it placed any
+  auto walk_row = [&](int64_t r, int32_t start, int32_t g) {
+    std::vector<int32_t>& list = row_free[(size_t)r];
+    size_t keep = 0;
+    bool placed = false;
+    for (size_t t = 0; t < list.size(); ++t) {
+      const int32_t i = list[t];
+      if (i >= start) {
+        colour[(size_t)(r * M + i)] = g;
+        placed = true;
+        start = i + sigma;
+      } else {
+        list[keep++] = i;
       }
+    }
+    list.resize(keep);
+    return placed;
+  };
+  int32_t g = 0;
+  int64_t seed_row = 0;
+  for (;;) {
+    while (seed_row < M * M && row_free[(size_t)seed_row].empty()) ++seed_row;
+    if (seed_row == M * M) break;
+    const int32_t k0 = (int32_t)(seed_row / M), j0 = (int32_t)(seed_row % M);
+    // the seed: first free box of the first row that has one
+    std::vector<int32_t>& first = row_free[(size_t)seed_row];
+    const int32_t i0 = first.front();
+    colour[(size_t)(seed_row * M + i0)] = g;
+    first.erase(first.begin());
+    for (int32_t k = k0; k < m;) {
+      const bool seed_plane = k == k0;
+      bool plane_placed = seed_plane;
+      for (int32_t j = seed_plane ? j0 : 0; j < m;) {
+        const int64_t r = (int64_t)k * M + j;
+        const bool seed_row_here = seed_plane && j == j0;
+        const bool row_placed = walk_row(r, seed_row_here ? i0 + sigma : 0, g) || seed_row_here;
+        plane_placed = plane_placed || row_placed;
+        j += row_placed ? sigma : 1;
+      }
+      k += plane_placed ? sigma : 1;
+    }
+    ++g;
+  }
   return g;
 }
 

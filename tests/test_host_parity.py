@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol():
 
 @pytest.mark.parametrize("shape,N,leaf,sigma,seed", [
     ("sphere", 4096, 64, 6, 1), ("sphere", 20000, 32, 3, 2), ("ellipsoid", 30000, 16, 3, 5),
-    ("cube", 12000, 40, 6, 4), ("sphere", 3, 1, 3, 9)])
+    ("cube", 12000, 40, 6, 4), ("sphere", 3, 1, 3, 9), ("sphere", 20000, 32, 4, 3), ("ellipsoid", 20000, 24, 5, 6)])
 def test_tree_bit_exact(shape, N, leaf, sigma, seed):
     from paper_1905_10602_amd import IFMM
     kw = {"jitter": 0.05} if shape == "ellipsoid" else {}
