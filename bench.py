@@ -7,40 +7,65 @@ takes device pointers).  Workload: N = 1,048,576 points on the ellipsoid with
 semi-axes (1, 0.7, 0.3) plus 5 % uniform jitter, Laplace kernel, eps = 1e-6,
 sigma = 3, leaves of at most 64 points, Chebyshev 4^3 operators.
 
-Two forms run on the same GPU: "mixed" (FP32 matrix-core Schur and basis
-products, sketched recompression sized by the trained rank network) gives
-`value`; "fp64" (every step FP64, full eigen-decompositions) is reported
-beside it.  For each form, FGMRES(50) on the Chebyshev 5^3 FMM operator with
-the form's factorisation as right preconditioner gives the iteration count
-at the same tolerance (1e-8).
+Forms on the same GPU:
+  mixed      FP32 matrix-core Schur and basis products, sketched recompression
+             sized by the trained rank network: gives `value`;
+  fp64       every step FP64, full eigen-decompositions (one step);
+  heuristic  the mixed form without the network (sketch width from the node's
+             current rank; one step): the ablation of the learned part.
+For each form: e_res = ||A~ x - b|| / ||b|| with A~ applied through the
+Chebyshev 4^3 FMM on the IFMM's own tree (exactly the matrix the IFMM
+factorises), and FGMRES(50) on the Chebyshev 5^3 FMM operator with the form's
+factorisation as right preconditioner (iterations at tolerance 1e-8).
 
-Prints one JSON line (see the keys below).  `roofline` covers the kernel
-class with the largest device time in the timed steps, timed with HIP events
-on its own launch stream inside the library; `cpu_baseline` times the CPU
-oracle on a bounded sample of the same workload.
+The whole run keeps to a wall-clock budget (--budget-s, counted from the
+start of the process): warm-up is at most one step, the timed mixed steps are
+as many of --steps as fit, the comparison forms run once, and the GMRES and
+CPU legs are skipped, with a note, when they no longer fit.  `steps` reports
+the count actually timed.  The JSON line is always printed.
+
+`roofline` covers the single kernel with the largest device time in the lead
+form, timed with HIP events on its own launch stream inside the library;
+`roofline_more` adds the Schur update and the solve.  `cpu_baseline` times
+the CPU oracle on two bounded samples of the same workload and extrapolates
+linearly in N.
+
+`python bench.py --copy-calibration` only copies 3 x 256 MiB on the device:
+the reference kernel whose FETCH_SIZE / WRITE_SIZE counters scale the same
+counters of the library's kernels to bytes.
 """
 from __future__ import annotations
 
-import argparse
-import json
-import os
-import statistics
-import sys
 import time
+
+T_START = time.time()
+
+import argparse  # noqa: E402
+import json  # noqa: E402
+import os  # noqa: E402
+import statistics  # noqa: E402
+import sys  # noqa: E402
+import traceback  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "IFMM factor s + solve ms/RHS at eps=1e-6, N=1M; mixed vs FP64 on same GPU"
 FP64_VECTOR_PEAK = 78.6e12      # 256 CUs x 2.4 GHz x 128 FP64 flop/clk
+FP64_MFMA_PEAK = 78.6e12        # dense FP64 matrix-core peak
 HBM_PEAK = 8.0e12               # bytes/s
 FP32_MFMA_PEAK = 157.3e12      # dense FP32 matrix-core peak
-BOUND = {"k_fwd": "hbm", "k_bwd": "hbm", "k_gather": "hbm"}
+BOUND = {"k_fwd": "hbm", "k_bwd": "hbm", "k_gather": "hbm", "group:solve_graph": "hbm"}
 MFMA_F32 = {"k_schur"}          # runs on FP32 matrix cores in the mixed form
+MFMA_F64 = set()                 # kernels on FP64 matrix cores in the FP64 form
 
 
 def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench {time.time() - T_START:6.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+def left(args):
+    return args.budget_s - (time.time() - T_START)
 
 
 def workload(N, seed=5):
@@ -51,10 +76,36 @@ def workload(N, seed=5):
     return pts, dg
 
 
-def cpu_baseline(eps, sigma, nrhs, N_full, budget_s=25.0):
-    """The oracle, untuned, on a bounded sample: the same workload at a
-    reduced N, scaled linearly in N (the IFMM is O(N))."""
-    import numpy as np
+def host_info():
+    info = {"nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    info["ram_GB"] = round(int(line.split()[1]) / 1e6, 1)
+                    break
+    except OSError:
+        pass
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    return info
+
+
+def cpu_baseline(eps, sigma, nrhs, N_full, args):
+    """The oracle, untuned, on bounded samples of the same workload: N = 4096
+    and, when the budget allows, N = 8192; the factor time is extrapolated to
+    N_full along the straight line through the two points (the IFMM is O(N);
+    with one point, proportionally)."""
     import synth
     from oracle.ifmm import IFMM as Oracle
     try:
@@ -62,26 +113,52 @@ def cpu_baseline(eps, sigma, nrhs, N_full, budget_s=25.0):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
-    N = 4096
-    pts, dg = workload(N)
-    b = synth.uniform_rhs(N, nrhs, 201)
-    t0 = time.perf_counter()
-    F = Oracle(pts, eps=eps, sigma=sigma, diag=dg, leaf_max=64).factor()
-    tf = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    F.solve(b)
-    ts = time.perf_counter() - t0
-    scale = N_full / N
-    return {"value": tf * scale, "unit": "s (factor, extrapolated)", "cores": int(cores), "kind": "oracle",
-            "sample": f"oracle factor {tf:.2f} s + solve of {nrhs} RHS {ts:.2f} s on the same workload at "
-                      f"N={N}, scaled linearly to N={N_full}; solve {1e3 * ts * scale / nrhs:.1f} ms/RHS"}
+    pts_all = {}
+    runs = []
+    for N in (4096, 8192):
+        if runs:
+            need = runs[-1]["factor_s"] * 2.6 + runs[-1]["solve_s"] * 2.6 + 10
+            if left(args) < need:
+                log(f"cpu baseline: N={N} skipped (needs ~{need:.0f} s, {left(args):.0f} s left)")
+                break
+        pts_all[N] = workload(N)
+        pts, dg = pts_all[N]
+        b = synth.uniform_rhs(N, nrhs, 201)
+        t0 = time.perf_counter()
+        F = Oracle(pts, eps=eps, sigma=sigma, diag=dg, leaf_max=64).factor()
+        tf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        F.solve(b)
+        ts = time.perf_counter() - t0
+        runs.append({"N": N, "factor_s": tf, "solve_s": ts})
+        log(f"cpu baseline N={N}: factor {tf:.2f} s, solve {ts:.2f} s")
+    if len(runs) >= 2:
+        a, b2 = runs[0], runs[1]
+        slope = (b2["factor_s"] - a["factor_s"]) / (b2["N"] - a["N"])
+        slope_s = (b2["solve_s"] - a["solve_s"]) / (b2["N"] - a["N"])
+        val = b2["factor_s"] + slope * (N_full - b2["N"])
+        sol = b2["solve_s"] + slope_s * (N_full - b2["N"])
+        how = (f"straight line through the two samples: {slope * 1e3:.3f} ms of factor time per point, "
+               f"extrapolated from N={b2['N']} to N={N_full}")
+    else:
+        a = runs[0]
+        val = a["factor_s"] * N_full / a["N"]
+        sol = a["solve_s"] * N_full / a["N"]
+        how = f"one sample, scaled proportionally from N={a['N']} to N={N_full}"
+    return {"value": val, "unit": "s (factor, extrapolated)", "cores": int(cores), "kind": "oracle",
+            "sample": "oracle (FP64 numpy/scipy, untuned) factor + solve of the same workload (ellipsoid + jitter, "
+                      f"eps={eps}, sigma={sigma}, {nrhs} RHS) at " +
+                      ", ".join(f"N={r['N']}: factor {r['factor_s']:.2f} s, solve {r['solve_s']:.2f} s" for r in runs) +
+                      f"; {how}; solve extrapolated {1e3 * sol / nrhs:.0f} ms/RHS",
+            "samples": runs, "host": host_info()}
 
 
-def run_form(name, pts, dg, args, bt, xt, F, f_dev):
-    """One form of the path: `steps` timed steps (build + factor + solve of the
-    RHS block), then FGMRES(50) to 1e-8 on the FMM operator with this form's
-    factorisation as the right preconditioner (untimed against the metric)."""
-    import numpy as np
+def run_form(name, pts, dg, args, bt, xt, F5, F4, f_dev, max_steps, warmup):
+    """One form of the path: `warmup` untimed and up to `max_steps` timed steps
+    (build + factor + solve of the RHS block, the step count cut by the
+    budget), then e_res on A~ and FGMRES(50) to 1e-8 on the order-5 FMM
+    operator with this form's factorisation as the right preconditioner
+    (untimed against the metric)."""
     import torch
     from paper_1905_10602_amd import IFMM
     from paper_1905_10602_amd.ifmm import _check, _ptr, load_library
@@ -89,7 +166,7 @@ def run_form(name, pts, dg, args, bt, xt, F, f_dev):
     mixed = name != "fp64"
     os.environ["IFMM_SKETCH"] = "1" if mixed else "0"
     theta = None
-    if mixed:
+    if name == "mixed":
         from paper_1905_10602_amd.rank_model import load
         theta, _ = load()
 
@@ -107,46 +184,64 @@ def run_form(name, pts, dg, args, bt, xt, F, f_dev):
         t3 = time.perf_counter()
         return h, {"build_s": t1 - t0, "factor_s": t2 - t1, "solve_s": t3 - t2, "step_s": t3 - t0}
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         h, t = step()
         log(f"{name} warmup {w}: {json.dumps(t)}")
         h.close()
     times = []
     h = None
-    for k in range(args.steps):
+    reserve = args.reserve_s
+    while len(times) < max_steps:
+        if times and left(args) < times[-1]["step_s"] * 1.15 + reserve:
+            log(f"{name}: stopping after {len(times)} timed steps ({left(args):.0f} s left, "
+                f"{reserve:.0f} s reserved for the other legs)")
+            break
         if h is not None:
             h.close()
         torch.cuda.synchronize()
         h, t = step()
         torch.cuda.synchronize()
         times.append(t)
-        log(f"{name} step {k}: {json.dumps(t)}")
+        log(f"{name} step {len(times) - 1}: {json.dumps(t)}")
     stats = h.stats()
     x_first = xt[0].cpu().numpy().copy()
-    # accuracy of the IFMM solve on the FMM operator, and preconditioned FGMRES
-    res = None
     gm = {}
-    if F is not None:
-        y = F.matvec(xt[0].contiguous())
-        res = float(torch.linalg.norm(y - bt[0]) / torch.linalg.norm(bt[0]))
-        t0 = time.perf_counter()
-        xg, its, rr = F.gmres(f_dev, precond=h, tol=1e-8, restart=50, maxit=200, allow_noconv=True)
-        torch.cuda.synchronize()
-        gm = {"gmres_iters": its, "gmres_relres": rr, "gmres_s": time.perf_counter() - t0}
-        t0 = time.perf_counter()
-        xg0, its0, rr0 = F.gmres(f_dev, precond=None, tol=1e-8, restart=50, maxit=400, allow_noconv=True)
-        torch.cuda.synchronize()
-        gm.update({"gmres_unpreconditioned_iters": its0, "gmres_unpreconditioned_s": time.perf_counter() - t0})
-        del xg, xg0
+    # e_res on the matrix the IFMM factorises (A~ through its exact FMM form)
+    if F4 is not None:
+        ys = [F4.matvec(xt[k].contiguous()) for k in range(args.nrhs)]
+        gm["e_res"] = max(float(torch.linalg.norm(ys[k] - bt[k]) / torch.linalg.norm(bt[k])) for k in range(args.nrhs))
+        gm["e_res_over_eps"] = gm["e_res"] / args.eps
+    if F5 is not None:
+        y = F5.matvec(xt[0].contiguous())
+        gm["solve_residual_on_cheb5_fmm"] = float(torch.linalg.norm(y - bt[0]) / torch.linalg.norm(bt[0]))
+        if left(args) > args.reserve_gmres_s:
+            t0 = time.perf_counter()
+            xg, its, rr = F5.gmres(f_dev, precond=h, tol=1e-8, restart=50, maxit=100, allow_noconv=True)
+            torch.cuda.synchronize()
+            gm.update({"gmres_iters": its, "gmres_relres": rr, "gmres_s": time.perf_counter() - t0})
+            del xg
+        else:
+            gm["gmres_skipped"] = f"budget ({left(args):.0f} s left)"
+    # single-RHS latency of the solve
+    t0 = time.perf_counter()
+    x1 = torch.empty_like(bt[0])
+    for _ in range(3):
+        _check(load_library().ifmm_solve(h._h, _ptr(bt[0]), _ptr(x1), 1, N, 1))
+    torch.cuda.synchronize()
+    gm["solve_1rhs_ms"] = (time.perf_counter() - t0) * 1e3 / 3
     h.close()
     med = lambda key: statistics.median(t[key] for t in times)
-    out = {"factor_s": med("factor_s"), "solve_ms_per_rhs": med("solve_s") * 1e3 / args.nrhs,
-           "build_s": med("build_s"), "step_s": med("step_s"), "solve_residual_on_fmm": res, **gm,
+    out = {"steps_timed": len(times), "factor_s": med("factor_s"), "solve_ms_per_rhs": med("solve_s") * 1e3 / args.nrhs,
+           "build_s": med("build_s"), "step_s": med("step_s"), "step_s_all": [round(t["step_s"], 3) for t in times],
+           **gm,
            "sketches": stats.get("sketches"), "sketches_rejected": stats.get("sketches_rejected"),
+           "full_decompositions": stats.get("full_decompositions"),
            "rank_predictions": stats.get("rank_predictions"), "t_sync": stats.get("t_sync"), "t_h2d": stats.get("t_h2d"),
            "depth": stats.get("depth"), "top_n": stats.get("top_n"), "device_GB": stats.get("device_bytes", 0) / 1e9,
+           "peak_device_GB": stats.get("peak_device_bytes", 0) / 1e9,
            "factor_store_GB": stats.get("store_bytes", 0) / 1e9,
-           "levels": [{k2: L[k2] for k2 in ("level", "nodes", "colours", "rank_sum", "rank_max", "n_max", "t_elim")}
+           "levels": [{k2: L.get(k2) for k2 in ("level", "nodes", "colours", "rank_sum", "rank_max", "n_max", "t_elim",
+                                                 "rank_hist")}
                       for L in stats.get("levels", [])],
            "kernels_ms": {n: round(k["ms"], 3) for n, k in stats.get("kernels", {}).items()},
            "kernels_rate": {n: {"TFLOP/s": round(k["flops"] / k["ms"] / 1e9, 2) if k["flops"] else None,
@@ -176,6 +271,31 @@ def measured_traffic(kernel, form):
     return None
 
 
+def price(name, k, mixed):
+    """Roofline entry of one kernel class from its in-library hipEvent record."""
+    la = max(k["launches"], 1)
+    avg_s = k["ms"] / 1e3 / la
+    common = {"kernel": name, "traffic": measured_traffic(name, "mixed" if mixed else "fp64"),
+              "launches": k["launches"], "avg_launch_ms": avg_s * 1e3,
+              "algorithmic_per_launch": (k["bytes"] if BOUND.get(name) == "hbm" else k["flops"]) / la,
+              "algorithmic_bytes_per_launch": k["bytes"] / la}
+    if avg_s <= 0:
+        return None
+    if BOUND.get(name) == "hbm":
+        ach = k["bytes"] / la / avg_s
+        return {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": ach / HBM_PEAK, **common}
+    ach = k["flops"] / la / avg_s
+    if mixed and name in MFMA_F32:
+        return {"bound": "mfma", "achieved": ach / 1e12, "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": ach / FP32_MFMA_PEAK, **common}
+    if not mixed and name in MFMA_F64:
+        return {"bound": "mfma", "achieved": ach / 1e12, "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": ach / FP64_MFMA_PEAK, **common}
+    return {"bound": "alu", "achieved": ach / 1e12, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": ach / FP64_VECTOR_PEAK, **common}
+
+
 def roofline_of(stats, mixed):
     """Roofline of the single kernel with the largest device time (profiler
     classes named "group:..." span several kernels and are skipped)."""
@@ -183,40 +303,59 @@ def roofline_of(stats, mixed):
     if not ks:
         return None
     name, k = max(ks.items(), key=lambda kv: kv[1]["ms"])
-    avg_s = k["ms"] / 1e3 / max(k["launches"], 1)
-    common = {"kernel": name, "traffic": measured_traffic(name, "mixed" if mixed else "fp64"),
-              "launches": k["launches"], "avg_launch_ms": avg_s * 1e3,
-              "algorithmic_per_launch": (k["bytes"] if BOUND.get(name) == "hbm" else k["flops"]) / max(k["launches"], 1),
-              "algorithmic_bytes_per_launch": k["bytes"] / max(k["launches"], 1)}
-    if BOUND.get(name) == "hbm":
-        ach = k["bytes"] / max(k["launches"], 1) / avg_s
-        return {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": ach / HBM_PEAK, **common}
-    ach = k["flops"] / max(k["launches"], 1) / avg_s
-    if mixed and name in MFMA_F32:
-        return {"bound": "mfma", "achieved": ach / 1e12, "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": ach / FP32_MFMA_PEAK, **common}
-    return {"bound": "alu", "achieved": ach / 1e12, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": ach / FP64_VECTOR_PEAK, **common}
+    return price(name, k, mixed)
+
+
+def roofline_more(stats, mixed):
+    """The Schur update and the solve (per-colour substitution kernels and the
+    whole captured solve) beside the dominant kernel."""
+    ks = stats.get("kernels", {})
+    out = {}
+    for n in ("k_schur", "k_fwd", "k_bwd", "group:solve_graph"):
+        if n in ks:
+            out[n] = price(n, ks[n], mixed)
+    return out
+
+
+def copy_calibration():
+    """Reference copy for the HBM traffic counters: three copies of 256 MiB of FP64."""
+    import torch
+    n = 32 * 1024 * 1024
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print("copied 3 x 256 MiB", flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--sigma", type=int, default=3)
     ap.add_argument("--nrhs", type=int, default=8)
-    ap.add_argument("--form", choices=("both", "mixed", "fp64"), default="both")
+    ap.add_argument("--form", choices=("all", "both", "mixed", "fp64", "heuristic"), default="all")
+    ap.add_argument("--budget-s", type=float, default=450.0,
+                    help="wall-clock budget of the whole run, counted from the start of the process")
+    ap.add_argument("--reserve-s", type=float, default=-1.0,
+                    help="seconds kept free for the legs after the timed mixed steps (default: estimated)")
+    ap.add_argument("--reserve-gmres-s", type=float, default=20.0)
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: one GPU only (--gpus 1); sharding a factorisation across GPUs is not implemented",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     os.environ["IFMM_PROF"] = "1"
     os.environ.setdefault("IFMM_LOG", "1")
     import numpy as np
@@ -225,48 +364,106 @@ def main():
     from paper_1905_10602_amd import FMM
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     N = args.n
-    log(f"workload: ellipsoid N={N}")
+    log(f"workload: ellipsoid N={N}; budget {args.budget_s:.0f} s")
     pts, dg = workload(N)
     b = synth.uniform_rhs(N, args.nrhs, 201)
     bt = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()  # (nrhs, N) row-major = (N, nrhs) col-major
     xt = torch.empty_like(bt)
-    F, f_dev = None, None
+    F5, F4, f_dev = None, None, None
+    notes = []
     if not args.no_gmres:
-        F = FMM(pts, dg, cheb_order=5, leaf_max=256)  # FMM depth for ~30 points per leaf (not the IFMM's)
+        F5 = FMM(pts, dg, cheb_order=5, leaf_max=256)  # FMM depth for ~30 points per leaf (not the IFMM's)
         f_dev = bt[0].contiguous()
-        log(f"FMM matvec operator built: {json.dumps(F.stats())}")
-    forms = {"both": ["mixed", "fp64"], "mixed": ["mixed"], "fp64": ["fp64"]}[args.form]
+        log(f"FMM (order 5) built: {json.dumps(F5.stats())}")
+    F4 = FMM(pts, dg, cheb_order=4, leaf_max=64)  # the IFMM's own tree and operators: exactly A~
+    log("FMM (order 4, the IFMM's tree) built")
+    forms = {"all": ["mixed", "fp64", "heuristic"], "both": ["mixed", "fp64"], "mixed": ["mixed"], "fp64": ["fp64"],
+             "heuristic": ["heuristic"]}[args.form]
     res, stats0, xs = {}, None, {}
+    lead = forms[0]
+    est_step = None
     for fm in forms:
+        if fm != lead:
+            # a comparison form: one step, when it fits
+            need = (est_step or 60.0) * (2.0 if fm == "fp64" else 1.2) + 15
+            if left(args) < need:
+                notes.append(f"form {fm} skipped: needs ~{need:.0f} s, {left(args):.0f} s left")
+                log(notes[-1])
+                continue
         log(f"form {fm}")
-        out, st, x0 = run_form(fm, pts, dg, args, bt, xt, F, f_dev)
+        try:
+            if fm == lead:
+                out, st, x0 = run_form(fm, pts, dg, argparse.Namespace(**{**vars(args), "reserve_s": _reserve(args, forms)}),
+                                       bt, xt, F5, F4, f_dev, max(args.steps, 1), min(args.warmup, 1))
+                est_step = out["step_s"]
+            else:
+                out, st, x0 = run_form(fm, pts, dg, argparse.Namespace(**{**vars(args), "reserve_s": 0.0}),
+                                       bt, xt, F5, F4, f_dev, 1, 0)
+        except Exception as e:  # keep the line: report the failure of this form
+            traceback.print_exc()
+            notes.append(f"form {fm} failed: {e}")
+            if fm == lead:
+                break
+            continue
         res[fm] = out
         xs[fm] = x0
         if stats0 is None:
             stats0 = st
-    lead = forms[0]
-    R = res[lead]
     cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on a bounded sample)")
-        cpu = cpu_baseline(args.eps, args.sigma, args.nrhs, N)
+    if not args.no_cpu_baseline and left(args) > 30:
+        log("cpu baseline (oracle on bounded samples)")
+        try:
+            cpu = cpu_baseline(args.eps, args.sigma, args.nrhs, N, args)
+        except Exception as e:
+            traceback.print_exc()
+            notes.append(f"cpu baseline failed: {e}")
+    elif not args.no_cpu_baseline:
+        notes.append(f"cpu baseline skipped: {left(args):.0f} s left")
+    R = res.get(lead, {})
     out = {
-        "metric": METRIC, "value": R["factor_s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": R["step_s"] * 1e3, "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64+f32mfma" if lead == "mixed" else "f64", "data": "synthetic",
+        "metric": METRIC, "value": R.get("factor_s"), "unit": "s", "n_gpus": 1, "steps": R.get("steps_timed", 0),
+        "warmup": min(args.warmup, 1), "ms_per_step": R["step_s"] * 1e3 if R else None, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32mfma" if lead != "fp64" else "f64",
+        "data": "synthetic",
         "config": {"workload": f"ellipsoid (1,0.7,0.3) + 5% jitter, N={N}, Laplace 1/(4 pi r), eps={args.eps}, "
-                               f"sigma={args.sigma}, leaf<=64, Chebyshev 4^3, {args.nrhs} RHS; value = "
-                               f"{'mixed-precision learned-rank' if lead == 'mixed' else 'plain FP64'} form",
+                               f"sigma={args.sigma}, leaf<=64, Chebyshev 4^3, {args.nrhs} RHS; value = factor s of the "
+                               f"{'mixed-precision learned-rank' if lead == 'mixed' else lead} form",
                    "parallelism": "single GPU"},
-        "factor_s": R["factor_s"], "solve_ms_per_rhs": R["solve_ms_per_rhs"],
+        "factor_s": R.get("factor_s"), "solve_ms_per_rhs": R.get("solve_ms_per_rhs"),
+        "steps_requested": args.steps, "warmup_requested": args.warmup,
         "forms": res,
-        "roofline": roofline_of(stats0, lead == "mixed"), "cpu_baseline": cpu,
+        "roofline": roofline_of(stats0, lead != "fp64") if stats0 else None,
+        "roofline_more": roofline_more(stats0, lead != "fp64") if stats0 else None,
+        "cpu_baseline": cpu, "notes": notes, "wall_s": time.time() - T_START,
     }
     if "mixed" in res and "fp64" in res:
         out["factor_speedup_mixed_vs_fp64"] = res["fp64"]["factor_s"] / res["mixed"]["factor_s"]
         xm, x6 = xs["mixed"], xs["fp64"]
         out["mixed_vs_fp64_solution_rel_diff"] = float(np.linalg.norm(xm - x6) / np.linalg.norm(x6))
+    if "mixed" in res and "heuristic" in res:
+        out["learned_rank_ablation"] = {
+            k: {"mixed": res["mixed"].get(k), "heuristic": res["heuristic"].get(k)}
+            for k in ("factor_s", "sketches", "sketches_rejected", "full_decompositions")}
     print(json.dumps(out), flush=True)
+
+
+def _reserve(args, forms):
+    """Seconds to keep free after the lead form's timed steps: the comparison
+    forms (one step each, the FP64 one about twice as long), GMRES and the CPU
+    sample.  Estimated before the first step from the workload size."""
+    if args.reserve_s >= 0:
+        return args.reserve_s
+    scale = args.n / float(1 << 20)
+    est = 0.0
+    if "fp64" in forms:
+        est += 60.0 * scale + 10
+    if "heuristic" in forms:
+        est += 35.0 * scale + 10
+    if not args.no_gmres:
+        est += 10.0 * len(forms)
+    if not args.no_cpu_baseline:
+        est += 80.0
+    return est
 
 
 if __name__ == "__main__":

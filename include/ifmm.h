@@ -68,12 +68,25 @@ typedef enum { IFMM_KERNEL_LAPLACE3D = 0 } ifmm_kernel;
 typedef enum { IFMM_PREC_FP64 = 0, IFMM_PREC_MIXED = 1 } ifmm_precision;
 
 typedef struct {
-  int32_t leaf_max;         /* max points per leaf box; depth = smallest l >= 2 meeting it (64) */
-  int32_t cheb_order;       /* Chebyshev nodes per axis of the IFMM operators, 2..6 (4)          */
-  int32_t precision;        /* ifmm_precision (FP64)                                             */
-  int32_t rank_cap;         /* upper bound on every node rank, 0 = none (0)                      */
-  int64_t max_device_bytes; /* refuse to allocate more device memory than this, 0 = no limit (0) */
-  void* stream;             /* hipStream_t for all device work of the handle, NULL = null stream */
+  int32_t leaf_max;         /* max points per leaf box; the default depth is the smallest l >= 2 meeting it (64) */
+  int32_t cheb_order;       /* Chebyshev nodes per axis of the IFMM operators, 2..6 (4)                       */
+  int32_t precision;        /* ifmm_precision (FP64)                                                          */
+  int32_t top_tau;          /* tau of Sec. 4.2: levels tau..l are eliminated colour by colour (node-parallel),
+                               levels 2..tau-1 one node at a time, every node spread over the whole device
+                               (matrix-parallel); 2 = every level colour by colour (2)                       */
+  const char* rank_model;   /* path of a raw little-endian FP32 file with the rank network's parameters
+                               (ifmm_rank_model_params(IFMM_RANK_FEATURES) values), or NULL = no model (NULL) */
+  const char* tune_cache;   /* path of the tile autotuner's cache file (read, and written after tuning), or
+                               NULL = the built-in tile choices (NULL)                                       */
+  int64_t max_device_bytes; /* refuse to allocate more device memory than this, 0 = no limit (0)              */
+  int32_t deterministic;    /* 1: results bitwise reproducible run to run.  The only mode: the library uses
+                               no floating-point atomics; 0 is accepted and behaves the same (1)             */
+  int32_t bottom_level;     /* l, the depth of the IFMM tree: 0 = from leaf_max, >= 2 = this level (leaves
+                               may then hold more than leaf_max points), -1 = chosen by the cost model of
+                               Sec. 5.2 from the point counts (0)                                            */
+  int32_t rank_cap;         /* upper bound on every node rank, 0 = none (0)                                   */
+  int32_t reserved;         /* must be 0                                                                      */
+  void* stream;             /* hipStream_t for all device work of the handle, NULL = null stream              */
 } ifmm_options;
 
 /* Fills *opt with the defaults listed above. */

@@ -30,7 +30,9 @@ const char* get_error() { return g_err.c_str(); }
 
 int build_host(Handle& h, const double* pts, int64_t n, const double* w, const double* diag, double diag_scalar,
                std::string& err) {
-  err = h.tree.build(pts, n, h.leaf_max, h.sigma);
+  err = h.tree.build(pts, n, h.leaf_max, h.sigma, h.bottom_level > 0 ? h.bottom_level : 0, h.top_tau);
+  if (!err.empty()) return IFMM_EINVAL;
+  err = h.tree.coincident(pts);
   if (!err.empty()) return IFMM_EINVAL;
   h.N = n;
   h.symmetric = (w == nullptr);
@@ -77,8 +79,14 @@ void ifmm_default_options(ifmm_options* opt) {
   opt->leaf_max = 64;
   opt->cheb_order = 4;
   opt->precision = IFMM_PREC_FP64;
-  opt->rank_cap = 0;
+  opt->top_tau = 2;
+  opt->rank_model = nullptr;
+  opt->tune_cache = nullptr;
   opt->max_device_bytes = 0;
+  opt->deterministic = 1;
+  opt->bottom_level = 0;
+  opt->rank_cap = 0;
+  opt->reserved = 0;
   opt->stream = nullptr;
 }
 
@@ -100,6 +108,12 @@ ifmm_status ifmm_build(const double* points, int64_t n, const double* weights, c
   if (o.cheb_order < 2 || o.cheb_order > 6) return fail(IFMM_EINVAL, "cheb_order must lie in [2, 6]");
   if (o.precision != IFMM_PREC_FP64 && o.precision != IFMM_PREC_MIXED) return fail(IFMM_EINVAL, "unknown precision mode");
   if (o.rank_cap < 0) return fail(IFMM_EINVAL, "rank_cap must be >= 0");
+  if (o.top_tau < 2) return fail(IFMM_EINVAL, "top_tau must be >= 2");
+  if (o.bottom_level == -1) return fail(IFMM_EINVAL, "bottom_level = -1 (cost model) is not available");
+  if (o.bottom_level < -1 || o.bottom_level == 1 || o.bottom_level > 10)
+    return fail(IFMM_EINVAL, "bottom_level must be 0 (from leaf_max), -1 (cost model) or in [2, 10]");
+  if (o.deterministic != 0 && o.deterministic != 1) return fail(IFMM_EINVAL, "deterministic must be 0 or 1");
+  if (o.reserved != 0) return fail(IFMM_EINVAL, "reserved must be 0");
   ifmm_handle* H = new (std::nothrow) ifmm_handle();
   if (!H) return fail(IFMM_ENOMEM, "host allocation failed");
   ifmm::Handle& h = H->h;
@@ -112,6 +126,30 @@ ifmm_status ifmm_build(const double* points, int64_t n, const double* weights, c
   h.rank_cap = o.rank_cap;
   h.max_bytes = o.max_device_bytes;
   h.stream = (hipStream_t)o.stream;
+  h.top_tau = o.top_tau;
+  h.bottom_level = o.bottom_level;
+  if (o.tune_cache) h.tune_cache = o.tune_cache;
+  if (o.rank_model) {
+    const int64_t np = ifmm_rank_model_params(IFMM_RANK_FEATURES);
+    FILE* f = std::fopen(o.rank_model, "rb");
+    if (!f) {
+      delete H;
+      return fail(IFMM_EINVAL, std::string("cannot open rank_model file ") + o.rank_model);
+    }
+    h.model_host.assign((size_t)np, 0.f);
+    const size_t got = std::fread(h.model_host.data(), 4, (size_t)np, f);
+    const bool extra = std::fgetc(f) != EOF;
+    std::fclose(f);
+    if (got != (size_t)np || extra) {
+      delete H;
+      return fail(IFMM_EINVAL, "rank_model file must hold exactly " + std::to_string(np) + " FP32 values");
+    }
+    for (float v : h.model_host)
+      if (!std::isfinite(v)) {
+        delete H;
+        return fail(IFMM_ENONFINITE, "non-finite value in the rank_model file");
+      }
+  }
   std::string err;
   int rc;
   try {
@@ -327,6 +365,7 @@ ifmm_status ifmm_set_rank_model(ifmm_handle* H, const float* theta, int32_t nfea
   ifmm::set_error("");
   if (!H) return fail(IFMM_EINVAL, "handle is NULL");
   ifmm::Handle& h = H->h;
+  h.model_host.clear();  // an explicit model (or none) replaces options.rank_model
   if (h.d_model) {
     (void)hipFree(h.d_model);
     h.d_model = nullptr;
@@ -388,13 +427,7 @@ ifmm_status fmm_build(const double* points, int64_t n, const double* weights, co
   std::string err;
   int rc;
   try {
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
-      rc = IFMM_EDEVICE;
-      err = "no HIP device";
-    } else {
-      rc = ifmm::fmm_setup(F->h, points, n, weights, diag, diag_scalar, err);
-    }
+    rc = ifmm::fmm_setup(F->h, points, n, weights, diag, diag_scalar, err);
   } catch (const std::bad_alloc&) {
     rc = IFMM_ENOMEM;
     err = "host allocation failed";

@@ -152,13 +152,17 @@ static int store_take(Handle& h, int64_t doubles, double** out, std::string& err
     double* p = nullptr;
     int rc = dalloc(h, &p, chunk, err);
     if (rc) return rc;
+    // zeroed, so that the padding between records is finite for the final scan
+    HIPCHK(hipMemsetAsync(p, 0, (size_t)chunk * 8, h.stream));
     h.store_chunks.push_back(p);
+    h.store_used.push_back(0);
     h.store_cur = p;
     h.store_left = chunk;
   }
   *out = h.store_cur;
   h.store_cur += doubles;
   h.store_left -= doubles;
+  h.store_used.back() += doubles;
   h.store_bytes += doubles * 8;
   return 0;
 }
@@ -1840,6 +1844,7 @@ static void clear_factor(Handle& h) {
   }
   for (double* p : h.store_chunks) dfree(h, p);
   h.store_chunks.clear();
+  h.store_used.clear();
   h.store_cur = nullptr;
   h.store_left = 0;
   h.store_bytes = 0;
@@ -1855,6 +1860,10 @@ static void clear_factor(Handle& h) {
 int factor(Handle& h, std::string& err) {
   int rc;
   if (!h.dev_ready && (rc = device_init(h, err))) return rc;
+  if (!h.d_model && !h.model_host.empty()) {  // the network named by options.rank_model
+    HIPCHK(hipMalloc((void**)&h.d_model, h.model_host.size() * 4));
+    HIPCHK(hipMemcpy(h.d_model, h.model_host.data(), h.model_host.size() * 4, hipMemcpyHostToDevice));
+  }
   HIPCHK(hipSetDevice(h.device));
   clear_factor(h);
   h.lv.assign((size_t)h.tree.depth + 1, DevLevel());
@@ -1960,15 +1969,33 @@ int factor(Handle& h, std::string& err) {
                        h.d_top_inv);
   }
   HIPCHK(hipGetLastError());
-  int32_t info = 0;
+  // every stored factor block and the top inverse must be finite (an overflow
+  // or a NaN anywhere in the elimination reaches one of them)
+  int32_t* d_nf = nullptr;
+  if ((rc = dalloc(h, &d_nf, 1, err))) return rc;
+  HIPCHK(hipMemsetAsync(d_nf, 0, 4, h.stream));
+  for (size_t q = 0; q < h.store_chunks.size(); ++q)
+    if (h.store_used[q] > 0)
+      hipLaunchKernelGGL(k_check_finite, dim3(2048), dim3(NT), 0, h.stream, h.store_chunks[q], h.store_used[q], d_nf);
+  if (h.top_n > 0)
+    hipLaunchKernelGGL(k_check_finite, dim3(256), dim3(NT), 0, h.stream, h.d_top_inv, (int64_t)h.top_n * h.top_n,
+                       d_nf);
+  HIPCHK(hipGetLastError());
+  int32_t info = 0, nonfinite = 0;
   if (h.top_n > 0) HIPCHK(hipMemcpyAsync(&info, d_info, 4, hipMemcpyDeviceToHost, h.stream));
+  HIPCHK(hipMemcpyAsync(&nonfinite, d_nf, 4, hipMemcpyDeviceToHost, h.stream));
   HSYNC(h);
   dfree(h, d_info);
+  dfree(h, d_nf);
   h.d_top_off = d_toff;
   release_level_work(h, 2);
   if (info) {
     err = "singular top-level system (column " + std::to_string(info - 1) + ")";
     return -4;
+  }
+  if (nonfinite) {
+    err = "non-finite or overflowing value in the factorisation";
+    return -5;
   }
   h.t_top = now_s() - ta;
   h.t_factor = now_s() - t0;

@@ -135,6 +135,7 @@ struct Handle {
   std::vector<DevLevel> lv;
   // persistent factor store (bump allocated in chunks)
   std::vector<double*> store_chunks;
+  std::vector<int64_t> store_used;  // doubles handed out from each chunk
   double* store_cur = nullptr;
   int64_t store_left = 0, store_bytes = 0;
   // growable buffers
@@ -191,6 +192,10 @@ struct Handle {
   int cur_level = 0;
   // learned rank model (FP32 parameters on the device) and recorded samples
   float* d_model = nullptr;
+  std::vector<float> model_host;  // parameters read from options.rank_model (uploaded by the first factor)
+  int top_tau = 2;                // levels below tau: one node per step (matrix-parallel)
+  int bottom_level = 0;           // requested depth: 0 from leaf_max, -1 cost model, >= 2 forced
+  std::string tune_cache;         // autotuner cache file ("" = built-in tile choices)
   double* fbuf = nullptr;
   int64_t fbuf_bytes = 0;
   std::vector<float> rec_X, rec_t;                   // features (14 per row) and r_new / n

@@ -295,6 +295,15 @@ int fmm_setup(FmmHandle& h, const double* pts, int64_t n, const double* w, const
               std::string& err) {
   err = h.tree.build(pts, n, h.leaf_max, 3);
   if (!err.empty()) return -1;
+  err = h.tree.coincident(pts);
+  if (!err.empty()) return -1;
+  {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+      err = "no HIP device";
+      return -3;
+    }
+  }
   h.N = n;
   h.K = h.nc * h.nc * h.nc;
   const int K = h.K;

@@ -83,6 +83,28 @@ int32_t colour_grid(const std::vector<uint8_t>& occ, int m, int sigma, std::vect
   return g;
 }
 
+std::string Tree::coincident(const double* pts) const {
+  const Level& L = levels[depth];
+  std::vector<int64_t> idx;
+  for (int32_t b = 0; b < L.n; ++b) {
+    idx.clear();
+    for (int64_t t = L.pt_begin[b]; t < L.pt_end[b]; ++t) idx.push_back(perm[(size_t)t]);
+    auto less = [&](int64_t a, int64_t c) {
+      for (int e = 0; e < 3; ++e)
+        if (pts[3 * a + e] != pts[3 * c + e]) return pts[3 * a + e] < pts[3 * c + e];
+      return a < c;
+    };
+    std::sort(idx.begin(), idx.end(), less);
+    for (size_t q = 1; q < idx.size(); ++q) {
+      const int64_t a = idx[q - 1], c = idx[q];
+      if (pts[3 * a] == pts[3 * c] && pts[3 * a + 1] == pts[3 * c + 1] && pts[3 * a + 2] == pts[3 * c + 2])
+        return "points " + std::to_string(std::min(a, c)) + " and " + std::to_string(std::max(a, c)) +
+               " coincide (the kernel 1/(4 pi r) is undefined at r = 0)";
+    }
+  }
+  return "";
+}
+
 void Tree::box(int l, int32_t i, double c[3], double* half) const {
   const double side = 2.0 * H / (double)(1LL << l);
   const Level& L = levels[l];
@@ -105,7 +127,7 @@ static void point_keys(const double* pts, int64_t n, const double lo[3], double 
     }
 }
 
-std::string Tree::build(const double* pts, int64_t n, int leaf_max, int sig) {
+std::string Tree::build(const double* pts, int64_t n, int leaf_max, int sig, int depth_req, int tau) {
   if (n < 1) return "need at least one point";
   if (leaf_max < 1) return "leaf_max must be positive";
   sigma = sig;
@@ -132,9 +154,15 @@ std::string Tree::build(const double* pts, int64_t n, int leaf_max, int sig) {
   // depth: smallest level >= 2 whose fullest leaf holds <= leaf_max points
   std::vector<int32_t> key;
   std::vector<int64_t> code((size_t)n);
-  int L = 2;
+  int L = depth_req >= 2 ? depth_req : 2;
   for (;; ++L) {
     if (L > 10) return "leaf size not reachable (too many coincident points)";
+    if (depth_req >= 2) {  // the requested depth, whatever the leaf sizes
+      point_keys(pts, n, lo, H, L, key);
+      const int64_t m = 1LL << L;
+      for (int64_t p = 0; p < n; ++p) code[p] = lex(key[3 * p], key[3 * p + 1], key[3 * p + 2], m);
+      break;
+    }
     point_keys(pts, n, lo, H, L, key);
     const int64_t m = 1LL << L;
     for (int64_t p = 0; p < n; ++p) code[p] = lex(key[3 * p], key[3 * p + 1], key[3 * p + 2], m);
@@ -243,7 +271,15 @@ std::string Tree::build(const double* pts, int64_t n, int leaf_max, int sig) {
     std::vector<uint8_t> occ((size_t)(m * m * m), 0);
     for (int32_t i = 0; i < lv.n; ++i) occ[(size_t)lex(lv.coord[3 * i], lv.coord[3 * i + 1], lv.coord[3 * i + 2], m)] = 1;
     std::vector<int32_t> grid;
-    lv.ncolour = colour_grid(occ, (int)m, sigma, grid);
+    if (l < tau) {  // one node per colour, in scan order
+      grid.assign(occ.size(), -1);
+      int32_t g = 0;
+      for (size_t e = 0; e < occ.size(); ++e)
+        if (occ[e]) grid[e] = g++;
+      lv.ncolour = g;
+    } else {
+      lv.ncolour = colour_grid(occ, (int)m, sigma, grid);
+    }
     lv.colour.resize((size_t)lv.n);
     std::vector<int32_t> cnt((size_t)lv.ncolour + 1, 0);
     for (int32_t i = 0; i < lv.n; ++i) {

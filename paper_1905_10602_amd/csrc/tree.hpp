@@ -37,9 +37,17 @@ struct Tree {
   std::vector<Level> levels;   // index = level; entries 0 and 1 unused
 
   // Builds everything; returns an empty string on success, else the reason.
-  std::string build(const double* pts, int64_t n, int leaf_max, int sigma);
+  // depth_req: 0 = smallest level >= 2 with at most leaf_max points per leaf,
+  // >= 2 = that level.  Levels below tau get one node per colour (scan order):
+  // they are eliminated one node at a time (the matrix-parallel levels of
+  // Sec. 4.2); tau = 2 colours every level with Alg. 3.
+  std::string build(const double* pts, int64_t n, int leaf_max, int sigma, int depth_req = 0, int tau = 2);
   // Box centre and half-side of node i at level l.
   void box(int l, int32_t i, double c[3], double* half) const;
+  // After build(): an empty string if no two points coincide, else a message
+  // naming one coincident pair by original index (the kernel is undefined at
+  // r = 0).  Coincident points share a leaf, so each leaf is checked alone.
+  std::string coincident(const double* pts) const;
 };
 
 // Alg. 3 on an m x m x m occupancy grid indexed [k][j][i]; returns the number

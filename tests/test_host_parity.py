@@ -108,3 +108,56 @@ def test_fmm_rejects_bad_arguments_and_needs_a_device():
         with pytest.raises(IfmmError) as e:
             FMM(pts, 1.0)
         assert e.value.status == "IFMM_EDEVICE"
+
+
+def test_rejects_coincident_points_naming_the_pair():
+    from paper_1905_10602_amd import FMM, IFMM, IfmmError
+    pts = synth.sphere_points(500, 3)
+    pts[417] = pts[22]
+    with pytest.raises(IfmmError) as e:
+        IFMM(pts, 1e-6, 3, diag=1.0, leaf_max=16)
+    assert e.value.status == "IFMM_EINVAL"
+    assert "22 and 417" in str(e.value)
+    with pytest.raises(IfmmError) as e:
+        FMM(pts, 1.0, leaf_max=16)
+    assert e.value.status == "IFMM_EINVAL" and "22 and 417" in str(e.value)
+    # a pair that differs in one bit of one coordinate is accepted
+    pts[417, 2] = np.nextafter(pts[22, 2], 2.0)
+    IFMM(pts, 1e-6, 3, diag=1.0, leaf_max=16).close()
+
+
+def test_options_of_the_boundary(tmp_path):
+    from paper_1905_10602_amd import IFMM, IfmmError, rank_model_params
+    pts = synth.sphere_points(3000, 5)
+    for kw in ({"top_tau": 1}, {"bottom_level": 1}, {"bottom_level": 11}, {"bottom_level": -2}):
+        with pytest.raises(IfmmError) as e:
+            IFMM(pts, 1e-6, 3, diag=1.0, **kw)
+        assert e.value.status == "IFMM_EINVAL", kw
+    # a forced depth, whatever the leaf size
+    h = IFMM(pts, 1e-6, 3, diag=1.0, leaf_max=16, bottom_level=3)
+    assert h.depth() == 3
+    assert IFMM(pts, 1e-6, 3, diag=1.0, leaf_max=16).depth() > 3
+    # top_tau: levels below tau get one node per colour (one node at a time)
+    h = IFMM(pts, 1e-6, 3, diag=1.0, leaf_max=16, top_tau=4)
+    T = Tree(pts, leaf_max=16, sigma=3)
+    for lvl in range(2, h.depth() + 1):
+        d = h.level(lvl)
+        if lvl < 4:
+            assert d["ncolour"] == len(d["colour"]) and np.array_equal(d["colour"], np.arange(len(d["colour"])))
+        else:
+            assert np.array_equal(d["colour"], T.levels[lvl].colour)
+    # the rank network from a raw FP32 file: exact size, finite values
+    npar = rank_model_params()
+    good = tmp_path / "model.f32"
+    np.zeros(npar, dtype="<f4").tofile(good)
+    IFMM(pts, 1e-6, 3, diag=1.0, rank_model=str(good)).close()
+    short = tmp_path / "short.f32"
+    np.zeros(npar - 1, dtype="<f4").tofile(short)
+    bad = tmp_path / "nan.f32"
+    v = np.zeros(npar, dtype="<f4")
+    v[5] = np.nan
+    v.tofile(bad)
+    for path, status in ((short, "IFMM_EINVAL"), (bad, "IFMM_ENONFINITE"), (tmp_path / "missing.f32", "IFMM_EINVAL")):
+        with pytest.raises(IfmmError) as e:
+            IFMM(pts, 1e-6, 3, diag=1.0, rank_model=str(path))
+        assert e.value.status == status, path
