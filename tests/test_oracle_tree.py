@@ -24,9 +24,9 @@ def sphere_occupancy(level):
     return (dmin < 0.5) & (dmax > 0.5)
 
 
-def load_table1():
+def load_table2():
     rows = []
-    with open(os.path.join(GOLDEN, "table1_sphere_colouring.txt")) as f:
+    with open(os.path.join(GOLDEN, "table2_sphere_colouring.txt")) as f:
         for line in f:
             if line.startswith("#") or not line.strip():
                 continue
@@ -35,8 +35,8 @@ def load_table1():
     return rows
 
 
-@pytest.mark.parametrize("row", load_table1())
-def test_table1_sigma3(row):
+@pytest.mark.parametrize("row", load_table2())
+def test_table2_sigma3(row):
     lv, nodes, groups, mn, avg, mx = row
     occ = sphere_occupancy(lv)
     assert occ.sum() == nodes
