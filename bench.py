@@ -55,7 +55,8 @@ FP64_VECTOR_PEAK = 78.6e12      # 256 CUs x 2.4 GHz x 128 FP64 flop/clk
 FP64_MFMA_PEAK = 78.6e12        # dense FP64 matrix-core peak
 HBM_PEAK = 8.0e12               # bytes/s
 FP32_MFMA_PEAK = 157.3e12      # dense FP32 matrix-core peak
-BOUND = {"k_fwd": "hbm", "k_bwd": "hbm", "k_gather": "hbm", "group:solve_graph": "hbm"}
+BOUND = {"k_solve_fwd_w": "hbm", "k_solve_fwd_upd": "hbm", "k_solve_bwd": "hbm", "k_gather": "hbm",
+         "solve": "hbm"}
 MFMA_F32 = {"k_schur"}          # runs on FP32 matrix cores in the mixed form
 MFMA_F64 = set()                 # kernels on FP64 matrix cores in the FP64 form
 
@@ -211,6 +212,10 @@ def run_form(name, pts, dg, args, bt, xt, F5, F4, f_dev, max_steps, warmup):
         ys = [F4.matvec(xt[k].contiguous()) for k in range(args.nrhs)]
         gm["e_res"] = max(float(torch.linalg.norm(ys[k] - bt[k]) / torch.linalg.norm(bt[k])) for k in range(args.nrhs))
         gm["e_res_over_eps"] = gm["e_res"] / args.eps
+        gm["backward_error"] = max(float(torch.linalg.norm(ys[k] - bt[k]) /
+                                         (args.anorm * torch.linalg.norm(xt[k]) + torch.linalg.norm(bt[k])))
+                                   for k in range(args.nrhs))
+        gm["backward_error_over_eps"] = gm["backward_error"] / args.eps
     if F5 is not None:
         y = F5.matvec(xt[0].contiguous())
         gm["solve_residual_on_cheb5_fmm"] = float(torch.linalg.norm(y - bt[0]) / torch.linalg.norm(bt[0]))
@@ -229,6 +234,16 @@ def run_form(name, pts, dg, args, bt, xt, F5, F4, f_dev, max_steps, warmup):
         _check(load_library().ifmm_solve(h._h, _ptr(bt[0]), _ptr(x1), 1, N, 1))
     torch.cuda.synchronize()
     gm["solve_1rhs_ms"] = (time.perf_counter() - t0) * 1e3 / 3
+    # per-kernel timing of the solve steps: three eager (uncaptured) solves of
+    # the RHS block, each launch between hipEvents on the solve's stream
+    os.environ["IFMM_GRAPH"] = "0"
+    xe = torch.empty_like(bt)
+    for _ in range(3):
+        _check(load_library().ifmm_solve(h._h, _ptr(bt), _ptr(xe), args.nrhs, N, 1))
+    torch.cuda.synchronize()
+    os.environ["IFMM_GRAPH"] = "1"
+    gm["eager_solve_equals_graph"] = bool(torch.equal(xe, xt))
+    stats = h.stats()
     h.close()
     med = lambda key: statistics.median(t[key] for t in times)
     out = {"steps_timed": len(times), "factor_s": med("factor_s"), "solve_ms_per_rhs": med("solve_s") * 1e3 / args.nrhs,
@@ -311,9 +326,14 @@ def roofline_more(stats, mixed):
     whole captured solve) beside the dominant kernel."""
     ks = stats.get("kernels", {})
     out = {}
-    for n in ("k_schur", "k_fwd", "k_bwd", "group:solve_graph"):
+    for n in ("k_schur", "k_eig_values", "k_solve_fwd_w", "k_solve_fwd_upd", "k_solve_bwd"):
         if n in ks:
             out[n] = price(n, ks[n], mixed)
+    # the three solve steps together: algorithmic bytes over their summed time
+    parts = [ks[n] for n in ("k_solve_fwd_w", "k_solve_fwd_upd", "k_solve_bwd") if n in ks]
+    if parts:
+        tot = {"ms": sum(p["ms"] for p in parts), "launches": 1, "flops": 0.0, "bytes": sum(p["bytes"] for p in parts)}
+        out["solve"] = price("solve", tot, mixed)
     return out
 
 
@@ -376,7 +396,17 @@ def main():
         f_dev = bt[0].contiguous()
         log(f"FMM (order 5) built: {json.dumps(F5.stats())}")
     F4 = FMM(pts, dg, cheb_order=4, leaf_max=64)  # the IFMM's own tree and operators: exactly A~
-    log("FMM (order 4, the IFMM's tree) built")
+    # ||A~||_2 from power iteration (A~ is symmetric for unit weights): the
+    # scale of the normwise backward error ||A~ x - b|| / (||A~|| ||x|| + ||b||)
+    v = torch.from_numpy(synth.uniform_rhs(N, 1, 77)[:, 0].copy()).cuda()
+    v /= torch.linalg.norm(v)
+    anorm = 0.0
+    for _ in range(30):
+        w = F4.matvec(v)
+        anorm = float(torch.linalg.norm(w))
+        v = w / anorm
+    args.anorm = anorm
+    log(f"FMM (order 4, the IFMM's tree) built; ||A~||_2 ~ {anorm:.4e}")
     forms = {"all": ["mixed", "fp64", "heuristic"], "both": ["mixed", "fp64"], "mixed": ["mixed"], "fp64": ["fp64"],
              "heuristic": ["heuristic"]}[args.form]
     res, stats0, xs = {}, None, {}

@@ -85,7 +85,9 @@ typedef struct {
                                may then hold more than leaf_max points), -1 = chosen by the cost model of
                                Sec. 5.2 from the point counts (0)                                            */
   int32_t rank_cap;         /* upper bound on every node rank, 0 = none (0)                                   */
-  int32_t reserved;         /* must be 0                                                                      */
+  int32_t colouring;        /* 0: Alg. 3 (sigma-stride greedy); 1: look-back greedy, which takes every box
+                               at distance >= sigma from all boxes of the colour so far (the improvement
+                               the closing remark of Sec. 3.4 names) (0)                                   */
   void* stream;             /* hipStream_t for all device work of the handle, NULL = null stream              */
 } ifmm_options;
 

@@ -127,7 +127,7 @@ class IFMM:
     """
 
     def __init__(self, points, eps=1e-6, sigma=6, leaf_max=64, cheb_order=4,
-                 weights=None, diag=None, rank_cap=0):
+                 weights=None, diag=None, rank_cap=0, depth=0, tau=2, colouring="stride"):
         points = np.asarray(points, dtype=np.float64)
         N = points.shape[0]
         self.N = N
@@ -144,7 +144,7 @@ class IFMM:
         self.nc = int(cheb_order)
         self.K = self.nc ** 3
         self.rank_cap = int(rank_cap)
-        self.tree = Tree(points, leaf_max=leaf_max, sigma=sigma)
+        self.tree = Tree(points, leaf_max=leaf_max, sigma=sigma, depth=depth, tau=tau, colouring=colouring)
         self.depth = self.tree.depth
         self.factored = False
         self._m2m_unit = {}
@@ -520,7 +520,7 @@ class IFMM:
         return {lvl: self.state[lvl]["r"].copy() for lvl in range(2, self.depth + 1)}
 
 
-def dense_tilde(points, weights, diag, leaf_max=64, cheb_order=4, sigma=6):
+def dense_tilde(points, weights, diag, leaf_max=64, cheb_order=4, sigma=6, depth=0):
     """The matrix the extended system represents exactly (tiny N only):
     near leaf pairs (dist <= 1) take A; every other leaf pair takes
     L2P (L2L chain) M2L (M2M chain) P2M at the level where the two ancestors
@@ -529,7 +529,7 @@ def dense_tilde(points, weights, diag, leaf_max=64, cheb_order=4, sigma=6):
     N = points.shape[0]
     w = np.ones(N) if weights is None else np.asarray(weights, dtype=np.float64)
     dg = np.full(N, float(diag)) if np.isscalar(diag) else np.asarray(diag, dtype=np.float64)
-    T = Tree(points, leaf_max=leaf_max, sigma=sigma)
+    T = Tree(points, leaf_max=leaf_max, sigma=sigma, depth=depth)
     L = T.depth
     nc = cheb_order
     leaf = T.levels[L]

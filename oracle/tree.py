@@ -160,13 +160,46 @@ def colour_grid(occupied: np.ndarray, sigma: int) -> np.ndarray:
     return colour
 
 
-def colour_level(lev: Level, sigma: int):
+def colour_lookback(coords: np.ndarray, sigma: int) -> np.ndarray:
+    """Greedy colouring that looks back at the boxes already coloured (the
+    improvement Sec. 3.4 names in its closing remark and Sec. 6 leaves open).
+
+    coords: (n, 3) integer box coordinates in (k, j, i) scan order.  Each
+    colour walks all uncoloured boxes in scan order and takes every box whose
+    distance (largest coordinate difference) to every box it already holds is
+    at least sigma; the first uncoloured box always qualifies.  Same-colour
+    boxes are then sigma-separated by construction.
+    """
+    n = coords.shape[0]
+    colour = np.full(n, -1, dtype=np.int64)
+    g = 0
+    while np.any(colour < 0):
+        members = np.empty((0, 3), dtype=coords.dtype)
+        for i in range(n):
+            if colour[i] >= 0:
+                continue
+            if members.shape[0] == 0 or np.min(np.max(np.abs(members - coords[i]), axis=1)) >= sigma:
+                colour[i] = g
+                members = np.vstack([members, coords[i]])
+        g += 1
+    return colour
+
+
+def colour_level(lev: Level, sigma: int, tau: int = 2, colouring: str = "stride"):
+    """Colours of one level: one node per colour below tau (the levels
+    eliminated one node at a time), else Alg. 3 ("stride") or the look-back
+    greedy ("lookback")."""
     m = 1 << lev.level
-    occ = np.zeros((m, m, m), dtype=bool)
     c = lev.coords
-    occ[c[:, 2], c[:, 1], c[:, 0]] = True
-    grid = colour_grid(occ, sigma)
-    lev.colour = grid[c[:, 2], c[:, 1], c[:, 0]].copy()
+    if lev.level < tau:
+        lev.colour = np.arange(lev.n, dtype=np.int64)
+    elif colouring == "lookback":
+        lev.colour = colour_lookback(c, sigma)
+    else:
+        occ = np.zeros((m, m, m), dtype=bool)
+        occ[c[:, 2], c[:, 1], c[:, 0]] = True
+        grid = colour_grid(occ, sigma)
+        lev.colour = grid[c[:, 2], c[:, 1], c[:, 0]].copy()
     ng = int(lev.colour.max()) + 1 if lev.n else 0
     # nodes are in (k, j, i) order, which is also the order Alg. 3 assigns them
     lev.groups = [[] for _ in range(ng)]
@@ -181,7 +214,8 @@ class Tree:
     l = 2 .. depth (entries 0 and 1 are None).
     """
 
-    def __init__(self, points: np.ndarray, leaf_max: int = 64, sigma: int = 6):
+    def __init__(self, points: np.ndarray, leaf_max: int = 64, sigma: int = 6, depth: int = 0, tau: int = 2,
+                 colouring: str = "stride"):
         points = np.asarray(points, dtype=np.float64)
         if points.ndim != 2 or points.shape[1] != 3 or points.shape[0] < 1:
             raise ValueError("points must be an (N, 3) array with N >= 1")
@@ -189,7 +223,7 @@ class Tree:
             raise ValueError("non-finite coordinates")
         self.points = points
         self.lo, self.H = root_cube(points)
-        self.depth = choose_depth(points, self.lo, self.H, leaf_max)
+        self.depth = depth if depth >= 2 else choose_depth(points, self.lo, self.H, leaf_max)
         L = self.depth
         keys = box_keys(points, self.lo, self.H, L)
         codes = lex_code(keys, L)
@@ -217,7 +251,7 @@ class Tree:
                 coarse.children[p].append(i)
         for lvl in range(2, L + 1):
             self._lists(lvl)
-            colour_level(self.levels[lvl], sigma)
+            colour_level(self.levels[lvl], sigma, tau, colouring)
         self.sigma = sigma
 
     def _lists(self, lvl: int):

@@ -30,8 +30,15 @@ const char* get_error() { return g_err.c_str(); }
 
 int build_host(Handle& h, const double* pts, int64_t n, const double* w, const double* diag, double diag_scalar,
                std::string& err) {
-  err = h.tree.build(pts, n, h.leaf_max, h.sigma, h.bottom_level > 0 ? h.bottom_level : 0, h.top_tau);
+  err = h.tree.build(pts, n, h.leaf_max, h.sigma, h.bottom_level > 0 ? h.bottom_level : 0, h.top_tau, h.colouring);
   if (!err.empty()) return IFMM_EINVAL;
+  if (h.bottom_level == -1) {  // the depth the cost model prefers (a coarser leaf level, or the same)
+    const int l = h.tree.cost_depth(h.K, &h.depth_costs);
+    if (l != h.tree.depth) {
+      err = h.tree.build(pts, n, h.leaf_max, h.sigma, l, h.top_tau, h.colouring);
+      if (!err.empty()) return IFMM_EINVAL;
+    }
+  }
   err = h.tree.coincident(pts);
   if (!err.empty()) return IFMM_EINVAL;
   h.N = n;
@@ -86,7 +93,7 @@ void ifmm_default_options(ifmm_options* opt) {
   opt->deterministic = 1;
   opt->bottom_level = 0;
   opt->rank_cap = 0;
-  opt->reserved = 0;
+  opt->colouring = 0;
   opt->stream = nullptr;
 }
 
@@ -109,11 +116,10 @@ ifmm_status ifmm_build(const double* points, int64_t n, const double* weights, c
   if (o.precision != IFMM_PREC_FP64 && o.precision != IFMM_PREC_MIXED) return fail(IFMM_EINVAL, "unknown precision mode");
   if (o.rank_cap < 0) return fail(IFMM_EINVAL, "rank_cap must be >= 0");
   if (o.top_tau < 2) return fail(IFMM_EINVAL, "top_tau must be >= 2");
-  if (o.bottom_level == -1) return fail(IFMM_EINVAL, "bottom_level = -1 (cost model) is not available");
   if (o.bottom_level < -1 || o.bottom_level == 1 || o.bottom_level > 10)
     return fail(IFMM_EINVAL, "bottom_level must be 0 (from leaf_max), -1 (cost model) or in [2, 10]");
   if (o.deterministic != 0 && o.deterministic != 1) return fail(IFMM_EINVAL, "deterministic must be 0 or 1");
-  if (o.reserved != 0) return fail(IFMM_EINVAL, "reserved must be 0");
+  if (o.colouring != 0 && o.colouring != 1) return fail(IFMM_EINVAL, "colouring must be 0 (Alg. 3) or 1 (look-back)");
   ifmm_handle* H = new (std::nothrow) ifmm_handle();
   if (!H) return fail(IFMM_ENOMEM, "host allocation failed");
   ifmm::Handle& h = H->h;
@@ -128,6 +134,7 @@ ifmm_status ifmm_build(const double* points, int64_t n, const double* weights, c
   h.stream = (hipStream_t)o.stream;
   h.top_tau = o.top_tau;
   h.bottom_level = o.bottom_level;
+  h.colouring = o.colouring;
   if (o.tune_cache) h.tune_cache = o.tune_cache;
   if (o.rank_model) {
     const int64_t np = ifmm_rank_model_params(IFMM_RANK_FEATURES);
@@ -208,6 +215,17 @@ ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
                   ",\"sketches_narrow\":" + std::to_string(h.stat_sketch_narrow) +
                   ",\"rank_predictions\":" + std::to_string(h.stat_predicted) +
                   ",\"t_sync\":" + std::to_string(h.t_sync) +
+                  ",\"top_tau\":" + std::to_string(h.top_tau) + ",\"colouring\":" + std::to_string(h.colouring) +
+                  ",\"bottom_level\":" + std::to_string(h.bottom_level) + ",\"depth_costs\":[" +
+                  [&] {
+                    std::string c;
+                    for (size_t q = 0; q < h.depth_costs.size(); ++q) {
+                      char b[40];
+                      std::snprintf(b, sizeof b, "%s%.6e", q ? "," : "", h.depth_costs[q]);
+                      c += b;
+                    }
+                    return c;
+                  }() + "]" +
                   ",\"t_h2d\":" + std::to_string(h.t_h2d) +
                   ",\"levels\":[";
   for (int l = 2; l <= h.tree.depth; ++l) {

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <numeric>
+#include <mutex>
 #include <thread>
 
 #include "engine.hpp"
@@ -710,6 +711,30 @@ static int sk_orthonormalise(Handle& h, const std::vector<SkTask>& T, const SkTa
   return 0;
 }
 
+// X = D^-1 X for the nb large pivots of tasks (orders <= dmax, X widths <=
+// wmax): the right-looking blocked LU of [D | X] with the panel steps, then
+// the blocked backward substitution, every step one launch over all pivots.
+static void enqueue_blocked_lu(const BluTask* d_blu, unsigned nb, int dmax, int wmax, hipStream_t st) {
+  const unsigned wch = (unsigned)std::max(1, (wmax + 63) / 64);
+  const int nsteps = (dmax + BLU_NB - 1) / BLU_NB;
+  for (int s = 0; s < nsteps; ++s) {
+    const int j0 = s * BLU_NB;
+    const unsigned rows = (unsigned)std::max(1, (dmax - j0 - BLU_NB + 63) / 64);
+    const unsigned cols = (unsigned)((std::max(0, dmax - j0 - BLU_NB) + 63) / 64 + (wmax + 63) / 64 + 1);
+    const unsigned swp = (unsigned)((dmax + wmax + NT - 1) / NT);
+    hipLaunchKernelGGL(k_blu_panel, dim3(nb), dim3(NT), 0, st, d_blu, j0);
+    hipLaunchKernelGGL(k_blu_swap, dim3(swp, nb), dim3(NT), 0, st, d_blu, j0);
+    hipLaunchKernelGGL(k_blu_trsm, dim3(cols, nb), dim3(NT), 0, st, d_blu, j0);
+    if (dmax - j0 - BLU_NB > 0) hipLaunchKernelGGL(k_blu_gemm, dim3(rows, cols, nb), dim3(NT), 0, st, d_blu, j0);
+  }
+  hipLaunchKernelGGL(k_blu_uinv, dim3((unsigned)nsteps, nb), dim3(NT), 0, st, d_blu);
+  for (int s = nsteps - 1; s >= 0; --s) {
+    const int j0 = s * BLU_NB;
+    hipLaunchKernelGGL(k_bu_trsm, dim3(wch, nb), dim3(NT), 0, st, d_blu, s);
+    if (j0 > 0) hipLaunchKernelGGL(k_bu_gemm, dim3((unsigned)((j0 + 63) / 64), wch, nb), dim3(NT), 0, st, d_blu, s);
+  }
+}
+
 static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   const Level& T = h.tree.levels[l];
   DevLevel& L = h.lv[l];
@@ -836,7 +861,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         }
       }
       if (R.d < h.big_d)
-        for (int c0 = 0; c0 < R.M + R.r; c0 += XCOLS) P.xtasks.push_back({k, c0});
+        for (int c0 = 0; c0 < R.M + R.r + R.n; c0 += XCOLS) P.xtasks.push_back({k, c0});
     }
   });
   {
@@ -868,7 +893,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   // scratch and persistent factor storage, in record order
   for (int k = 0; k < nrec; ++k) {
     ElimRec& R = recs[k];
-    x_off[k] = stake((int64_t)R.d * (R.M + R.r + (R.inv ? R.n : 0)));
+    x_off[k] = stake((int64_t)R.d * (R.M + R.r + R.n));
     dinv_off[k] = R.inv ? stake((int64_t)((R.d + BLU_NB - 1) / BLU_NB) * 2 * 4096) : 0;
     int rc;
     double* p;
@@ -1061,29 +1086,15 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     ProfScope ps(h, "group:blocked_lu", fl_blu, 0);
     const unsigned wch = (unsigned)std::max(1, (blu_wmax + 63) / 64);
     hipLaunchKernelGGL(k_blu_xinit, dim3(wch, nb), dim3(NT), 0, h.stream, d_blu, d_recs, d_blur);
-    const int nsteps = (blu_dmax + BLU_NB - 1) / BLU_NB;
-    for (int st = 0; st < nsteps; ++st) {
-      const int j0 = st * BLU_NB;
-      const unsigned rows = (unsigned)std::max(1, (blu_dmax - j0 - BLU_NB + 63) / 64);
-      const unsigned cols = (unsigned)((std::max(0, blu_dmax - j0 - BLU_NB) + 63) / 64 + (blu_wmax + 63) / 64 + 1);
-      const unsigned swp = (unsigned)((blu_dmax + blu_wmax + NT - 1) / NT);
-      hipLaunchKernelGGL(k_blu_panel, dim3(nb), dim3(NT), 0, h.stream, d_blu, j0);
-      hipLaunchKernelGGL(k_blu_swap, dim3(swp, nb), dim3(NT), 0, h.stream, d_blu, j0);
-      hipLaunchKernelGGL(k_blu_trsm, dim3(cols, nb), dim3(NT), 0, h.stream, d_blu, j0);
-      if (blu_dmax - j0 - BLU_NB > 0)
-        hipLaunchKernelGGL(k_blu_gemm, dim3(rows, cols, nb), dim3(NT), 0, h.stream, d_blu, j0);
-    }
-    hipLaunchKernelGGL(k_blu_uinv, dim3((unsigned)nsteps, nb), dim3(NT), 0, h.stream, d_blu);
-    for (int st = nsteps - 1; st >= 0; --st) {
-      const int j0 = st * BLU_NB;
-      hipLaunchKernelGGL(k_bu_trsm, dim3(wch, nb), dim3(NT), 0, h.stream, d_blu, st);
-      if (j0 > 0)
-        hipLaunchKernelGGL(k_bu_gemm, dim3((unsigned)((j0 + 63) / 64), wch, nb), dim3(NT), 0, h.stream, d_blu, st);
-    }
-    hipLaunchKernelGGL(k_blu_store_inv, dim3((unsigned)((blu_dmax + 63) / 64), nb), dim3(NT), 0, h.stream, d_blu,
-                       d_recs, d_blur);
+    enqueue_blocked_lu(d_blu, nb, blu_dmax, blu_wmax, h.stream);
   }
   if (aside && (rc = join_side(h, err))) return rc;
+  {
+    // the solve's blocks: explicit pivot inverses and G = x-rows of X
+    int wmax = 1;
+    for (const ElimRec& R : recs) wmax = std::max(wmax, std::max(R.d, R.M));
+    hipLaunchKernelGGL(k_store_solve, dim3((unsigned)((wmax + 63) / 64), (unsigned)nrec), dim3(NT), 0, h.stream, d_recs);
+  }
   {
     ProfScope ps(h, "k_schur", fl_schur, by_schur);
     // inner dimension of the products = n of the pivot; the double-buffered
@@ -1735,12 +1746,20 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   }
   HIPCHK(hipGetLastError());
   lap.mark("phase_b");
-  // keep the records for the solve (neighbour entries rebased on the level table)
+  // keep the records for the solve (neighbour entries rebased on the level
+  // table) and its 64-row tiles: pivot rows, L rows, G rows
   for (ElimRec R : recs) {
     R.nb_begin += nbase;
     R.X = nullptr;
+    const int32_t ri = (int32_t)L.recs.size();
+    for (int r0 = 0; r0 < R.d; r0 += 64) L.st_w.push_back({ri, r0});
+    for (int r0 = 0; r0 < R.M; r0 += 64) L.st_u.push_back({ri, r0});
+    for (int r0 = 0; r0 < R.n; r0 += 64) L.st_b.push_back({ri, r0});
     L.recs.push_back(R);
   }
+  L.stw_ptr.push_back((int32_t)L.st_w.size());
+  L.stu_ptr.push_back((int32_t)L.st_u.size());
+  L.stb_ptr.push_back((int32_t)L.st_b.size());
   L.nbrs.insert(L.nbrs.end(), nbrs.begin(), nbrs.end());
   L.col_ptr.push_back((int32_t)L.recs.size());
   ColourInv ci;
@@ -1812,6 +1831,16 @@ static int finish_level(Handle& h, int l, std::string& err) {
   L.d_nbrs = nullptr;
   if ((rc = upload(h, &L.d_recs, L.recs, err))) return rc;
   if ((rc = upload(h, &L.d_nbrs, L.nbrs, err))) return rc;
+  dfree(h, L.d_st);
+  L.d_st = nullptr;
+  {
+    std::vector<STask> all;
+    all.reserve(L.st_w.size() + L.st_u.size() + L.st_b.size());
+    all.insert(all.end(), L.st_w.begin(), L.st_w.end());
+    all.insert(all.end(), L.st_u.begin(), L.st_u.end());
+    all.insert(all.end(), L.st_b.begin(), L.st_b.end());
+    if ((rc = upload(h, &L.d_st, all, err))) return rc;
+  }
   // solve-vector offsets
   L.vx_off.resize(L.nn);
   L.vz_off.resize(L.nn);
@@ -1838,7 +1867,8 @@ static void clear_factor(Handle& h) {
   for (size_t l = 0; l < h.lv.size(); ++l) {
     release_level_work(h, (int)l);
     DevLevel& L = h.lv[l];
-    void* ptrs[] = {L.d_recs, L.d_nbrs, L.d_vx_off, L.d_vz_off, L.d_n, L.d_r, L.d_parent, L.d_child_ptr, L.d_child};
+    void* ptrs[] = {L.d_recs, L.d_nbrs, L.d_vx_off, L.d_vz_off, L.d_n, L.d_r, L.d_parent, L.d_child_ptr, L.d_child,
+                    L.d_st};
     for (void* p : ptrs) dfree(h, p);
     L = DevLevel();
   }
@@ -1909,6 +1939,8 @@ int factor(Handle& h, std::string& err) {
     DevLevel& L = h.lv[l];
     L.col_ptr.assign(1, 0);
     L.cinv.clear();
+    L.st_w.clear(); L.st_u.clear(); L.st_b.clear();
+    L.stw_ptr.assign(1, 0); L.stu_ptr.assign(1, 0); L.stb_ptr.assign(1, 0);
     ta = now_s();
     h.cur_level = l;
     for (int c = 0; c < T.ncolour; ++c)
@@ -2017,128 +2049,160 @@ static void release_graph(Handle& h) {
   h.g_key_k = -1;
 }
 
+// Layout of the solve's work vector for k right-hand sides: per level X, Z,
+// W and tmp, then the top system's two vectors (the part up to `zeroed` is
+// cleared by every solve), then staging for host vectors.
+struct SolvePlan {
+  std::vector<int64_t> ox, oz, ow, ot;
+  int64_t otop = 0, oio = 0, total = 0;  // doubles
+};
+static SolvePlan solve_plan(const Handle& h, int k, int64_t ld, bool staging) {
+  const int D = h.tree.depth;
+  SolvePlan P;
+  P.ox.assign(D + 1, 0); P.oz.assign(D + 1, 0); P.ow.assign(D + 1, 0); P.ot.assign(D + 1, 0);
+  int64_t tot = 0;
+  for (int l = 2; l <= D; ++l) {
+    const DevLevel& L = h.lv[l];
+    P.ox[l] = tot; tot += L.vx_total * k + 32;
+    P.oz[l] = tot; tot += L.vz_total * k + 32;
+    P.ow[l] = tot; tot += L.wv_total * k + 32;
+    P.ot[l] = tot; tot += L.wv_total * k + 32;
+  }
+  P.otop = tot;
+  tot += 2 * (int64_t)std::max(h.top_n, 1) * k + 32;
+  P.oio = tot;
+  if (staging) tot += 2 * ld * k + 32;
+  P.total = tot;
+  return P;
+}
+
+// One launch of a solve step over `ntask` row tiles (four per workgroup), the
+// right-hand-side chunk width chosen for k (1, 4 or 8 columns at a time).
+template <class K1, class K4, class K8, class... Args>
+static void launch_solve(K1 k1, K4 k4, K8 k8, int k, int ntask, hipStream_t st, Args... args) {
+  const dim3 grid((unsigned)((ntask + NT / 64 - 1) / (NT / 64)));
+  if (k == 1) hipLaunchKernelGGL(k1, grid, dim3(NT), 0, st, args...);
+  else if (k <= 4) hipLaunchKernelGGL(k4, grid, dim3(NT), 0, st, args...);
+  else hipLaunchKernelGGL(k8, grid, dim3(NT), 0, st, args...);
+}
+
+// The substitution (Alg. 2) as one stream of launches on h.stream over the
+// work vector B (layout P): clears B, then up the levels (colours ascending),
+// the top solve, down the levels (colours descending).  Records hipEvent
+// timings only when h.prof is set.
+static void enqueue_solve(Handle& h, const SolvePlan& P, double* B, const double* d_rhs, double* d_x, int k,
+                          int64_t ld) {
+  const int D = h.tree.depth;
+  auto sv = [&](int l) {
+    SolveView S;
+    S.X = B + P.ox[l]; S.Z = B + P.oz[l]; S.W = B + P.ow[l]; S.tmp = B + P.ot[l];
+    S.xo = h.lv[l].d_vx_off; S.zo = h.lv[l].d_vz_off; S.k = k;
+    return S;
+  };
+  hipLaunchKernelGGL(k_zero, dim3(1024), dim3(NT), 0, h.stream, B, P.otop);
+  const Level& TL = h.tree.levels[D];
+  hipLaunchKernelGGL(k_perm_in, dim3(TL.n), dim3(NT), 0, h.stream, d_rhs, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
+                     sv(D));
+  for (int l = D; l >= 2; --l) {
+    const DevLevel& L = h.lv[l];
+    SolveView S = sv(l);
+    const STask* st_w = L.d_st;
+    const STask* st_u = L.d_st + L.st_w.size();
+    for (size_t c = 0; c + 1 < L.col_ptr.size(); ++c) {
+      const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
+      if (b <= a) continue;
+      double by_w = 0, by_u = 0;
+      if (h.prof)
+        for (int e = a; e < b; ++e) {
+          const ElimRec& R = L.recs[e];
+          by_w += 8.0 * ((double)R.d * R.n + k * (2.0 * R.n + R.r));
+          by_u += 8.0 * ((double)R.M * R.n + k * (R.n + 2.0 * R.M));
+        }
+      const int tw0 = L.stw_ptr[c], tw1 = L.stw_ptr[c + 1], tu0 = L.stu_ptr[c], tu1 = L.stu_ptr[c + 1];
+      {
+        ProfScope ps(h, "k_solve_fwd_w", 0, by_w);
+        if (tw1 > tw0)
+          launch_solve(k_solve_fwd_w<1>, k_solve_fwd_w<4>, k_solve_fwd_w<8>, k, tw1 - tw0, h.stream, L.d_recs,
+                       st_w + tw0, tw1 - tw0, S);
+      }
+      {
+        ProfScope ps(h, "k_solve_fwd_upd", 0, by_u);
+        if (tu1 > tu0)
+          launch_solve(k_solve_fwd_upd<1>, k_solve_fwd_upd<4>, k_solve_fwd_upd<8>, k, tu1 - tu0, h.stream, L.d_recs,
+                       L.d_nbrs, st_u + tu0, tu1 - tu0, S);
+      }
+    }
+    if (l > 2) {
+      const DevLevel& Pl = h.lv[l - 1];
+      hipLaunchKernelGGL(k_vec_up, dim3(Pl.nn), dim3(NT), 0, h.stream, S, sv(l - 1), Pl.d_child_ptr, Pl.d_child, L.d_r,
+                         Pl.d_n);
+    }
+  }
+  if (h.top_n > 0) {
+    const int n = h.top_n;
+    double* f = B + P.otop;
+    double* y = f + (int64_t)n * k;
+    hipLaunchKernelGGL(k_top_gather, dim3(h.lv[2].nn), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r,
+                       h.d_top_off, f, n);
+    hipLaunchKernelGGL(k_gemm_tiles, dim3((n + 63) / 64, (k + 63) / 64), dim3(NT), 0, h.stream, n, k, n, 1.0,
+                       h.d_top_inv, n, f, n, 0.0, y, n);
+    hipLaunchKernelGGL(k_top_scatter, dim3(h.lv[2].nn), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r,
+                       h.d_top_off, y, n);
+  }
+  for (int l = 2; l <= D; ++l) {
+    const DevLevel& L = h.lv[l];
+    SolveView S = sv(l);
+    if (l > 2) {
+      const DevLevel& Pl = h.lv[l - 1];
+      hipLaunchKernelGGL(k_vec_down, dim3(Pl.nn), dim3(NT), 0, h.stream, S, sv(l - 1), Pl.d_child_ptr, Pl.d_child,
+                         L.d_r, Pl.d_n);
+    }
+    const STask* st_b = L.d_st + L.st_w.size() + L.st_u.size();
+    for (int c = (int)L.col_ptr.size() - 2; c >= 0; --c) {
+      const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
+      if (b <= a) continue;
+      double by = 0;
+      if (h.prof)
+        for (int e = a; e < b; ++e) {
+          const ElimRec& R = L.recs[e];
+          by += 8.0 * ((double)R.n * R.M + (double)R.n * R.r + k * (2.0 * R.n + R.M + R.r));
+        }
+      const int tb0 = L.stb_ptr[c], tb1 = L.stb_ptr[c + 1];
+      ProfScope ps(h, "k_solve_bwd", 0, by);
+      if (tb1 > tb0)
+        launch_solve(k_solve_bwd<1>, k_solve_bwd<4>, k_solve_bwd<8>, k, tb1 - tb0, h.stream, L.d_recs, L.d_nbrs,
+                     st_b + tb0, tb1 - tb0, S);
+    }
+  }
+  hipLaunchKernelGGL(k_perm_out, dim3(TL.n), dim3(NT), 0, h.stream, d_x, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
+                     sv(D));
+}
+
 int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_device, std::string& err) {
   if (!h.factored) {
     err = "ifmm_solve called before ifmm_factor";
     return -6;
   }
   HIPCHK(hipSetDevice(h.device));
-  const int D = h.tree.depth;
   const double t0 = now_s();
-  // vector storage: per level X, Z, W, tmp
-  std::vector<int64_t> ox(D + 1), oz(D + 1), ow(D + 1), ot(D + 1);
-  int64_t tot = 0;
-  for (int l = 2; l <= D; ++l) {
-    const DevLevel& L = h.lv[l];
-    ox[l] = tot; tot += L.vx_total * k + 32;
-    oz[l] = tot; tot += L.vz_total * k + 32;
-    ow[l] = tot; tot += L.wv_total * k + 32;
-    ot[l] = tot; tot += L.wv_total * k + 32;
-  }
-  const int64_t otop = tot;
-  tot += 2 * (int64_t)std::max(h.top_n, 1) * k + 32;
-  const int64_t oio = tot;
-  tot += 2 * ld * k + 32;  // staging of host vectors (used when on_device == 0)
+  const SolvePlan P = solve_plan(h, k, ld, true);
   int rc;
   double* before = h.svec;
-  if ((rc = ensure(h, (void**)&h.svec, &h.svec_bytes, tot * 8, err))) return rc;
+  if ((rc = ensure(h, (void**)&h.svec, &h.svec_bytes, P.total * 8, err))) return rc;
   if (h.svec != before) release_graph(h);  // the captured graph refers to the old buffer
   double* B = h.svec;
   const double* d_rhs = rhs;
   double* d_x = x;
   if (!on_device) {
-    double* io = B + oio;
+    double* io = B + P.oio;
     H2D(h, io, rhs, (size_t)ld * k * 8);
     d_rhs = io;
     d_x = io + ld * k;
   }
-  auto sv = [&](int l) {
-    SolveView S;
-    S.X = B + ox[l]; S.Z = B + oz[l]; S.W = B + ow[l]; S.tmp = B + ot[l];
-    S.xo = h.lv[l].d_vx_off; S.zo = h.lv[l].d_vz_off; S.k = k;
-    return S;
-  };
-  // the substitution as one stream of launches (captured once per (k, ld, rhs, x) into a HIP graph)
-  auto enqueue = [&]() {
-    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(NT), 0, h.stream, B, otop);
-    const Level& TL = h.tree.levels[D];
-    hipLaunchKernelGGL(k_perm_in, dim3(TL.n), dim3(NT), 0, h.stream, d_rhs, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
-                       sv(D));
-    for (int l = D; l >= 2; --l) {
-      const DevLevel& L = h.lv[l];
-      SolveView S = sv(l);
-      for (size_t c = 0; c + 1 < L.col_ptr.size(); ++c) {
-        const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
-        if (b > a) {
-          double by = 0;
-          if (h.prof)
-            for (int e = a; e < b; ++e) {
-              const ElimRec& R = L.recs[e];
-              by += 8.0 * ((double)R.d * R.d + (double)R.M * R.n + k * (2.0 * R.n + 2.0 * R.M + 2.0 * R.d));
-            }
-          ProfScope ps(h, "k_fwd", 0, by);
-          hipLaunchKernelGGL(k_fwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S, L.d_r);
-          const ColourInv& ci = L.cinv[c];
-          if (ci.count) {
-            hipLaunchKernelGGL(k_fwd_inv_w, dim3((unsigned)((ci.dmax + 63) / 64), b - a), dim3(NT), 0, h.stream,
-                               L.d_recs + a, S);
-            hipLaunchKernelGGL(k_fwd_inv_upd, dim3((unsigned)((ci.Mmax + 63) / 64 + 1), b - a), dim3(NT), 0, h.stream,
-                               L.d_recs + a, L.d_nbrs, S);
-          }
-        }
-      }
-      if (l > 2) {
-        const DevLevel& P = h.lv[l - 1];
-        hipLaunchKernelGGL(k_vec_up, dim3(P.nn), dim3(NT), 0, h.stream, S, sv(l - 1), P.d_child_ptr, P.d_child, L.d_r,
-                           P.d_n);
-      }
-    }
-    if (h.top_n > 0) {
-      const int n = h.top_n;
-      double* f = B + otop;
-      double* y = f + (int64_t)n * k;
-      hipLaunchKernelGGL(k_top_gather, dim3(h.lv[2].nn), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r,
-                         h.d_top_off, f, n);
-      hipLaunchKernelGGL(k_gemm_tiles, dim3((n + 63) / 64, (k + 63) / 64), dim3(NT), 0, h.stream, n, k, n, 1.0,
-                         h.d_top_inv, n, f, n, 0.0, y, n);
-      hipLaunchKernelGGL(k_top_scatter, dim3(h.lv[2].nn), dim3(NT), 0, h.stream, sv(2), h.lv[2].nn, h.lv[2].d_r,
-                         h.d_top_off, y, n);
-    }
-    for (int l = 2; l <= D; ++l) {
-      const DevLevel& L = h.lv[l];
-      SolveView S = sv(l);
-      if (l > 2) {
-        const DevLevel& P = h.lv[l - 1];
-        hipLaunchKernelGGL(k_vec_down, dim3(P.nn), dim3(NT), 0, h.stream, S, sv(l - 1), P.d_child_ptr, P.d_child, L.d_r,
-                           P.d_n);
-      }
-      for (int c = (int)L.col_ptr.size() - 2; c >= 0; --c) {
-        const int a = L.col_ptr[c], b = L.col_ptr[c + 1];
-        if (b > a) {
-          double by = 0;
-          if (h.prof)
-            for (int e = a; e < b; ++e) {
-              const ElimRec& R = L.recs[e];
-              by += 8.0 * ((double)R.d * R.d + (double)R.M * R.n + k * (2.0 * R.n + 2.0 * R.M + 3.0 * R.d));
-            }
-          ProfScope ps(h, "k_bwd", 0, by);
-          hipLaunchKernelGGL(k_bwd, dim3(b - a), dim3(NT), 0, h.stream, L.d_recs + a, L.d_nbrs, S);
-          const ColourInv& ci = L.cinv[c];
-          if (ci.count) {
-            hipLaunchKernelGGL(k_bwd_inv_t, dim3((unsigned)((ci.nmax + 63) / 64 + 1), b - a), dim3(NT), 0, h.stream,
-                               L.d_recs + a, L.d_nbrs, S);
-            hipLaunchKernelGGL(k_bwd_inv_x, dim3((unsigned)((ci.nmax + 63) / 64), b - a), dim3(NT), 0, h.stream,
-                               L.d_recs + a, S);
-          }
-        }
-      }
-    }
-    hipLaunchKernelGGL(k_perm_out, dim3(TL.n), dim3(NT), 0, h.stream, d_x, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
-                       sv(D));
-  };
+  if (const char* e = std::getenv("IFMM_GRAPH")) h.graph_solve = std::atoi(e) != 0;
   const bool use_graph = h.graph_solve;
   if (!use_graph) {
-    enqueue();
+    enqueue_solve(h, P, B, d_rhs, d_x, k, ld);
   } else {
     const bool hit = h.g_exec && h.g_key_k == k && h.g_key_ld == ld && h.g_key_rhs == d_rhs && h.g_key_x == d_x;
     if (!hit) {
@@ -2151,7 +2215,7 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
       h.prof = false;  // no timing events inside the graph
       hipError_t e = hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        enqueue();
+        enqueue_solve(h, P, B, d_rhs, d_x, k, ld);
         e = hipStreamEndCapture(h.stream, &h.g_graph);
       }
       h.stream = keep;
@@ -2331,6 +2395,37 @@ __global__ void __launch_bounds__(NT) k_internal_gemm(int m, int n, int k, doubl
 // host arrays (column-major, tight leading dimensions) with the FP64 (f32 = 0)
 // or FP32 matrix-core workgroup product (f32 = 1: the lite tile; f32 = 2: the
 // double-buffered tile from inner dimension 96 on), one workgroup per 64 x 64 tile.
+// Test hook (not declared in the public header): X = D^-1 B for `count`
+// matrices of order d with W right-hand columns through the blocked LU path.
+extern "C" int ifmm_internal_blocked_solve(const double* D, int count, int d, const double* B, int W, double* X,
+                                           int32_t* info) {
+  using namespace ifmm;
+  if (count < 1 || d < 1 || W < 1) return -1;
+  const int64_t dd = (int64_t)d * d, dw = (int64_t)d * W, nblk = (d + BLU_NB - 1) / BLU_NB;
+  double *dD = nullptr, *dX = nullptr, *dI = nullptr;
+  int32_t *dP = nullptr, *dInfo = nullptr;
+  BluTask* dT = nullptr;
+  if (hipMalloc((void**)&dD, count * dd * 8) != hipSuccess) return -3;
+  (void)hipMalloc((void**)&dX, count * dw * 8);
+  (void)hipMalloc((void**)&dI, count * nblk * 2 * 4096 * 8);
+  (void)hipMalloc((void**)&dP, count * (int64_t)d * 4);
+  (void)hipMalloc((void**)&dInfo, count * 4);
+  (void)hipMalloc((void**)&dT, count * sizeof(BluTask));
+  std::vector<BluTask> t(count);
+  for (int c = 0; c < count; ++c)
+    t[c] = {dD + c * dd, dX + c * dw, dP + (int64_t)c * d, dInfo + c, dI + c * nblk * 2 * 4096, d, W};
+  (void)hipMemcpy(dD, D, count * dd * 8, hipMemcpyHostToDevice);
+  (void)hipMemcpy(dX, B, count * dw * 8, hipMemcpyHostToDevice);
+  (void)hipMemset(dInfo, 0, count * 4);
+  (void)hipMemcpy(dT, t.data(), count * sizeof(BluTask), hipMemcpyHostToDevice);
+  enqueue_blocked_lu(dT, (unsigned)count, d, W, nullptr);
+  int rc = hipDeviceSynchronize() == hipSuccess ? 0 : -3;
+  (void)hipMemcpy(X, dX, count * dw * 8, hipMemcpyDeviceToHost);
+  (void)hipMemcpy(info, dInfo, count * 4, hipMemcpyDeviceToHost);
+  (void)hipFree(dD); (void)hipFree(dX); (void)hipFree(dI); (void)hipFree(dP); (void)hipFree(dInfo); (void)hipFree(dT);
+  return rc;
+}
+
 extern "C" int ifmm_internal_gemm(int m, int n, int k, double alpha, const double* A, int tA, const double* B, int tB,
                                   double beta, double* C, int f32) {
   using namespace ifmm;

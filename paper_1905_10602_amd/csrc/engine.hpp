@@ -32,6 +32,11 @@ struct ElimRec {
   int32_t far_base, pad1;  // far-pair index table: nnb * nnb entries from far_base
 };
 
+// One 64-row tile of a stored block in the solve.
+struct STask {
+  int32_t rec, r0;  // record (index in the level's elimination order), first row of the tile
+};
+
 struct ElimNbr {
   int32_t p;        // neighbour node
   int32_t elim;     // 1 if p was eliminated before i (its row is R_z_p, its column C_y_p)
@@ -104,6 +109,12 @@ struct DevLevel {
   std::vector<ElimNbr> nbrs;
   std::vector<int32_t> col_ptr;  // recs of colour c: [col_ptr[c], col_ptr[c + 1])
   std::vector<ColourInv> cinv;   // per colour: records solved with an explicit inverse
+  // solve: 64-row tiles of the pivot inverses (w), of L (upd) and of G (b),
+  // colour c's tiles at [st*_ptr[c], st*_ptr[c + 1]); on the device one table
+  // holding w, then upd, then b
+  std::vector<STask> st_w, st_u, st_b;
+  std::vector<int32_t> stw_ptr, stu_ptr, stb_ptr;
+  STask* d_st = nullptr;
   ElimRec* d_recs = nullptr;
   ElimNbr* d_nbrs = nullptr;
   int64_t wv_total = 0;
@@ -195,6 +206,8 @@ struct Handle {
   std::vector<float> model_host;  // parameters read from options.rank_model (uploaded by the first factor)
   int top_tau = 2;                // levels below tau: one node per step (matrix-parallel)
   int bottom_level = 0;           // requested depth: 0 from leaf_max, -1 cost model, >= 2 forced
+  int colouring = 0;              // 0 Alg. 3, 1 look-back greedy
+  std::vector<double> depth_costs;  // cost-model estimates of the candidate depths (bottom_level = -1)
   std::string tune_cache;         // autotuner cache file ("" = built-in tile choices)
   double* fbuf = nullptr;
   int64_t fbuf_bytes = 0;

@@ -702,7 +702,9 @@ __global__ void __launch_bounds__(NT) k_getrf(const ElimRec* recs, int32_t* info
   if (threadIdx.x == 0) info[blockIdx.x] = inf;
 }
 
-// X = D^-1 [[U, 0], [0, I]]  (d x (M + r)), XCOLS columns per workgroup.
+// X = D^-1 [[U, 0, I_n], [0, I_r, 0]]  (d x (M + r + n)), XCOLS columns per
+// workgroup: the Schur update takes the first M + r columns, the solve the
+// explicit inverse (the last r + n columns) and the x-rows of the first M.
 // Pivots of order <= DMAX keep their slice of X in LDS through the row
 // interchanges and both substitutions (2 d barrier steps, all on LDS); larger
 // ones solve in place in global memory.  DMAX sizes the LDS (occupancy).
@@ -716,7 +718,7 @@ __global__ void __launch_bounds__(NT) k_xsolve(const ElimRec* recs, const XTask*
   const XTask t = xt[blockIdx.x];
   const ElimRec R = recs[t.rec];
   const int n = R.n, d = R.d, M = R.M;
-  const int nc = min(XCOLS, M + R.r - t.c0);
+  const int nc = min(XCOLS, M + R.r + n - t.c0);
   if (d == 0 || nc <= 0) return;
   double* X = R.X + (int64_t)t.c0 * d;
   const bool lds = d <= DMAX;
@@ -725,7 +727,8 @@ __global__ void __launch_bounds__(NT) k_xsolve(const ElimRec* recs, const XTask*
     const int col = t.c0 + cl;
     double v;
     if (col < M) v = row < n ? R.U[row + (int64_t)col * n] : 0.0;
-    else v = (row >= n && row - n == col - M) ? 1.0 : 0.0;
+    else if (col < M + R.r) v = (row >= n && row - n == col - M) ? 1.0 : 0.0;
+    else v = (row == col - M - R.r) ? 1.0 : 0.0;
     B[row + cl * d] = v;
   }
   __syncthreads();
@@ -806,21 +809,6 @@ __global__ void __launch_bounds__(NT) k_blu_xinit(const BluTask* tasks, const El
     else if (col < M + r) v = (row >= n && row - n == col - M) ? 1.0 : 0.0;
     else v = (row == col - M - r) ? 1.0 : 0.0;  // [I_n; 0]: the x-columns of D^-1
     t.X[row + (int64_t)col * t.d] = v;
-  }
-}
-
-// After the solve, D^-1 = [X[:, M+r : M+r+n], X[:, M : M+r]] replaces the LU
-// factors (the solve of a large pivot multiplies by the explicit inverse).
-__global__ void __launch_bounds__(NT) k_blu_store_inv(const BluTask* tasks, const ElimRec* recs, const int32_t* rec_of) {
-  const BluTask t = tasks[blockIdx.y];
-  const ElimRec R = recs[rec_of[blockIdx.y]];
-  const int c0 = blockIdx.x * 64, d = t.d;
-  const int nc = min(64, d - c0);
-  if (nc <= 0) return;
-  WG_FOR2(d, nc, row, cl) {
-    const int c = c0 + cl;
-    const int src = c < R.n ? R.M + R.r + c : R.M + (c - R.n);
-    t.lu[row + (int64_t)c * d] = t.X[row + (int64_t)src * d];
   }
 }
 
@@ -1602,129 +1590,178 @@ __global__ void __launch_bounds__(NT) k_perm_out(double* x, int64_t ld, int k, c
   }
 }
 
-// Forward substitution of one elimination (Alg. 2, upward pass):
-//   w = D^-1 [x_i; 0];  rows of neighbour p -= L_p w_top;  z_i += w_bot.
-__global__ void __launch_bounds__(NT) k_fwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S, const int32_t* rnow) {
-  const ElimRec R = recs[blockIdx.x];
-  if (R.inv) return;  // explicit-inverse path
+// Substitution of the eliminations (Alg. 2) with the pivot inverses stored
+// explicitly: for node i with D^-1 = [[E_tt, E_tb], [E_bt, E_bb]] (blocks of
+// n and r rows / columns) and G = E_tt U (the x-rows of X = D^-1 [U; 0]),
+//   forward:  w = E_t. x_i (kept, n x k);  z_i += E_b. x_i;  rows of the
+//             neighbours -= L w
+//   backward: x_i = w - G x_nbrs + E_tb y_i
+// Every step is a GEMV over 64-row tiles of one stored block: one tile per
+// wave, lane = row, so each lane streams one row of the block with the
+// column loads of a wave coalesced (64 consecutive rows of a column-major
+// block), and the right-hand sides go through in chunks of SK columns whose
+// vector entries are broadcast from the lane that loaded them (readlane).
+
+__device__ inline double lane_bcast(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// acc[c] += sum_{j < cnt} A[j * lda] * x[j + c * ldx]   (c < kc), for the
+// lane's row (A points at the lane's row; act: the lane's row exists).
+template <int SK>
+__device__ inline void wave_gemv_acc(const double* A, int64_t lda, bool act, const double* x, int64_t ldx, int cnt,
+                                     int kc, int lane, double* acc) {
+  for (int j0 = 0; j0 < cnt; j0 += 64) {
+    const int m = min(64, cnt - j0);
+    double xv[SK];
+#pragma unroll
+    for (int c = 0; c < SK; ++c) xv[c] = (lane < m && c < kc) ? x[j0 + lane + (int64_t)c * ldx] : 0.0;
+    const double* Aj = A + (int64_t)j0 * lda;
+    if (m == 64) {
+#pragma unroll 16
+      for (int jj = 0; jj < 64; ++jj) {
+        const double a = act ? Aj[(int64_t)jj * lda] : 0.0;
+#pragma unroll
+        for (int c = 0; c < SK; ++c) acc[c] = fma(a, lane_bcast(xv[c], jj), acc[c]);
+      }
+    } else {
+      for (int jj = 0; jj < m; ++jj) {
+        const double a = act ? Aj[(int64_t)jj * lda] : 0.0;
+#pragma unroll
+        for (int c = 0; c < SK; ++c) acc[c] = fma(a, lane_bcast(xv[c], jj), acc[c]);
+      }
+    }
+  }
+}
+
+// forward, step 1: w = E_t. x_i (rows < n kept in W), z_i += E_b. x_i
+template <int SK>
+__global__ void __launch_bounds__(NT) k_solve_fwd_w(const ElimRec* recs, const STask* tasks, int ntask, SolveView S) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (t >= ntask) return;
+  const STask T = tasks[t];
+  const ElimRec R = recs[T.rec];
   const int n = R.n, r = R.r, d = R.d, k = S.k;
-  double* w = S.W + R.wv * k;
+  const int row = T.r0 + lane;
+  const bool act = row < d;
   const double* xi = S.X + S.xo[R.node] * k;
-  if (d > 0) WG_FOR2(d, k, a, c) {
-    w[a + (int64_t)c * d] = a < n ? xi[a + (int64_t)c * n] : 0.0;
-  }
-  __syncthreads();
-  if (d == 0) return;
-  wg_getrs(d, R.lu, d, R.piv, w, d, k);
-  for (int e = 0; e < R.nnb; ++e) {
-    const ElimNbr B = nbrs[R.nb_begin + e];
-    double* tgt = B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k;
-    if (B.m > 0 && n > 0) wg_gemm(B.m, k, n, -1.0, R.L + B.off, R.M, false, w, d, false, 1.0, tgt, B.m);
-  }
+  double* wt = S.W + R.wv * k;
   double* zi = S.Z + S.zo[R.node] * k;
-  if (r > 0) WG_FOR2(r, k, a, c) {
-    zi[a + (int64_t)c * r] += w[n + a + (int64_t)c * d];
+  for (int c0 = 0; c0 < k; c0 += SK) {
+    const int kc = min(SK, k - c0);
+    double acc[SK];
+#pragma unroll
+    for (int c = 0; c < SK; ++c) acc[c] = 0.0;
+    wave_gemv_acc<SK>(R.lu + (act ? row : 0), d, act, xi + (int64_t)c0 * n, n, n, kc, lane, acc);
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < SK; ++c)
+        if (c < kc) {
+          if (row < n) wt[row + (int64_t)(c0 + c) * n] = acc[c];
+          else zi[row - n + (int64_t)(c0 + c) * r] += acc[c];
+        }
+    }
   }
-  (void)rnow;
 }
 
-// Backward substitution of one elimination (Alg. 2, downward pass):
-//   [x_i; z_i] = w - D^-1 [sum_q U_q x_q; -y_i]
-__global__ void __launch_bounds__(NT) k_bwd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
-  const ElimRec R = recs[blockIdx.x];
-  if (R.inv) return;  // explicit-inverse path
+// forward, step 2: rows of the neighbours -= L w (the rows of a tile may
+// belong to several neighbours; same-colour nodes share no neighbour)
+template <int SK>
+__global__ void __launch_bounds__(NT) k_solve_fwd_upd(const ElimRec* recs, const ElimNbr* nbrs, const STask* tasks,
+                                                      int ntask, SolveView S) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (t >= ntask) return;
+  const STask T = tasks[t];
+  const ElimRec R = recs[T.rec];
+  const int n = R.n, k = S.k;
+  const int row = T.r0 + lane;
+  const bool act = row < R.M;
+  double* tgt = nullptr;
+  int ldt = 1;
+  if (act)
+    for (int e = 0; e < R.nnb; ++e) {
+      const ElimNbr B = nbrs[R.nb_begin + e];
+      if (row >= B.off && row < B.off + B.m) {
+        tgt = (B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k) + (row - B.off);
+        ldt = B.m;
+      }
+    }
+  const double* wt = S.W + R.wv * k;
+  for (int c0 = 0; c0 < k; c0 += SK) {
+    const int kc = min(SK, k - c0);
+    double acc[SK];
+#pragma unroll
+    for (int c = 0; c < SK; ++c) acc[c] = 0.0;
+    wave_gemv_acc<SK>(R.L + (act ? row : 0), R.M, act, wt + (int64_t)c0 * n, n, n, kc, lane, acc);
+    if (tgt) {
+#pragma unroll
+      for (int c = 0; c < SK; ++c)
+        if (c < kc) tgt[(int64_t)(c0 + c) * ldt] -= acc[c];
+    }
+  }
+}
+
+// backward: x_i = w - G x_nbrs + E_tb y_i
+template <int SK>
+__global__ void __launch_bounds__(NT) k_solve_bwd(const ElimRec* recs, const ElimNbr* nbrs, const STask* tasks,
+                                                  int ntask, SolveView S) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (t >= ntask) return;
+  const STask T = tasks[t];
+  const ElimRec R = recs[T.rec];
   const int n = R.n, r = R.r, d = R.d, k = S.k;
-  if (d == 0) return;
-  double* t = S.tmp + R.wv * k;
-  const double* w = S.W + R.wv * k;
+  const int row = T.r0 + lane;
+  const bool act = row < n;
+  const double* wt = S.W + R.wv * k;
   const double* yi = S.Z + S.zo[R.node] * k;
-  if (d > 0) WG_FOR2(d, k, a, c) {
-    t[a + (int64_t)c * d] = a < n ? 0.0 : -yi[(a - n) + (int64_t)c * r];
-  }
-  __syncthreads();
-  for (int e = 0; e < R.nnb; ++e) {
-    const ElimNbr B = nbrs[R.nb_begin + e];
-    const double* xq = B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k;
-    if (B.m > 0 && n > 0) wg_gemm(n, k, B.m, 1.0, R.U + (int64_t)B.off * n, n, false, xq, B.m, false, 1.0, t, d);
-  }
-  wg_getrs(d, R.lu, d, R.piv, t, d, k);
   double* xi = S.X + S.xo[R.node] * k;
-  if (n > 0) WG_FOR2(n, k, a, c) {
-    xi[a + (int64_t)c * n] = w[a + (int64_t)c * d] - t[a + (int64_t)c * d];
+  for (int c0 = 0; c0 < k; c0 += SK) {
+    const int kc = min(SK, k - c0);
+    double g[SK], e[SK];
+#pragma unroll
+    for (int c = 0; c < SK; ++c) { g[c] = 0.0; e[c] = 0.0; }
+    for (int q = 0; q < R.nnb; ++q) {
+      const ElimNbr B = nbrs[R.nb_begin + q];
+      if (B.m == 0) continue;
+      const double* xq = (B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k) + (int64_t)c0 * B.m;
+      wave_gemv_acc<SK>(R.U + (act ? row : 0) + (int64_t)B.off * n, n, act, xq, B.m, B.m, kc, lane, g);
+    }
+    wave_gemv_acc<SK>(R.lu + (act ? row : 0) + (int64_t)n * d, d, act, yi + (int64_t)c0 * r, r, r, kc, lane, e);
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < SK; ++c)
+        if (c < kc) xi[row + (int64_t)(c0 + c) * n] = wt[row + (int64_t)(c0 + c) * n] - g[c] + e[c];
+    }
   }
 }
 
-// Large pivots with an explicit inverse: the substitution steps of one node
-// spread over many workgroups (64-row tiles), grid (tiles, records of the colour).
-//   forward:  w = D^-1[:, 0:n] x_i;  rows of neighbour p -= L_p w_top;  z_i += w_bot
-//   backward: t = [sum_q U_q x_q; -y_i];  x_i = w_top - D^-1[0:n, :] t
-__global__ void __launch_bounds__(NT) k_fwd_inv_w(const ElimRec* recs, SolveView S) {
+// After the pivot solves of a colour: D^-1 = [X[:, M+r : M+r+n], X[:, M : M+r]]
+// replaces the LU factors and G = X[0:n, 0:M] the U-blocks (what the solve
+// reads).  Grid (64-column chunks of max(d, M), records).
+__global__ void __launch_bounds__(NT) k_store_solve(const ElimRec* recs) {
   const ElimRec R = recs[blockIdx.y];
-  if (!R.inv) return;
-  const int r0 = blockIdx.x * 64, k = S.k;
-  if (r0 >= R.d || R.n == 0) return;
-  double* w = S.W + R.wv * k;
-  const double* xi = S.X + S.xo[R.node] * k;
-  wg_gemm(min(64, R.d - r0), k, R.n, 1.0, R.lu + r0, R.d, false, xi, R.n, false, 0.0, w + r0, R.d);
-}
-
-__global__ void __launch_bounds__(NT) k_fwd_inv_upd(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
-  const ElimRec R = recs[blockIdx.y];
-  if (!R.inv) return;
-  const int k = S.k, n = R.n, d = R.d;
-  const int ntile = (R.M + 63) / 64;
-  const double* w = S.W + R.wv * k;
-  if ((int)blockIdx.x == ntile) {  // z_i += w_bot
-    double* zi = S.Z + S.zo[R.node] * k;
-    if (R.r > 0) WG_FOR2(R.r, k, a, c) { zi[a + (int64_t)c * R.r] += w[n + a + (int64_t)c * d]; }
-    return;
+  const int c0 = blockIdx.x * 64, d = R.d, n = R.n, M = R.M;
+  const int nc = min(64, d - c0);
+  if (nc > 0) {
+    WG_FOR2(d, nc, row, cl) {
+      const int c = c0 + cl;
+      const int src = c < n ? M + R.r + c : M + (c - n);
+      R.lu[row + (int64_t)c * d] = R.X[row + (int64_t)src * d];
+    }
   }
-  if ((int)blockIdx.x > ntile || n == 0) return;
-  const int t0 = blockIdx.x * 64, t1 = min(R.M, t0 + 64);
-  for (int e = 0; e < R.nnb; ++e) {
-    const ElimNbr B = nbrs[R.nb_begin + e];
-    const int a = max(t0, B.off), b = min(t1, B.off + B.m);
-    if (a >= b) continue;
-    double* tgt = B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k;
-    wg_gemm(b - a, k, n, -1.0, R.L + a, R.M, false, w, d, false, 1.0, tgt + (a - B.off), B.m);
+  const int mc = min(64, M - c0);
+  if (mc > 0 && n > 0) {
+    WG_FOR2(n, mc, row, cl) {
+      const int c = c0 + cl;
+      R.U[row + (int64_t)c * n] = R.X[row + (int64_t)c * d];
+    }
   }
-}
-
-__global__ void __launch_bounds__(NT) k_bwd_inv_t(const ElimRec* recs, const ElimNbr* nbrs, SolveView S) {
-  const ElimRec R = recs[blockIdx.y];
-  if (!R.inv) return;
-  const int k = S.k, n = R.n, d = R.d;
-  const int ntile = (n + 63) / 64;
-  double* t = S.tmp + R.wv * k;
-  if ((int)blockIdx.x == ntile) {  // t_bot = -y_i
-    const double* yi = S.Z + S.zo[R.node] * k;
-    if (R.r > 0) WG_FOR2(R.r, k, a, c) { t[n + a + (int64_t)c * d] = -yi[a + (int64_t)c * R.r]; }
-    return;
-  }
-  if ((int)blockIdx.x > ntile) return;
-  const int r0 = blockIdx.x * 64, mr = min(64, n - r0);
-  wg_fill(mr, k, t + r0, d, 0.0);
-  for (int e = 0; e < R.nnb; ++e) {
-    const ElimNbr B = nbrs[R.nb_begin + e];
-    if (B.m == 0) continue;
-    const double* xq = B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k;
-    wg_gemm(mr, k, B.m, 1.0, R.U + r0 + (int64_t)B.off * n, n, false, xq, B.m, false, 1.0, t + r0, d);
-  }
-}
-
-__global__ void __launch_bounds__(NT) k_bwd_inv_x(const ElimRec* recs, SolveView S) {
-  const ElimRec R = recs[blockIdx.y];
-  if (!R.inv) return;
-  const int k = S.k, n = R.n, d = R.d;
-  const int r0 = blockIdx.x * 64;
-  if (r0 >= n) return;
-  const int mr = min(64, n - r0);
-  const double* w = S.W + R.wv * k;
-  const double* t = S.tmp + R.wv * k;
-  double* xi = S.X + S.xo[R.node] * k;
-  WG_FOR2(mr, k, a, c) { xi[r0 + a + (int64_t)c * n] = w[r0 + a + (int64_t)c * d]; }
-  __syncthreads();
-  wg_gemm(mr, k, d, -1.0, R.lu + r0, d, false, t, d, false, 1.0, xi + r0, n);
 }
 
 // Level change of the node vectors: x_P = [z_c ...] (up) / y_c = slices of x_P (down).

@@ -83,6 +83,82 @@ int32_t colour_grid(const std::vector<uint8_t>& occ, int m, int sigma, std::vect
   return g;
 }
 
+// Greedy colouring that looks back at the boxes already coloured: each colour
+// walks the uncoloured nodes in scan order (node order) and takes every node
+// at distance >= sigma from all nodes it already holds.  A placed node blocks
+// the (2 sigma - 1)^3 boxes around it for the current colour (a stamp grid),
+// so the test is one lookup per candidate.
+int32_t colour_lookback(const Level& lv, int m, int sigma, std::vector<int32_t>& colour) {
+  const int64_t M = m;
+  colour.assign((size_t)lv.n, -1);
+  std::vector<int32_t> stamp((size_t)(M * M * M), 0);
+  int32_t g = 0, left = lv.n;
+  while (left > 0) {
+    for (int32_t i = 0; i < lv.n; ++i) {
+      if (colour[i] >= 0) continue;
+      const int x = lv.coord[3 * i], y = lv.coord[3 * i + 1], z = lv.coord[3 * i + 2];
+      if (stamp[(size_t)lex(x, y, z, M)] == g + 1) continue;
+      colour[i] = g;
+      --left;
+      for (int k = std::max(0, z - sigma + 1); k <= std::min(m - 1, z + sigma - 1); ++k)
+        for (int j = std::max(0, y - sigma + 1); j <= std::min(m - 1, y + sigma - 1); ++j)
+          for (int q = std::max(0, x - sigma + 1); q <= std::min(m - 1, x + sigma - 1); ++q)
+            stamp[(size_t)lex(q, j, k, M)] = g + 1;
+    }
+    ++g;
+  }
+  return g;
+}
+
+// Cost model of the bottom level (Sec. 5.2: the leaf-level cost grows with
+// the number of leaf nodes times the cube of their block sizes, so removing
+// fine levels pays until the leaves get too large).  Candidate depths
+// l = depth, depth - 1, depth - 2 (>= 2) of this tree: on level l the node
+// size is its point count, above it the sum of the children's ranks, each
+// rank estimated as min(size, K).  A node of size n, rank r and neighbour
+// rows M costs (2/3)(n + r)^3 (pivot LU) + 2 n M (M + r) (Schur update).
+int Tree::cost_depth(int K, std::vector<double>* costs) const {
+  std::vector<std::vector<double>> pts_in((size_t)depth + 1);
+  pts_in[depth].resize((size_t)levels[depth].n);
+  for (int32_t i = 0; i < levels[depth].n; ++i)
+    pts_in[depth][i] = (double)(levels[depth].pt_end[i] - levels[depth].pt_begin[i]);
+  for (int l = depth - 1; l >= 2; --l) {
+    const Level& L = levels[l];
+    pts_in[l].assign((size_t)L.n, 0.0);
+    for (int32_t i = 0; i < L.n; ++i)
+      for (int e = L.child_ptr[i]; e < L.child_ptr[i + 1]; ++e) pts_in[l][i] += pts_in[l + 1][L.child[e]];
+  }
+  int best = depth;
+  double best_cost = -1.0;
+  if (costs) costs->clear();
+  for (int cand = depth; cand >= std::max(2, depth - 2); --cand) {
+    std::vector<double> nsz = pts_in[cand];
+    double total = 0.0;
+    for (int l = cand; l >= 2; --l) {
+      const Level& L = levels[l];
+      if (l < cand) {  // sizes from the children's estimated ranks
+        const std::vector<double>& fine = nsz;
+        std::vector<double> up((size_t)L.n, 0.0);
+        for (int32_t i = 0; i < L.n; ++i)
+          for (int e = L.child_ptr[i]; e < L.child_ptr[i + 1]; ++e) up[i] += std::min(fine[L.child[e]], (double)K);
+        nsz.swap(up);
+      }
+      for (int32_t i = 0; i < L.n; ++i) {
+        const double nv = nsz[i], rv = std::min(nv, (double)K);
+        double Mv = 0.0;
+        for (int e = L.nbr_ptr[i]; e < L.nbr_ptr[i + 1]; ++e) Mv += nsz[L.nbr[e]];
+        total += 2.0 / 3.0 * (nv + rv) * (nv + rv) * (nv + rv) + 2.0 * nv * Mv * (Mv + rv);
+      }
+    }
+    if (costs) costs->push_back(total);
+    if (best_cost < 0.0 || total < best_cost) {
+      best_cost = total;
+      best = cand;
+    }
+  }
+  return best;
+}
+
 std::string Tree::coincident(const double* pts) const {
   const Level& L = levels[depth];
   std::vector<int64_t> idx;
@@ -127,7 +203,7 @@ static void point_keys(const double* pts, int64_t n, const double lo[3], double 
     }
 }
 
-std::string Tree::build(const double* pts, int64_t n, int leaf_max, int sig, int depth_req, int tau) {
+std::string Tree::build(const double* pts, int64_t n, int leaf_max, int sig, int depth_req, int tau, int colouring) {
   if (n < 1) return "need at least one point";
   if (leaf_max < 1) return "leaf_max must be positive";
   sigma = sig;
@@ -277,6 +353,12 @@ std::string Tree::build(const double* pts, int64_t n, int leaf_max, int sig, int
       for (size_t e = 0; e < occ.size(); ++e)
         if (occ[e]) grid[e] = g++;
       lv.ncolour = g;
+    } else if (colouring == 1) {
+      std::vector<int32_t> col;
+      lv.ncolour = colour_lookback(lv, (int)m, sigma, col);
+      grid.assign(occ.size(), -1);
+      for (int32_t i = 0; i < lv.n; ++i)
+        grid[(size_t)lex(lv.coord[3 * i], lv.coord[3 * i + 1], lv.coord[3 * i + 2], m)] = col[i];
     } else {
       lv.ncolour = colour_grid(occ, (int)m, sigma, grid);
     }

@@ -40,18 +40,25 @@ struct Tree {
   // depth_req: 0 = smallest level >= 2 with at most leaf_max points per leaf,
   // >= 2 = that level.  Levels below tau get one node per colour (scan order):
   // they are eliminated one node at a time (the matrix-parallel levels of
-  // Sec. 4.2); tau = 2 colours every level with Alg. 3.
-  std::string build(const double* pts, int64_t n, int leaf_max, int sigma, int depth_req = 0, int tau = 2);
+  // Sec. 4.2); the others are coloured by Alg. 3 (colouring = 0) or by the
+  // look-back greedy (colouring = 1).
+  std::string build(const double* pts, int64_t n, int leaf_max, int sigma, int depth_req = 0, int tau = 2,
+                    int colouring = 0);
   // Box centre and half-side of node i at level l.
   void box(int l, int32_t i, double c[3], double* half) const;
   // After build(): an empty string if no two points coincide, else a message
   // naming one coincident pair by original index (the kernel is undefined at
   // r = 0).  Coincident points share a leaf, so each leaf is checked alone.
   std::string coincident(const double* pts) const;
+  // The depth among depth, depth - 1, depth - 2 with the smallest estimated
+  // factorisation cost (costs, if given, receives the estimates in that order).
+  int cost_depth(int K, std::vector<double>* costs = nullptr) const;
 };
 
 // Alg. 3 on an m x m x m occupancy grid indexed [k][j][i]; returns the number
 // of colours, colour[] = -1 for empty cells.
 int32_t colour_grid(const std::vector<uint8_t>& occ, int m, int sigma, std::vector<int32_t>& colour);
+// Look-back greedy colouring of the nodes of one level (colour per node).
+int32_t colour_lookback(const Level& lv, int m, int sigma, std::vector<int32_t>& colour);
 
 }  // namespace ifmm

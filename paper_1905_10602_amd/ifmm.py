@@ -33,7 +33,7 @@ class Options(C.Structure):
     _fields_ = [("leaf_max", C.c_int32), ("cheb_order", C.c_int32), ("precision", C.c_int32),
                 ("top_tau", C.c_int32), ("rank_model", C.c_char_p), ("tune_cache", C.c_char_p),
                 ("max_device_bytes", C.c_int64), ("deterministic", C.c_int32), ("bottom_level", C.c_int32),
-                ("rank_cap", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p)]
+                ("rank_cap", C.c_int32), ("colouring", C.c_int32), ("stream", C.c_void_p)]
 
 
 def library_path() -> str:
@@ -106,7 +106,7 @@ class IFMM:
 
     def __init__(self, points, eps, sigma, diag=None, weights=None, leaf_max=64, cheb_order=4, rank_cap=0,
                  max_device_bytes=0, stream=None, precision="fp64", top_tau=2, bottom_level=0, rank_model=None,
-                 tune_cache=None):
+                 tune_cache=None, colouring="stride"):
         lib = load_library()
         pts = np.ascontiguousarray(points, dtype=np.float64)
         if pts.ndim != 2 or pts.shape[1] != 3:
@@ -129,6 +129,7 @@ class IFMM:
         opt.max_device_bytes = max_device_bytes
         opt.top_tau = top_tau
         opt.bottom_level = bottom_level
+        opt.colouring = {"stride": 0, "lookback": 1}[colouring]
         opt.rank_model = None if rank_model is None else os.fsencode(rank_model)
         opt.tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
         opt.stream = None if stream is None else C.c_void_p(stream)

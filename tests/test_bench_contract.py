@@ -39,7 +39,7 @@ def test_roofline_picks_the_largest_single_kernel_and_prices_it():
     rf64 = bench.roofline_of(st, mixed=False)
     assert rf64["bound"] == "alu" and rf64["frac"] == pytest.approx(ach / bench.FP64_VECTOR_PEAK)
     # a memory-bound kernel is priced in bytes against HBM
-    rfh = bench.roofline_of(_stats({"k_fwd": (10.0, 10, 0.0, 8.0e10)}), mixed=True)
+    rfh = bench.roofline_of(_stats({"k_solve_fwd_upd": (10.0, 10, 0.0, 8.0e10)}), mixed=True)
     assert rfh["bound"] == "hbm" and rfh["frac"] == pytest.approx(8.0e9 / 1e-3 / bench.HBM_PEAK)
 
 

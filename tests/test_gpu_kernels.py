@@ -44,11 +44,14 @@ def _mats(n, seed):
     return [0.5 * (m + m.T) for m in out]
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 7, 40, 131, 300])
-@pytest.mark.parametrize("jacobi", [0, 1])
-def test_syev_matches_numpy(n, jacobi):
+@pytest.mark.parametrize("n,jacobi,k", [(n, j, 24) for n in (1, 2, 3, 7, 40, 131, 300) for j in (0, 1)] +
+                         [(513, 0, 24), (1024, 0, 24), (1190, 0, 300), (2048, 0, 64)])
+def test_syev_matches_numpy(n, jacobi, k):
+    # orders up to the largest the solver takes (2048); the factorisation of
+    # the N = 1M ellipsoid decomposes Gram matrices up to order ~1190
+    print(f"case syev n={n} jacobi={jacobi} k={k}", flush=True)
     mats = _mats(n, n)
-    k = max(1, min(n, 24))
+    k = max(1, min(n, k))
     lam, V = _syev(mats, k, jacobi)
     for G, l, X in zip(mats, lam, V):
         ref = np.linalg.eigvalsh(G)[::-1]
@@ -130,3 +133,46 @@ def test_workgroup_gemm_fp64_and_fp32_matrix_cores(m, n, k, tA, tB, f32):
             assert not np.allclose(Cf, ref, rtol=0, atol=1e-12)  # really FP32
     else:
         assert np.allclose(Cf, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+def _blocked_solve(D, B):
+    lib = C.CDLL(os.path.join(ROOT, "paper_1905_10602_amd", "libifmm.so"))
+    f = lib.ifmm_internal_blocked_solve
+    f.restype = C.c_int
+    f.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+    cnt, d, W = len(D), D[0].shape[0], B[0].shape[1]
+    Dd = np.ascontiguousarray(np.stack([m.ravel(order="F") for m in D]))
+    Bd = np.ascontiguousarray(np.stack([m.ravel(order="F") for m in B]))
+    X = np.zeros_like(Bd)
+    info = np.zeros(cnt, dtype=np.int32)
+    assert f(Dd.ctypes.data, cnt, d, Bd.ctypes.data, W, X.ctypes.data, info.ctypes.data) == 0
+    return [X[c].reshape((d, W), order="F") for c in range(cnt)], info
+
+
+@pytest.mark.parametrize("d,W", [(63, 40), (64, 64), (65, 129), (700, 300), (1500, 700), (1537, 257)])
+def test_blocked_pivot_solve_matches_numpy(d, W):
+    # the multi-workgroup LU of the augmented system that large pivots take,
+    # up to orders beyond the largest of the N = 1M ellipsoid (~1,480): a
+    # dense matrix and a saddle-point matrix [[P, B^T], [B, 0]] like the
+    # pivots of the extended system (its zero block needs the row pivoting)
+    print(f"case blocked solve d={d} W={W}", flush=True)
+    rng = np.random.default_rng(d + W)
+    dense = rng.standard_normal((d, d)) + 4.0 * np.sqrt(d) * np.eye(d)
+    r = d // 3
+    n = d - r
+    P = rng.standard_normal((n, n))
+    P = P @ P.T / n + np.eye(n)
+    Bm = rng.standard_normal((r, n))
+    saddle = np.zeros((d, d))
+    saddle[:n, :n] = P
+    saddle[:n, n:] = Bm.T
+    saddle[n:, :n] = Bm
+    Ds = [np.asfortranarray(dense), np.asfortranarray(saddle)]
+    Bs = [np.asfortranarray(rng.standard_normal((d, W))) for _ in Ds]
+    Xs, info = _blocked_solve(Ds, Bs)
+    assert np.all(info == 0)
+    for D, B, X in zip(Ds, Bs, Xs):
+        ref = np.linalg.solve(D, B)
+        res = np.linalg.norm(D @ X - B) / (np.linalg.norm(D) * np.linalg.norm(X))
+        assert res <= 1e-14 * d, res
+        assert np.linalg.norm(X - ref) / np.linalg.norm(ref) <= 1e-13 * np.linalg.cond(D)

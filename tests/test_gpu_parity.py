@@ -157,9 +157,8 @@ def test_blocked_pivot_path_matches_oracle(monkeypatch):
                                                     ("sphere", 1500, 24, 3, 1e-4)])
 def test_mixed_precision_error_vs_oracle(shape, N, leaf, sigma, eps):
     # FP32 matrix cores for the Schur and basis-change products: the solution
-    # stays within 100 eps of the FP64 oracle (FP32 rounding, 6e-8, enters the
-    # updated blocks at about the level of the truncation itself) and its
-    # backward error on A~ within 100 eps
+    # stays within 10 eps of the FP64 oracle (the FP32 rounding of an operand,
+    # 6e-8 relative, is 0.06 eps at eps = 1e-6, well inside the truncation)
     print(f"case mixed {shape} N={N} eps={eps}", flush=True)
     pts, dg = _case(shape, N, 1)
     b = synth.uniform_rhs(N, 2, 101)
@@ -170,7 +169,7 @@ def test_mixed_precision_error_vs_oracle(shape, N, leaf, sigma, eps):
     x64 = _gpu(pts, eps, sigma, dg, leaf).solve(b)
     rel64 = np.linalg.norm(x64 - xo) / np.linalg.norm(xo)
     print(f"mixed error vs oracle {rel:.3e} (fp64 {rel64:.3e})", flush=True)
-    assert rel <= 100 * eps
+    assert rel <= 10 * eps
     assert not np.array_equal(x, x64)  # the FP32 path really ran
 
 
@@ -278,3 +277,66 @@ def test_graph_captured_solve_replays(monkeypatch):
     x1 = hg.solve(b[:, 0])
     assert np.array_equal(x1, he.solve(b[:, 0]))
     assert np.array_equal(hg.solve(b), ref)
+
+
+def _cfg2(sigma):
+    """The N = 65,536 sphere workload with the oracle's stored solutions
+    (tests/golden/make_cfg2.py, oracle only)."""
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    ref = np.load(os.path.join(here, f"cfg2_sphere65536_sigma{sigma}.npz"))
+    N = 65536
+    pts = synth.sphere_points(N, 2)
+    dg = synth.laplace_self_term(N)
+    b = np.asfortranarray(np.concatenate([synth.uniform_rhs(N, 1, s) for s in range(201, 209)], axis=1))
+    return pts, dg, b, ref
+
+
+@pytest.mark.parametrize("sigma", [3, 6])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sphere_65536_eight_rhs_vs_oracle_fixture(sigma, precision):
+    # FP64 and mixed GPU solves of 8 right-hand sides against the oracle's
+    # stored solutions at eps = 1e-6.  At this size A~ has condition numbers
+    # ~1e5 (i.i.d. points come arbitrarily close), so two factorisations that
+    # are each eps-accurate (rank decisions of the GPU's Gram eigenvalues and
+    # the oracle's SVD differ inside the truncation band) can differ by
+    # ~eps cond(A~) in the solution.  The bar is therefore the normwise
+    # backward error on A~ (applied exactly through the Chebyshev 4^3 FMM on
+    # the IFMM's own tree): <= 10 eps for the GPU, and its residual no larger
+    # than the oracle's times 2; the difference of the two solutions is
+    # reported, and the ranks per level agree except inside the band (R9).
+    import torch
+    from paper_1905_10602_amd import FMM
+    print(f"case cfg2 sphere N=65536 sigma={sigma} {precision}", flush=True)
+    pts, dg, b, ref = _cfg2(sigma)
+    eps = float(ref["eps"])
+    h = _gpu(pts, eps, sigma, dg, 64, precision=precision)
+    assert h.depth() == int(ref["depth"])
+    bt = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    xg = h.solve(bt)
+    xo = torch.from_numpy(np.ascontiguousarray(ref["x"])).cuda()
+    F = FMM(pts, dg, cheb_order=4, leaf_max=64)
+    v = torch.ones(pts.shape[0], dtype=torch.float64, device="cuda")
+    for _ in range(30):
+        w = F.matvec(v / torch.linalg.norm(v))
+        v = w
+    anorm = float(torch.linalg.norm(v))
+    for c in range(b.shape[1]):
+        bc = bt[:, c].contiguous()
+        rg = float(torch.linalg.norm(F.matvec(xg[:, c].contiguous()) - bc))
+        ro = float(torch.linalg.norm(F.matvec(xo[:, c].contiguous()) - bc))
+        nb = float(torch.linalg.norm(bc))
+        bwg = rg / (anorm * float(torch.linalg.norm(xg[:, c])) + nb)
+        bwo = ro / (anorm * float(torch.linalg.norm(xo[:, c])) + nb)
+        fwd = float(torch.linalg.norm(xg[:, c] - xo[:, c]) / torch.linalg.norm(xo[:, c]))
+        print(f"  column {c}: backward error GPU {bwg:.2e} oracle {bwo:.2e}; residual GPU {rg / nb:.2e} "
+              f"oracle {ro / nb:.2e}; GPU vs oracle {fwd:.2e}", flush=True)
+        assert bwg <= 10 * eps
+        assert rg <= 2.0 * ro + 10 * eps * nb
+    for lvl in range(2, int(ref["depth"]) + 1):
+        ro_ = ref[f"ranks_level{lvl}"]
+        rg_ = h.ranks(lvl)
+        print(f"  level {lvl}: ranks differ at {np.mean(ro_ != rg_):.3f} of the nodes, by at most "
+              f"{np.abs(ro_.astype(int) - rg_).max()}", flush=True)
+        assert np.mean(ro_ != rg_) <= 0.10, lvl
+        assert np.abs(ro_.astype(int) - rg_).max() <= 2, lvl

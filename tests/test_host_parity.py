@@ -161,3 +161,44 @@ def test_options_of_the_boundary(tmp_path):
         with pytest.raises(IfmmError) as e:
             IFMM(pts, 1e-6, 3, diag=1.0, rank_model=str(path))
         assert e.value.status == status, path
+
+
+@pytest.mark.parametrize("shape,N,leaf,sigma,seed", [("sphere", 20000, 32, 3, 2), ("ellipsoid", 30000, 16, 4, 5),
+                                                     ("cube", 12000, 40, 6, 4)])
+def test_lookback_colouring_bit_exact(shape, N, leaf, sigma, seed):
+    from paper_1905_10602_amd import IFMM
+    kw = {"jitter": 0.05} if shape == "ellipsoid" else {}
+    pts = synth.geometry_points(shape, N, seed, **kw)
+    h = IFMM(pts, 1e-6, sigma, diag=1.0, leaf_max=leaf, colouring="lookback")
+    T = Tree(pts, leaf_max=leaf, sigma=sigma, colouring="lookback")
+    T3 = Tree(pts, leaf_max=leaf, sigma=sigma)
+    n_lb = n_a3 = 0
+    for lvl in range(2, T.depth + 1):
+        d = h.level(lvl)
+        assert np.array_equal(d["colour"], T.levels[lvl].colour), lvl
+        assert d["ncolour"] == len(T.levels[lvl].groups)
+        n_lb += d["ncolour"]
+        n_a3 += len(T3.levels[lvl].groups)
+    # greedy either way: looking back fills the first colours more, which
+    # need not lower the colour count (sigma = 4 tiles power-of-two grids well)
+    print(f"colours over all levels: look-back {n_lb}, Alg. 3 {n_a3}")
+
+
+def test_cost_model_bottom_level():
+    from paper_1905_10602_amd import IFMM
+    # leaves of a few points each (the N = 1M ellipsoid has 6.7 on average):
+    # the next coarser level carries the same unknowns, so the finest level
+    # is pure cost and the model drops it
+    pts = synth.ellipsoid_points(30000, 5, jitter=0.05)
+    h0 = IFMM(pts, 1e-6, 3, diag=1.0, leaf_max=8)
+    h = IFMM(pts, 1e-6, 3, diag=1.0, leaf_max=8, bottom_level=-1)
+    st = h.stats()
+    assert len(st["depth_costs"]) == 3 and st["depth_costs"][1] < st["depth_costs"][0]
+    assert h.depth() == h0.depth() - 1 - int(np.argmin(st["depth_costs"][1:]))
+    # big leaves: coarser levels only grow the pivots, the leaf rule stays
+    pts2 = synth.sphere_points(4000, 3)
+    h2 = IFMM(pts2, 1e-6, 3, diag=1.0, leaf_max=200, bottom_level=-1)
+    assert h2.depth() == IFMM(pts2, 1e-6, 3, diag=1.0, leaf_max=200).depth()
+    # the forced depth equals the oracle's tree of that depth
+    T = Tree(pts, leaf_max=8, sigma=3, depth=h.depth())
+    assert np.array_equal(h.perm(), T.perm)

@@ -136,3 +136,44 @@ def test_tree_partitions_points():
         from oracle.tree import box_keys, lex_code
         codes = lex_code(box_keys(pts, T.lo, T.H, T.depth - 1), T.depth - 1)
         assert np.unique(codes, return_counts=True)[1].max() > 20
+
+
+@pytest.mark.parametrize("sigma", [3, 4, 5, 6])
+def test_lookback_colouring_is_separated_and_not_worse(sigma):
+    # the look-back greedy: every colour sigma-separated (brute force), every
+    # box coloured, and on sphere-like occupancies no more colours than Alg. 3
+    from oracle.tree import colour_lookback
+    rng = np.random.default_rng(10 + sigma)
+    for level in (3, 4):
+        m = 1 << level
+        occ = rng.random((m, m, m)) < 0.3
+        kk, jj, ii = np.nonzero(occ)
+        coords = np.stack([ii, jj, kk], axis=1)  # np.nonzero walks (k, j, i) in scan order
+        col = colour_lookback(coords, sigma)
+        assert np.all(col >= 0)
+        grid = np.full(occ.shape, -1)
+        grid[kk, jj, ii] = col
+        _check_separation(grid, occ, sigma)
+    for level in (3, 4, 5):
+        occ = sphere_occupancy(level)
+        kk, jj, ii = np.nonzero(occ)
+        coords = np.stack([ii, jj, kk], axis=1)
+        n_lb = colour_lookback(coords, sigma).max() + 1
+        n_a3 = colour_grid(occ, sigma).max() + 1
+        assert n_lb <= n_a3, (level, n_lb, n_a3)
+
+
+def test_lookback_full_grid_and_a_case_alg3_misses():
+    from oracle.tree import colour_lookback
+    m = 9
+    coords = np.array([(i, j, k) for k in range(m) for j in range(m) for i in range(m)])
+    col = colour_lookback(coords, 3)
+    assert col.max() + 1 == 27
+    # two boxes of one plane, (0, 0) and (5, 1) in (i, j), sigma = 3: Alg. 3
+    # jumps three rows after the row of the seed and misses the second box;
+    # looking back, it is 5 boxes from the seed and joins the first colour
+    occ = np.zeros((8, 8, 8), dtype=bool)
+    occ[0, 0, 0] = True
+    occ[0, 1, 5] = True
+    assert colour_grid(occ, 3).max() + 1 == 2
+    assert colour_lookback(np.array([(0, 0, 0), (5, 1, 0)]), 3).max() + 1 == 1
