@@ -286,8 +286,10 @@ def measured_traffic(kernel, form):
     return None
 
 
-def price(name, k, mixed):
-    """Roofline entry of one kernel class from its in-library hipEvent record."""
+def price(name, k, mixed, f32_flops=None):
+    """Roofline entry of one kernel class from its in-library hipEvent record.
+    f32_flops: the part of the kernel's flops on FP32 matrix cores (mixed form);
+    the peak is then the time-weighted blend of the FP32 and FP64 peaks."""
     la = max(k["launches"], 1)
     avg_s = k["ms"] / 1e3 / la
     common = {"kernel": name, "traffic": measured_traffic(name, "mixed" if mixed else "fp64"),
@@ -302,8 +304,13 @@ def price(name, k, mixed):
                 "frac": ach / HBM_PEAK, **common}
     ach = k["flops"] / la / avg_s
     if mixed and name in MFMA_F32:
-        return {"bound": "mfma", "achieved": ach / 1e12, "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": ach / FP32_MFMA_PEAK, **common}
+        peak = FP32_MFMA_PEAK
+        if f32_flops is not None and k["flops"] > 0:
+            f = min(max(f32_flops / k["flops"], 0.0), 1.0)  # flops share on FP32 matrix cores
+            peak = 1.0 / (f / FP32_MFMA_PEAK + (1.0 - f) / FP64_VECTOR_PEAK)
+            common["fp32_share_of_flops"] = f
+        return {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": ach / peak, **common}
     if not mixed and name in MFMA_F64:
         return {"bound": "mfma", "achieved": ach / 1e12, "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
                 "frac": ach / FP64_MFMA_PEAK, **common}
@@ -318,7 +325,13 @@ def roofline_of(stats, mixed):
     if not ks:
         return None
     name, k = max(ks.items(), key=lambda kv: kv[1]["ms"])
-    return price(name, k, mixed)
+    return price(name, k, mixed, _f32_flops(stats, name))
+
+
+def _f32_flops(stats, name):
+    if name == "k_schur":
+        return stats.get("aux", {}).get("schur_far_flops")
+    return None
 
 
 def roofline_more(stats, mixed):
@@ -328,7 +341,7 @@ def roofline_more(stats, mixed):
     out = {}
     for n in ("k_schur", "k_eig_values", "k_solve_fwd_w", "k_solve_fwd_upd", "k_solve_bwd"):
         if n in ks:
-            out[n] = price(n, ks[n], mixed)
+            out[n] = price(n, ks[n], mixed, _f32_flops(stats, n))
     # the three solve steps together: algorithmic bytes over their summed time
     parts = [ks[n] for n in ("k_solve_fwd_w", "k_solve_fwd_upd", "k_solve_bwd") if n in ks]
     if parts:

@@ -248,7 +248,8 @@ typedef struct fmm_handle fmm_handle;
  * Builds the FMM of A (same arguments and meaning as ifmm_build).
  *   cheb_order  2..6 (interpolation points per axis; K = cheb_order^3)
  *   leaf_max    >= 1, the octree depth is the smallest with <= leaf_max points per leaf
- *   stream      hipStream_t for all device work, or NULL (a library-owned stream)
+ *   stream      hipStream_t for all device work, or NULL (a library-owned stream that is
+ *               ordered with the null stream, so device vectors written there are ready)
  * Errors: IFMM_EINVAL, IFMM_ENONFINITE, IFMM_ENOMEM, IFMM_EDEVICE.
  */
 ifmm_status fmm_build(const double* points, int64_t n, const double* weights, const double* diag,

@@ -252,6 +252,14 @@ ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
     s += buf;
     first = false;
   }
+  s += "},\"aux\":{";
+  first = true;
+  for (const auto& kv : h.aux) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s\"%s\":%.6e", first ? "" : ",", kv.first.c_str(), kv.second);
+    s += buf;
+    first = false;
+  }
   s += "},\"host_ms\":{";
   first = true;
   for (const auto& kv : h.host_ms) {

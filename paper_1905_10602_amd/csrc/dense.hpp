@@ -495,6 +495,8 @@ __device__ inline int sturm_count(int n, const double* d, const double* e, doubl
   return c;
 }
 
+__device__ inline void wg_trd_eigenvalues(int n, const double* A, int lda, double* W, double* lam);
+
 // Eigenvalues of a symmetric A (n x n, overwritten): Householder reduction to
 // tridiagonal form (the reflectors v_k are left in A[k+1:, k], tau[k] = 1 if
 // reflector k is applied), then bisection on Sturm counts.  W holds d, e and
@@ -503,7 +505,6 @@ __device__ inline int sturm_count(int n, const double* d, const double* e, doubl
 // pass over the trailing matrix.
 __device__ inline void wg_syev_values(int n, double* A, int lda, double* W, double* lam) {
   __shared__ double sv[TRD_MAXN], sw[TRD_MAXN], sp[TRD_MAXN];  // 48 KiB
-  __shared__ double s_lo, s_hi;
   double* d = W;
   double* e = W + n;
   double* tau = W + 2 * n;
@@ -624,6 +625,18 @@ __device__ inline void wg_syev_values(int n, double* A, int lda, double* W, doub
       __syncthreads();
     }
   }
+  wg_trd_eigenvalues(n, A, lda, W, lam);
+}
+
+// After a Householder reduction that left e[0..n-3] and the reflectors in W /
+// below the subdiagonal of A: the diagonal d, the last off-diagonal, then the
+// eigenvalues by bisection on Sturm counts (one thread per eigenvalue),
+// descending into lam.
+__device__ inline void wg_trd_eigenvalues(int n, const double* A, int lda, double* W, double* lam) {
+  __shared__ double s_lo, s_hi;
+  double* d = W;
+  double* e = W + n;
+  const int tid = threadIdx.x;
   for (int i = tid; i < n; i += NT) d[i] = A[i + (int64_t)i * lda];
   if (tid == 0 && n >= 2) e[n - 2] = A[(n - 1) + (int64_t)(n - 2) * lda];
   __syncthreads();

@@ -283,6 +283,75 @@ static int check_arena(Handle& h, int l, const char* step, int c, std::string& e
   return 0;
 }
 
+// ------------------------------------------------------------------ eigenvalues
+// Eigenvalues of the matrices of T (device table d_T, counts above eps2 *
+// lam_1 into d_cnt) on stream st: orders below TRD_BIG take the one-workgroup
+// solver, larger ones the multi-workgroup reduction (their work vectors in a
+// buffer of this stream; the stream is synchronised before it grows).
+static int eig_values(Handle& h, const std::vector<EigTask>& T, const EigTask* d_T, double eps2, int32_t* d_cnt,
+                      hipStream_t st, std::string& err) {
+  if (T.empty()) return 0;
+  std::vector<int32_t> big;
+  int nmax = 0;
+  int64_t need = 0;
+  for (size_t a = 0; a < T.size(); ++a)
+    if (!h.eig_jacobi && T[a].n >= TRD_BIG && T[a].n <= TRD_MAXN) {
+      big.push_back((int32_t)a);
+      nmax = std::max(nmax, T[a].n);
+      need += 3LL * T[a].n + (int64_t)T[a].n * ((T[a].n + 63) / 64) + 32;
+    }
+  if (h.eig_jacobi)
+    hipLaunchKernelGGL(k_eig_jacobi, dim3((unsigned)T.size()), dim3(NT), 0, st, d_T, eps2, d_cnt);
+  else
+    hipLaunchKernelGGL(k_eig_values, dim3((unsigned)T.size()), dim3(NT), 0, st, d_T, eps2, d_cnt, TRD_BIG);
+  if (big.empty()) return 0;
+  const bool side = st == h.side_stream && st != nullptr;
+  double*& buf = side ? h.trd_buf_side : h.trd_buf;
+  int64_t& cap = side ? h.trd_cap_side : h.trd_cap;
+  const int64_t tb = ((int64_t)(big.size() * sizeof(TrdTask)) + 255) & ~255LL;
+  const int64_t bytes = tb + need * 8 + 256;
+  if (bytes > cap) {
+    HIPCHK(hipStreamSynchronize(st));
+    dfree(h, buf);
+    buf = nullptr;
+    cap = 0;
+    int rc;
+    if ((rc = dalloc(h, &buf, (bytes + 7) / 8, err))) return rc;
+    cap = ((bytes + 7) / 8) * 8;
+  }
+  TrdTask* d_trd = (TrdTask*)buf;
+  double* w0 = (double*)((char*)buf + tb);
+  std::vector<TrdTask> tt(big.size());
+  int64_t o = 0;
+  for (size_t q = 0; q < big.size(); ++q) {
+    const EigTask& e = T[big[q]];
+    TrdTask& t = tt[q];
+    t.A = e.A;
+    t.W = e.W;
+    t.vec = w0 + o;
+    o += 3LL * e.n;
+    t.part = w0 + o;
+    o += (int64_t)e.n * ((e.n + 63) / 64) + 32;
+    t.n = e.n;
+    t.slot = big[q];
+  }
+  HIPCHK(hipMemcpyAsync(d_trd, held(h, tt), tt.size() * sizeof(TrdTask), hipMemcpyHostToDevice, st));
+  const unsigned nb = (unsigned)big.size();
+  hipLaunchKernelGGL(k_trd_start, dim3(nb), dim3(NT), 0, st, d_trd);
+  auto tiles = [&](int k) {
+    const int m = nmax - k - 2, b = (m + 63) / 64;
+    if (m > 0) hipLaunchKernelGGL(k_trd_tiles, dim3((unsigned)(b * b), nb), dim3(NT), 0, st, d_trd, k);
+  };
+  tiles(-1);
+  for (int k = 0; k + 2 < nmax; ++k) {
+    hipLaunchKernelGGL(k_trd_step, dim3(nb), dim3(NT), 0, st, d_trd, k);
+    tiles(k);
+  }
+  hipLaunchKernelGGL(k_trd_values, dim3(nb), dim3(NT), 0, st, d_trd, d_T, eps2, d_cnt);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
 // ------------------------------------------------------------------ level set-up
 static LevelView view_of(DevLevel& L) {
   LevelView V;
@@ -487,12 +556,8 @@ static int reduce_level(Handle& h, int l, std::string& err) {
   const double* G = h.weights_G[l];
   if (nn > 0) {
     hipLaunchKernelGGL(k_reduce_gram, dim3(nn), dim3(NT), 0, h.stream, V, K, G, work, d_woff);
-    if (h.eig_jacobi)
-      hipLaunchKernelGGL(k_eig_jacobi, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, d_tasks, h.eps * h.eps,
-                         d_cnt);
-    else
-      hipLaunchKernelGGL(k_eig_values, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, d_tasks, h.eps * h.eps,
-                         d_cnt, 0);
+    int rc2;
+    if ((rc2 = eig_values(h, tasks, d_tasks, h.eps * h.eps, d_cnt, h.stream, err))) return rc2;
   }
   HIPCHK(hipGetLastError());
   std::vector<int32_t> cnt(tasks.size());
@@ -616,7 +681,7 @@ static int rank_features(Handle& h, int l, std::vector<Changed>& chg, const std:
   }
   H2D(h, d_t, tt.data(), nf * sizeof(SkTask));
   hipLaunchKernelGGL(k_sk_omega, dim3(16, (unsigned)nf), dim3(NT), 0, h.stream, d_t);
-  hipLaunchKernelGGL(k_sk_range, dim3((unsigned)((nmax + 63) / 64), 1, (unsigned)nf), dim3(NT), 0, h.stream, d_chg,
+  hipLaunchKernelGGL(k_sk_range<false>, dim3((unsigned)((nmax + 63) / 64), 1, (unsigned)nf), dim3(NT), 0, h.stream, d_chg,
                      d_refs, d_far, d_nbrs, d_recs, d_t);
   hipLaunchKernelGGL(k_feat_sv, dim3((unsigned)nf), dim3(NT), 0, h.stream, d_t, d_sv);
   std::vector<double> sv(8 * nf);
@@ -1027,7 +1092,12 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   LevelView V = view_of(L);
   const int nchg = (int)chg.size();
   // algorithmic work of the phase-A steps (counted from the block sizes)
-  double fl_lu = 0, fl_x = 0, fl_schur = 0, by_gather = 0, by_schur = 0;
+  double fl_lu = 0, fl_x = 0, fl_schur = 0, by_gather = 0, by_schur = 0, fl_far = 0;
+  for (const FarPair& F : far) {  // far fill-in products (FP32 in the mixed form)
+    const ElimRec& R = recs[F.rec];
+    fl_far += 2.0 * nbrs[R.nb_begin + F.a].m * (double)R.n * nbrs[R.nb_begin + F.b].m;
+  }
+  h.aux["schur_far_flops"] += fl_far;
   for (const ElimRec& R : recs) {
     const double d = R.d, n = R.n, M = R.M, r = R.r;
     fl_lu += 2.0 / 3.0 * d * d * d;
@@ -1237,10 +1307,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     if (nfull) {
       ProfScope ps(h, "k_eig_values", fl_ev, 0, side);
       const hipStream_t st = side ? h.side_stream : h.stream;
-      if (h.eig_jacobi)
-        hipLaunchKernelGGL(k_eig_jacobi, dim3((unsigned)nfull), dim3(NT), 0, st, d_fullT, eps2, d_cf);
-      else
-        hipLaunchKernelGGL(k_eig_values, dim3((unsigned)nfull), dim3(NT), 0, st, d_fullT, eps2, d_cf, 0);
+      if ((rc = eig_values(h, fullT, d_fullT, eps2, d_cf, st, err))) return rc;
     }
     if (nsk) {
       double fl_sk = 0;
@@ -1251,8 +1318,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       {
         ProfScope ps(h, "group:sketch_range", fl_sk, 0);
         hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
-        hipLaunchKernelGGL(k_sk_range, dim3(tn, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_chg, d_refs, d_far,
-                           d_nbrs, d_recs, d_skT);
+        hipLaunchKernelGGL(h.precision == 1 ? k_sk_range<true> : k_sk_range<false>, dim3(tn, ts, (unsigned)nsk),
+                           dim3(NT), 0, h.stream, d_chg, d_refs, d_far, d_nbrs, d_recs, d_skT);
       }
       {
         ProfScope ps(h, "group:sketch_orth", 0, 0);
@@ -1262,7 +1329,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       hipLaunchKernelGGL(k_gemm_batch, dim3(tn, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_gT);
       hipLaunchKernelGGL(k_gemm_batch, dim3(ts, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_gT + nsk);
       hipLaunchKernelGGL(k_sk_trace, dim3((unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
-      hipLaunchKernelGGL(k_eig_values, dim3((unsigned)nsk), dim3(NT), 0, h.stream, d_skE, eps2, d_cs, 0);
+      if ((rc = eig_values(h, skE, d_skE, eps2, d_cs, h.stream, err))) return rc;
       hipLaunchKernelGGL(k_sk_check, dim3((unsigned)((nsk + NT - 1) / NT)), dim3(NT), 0, h.stream, d_skT, d_skE, d_cs,
                          eps2, d_ok, (int)nsk);
     }
@@ -1376,8 +1443,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         {
           ProfScope ps(h, "group:sketch_range", fl2, 0);
           hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)n2), dim3(NT), 0, h.stream, d_T2);
-          hipLaunchKernelGGL(k_sk_range, dim3(tn, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_chg, d_refs, d_far,
-                             d_nbrs, d_recs, d_T2);
+          hipLaunchKernelGGL(h.precision == 1 ? k_sk_range<true> : k_sk_range<false>, dim3(tn, ts, (unsigned)n2),
+                             dim3(NT), 0, h.stream, d_chg, d_refs, d_far, d_nbrs, d_recs, d_T2);
         }
         {
           ProfScope ps(h, "group:sketch_orth", 0, 0);
@@ -1387,7 +1454,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
         hipLaunchKernelGGL(k_gemm_batch, dim3(tn, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_G2);
         hipLaunchKernelGGL(k_gemm_batch, dim3(ts, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_G2 + n2);
         hipLaunchKernelGGL(k_sk_trace, dim3((unsigned)n2), dim3(NT), 0, h.stream, d_T2);
-        hipLaunchKernelGGL(k_eig_values, dim3((unsigned)n2), dim3(NT), 0, h.stream, d_E2, eps2, d_c2, 0);
+        if ((rc = eig_values(h, r2E, d_E2, eps2, d_c2, h.stream, err))) return rc;
         hipLaunchKernelGGL(k_sk_check, dim3((unsigned)((n2 + NT - 1) / NT)), dim3(NT), 0, h.stream, d_T2, d_E2, d_c2,
                            eps2, d_o2, (int)n2);
       }
@@ -1412,7 +1479,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       H2D(h, d_fbT, fb.data(), fb.size() * sizeof(EigTask));
       {
         ProfScope ps(h, "k_eig_values", 0, 0);
-        hipLaunchKernelGGL(k_eig_values, dim3((unsigned)fb.size()), dim3(NT), 0, h.stream, d_fbT, eps2, d_cfb, 0);
+        if ((rc = eig_values(h, fb, d_fbT, eps2, d_cfb, h.stream, err))) return rc;
       }
       std::vector<int32_t> cfb(fb.size());
       HSYNC(h);
@@ -1921,6 +1988,7 @@ int factor(Handle& h, std::string& err) {
   h.stat_predicted = 0;
   h.kstat.clear();
   h.host_ms.clear();
+  h.aux.clear();
   h.stat_far = 0;
   h.stat_changed = 0;
   h.stat_grown = 0;
@@ -2366,10 +2434,20 @@ extern "C" int ifmm_internal_syev(const double* A, int count, int n, int k, doub
     t[c] = {dA + c * nn, dV + c * nn, dW + c * wsz, dL + (int64_t)c * n, dI + c * (5LL * n * std::max(k, 1)), n, k};
   (void)hipMemcpy(dA, A, count * nn * 8, hipMemcpyHostToDevice);
   (void)hipMemcpy(dT, t.data(), count * sizeof(EigTask), hipMemcpyHostToDevice);
-  if (jacobi) hipLaunchKernelGGL(k_eig_jacobi, dim3(count), dim3(NT), 0, nullptr, dT, 0.0, dC);
-  else hipLaunchKernelGGL(k_eig_values, dim3(count), dim3(NT), 0, nullptr, dT, 0.0, dC, 0);
-  if (!jacobi) hipLaunchKernelGGL(k_eig_vectors, dim3(count), dim3(NT), 0, nullptr, dT);
-  int rc = hipDeviceSynchronize() == hipSuccess ? 0 : -3;
+  int rc = 0;
+  if (jacobi) {
+    hipLaunchKernelGGL(k_eig_jacobi, dim3(count), dim3(NT), 0, nullptr, dT, 0.0, dC);
+  } else {
+    // the factorisation's routing: one workgroup below TRD_BIG, the
+    // multi-workgroup reduction from there on
+    Handle hh;
+    std::string err;
+    rc = eig_values(hh, t, dT, 0.0, dC, nullptr, err);
+    if (rc == 0) hipLaunchKernelGGL(k_eig_vectors, dim3(count), dim3(NT), 0, nullptr, dT);
+    if (hipDeviceSynchronize() != hipSuccess) rc = -3;
+    for (auto& a : hh.allocs) (void)hipFree(a.first);
+  }
+  if (hipDeviceSynchronize() != hipSuccess) rc = -3;
   (void)hipMemcpy(lam, dL, count * (int64_t)n * 8, hipMemcpyDeviceToHost);
   for (int c = 0; c < count; ++c)
     (void)hipMemcpy(V + c * (int64_t)n * k, dV + c * nn, (int64_t)n * k * 8, hipMemcpyDeviceToHost);

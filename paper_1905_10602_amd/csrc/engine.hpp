@@ -241,6 +241,7 @@ struct Handle {
   };
   std::map<std::string, KStat> kstat;
   std::map<std::string, double> host_ms;  // host time of the factorisation by phase, stream waits excluded
+  std::map<std::string, double> aux;      // further counters (e.g. the far fill-in share of the Schur flops)
   struct Pending {
     hipEvent_t a, b;
     std::string name;
@@ -250,6 +251,10 @@ struct Handle {
   std::vector<hipEvent_t> event_pool;
   int32_t* d_flag = nullptr;
   bool eig_jacobi = false;  // IFMM_EIG=jacobi: cyclic Jacobi instead of tridiagonal + bisection
+  // work buffers of the multi-workgroup tridiagonal reduction, one per stream
+  double* trd_buf = nullptr;
+  double* trd_buf_side = nullptr;
+  int64_t trd_cap = 0, trd_cap_side = 0;
 };
 
 // status helpers

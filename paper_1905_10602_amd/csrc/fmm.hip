@@ -311,7 +311,9 @@ int fmm_setup(FmmHandle& h, const double* pts, int64_t n, const double* w, const
   const int D = T.depth;
   FCHK(hipGetDevice(&h.device));
   if (!h.stream) {
-    FCHK(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
+    // a blocking stream: ordered with the null stream, on which callers
+    // (torch's default stream among them) produce the device vectors
+    FCHK(hipStreamCreate(&h.stream));
     h.own_stream = true;
   }
   // points, weights, diagonal in tree order

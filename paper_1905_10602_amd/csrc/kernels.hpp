@@ -216,8 +216,10 @@ __global__ void __launch_bounds__(NT) k_eig_jacobi(const EigTask* tasks, double 
   eig_count(t, eps2, cnt);
 }
 
-__global__ void __launch_bounds__(NT) k_eig_values(const EigTask* tasks, double eps2, int32_t* cnt, int unused) {
+// big > 0: matrices of order >= big are left to the multi-workgroup reduction
+__global__ void __launch_bounds__(NT) k_eig_values(const EigTask* tasks, double eps2, int32_t* cnt, int big) {
   const EigTask t = tasks[blockIdx.x];
+  if (big > 0 && t.n >= big) return;
   if (t.n == 0) {
     if (threadIdx.x == 0) cnt[blockIdx.x] = 0;
     return;
@@ -237,6 +239,172 @@ __global__ void __launch_bounds__(NT) k_eig_vectors(const EigTask* tasks) {
   const EigTask t = tasks[blockIdx.x];
   if (t.n == 0 || t.k == 0) return;
   wg_syev_vectors(t.n, t.A, t.n, t.W, t.lam, t.k, t.V, t.n, t.IW);
+}
+
+// ---- Householder tridiagonalisation spread over many workgroups (large
+// matrices, batched over the matrices of a colour).  The same reduction as
+// wg_syev_values, one reflector per step: a one-workgroup step kernel per
+// matrix (reduce p = S v from partial sums, K = p^T v, w = p - K v, update the
+// leading column of S, form the next reflector from it) and a tiled kernel
+// over the trailing matrix (S -= 2 (v w^T + w v^T) on 64 x 64 tiles, each
+// tile also accumulating its part of the next product S' v').  Per step the
+// trailing matrix is read and written once by the whole device instead of
+// by one compute unit.
+struct TrdTask {
+  double* A;     // n x n, ld n: symmetric input, overwritten (reflectors below the subdiagonal)
+  double* W;     // d (n), e (n), tau (n), as the one-workgroup solver leaves them
+  double* vec;   // 3 n: v, w of the current step and the next reflector, in trailing coordinates
+  double* part;  // n x ceil(n / 64): partial sums of the next product, one column per column tile
+  int32_t n, slot;  // order; index of the matrix in the caller's EigTask table and count array
+};
+constexpr int TRD_BIG = 384;  // matrices of at least this order take the multi-workgroup reduction
+
+// Householder vector of x (length m, in place in A's column): sets e / tau of
+// step `k`; returns the vector (normalised, 0 if x[1:] is already zero) in v.
+__device__ inline void trd_reflector(double* x, int m, double* e, double* tau, int k, double* v) {
+  __shared__ double s_sig;
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int i = 1 + tid; i < m; i += NT) part += x[i] * x[i];
+  const double sig = wg_sum(part);
+  if (tid == 0) s_sig = sig;
+  __syncthreads();
+  const double x0 = x[0];
+  if (sig == 0.0) {
+    for (int i = tid; i < m; i += NT) v[i] = 0.0;
+    if (tid == 0) { e[k] = x0; tau[k] = 0.0; }
+    __syncthreads();
+    return;
+  }
+  const double alpha = -copysign(sqrt(x0 * x0 + sig), x0);
+  const double v0 = x0 - alpha;
+  const double inv = 1.0 / sqrt(sig + v0 * v0);
+  for (int i = tid; i < m; i += NT) v[i] = (i == 0 ? v0 : x[i]) * inv;
+  __syncthreads();
+  for (int i = tid; i < m; i += NT) x[i] = v[i];
+  if (tid == 0) { e[k] = alpha; tau[k] = 1.0; }
+  __syncthreads();
+}
+
+// Start: the first reflector (from column 0) into vec's next-reflector slot;
+// v, w of the "previous step" are zero, so the first tiled pass only forms S v.
+__global__ void __launch_bounds__(NT) k_trd_start(const TrdTask* tasks) {
+  const TrdTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  if (n < 3) return;
+  const int m = n - 1;
+  double* v = t.vec;
+  double* w = t.vec + n;
+  double* vn = t.vec + 2 * n;
+  for (int i = threadIdx.x; i < m; i += NT) { v[i] = 0.0; w[i] = 0.0; }
+  trd_reflector(t.A + 1, m, t.W + n, t.W + 2 * n, 0, vn);
+}
+
+// Tiled pass after step k (k = -1: the first product only) over the trailing
+// matrix S = A[k+2:, k+2:] (order m = n - k - 2): S -= 2 (v w^T + w v^T) with
+// the step's v, w (already in S's coordinates), and part[tj][i] = sum over the
+// tile's columns of S[i, j] vn[j].  grid (tiles of the largest S, task).
+__global__ void __launch_bounds__(NT) k_trd_tiles(const TrdTask* tasks, int k) {
+  __shared__ double red[NT / 64][64];
+  const TrdTask t = tasks[blockIdx.y];
+  const int n = t.n, m = n - k - 2;
+  if (n < 3 || k > n - 3 || m <= 0) return;
+  const int nb = (m + 63) / 64;
+  if ((int)blockIdx.x >= nb * nb) return;
+  const int ti = blockIdx.x % nb, tj = blockIdx.x / nb;
+  const int I = 64 * ti, J = 64 * tj;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double* v = t.vec;
+  const double* w = t.vec + n;
+  const double* vn = t.vec + 2 * n;
+  double* S = t.A + (k + 2) + (int64_t)(k + 2) * n;
+  const int i = I + lane;
+  double acc = 0.0;
+  if (i < m) {
+    const double vi = v[i], wi = w[i];
+    for (int jj = wave; jj < 64; jj += NT / 64) {
+      const int j = J + jj;
+      if (j >= m) break;
+      double* c = S + i + (int64_t)j * n;
+      const double sv = *c - 2.0 * (vi * w[j] + wi * v[j]);
+      *c = sv;
+      acc += sv * vn[j];
+    }
+  }
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && i < m) {
+    double a = 0.0;
+    for (int q = 0; q < NT / 64; ++q) a += red[q][lane];
+    t.part[(int64_t)tj * n + i] = a;
+  }
+}
+
+// Step k (0 <= k <= n - 3): p = sum of the partial sums (S_k v_k, S_k =
+// A[k+1:, k+1:] of order m = n - k - 1), K = p^T v, w = p - K v, update of
+// S_k's leading column, the next reflector from it, and v, w, vn of the
+// following tiled pass in the coordinates of A[k+2:, k+2:].
+__global__ void __launch_bounds__(NT) k_trd_step(const TrdTask* tasks, int k) {
+  __shared__ double sp[TRD_MAXN], sv[TRD_MAXN], sw[TRD_MAXN];
+  const TrdTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  if (n < 3 || k > n - 3) return;
+  const int m = n - k - 1, nb = (m + 63) / 64;
+  const int tid = threadIdx.x;
+  double* vec_v = t.vec;
+  double* vec_w = t.vec + n;
+  double* vec_n = t.vec + 2 * n;
+  double* col = t.A + (k + 1) + (int64_t)k * n;  // reflector v_k, stored by the previous step
+  for (int i = tid; i < m; i += NT) {
+    double a = 0.0;
+    for (int c = 0; c < nb; ++c) a += t.part[(int64_t)c * n + i];
+    sp[i] = a;
+    sv[i] = t.W[2 * n + k] != 0.0 ? col[i] : 0.0;  // tau_k = 0: no reflector at this step
+  }
+  __syncthreads();
+  double kp = 0.0;
+  for (int i = tid; i < m; i += NT) kp += sp[i] * sv[i];
+  const double K = wg_sum(kp);
+  for (int i = tid; i < m; i += NT) sw[i] = sp[i] - K * sv[i];
+  __syncthreads();
+  // leading column of S_k: column k + 1 of A, rows k + 1 ..
+  double* S0 = t.A + (k + 1) + (int64_t)(k + 1) * n;
+  for (int i = tid; i < m; i += NT) S0[i] -= 2.0 * (sv[i] * sw[0] + sw[i] * sv[0]);
+  __syncthreads();
+  const int m2 = m - 1;
+  for (int i = tid; i < m2; i += NT) {
+    vec_v[i] = sv[i + 1];
+    vec_w[i] = sw[i + 1];
+  }
+  if (k + 3 < n) {
+    trd_reflector(S0 + 1, m2, t.W + n, t.W + 2 * n, k + 1, sp);  // sp now holds the next reflector
+    for (int i = tid; i < m2; i += NT) vec_n[i] = sp[i];
+  } else {
+    for (int i = tid; i < m2; i += NT) vec_n[i] = 0.0;
+  }
+}
+
+// After the last step: d, the last off-diagonal and the eigenvalues.
+__global__ void __launch_bounds__(NT) k_trd_values(const TrdTask* tasks, const EigTask* et, double eps2, int32_t* cnt) {
+  const TrdTask t = tasks[blockIdx.x];
+  const EigTask e = et[t.slot];
+  if (t.n == 0) {
+    if (threadIdx.x == 0) cnt[t.slot] = 0;
+    return;
+  }
+  if (t.n < 3) {  // nothing reduced: the one-workgroup solver on the tiny matrix
+    wg_syev_values(t.n, t.A, t.n, t.W, e.lam);
+  } else {
+    wg_trd_eigenvalues(t.n, t.A, t.n, t.W, e.lam);
+  }
+  if (threadIdx.x == 0) {
+    const double l0 = e.lam[0];
+    int c = 0;
+    if (l0 > 0.0)
+      for (int q = 0; q < t.n; ++q)
+        if (e.lam[q] > eps2 * l0) ++c;
+    cnt[t.slot] = c;
+  }
 }
 
 // ------------------------------------------------------------------ batched tiled GEMM
@@ -296,7 +464,10 @@ __global__ void __launch_bounds__(NT) k_sk_omega(const SkTask* tasks) {
 // sampled directions carry singular values, not their squares:
 //   side 0:  Y = W^T Omega,  W = [diag(sig_s) P2M ; F_qp ...]   (rows: r, then m_q each)
 //   side 1:  Y = W Omega,    W = [L2P diag(sig_t) , F_pq ...]   (columns likewise)
-// grid (row tiles of n, column tiles of s, sketch task).
+// grid (row tiles of n, column tiles of s, sketch task).  F32: the products
+// on FP32 matrix cores (mixed form); the Rayleigh-Ritz step and the
+// a-posteriori test that judge the sample stay FP64.
+template <bool F32>
 __global__ void __launch_bounds__(NT) k_sk_range(const Changed* chg, const FarRef* refs, const FarPair* far, const ElimNbr* nbrs,
                            const ElimRec* recs, const SkTask* tasks) {
   const SkTask t = tasks[blockIdx.z];
@@ -310,21 +481,21 @@ __global__ void __launch_bounds__(NT) k_sk_range(const Changed* chg, const FarRe
   double* Y = t.Y + I + (int64_t)J * n;
   const double* Om = t.O + (int64_t)J * t.R;
   if (t.side == 0) {
-    wg_gemm(mi, sj, r, 1.0, tb + (int64_t)I * r, r, true, Om, t.R, false, 0.0, Y, n);
+    wg_gemm_p(F32, mi, sj, r, 1.0, tb + (int64_t)I * r, r, true, Om, t.R, false, 0.0, Y, n);
     int off = r;
     for (int k = 0; k < C.far_count; ++k) {
       const FarPair Pq = far[refs[C.far_begin + k].ba];
       const int mq = nbrs[R.nb_begin + Pq.a].m;
-      wg_gemm(mi, sj, mq, 1.0, Pq.F + (int64_t)I * mq, mq, true, Om + off, t.R, false, 1.0, Y, n);
+      wg_gemm_p(F32, mi, sj, mq, 1.0, Pq.F + (int64_t)I * mq, mq, true, Om + off, t.R, false, 1.0, Y, n);
       off += mq;
     }
   } else {
-    wg_gemm(mi, sj, r, 1.0, tb + I, n, false, Om, t.R, false, 0.0, Y, n);
+    wg_gemm_p(F32, mi, sj, r, 1.0, tb + I, n, false, Om, t.R, false, 0.0, Y, n);
     int off = r;
     for (int k = 0; k < C.far_count; ++k) {
       const FarPair Pq = far[refs[C.far_begin + k].ab];
       const int mq = nbrs[R.nb_begin + Pq.b].m;
-      wg_gemm(mi, sj, mq, 1.0, Pq.F + I, n, false, Om + off, t.R, false, 1.0, Y, n);
+      wg_gemm_p(F32, mi, sj, mq, 1.0, Pq.F + I, n, false, Om + off, t.R, false, 1.0, Y, n);
       off += mq;
     }
   }
@@ -985,7 +1156,11 @@ struct SchurTask {
   int32_t rec, a, b, tile;
 };
 // product of the Schur update: FP64, FP32 lite tile, or FP32 with the
-// double-buffered tile for long inner dimensions (own kernel instances)
+// double-buffered tile for long inner dimensions (own kernel instances).
+// In the mixed form only the far fill-in F = -L_a X_b goes through FP32: it
+// is formed fresh (no cancellation against stored data) and then compressed
+// at relative accuracy eps.  The near blocks are updated in place, M -= L X,
+// where the difference can be far smaller than either term, and stay FP64.
 template <bool f32, bool deep>
 __device__ inline void schur_gemm(int m, int n, int k, double alpha, const double* A, int lda, const double* B,
                                   int ldb, double beta, double* C, int ldc) {
@@ -1006,11 +1181,11 @@ __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const E
       const double* Xb = R.X + (int64_t)B.off * d;
       const int fi = far_idx[R.far_base + a * R.nnb + b];
       if (fi < 0)
-        schur_gemm<f32, deep>(A.m, B.m, n, -1.0, La, M, Xb, d, 1.0, V.arena + near_block(V, A.p, B.p), np);
+        schur_gemm<false, false>(A.m, B.m, n, -1.0, La, M, Xb, d, 1.0, V.arena + near_block(V, A.p, B.p), np);
       else schur_gemm<f32, deep>(A.m, B.m, n, -1.0, La, M, Xb, d, 0.0, far[fi].F, A.m);
     } else {
       // new block (p, i) = L_a F   with [F; H] = D^-1 [0; I]
-      schur_gemm<f32, deep>(A.m, r, n, 1.0, La, M, R.X + (int64_t)M * d, d, 0.0, V.arena + A.blk_pi, np);
+      schur_gemm<false, false>(A.m, r, n, 1.0, La, M, R.X + (int64_t)M * d, d, 0.0, V.arena + A.blk_pi, np);
     }
   } else {
     if (b >= 0) {
@@ -1037,13 +1212,13 @@ __device__ inline void schur_tile(const LevelView& V, const ElimRec& R, const El
     const double* Xb = R.X + (int64_t)(B.off + j0) * d;
     const int fi = far_idx[R.far_base + a * R.nnb + b];
     if (fi < 0)
-      schur_gemm<f32, deep>(mt, nt, n, -1.0, La, M, Xb, d, 1.0,
-                            V.arena + near_block(V, A.p, B.p) + i0 + (int64_t)j0 * np, np);
+      schur_gemm<false, false>(mt, nt, n, -1.0, La, M, Xb, d, 1.0,
+                               V.arena + near_block(V, A.p, B.p) + i0 + (int64_t)j0 * np, np);
     else schur_gemm<f32, deep>(mt, nt, n, -1.0, La, M, Xb, d, 0.0, far[fi].F + i0 + (int64_t)j0 * A.m, A.m);
   } else {
     const int nt = min(64, R.r - j0);
-    schur_gemm<f32, deep>(mt, nt, n, 1.0, La, M, R.X + (int64_t)(M + j0) * d, d, 0.0,
-                          V.arena + A.blk_pi + i0 + (int64_t)j0 * np, np);
+    schur_gemm<false, false>(mt, nt, n, 1.0, La, M, R.X + (int64_t)(M + j0) * d, d, 0.0,
+                             V.arena + A.blk_pi + i0 + (int64_t)j0 * np, np);
   }
 }
 
