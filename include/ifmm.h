@@ -135,6 +135,27 @@ ifmm_status ifmm_solve(ifmm_handle* h, const double* rhs, double* x, int32_t nrh
                        int32_t on_device);
 
 /*
+ * The solve of ifmm_solve without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops.
+ *   rhs, x     device pointers, N x nrhs column-major, leading dimension
+ *              ld >= N; they may alias.
+ * The work vector lives in one fixed device array of the library per device
+ * (ifmm_solve_noalloc_max_bytes() bytes, 256 MiB, held until the process
+ * ends), shared by every handle and every call on that device: calls that
+ * overlap on one device race, so serialise them (one stream, or events).
+ * The work is enqueued on the handle's stream and the call returns without
+ * synchronising; x is valid once that stream has reached this point.  No
+ * HIP graph is used and no timing events are recorded.
+ * Errors: IFMM_ESTATE (no factorisation), IFMM_EINVAL (bad argument, or the
+ * work vector for nrhs right-hand sides exceeds the fixed array; the message
+ * gives the bytes needed), IFMM_EDEVICE.
+ */
+ifmm_status ifmm_solve_noalloc(ifmm_handle* h, const double* rhs, double* x, int32_t nrhs, int64_t ld);
+
+/* Size in bytes of the fixed work array of ifmm_solve_noalloc. */
+int64_t ifmm_solve_noalloc_max_bytes(void);
+
+/*
  * Writes a JSON object with per-level statistics (nodes, colours, rank
  * histogram summary, bytes) and phase times into json (NUL-terminated,
  * truncated to cap bytes).  Errors: IFMM_EINVAL.

@@ -201,6 +201,21 @@ ifmm_status ifmm_solve(ifmm_handle* H, const double* rhs, double* x, int32_t nrh
   return IFMM_OK;
 }
 
+ifmm_status ifmm_solve_noalloc(ifmm_handle* H, const double* rhs, double* x, int32_t nrhs, int64_t ld) {
+  ifmm::set_error("");
+  if (!H) return fail(IFMM_EINVAL, "handle is NULL");
+  if (!H->h.factored) return fail(IFMM_ESTATE, "ifmm_solve_noalloc called before ifmm_factor");
+  if (!rhs || !x) return fail(IFMM_EINVAL, "rhs / x is NULL");
+  if (nrhs < 1) return fail(IFMM_EINVAL, "nrhs must be >= 1");
+  if (ld < H->h.N) return fail(IFMM_EINVAL, "ld must be >= N");
+  std::string err;
+  int rc = ifmm::solve_noalloc(H->h, rhs, x, nrhs, ld, err);
+  if (rc) return fail(rc, err);
+  return IFMM_OK;
+}
+
+int64_t ifmm_solve_noalloc_max_bytes(void) { return ifmm::solve_noalloc_limit_bytes(); }
+
 ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
   if (!H || !json || cap < 1) return fail(IFMM_EINVAL, "bad arguments");
   const ifmm::Handle& h = H->h;

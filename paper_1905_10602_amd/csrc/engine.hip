@@ -2312,6 +2312,59 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
   return 0;
 }
 
+// ---- the solve without allocations: the work vector lives in a fixed
+// device array of this library, one per device, shared by every handle and
+// call on that device (so calls that overlap on one device race).
+constexpr int64_t SOLVE_SCRATCH_DOUBLES = (int64_t)32 << 20;  // 256 MiB
+static __device__ __align__(256) double scratch[SOLVE_SCRATCH_DOUBLES];
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[64] = {};  // device address of `scratch`, per device
+
+int64_t solve_noalloc_limit_bytes() { return SOLVE_SCRATCH_DOUBLES * 8; }
+
+int solve_noalloc(Handle& h, const double* rhs, double* x, int k, int64_t ld, std::string& err) {
+  if (!h.factored) {
+    err = "solve called before ifmm_factor";
+    return -6;
+  }
+  if (h.device < 0 || h.device >= 64) {
+    err = "device index out of range";
+    return -3;
+  }
+  const SolvePlan P = solve_plan(h, k, ld, false);
+  if (P.total > SOLVE_SCRATCH_DOUBLES) {
+    err = "the solve needs " + std::to_string(P.total * 8) + " bytes of work space for " + std::to_string(k) +
+          " right-hand sides, above the fixed " + std::to_string(SOLVE_SCRATCH_DOUBLES * 8) +
+          " bytes of the allocation-free solve (use ifmm_solve, or fewer right-hand sides)";
+    return -1;
+  }
+  double* B = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[h.device]) {
+      int cur = -1;
+      HIPCHK(hipGetDevice(&cur));
+      HIPCHK(hipSetDevice(h.device));
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      (void)hipSetDevice(cur);
+      if (e != hipSuccess || !ptr) {
+        err = std::string("hipGetSymbolAddress of the solve scratch failed: ") + hipGetErrorString(e);
+        return -3;
+      }
+      g_scratch_ptr[h.device] = (double*)ptr;
+    }
+    B = g_scratch_ptr[h.device];
+  }
+  HIPCHK(hipSetDevice(h.device));
+  const bool prof = h.prof;
+  h.prof = false;  // no timing events: the caller may be capturing this stream
+  enqueue_solve(h, P, B, rhs, x, k, ld);
+  h.prof = prof;
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
 // ------------------------------------------------------------------ init / release
 int device_init(Handle& h, std::string& err) {
   int ndev = 0;

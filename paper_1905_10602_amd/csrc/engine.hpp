@@ -266,6 +266,10 @@ int build_host(Handle& h, const double* pts, int64_t n, const double* w, const d
 int device_init(Handle& h, std::string& err);
 int factor(Handle& h, std::string& err);
 int solve(Handle& h, const double* rhs, double* x, int nrhs, int64_t ld, int on_device, std::string& err);
+// The same solve with device vectors only, its work vector in a fixed per-device
+// array (no allocation, no synchronisation: the work is left queued on h.stream).
+int solve_noalloc(Handle& h, const double* rhs, double* x, int nrhs, int64_t ld, std::string& err);
+int64_t solve_noalloc_limit_bytes();
 void release(Handle& h);
 
 }  // namespace ifmm

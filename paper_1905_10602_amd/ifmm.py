@@ -55,6 +55,8 @@ def load_library():
         "ifmm_build": (I32, [P, I64, P, P, D, I32, D, I32, C.POINTER(Options), C.POINTER(P)]),
         "ifmm_factor": (I32, [P]),
         "ifmm_solve": (I32, [P, P, P, I32, I64, I32]),
+        "ifmm_solve_noalloc": (I32, [P, P, P, I32, I64]),
+        "ifmm_solve_noalloc_max_bytes": (I64, []),
         "ifmm_stats": (I32, [P, C.c_char_p, I64]),
         "ifmm_tree_depth": (I32, [P, C.POINTER(I32)]),
         "ifmm_tree_perm": (I32, [P, P]),
