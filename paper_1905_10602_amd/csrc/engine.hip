@@ -2144,15 +2144,25 @@ static SolvePlan solve_plan(const Handle& h, int k, int64_t ld, bool staging) {
   return P;
 }
 
-// One launch of a solve step over `ntask` row tiles (four per workgroup), the
-// right-hand-side chunk width chosen for k (1, 4 or 8 columns at a time).
-template <class K1, class K4, class K8, class... Args>
-static void launch_solve(K1 k1, K4 k4, K8 k8, int k, int ntask, hipStream_t st, Args... args) {
-  const dim3 grid((unsigned)((ntask + NT / 64 - 1) / (NT / 64)));
-  if (k == 1) hipLaunchKernelGGL(k1, grid, dim3(NT), 0, st, args...);
-  else if (k <= 4) hipLaunchKernelGGL(k4, grid, dim3(NT), 0, st, args...);
-  else hipLaunchKernelGGL(k8, grid, dim3(NT), 0, st, args...);
-}
+// One launch of a solve step over `ntask` row tiles, one workgroup each: the
+// right-hand-side chunk width SK chosen for k (1, 4 or 8 columns at a time),
+// the number of waves NW that split the tile's inner dimension (64-column
+// chunks) for the colour's longest inner dimension.
+static int solve_waves(int inner) { return inner <= 64 ? 1 : inner <= 256 ? 4 : 8; }
+#define IFMM_SOLVE_LAUNCH(KERN, k, nw, ntask, st, ...)                                                           \
+  do {                                                                                                         \
+    const dim3 g_((unsigned)(ntask));                                                                          \
+    const int sk_ = (k) == 1 ? 1 : (k) <= 4 ? 4 : 8;                                                           \
+    if (sk_ == 1 && (nw) == 1) hipLaunchKernelGGL((KERN<1, 1>), g_, dim3(64), 0, st, __VA_ARGS__);           \
+    else if (sk_ == 1 && (nw) == 4) hipLaunchKernelGGL((KERN<1, 4>), g_, dim3(256), 0, st, __VA_ARGS__);     \
+    else if (sk_ == 1) hipLaunchKernelGGL((KERN<1, 8>), g_, dim3(512), 0, st, __VA_ARGS__);                  \
+    else if (sk_ == 4 && (nw) == 1) hipLaunchKernelGGL((KERN<4, 1>), g_, dim3(64), 0, st, __VA_ARGS__);      \
+    else if (sk_ == 4 && (nw) == 4) hipLaunchKernelGGL((KERN<4, 4>), g_, dim3(256), 0, st, __VA_ARGS__);     \
+    else if (sk_ == 4) hipLaunchKernelGGL((KERN<4, 8>), g_, dim3(512), 0, st, __VA_ARGS__);                  \
+    else if ((nw) == 1) hipLaunchKernelGGL((KERN<8, 1>), g_, dim3(64), 0, st, __VA_ARGS__);                  \
+    else if ((nw) == 4) hipLaunchKernelGGL((KERN<8, 4>), g_, dim3(256), 0, st, __VA_ARGS__);                 \
+    else hipLaunchKernelGGL((KERN<8, 8>), g_, dim3(512), 0, st, __VA_ARGS__);                                \
+  } while (0)
 
 // The substitution (Alg. 2) as one stream of launches on h.stream over the
 // work vector B (layout P): clears B, then up the levels (colours ascending),
@@ -2187,17 +2197,16 @@ static void enqueue_solve(Handle& h, const SolvePlan& P, double* B, const double
           by_u += 8.0 * ((double)R.M * R.n + k * (R.n + 2.0 * R.M));
         }
       const int tw0 = L.stw_ptr[c], tw1 = L.stw_ptr[c + 1], tu0 = L.stu_ptr[c], tu1 = L.stu_ptr[c + 1];
+      int nmx = 0;  // inner dimension of both forward steps: n
+      for (int e = a; e < b; ++e) nmx = std::max(nmx, L.recs[e].n);
       {
         ProfScope ps(h, "k_solve_fwd_w", 0, by_w);
-        if (tw1 > tw0)
-          launch_solve(k_solve_fwd_w<1>, k_solve_fwd_w<4>, k_solve_fwd_w<8>, k, tw1 - tw0, h.stream, L.d_recs,
-                       st_w + tw0, tw1 - tw0, S);
+        if (tw1 > tw0) IFMM_SOLVE_LAUNCH(k_solve_fwd_w, k, solve_waves(nmx), tw1 - tw0, h.stream, L.d_recs, st_w + tw0, S);
       }
       {
         ProfScope ps(h, "k_solve_fwd_upd", 0, by_u);
         if (tu1 > tu0)
-          launch_solve(k_solve_fwd_upd<1>, k_solve_fwd_upd<4>, k_solve_fwd_upd<8>, k, tu1 - tu0, h.stream, L.d_recs,
-                       L.d_nbrs, st_u + tu0, tu1 - tu0, S);
+          IFMM_SOLVE_LAUNCH(k_solve_fwd_upd, k, solve_waves(nmx), tu1 - tu0, h.stream, L.d_recs, L.d_nbrs, st_u + tu0, S);
       }
     }
     if (l > 2) {
@@ -2237,9 +2246,10 @@ static void enqueue_solve(Handle& h, const SolvePlan& P, double* B, const double
         }
       const int tb0 = L.stb_ptr[c], tb1 = L.stb_ptr[c + 1];
       ProfScope ps(h, "k_solve_bwd", 0, by);
+      int inner = 0;
+      for (int e = a; e < b; ++e) inner = std::max(inner, L.recs[e].M + L.recs[e].r);
       if (tb1 > tb0)
-        launch_solve(k_solve_bwd<1>, k_solve_bwd<4>, k_solve_bwd<8>, k, tb1 - tb0, h.stream, L.d_recs, L.d_nbrs,
-                     st_b + tb0, tb1 - tb0, S);
+        IFMM_SOLVE_LAUNCH(k_solve_bwd, k, solve_waves(inner), tb1 - tb0, h.stream, L.d_recs, L.d_nbrs, st_b + tb0, S);
     }
   }
   hipLaunchKernelGGL(k_perm_out, dim3(TL.n), dim3(NT), 0, h.stream, d_x, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,

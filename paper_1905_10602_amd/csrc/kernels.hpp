@@ -1784,41 +1784,64 @@ __device__ inline double lane_bcast(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// acc[c] += sum_{j < cnt} A[j * lda] * x[j + c * ldx]   (c < kc), for the
-// lane's row (A points at the lane's row; act: the lane's row exists).
+// acc[c] += sign * sum_{j < cnt} A[j * lda] * x[j + c * ldx]   (c < kc, cnt <=
+// 64), for the lane's row (A points at the lane's row; act: the row exists):
+// each lane loads one entry of the vector chunk, readlane broadcasts it.
 template <int SK>
-__device__ inline void wave_gemv_acc(const double* A, int64_t lda, bool act, const double* x, int64_t ldx, int cnt,
-                                     int kc, int lane, double* acc) {
-  for (int j0 = 0; j0 < cnt; j0 += 64) {
-    const int m = min(64, cnt - j0);
-    double xv[SK];
+__device__ inline void wave_gemv_chunk(const double* A, int64_t lda, bool act, const double* x, int64_t ldx, int cnt,
+                                       int kc, int lane, double sign, double* acc) {
+  double xv[SK];
 #pragma unroll
-    for (int c = 0; c < SK; ++c) xv[c] = (lane < m && c < kc) ? x[j0 + lane + (int64_t)c * ldx] : 0.0;
-    const double* Aj = A + (int64_t)j0 * lda;
-    if (m == 64) {
+  for (int c = 0; c < SK; ++c) xv[c] = (lane < cnt && c < kc) ? sign * x[lane + (int64_t)c * ldx] : 0.0;
+  if (cnt == 64) {
 #pragma unroll 16
-      for (int jj = 0; jj < 64; ++jj) {
-        const double a = act ? Aj[(int64_t)jj * lda] : 0.0;
+    for (int jj = 0; jj < 64; ++jj) {
+      const double a = act ? A[(int64_t)jj * lda] : 0.0;
 #pragma unroll
-        for (int c = 0; c < SK; ++c) acc[c] = fma(a, lane_bcast(xv[c], jj), acc[c]);
-      }
-    } else {
-      for (int jj = 0; jj < m; ++jj) {
-        const double a = act ? Aj[(int64_t)jj * lda] : 0.0;
+      for (int c = 0; c < SK; ++c) acc[c] = fma(a, lane_bcast(xv[c], jj), acc[c]);
+    }
+  } else {
+    for (int jj = 0; jj < cnt; ++jj) {
+      const double a = act ? A[(int64_t)jj * lda] : 0.0;
 #pragma unroll
-        for (int c = 0; c < SK; ++c) acc[c] = fma(a, lane_bcast(xv[c], jj), acc[c]);
-      }
+      for (int c = 0; c < SK; ++c) acc[c] = fma(a, lane_bcast(xv[c], jj), acc[c]);
     }
   }
 }
 
+// One segment of a tile's inner dimension, split into 64-column chunks that
+// the NW waves of the workgroup take in turn (g counts chunks over segments).
+template <int SK, int NW>
+__device__ inline void seg_gemv(const double* A, int64_t lda, bool act, const double* x, int64_t ldx, int len, int kc,
+                                int lane, int wave, double sign, int& g, double* acc) {
+  for (int j0 = 0; j0 < len; j0 += 64, ++g)
+    if (g % NW == wave)
+      wave_gemv_chunk<SK>(A + (int64_t)j0 * lda, lda, act, x + j0, ldx, min(64, len - j0), kc, lane, sign, acc);
+}
+
+// Sum of the waves' partial accumulators into wave 0 (returns true there).
+template <int SK, int NW>
+__device__ inline bool wg_reduce_acc(double (*red)[SK][64], int lane, int wave, double* acc) {
+  if (NW == 1) return true;
+#pragma unroll
+  for (int c = 0; c < SK; ++c) red[wave][c][lane] = acc[c];
+  __syncthreads();
+  if (wave != 0) return false;
+#pragma unroll
+  for (int c = 0; c < SK; ++c) {
+    double v = 0.0;
+    for (int q = 0; q < NW; ++q) v += red[q][c][lane];
+    acc[c] = v;
+  }
+  return true;
+}
+
 // forward, step 1: w = E_t. x_i (rows < n kept in W), z_i += E_b. x_i
-template <int SK>
-__global__ void __launch_bounds__(NT) k_solve_fwd_w(const ElimRec* recs, const STask* tasks, int ntask, SolveView S) {
-  const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  if (t >= ntask) return;
-  const STask T = tasks[t];
+template <int SK, int NW>
+__global__ void __launch_bounds__(64 * NW) k_solve_fwd_w(const ElimRec* recs, const STask* tasks, SolveView S) {
+  __shared__ double red[NW][SK][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const STask T = tasks[blockIdx.x];
   const ElimRec R = recs[T.rec];
   const int n = R.n, r = R.r, d = R.d, k = S.k;
   const int row = T.r0 + lane;
@@ -1831,8 +1854,9 @@ __global__ void __launch_bounds__(NT) k_solve_fwd_w(const ElimRec* recs, const S
     double acc[SK];
 #pragma unroll
     for (int c = 0; c < SK; ++c) acc[c] = 0.0;
-    wave_gemv_acc<SK>(R.lu + (act ? row : 0), d, act, xi + (int64_t)c0 * n, n, n, kc, lane, acc);
-    if (act) {
+    int g = 0;
+    seg_gemv<SK, NW>(R.lu + (act ? row : 0), d, act, xi + (int64_t)c0 * n, n, n, kc, lane, wave, 1.0, g, acc);
+    if (wg_reduce_acc<SK, NW>(red, lane, wave, acc) && act) {
 #pragma unroll
       for (int c = 0; c < SK; ++c)
         if (c < kc) {
@@ -1840,25 +1864,25 @@ __global__ void __launch_bounds__(NT) k_solve_fwd_w(const ElimRec* recs, const S
           else zi[row - n + (int64_t)(c0 + c) * r] += acc[c];
         }
     }
+    if (NW > 1) __syncthreads();
   }
 }
 
 // forward, step 2: rows of the neighbours -= L w (the rows of a tile may
 // belong to several neighbours; same-colour nodes share no neighbour)
-template <int SK>
-__global__ void __launch_bounds__(NT) k_solve_fwd_upd(const ElimRec* recs, const ElimNbr* nbrs, const STask* tasks,
-                                                      int ntask, SolveView S) {
-  const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  if (t >= ntask) return;
-  const STask T = tasks[t];
+template <int SK, int NW>
+__global__ void __launch_bounds__(64 * NW) k_solve_fwd_upd(const ElimRec* recs, const ElimNbr* nbrs,
+                                                           const STask* tasks, SolveView S) {
+  __shared__ double red[NW][SK][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const STask T = tasks[blockIdx.x];
   const ElimRec R = recs[T.rec];
   const int n = R.n, k = S.k;
   const int row = T.r0 + lane;
   const bool act = row < R.M;
   double* tgt = nullptr;
   int ldt = 1;
-  if (act)
+  if (act && wave == 0)
     for (int e = 0; e < R.nnb; ++e) {
       const ElimNbr B = nbrs[R.nb_begin + e];
       if (row >= B.off && row < B.off + B.m) {
@@ -1872,23 +1896,25 @@ __global__ void __launch_bounds__(NT) k_solve_fwd_upd(const ElimRec* recs, const
     double acc[SK];
 #pragma unroll
     for (int c = 0; c < SK; ++c) acc[c] = 0.0;
-    wave_gemv_acc<SK>(R.L + (act ? row : 0), R.M, act, wt + (int64_t)c0 * n, n, n, kc, lane, acc);
-    if (tgt) {
+    int g = 0;
+    seg_gemv<SK, NW>(R.L + (act ? row : 0), R.M, act, wt + (int64_t)c0 * n, n, n, kc, lane, wave, 1.0, g, acc);
+    if (wg_reduce_acc<SK, NW>(red, lane, wave, acc) && tgt) {
 #pragma unroll
       for (int c = 0; c < SK; ++c)
         if (c < kc) tgt[(int64_t)(c0 + c) * ldt] -= acc[c];
     }
+    if (NW > 1) __syncthreads();
   }
 }
 
-// backward: x_i = w - G x_nbrs + E_tb y_i
-template <int SK>
-__global__ void __launch_bounds__(NT) k_solve_bwd(const ElimRec* recs, const ElimNbr* nbrs, const STask* tasks,
-                                                  int ntask, SolveView S) {
-  const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  if (t >= ntask) return;
-  const STask T = tasks[t];
+// backward: x_i = w - (G x_nbrs - E_tb y_i), the inner dimension running over
+// the neighbours' blocks of G and then E_tb
+template <int SK, int NW>
+__global__ void __launch_bounds__(64 * NW) k_solve_bwd(const ElimRec* recs, const ElimNbr* nbrs, const STask* tasks,
+                                                       SolveView S) {
+  __shared__ double red[NW][SK][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const STask T = tasks[blockIdx.x];
   const ElimRec R = recs[T.rec];
   const int n = R.n, r = R.r, d = R.d, k = S.k;
   const int row = T.r0 + lane;
@@ -1898,21 +1924,24 @@ __global__ void __launch_bounds__(NT) k_solve_bwd(const ElimRec* recs, const Eli
   double* xi = S.X + S.xo[R.node] * k;
   for (int c0 = 0; c0 < k; c0 += SK) {
     const int kc = min(SK, k - c0);
-    double g[SK], e[SK];
+    double acc[SK];
 #pragma unroll
-    for (int c = 0; c < SK; ++c) { g[c] = 0.0; e[c] = 0.0; }
+    for (int c = 0; c < SK; ++c) acc[c] = 0.0;
+    int g = 0;
     for (int q = 0; q < R.nnb; ++q) {
       const ElimNbr B = nbrs[R.nb_begin + q];
       if (B.m == 0) continue;
       const double* xq = (B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k) + (int64_t)c0 * B.m;
-      wave_gemv_acc<SK>(R.U + (act ? row : 0) + (int64_t)B.off * n, n, act, xq, B.m, B.m, kc, lane, g);
+      seg_gemv<SK, NW>(R.U + (act ? row : 0) + (int64_t)B.off * n, n, act, xq, B.m, B.m, kc, lane, wave, 1.0, g, acc);
     }
-    wave_gemv_acc<SK>(R.lu + (act ? row : 0) + (int64_t)n * d, d, act, yi + (int64_t)c0 * r, r, r, kc, lane, e);
-    if (act) {
+    seg_gemv<SK, NW>(R.lu + (act ? row : 0) + (int64_t)n * d, d, act, yi + (int64_t)c0 * r, r, r, kc, lane, wave, -1.0,
+                     g, acc);
+    if (wg_reduce_acc<SK, NW>(red, lane, wave, acc) && act) {
 #pragma unroll
       for (int c = 0; c < SK; ++c)
-        if (c < kc) xi[row + (int64_t)(c0 + c) * n] = wt[row + (int64_t)(c0 + c) * n] - g[c] + e[c];
+        if (c < kc) xi[row + (int64_t)(c0 + c) * n] = wt[row + (int64_t)(c0 + c) * n] - acc[c];
     }
+    if (NW > 1) __syncthreads();
   }
 }
 
