@@ -174,7 +174,8 @@ def run_form(name, pts, dg, args, bt, xt, F5, F4, f_dev, max_steps, warmup):
     def step():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        h = IFMM(pts, args.eps, args.sigma, diag=dg, leaf_max=64, precision="mixed" if mixed else "fp64")
+        h = IFMM(pts, args.eps, args.sigma, diag=dg, leaf_max=64, precision="mixed" if mixed else "fp64",
+                 bottom_level=args.bottom_level, colouring=args.colouring)
         if theta is not None:
             h.set_rank_model(theta)
         t1 = time.perf_counter()
@@ -207,7 +208,15 @@ def run_form(name, pts, dg, args, bt, xt, F5, F4, f_dev, max_steps, warmup):
     stats = h.stats()
     x_first = xt[0].cpu().numpy().copy()
     gm = {}
-    # e_res on the matrix the IFMM factorises (A~ through its exact FMM form)
+    # e_res on the matrix the IFMM factorises (A~ through its exact FMM form,
+    # on a tree of the IFMM's depth: with a coarser bottom level the leaves
+    # hold more points and A~ has more exact near-field blocks)
+    F4_own = None
+    if F4 is not None and stats.get("depth") != F4.stats().get("depth"):
+        from paper_1905_10602_amd import FMM
+        leaf = max(L["n_max"] for L in stats["levels"] if L["level"] == stats["depth"])
+        F4_own = F4 = FMM(pts, dg, cheb_order=4, leaf_max=int(leaf))
+        gm["e_res_tree_depth"] = F4.stats().get("depth")
     if F4 is not None:
         ys = [F4.matvec(xt[k].contiguous()) for k in range(args.nrhs)]
         gm["e_res"] = max(float(torch.linalg.norm(ys[k] - bt[k]) / torch.linalg.norm(bt[k])) for k in range(args.nrhs))
@@ -245,6 +254,8 @@ def run_form(name, pts, dg, args, bt, xt, F5, F4, f_dev, max_steps, warmup):
     gm["eager_solve_equals_graph"] = bool(torch.equal(xe, xt))
     stats = h.stats()
     h.close()
+    if F4_own is not None:
+        F4_own.close()
     med = lambda key: statistics.median(t[key] for t in times)
     out = {"steps_timed": len(times), "factor_s": med("factor_s"), "solve_ms_per_rhs": med("solve_s") * 1e3 / args.nrhs,
            "build_s": med("build_s"), "step_s": med("step_s"), "step_s_all": [round(t["step_s"], 3) for t in times],
@@ -378,6 +389,9 @@ def main():
     ap.add_argument("--reserve-s", type=float, default=-1.0,
                     help="seconds kept free for the legs after the timed mixed steps (default: estimated)")
     ap.add_argument("--reserve-gmres-s", type=float, default=20.0)
+    ap.add_argument("--bottom-level", type=int, default=0,
+                    help="IFMM depth: 0 = from leaves of <= 64 points, -1 = the cost model, >= 2 = forced")
+    ap.add_argument("--colouring", choices=("stride", "lookback"), default="stride")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -471,7 +485,7 @@ def main():
         "config": {"workload": f"ellipsoid (1,0.7,0.3) + 5% jitter, N={N}, Laplace 1/(4 pi r), eps={args.eps}, "
                                f"sigma={args.sigma}, leaf<=64, Chebyshev 4^3, {args.nrhs} RHS; value = factor s of the "
                                f"{'mixed-precision learned-rank' if lead == 'mixed' else lead} form",
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "bottom_level": args.bottom_level, "colouring": args.colouring},
         "factor_s": R.get("factor_s"), "solve_ms_per_rhs": R.get("solve_ms_per_rhs"),
         "steps_requested": args.steps, "warmup_requested": args.warmup,
         "forms": res,

@@ -228,6 +228,8 @@ ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
                   ",\"sketches\":" + std::to_string(h.stat_sketch) +
                   ",\"sketches_rejected\":" + std::to_string(h.stat_sketch_rejected) +
                   ",\"sketches_narrow\":" + std::to_string(h.stat_sketch_narrow) +
+                  ",\"full_decompositions\":" + std::to_string(h.stat_full) +
+                  ",\"sketch_columns\":" + std::to_string(h.stat_sketch_cols) +
                   ",\"rank_predictions\":" + std::to_string(h.stat_predicted) +
                   ",\"t_sync\":" + std::to_string(h.t_sync) +
                   ",\"top_tau\":" + std::to_string(h.top_tau) + ",\"colouring\":" + std::to_string(h.colouring) +

@@ -337,10 +337,13 @@ static int eig_values(Handle& h, const std::vector<EigTask>& T, const EigTask* d
   }
   HIPCHK(hipMemcpyAsync(d_trd, held(h, tt), tt.size() * sizeof(TrdTask), hipMemcpyHostToDevice, st));
   const unsigned nb = (unsigned)big.size();
+  double fl = 0;
+  for (int32_t a : big) fl += 4.0 / 3.0 * (double)T[a].n * T[a].n * T[a].n;
+  ProfScope ps(h, "group:trd_multi", fl, 0, side);
   hipLaunchKernelGGL(k_trd_start, dim3(nb), dim3(NT), 0, st, d_trd);
   auto tiles = [&](int k) {
     const int m = nmax - k - 2, b = (m + 63) / 64;
-    if (m > 0) hipLaunchKernelGGL(k_trd_tiles, dim3((unsigned)(b * b), nb), dim3(NT), 0, st, d_trd, k);
+    if (m > 0) hipLaunchKernelGGL(k_trd_tiles, dim3((unsigned)(b * (b + 1) / 2), nb), dim3(NT), 0, st, d_trd, k);
   };
   tiles(-1);
   for (int k = 0; k + 2 < nmax; ++k) {
@@ -1492,6 +1495,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       full_ids.push_back(fb_of[a] >= 0 ? sk_ids[fb_of[a]] : r2_ids[-1 - fb_of[a]]);
       fullT.push_back(fb[a]);
     }
+    h.stat_full += (int64_t)full_ids.size();  // every decomposition that was not a sketch in the end
+    for (int e : sk_ids) h.stat_sketch_cols += skw[e];
     std::vector<int32_t> keep_ids;
     std::vector<EigTask> keepE;
     std::vector<SkTask> keepT;
@@ -1981,6 +1986,7 @@ int factor(Handle& h, std::string& err) {
   h.prof_level = std::getenv("IFMM_PROF_LEVEL") != nullptr;
   if (const char* e = std::getenv("IFMM_SKETCH_MIN")) h.sketch_min = std::max(1, std::atoi(e));
   h.stat_sketch = h.stat_sketch_rejected = h.stat_sketch_narrow = 0;
+  h.stat_full = h.stat_sketch_cols = 0;
   h.t_sync = 0;
   h.t_h2d = 0;
   h.rec_X.clear();

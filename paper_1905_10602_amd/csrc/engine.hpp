@@ -198,6 +198,8 @@ struct Handle {
   char* meta2b = nullptr;
   int64_t meta2b_bytes = 0;
   int64_t stat_sketch = 0, stat_sketch_rejected = 0, stat_sketch_narrow = 0;
+  int64_t stat_full = 0;         // full eigen-decompositions of recompressions (incl. fall-backs of rejected sketches)
+  int64_t stat_sketch_cols = 0;  // columns of all first-round sketches
   bool record_ranks = false;
   bool prof_level = false;  // IFMM_PROF_LEVEL: profile classes keyed "name@level"
   int cur_level = 0;

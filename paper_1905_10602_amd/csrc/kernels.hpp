@@ -300,18 +300,28 @@ __global__ void __launch_bounds__(NT) k_trd_start(const TrdTask* tasks) {
   trd_reflector(t.A + 1, m, t.W + n, t.W + 2 * n, 0, vn);
 }
 
-// Tiled pass after step k (k = -1: the first product only) over the trailing
-// matrix S = A[k+2:, k+2:] (order m = n - k - 2): S -= 2 (v w^T + w v^T) with
-// the step's v, w (already in S's coordinates), and part[tj][i] = sum over the
-// tile's columns of S[i, j] vn[j].  grid (tiles of the largest S, task).
+// Tiled pass after step k (k = -1: the first product only) over the lower
+// triangle of the trailing matrix S = A[k+2:, k+2:] (order m = n - k - 2; the
+// upper triangle is never read): S -= 2 (v w^T + w v^T) with the step's v, w
+// (already in S's coordinates), and the partial sums of p = S vn with S
+// symmetric.  A tile (ti >= tj) contributes S_tile vn_J to the rows of block
+// ti (slot tj of part) and S_tile^T vn_I to the rows of block tj (slot ti),
+// so every (row, slot) is written by exactly one tile; a diagonal tile adds
+// both into slot ti.  grid (lower tiles of the largest S, task).
 __global__ void __launch_bounds__(NT) k_trd_tiles(const TrdTask* tasks, int k) {
   __shared__ double red[NT / 64][64];
+  __shared__ double colsum[64];
   const TrdTask t = tasks[blockIdx.y];
   const int n = t.n, m = n - k - 2;
   if (n < 3 || k > n - 3 || m <= 0) return;
   const int nb = (m + 63) / 64;
-  if ((int)blockIdx.x >= nb * nb) return;
-  const int ti = blockIdx.x % nb, tj = blockIdx.x / nb;
+  const int tile = blockIdx.x;
+  if (tile >= nb * (nb + 1) / 2) return;
+  int ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > tile) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+  const int tj = tile - ti * (ti + 1) / 2;
+  const bool diag = ti == tj;
   const int I = 64 * ti, J = 64 * tj;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double* v = t.vec;
@@ -319,24 +329,34 @@ __global__ void __launch_bounds__(NT) k_trd_tiles(const TrdTask* tasks, int k) {
   const double* vn = t.vec + 2 * n;
   double* S = t.A + (k + 2) + (int64_t)(k + 2) * n;
   const int i = I + lane;
+  const bool row_ok = i < m;
+  const double vi = row_ok ? v[i] : 0.0, wi = row_ok ? w[i] : 0.0, vni = row_ok ? vn[i] : 0.0;
   double acc = 0.0;
-  if (i < m) {
-    const double vi = v[i], wi = w[i];
-    for (int jj = wave; jj < 64; jj += NT / 64) {
-      const int j = J + jj;
-      if (j >= m) break;
+  for (int jj = wave; jj < 64; jj += NT / 64) {
+    const int j = J + jj;
+    if (j >= m) break;  // uniform over the wave
+    double tr = 0.0;    // this lane's term of (S^T vn_I)[j]
+    if (row_ok && (!diag || i >= j)) {
       double* c = S + i + (int64_t)j * n;
       const double sv = *c - 2.0 * (vi * w[j] + wi * v[j]);
       *c = sv;
       acc += sv * vn[j];
+      if (!diag || i > j) tr = sv * vni;
     }
+    for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
+    if (lane == 0) colsum[jj] = tr;
   }
   red[wave][lane] = acc;
   __syncthreads();
-  if (wave == 0 && i < m) {
+  if (wave == 0) {
     double a = 0.0;
     for (int q = 0; q < NT / 64; ++q) a += red[q][lane];
-    t.part[(int64_t)tj * n + i] = a;
+    if (diag) {
+      if (row_ok) t.part[(int64_t)ti * n + i] = a + colsum[lane];
+    } else {
+      if (row_ok) t.part[(int64_t)tj * n + i] = a;
+      if (J + lane < m) t.part[(int64_t)ti * n + J + lane] = colsum[lane];
+    }
   }
 }
 

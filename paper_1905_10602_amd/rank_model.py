@@ -25,7 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT = os.path.join(HERE, "rank_model_laplace.npz")
 
 
-def training_geometries(count=8, n_values=(65536, 131072), base_seed=5001):
+def training_geometries(count=16, n_values=(65536, 131072, 262144), base_seed=5001):
     """(name, points, diag) of the training set: spheres, ellipsoids with random
     semi-axes in [0.5, 2] (plus 5 % jitter) and cube surfaces, seeds from 5001."""
     sys.path.insert(0, os.path.dirname(HERE))
@@ -94,14 +94,18 @@ def load(path=DEFAULT):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT)
-    ap.add_argument("--count", type=int, default=8)
+    ap.add_argument("--count", type=int, default=16)
+    ap.add_argument("--records", default=None, help="also save the recorded samples (npz) here")
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--tau", type=float, default=0.9)
     a = ap.parse_args(argv)
     X, t = record(training_geometries(a.count), log=lambda s: print(s, flush=True))
+    if a.records:
+        np.savez_compressed(a.records, X=X, t=t)
     th, hist = train(X, t, steps=a.steps, tau=a.tau)
     meta = {"samples": int(len(t)), "steps": a.steps, "tau": a.tau, "loss_first": float(hist[0]),
-            "loss_last": float(hist[-1]), "features": RANK_FEATURES}
+            "loss_last": float(hist[-1]), "features": RANK_FEATURES, "geometries": a.count,
+            "seeds": f"5001-{5000 + a.count}", "n_values": [65536, 131072, 262144]}
     save(a.out, th, meta)
     print(json.dumps(meta), flush=True)
 
