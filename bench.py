@@ -5,7 +5,9 @@ operators, colour-by-colour elimination, top LU) + ifmm_solve of 8
 right-hand sides, all inputs resident before the timed region (the solve
 takes device pointers).  Workload: N = 1,048,576 points on the ellipsoid with
 semi-axes (1, 0.7, 0.3) plus 5 % uniform jitter, Laplace kernel, eps = 1e-6,
-sigma = 3, leaves of at most 64 points, Chebyshev 4^3 operators.
+sigma = 3, Chebyshev 4^3 operators; the IFMM's depth (bottom level) is the
+one the library's cost model picks among the depth with leaves of at most 64
+points (7 here) and the two coarser ones (Sec. 5.2 tunes it the same way).
 
 Forms on the same GPU:
   mixed      FP32 matrix-core Schur and basis products, sketched recompression
@@ -361,6 +363,63 @@ def roofline_more(stats, mixed):
     return out
 
 
+def bem_comparison(args):
+    """The FMBEM workload (Laplace single layer on the unit sphere, icosphere of
+    327,680 panels, f = 1/|x - (0,0,0.5)|): FGMRES(50) to 1e-8 with the
+    Chebyshev 5^3 FMM product and no preconditioner, BD at the leaf level and
+    one level coarser (Sec. 4.3), and the IFMM (eps = 1e-3, sigma = 3) in FP64
+    and in the mixed form.  One JSON line: iterations, set-up and solve times,
+    density error against the closed form."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1905_10602_amd import BD, FMM, IFMM
+    v, f = synth.icosphere(7)
+    a_ = v[f[:, 0]]
+    b_ = v[f[:, 1]]
+    c_ = v[f[:, 2]]
+    cen = (a_ + b_ + c_) / 3.0
+    area = 0.5 * np.linalg.norm(np.cross(b_ - a_, c_ - a_), axis=1)
+    st = np.sqrt(area / np.pi) / 2.0
+    x0 = np.array([0.0, 0.0, 0.5])
+    rhs = 1.0 / np.linalg.norm(cen - x0, axis=1)
+    exact = (1.0 - x0 @ x0) / np.linalg.norm(cen - x0, axis=1) ** 3
+    N = cen.shape[0]
+    log(f"BEM: {N} panels")
+    F = FMM(cen, st, weights=area, cheb_order=5, leaf_max=64)
+    bt = torch.from_numpy(rhs).cuda()
+    res = {"panels": N, "fmm_depth": F.stats()["depth"]}
+
+    def run(name, pre, setup_s):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, it, rr = F.gmres(bt, precond=pre, tol=1e-8, restart=50, maxit=2000, allow_noconv=True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        xs = x.cpu().numpy()
+        res[name] = {"iterations": it, "relres": rr, "setup_s": setup_s, "gmres_s": ts, "total_s": setup_s + ts,
+                     "density_error": float(np.linalg.norm(xs - exact) / np.linalg.norm(exact))}
+        log(f"BEM {name}: {json.dumps(res[name])}")
+
+    run("none", None, 0.0)
+    for coarser in (0, 1):
+        t0 = time.perf_counter()
+        lvl = F.stats()["depth"] - coarser
+        bd = BD(cen, st, weights=area, level=lvl, leaf_max=64)
+        torch.cuda.synchronize()
+        run(f"BD_level{lvl}", bd, time.perf_counter() - t0)
+        bd.close()
+    for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        h = IFMM(cen, 1e-3, 3, diag=st, weights=area, leaf_max=64, precision=prec, bottom_level=args.bottom_level)
+        h.factor()
+        torch.cuda.synchronize()
+        run(f"IFMM_eps1e-3_{prec}", h, time.perf_counter() - t0)
+        res[f"IFMM_eps1e-3_{prec}"]["depth"] = h.depth()
+        h.close()
+    print(json.dumps({"bem_comparison": res}), flush=True)
+
+
 def copy_calibration():
     """Reference copy for the HBM traffic counters: three copies of 256 MiB of FP64."""
     import torch
@@ -389,12 +448,14 @@ def main():
     ap.add_argument("--reserve-s", type=float, default=-1.0,
                     help="seconds kept free for the legs after the timed mixed steps (default: estimated)")
     ap.add_argument("--reserve-gmres-s", type=float, default=20.0)
-    ap.add_argument("--bottom-level", type=int, default=0,
-                    help="IFMM depth: 0 = from leaves of <= 64 points, -1 = the cost model, >= 2 = forced")
+    ap.add_argument("--bottom-level", type=int, default=-1,
+                    help="IFMM depth: -1 = chosen by the cost model among the depth of leaves of <= 64 points and "
+                         "the two coarser ones (default), 0 = leaves of <= 64 points, >= 2 = forced")
     ap.add_argument("--colouring", choices=("stride", "lookback"), default="stride")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--bem", action="store_true", help="only the FMBEM preconditioner comparison (327,680 panels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: one GPU only (--gpus 1); sharding a factorisation across GPUs is not implemented",
@@ -402,6 +463,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.bem:
+        bem_comparison(args)
         return
     os.environ["IFMM_PROF"] = "1"
     os.environ.setdefault("IFMM_LOG", "1")
@@ -483,7 +547,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32mfma" if lead != "fp64" else "f64",
         "data": "synthetic",
         "config": {"workload": f"ellipsoid (1,0.7,0.3) + 5% jitter, N={N}, Laplace 1/(4 pi r), eps={args.eps}, "
-                               f"sigma={args.sigma}, leaf<=64, Chebyshev 4^3, {args.nrhs} RHS; value = factor s of the "
+                               f"sigma={args.sigma}, depth {R.get('depth')} (bottom level "
+                               f"{'by the cost model' if args.bottom_level == -1 else args.bottom_level}; leaves of <= 64 "
+                               f"points at depth 7), Chebyshev 4^3, {args.nrhs} RHS; value = factor s of the "
                                f"{'mixed-precision learned-rank' if lead == 'mixed' else lead} form",
                    "parallelism": "single GPU", "bottom_level": args.bottom_level, "colouring": args.colouring},
         "factor_s": R.get("factor_s"), "solve_ms_per_rhs": R.get("solve_ms_per_rhs"),

@@ -299,6 +299,39 @@ ifmm_status fmm_stats(const fmm_handle* h, char* json, int64_t cap);
 
 void fmm_destroy(fmm_handle* h);
 
+/* ---- block-diagonal preconditioner (BD, Sec. 4.3) ---------------------------
+ * M^-1 = blockdiag(A_bb^-1) over the boxes b of level l_BD of the uniform
+ * octree (same root cube as the IFMM): A_bb is the dense block of A over the
+ * points of box b (A_ij = K(p_i, p_j) w_j, A_ii = diag_i), inverted on the
+ * device by a blocked LU with partial pivoting.  The paper's leaf BD uses the
+ * leaf level; a coarser l_BD (BDbot l_BD) widens the blocks.
+ */
+typedef struct bd_handle bd_handle;
+
+/*
+ * Builds BD (same geometry arguments as ifmm_build).
+ *   level     l_BD in [2, 10], or 0 = the level where every box holds at most
+ *             leaf_max points; boxes may hold at most 4096 points
+ *   stream    hipStream_t for all device work, or NULL (a library-owned stream
+ *             ordered with the null stream)
+ * Errors: IFMM_EINVAL (bad argument, coincident points, a box too large),
+ * IFMM_ENONFINITE, IFMM_ESINGULAR (a singular block), IFMM_ENOMEM, IFMM_EDEVICE.
+ */
+ifmm_status bd_build(const double* points, int64_t n, const double* weights, const double* diag, double diag_scalar,
+                     int32_t level, int32_t leaf_max, void* stream, bd_handle** out);
+
+/* z = M^-1 r (length N, host or device pointers; r and z may not alias). */
+ifmm_status bd_apply(bd_handle* h, const double* r, double* z, int32_t on_device);
+
+/* fmm_gmres (same arguments and results) with BD as the right preconditioner. */
+ifmm_status fmm_gmres_bd(fmm_handle* h, const double* b, bd_handle* bd, double tol, int32_t restart, int32_t maxit,
+                         double* x, int32_t on_device, int32_t* iters, double* relres);
+
+/* JSON: N, level, boxes, largest box, bytes of the stored inverses, build time. */
+ifmm_status bd_stats(const bd_handle* h, char* json, int64_t cap);
+
+void bd_destroy(bd_handle* h);
+
 /*
  * The FMBEM driver in one call (Alg. 4): piecewise-constant collocation,
  * A_ij = areas_j / (4 pi |c_i - c_j|), A_ii = self_terms_i, solved by

@@ -23,6 +23,10 @@ struct fmm_handle {
   ifmm::FmmHandle h;
 };
 
+struct bd_handle {
+  ifmm::BdHandle h;
+};
+
 namespace ifmm {
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
@@ -540,6 +544,98 @@ ifmm_status fmm_gmres(fmm_handle* F, const double* b, ifmm_handle* P, double tol
   if (rc) return fail(rc, err);
   if (!(*relres <= tol)) return fail(IFMM_ENOCONV, "GMRES did not reach the tolerance");
   return IFMM_OK;
+}
+
+ifmm_status bd_build(const double* points, int64_t n, const double* weights, const double* diag, double diag_scalar,
+                     int32_t level, int32_t leaf_max, void* stream, bd_handle** out) {
+  ifmm::set_error("");
+  if (!out) return fail(IFMM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!points) return fail(IFMM_EINVAL, "points is NULL");
+  if (n < 1) return fail(IFMM_EINVAL, "n must be >= 1");
+  if (level != 0 && (level < 2 || level > 10)) return fail(IFMM_EINVAL, "level must be 0 (from leaf_max) or in [2, 10]");
+  if (leaf_max < 1) return fail(IFMM_EINVAL, "leaf_max must be >= 1");
+  if (!diag && !std::isfinite(diag_scalar)) return fail(IFMM_ENONFINITE, "non-finite diag_scalar");
+  bd_handle* B = new (std::nothrow) bd_handle();
+  if (!B) return fail(IFMM_ENOMEM, "host allocation failed");
+  B->h.stream = (hipStream_t)stream;
+  std::string err;
+  int rc;
+  try {
+    rc = ifmm::bd_setup(B->h, points, n, weights, diag, diag_scalar, level, leaf_max, err);
+  } catch (const std::bad_alloc&) {
+    rc = IFMM_ENOMEM;
+    err = "host allocation failed";
+  }
+  if (rc) {
+    ifmm::bd_release(B->h);
+    delete B;
+    return fail(rc, err);
+  }
+  *out = B;
+  return IFMM_OK;
+}
+
+ifmm_status bd_apply(bd_handle* B, const double* r, double* z, int32_t on_device) {
+  ifmm::set_error("");
+  if (!B || !r || !z) return fail(IFMM_EINVAL, "bad arguments");
+  if (r == z) return fail(IFMM_EINVAL, "r and z may not alias");
+  ifmm::BdHandle& h = B->h;
+  std::string err;
+  int rc;
+  if (on_device) {
+    rc = ifmm::bd_apply(h, r, z, err);
+  } else {
+    Staged st;
+    if (hipMalloc((void**)&st.d, (size_t)(2 * h.N) * 8) != hipSuccess) return fail(IFMM_ENOMEM, "device allocation failed");
+    if (hipMemcpy(st.d, r, (size_t)h.N * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(IFMM_EDEVICE, "copy failed");
+    rc = ifmm::bd_apply(h, st.d, st.d + h.N, err);
+    if (!rc && hipMemcpy(z, st.d + h.N, (size_t)h.N * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(IFMM_EDEVICE, "copy failed");
+  }
+  if (rc) return fail(rc, err);
+  return IFMM_OK;
+}
+
+ifmm_status fmm_gmres_bd(fmm_handle* F, const double* b, bd_handle* B, double tol, int32_t restart, int32_t maxit,
+                         double* x, int32_t on_device, int32_t* iters, double* relres) {
+  ifmm::set_error("");
+  if (!F || !B || !b || !x || !iters || !relres) return fail(IFMM_EINVAL, "bad arguments");
+  if (restart < 1 || restart > 1000) return fail(IFMM_EINVAL, "restart must lie in [1, 1000]");
+  if (maxit < 0) return fail(IFMM_EINVAL, "maxit must be >= 0");
+  if (!(tol > 0.0)) return fail(IFMM_EINVAL, "tol must be > 0");
+  if (b == x) return fail(IFMM_EINVAL, "b and x may not alias");
+  ifmm::FmmHandle& h = F->h;
+  if (B->h.N != h.N) return fail(IFMM_EINVAL, "preconditioner size differs from the FMM's");
+  std::string err;
+  int rc;
+  if (on_device) {
+    rc = ifmm::fmm_gmres(h, nullptr, b, x, tol, restart, maxit, iters, relres, err, &B->h);
+  } else {
+    Staged st;
+    if (hipMalloc((void**)&st.d, (size_t)(2 * h.N) * 8) != hipSuccess) return fail(IFMM_ENOMEM, "device allocation failed");
+    if (hipMemcpy(st.d, b, (size_t)h.N * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(IFMM_EDEVICE, "copy failed");
+    rc = ifmm::fmm_gmres(h, nullptr, st.d, st.d + h.N, tol, restart, maxit, iters, relres, err, &B->h);
+    if (!rc && hipMemcpy(x, st.d + h.N, (size_t)h.N * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(IFMM_EDEVICE, "copy failed");
+  }
+  if (rc) return fail(rc, err);
+  if (!(*relres <= tol)) return fail(IFMM_ENOCONV, "GMRES did not reach the tolerance");
+  return IFMM_OK;
+}
+
+ifmm_status bd_stats(const bd_handle* B, char* json, int64_t cap) {
+  if (!B || !json || cap < 1) return fail(IFMM_EINVAL, "bad arguments");
+  const ifmm::BdHandle& h = B->h;
+  std::snprintf(json, (size_t)cap, "{\"N\":%lld,\"level\":%d,\"boxes\":%d,\"largest_box\":%d,\"block_bytes\":%lld,\"t_build\":%.6f}",
+                (long long)h.N, h.tree.depth, h.nbox, h.nmax, (long long)(h.block_doubles * 8), h.t_build);
+  return IFMM_OK;
+}
+
+void bd_destroy(bd_handle* B) {
+  if (!B) return;
+  ifmm::bd_release(B->h);
+  delete B;
 }
 
 ifmm_status fmm_stats(const fmm_handle* F, char* json, int64_t cap) {

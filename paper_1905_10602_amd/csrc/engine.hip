@@ -2381,6 +2381,129 @@ int solve_noalloc(Handle& h, const double* rhs, double* x, int k, int64_t ld, st
   return 0;
 }
 
+// ------------------------------------------------------------------ BD preconditioner
+#define BDCHK(x)                                                                    \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) {                                                         \
+      err = std::string(#x) + " failed: " + hipGetErrorString(e_);                  \
+      return -3;                                                                    \
+    }                                                                               \
+  } while (0)
+
+int bd_setup(BdHandle& h, const double* pts, int64_t n, const double* w, const double* diag, double diag_scalar,
+             int level, int leaf_max, std::string& err) {
+  const double t0 = now_s();
+  err = h.tree.build(pts, n, leaf_max, 3, level, 2, 0);
+  if (!err.empty()) return -1;
+  err = h.tree.coincident(pts);
+  if (!err.empty()) return -1;
+  const Level& Lf = h.tree.levels[h.tree.depth];
+  h.N = n;
+  h.nbox = Lf.n;
+  std::vector<int64_t> begin((size_t)Lf.n + 1, 0), off((size_t)Lf.n, 0);
+  int64_t tot = 0;
+  for (int32_t b = 0; b < Lf.n; ++b) {
+    const int nb = (int)(Lf.pt_end[b] - Lf.pt_begin[b]);
+    begin[b] = Lf.pt_begin[b];
+    off[b] = tot;
+    tot += (int64_t)nb * nb;
+    h.nmax = std::max(h.nmax, nb);
+  }
+  begin[Lf.n] = n;
+  if (h.nmax > BD_MAXN) {
+    err = "a box of level " + std::to_string(h.tree.depth) + " holds " + std::to_string(h.nmax) +
+          " points, above the supported " + std::to_string(BD_MAXN) + " (choose a finer level)";
+    return -1;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    err = "no HIP device";
+    return -3;
+  }
+  BDCHK(hipGetDevice(&h.device));
+  if (!h.stream) {
+    BDCHK(hipStreamCreate(&h.stream));
+    h.own_stream = true;
+  }
+  std::vector<double> P(3 * n), W(n), Dg(n);
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t p = h.tree.perm[t];
+    for (int e = 0; e < 3; ++e) P[3 * t + e] = pts[3 * p + e];
+    W[t] = w ? w[p] : 1.0;
+    Dg[t] = diag ? diag[p] : diag_scalar;
+    if (!std::isfinite(W[t]) || !std::isfinite(Dg[t])) {
+      err = "non-finite weight or diagonal entry";
+      return -5;
+    }
+  }
+  auto up = [&](auto** d, const auto& v) -> int {
+    BDCHK(hipMalloc((void**)d, std::max<size_t>(v.size(), 1) * sizeof(v[0])));
+    if (!v.empty()) BDCHK(hipMemcpy(*d, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice));
+    return 0;
+  };
+  int rc;
+  if ((rc = up(&h.d_pts, P)) || (rc = up(&h.d_w, W)) || (rc = up(&h.d_diag, Dg)) || (rc = up(&h.d_perm, h.tree.perm)) ||
+      (rc = up(&h.d_pt_begin, begin)))
+    return rc;
+  // per box: D (overwritten by its LU), X (becomes D^-1), panel inverses
+  int64_t dinv = 0;
+  std::vector<int64_t> doff((size_t)Lf.n);
+  for (int32_t b = 0; b < Lf.n; ++b) {
+    const int nb = (int)(begin[b + 1] - begin[b]);
+    doff[b] = dinv;
+    dinv += (int64_t)((nb + BLU_NB - 1) / BLU_NB) * 2 * 4096;
+  }
+  h.block_doubles = tot;
+  BDCHK(hipMalloc((void**)&h.d_mem, (size_t)std::max<int64_t>(2 * tot, 1) * 8));
+  BDCHK(hipMalloc((void**)&h.d_dinv, (size_t)std::max<int64_t>(dinv, 1) * 8));
+  BDCHK(hipMalloc((void**)&h.d_piv, (size_t)std::max<int64_t>(n, 1) * 4));
+  BDCHK(hipMalloc((void**)&h.d_info, (size_t)std::max(Lf.n, 1) * 4));
+  std::vector<BluTask> tasks((size_t)Lf.n);
+  for (int32_t b = 0; b < Lf.n; ++b) {
+    const int nb = (int)(begin[b + 1] - begin[b]);
+    tasks[b] = {h.d_mem + off[b], h.d_mem + tot + off[b], h.d_piv + begin[b], h.d_info + b, h.d_dinv + doff[b], nb, nb};
+  }
+  if ((rc = up((BluTask**)&h.d_tasks, tasks))) return rc;
+  if (Lf.n > 0) {
+    const BluTask* dt = (const BluTask*)h.d_tasks;
+    hipLaunchKernelGGL(k_bd_assemble, dim3((unsigned)((h.nmax + 63) / 64), (unsigned)Lf.n), dim3(NT), 0, h.stream,
+                       h.d_pts, h.d_w, h.d_diag, h.d_pt_begin, dt);
+    enqueue_blocked_lu(dt, (unsigned)Lf.n, h.nmax, h.nmax, h.stream);
+  }
+  BDCHK(hipGetLastError());
+  std::vector<int32_t> info((size_t)std::max(Lf.n, 1), 0);
+  if (Lf.n > 0) BDCHK(hipMemcpyAsync(info.data(), h.d_info, (size_t)Lf.n * 4, hipMemcpyDeviceToHost, h.stream));
+  BDCHK(hipStreamSynchronize(h.stream));
+  for (int32_t b = 0; b < Lf.n; ++b)
+    if (info[b]) {
+      err = "singular diagonal block of box " + std::to_string(b);
+      return -4;
+    }
+  // the LU factors and panel inverses are no longer needed
+  (void)hipFree(h.d_dinv);
+  h.d_dinv = nullptr;
+  h.t_build = now_s() - t0;
+  return 0;
+}
+
+int bd_apply(BdHandle& h, const double* r, double* z, std::string& err) {
+  if (h.nbox > 0)
+    hipLaunchKernelGGL(k_bd_apply, dim3((unsigned)h.nbox), dim3(NT), 0, h.stream, (const BluTask*)h.d_tasks,
+                       h.d_pt_begin, h.d_perm, r, z);
+  BDCHK(hipGetLastError());
+  BDCHK(hipStreamSynchronize(h.stream));
+  return 0;
+}
+
+void bd_release(BdHandle& h) {
+  void* ptrs[] = {h.d_pts, h.d_w, h.d_diag, h.d_mem, h.d_dinv, h.d_perm, h.d_pt_begin, h.d_piv, h.d_info, h.d_tasks};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h.own_stream && h.stream) (void)hipStreamDestroy(h.stream);
+  h.stream = nullptr;
+}
+
 // ------------------------------------------------------------------ init / release
 int device_init(Handle& h, std::string& err) {
   int ndev = 0;

@@ -259,6 +259,27 @@ struct Handle {
   int64_t trd_cap = 0, trd_cap_side = 0;
 };
 
+// Block-diagonal preconditioner (Sec. 4.3): the inverses of the dense
+// diagonal blocks of the boxes of one level.
+struct BdHandle {
+  Tree tree;
+  int64_t N = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int nbox = 0, nmax = 0;
+  int64_t block_doubles = 0;
+  double *d_pts = nullptr, *d_w = nullptr, *d_diag = nullptr, *d_mem = nullptr, *d_dinv = nullptr;
+  int64_t *d_perm = nullptr, *d_pt_begin = nullptr;
+  int32_t *d_piv = nullptr, *d_info = nullptr;
+  void* d_tasks = nullptr;  // BluTask table
+  double t_build = 0;
+};
+int bd_setup(BdHandle& h, const double* pts, int64_t n, const double* w, const double* diag, double diag_scalar,
+             int level, int leaf_max, std::string& err);
+int bd_apply(BdHandle& h, const double* r, double* z, std::string& err);  // device vectors, caller order
+void bd_release(BdHandle& h);
+
 // status helpers
 void set_error(const std::string& msg);
 const char* get_error();

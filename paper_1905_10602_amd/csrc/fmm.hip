@@ -480,7 +480,7 @@ int fmm_apply(FmmHandle& h, const double* x, double* y, std::string& err) {
 }
 
 int fmm_gmres(FmmHandle& h, Handle* pre, const double* b, double* x, double tol, int restart, int maxit, int* iters,
-              double* relres, std::string& err) {
+              double* relres, std::string& err, BdHandle* bd) {
   const int64_t n = h.N;
   const int m = restart;
   const int64_t chunk = 1 << 15;
@@ -515,6 +515,14 @@ int fmm_gmres(FmmHandle& h, Handle* pre, const double* b, double* x, double tol,
     return 0;
   };
   auto precond = [&](const double* v, double* z, std::string& e2) -> int {
+    if (bd) {
+      hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        e2 = std::string("stream sync failed: ") + hipGetErrorString(e);
+        return -3;
+      }
+      return bd_apply(*bd, v, z, e2);
+    }
     if (!pre) {
       hipLaunchKernelGGL(k_gm_axpby, dim3(g1), dim3(NT), 0, s, n, 1.0, v, 0.0, z);
       return 0;

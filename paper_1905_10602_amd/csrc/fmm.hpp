@@ -13,6 +13,7 @@
 namespace ifmm {
 
 struct Handle;
+struct BdHandle;
 
 struct FmmHandle {
   Tree tree;
@@ -60,7 +61,7 @@ int fmm_setup(FmmHandle& h, const double* pts, int64_t n, const double* w, const
 int fmm_apply(FmmHandle& h, const double* x, double* y, std::string& err);
 // Right-preconditioned FGMRES(restart) from x = 0 on device vectors; pre may be null.
 int fmm_gmres(FmmHandle& h, Handle* pre, const double* b, double* x, double tol, int restart, int maxit, int* iters,
-              double* relres, std::string& err);
+              double* relres, std::string& err, BdHandle* bd = nullptr);
 void fmm_release(FmmHandle& h);
 
 }  // namespace ifmm

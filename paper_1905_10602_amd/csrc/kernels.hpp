@@ -939,6 +939,7 @@ __global__ void __launch_bounds__(NT) k_xsolve(const ElimRec* recs, const XTask*
 // 64; the panel itself is factorised by one workgroup.  piv follows the
 // convention of wg_getrf, so the solve phase reads the factors unchanged.
 constexpr int BLU_NB = 64;
+constexpr int BD_MAXN = 4096;  // largest box of the block-diagonal preconditioner
 constexpr int BLU_NB_PAD = BLU_NB + 1;
 
 struct BluTask {
@@ -2036,6 +2037,52 @@ __global__ void __launch_bounds__(NT) k_top_scatter(SolveView S, int nn, const i
   const int k = S.k, rP = r[P];
   double* z = S.Z + S.zo[P] * k;
   if (rP > 0) WG_FOR2(rP, k, a, c) z[a + (int64_t)c * rP] = buf[top_off[P] + a + (int64_t)c * ldt];
+}
+
+// ------------------------------------------------------------------ BD preconditioner
+// Block-diagonal preconditioner (Sec. 4.3): the dense diagonal block of every
+// box of level l_BD, inverted by the blocked LU path.  Assembly: box b's block
+// D (n_b x n_b, points [pt_begin[b], pt_begin[b + 1]) in tree order) and the
+// identity in X; grid (64-column chunks, boxes).
+__global__ void __launch_bounds__(NT) k_bd_assemble(const double* pts, const double* w, const double* diag,
+                                                    const int64_t* pt_begin, const BluTask* tasks) {
+  const BluTask t = tasks[blockIdx.y];
+  const int nb = t.d, c0 = blockIdx.x * 64;
+  if (threadIdx.x == 0 && blockIdx.x == 0) *t.info = 0;
+  if (c0 >= nb) return;
+  const int nc = min(64, nb - c0);
+  const int64_t p0 = pt_begin[blockIdx.y];
+  WG_FOR2(nb, nc, a, cl) {
+    const int b = c0 + cl;
+    double v;
+    if (a == b) {
+      v = diag[p0 + a];
+    } else {
+      const double* x = pts + 3 * (p0 + a);
+      const double* y = pts + 3 * (p0 + b);
+      const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+      v = w[p0 + b] / (4.0 * M_PI * sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    t.lu[a + (int64_t)b * nb] = v;
+    t.X[a + (int64_t)b * nb] = a == b ? 1.0 : 0.0;
+  }
+}
+
+// z_b = D_b^-1 r_b for every box (one workgroup each), in the caller's point
+// order (perm: tree position -> original index).
+__global__ void __launch_bounds__(NT) k_bd_apply(const BluTask* tasks, const int64_t* pt_begin, const int64_t* perm,
+                                                 const double* r, double* z) {
+  __shared__ double rb[BD_MAXN];
+  const BluTask t = tasks[blockIdx.x];
+  const int nb = t.d;
+  const int64_t p0 = pt_begin[blockIdx.x];
+  for (int j = threadIdx.x; j < nb; j += NT) rb[j] = r[perm[p0 + j]];
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += NT) {
+    double acc = 0.0;
+    for (int j = 0; j < nb; ++j) acc += t.X[i + (int64_t)j * nb] * rb[j];
+    z[perm[p0 + i]] = acc;
+  }
 }
 
 }  // namespace ifmm

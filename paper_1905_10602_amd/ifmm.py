@@ -80,6 +80,11 @@ def load_library():
         "fmm_stats": (I32, [P, C.c_char_p, I64]),
         "fmm_destroy": (None, [P]),
         "fmbem_gmres": (I32, [P, P, P, I64, P, P, I32, D, I32, I32, P, C.POINTER(I32), C.POINTER(D)]),
+        "bd_build": (I32, [P, I64, P, P, D, I32, I32, P, C.POINTER(P)]),
+        "bd_apply": (I32, [P, P, P, I32]),
+        "fmm_gmres_bd": (I32, [P, P, P, D, I32, I32, P, I32, C.POINTER(I32), C.POINTER(D)]),
+        "bd_stats": (I32, [P, C.c_char_p, I64]),
+        "bd_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -293,21 +298,20 @@ class FMM:
         return y
 
     def gmres(self, b, precond=None, tol=1e-8, restart=50, maxit=1000, allow_noconv=False):
-        """Returns (x, iterations, relative residual).  precond: a factored IFMM or None."""
+        """Returns (x, iterations, relative residual).  precond: a factored IFMM, a BD or None."""
         lib = load_library()
         it, rr = C.c_int32(), C.c_double()
         ph = None if precond is None else precond._h
+        fn = lib.fmm_gmres_bd if isinstance(precond, BD) else lib.fmm_gmres
         if _is_dev(b):
             import torch
             bc = b.contiguous()
             x = torch.empty_like(bc)
-            code = lib.fmm_gmres(self._h, _ptr(bc), ph, float(tol), int(restart), int(maxit), _ptr(x), 1,
-                                 C.byref(it), C.byref(rr))
+            code = fn(self._h, _ptr(bc), ph, float(tol), int(restart), int(maxit), _ptr(x), 1, C.byref(it), C.byref(rr))
         else:
             bc = np.ascontiguousarray(b, dtype=np.float64)
             x = np.empty_like(bc)
-            code = lib.fmm_gmres(self._h, _ptr(bc), ph, float(tol), int(restart), int(maxit), _ptr(x), 0,
-                                 C.byref(it), C.byref(rr))
+            code = fn(self._h, _ptr(bc), ph, float(tol), int(restart), int(maxit), _ptr(x), 0, C.byref(it), C.byref(rr))
         if not (allow_noconv and code == -7):
             _check(code)
         return x, it.value, rr.value
@@ -315,6 +319,51 @@ class FMM:
     def stats(self):
         buf = C.create_string_buffer(4096)
         _check(load_library().fmm_stats(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+
+class BD:
+    """Handle of the block-diagonal preconditioner (bd_build / bd_apply)."""
+
+    def __init__(self, points, diag, weights=None, level=0, leaf_max=64, stream=None):
+        lib = load_library()
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        if pts.ndim != 2 or pts.shape[1] != 3:
+            raise ValueError("points must be (N, 3)")
+        self.N = pts.shape[0]
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        dvec, dsc = (None, float(diag)) if np.isscalar(diag) else (np.ascontiguousarray(diag, dtype=np.float64), 0.0)
+        h = C.c_void_p()
+        _check(lib.bd_build(_ptr(pts), self.N, _ptr(w), _ptr(dvec), dsc, int(level), int(leaf_max),
+                            None if stream is None else C.c_void_p(stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, r):
+        lib = load_library()
+        if _is_dev(r):
+            import torch
+            z = torch.empty_like(r)
+            _check(lib.bd_apply(self._h, _ptr(r.contiguous()), _ptr(z), 1))
+            return z
+        rv = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.empty_like(rv)
+        _check(lib.bd_apply(self._h, _ptr(rv), _ptr(z), 0))
+        return z
+
+    def stats(self):
+        buf = C.create_string_buffer(1024)
+        _check(load_library().bd_stats(self._h, buf, len(buf)))
         return json.loads(buf.value.decode())
 
 

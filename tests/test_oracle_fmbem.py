@@ -122,3 +122,34 @@ def test_bem_pieces():
     assert np.allclose(bem.self_terms(np.array([np.pi])), 0.5)
     # the closed form reduces to the uniform density 1 for x0 = 0 (f = 1 on the sphere)
     assert np.allclose(bem.exact_density(c / np.linalg.norm(c, axis=1)[:, None], (0.0, 0.0, 0.0)), 1.0)
+
+
+def test_bd_oracle_inverts_the_block_diagonal_part():
+    # BD is exact on the block-diagonal part of A: BD (A_bd x) = x at every
+    # level.  On the BEM system (panel areas as weights) wider blocks (coarser
+    # l_BD) take no more FGMRES iterations (Sec. 4.3); for this first-kind
+    # Laplace operator the leaf BD is no better than no preconditioner
+    import synth
+    from oracle.bd import BD
+    from oracle.bem import dense_matrix, panels, point_source, self_terms
+    from oracle.krylov import fgmres
+    from oracle.tree import Tree
+    v, f = synth.icosphere(4)
+    c, a = panels(v, f)
+    N = c.shape[0]
+    A = dense_matrix(c, a)
+    st = self_terms(a)
+    x = np.random.default_rng(0).standard_normal(N)
+    depth = Tree(c, leaf_max=16, sigma=3).depth
+    its = []
+    for level in range(depth, 1, -1):
+        bd = BD(c, st, weights=a, level=level, leaf_max=16)
+        Abd = np.zeros_like(A)
+        for idx, _ in bd.boxes:
+            Abd[np.ix_(idx, idx)] = A[np.ix_(idx, idx)]
+        assert np.allclose(bd.apply(Abd @ x), x, rtol=0, atol=1e-9 * np.abs(x).max())
+        _, it, rr = fgmres(lambda y: A @ y, point_source(c), precond=bd.apply, tol=1e-8, restart=50)
+        assert rr <= 1e-8
+        its.append(it)
+    print(f"FGMRES iterations with BD at levels {depth}..2: {its}")
+    assert all(b <= a for a, b in zip(its, its[1:]))
