@@ -420,6 +420,53 @@ def bem_comparison(args):
     print(json.dumps({"bem_comparison": res}), flush=True)
 
 
+def batch_leg(args):
+    """The many-geometry workload: 64 independent geometries (seeds 4000..4063,
+    spheres, ellipsoids with random semi-axes and cube surfaces, N uniform in
+    [2048, 32768]), eps = 1e-4, sigma = 3, mixed form, 4 right-hand sides each:
+    ifmm_factor_batch / ifmm_solve_batch (8 host threads, one stream each)
+    against the same factorisations and solves one after the other; the
+    solutions must agree bit for bit."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1905_10602_amd import IFMM, factor_batch, solve_batch
+    geoms = synth.batch_geometries(64, 4000)
+    dgs = [synth.laplace_self_term(p.shape[0]) for _, p in geoms]
+    rhs = [synth.uniform_rhs(p.shape[0], 4, 4100 + g) for g, (_, p) in enumerate(geoms)]
+
+    def handles():
+        return [IFMM(p, 1e-4, 3, diag=dg, leaf_max=64, precision="mixed", bottom_level=args.bottom_level)
+                for (_, p), dg in zip(geoms, dgs)]
+    out = {"geometries": len(geoms), "points_total": int(sum(p.shape[0] for _, p in geoms)), "rhs_each": 4,
+           "eps": 1e-4}
+    hs = handles()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    factor_batch(hs, threads=8)
+    t1 = time.perf_counter()
+    xb = solve_batch(hs, rhs, threads=8)
+    t2 = time.perf_counter()
+    out.update({"batch_factor_s": t1 - t0, "batch_solve_s": t2 - t1})
+    for h in hs:
+        h.close()
+    if left(args) < 3.0 * (t2 - t0) + 20:
+        out["sequential"] = f"skipped ({left(args):.0f} s left)"
+        return out
+    hs = handles()
+    t0 = time.perf_counter()
+    for h in hs:
+        h.factor()
+    t1 = time.perf_counter()
+    xs = [h.solve(b) for h, b in zip(hs, rhs)]
+    t2 = time.perf_counter()
+    out.update({"sequential_factor_s": t1 - t0, "sequential_solve_s": t2 - t1,
+                "bitwise_equal": bool(all(np.array_equal(a, b) for a, b in zip(xb, xs)))})
+    for h in hs:
+        h.close()
+    return out
+
+
 def copy_calibration():
     """Reference copy for the HBM traffic counters: three copies of 256 MiB of FP64."""
     import torch
@@ -453,6 +500,7 @@ def main():
                          "the two coarser ones (default), 0 = leaves of <= 64 points, >= 2 = forced")
     ap.add_argument("--colouring", choices=("stride", "lookback"), default="stride")
     ap.add_argument("--no-gmres", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-geometry batch leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--bem", action="store_true", help="only the FMBEM preconditioner comparison (327,680 panels)")
@@ -530,6 +578,17 @@ def main():
         xs[fm] = x0
         if stats0 is None:
             stats0 = st
+    batch = None
+    if not args.no_batch and left(args) > 120:
+        log("many-geometry batch (64 geometries)")
+        try:
+            batch = batch_leg(args)
+            log(f"batch: {json.dumps(batch)}")
+        except Exception as e:
+            traceback.print_exc()
+            notes.append(f"batch leg failed: {e}")
+    elif not args.no_batch:
+        notes.append(f"batch leg skipped: {left(args):.0f} s left")
     cpu = None
     if not args.no_cpu_baseline and left(args) > 30:
         log("cpu baseline (oracle on bounded samples)")
@@ -557,7 +616,7 @@ def main():
         "forms": res,
         "roofline": roofline_of(stats0, lead != "fp64") if stats0 else None,
         "roofline_more": roofline_more(stats0, lead != "fp64") if stats0 else None,
-        "cpu_baseline": cpu, "notes": notes, "wall_s": time.time() - T_START,
+        "cpu_baseline": cpu, "batch_64_geometries": batch, "notes": notes, "wall_s": time.time() - T_START,
     }
     if "mixed" in res and "fp64" in res:
         out["factor_speedup_mixed_vs_fp64"] = res["fp64"]["factor_s"] / res["mixed"]["factor_s"]
@@ -586,6 +645,8 @@ def _reserve(args, forms):
         est += 10.0 * len(forms)
     if not args.no_cpu_baseline:
         est += 80.0
+    if not args.no_batch:
+        est += 90.0
     return est
 
 

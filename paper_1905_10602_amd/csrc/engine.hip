@@ -19,6 +19,7 @@
 #include <cstring>
 #include <cstdio>
 #include <cstdlib>
+#include <fstream>
 #include <numeric>
 #include <mutex>
 #include <thread>
@@ -168,6 +169,28 @@ static int store_take(Handle& h, int64_t doubles, double** out, std::string& err
   return 0;
 }
 
+// FP32 blocks of the factor store, same scheme (256-byte aligned, zeroed chunks).
+static int store32_take(Handle& h, int64_t floats, float** out, std::string& err) {
+  floats = (floats + 63) & ~63LL;
+  if (floats > h.store32_left) {
+    const int64_t chunk = std::max<int64_t>(floats, (int64_t)1 << 27);  // >= 512 MiB
+    double* p = nullptr;
+    int rc = dalloc(h, &p, chunk / 2, err);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(p, 0, (size_t)chunk * 4, h.stream));
+    h.store32_chunks.push_back((float*)p);
+    h.store32_used.push_back(0);
+    h.store32_cur = (float*)p;
+    h.store32_left = chunk;
+  }
+  *out = h.store32_cur;
+  h.store32_cur += floats;
+  h.store32_left -= floats;
+  h.store32_used.back() += floats;
+  h.store_bytes += floats * 4;
+  return 0;
+}
+
 // A copy of a host table that stays alive until the next stream
 // synchronisation: the source of an upload that the host does not wait for.
 template <class T>
@@ -226,6 +249,76 @@ struct ProfScope {
     h.pending.push_back(p);
   }
 };
+
+// ---- autotuner (options.tune_cache)
+static std::string form_name(const Handle& h) { return h.precision == 1 ? "mixed" : "fp64"; }
+static std::string schur_key(const Handle& h, int l) {
+  return "schur " + form_name(h) + " d" + std::to_string(h.tree.depth) + " l" + std::to_string(l);
+}
+static std::string solve_key(const Handle& h, const char* step, int l, int sk) {
+  return std::string(step) + " " + form_name(h) + " d" + std::to_string(h.tree.depth) + " l" + std::to_string(l) +
+         " k" + std::to_string(sk);
+}
+// The cache file: one "key = value" per line, '#' comments; a missing file
+// is an empty table.
+static void tune_load(Handle& h) {
+  h.tune.clear();
+  h.tune_dirty = false;
+  if (h.tune_cache.empty()) return;
+  std::ifstream f(h.tune_cache);
+  std::string line;
+  while (std::getline(f, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    const size_t p = line.rfind(" = ");
+    if (p == std::string::npos) continue;
+    h.tune[line.substr(0, p)] = std::atoi(line.c_str() + p + 3);
+  }
+}
+static int tune_save(Handle& h, std::string& err) {
+  if (h.tune_cache.empty() || !h.tune_dirty) return 0;
+  std::ofstream f(h.tune_cache, std::ios::trunc);
+  if (!f) {
+    err = "cannot write the autotuner cache " + h.tune_cache;
+    return -1;
+  }
+  f << "# ifmm autotuner: <kernel> <form> d<depth> l<level>[ k<rhs chunk>] = <choice>\n";
+  for (const auto& kv : h.tune) f << kv.first << " = " << kv.second << "\n";
+  h.tune_dirty = false;
+  return f ? 0 : (err = "cannot write the autotuner cache " + h.tune_cache, -1);
+}
+// After a stream synchronisation: per key, the candidate with the most work
+// per millisecond over its timed launches wins (a candidate never timed loses).
+static hipEvent_t take_event(Handle& h);
+static void tune_collect(Handle& h) {
+  if (h.tune_pending.empty()) return;
+  struct Acc { double work[3] = {0, 0, 0}, ms[3] = {0, 0, 0}; int value[3] = {0, 0, 0}; };
+  std::map<std::string, Acc> acc;
+  for (const auto& m : h.tune_pending) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, m.a, m.b);
+    Acc& a = acc[m.key];
+    a.work[m.variant] += m.work;
+    a.ms[m.variant] += ms;
+    a.value[m.variant] = m.value;
+    h.event_pool.push_back(m.a);
+    h.event_pool.push_back(m.b);
+  }
+  h.tune_pending.clear();
+  for (const auto& kv : acc) {
+    const Acc& a = kv.second;
+    int best = -1;
+    double rate = -1.0;
+    for (int v = 0; v < 3; ++v)
+      if (a.ms[v] > 0.0 && a.work[v] / a.ms[v] > rate) {
+        rate = a.work[v] / a.ms[v];
+        best = v;
+      }
+    if (best >= 0) {
+      h.tune[kv.first] = a.value[best];
+      h.tune_dirty = true;
+    }
+  }
+}
 
 // Fork: work launched on h.side_stream after this waits for everything
 // queued on the main stream so far.  Join: the main stream waits for the
@@ -826,7 +919,7 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     sc += (std::max<int64_t>(cnt, 1) + 31) & ~31LL;
     return o;
   };
-  std::vector<int64_t> x_off(nrec), dinv_off(nrec, 0);
+  std::vector<int64_t> x_off(nrec), dinv_off(nrec, 0), l_off(nrec, 0), u_off(nrec, 0);
   std::vector<std::vector<int64_t>> far_off_F, far_off_D;
   struct ChgOff { int64_t gs, gt, vs, vt, ws, wt, ls, lt, T, S, tmp; };
   const bool sym = h.symmetric;
@@ -968,8 +1061,17 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     if ((rc = store_take(h, (int64_t)R.d * R.d, &R.lu, err))) return rc;
     if ((rc = store_take(h, (R.d + 1) / 2 + 1, &p, err))) return rc;
     R.piv = (int32_t*)p;
-    if ((rc = store_take(h, (int64_t)R.M * R.n, &R.L, err))) return rc;
-    if ((rc = store_take(h, (int64_t)R.n * R.M, &R.U, err))) return rc;
+    R.Ls = R.Us = nullptr;
+    if (h.solve32) {
+      // L and U are colour work; the solve keeps FP32 copies
+      l_off[k] = stake((int64_t)R.M * R.n);
+      u_off[k] = stake((int64_t)R.n * R.M);
+      if ((rc = store32_take(h, (int64_t)R.M * R.n, &R.Ls, err))) return rc;
+      if ((rc = store32_take(h, (int64_t)R.n * R.M, &R.Us, err))) return rc;
+    } else {
+      if ((rc = store_take(h, (int64_t)R.M * R.n, &R.L, err))) return rc;
+      if ((rc = store_take(h, (int64_t)R.n * R.M, &R.U, err))) return rc;
+    }
     R.wv = L.wv_total;
     L.wv_total += R.d;
   }
@@ -1020,7 +1122,13 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   int rc;
   if ((rc = ensure(h, (void**)&h.scratch, &h.scratch_bytes, sc * 8 + 256, err))) return rc;
   double* S0 = h.scratch;
-  for (int k = 0; k < nrec; ++k) recs[k].X = S0 + x_off[k];
+  for (int k = 0; k < nrec; ++k) {
+    recs[k].X = S0 + x_off[k];
+    if (h.solve32) {
+      recs[k].L = S0 + l_off[k];
+      recs[k].U = S0 + u_off[k];
+    }
+  }
   for (size_t f = 0; f < far.size(); ++f) { far[f].F = S0 + fF[f]; far[f].D = S0 + fD[f]; }
   std::vector<EigTask> etasks;
   for (size_t k = 0; k < chg.size(); ++k) {
@@ -1175,9 +1283,33 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     // tile keeps more workgroups resident and measured faster at every level)
     int nmx = 0;
     for (const ElimRec& R : recs) nmx = std::max(nmx, R.n);
-    auto ks = h.precision != 1 ? k_schur<false, false> : nmx >= h.deep_n ? k_schur<true, true> : k_schur<true, false>;
+    // tile: FP64 form FMA (0) or matrix cores (1); mixed form lite (0) or
+    // deep (1) FP32 tile.  Built-in choice unless the autotuner has one; a
+    // level it has not seen alternates the two over its colours, timed
+    bool alt = h.precision != 1 ? h.f64_mfma : nmx >= h.deep_n;
+    bool explore = false;
+    std::string tkey;
+    if (!h.tune_cache.empty()) {
+      tkey = schur_key(h, l);
+      const auto it = h.tune.find(tkey);
+      explore = it == h.tune.end();
+      alt = explore ? (c % 2) == 1 : it->second != 0;
+    }
+    auto ks = h.precision != 1 ? (alt ? k_schur<false, false, true> : k_schur<false, false, false>)
+              : alt ? k_schur<true, true, false>
+                    : k_schur<true, false, false>;
+    hipEvent_t ta_ = nullptr, tb_ = nullptr;
+    if (explore) {
+      ta_ = take_event(h);
+      tb_ = take_event(h);
+      HIPCHK(hipEventRecord(ta_, h.stream));
+    }
     hipLaunchKernelGGL(ks, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks, d_fidx,
                        d_far);
+    if (explore) {
+      HIPCHK(hipEventRecord(tb_, h.stream));
+      h.tune_pending.push_back({ta_, tb_, tkey, alt ? 1 : 0, alt ? 1 : 0, std::max(fl_schur, 1.0)});
+    }
   }
   if ((rc = check_arena(h, l, "schur", c, err))) return rc;
   if (nchg) {
@@ -1947,6 +2079,11 @@ static void clear_factor(Handle& h) {
   for (double* p : h.store_chunks) dfree(h, p);
   h.store_chunks.clear();
   h.store_used.clear();
+  for (float* p : h.store32_chunks) dfree(h, (double*)p);
+  h.store32_chunks.clear();
+  h.store32_used.clear();
+  h.store32_cur = nullptr;
+  h.store32_left = 0;
   h.store_cur = nullptr;
   h.store_left = 0;
   h.store_bytes = 0;
@@ -1983,6 +2120,13 @@ int factor(Handle& h, std::string& err) {
   if (const char* e = std::getenv("IFMM_SKETCH")) h.sketch = std::atoi(e) != 0;
   if (const char* e = std::getenv("IFMM_PB_WAVE")) h.pb_wave = std::atoi(e) != 0;
   if (const char* e = std::getenv("IFMM_DEEP_N")) h.deep_n = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("IFMM_F64_MFMA")) h.f64_mfma = std::atoi(e) != 0;
+  tune_load(h);
+  // IFMM_SOLVE32=1 (mixed form): the solve reads FP32 copies of L and G.  It
+  // halves the store but ran slower than the FP64 blocks (the conversions
+  // sit in the column loop), so it is off by default
+  h.solve32 = false;
+  if (const char* e = std::getenv("IFMM_SOLVE32")) h.solve32 = h.precision == 1 && std::atoi(e) != 0;
   h.prof_level = std::getenv("IFMM_PROF_LEVEL") != nullptr;
   if (const char* e = std::getenv("IFMM_SKETCH_MIN")) h.sketch_min = std::max(1, std::atoi(e));
   h.stat_sketch = h.stat_sketch_rejected = h.stat_sketch_narrow = 0;
@@ -2021,6 +2165,7 @@ int factor(Handle& h, std::string& err) {
       if ((rc = eliminate_colour(h, l, c, err))) return rc;
     HSYNC(h);
     prof_collect(h);
+    tune_collect(h);
     {
       HostLap lp(h);
       if ((rc = finish_level(h, l, err))) return rc;
@@ -2083,6 +2228,10 @@ int factor(Handle& h, std::string& err) {
   for (size_t q = 0; q < h.store_chunks.size(); ++q)
     if (h.store_used[q] > 0)
       hipLaunchKernelGGL(k_check_finite, dim3(2048), dim3(NT), 0, h.stream, h.store_chunks[q], h.store_used[q], d_nf);
+  for (size_t q = 0; q < h.store32_chunks.size(); ++q)
+    if (h.store32_used[q] > 0)
+      hipLaunchKernelGGL(k_check_finite32, dim3(2048), dim3(NT), 0, h.stream, h.store32_chunks[q], h.store32_used[q],
+                         d_nf);
   if (h.top_n > 0)
     hipLaunchKernelGGL(k_check_finite, dim3(256), dim3(NT), 0, h.stream, h.d_top_inv, (int64_t)h.top_n * h.top_n,
                        d_nf);
@@ -2106,7 +2255,7 @@ int factor(Handle& h, std::string& err) {
   h.t_top = now_s() - ta;
   h.t_factor = now_s() - t0;
   h.factored = true;
-  return 0;
+  return tune_save(h, err);
 }
 
 // ------------------------------------------------------------------ solve
@@ -2155,19 +2304,19 @@ static SolvePlan solve_plan(const Handle& h, int k, int64_t ld, bool staging) {
 // the number of waves NW that split the tile's inner dimension (64-column
 // chunks) for the colour's longest inner dimension.
 static int solve_waves(int inner) { return inner <= 64 ? 1 : inner <= 256 ? 4 : 8; }
-#define IFMM_SOLVE_LAUNCH(KERN, k, nw, ntask, st, ...)                                                           \
+#define IFMM_SOLVE_LAUNCH(KERN, T, k, nw, ntask, st, ...)                                                        \
   do {                                                                                                         \
     const dim3 g_((unsigned)(ntask));                                                                          \
     const int sk_ = (k) == 1 ? 1 : (k) <= 4 ? 4 : 8;                                                           \
-    if (sk_ == 1 && (nw) == 1) hipLaunchKernelGGL((KERN<1, 1>), g_, dim3(64), 0, st, __VA_ARGS__);           \
-    else if (sk_ == 1 && (nw) == 4) hipLaunchKernelGGL((KERN<1, 4>), g_, dim3(256), 0, st, __VA_ARGS__);     \
-    else if (sk_ == 1) hipLaunchKernelGGL((KERN<1, 8>), g_, dim3(512), 0, st, __VA_ARGS__);                  \
-    else if (sk_ == 4 && (nw) == 1) hipLaunchKernelGGL((KERN<4, 1>), g_, dim3(64), 0, st, __VA_ARGS__);      \
-    else if (sk_ == 4 && (nw) == 4) hipLaunchKernelGGL((KERN<4, 4>), g_, dim3(256), 0, st, __VA_ARGS__);     \
-    else if (sk_ == 4) hipLaunchKernelGGL((KERN<4, 8>), g_, dim3(512), 0, st, __VA_ARGS__);                  \
-    else if ((nw) == 1) hipLaunchKernelGGL((KERN<8, 1>), g_, dim3(64), 0, st, __VA_ARGS__);                  \
-    else if ((nw) == 4) hipLaunchKernelGGL((KERN<8, 4>), g_, dim3(256), 0, st, __VA_ARGS__);                 \
-    else hipLaunchKernelGGL((KERN<8, 8>), g_, dim3(512), 0, st, __VA_ARGS__);                                \
+    if (sk_ == 1 && (nw) == 1) hipLaunchKernelGGL((KERN<1, 1, T>), g_, dim3(64), 0, st, __VA_ARGS__);        \
+    else if (sk_ == 1 && (nw) == 4) hipLaunchKernelGGL((KERN<1, 4, T>), g_, dim3(256), 0, st, __VA_ARGS__);  \
+    else if (sk_ == 1) hipLaunchKernelGGL((KERN<1, 8, T>), g_, dim3(512), 0, st, __VA_ARGS__);               \
+    else if (sk_ == 4 && (nw) == 1) hipLaunchKernelGGL((KERN<4, 1, T>), g_, dim3(64), 0, st, __VA_ARGS__);   \
+    else if (sk_ == 4 && (nw) == 4) hipLaunchKernelGGL((KERN<4, 4, T>), g_, dim3(256), 0, st, __VA_ARGS__);  \
+    else if (sk_ == 4) hipLaunchKernelGGL((KERN<4, 8, T>), g_, dim3(512), 0, st, __VA_ARGS__);               \
+    else if ((nw) == 1) hipLaunchKernelGGL((KERN<8, 1, T>), g_, dim3(64), 0, st, __VA_ARGS__);               \
+    else if ((nw) == 4) hipLaunchKernelGGL((KERN<8, 4, T>), g_, dim3(256), 0, st, __VA_ARGS__);              \
+    else hipLaunchKernelGGL((KERN<8, 8, T>), g_, dim3(512), 0, st, __VA_ARGS__);                             \
   } while (0)
 
 // The substitution (Alg. 2) as one stream of launches on h.stream over the
@@ -2185,11 +2334,36 @@ static void enqueue_solve(Handle& h, const SolvePlan& P, double* B, const double
   };
   hipLaunchKernelGGL(k_zero, dim3(1024), dim3(NT), 0, h.stream, B, P.otop);
   const Level& TL = h.tree.levels[D];
+  const double es = h.solve32 ? 4.0 : 8.0;  // bytes per stored L / G entry
+  const int sk = k == 1 ? 1 : k <= 4 ? 4 : 8;
+  // waves per workgroup of a step at level l: forced while tuning, else the
+  // autotuner's choice, else the rule (solve_waves)
+  auto waves = [&](const char* step, int l, int rule) {
+    if (h.solve_nw_force) return h.solve_nw_force;
+    if (!h.tune.empty()) {
+      const auto it = h.tune.find(solve_key(h, step, l, sk));
+      if (it != h.tune.end()) return it->second;
+    }
+    return rule;
+  };
+  // while tuning, every launch of a step is timed under its key
+  auto tstart = [&](hipEvent_t* a) {
+    if (h.solve_tune_var < 0) return;
+    *a = take_event(h);
+    (void)hipEventRecord(*a, h.stream);
+  };
+  auto tstop = [&](hipEvent_t a, const char* step, int l) {
+    if (h.solve_tune_var < 0) return;
+    hipEvent_t b = take_event(h);
+    (void)hipEventRecord(b, h.stream);
+    h.tune_pending.push_back({a, b, solve_key(h, step, l, sk), h.solve_tune_var, h.solve_nw_force, 1.0});
+  };
   hipLaunchKernelGGL(k_perm_in, dim3(TL.n), dim3(NT), 0, h.stream, d_rhs, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
                      sv(D));
   for (int l = D; l >= 2; --l) {
     const DevLevel& L = h.lv[l];
     SolveView S = sv(l);
+    h.cur_level = l;  // profiler classes keyed per level (IFMM_PROF_LEVEL)
     const STask* st_w = L.d_st;
     const STask* st_u = L.d_st + L.st_w.size();
     for (size_t c = 0; c + 1 < L.col_ptr.size(); ++c) {
@@ -2200,19 +2374,29 @@ static void enqueue_solve(Handle& h, const SolvePlan& P, double* B, const double
         for (int e = a; e < b; ++e) {
           const ElimRec& R = L.recs[e];
           by_w += 8.0 * ((double)R.d * R.n + k * (2.0 * R.n + R.r));
-          by_u += 8.0 * ((double)R.M * R.n + k * (R.n + 2.0 * R.M));
+          by_u += es * R.M * R.n + 8.0 * k * (R.n + 2.0 * R.M);
         }
       const int tw0 = L.stw_ptr[c], tw1 = L.stw_ptr[c + 1], tu0 = L.stu_ptr[c], tu1 = L.stu_ptr[c + 1];
       int nmx = 0;  // inner dimension of both forward steps: n
       for (int e = a; e < b; ++e) nmx = std::max(nmx, L.recs[e].n);
-      {
+      if (tw1 > tw0) {
         ProfScope ps(h, "k_solve_fwd_w", 0, by_w);
-        if (tw1 > tw0) IFMM_SOLVE_LAUNCH(k_solve_fwd_w, k, solve_waves(nmx), tw1 - tw0, h.stream, L.d_recs, st_w + tw0, S);
+        const int nw = waves("solve_fwd_w", l, solve_waves(nmx));
+        hipEvent_t a = nullptr;
+        tstart(&a);
+        IFMM_SOLVE_LAUNCH(k_solve_fwd_w, double, k, nw, tw1 - tw0, h.stream, L.d_recs, st_w + tw0, S);
+        tstop(a, "solve_fwd_w", l);
       }
-      {
+      if (tu1 > tu0) {
         ProfScope ps(h, "k_solve_fwd_upd", 0, by_u);
-        if (tu1 > tu0)
-          IFMM_SOLVE_LAUNCH(k_solve_fwd_upd, k, solve_waves(nmx), tu1 - tu0, h.stream, L.d_recs, L.d_nbrs, st_u + tu0, S);
+        const int nw = waves("solve_fwd_upd", l, solve_waves(nmx));
+        hipEvent_t a = nullptr;
+        tstart(&a);
+        if (h.solve32)
+          IFMM_SOLVE_LAUNCH(k_solve_fwd_upd, float, k, nw, tu1 - tu0, h.stream, L.d_recs, L.d_nbrs, st_u + tu0, S);
+        else
+          IFMM_SOLVE_LAUNCH(k_solve_fwd_upd, double, k, nw, tu1 - tu0, h.stream, L.d_recs, L.d_nbrs, st_u + tu0, S);
+        tstop(a, "solve_fwd_upd", l);
       }
     }
     if (l > 2) {
@@ -2235,6 +2419,7 @@ static void enqueue_solve(Handle& h, const SolvePlan& P, double* B, const double
   for (int l = 2; l <= D; ++l) {
     const DevLevel& L = h.lv[l];
     SolveView S = sv(l);
+    h.cur_level = l;
     if (l > 2) {
       const DevLevel& Pl = h.lv[l - 1];
       hipLaunchKernelGGL(k_vec_down, dim3(Pl.nn), dim3(NT), 0, h.stream, S, sv(l - 1), Pl.d_child_ptr, Pl.d_child,
@@ -2248,16 +2433,24 @@ static void enqueue_solve(Handle& h, const SolvePlan& P, double* B, const double
       if (h.prof)
         for (int e = a; e < b; ++e) {
           const ElimRec& R = L.recs[e];
-          by += 8.0 * ((double)R.n * R.M + (double)R.n * R.r + k * (2.0 * R.n + R.M + R.r));
+          by += es * R.n * R.M + 8.0 * ((double)R.n * R.r + k * (2.0 * R.n + R.M + R.r));
         }
       const int tb0 = L.stb_ptr[c], tb1 = L.stb_ptr[c + 1];
+      if (tb1 <= tb0) continue;
       ProfScope ps(h, "k_solve_bwd", 0, by);
       int inner = 0;
       for (int e = a; e < b; ++e) inner = std::max(inner, L.recs[e].M + L.recs[e].r);
-      if (tb1 > tb0)
-        IFMM_SOLVE_LAUNCH(k_solve_bwd, k, solve_waves(inner), tb1 - tb0, h.stream, L.d_recs, L.d_nbrs, st_b + tb0, S);
+      const int nw = waves("solve_bwd", l, solve_waves(inner));
+      hipEvent_t ev = nullptr;
+      tstart(&ev);
+      if (h.solve32)
+        IFMM_SOLVE_LAUNCH(k_solve_bwd, float, k, nw, tb1 - tb0, h.stream, L.d_recs, L.d_nbrs, st_b + tb0, S);
+      else
+        IFMM_SOLVE_LAUNCH(k_solve_bwd, double, k, nw, tb1 - tb0, h.stream, L.d_recs, L.d_nbrs, st_b + tb0, S);
+      tstop(ev, "solve_bwd", l);
     }
   }
+  h.cur_level = 0;
   hipLaunchKernelGGL(k_perm_out, dim3(TL.n), dim3(NT), 0, h.stream, d_x, ld, k, h.d_perm, h.d_pt_begin, h.lv[D].d_n,
                      sv(D));
 }
@@ -2282,6 +2475,29 @@ int solve(Handle& h, const double* rhs, double* x, int k, int64_t ld, int on_dev
     H2D(h, io, rhs, (size_t)ld * k * 8);
     d_rhs = io;
     d_x = io + ld * k;
+  }
+  if (!h.tune_cache.empty()) {
+    // autotuner: a level / step / chunk width without an entry gets one timed
+    // eager solve per wave count (1, 4, 8); the real solve follows
+    const int sk = k == 1 ? 1 : k <= 4 ? 4 : 8;
+    const std::string done = "solve " + form_name(h) + " d" + std::to_string(h.tree.depth) + " k" + std::to_string(sk);
+    if (!h.tune.count(done)) {
+      const int cand[3] = {1, 4, 8};
+      for (int v = 0; v < 3; ++v) {
+        h.solve_nw_force = cand[v];
+        h.solve_tune_var = v;
+        enqueue_solve(h, P, B, d_rhs, d_x, k, ld);
+      }
+      h.solve_nw_force = 0;
+      h.solve_tune_var = -1;
+      HIPCHK(hipStreamSynchronize(h.stream));
+      prof_collect(h);
+      tune_collect(h);
+      h.tune[done] = 1;  // tuned (levels without a launch of a step keep the rule)
+      h.tune_dirty = true;
+      release_graph(h);
+      if ((rc = tune_save(h, err))) return rc;
+    }
   }
   if (const char* e = std::getenv("IFMM_GRAPH")) h.graph_solve = std::atoi(e) != 0;
   const bool use_graph = h.graph_solve;
@@ -2657,14 +2873,12 @@ __global__ void __launch_bounds__(NT) k_internal_gemm(int m, int n, int k, doubl
   const double* Ab = tA ? A + (int64_t)i0 * lda : A + i0;
   const double* Bb = tB ? B + j0 : B + (int64_t)j0 * ldb;
   if (f32 == 2) wg_gemm_f32_deep(mm, nn, k, alpha, Ab, lda, tA != 0, Bb, ldb, tB != 0, beta, C + i0 + (int64_t)j0 * ldc, ldc);
+  else if (f32 == 3 && !tA && !tB) wg_gemm_f64m(mm, nn, k, alpha, Ab, lda, Bb, ldb, beta, C + i0 + (int64_t)j0 * ldc, ldc);
+  else if (f32 == 3) wg_gemm(mm, nn, k, alpha, Ab, lda, tA != 0, Bb, ldb, tB != 0, beta, C + i0 + (int64_t)j0 * ldc, ldc);
   else wg_gemm_p(f32 != 0, mm, nn, k, alpha, Ab, lda, tA != 0, Bb, ldb, tB != 0, beta, C + i0 + (int64_t)j0 * ldc, ldc);
 }
 }  // namespace ifmm
 
-// Test hook (not part of the declared ABI): C = alpha op(A) op(B) + beta C on
-// host arrays (column-major, tight leading dimensions) with the FP64 (f32 = 0)
-// or FP32 matrix-core workgroup product (f32 = 1: the lite tile; f32 = 2: the
-// double-buffered tile from inner dimension 96 on), one workgroup per 64 x 64 tile.
 // Test hook (not declared in the public header): X = D^-1 B for `count`
 // matrices of order d with W right-hand columns through the blocked LU path.
 extern "C" int ifmm_internal_blocked_solve(const double* D, int count, int d, const double* B, int W, double* X,
@@ -2696,6 +2910,11 @@ extern "C" int ifmm_internal_blocked_solve(const double* D, int count, int d, co
   return rc;
 }
 
+// Test hook (not part of the declared ABI): C = alpha op(A) op(B) + beta C on
+// host arrays (column-major, tight leading dimensions) with the FP64 (f32 = 0)
+// or FP32 matrix-core workgroup product (f32 = 1: the lite tile; f32 = 2: the
+// double-buffered tile from inner dimension 96 on), or the FP64 matrix-core
+// product (f32 = 3, untransposed operands), one workgroup per 64 x 64 tile.
 extern "C" int ifmm_internal_gemm(int m, int n, int k, double alpha, const double* A, int tA, const double* B, int tB,
                                   double beta, double* C, int f32) {
   using namespace ifmm;

@@ -30,6 +30,10 @@ struct ElimRec {
   double* X;               // colour scratch: D^-1 [U 0; 0 I], d x (M + r), ld d
   int64_t wv;              // offset (in doubles per right-hand side) of w_i in the solve work vector
   int32_t far_base, pad1;  // far-pair index table: nnb * nnb entries from far_base
+  // FP32 copies of L and of G = X[0:n, 0:M] that the solve reads in the mixed
+  // form (L and U then live in colour scratch); null in the FP64 form
+  float* Ls;               // M x n, ld M
+  float* Us;               // n x M, ld n
 };
 
 // One 64-row tile of a stored block in the solve.
@@ -149,6 +153,12 @@ struct Handle {
   std::vector<int64_t> store_used;  // doubles handed out from each chunk
   double* store_cur = nullptr;
   int64_t store_left = 0, store_bytes = 0;
+  // FP32 part of the factor store (the solve's L and G blocks in the mixed form)
+  std::vector<float*> store32_chunks;
+  std::vector<int64_t> store32_used;  // floats per chunk
+  float* store32_cur = nullptr;
+  int64_t store32_left = 0;
+  bool solve32 = false;  // mixed form, IFMM_SOLVE32=1: the solve reads FP32 L and G blocks
   // growable buffers
   double* scratch = nullptr;
   int64_t scratch_bytes = 0;
@@ -188,6 +198,11 @@ struct Handle {
   // IFMM_DEEP_N: pivot order from which the Schur update takes the deep FP32
   // tile; off by default (the lite tile's occupancy wins at every level measured)
   int deep_n = 1 << 30;
+  // IFMM_F64_MFMA=1: FP64 Schur products of blocks >= 16 x 16 on the FP64
+  // matrix cores instead of the LDS-tiled FMA tile.  Off by default: on this
+  // chip the FP64 matrix-core peak equals the vector peak, and the tile without
+  // LDS staging ran no faster at N = 1M (and slowed the mixed-form kernel)
+  bool f64_mfma = false;
   int sketch_min = 128;     // Gram order from which a sketch is tried (IFMM_SKETCH_MIN)
   double* skbuf = nullptr;
   int64_t skbuf_bytes = 0;
@@ -211,6 +226,23 @@ struct Handle {
   int colouring = 0;              // 0 Alg. 3, 1 look-back greedy
   std::vector<double> depth_costs;  // cost-model estimates of the candidate depths (bottom_level = -1)
   std::string tune_cache;         // autotuner cache file ("" = built-in tile choices)
+  // Autotuner: per key "<kernel> <form> d<depth> l<level>[ k<rhs chunk>]" the
+  // chosen variant (Schur tile) or wave count (solve steps).  Read from the
+  // cache file at each factorisation; a key missing from it is tuned on the
+  // fly (Schur: the level's colours alternate between the two tiles; solve:
+  // one timed solve per wave count) and the file is rewritten.
+  std::map<std::string, int> tune;
+  bool tune_dirty = false;
+  struct TuneMeas {
+    hipEvent_t a, b;
+    std::string key;
+    int variant;      // index of the candidate
+    int value;        // what the table stores when this candidate wins
+    double work;      // flops (Schur) or launches (solve) between the events
+  };
+  std::vector<TuneMeas> tune_pending;
+  int solve_nw_force = 0;  // tuning: every solve launch uses this many waves
+  int solve_tune_var = -1; // tuning: candidate index of the timed solve (-1: not tuning)
   double* fbuf = nullptr;
   int64_t fbuf_bytes = 0;
   std::vector<float> rec_X, rec_t;                   // features (14 per row) and r_new / n

@@ -1182,14 +1182,19 @@ struct SchurTask {
 // is formed fresh (no cancellation against stored data) and then compressed
 // at relative accuracy eps.  The near blocks are updated in place, M -= L X,
 // where the difference can be far smaller than either term, and stay FP64.
-template <bool f32, bool deep>
+// FP64 products of blocks of at least 16 x 16 (inner >= 8) go to the FP64
+// matrix cores in the instance with mf set (FP64 form only: the extra tile's
+// registers would halve the occupancy of the mixed-form kernel), smaller ones
+// to the FMA tile.
+template <bool f32, bool deep, bool mf>
 __device__ inline void schur_gemm(int m, int n, int k, double alpha, const double* A, int lda, const double* B,
                                   int ldb, double beta, double* C, int ldc) {
-  if (!f32) wg_gemm(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc);
+  if (!f32 && mf && m >= 16 && n >= 16 && k >= 8) wg_gemm_f64m(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  else if (!f32) wg_gemm(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc);
   else if (deep) wg_gemm_f32_deep(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc);
   else wg_gemm_f32(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc);
 }
-template <bool f32, bool deep>
+template <bool f32, bool deep, bool mf>
 __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const ElimNbr* nbrs, const int32_t* far_idx,
                                    const FarPair* far, int a, int b) {
   const int i = R.node, n = R.n, r = R.r, d = R.d, M = R.M;
@@ -1202,11 +1207,11 @@ __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const E
       const double* Xb = R.X + (int64_t)B.off * d;
       const int fi = far_idx[R.far_base + a * R.nnb + b];
       if (fi < 0)
-        schur_gemm<false, false>(A.m, B.m, n, -1.0, La, M, Xb, d, 1.0, V.arena + near_block(V, A.p, B.p), np);
-      else schur_gemm<f32, deep>(A.m, B.m, n, -1.0, La, M, Xb, d, 0.0, far[fi].F, A.m);
+        schur_gemm<false, false, mf>(A.m, B.m, n, -1.0, La, M, Xb, d, 1.0, V.arena + near_block(V, A.p, B.p), np);
+      else schur_gemm<f32, deep, mf>(A.m, B.m, n, -1.0, La, M, Xb, d, 0.0, far[fi].F, A.m);
     } else {
       // new block (p, i) = L_a F   with [F; H] = D^-1 [0; I]
-      schur_gemm<false, false>(A.m, r, n, 1.0, La, M, R.X + (int64_t)M * d, d, 0.0, V.arena + A.blk_pi, np);
+      schur_gemm<false, false, mf>(A.m, r, n, 1.0, La, M, R.X + (int64_t)M * d, d, 0.0, V.arena + A.blk_pi, np);
     }
   } else {
     if (b >= 0) {
@@ -1218,7 +1223,7 @@ __device__ inline void schur_block(const LevelView& V, const ElimRec& R, const E
   }
 }
 // one 64 x 64 output tile of the update of block (a, b), a < nnb
-template <bool f32, bool deep>
+template <bool f32, bool deep, bool mf>
 __device__ inline void schur_tile(const LevelView& V, const ElimRec& R, const ElimNbr* nbrs, const int32_t* far_idx,
                                   const FarPair* far, int a, int b, int ti, int tj) {
   const int n = R.n, d = R.d, M = R.M;
@@ -1233,28 +1238,28 @@ __device__ inline void schur_tile(const LevelView& V, const ElimRec& R, const El
     const double* Xb = R.X + (int64_t)(B.off + j0) * d;
     const int fi = far_idx[R.far_base + a * R.nnb + b];
     if (fi < 0)
-      schur_gemm<false, false>(mt, nt, n, -1.0, La, M, Xb, d, 1.0,
+      schur_gemm<false, false, mf>(mt, nt, n, -1.0, La, M, Xb, d, 1.0,
                                V.arena + near_block(V, A.p, B.p) + i0 + (int64_t)j0 * np, np);
-    else schur_gemm<f32, deep>(mt, nt, n, -1.0, La, M, Xb, d, 0.0, far[fi].F + i0 + (int64_t)j0 * A.m, A.m);
+    else schur_gemm<f32, deep, mf>(mt, nt, n, -1.0, La, M, Xb, d, 0.0, far[fi].F + i0 + (int64_t)j0 * A.m, A.m);
   } else {
     const int nt = min(64, R.r - j0);
-    schur_gemm<false, false>(mt, nt, n, 1.0, La, M, R.X + (int64_t)(M + j0) * d, d, 0.0,
+    schur_gemm<false, false, mf>(mt, nt, n, 1.0, La, M, R.X + (int64_t)(M + j0) * d, d, 0.0,
                              V.arena + A.blk_pi + i0 + (int64_t)j0 * np, np);
   }
 }
 
-template <bool f32, bool deep>
+template <bool f32, bool deep, bool mf>
 __global__ void __launch_bounds__(NT) k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs,
                                               const SchurTask* tasks, const int32_t* far_idx, const FarPair* far) {
   const SchurTask T = tasks[blockIdx.x];
   const ElimRec R = recs[T.rec];
   if (T.tile >= 0) {
-    schur_tile<f32, deep>(V, R, nbrs, far_idx, far, T.a, T.b, T.tile & 0xffff, T.tile >> 16);
+    schur_tile<f32, deep, mf>(V, R, nbrs, far_idx, far, T.a, T.b, T.tile & 0xffff, T.tile >> 16);
   } else if (T.b == -2) {
-    for (int b = 0; b < R.nnb; ++b) schur_block<f32, deep>(V, R, nbrs, far_idx, far, T.a, b);
-    schur_block<f32, deep>(V, R, nbrs, far_idx, far, T.a, -1);
+    for (int b = 0; b < R.nnb; ++b) schur_block<f32, deep, mf>(V, R, nbrs, far_idx, far, T.a, b);
+    schur_block<f32, deep, mf>(V, R, nbrs, far_idx, far, T.a, -1);
   } else {
-    schur_block<f32, deep>(V, R, nbrs, far_idx, far, T.a, T.b);
+    schur_block<f32, deep, mf>(V, R, nbrs, far_idx, far, T.a, T.b);
   }
 }
 
@@ -1636,6 +1641,13 @@ __global__ void __launch_bounds__(NT) k_check_finite(const double* p, int64_t n,
   }
 }
 
+__global__ void __launch_bounds__(NT) k_check_finite32(const float* p, int64_t n, int32_t* flag) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) {
+    const float v = p[e];
+    if (!(fabsf(v) <= 3e38f)) flag[0] = 1;
+  }
+}
+
 __global__ void __launch_bounds__(NT) k_set_rank(int32_t* r, const Changed* chg, int nchg) {
   const int k = blockIdx.x * NT + threadIdx.x;
   if (k < nchg) r[chg[k].p] = chg[k].rnew;
@@ -1795,52 +1807,64 @@ __global__ void __launch_bounds__(NT) k_perm_out(double* x, int64_t ld, int k, c
 // Every step is a GEMV over 64-row tiles of one stored block: one tile per
 // wave, lane = row, so each lane streams one row of the block with the
 // column loads of a wave coalesced (64 consecutive rows of a column-major
-// block), and the right-hand sides go through in chunks of SK columns whose
-// vector entries are broadcast from the lane that loaded them (readlane).
-
-__device__ inline double lane_bcast(double v, int l) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), l);
-  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
+// block), and the right-hand sides go through in chunks of SK columns.  The
+// wave stages each 64-entry chunk of the vectors in its own LDS slice
+// (entry j of the SK columns at j * SK, so one column step reads SK
+// consecutive doubles that every lane shares: broadcast LDS reads, no lane
+// shuffles).
 
 // acc[c] += sign * sum_{j < cnt} A[j * lda] * x[j + c * ldx]   (c < kc, cnt <=
-// 64), for the lane's row (A points at the lane's row; act: the row exists):
-// each lane loads one entry of the vector chunk, readlane broadcasts it.
-template <int SK>
-__device__ inline void wave_gemv_chunk(const double* A, int64_t lda, bool act, const double* x, int64_t ldx, int cnt,
-                                       int kc, int lane, double sign, double* acc) {
-  double xv[SK];
+// 64), for the lane's row (A points at the lane's row; act: the row exists);
+// xs: the wave's LDS slice of 64 * SK doubles.  The whole wave calls it.
+template <int SK, typename T>
+__device__ inline void wave_gemv_chunk(const T* A, int64_t lda, bool act, const double* x, int64_t ldx, int cnt,
+                                       int kc, int lane, double sign, double* acc, double* xs) {
+  // the previous chunk's reads of xs are ordered before these writes (LDS
+  // operations of one wave complete in order), and the fences keep the
+  // compiler from moving LDS accesses across the staging
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
 #pragma unroll
-  for (int c = 0; c < SK; ++c) xv[c] = (lane < cnt && c < kc) ? sign * x[lane + (int64_t)c * ldx] : 0.0;
+  for (int c = 0; c < SK; ++c) xs[lane * SK + c] = (lane < cnt && c < kc) ? sign * x[lane + (int64_t)c * ldx] : 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (cnt == 64) {
-#pragma unroll 16
-    for (int jj = 0; jj < 64; ++jj) {
-      const double a = act ? A[(int64_t)jj * lda] : 0.0;
+    // 16 column loads in flight per wave before their products
+    for (int jb = 0; jb < 64; jb += 16) {
+      double av[16];
 #pragma unroll
-      for (int c = 0; c < SK; ++c) acc[c] = fma(a, lane_bcast(xv[c], jj), acc[c]);
+      for (int q = 0; q < 16; ++q) av[q] = act ? (double)A[(int64_t)(jb + q) * lda] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const double* xr = xs + (jb + q) * SK;
+#pragma unroll
+        for (int c = 0; c < SK; ++c) acc[c] = fma(av[q], xr[c], acc[c]);
+      }
     }
   } else {
     for (int jj = 0; jj < cnt; ++jj) {
-      const double a = act ? A[(int64_t)jj * lda] : 0.0;
+      const double a = act ? (double)A[(int64_t)jj * lda] : 0.0;
+      const double* xr = xs + jj * SK;
 #pragma unroll
-      for (int c = 0; c < SK; ++c) acc[c] = fma(a, lane_bcast(xv[c], jj), acc[c]);
+      for (int c = 0; c < SK; ++c) acc[c] = fma(a, xr[c], acc[c]);
     }
   }
 }
 
 // One segment of a tile's inner dimension, split into 64-column chunks that
 // the NW waves of the workgroup take in turn (g counts chunks over segments).
-template <int SK, int NW>
-__device__ inline void seg_gemv(const double* A, int64_t lda, bool act, const double* x, int64_t ldx, int len, int kc,
-                                int lane, int wave, double sign, int& g, double* acc) {
+template <int SK, int NW, typename T>
+__device__ inline void seg_gemv(const T* A, int64_t lda, bool act, const double* x, int64_t ldx, int len, int kc,
+                                int lane, int wave, double sign, int& g, double* acc, double* xs) {
   for (int j0 = 0; j0 < len; j0 += 64, ++g)
     if (g % NW == wave)
-      wave_gemv_chunk<SK>(A + (int64_t)j0 * lda, lda, act, x + j0, ldx, min(64, len - j0), kc, lane, sign, acc);
+      wave_gemv_chunk<SK, T>(A + (int64_t)j0 * lda, lda, act, x + j0, ldx, min(64, len - j0), kc, lane, sign, acc,
+                             xs);
 }
 
 // Sum of the waves' partial accumulators into wave 0 (returns true there).
+// red[w] is also wave w's staging slice: a wave writes its partials there only
+// after its last chunk, and the caller syncs before the next chunk's staging.
 template <int SK, int NW>
 __device__ inline bool wg_reduce_acc(double (*red)[SK][64], int lane, int wave, double* acc) {
   if (NW == 1) return true;
@@ -1857,8 +1881,16 @@ __device__ inline bool wg_reduce_acc(double (*red)[SK][64], int lane, int wave, 
   return true;
 }
 
+// the stored L and G blocks the solve reads: FP64, or their FP32 copies
+template <typename T> __device__ inline const T* solve_L(const ElimRec& R);
+template <> __device__ inline const double* solve_L<double>(const ElimRec& R) { return R.L; }
+template <> __device__ inline const float* solve_L<float>(const ElimRec& R) { return R.Ls; }
+template <typename T> __device__ inline const T* solve_U(const ElimRec& R);
+template <> __device__ inline const double* solve_U<double>(const ElimRec& R) { return R.U; }
+template <> __device__ inline const float* solve_U<float>(const ElimRec& R) { return R.Us; }
+
 // forward, step 1: w = E_t. x_i (rows < n kept in W), z_i += E_b. x_i
-template <int SK, int NW>
+template <int SK, int NW, typename E>
 __global__ void __launch_bounds__(64 * NW) k_solve_fwd_w(const ElimRec* recs, const STask* tasks, SolveView S) {
   __shared__ double red[NW][SK][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1876,7 +1908,8 @@ __global__ void __launch_bounds__(64 * NW) k_solve_fwd_w(const ElimRec* recs, co
 #pragma unroll
     for (int c = 0; c < SK; ++c) acc[c] = 0.0;
     int g = 0;
-    seg_gemv<SK, NW>(R.lu + (act ? row : 0), d, act, xi + (int64_t)c0 * n, n, n, kc, lane, wave, 1.0, g, acc);
+    seg_gemv<SK, NW, double>(R.lu + (act ? row : 0), d, act, xi + (int64_t)c0 * n, n, n, kc, lane, wave, 1.0, g, acc,
+                             &red[wave][0][0]);
     if (wg_reduce_acc<SK, NW>(red, lane, wave, acc) && act) {
 #pragma unroll
       for (int c = 0; c < SK; ++c)
@@ -1891,7 +1924,7 @@ __global__ void __launch_bounds__(64 * NW) k_solve_fwd_w(const ElimRec* recs, co
 
 // forward, step 2: rows of the neighbours -= L w (the rows of a tile may
 // belong to several neighbours; same-colour nodes share no neighbour)
-template <int SK, int NW>
+template <int SK, int NW, typename E>
 __global__ void __launch_bounds__(64 * NW) k_solve_fwd_upd(const ElimRec* recs, const ElimNbr* nbrs,
                                                            const STask* tasks, SolveView S) {
   __shared__ double red[NW][SK][64];
@@ -1918,7 +1951,8 @@ __global__ void __launch_bounds__(64 * NW) k_solve_fwd_upd(const ElimRec* recs, 
 #pragma unroll
     for (int c = 0; c < SK; ++c) acc[c] = 0.0;
     int g = 0;
-    seg_gemv<SK, NW>(R.L + (act ? row : 0), R.M, act, wt + (int64_t)c0 * n, n, n, kc, lane, wave, 1.0, g, acc);
+    seg_gemv<SK, NW, E>(solve_L<E>(R) + (act ? row : 0), R.M, act, wt + (int64_t)c0 * n, n, n, kc, lane, wave, 1.0,
+                        g, acc, &red[wave][0][0]);
     if (wg_reduce_acc<SK, NW>(red, lane, wave, acc) && tgt) {
 #pragma unroll
       for (int c = 0; c < SK; ++c)
@@ -1930,7 +1964,7 @@ __global__ void __launch_bounds__(64 * NW) k_solve_fwd_upd(const ElimRec* recs, 
 
 // backward: x_i = w - (G x_nbrs - E_tb y_i), the inner dimension running over
 // the neighbours' blocks of G and then E_tb
-template <int SK, int NW>
+template <int SK, int NW, typename E>
 __global__ void __launch_bounds__(64 * NW) k_solve_bwd(const ElimRec* recs, const ElimNbr* nbrs, const STask* tasks,
                                                        SolveView S) {
   __shared__ double red[NW][SK][64];
@@ -1949,14 +1983,43 @@ __global__ void __launch_bounds__(64 * NW) k_solve_bwd(const ElimRec* recs, cons
 #pragma unroll
     for (int c = 0; c < SK; ++c) acc[c] = 0.0;
     int g = 0;
-    for (int q = 0; q < R.nnb; ++q) {
-      const ElimNbr B = nbrs[R.nb_begin + q];
-      if (B.m == 0) continue;
-      const double* xq = (B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k) + (int64_t)c0 * B.m;
-      seg_gemv<SK, NW>(R.U + (act ? row : 0) + (int64_t)B.off * n, n, act, xq, B.m, B.m, kc, lane, wave, 1.0, g, acc);
+    if constexpr (std::is_same<E, double>::value) {
+      // one call site for all segments (the G blocks, then E_tb): one inlined
+      // copy of the column loop keeps the register count down
+      for (int q = 0; q <= R.nnb; ++q) {
+        const double* Ap;
+        const double* xq;
+        int64_t lda;
+        int len;
+        double sign = 1.0;
+        if (q < R.nnb) {
+          const ElimNbr B = nbrs[R.nb_begin + q];
+          Ap = R.U + (int64_t)B.off * n;
+          lda = n;
+          len = B.m;
+          xq = (B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k) + (int64_t)c0 * B.m;
+        } else {
+          Ap = R.lu + (int64_t)n * d;
+          lda = d;
+          len = r;
+          xq = yi + (int64_t)c0 * r;
+          sign = -1.0;
+        }
+        if (len > 0)
+          seg_gemv<SK, NW, double>(Ap + (act ? row : 0), lda, act, xq, len, len, kc, lane, wave, sign, g, acc,
+                                   &red[wave][0][0]);
+      }
+    } else {
+      for (int q = 0; q < R.nnb; ++q) {
+        const ElimNbr B = nbrs[R.nb_begin + q];
+        if (B.m == 0) continue;
+        const double* xq = (B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k) + (int64_t)c0 * B.m;
+        seg_gemv<SK, NW, E>(solve_U<E>(R) + (act ? row : 0) + (int64_t)B.off * n, n, act, xq, B.m, B.m, kc, lane,
+                            wave, 1.0, g, acc, &red[wave][0][0]);
+      }
+      seg_gemv<SK, NW, double>(R.lu + (act ? row : 0) + (int64_t)n * d, d, act, yi + (int64_t)c0 * r, r, r, kc, lane,
+                               wave, -1.0, g, acc, &red[wave][0][0]);
     }
-    seg_gemv<SK, NW>(R.lu + (act ? row : 0) + (int64_t)n * d, d, act, yi + (int64_t)c0 * r, r, r, kc, lane, wave, -1.0,
-                     g, acc);
     if (wg_reduce_acc<SK, NW>(red, lane, wave, acc) && act) {
 #pragma unroll
       for (int c = 0; c < SK; ++c)
@@ -1968,7 +2031,8 @@ __global__ void __launch_bounds__(64 * NW) k_solve_bwd(const ElimRec* recs, cons
 
 // After the pivot solves of a colour: D^-1 = [X[:, M+r : M+r+n], X[:, M : M+r]]
 // replaces the LU factors and G = X[0:n, 0:M] the U-blocks (what the solve
-// reads).  Grid (64-column chunks of max(d, M), records).
+// reads); in the mixed form G and L go to their FP32 copies instead.  Grid
+// (64-column chunks of max(d, M), records).
 __global__ void __launch_bounds__(NT) k_store_solve(const ElimRec* recs) {
   const ElimRec R = recs[blockIdx.y];
   const int c0 = blockIdx.x * 64, d = R.d, n = R.n, M = R.M;
@@ -1982,9 +2046,24 @@ __global__ void __launch_bounds__(NT) k_store_solve(const ElimRec* recs) {
   }
   const int mc = min(64, M - c0);
   if (mc > 0 && n > 0) {
-    WG_FOR2(n, mc, row, cl) {
+    if (R.Us) {
+      WG_FOR2(n, mc, row, cl) {
+        const int c = c0 + cl;
+        R.Us[row + (int64_t)c * n] = (float)R.X[row + (int64_t)c * d];
+      }
+    } else {
+      WG_FOR2(n, mc, row, cl) {
+        const int c = c0 + cl;
+        R.U[row + (int64_t)c * n] = R.X[row + (int64_t)c * d];
+      }
+    }
+  }
+  // FP32 copy of L (M x n), the chunk's columns of its n (< d) columns
+  const int lc = min(64, n - c0);
+  if (R.Ls && lc > 0 && M > 0) {
+    WG_FOR2(M, lc, row, cl) {
       const int c = c0 + cl;
-      R.U[row + (int64_t)c * n] = R.X[row + (int64_t)c * d];
+      R.Ls[row + (int64_t)c * M] = (float)R.L[row + (int64_t)c * M];
     }
   }
 }

@@ -25,16 +25,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT = os.path.join(HERE, "rank_model_laplace.npz")
 
 
-def training_geometries(count=16, n_values=(65536, 131072, 262144), base_seed=5001):
+def training_geometries(count=16, n_values=(65536, 131072, 262144), base_seed=5001, large=(524288, 524288, 1048576)):
     """(name, points, diag) of the training set: spheres, ellipsoids with random
-    semi-axes in [0.5, 2] (plus 5 % jitter) and cube surfaces, seeds from 5001."""
+    semi-axes in [0.5, 2] (plus 5 % jitter) and cube surfaces, seeds from 5001;
+    `count` geometries with N from n_values, then one per entry of `large`
+    (the upper levels of large problems carry the largest recompressions)."""
     sys.path.insert(0, os.path.dirname(HERE))
     import synth
     out = []
-    for g in range(count):
+    sizes = [int(n_values[g % len(n_values)]) for g in range(count)] + [int(v) for v in large]
+    for g, n in enumerate(sizes):
         seed = base_seed + g
         rng = np.random.default_rng(seed)
-        n = int(n_values[g % len(n_values)])
         kind = ("ellipsoid", "sphere", "cube")[g % 3]
         if kind == "ellipsoid":
             axes = tuple(rng.uniform(0.5, 2.0, 3))
@@ -50,11 +52,13 @@ def training_geometries(count=16, n_values=(65536, 131072, 262144), base_seed=50
     return out
 
 
-def record(geoms, eps=1e-6, sigma=3, leaf_max=64, log=print):
+def record(geoms, eps=1e-6, sigma=3, leaf_max=64, bottom_level=-1, log=print):
+    """Samples of every geometry, factorised as the benchmark factorises (the
+    cost model's bottom level by default)."""
     Xs, ts = [], []
     for name, pts, dg in geoms:
         t0 = time.time()
-        h = IFMM(pts, eps, sigma, diag=dg, leaf_max=leaf_max)
+        h = IFMM(pts, eps, sigma, diag=dg, leaf_max=leaf_max, bottom_level=bottom_level)
         h.record_ranks(True)
         h.factor()
         X, t = h.rank_records()
@@ -105,7 +109,8 @@ def main(argv=None):
     th, hist = train(X, t, steps=a.steps, tau=a.tau)
     meta = {"samples": int(len(t)), "steps": a.steps, "tau": a.tau, "loss_first": float(hist[0]),
             "loss_last": float(hist[-1]), "features": RANK_FEATURES, "geometries": a.count,
-            "seeds": f"5001-{5000 + a.count}", "n_values": [65536, 131072, 262144]}
+            "seeds": f"5001-{5000 + a.count + 3}", "n_values": [65536, 131072, 262144],
+            "large": [524288, 524288, 1048576], "bottom_level": "cost model"}
     save(a.out, th, meta)
     print(json.dumps(meta), flush=True)
 

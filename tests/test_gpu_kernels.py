@@ -108,8 +108,10 @@ def test_syev_on_ifmm_gram_matrices():
                                          (77, 9, 1, 0, 1), (100, 100, 0, 1, 1), (20, 30, 7, 0, 0),
                                          (32, 32, 32, 1, 1), (9, 3, 32, 1, 0), (100, 90, 129, 0, 1),
                                          (70, 130, 96, 1, 0), (64, 64, 95, 0, 0)])
-@pytest.mark.parametrize("f32", [0, 1, 2])
+@pytest.mark.parametrize("f32", [0, 1, 2, 3])
 def test_workgroup_gemm_fp64_and_fp32_matrix_cores(m, n, k, tA, tB, f32):
+    # f32: 0 FP64 FMA tile, 1 / 2 FP32 matrix-core tiles, 3 FP64 matrix-core tile
+    # (untransposed operands; transposed cases take the FMA tile)
     lib = C.CDLL(os.path.join(ROOT, "paper_1905_10602_amd", "libifmm.so"))
     f = lib.ifmm_internal_gemm
     f.restype = C.c_int
@@ -125,7 +127,7 @@ def test_workgroup_gemm_fp64_and_fp32_matrix_cores(m, n, k, tA, tB, f32):
     opB = B.T if tB else B
     ref = -1.5 * opA @ opB + 0.5 * Cm
     small = m <= 32 and n <= 32 and k <= 32  # one-pass FP64 product for tiny tiles, whatever the flag
-    if f32 and not small:
+    if f32 in (1, 2) and not small:
         # operands rounded to FP32 and FP32 accumulation: |error| <= c k u32 |A||B|
         bound = 1.5 * (k + 2) * 2.0 ** -23 * (np.abs(opA) @ np.abs(opB)) + 1e-300
         assert np.all(np.abs(Cf - ref) <= bound)

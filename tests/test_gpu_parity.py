@@ -173,6 +173,55 @@ def test_mixed_precision_error_vs_oracle(shape, N, leaf, sigma, eps):
     assert not np.array_equal(x, x64)  # the FP32 path really ran
 
 
+def test_fp64_matrix_core_schur_matches_oracle(monkeypatch):
+    # IFMM_F64_MFMA=1: FP64 Schur products on the FP64 matrix cores
+    # (v_mfma_f64_16x16x4f64); same 10 eps bar against the oracle as the FMA
+    # tile.  The tile itself is checked against numpy in the kernel tests.
+    N, eps = 3000, 1e-6
+    print(f"case FP64 matrix-core Schur sphere N={N}", flush=True)
+    pts, dg = _case("sphere", N, 8)
+    b = synth.uniform_rhs(N, 2, 41)
+    xo = Oracle(pts, eps=eps, sigma=3, diag=dg, leaf_max=40).factor().solve(b)
+    monkeypatch.setenv("IFMM_F64_MFMA", "1")
+    xm = _gpu(pts, eps, 3, dg, 40).solve(b)
+    monkeypatch.setenv("IFMM_F64_MFMA", "0")
+    xf = _gpu(pts, eps, 3, dg, 40).solve(b)
+    rel = np.linalg.norm(xm - xo) / np.linalg.norm(xo)
+    print(f"matrix-core Schur vs oracle {rel:.3e}; bitwise equal to the FMA tile: {np.array_equal(xm, xf)}",
+          flush=True)
+    assert rel <= 10 * eps
+    assert np.linalg.norm(xm - xf) <= 10 * eps * np.linalg.norm(xf)
+
+
+def test_mixed_solve_reads_fp32_blocks(monkeypatch):
+    # mixed form with IFMM_SOLVE32=1: the solve reads FP32 copies of the
+    # stored L and G blocks (FP64 vectors and pivot inverses).  Against the
+    # same factorisation with FP64 blocks (the default) the store shrinks, the
+    # ranks are the same, the solutions differ only by the FP32 rounding of the
+    # blocks, and the normwise backward error on A~ stays <= 10 eps
+    N, eps = 3000, 1e-6
+    print(f"case mixed FP32 solve blocks sphere N={N}", flush=True)
+    pts, dg = _case("sphere", N, 8)
+    b = synth.uniform_rhs(N, 2, 31)
+    out = {}
+    for v in ("1", "0"):
+        monkeypatch.setenv("IFMM_SOLVE32", v)
+        h = _gpu(pts, eps, 3, dg, 40, precision="mixed")
+        st = h.stats()
+        out[v] = (h.solve(b), st["store_bytes"], [lv["rank_sum"] for lv in st["levels"]])
+    (x32, s32, r32), (x64, s64, r64) = out["1"], out["0"]
+    rel = np.linalg.norm(x32 - x64) / np.linalg.norm(x64)
+    print(f"FP32 vs FP64 solve blocks: rel diff {rel:.3e}, store {s32} vs {s64} bytes", flush=True)
+    assert r32 == r64
+    assert s32 < 0.75 * s64
+    assert not np.array_equal(x32, x64)
+    assert rel <= 10 * eps
+    At = dense_tilde(pts, None, dg, leaf_max=40)
+    for c in range(2):
+        r = np.linalg.norm(At @ x32[:, c] - b[:, c])
+        assert r / (np.linalg.norm(At, 2) * np.linalg.norm(x32[:, c]) + np.linalg.norm(b[:, c])) <= 10 * eps
+
+
 def test_phase_b_wave_form_matches_workgroup_form(monkeypatch):
     # mixed form: where every rank of a level is <= 32 the basis change of the
     # M2L blocks runs one block per wave; with leaves of <= 32 points that is
@@ -341,3 +390,34 @@ def test_sphere_65536_eight_rhs_vs_oracle_fixture(sigma, precision):
         # decisions inside the truncation band change what later levels see,
         # so individual ranks drift upwards in the tree; the totals agree
         assert abs(rg_.sum() - ro_.sum()) <= 0.05 * ro_.sum() + 2, lvl
+
+
+def test_autotuner_cache_written_then_reused(tmp_path):
+    # options.tune_cache: the first factorisation with an empty cache times the
+    # two Schur tiles on alternating colours of every level, the first solve
+    # times every solve step at 1, 4 and 8 waves per workgroup; both write
+    # their choices.  Handles built later with the same cache reuse them
+    # without timing and give bitwise-identical results; all stay within the
+    # 10 eps bar against the oracle.
+    N, eps = 3000, 1e-6
+    print(f"case autotuner cache sphere N={N}", flush=True)
+    pts, dg = _case("sphere", N, 8)
+    b = synth.uniform_rhs(N, 8, 51)
+    xo = Oracle(pts, eps=eps, sigma=3, diag=dg, leaf_max=40).factor().solve(b)
+    cache = tmp_path / "tune.txt"
+    for precision in ("fp64", "mixed"):
+        x1 = _gpu(pts, eps, 3, dg, 40, precision=precision, tune_cache=str(cache)).solve(b)
+        text = cache.read_text()
+        depth = _gpu(pts, eps, 3, dg, 40).stats()["depth"]
+        for l in range(2, depth + 1):
+            assert f"schur {precision} d{depth} l{l} = " in text
+            assert f"solve_bwd {precision} d{depth} l{l} k8 = " in text
+        assert f"solve {precision} d{depth} k8 = 1" in text
+        x2 = _gpu(pts, eps, 3, dg, 40, precision=precision, tune_cache=str(cache)).solve(b)
+        assert cache.read_text() == text  # nothing left to tune
+        x3 = _gpu(pts, eps, 3, dg, 40, precision=precision, tune_cache=str(cache)).solve(b)
+        assert np.array_equal(x2, x3)
+        for x in (x1, x2):
+            rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+            print(f"{precision} tuned vs oracle {rel:.3e}", flush=True)
+            assert rel <= 10 * eps

@@ -102,3 +102,48 @@ def test_learned_rank_factorisation():
     print(f"full eigen-decompositions: {st['changed']} without sketches, {full_with} with the model; "
           f"heuristic sketch: {s0['sketches']} tried, {s0['sketches_rejected']} rejected", flush=True)
     assert st["sketches"] - st["sketches_rejected"] > 0
+
+
+def test_trained_model_against_rule_on_held_out_geometry():
+    # What the committed network gains over the rule without it, on a geometry
+    # outside its training set (ellipsoid, seed 6001, N = 131,072, eps 1e-6,
+    # sigma 3, cost-model bottom level): every sketch-eligible recompression is
+    # recorded with the rank the full truncation chose.  A sketch of width s
+    # can only be accepted when that rank is below s.  Compared: the model's
+    # widths (prediction + max(8, pred / 8)) and the rule's (current rank +
+    # max(16, r / 4)).  On its training geometries the model misses the rank
+    # about ten times less often than the rule at the same mean width; on this
+    # held-out geometry the two are about even (4.5 % against 4.2 % misses,
+    # mean widths 85.0 and 85.7), so the test asserts only that the model is
+    # no worse than the rule by more than a small margin, and prints both.
+    # The factor time at N = 1M is reported by the benchmark (the
+    # learned_rank_ablation entry), not asserted here.
+    from paper_1905_10602_amd import IFMM, rank_model_eval
+    from paper_1905_10602_amd.rank_model import load
+    theta, meta = load()
+    N, eps = 131072, 1e-6
+    print(f"case trained model vs rule: ellipsoid seed 6001 N={N}", flush=True)
+    axes = (1.0, 0.6, 0.4)
+    pts = synth.ellipsoid_points(N, 6001, axes=axes, jitter=0.05)
+    h = IFMM(pts, eps, 3, diag=synth.laplace_self_term(N, synth.ellipsoid_area(axes)), leaf_max=64,
+             bottom_level=-1)
+    h.record_ranks(True)
+    h.factor()
+    X, t = h.rank_records()
+    h.close()
+    assert len(t) > 1000
+    n = np.rint(X[:, 4] * 1024).astype(np.int64)
+    r = np.rint(X[:, 5] * 512).astype(np.int64)
+    rnew = np.rint(t * n).astype(np.int64)
+    fr = np.clip(rank_model_eval(theta, X), 0.0, 1.0)
+    pred = np.maximum(1, np.ceil(fr * n)).astype(np.int64)
+    s_model = np.minimum(n, pred + np.maximum(8, pred // 8))
+    s_rule = np.minimum(n, r + np.maximum(16, r // 4))
+    both = (s_model <= 0.6 * n) & (s_rule <= 0.6 * n)
+    miss_model = float(np.mean(rnew[both] >= s_model[both]))
+    miss_rule = float(np.mean(rnew[both] >= s_rule[both]))
+    w_model, w_rule = float(np.mean(s_model[both])), float(np.mean(s_rule[both]))
+    print(f"{int(both.sum())} recompressions: rank above the width {miss_model:.4f} (model) vs {miss_rule:.4f} "
+          f"(rule); mean width {w_model:.1f} vs {w_rule:.1f}; model trained on {meta['samples']} samples", flush=True)
+    assert miss_model <= 1.5 * miss_rule + 0.01
+    assert w_model <= 1.1 * w_rule
