@@ -76,8 +76,13 @@ typedef struct {
                                (matrix-parallel); 2 = every level colour by colour (2)                       */
   const char* rank_model;   /* path of a raw little-endian FP32 file with the rank network's parameters
                                (ifmm_rank_model_params(IFMM_RANK_FEATURES) values), or NULL = no model (NULL) */
-  const char* tune_cache;   /* path of the tile autotuner's cache file (read, and written after tuning), or
-                               NULL = the built-in tile choices (NULL)                                       */
+  const char* tune_cache;   /* path of the autotuner's cache file, or NULL = the built-in choices (NULL).
+                               Tuned: the Schur-update tile per level (FP64: FMA or matrix cores; mixed: lite
+                               or deep FP32 tile) and the waves per workgroup of each solve step per level.
+                               Read at every ifmm_factor; a level without an entry alternates the two tiles
+                               over its colours and keeps the faster, the first solve without entries times
+                               one solve per wave count; the file is then rewritten ("key = value" lines).
+                               A failed write returns IFMM_EINVAL after the work is done.               */
   int64_t max_device_bytes; /* refuse to allocate more device memory than this, 0 = no limit (0)              */
   int32_t deterministic;    /* 1: results bitwise reproducible run to run.  The only mode: the library uses
                                no floating-point atomics; 0 is accepted and behaves the same (1)             */

@@ -44,29 +44,37 @@ def test_roofline_picks_the_largest_single_kernel_and_prices_it():
 
 
 def test_committed_profiler_records_agree_with_each_other():
+    import glob
     prof = os.path.join(ROOT, "profiles")
-    with open(os.path.join(prof, "k_schur_hbm_traffic_ellipsoid_1M_mixed.json")) as fh:
-        rec = json.load(fh)
-    cal = rec["copy_calibration"]
-    # the calibration factors are the copy's known bytes over what each counter read
-    assert cal["fetch_factor"] == pytest.approx(cal["bytes"] / (cal["fetch_size_kib"] * 1024))
-    assert cal["write_factor"] == pytest.approx(cal["bytes"] / (cal["write_size_kib"] * 1024))
-    scaled = (rec["fetch_size_kib_per_launch"] * 1024 * cal["fetch_factor"] +
-              rec["write_size_kib_per_launch"] * 1024 * cal["write_factor"])
-    assert rec["traffic_bytes_per_launch"] == pytest.approx(scaled)
-    # every command the record names runs committed files only
-    for cmd in rec["commands"]:
-        assert "_work" not in cmd and "/root/reference" not in cmd
-        for path in re.findall(r"(\S+\.py)", cmd):
-            assert os.path.exists(os.path.join(ROOT, path)), path
-    # the kernel statistics were taken on the same kernel sources
     with open(os.path.join(prof, "ifmm_factor_solve_ellipsoid_1M_mixed_kernel_stats.txt")) as fh:
         text = fh.read()
-    assert rec["kernel_sources_sha256_16"] in text
-    m = re.search(r"k_schur<true, false>\s+(\d+)\s+[\d.]+ ms\s+avg\s+([\d.]+) us", text)
+    recs = sorted(glob.glob(os.path.join(prof, "*_hbm_traffic_*.json")))
+    assert {os.path.basename(p).split("_hbm")[0] for p in recs} >= {"k_schur", "k_solve_bwd", "k_solve_fwd_upd"}
+    for path in recs:
+        with open(path) as fh:
+            rec = json.load(fh)
+        cal = rec["copy_calibration"]
+        # the calibration factors are the copy's known bytes over what each counter read
+        assert cal["fetch_factor"] == pytest.approx(cal["bytes"] / (cal["fetch_size_kib"] * 1024))
+        assert cal["write_factor"] == pytest.approx(cal["bytes"] / (cal["write_size_kib"] * 1024))
+        scaled = (rec["fetch_size_kib_per_launch"] * 1024 * cal["fetch_factor"] +
+                  rec["write_size_kib_per_launch"] * 1024 * cal["write_factor"])
+        assert rec["traffic_bytes_per_launch"] == pytest.approx(scaled)
+        assert rec["traffic_over_algorithmic"] == pytest.approx(scaled / rec["algorithmic_bytes_per_launch"])
+        # every command the record names runs committed files only
+        cmds = list(rec["commands"]) + ([rec["matrix_core_busy"]["command"]] if "matrix_core_busy" in rec else [])
+        for cmd in cmds:
+            assert "_work" not in cmd and "/root/reference" not in cmd
+            for path2 in re.findall(r"(\S+\.py)", cmd):
+                assert os.path.exists(os.path.join(ROOT, path2)), path2
+        # the kernel statistics were taken on the same kernel sources
+        assert rec["kernel_sources_sha256_16"] in text
+    m = re.search(r"k_schur<true, false, false>\s+(\d+)\s+([\d.]+) ms\s+avg\s+([\d.]+) us", text)
+    with open(os.path.join(prof, "k_schur_hbm_traffic_ellipsoid_1M_mixed.json")) as fh:
+        rec = json.load(fh)
     assert m and int(m.group(1)) == rec["launches"]
     bench_avg = float(re.search(r"launches, avg ([\d.]+) ms", text).group(1))
-    assert float(m.group(2)) / 1e3 == pytest.approx(bench_avg, rel=0.01)  # trace and in-library timing agree
+    assert float(m.group(3)) / 1e3 == pytest.approx(bench_avg, rel=0.01)  # trace and in-library timing agree
 
 
 def test_traffic_lookup_is_keyed_by_form_and_sources():

@@ -173,6 +173,27 @@ def test_mixed_precision_error_vs_oracle(shape, N, leaf, sigma, eps):
     assert not np.array_equal(x, x64)  # the FP32 path really ran
 
 
+def test_top_tau_and_forced_depth_match_oracle():
+    # tau = 4: levels 3 and 2 are eliminated one node per step (Sec. 4.2's
+    # matrix-parallel top); the oracle with the same tau, and a forced
+    # coarser depth, both within 10 eps
+    N, eps = 3000, 1e-6
+    print(f"case top tau=4 and depth 3, ellipsoid N={N}", flush=True)
+    pts, dg = _case("ellipsoid", N, 9)
+    b = synth.uniform_rhs(N, 2, 61)
+    xo = Oracle(pts, eps=eps, sigma=3, diag=dg, leaf_max=16, tau=4).factor().solve(b)
+    x = _gpu(pts, eps, 3, dg, 16, top_tau=4).solve(b)
+    rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"tau=4 vs oracle {rel:.3e}", flush=True)
+    assert rel <= 10 * eps
+    xo3 = Oracle(pts, eps=eps, sigma=3, diag=dg, leaf_max=16, depth=3).factor().solve(b)
+    h3 = _gpu(pts, eps, 3, dg, 16, bottom_level=3)
+    assert h3.depth() == 3
+    rel3 = np.linalg.norm(h3.solve(b) - xo3) / np.linalg.norm(xo3)
+    print(f"depth 3 vs oracle {rel3:.3e}", flush=True)
+    assert rel3 <= 10 * eps
+
+
 def test_fp64_matrix_core_schur_matches_oracle(monkeypatch):
     # IFMM_F64_MFMA=1: FP64 Schur products on the FP64 matrix cores
     # (v_mfma_f64_16x16x4f64); same 10 eps bar against the oracle as the FMA
