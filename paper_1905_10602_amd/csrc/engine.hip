@@ -896,16 +896,14 @@ static void enqueue_blocked_lu(const BluTask* d_blu, unsigned nb, int dmax, int 
   }
 }
 
-static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
-  const Level& T = h.tree.levels[l];
-  DevLevel& L = h.lv[l];
-  const int K = h.K;
-  const int g0 = T.grp_ptr[c], g1 = T.grp_ptr[c + 1];
-  const int nrec = g1 - g0;
-  if (nrec == 0) return 0;
-  HostLap lap(h);
-  // ---- records, neighbour entries, far pairs, changed nodes (host; sizes are known)
-  std::vector<ElimRec> recs(nrec);
+// State of one colour's elimination, shared by its steps: the host tables
+// (records, neighbour entries, far pairs, changed nodes, tasks), their device
+// copies in the meta buffer, the algorithmic counts, and the recompression's
+// per-task bookkeeping.
+struct ColourWork {
+  int l = 0, c = 0, g0 = 0, nrec = 0, sides = 1, nchg = 0, nbase = 0;
+  bool sym = true;
+  std::vector<ElimRec> recs;
   std::vector<ElimNbr> nbrs;
   std::vector<int32_t> far_idx;
   std::vector<FarPair> far;
@@ -913,19 +911,72 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   std::vector<FarRef> refs;
   std::vector<SchurTask> tasks;
   std::vector<XTask> xtasks;
+  std::vector<EigTask> etasks;  // per changed node and side: its Gram matrix
+  std::vector<int64_t> dinv_off;
+  double* S0 = nullptr;         // colour scratch
+  std::vector<BluTask> blu;     // large pivots (blocked LU)
+  std::vector<int32_t> blu_rec;
+  int blu_dmax = 0, blu_wmax = 0;
+  char* M = nullptr;            // meta buffer (device tables)
+  size_t o_blu = 0, o_blur = 0;
+  const ElimRec* d_recs = nullptr;
+  const ElimNbr* d_nbrs = nullptr;
+  const SchurTask* d_tasks = nullptr;
+  const int32_t* d_fidx = nullptr;
+  const FarPair* d_far = nullptr;
+  Changed* d_chg = nullptr;
+  const FarRef* d_refs = nullptr;
+  const EigTask* d_et = nullptr;
+  int32_t* d_cnt = nullptr;
+  int32_t* d_info = nullptr;
+  const XTask* d_xt = nullptr;
+  LevelView V;
+  double fl_lu = 0, fl_x = 0, fl_schur = 0, by_gather = 0, by_schur = 0, fl_gram = 0, fl_ev = 0, fl_evec = 0;
+  // recompression: counts per task, pivot info per record, the tasks that
+  // ended with a full decomposition and the accepted sketches
+  std::vector<int32_t> cnt, info, full_ids, sk_ids, fe_ids;
+  std::vector<EigTask> fullT, skE;
+  std::vector<SkTask> skT;
+  std::vector<float> rfeat;
+  // capacity growth of M2L blocks (moves of slot pointers, new capacities)
+  std::vector<SlotMove> moves;
+  std::vector<int32_t> capset;
+};
+
+// Records, neighbour entries, far pairs, Schur and pivot-solve tasks, changed
+// nodes; scratch offsets and persistent factor storage, in record order.
+static int colour_tables(Handle& h, ColourWork& W, std::string& err) {
+  const int l = W.l, c = W.c, nrec = W.nrec, sides = W.sides, K = h.K;
+  const bool sym = W.sym;
+  const Level& T = h.tree.levels[l];
+  DevLevel& L = h.lv[l];
+  auto& recs = W.recs;
+  auto& nbrs = W.nbrs;
+  auto& far_idx = W.far_idx;
+  auto& far = W.far;
+  auto& chg = W.chg;
+  auto& refs = W.refs;
+  auto& tasks = W.tasks;
+  auto& xtasks = W.xtasks;
+  auto& etasks = W.etasks;
+  auto& dinv_off = W.dinv_off;
+  auto& S0 = W.S0;
+  auto& cnt = W.cnt;
+  const int g0 = W.g0;
+  int rc = 0;
+  // ---- records, neighbour entries, far pairs, changed nodes (host; sizes are known)
+  recs.assign(nrec, ElimRec());
   int64_t sc = 0;  // scratch doubles
   auto stake = [&](int64_t cnt) {
     const int64_t o = sc;
     sc += (std::max<int64_t>(cnt, 1) + 31) & ~31LL;
     return o;
   };
-  std::vector<int64_t> x_off(nrec), dinv_off(nrec, 0), l_off(nrec, 0), u_off(nrec, 0);
+  std::vector<int64_t> x_off(nrec), l_off(nrec, 0), u_off(nrec, 0);
+  dinv_off.assign(nrec, 0);
   std::vector<std::vector<int64_t>> far_off_F, far_off_D;
   struct ChgOff { int64_t gs, gt, vs, vt, ws, wt, ls, lt, T, S, tmp; };
-  const bool sym = h.symmetric;
-  const int sides = sym ? 1 : 2;
   std::vector<ChgOff> coff;
-  const int nbase = (int)L.nbrs.size();
   // topology and sizes per record, in parallel over contiguous record chunks
   // (each chunk's entries are local; they are concatenated in record order)
   struct Part {
@@ -1056,7 +1107,6 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     ElimRec& R = recs[k];
     x_off[k] = stake((int64_t)R.d * (R.M + R.r + R.n));
     dinv_off[k] = R.inv ? stake((int64_t)((R.d + BLU_NB - 1) / BLU_NB) * 2 * 4096) : 0;
-    int rc;
     double* p;
     if ((rc = store_take(h, (int64_t)R.d * R.d, &R.lu, err))) return rc;
     if ((rc = store_take(h, (R.d + 1) / 2 + 1, &p, err))) return rc;
@@ -1119,9 +1169,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       chg.push_back(C);
     }
   }
-  int rc;
   if ((rc = ensure(h, (void**)&h.scratch, &h.scratch_bytes, sc * 8 + 256, err))) return rc;
-  double* S0 = h.scratch;
+  S0 = h.scratch;
   for (int k = 0; k < nrec; ++k) {
     recs[k].X = S0 + x_off[k];
     if (h.solve32) {
@@ -1130,7 +1179,6 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     }
   }
   for (size_t f = 0; f < far.size(); ++f) { far[f].F = S0 + fF[f]; far[f].D = S0 + fD[f]; }
-  std::vector<EigTask> etasks;
   for (size_t k = 0; k < chg.size(); ++k) {
     Changed& C = chg[k];
     const ChgOff& o = coff[k];
@@ -1139,7 +1187,53 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     etasks.push_back({C.gs, C.vs, C.ws, C.ls, nullptr, C.n, 0});
     if (!sym) etasks.push_back({C.gt, C.vt, C.wt, C.lt, nullptr, C.n, 0});
   }
-  lap.mark("tables");
+  return 0;
+}
+
+// Packs the tables into the meta buffer, uploads them, and counts the
+// algorithmic work of the phase-A steps from the block sizes.
+static int colour_upload(Handle& h, ColourWork& W, std::string& err) {
+  const int l = W.l, nrec = W.nrec, sides = W.sides;
+  DevLevel& L = h.lv[l];
+  auto& recs = W.recs;
+  auto& nbrs = W.nbrs;
+  auto& far_idx = W.far_idx;
+  auto& far = W.far;
+  auto& chg = W.chg;
+  auto& refs = W.refs;
+  auto& tasks = W.tasks;
+  auto& xtasks = W.xtasks;
+  auto& etasks = W.etasks;
+  auto& dinv_off = W.dinv_off;
+  auto& S0 = W.S0;
+  auto& blu = W.blu;
+  auto& blu_rec = W.blu_rec;
+  auto& blu_dmax = W.blu_dmax;
+  auto& blu_wmax = W.blu_wmax;
+  auto& M = W.M;
+  auto& o_blu = W.o_blu;
+  auto& o_blur = W.o_blur;
+  auto& d_recs = W.d_recs;
+  auto& d_nbrs = W.d_nbrs;
+  auto& d_tasks = W.d_tasks;
+  auto& d_fidx = W.d_fidx;
+  auto& d_far = W.d_far;
+  auto& d_chg = W.d_chg;
+  auto& d_refs = W.d_refs;
+  auto& d_et = W.d_et;
+  auto& d_cnt = W.d_cnt;
+  auto& d_info = W.d_info;
+  auto& d_xt = W.d_xt;
+  auto& V = W.V;
+  auto& nchg = W.nchg;
+  auto& fl_lu = W.fl_lu;
+  auto& fl_x = W.fl_x;
+  auto& fl_schur = W.fl_schur;
+  auto& by_gather = W.by_gather;
+  auto& by_schur = W.by_schur;
+  auto& fl_gram = W.fl_gram;
+  auto& fl_ev = W.fl_ev;
+  int rc = 0;
   // ---- pack the tables into the meta buffer
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t o_recs = 0;
@@ -1153,9 +1247,6 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   const size_t o_cnt = o_et + al(std::max<size_t>(etasks.size(), 1) * sizeof(EigTask));
   const size_t o_xt = o_cnt + al(std::max<size_t>(etasks.size(), 1) * 4);
   // large pivots (blocked LU of the augmented matrix, many workgroups each)
-  std::vector<BluTask> blu;
-  std::vector<int32_t> blu_rec;
-  int blu_dmax = 0, blu_wmax = 0;
   for (int k = 0; k < nrec; ++k)
     if (recs[k].inv) {
       const int W = recs[k].M + recs[k].r + recs[k].n;
@@ -1165,11 +1256,11 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       blu_wmax = std::max(blu_wmax, W);
     }
   const size_t o_info = o_xt + al(std::max<size_t>(xtasks.size(), 1) * sizeof(XTask));
-  const size_t o_blu = o_info + al((size_t)nrec * 4);
-  const size_t o_blur = o_blu + al(std::max<size_t>(blu.size(), 1) * sizeof(BluTask));
+  o_blu = o_info + al((size_t)nrec * 4);
+  o_blur = o_blu + al(std::max<size_t>(blu.size(), 1) * sizeof(BluTask));
   const size_t total = o_blur + al(std::max<size_t>(blu_rec.size(), 1) * 4);
   if ((rc = ensure(h, (void**)&h.meta, &h.meta_bytes, (int64_t)total, err))) return rc;
-  char* M = (char*)h.meta;
+  M = (char*)h.meta;
   h.host_meta.assign(total, 0);
   char* Hm = h.host_meta.data();
   std::memcpy(Hm + o_recs, recs.data(), recs.size() * sizeof(ElimRec));
@@ -1189,21 +1280,21 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   H2D(h, M, Hm, o_info);
   if (!blu.empty())
     H2D(h, M + o_blu, Hm + o_blu, total - o_blu);
-  const ElimRec* d_recs = (const ElimRec*)(M + o_recs);
-  const ElimNbr* d_nbrs = (const ElimNbr*)(M + o_nbrs);
-  const SchurTask* d_tasks = (const SchurTask*)(M + o_tasks);
-  const int32_t* d_fidx = (const int32_t*)(M + o_fidx);
-  const FarPair* d_far = (const FarPair*)(M + o_far);
-  Changed* d_chg = (Changed*)(M + o_chg);
-  const FarRef* d_refs = (const FarRef*)(M + o_refs);
-  const EigTask* d_et = (const EigTask*)(M + o_et);
-  int32_t* d_cnt = (int32_t*)(M + o_cnt);
-  int32_t* d_info = (int32_t*)(M + o_info);
-  const XTask* d_xt = (const XTask*)(M + o_xt);
-  LevelView V = view_of(L);
-  const int nchg = (int)chg.size();
+  d_recs = (const ElimRec*)(M + o_recs);
+  d_nbrs = (const ElimNbr*)(M + o_nbrs);
+  d_tasks = (const SchurTask*)(M + o_tasks);
+  d_fidx = (const int32_t*)(M + o_fidx);
+  d_far = (const FarPair*)(M + o_far);
+  d_chg = (Changed*)(M + o_chg);
+  d_refs = (const FarRef*)(M + o_refs);
+  d_et = (const EigTask*)(M + o_et);
+  d_cnt = (int32_t*)(M + o_cnt);
+  d_info = (int32_t*)(M + o_info);
+  d_xt = (const XTask*)(M + o_xt);
+  V = view_of(L);
+  nchg = (int)chg.size();
   // algorithmic work of the phase-A steps (counted from the block sizes)
-  double fl_lu = 0, fl_x = 0, fl_schur = 0, by_gather = 0, by_schur = 0, fl_far = 0;
+  double fl_far = 0;
   for (const FarPair& F : far) {  // far fill-in products (FP32 in the mixed form)
     const ElimRec& R = recs[F.rec];
     fl_far += 2.0 * nbrs[R.nb_begin + F.a].m * (double)R.n * nbrs[R.nb_begin + F.b].m;
@@ -1217,7 +1308,6 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     by_schur += 8.0 * (M * n + (double)R.d * (M + r) + 2.0 * M * (M + r));  // L, X once; blocks read + written
     by_gather += 8.0 * (d * d + 2.0 * M * n) * 2.0;
   }
-  double fl_gram = 0, fl_ev = 0, fl_evec = 0;
   for (const Changed& C : chg) {
     double sm = C.r;
     for (int q = 0; q < C.far_count; ++q) {
@@ -1227,7 +1317,44 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     fl_gram += sides * (double)C.n * (C.n + 1) * sm;  // symmetric product: lower triangle
     fl_ev += sides * 4.0 / 3.0 * (double)C.n * C.n * C.n;
   }
-  lap.mark("pack");
+  return 0;
+}
+
+// Phase A: gather of the pivots and their neighbour blocks, pivot LU and
+// solves (small pivots on the side stream, large ones blocked), the solve's
+// stored blocks, the Schur-complement update, the Gram matrices of the fill-in.
+static int colour_phase_a(Handle& h, ColourWork& W, std::string& err) {
+  const int l = W.l, c = W.c, nrec = W.nrec, sides = W.sides;
+  DevLevel& L = h.lv[l];
+  auto& recs = W.recs;
+  auto& nbrs = W.nbrs;
+  auto& chg = W.chg;
+  auto& tasks = W.tasks;
+  auto& xtasks = W.xtasks;
+  auto& blu = W.blu;
+  auto& blu_dmax = W.blu_dmax;
+  auto& blu_wmax = W.blu_wmax;
+  auto& M = W.M;
+  auto& o_blu = W.o_blu;
+  auto& o_blur = W.o_blur;
+  auto& d_recs = W.d_recs;
+  auto& d_nbrs = W.d_nbrs;
+  auto& d_tasks = W.d_tasks;
+  auto& d_fidx = W.d_fidx;
+  auto& d_far = W.d_far;
+  auto& d_chg = W.d_chg;
+  auto& d_refs = W.d_refs;
+  auto& d_info = W.d_info;
+  auto& d_xt = W.d_xt;
+  auto& V = W.V;
+  auto& nchg = W.nchg;
+  auto& fl_lu = W.fl_lu;
+  auto& fl_x = W.fl_x;
+  auto& fl_schur = W.fl_schur;
+  auto& by_gather = W.by_gather;
+  auto& by_schur = W.by_schur;
+  auto& fl_gram = W.fl_gram;
+  int rc = 0;
   // ---- phase A
   {
     ProfScope ps(h, "k_gather", 0, by_gather);
@@ -1324,18 +1451,143 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
                          h.stream, V, d_chg, d_refs, d_far, d_nbrs, d_recs, sides);
     }
   }
-  lap.mark("launch_a");
+  return 0;
+}
+
+// One batch of sketches (the randomised range finder of Sec. 5.1): for task
+// e of the colour (changed node e / sides, side e % sides) with width w, the
+// range sample of the stacked factor with a seeded Gaussian test matrix, its
+// orthonormalisation, the Rayleigh-Ritz step with the Gram matrix and the
+// a-posteriori check.  Tables and work space live in *buf (grown as needed);
+// the Ritz counts and the verdicts land in B.d_cnt and B.d_ok.
+struct SketchBatch {
+  std::vector<SkTask> T;
+  std::vector<EigTask> E;  // Rayleigh-Ritz eigen-problems (order = width)
+  SkTask* d_T = nullptr;
+  EigTask* d_E = nullptr;
+  int32_t* d_cnt = nullptr;
+  int32_t* d_ok = nullptr;
+};
+static int sketch_batch(Handle& h, const ColourWork& W, const std::vector<int32_t>& ids,
+                        const std::vector<int32_t>& width, const std::vector<int64_t>& wrows, uint32_t salt,
+                        double** buf, int64_t* buf_bytes, SketchBatch& B, std::string& err) {
+  const int sides = W.sides;
+  const size_t ns = ids.size();
+  B.T.clear();
+  B.E.clear();
+  if (!ns) return 0;
+  int64_t need = 0;
+  for (size_t q = 0; q < ns; ++q) {
+    const int64_t n = W.chg[ids[q] / sides].n, sw = width[q];
+    need += std::max<int64_t>(wrows[ids[q] / sides], n) * sw + n * sw + 2 * sw * sw + 3 * sw + 64;
+  }
+  const size_t tb = (ns * (sizeof(EigTask) + sizeof(SkTask) + 2 * sizeof(GemmTask) + 8) + 4096 + 255) & ~(size_t)255;
+  int rc;
+  if ((rc = ensure(h, (void**)buf, buf_bytes, (int64_t)tb + need * 8 + 256, err))) return rc;
+  char* base = (char*)*buf;
+  B.d_E = (EigTask*)base;
+  B.d_T = (SkTask*)(B.d_E + ns);
+  GemmTask* d_G = (GemmTask*)(B.d_T + ns);
+  B.d_cnt = (int32_t*)(d_G + 2 * ns);
+  B.d_ok = B.d_cnt + ns;
+  double* W0 = (double*)(base + tb);
+  int64_t o = 0;
+  int smax = 1, nmax = 1;
+  for (size_t q = 0; q < ns; ++q) {
+    const int e = ids[q];
+    const Changed& C = W.chg[e / sides];
+    const int side = e % sides, n = C.n, sw = width[q];
+    SkTask t;
+    t.G = side ? C.gt : C.gs;
+    t.O = W0 + o; o += std::max<int64_t>(wrows[e / sides], n) * sw;
+    t.Y = W0 + o; o += (int64_t)n * sw;
+    t.B = W0 + o; o += (int64_t)sw * sw;
+    double* U = W0 + o; o += (int64_t)sw * sw;
+    double* Wk = W0 + o; o += 3LL * sw;
+    t.tr = W0 + o; o += 64;
+    t.n = n; t.s = sw;
+    t.R = (int32_t)wrows[e / sides];
+    t.chg = e / sides;
+    t.seed = (uint32_t)(C.p * 2 + side) + salt;
+    t.side = (uint32_t)side;
+    B.T.push_back(t);
+    B.E.push_back({t.B, U, Wk, side ? C.lt : C.ls, nullptr, sw, 0});
+    smax = std::max(smax, sw);
+    nmax = std::max(nmax, n);
+  }
+  // Z = G Q (into O), B = Q^T Z
+  std::vector<GemmTask> g;
+  for (const SkTask& t : B.T) g.push_back({t.G, t.Y, t.O, t.n, t.s, t.n, t.n, t.n, t.n, 0, 0, 1.0, 0.0});
+  for (const SkTask& t : B.T) g.push_back({t.Y, t.O, t.B, t.s, t.s, t.n, t.n, t.n, t.s, 1, 0, 1.0, 0.0});
+  H2D(h, B.d_E, held(h, B.E), ns * sizeof(EigTask));
+  H2D(h, B.d_T, held(h, B.T), ns * sizeof(SkTask));
+  H2D(h, d_G, held(h, g), 2 * ns * sizeof(GemmTask));
+  double fl = 0;
+  for (const SkTask& t : B.T)
+    fl += 2.0 * t.n * (double)t.R * t.s + 2.0 * t.n * (double)t.n * t.s + 6.0 * t.n * (double)t.s * t.s;
+  const unsigned tn = (unsigned)((nmax + 63) / 64), ts = (unsigned)((smax + 63) / 64);
+  const double drop = std::max(1e-13, std::min(1e-9, 1e-3 * h.eps));
+  const double eps2 = h.eps * h.eps;
+  {
+    ProfScope ps(h, "group:sketch_range", fl, 0);
+    hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)ns), dim3(NT), 0, h.stream, B.d_T);
+    hipLaunchKernelGGL(h.precision == 1 ? k_sk_range<true> : k_sk_range<false>, dim3(tn, ts, (unsigned)ns), dim3(NT),
+                       0, h.stream, W.d_chg, W.d_refs, W.d_far, W.d_nbrs, W.d_recs, B.d_T);
+  }
+  {
+    ProfScope ps(h, "group:sketch_orth", 0, 0);
+    if ((rc = sk_orthonormalise(h, B.T, B.d_T, drop, err))) return rc;
+  }
+  ProfScope ps(h, "group:sketch_rr", 0, 0);
+  hipLaunchKernelGGL(k_gemm_batch, dim3(tn, ts, (unsigned)ns), dim3(NT), 0, h.stream, d_G);
+  hipLaunchKernelGGL(k_gemm_batch, dim3(ts, ts, (unsigned)ns), dim3(NT), 0, h.stream, d_G + ns);
+  hipLaunchKernelGGL(k_sk_trace, dim3((unsigned)ns), dim3(NT), 0, h.stream, B.d_T);
+  if ((rc = eig_values(h, B.E, B.d_E, eps2, B.d_cnt, h.stream, err))) return rc;
+  hipLaunchKernelGGL(k_sk_check, dim3((unsigned)((ns + NT - 1) / NT)), dim3(NT), 0, h.stream, B.d_T, B.d_E, B.d_cnt,
+                     eps2, B.d_ok, (int)ns);
+  return 0;
+}
+
+// Recompression of the fill-in: per changed node and side a sketch of width
+// s (predicted rank plus oversampling) or the full eigen-decomposition;
+// rejected sketches are retried once wider, then decomposed in full.
+static int colour_recompress(Handle& h, ColourWork& W, HostLap& lap, std::string& err) {
+  const int l = W.l, nrec = W.nrec, sides = W.sides;
+  const Level& T = h.tree.levels[l];
+  auto& recs = W.recs;
+  auto& nbrs = W.nbrs;
+  auto& far = W.far;
+  auto& chg = W.chg;
+  auto& refs = W.refs;
+  auto& tasks = W.tasks;
+  auto& etasks = W.etasks;
+  auto& d_recs = W.d_recs;
+  auto& d_nbrs = W.d_nbrs;
+  auto& d_far = W.d_far;
+  auto& d_chg = W.d_chg;
+  auto& d_refs = W.d_refs;
+  auto& d_info = W.d_info;
+  auto& nchg = W.nchg;
+  auto& fl_ev = W.fl_ev;
+  auto& cnt = W.cnt;
+  auto& info = W.info;
+  auto& full_ids = W.full_ids;
+  auto& sk_ids = W.sk_ids;
+  auto& fullT = W.fullT;
+  auto& skE = W.skE;
+  auto& skT = W.skT;
+  auto& rfeat = W.rfeat;
+  auto& fe_ids = W.fe_ids;
+  int rc = 0;
   // ---- recompression: per changed node and side, either a sketch of width s
   // (predicted rank plus oversampling) or the full eigen-decomposition
   const int ne = (int)etasks.size();
-  std::vector<int32_t> skw(ne, 0), cnt(ne, 0), info(nrec);
-  std::vector<int32_t> full_ids, sk_ids;
-  std::vector<EigTask> fullT, skE;
-  std::vector<SkTask> skT;
-  std::vector<GemmTask> gT;
+  std::vector<int32_t> skw(ne, 0);
+  cnt.assign(ne, 0);
+  info.assign(nrec, 0);
   std::vector<int32_t> cnt_full, cnt_sk, ok_sk;
-  std::vector<float> rfeat, rpred;
-  std::vector<int32_t> fe_ids, fe_of;
+  std::vector<float> rpred;
+  std::vector<int32_t> fe_of;
   if (nchg) {
     // rows of the stacked factor of each changed node's Gram matrix
     std::vector<int64_t> wrows(nchg, 0);
@@ -1379,61 +1631,19 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       skw[e] = s;
       (s ? sk_ids : full_ids).push_back(e);
     }
-    // device tables and buffers of the sketches
-    int64_t need = 0;
-    for (int e : sk_ids) {
-      const int64_t n = chg[e / sides].n, sw = skw[e];
-      need += std::max<int64_t>(wrows[e / sides], n) * sw + n * sw + 2 * sw * sw + 3 * sw + 64;
-    }
+    // tables of the full decompositions (and of the fall-backs of rejected
+    // sketches, at most one per sketch); the sketches have their own buffer
     const size_t nsk = sk_ids.size(), nfull = full_ids.size();
-    const size_t tb = ((nfull + 2 * nsk) * sizeof(EigTask) + nsk * sizeof(SkTask) + 4 * nsk * sizeof(GemmTask) +
-                       (nfull + 3 * nsk) * 4 + 4096 + 255) & ~(size_t)255;
-    if ((rc = ensure(h, (void**)&h.skbuf, &h.skbuf_bytes, (int64_t)tb + need * 8 + 256, err))) return rc;
-    char* base = (char*)h.skbuf;
-    EigTask* d_fullT = (EigTask*)base;
-    EigTask* d_skE = d_fullT + nfull;
-    EigTask* d_fbT = d_skE + nsk;  // fall-back full tasks of rejected sketches
-    SkTask* d_skT = (SkTask*)(d_fbT + nsk);
-    GemmTask* d_gT = (GemmTask*)(d_skT + nsk);
-    int32_t* d_cf = (int32_t*)(d_gT + 4 * nsk);
-    int32_t* d_cs = d_cf + nfull;
-    int32_t* d_ok = d_cs + nsk;
-    int32_t* d_cfb = d_ok + nsk;
-    double* W0 = (double*)(base + tb);
-    int64_t o = 0;
+    const size_t tb = ((nfull + nsk) * sizeof(EigTask) + (nfull + nsk) * 4 + 1024 + 255) & ~(size_t)255;
+    if ((rc = ensure(h, (void**)&h.eigtab, &h.eigtab_bytes, (int64_t)tb, err))) return rc;
+    EigTask* d_fullT = (EigTask*)h.eigtab;
+    EigTask* d_fbT = d_fullT + nfull;  // fall-back full tasks of rejected sketches
+    int32_t* d_cf = (int32_t*)(d_fbT + nsk);
+    int32_t* d_cfb = d_cf + nfull;
     for (int e : full_ids) fullT.push_back(etasks[e]);
-    int smax = 1, nmax = 1;
-    for (int e : sk_ids) {
-      const Changed& C = chg[e / sides];
-      const int side = e % sides;
-      const int n = C.n, sw = skw[e];
-      SkTask t;
-      t.G = side ? C.gt : C.gs;
-      t.O = W0 + o; o += std::max<int64_t>(wrows[e / sides], n) * sw;
-      t.Y = W0 + o; o += (int64_t)n * sw;
-      t.B = W0 + o; o += (int64_t)sw * sw;
-      double* U = W0 + o; o += (int64_t)sw * sw;
-      double* Wk = W0 + o; o += 3LL * sw;
-      t.tr = W0 + o; o += 64;
-      t.n = n; t.s = sw;
-      t.R = (int32_t)wrows[e / sides];
-      t.chg = e / sides;
-      t.seed = (uint32_t)(C.p * 2 + side + 1);
-      t.side = (uint32_t)side;
-      skT.push_back(t);
-      skE.push_back({t.B, U, Wk, side ? C.lt : C.ls, nullptr, sw, 0});
-      smax = std::max(smax, sw);
-      nmax = std::max(nmax, n);
-    }
-    // Z = G Q (into O), B = Q^T Z
-    for (const SkTask& t : skT) gT.push_back({t.G, t.Y, t.O, t.n, t.s, t.n, t.n, t.n, t.n, 0, 0, 1.0, 0.0});
-    for (const SkTask& t : skT) gT.push_back({t.Y, t.O, t.B, t.s, t.s, t.n, t.n, t.n, t.s, 1, 0, 1.0, 0.0});
     if (nfull) H2D(h, d_fullT, fullT.data(), nfull * sizeof(EigTask));
-    if (nsk) {
-      H2D(h, d_skE, skE.data(), nsk * sizeof(EigTask));
-      H2D(h, d_skT, skT.data(), nsk * sizeof(SkTask));
-      H2D(h, d_gT, gT.data(), 2 * nsk * sizeof(GemmTask));
-    }
+    std::vector<int32_t> sk_w;
+    for (int e : sk_ids) sk_w.push_back(skw[e]);
     const double eps2 = h.eps * h.eps;
     // the full decompositions (their own Gram matrices and work space) run on
     // the side stream while the sketches run on the main stream
@@ -1444,30 +1654,10 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       const hipStream_t st = side ? h.side_stream : h.stream;
       if ((rc = eig_values(h, fullT, d_fullT, eps2, d_cf, st, err))) return rc;
     }
-    if (nsk) {
-      double fl_sk = 0;
-      for (const SkTask& t : skT)
-        fl_sk += 2.0 * t.n * (double)t.R * t.s + 2.0 * t.n * (double)t.n * t.s + 6.0 * t.n * (double)t.s * t.s;
-      const unsigned tn = (unsigned)((nmax + 63) / 64), ts = (unsigned)((smax + 63) / 64);
-      const double drop = std::max(1e-13, std::min(1e-9, 1e-3 * h.eps));
-      {
-        ProfScope ps(h, "group:sketch_range", fl_sk, 0);
-        hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
-        hipLaunchKernelGGL(h.precision == 1 ? k_sk_range<true> : k_sk_range<false>, dim3(tn, ts, (unsigned)nsk),
-                           dim3(NT), 0, h.stream, d_chg, d_refs, d_far, d_nbrs, d_recs, d_skT);
-      }
-      {
-        ProfScope ps(h, "group:sketch_orth", 0, 0);
-        if ((rc = sk_orthonormalise(h, skT, d_skT, drop, err))) return rc;
-      }
-      ProfScope ps(h, "group:sketch_rr", 0, 0);
-      hipLaunchKernelGGL(k_gemm_batch, dim3(tn, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_gT);
-      hipLaunchKernelGGL(k_gemm_batch, dim3(ts, ts, (unsigned)nsk), dim3(NT), 0, h.stream, d_gT + nsk);
-      hipLaunchKernelGGL(k_sk_trace, dim3((unsigned)nsk), dim3(NT), 0, h.stream, d_skT);
-      if ((rc = eig_values(h, skE, d_skE, eps2, d_cs, h.stream, err))) return rc;
-      hipLaunchKernelGGL(k_sk_check, dim3((unsigned)((nsk + NT - 1) / NT)), dim3(NT), 0, h.stream, d_skT, d_skE, d_cs,
-                         eps2, d_ok, (int)nsk);
-    }
+    SketchBatch S1;
+    if ((rc = sketch_batch(h, W, sk_ids, sk_w, wrows, 1, &h.skbuf, &h.skbuf_bytes, S1, err))) return rc;
+    skT = S1.T;
+    skE = S1.E;
     if (side && (rc = join_side(h, err))) return rc;
     HIPCHK(hipGetLastError());
     cnt_full.assign(nfull, 0);
@@ -1477,8 +1667,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     HSYNC(h);  // the copies below wait for the queue: accounted here
     if (nfull) HIPCHK(hipMemcpyAsync(cnt_full.data(), d_cf, nfull * 4, hipMemcpyDeviceToHost, h.stream));
     if (nsk) {
-      HIPCHK(hipMemcpyAsync(cnt_sk.data(), d_cs, nsk * 4, hipMemcpyDeviceToHost, h.stream));
-      HIPCHK(hipMemcpyAsync(ok_sk.data(), d_ok, nsk * 4, hipMemcpyDeviceToHost, h.stream));
+      HIPCHK(hipMemcpyAsync(cnt_sk.data(), S1.d_cnt, nsk * 4, hipMemcpyDeviceToHost, h.stream));
+      HIPCHK(hipMemcpyAsync(ok_sk.data(), S1.d_ok, nsk * 4, hipMemcpyDeviceToHost, h.stream));
     }
     HIPCHK(hipMemcpyAsync(info.data(), d_info, nrec * 4, hipMemcpyDeviceToHost, h.stream));
     HSYNC(h);
@@ -1520,84 +1710,15 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
       fb_of.swap(fbof_keep);
     }
     std::vector<int32_t> r2_ok;
-    std::vector<SkTask> r2T;
-    std::vector<EigTask> r2E;
+    SketchBatch S2;
     if (!r2_ids.empty()) {
       const size_t n2 = r2_ids.size();
-      int64_t need2 = 0;
-      for (size_t q = 0; q < n2; ++q) {
-        const int64_t n = chg[r2_ids[q] / sides].n, sw = r2_w[q];
-        need2 += std::max<int64_t>(wrows[r2_ids[q] / sides], n) * sw + n * sw + 2 * sw * sw + 3 * sw + 64;
-      }
-      const size_t tb2 = (n2 * (sizeof(EigTask) + sizeof(SkTask) + 2 * sizeof(GemmTask) + 8) + 4096 + 255) &
-                         ~(size_t)255;
-      if ((rc = ensure(h, (void**)&h.skbuf2, &h.skbuf2_bytes, (int64_t)tb2 + need2 * 8 + 256, err))) return rc;
-      char* b2 = (char*)h.skbuf2;
-      EigTask* d_E2 = (EigTask*)b2;
-      SkTask* d_T2 = (SkTask*)(d_E2 + n2);
-      GemmTask* d_G2 = (GemmTask*)(d_T2 + n2);
-      int32_t* d_c2 = (int32_t*)(d_G2 + 2 * n2);
-      int32_t* d_o2 = d_c2 + n2;
-      double* V0 = (double*)(b2 + tb2);
-      int64_t o2 = 0;
-      int smax2 = 1, nmax2 = 1;
-      std::vector<GemmTask> g2;
-      for (size_t q = 0; q < n2; ++q) {
-        const int e = r2_ids[q];
-        const Changed& C = chg[e / sides];
-        const int side = e % sides, n = C.n, sw = r2_w[q];
-        SkTask t;
-        t.G = side ? C.gt : C.gs;
-        t.O = V0 + o2; o2 += std::max<int64_t>(wrows[e / sides], n) * sw;
-        t.Y = V0 + o2; o2 += (int64_t)n * sw;
-        t.B = V0 + o2; o2 += (int64_t)sw * sw;
-        double* U = V0 + o2; o2 += (int64_t)sw * sw;
-        double* Wk = V0 + o2; o2 += 3LL * sw;
-        t.tr = V0 + o2; o2 += 64;
-        t.n = n; t.s = sw;
-        t.R = (int32_t)wrows[e / sides];
-        t.chg = e / sides;
-        t.seed = (uint32_t)(C.p * 2 + side + 0x9E37);
-        t.side = (uint32_t)side;
-        r2T.push_back(t);
-        r2E.push_back({t.B, U, Wk, side ? C.lt : C.ls, nullptr, sw, 0});
-        smax2 = std::max(smax2, sw);
-        nmax2 = std::max(nmax2, n);
-      }
-      for (const SkTask& t : r2T) g2.push_back({t.G, t.Y, t.O, t.n, t.s, t.n, t.n, t.n, t.n, 0, 0, 1.0, 0.0});
-      for (const SkTask& t : r2T) g2.push_back({t.Y, t.O, t.B, t.s, t.s, t.n, t.n, t.n, t.s, 1, 0, 1.0, 0.0});
-      H2D(h, d_E2, r2E.data(), n2 * sizeof(EigTask));
-      H2D(h, d_T2, r2T.data(), n2 * sizeof(SkTask));
-      H2D(h, d_G2, g2.data(), 2 * n2 * sizeof(GemmTask));
-      {
-        double fl2 = 0;
-        for (const SkTask& t : r2T)
-          fl2 += 2.0 * t.n * (double)t.R * t.s + 2.0 * t.n * (double)t.n * t.s + 6.0 * t.n * (double)t.s * t.s;
-        const unsigned tn = (unsigned)((nmax2 + 63) / 64), ts = (unsigned)((smax2 + 63) / 64);
-        const double drop = std::max(1e-13, std::min(1e-9, 1e-3 * h.eps));
-        {
-          ProfScope ps(h, "group:sketch_range", fl2, 0);
-          hipLaunchKernelGGL(k_sk_omega, dim3(64, (unsigned)n2), dim3(NT), 0, h.stream, d_T2);
-          hipLaunchKernelGGL(h.precision == 1 ? k_sk_range<true> : k_sk_range<false>, dim3(tn, ts, (unsigned)n2),
-                             dim3(NT), 0, h.stream, d_chg, d_refs, d_far, d_nbrs, d_recs, d_T2);
-        }
-        {
-          ProfScope ps(h, "group:sketch_orth", 0, 0);
-          if ((rc = sk_orthonormalise(h, r2T, d_T2, drop, err))) return rc;
-        }
-        ProfScope ps(h, "group:sketch_rr", 0, 0);
-        hipLaunchKernelGGL(k_gemm_batch, dim3(tn, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_G2);
-        hipLaunchKernelGGL(k_gemm_batch, dim3(ts, ts, (unsigned)n2), dim3(NT), 0, h.stream, d_G2 + n2);
-        hipLaunchKernelGGL(k_sk_trace, dim3((unsigned)n2), dim3(NT), 0, h.stream, d_T2);
-        if ((rc = eig_values(h, r2E, d_E2, eps2, d_c2, h.stream, err))) return rc;
-        hipLaunchKernelGGL(k_sk_check, dim3((unsigned)((n2 + NT - 1) / NT)), dim3(NT), 0, h.stream, d_T2, d_E2, d_c2,
-                           eps2, d_o2, (int)n2);
-      }
+      if ((rc = sketch_batch(h, W, r2_ids, r2_w, wrows, 0x9E37, &h.skbuf2, &h.skbuf2_bytes, S2, err))) return rc;
       std::vector<int32_t> c2(n2);
       r2_ok.assign(n2, 0);
       HSYNC(h);
-      HIPCHK(hipMemcpyAsync(c2.data(), d_c2, n2 * 4, hipMemcpyDeviceToHost, h.stream));
-      HIPCHK(hipMemcpyAsync(r2_ok.data(), d_o2, n2 * 4, hipMemcpyDeviceToHost, h.stream));
+      HIPCHK(hipMemcpyAsync(c2.data(), S2.d_cnt, n2 * 4, hipMemcpyDeviceToHost, h.stream));
+      HIPCHK(hipMemcpyAsync(r2_ok.data(), S2.d_ok, n2 * 4, hipMemcpyDeviceToHost, h.stream));
       HSYNC(h);
       h.stat_sketch += (int64_t)n2;
       for (size_t q = 0; q < n2; ++q) {
@@ -1641,8 +1762,8 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     for (size_t q = 0; q < r2_ids.size(); ++q)
       if (r2_ok[q] > 0) {
         keep_ids.push_back(r2_ids[q]);
-        keepE.push_back(r2E[q]);
-        keepT.push_back(r2T[q]);
+        keepE.push_back(S2.E[q]);
+        keepT.push_back(S2.T[q]);
       }
     sk_ids.swap(keep_ids);
     skE.swap(keepE);
@@ -1654,7 +1775,30 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     HSYNC(h);
   }
   prof_collect(h);
-  lap.mark("select");
+  return 0;
+}
+
+// New ranks, eigenvectors of the accepted decompositions, new bases.
+static int colour_ranks_vectors(Handle& h, ColourWork& W, HostLap& lap, std::string& err) {
+  const int l = W.l, c = W.c, nrec = W.nrec, sides = W.sides;
+  const bool sym = W.sym;
+  DevLevel& L = h.lv[l];
+  auto& recs = W.recs;
+  auto& chg = W.chg;
+  auto& d_chg = W.d_chg;
+  auto& V = W.V;
+  auto& nchg = W.nchg;
+  auto& fl_evec = W.fl_evec;
+  auto& cnt = W.cnt;
+  auto& info = W.info;
+  auto& full_ids = W.full_ids;
+  auto& sk_ids = W.sk_ids;
+  auto& fullT = W.fullT;
+  auto& skE = W.skE;
+  auto& skT = W.skT;
+  auto& rfeat = W.rfeat;
+  auto& fe_ids = W.fe_ids;
+  int rc = 0;
   for (int k = 0; k < nrec; ++k)
     if (info[k]) {
       err = "singular pivot block at level " + std::to_string(l) + ", node " + std::to_string(recs[k].node);
@@ -1749,9 +1893,26 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     }
     if ((rc = check_arena(h, l, "basis", c, err))) return rc;
   }
+  return 0;
+}
+
+// Capacity growth of the M2L blocks of nodes whose new rank exceeds it, and
+// the projection of the far fill-in onto the new bases.
+static int colour_grow_project(Handle& h, ColourWork& W, std::string& err) {
+  const int l = W.l, c = W.c;
+  DevLevel& L = h.lv[l];
+  auto& far = W.far;
+  auto& chg = W.chg;
+  auto& d_recs = W.d_recs;
+  auto& d_nbrs = W.d_nbrs;
+  auto& d_far = W.d_far;
+  auto& d_chg = W.d_chg;
+  auto& V = W.V;
+  auto& nchg = W.nchg;
+  auto& moves = W.moves;
+  auto& capset = W.capset;
+  int rc = 0;
   // capacity growth of the M2L blocks of nodes whose new rank exceeds it
-  std::vector<SlotMove> moves;
-  std::vector<int32_t> capset;
   if (nchg) {
     const Level& TL = h.tree.levels[l];
     std::vector<int32_t> newcap(chg.size(), 0);
@@ -1816,7 +1977,22 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     hipLaunchKernelGGL(k_project, dim3((unsigned)far.size()), dim3(NT), 0, h.stream, V, d_far, d_recs, d_nbrs, d_chg);
   }
   if ((rc = check_arena(h, l, "project", c, err))) return rc;
-  lap.mark("moves_project");
+  return 0;
+}
+
+// Phase B: basis changes of the M2L / M2M / L2L blocks touching a changed node.
+static int colour_phase_b(Handle& h, ColourWork& W, std::string& err) {
+  const int l = W.l, c = W.c, K = h.K;
+  DevLevel& L = h.lv[l];
+  auto& chg = W.chg;
+  auto& d_far = W.d_far;
+  auto& d_chg = W.d_chg;
+  auto& d_refs = W.d_refs;
+  auto& V = W.V;
+  auto& nchg = W.nchg;
+  auto& moves = W.moves;
+  auto& capset = W.capset;
+  int rc = 0;
   // ---- phase B
   if (nchg) {
     {
@@ -1949,7 +2125,19 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
     for (const Changed& C : chg) L.r[C.p] = C.rnew;
   }
   HIPCHK(hipGetLastError());
-  lap.mark("phase_b");
+  return 0;
+}
+
+// Keeps the records for the solve (neighbour entries rebased on the level
+// table) and its 64-row tiles: pivot rows, L rows, G rows.
+static int colour_keep(Handle& h, ColourWork& W, std::string& err) {
+  const int l = W.l;
+  DevLevel& L = h.lv[l];
+  auto& recs = W.recs;
+  auto& nbrs = W.nbrs;
+  auto& far = W.far;
+  auto& nchg = W.nchg;
+  const int nbase = W.nbase;
   // keep the records for the solve (neighbour entries rebased on the level
   // table) and its 64-row tiles: pivot rows, L rows, G rows
   for (ElimRec R : recs) {
@@ -1977,6 +2165,36 @@ static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
   L.cinv.push_back(ci);
   h.stat_far += (int64_t)far.size();
   h.stat_changed += nchg;
+  return 0;
+}
+
+static int eliminate_colour(Handle& h, int l, int c, std::string& err) {
+  const Level& T = h.tree.levels[l];
+  ColourWork W;
+  W.l = l;
+  W.c = c;
+  W.g0 = T.grp_ptr[c];
+  W.nrec = T.grp_ptr[c + 1] - W.g0;
+  if (W.nrec == 0) return 0;
+  W.sym = h.symmetric;
+  W.sides = W.sym ? 1 : 2;
+  W.nbase = (int)h.lv[l].nbrs.size();
+  HostLap lap(h);
+  int rc;
+  if ((rc = colour_tables(h, W, err))) return rc;
+  lap.mark("tables");
+  if ((rc = colour_upload(h, W, err))) return rc;
+  lap.mark("pack");
+  if ((rc = colour_phase_a(h, W, err))) return rc;
+  lap.mark("launch_a");
+  if ((rc = colour_recompress(h, W, lap, err))) return rc;
+  lap.mark("select");
+  if ((rc = colour_ranks_vectors(h, W, lap, err))) return rc;
+  if ((rc = colour_grow_project(h, W, err))) return rc;
+  lap.mark("moves_project");
+  if ((rc = colour_phase_b(h, W, err))) return rc;
+  lap.mark("phase_b");
+  if ((rc = colour_keep(h, W, err))) return rc;
   lap.mark("keep");
   // no wait here: the host goes on to the next colour's tables while the
   // device finishes this one (pending uploads read held copies)

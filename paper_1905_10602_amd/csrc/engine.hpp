@@ -206,6 +206,8 @@ struct Handle {
   int sketch_min = 128;     // Gram order from which a sketch is tried (IFMM_SKETCH_MIN)
   double* skbuf = nullptr;
   int64_t skbuf_bytes = 0;
+  double* eigtab = nullptr;  // task tables and counts of a colour's full decompositions
+  int64_t eigtab_bytes = 0;
   double* skbuf2 = nullptr;  // second-round (wider) sketches
   double* orthbuf = nullptr;  // block Gram-Schmidt tables and coefficients
   int64_t orthbuf_bytes = 0;
