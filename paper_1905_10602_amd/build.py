@@ -34,8 +34,11 @@ def build(verbose: bool = False) -> str:
     jobs = [
         ("tree.cpp", ["-x", "c++", "-ffp-contract=off"]),
         ("capi.cpp", ["-x", "c++", "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"]),
+        # matrix-core accumulators in ordinary VGPRs (no copies to and from
+        # the accumulation registers around every k-chunk of the GEMM tiles)
         ("engine.hip", ["-x", "hip", "--offload-arch=gfx950", "-ffp-contract=fast",
-                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]),
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                        "-mllvm", "-amdgpu-mfma-vgpr-form=1"]),
         ("fmm.hip", ["-x", "hip", "--offload-arch=gfx950", "-ffp-contract=fast",
                      "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]),
         ("mlp.hip", ["-x", "hip", "--offload-arch=gfx950", "-ffp-contract=fast",

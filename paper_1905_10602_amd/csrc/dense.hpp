@@ -333,59 +333,101 @@ __device__ inline void wg_gemm_f32_deep(int m, int n, int k, double alpha, const
 }
 
 // FP64 matrix-core product C = alpha A B + beta C (A m x k, B k x n, column
-// major, no transposes), v_mfma_f64_16x16x4f64.  The product is formed
-// transposed, C^T = B^T A^T, so that the accumulator of lane l, register v,
-// holds C[l % 16][4 v + l / 16] of its 16 x 16 block: 16 consecutive rows of
-// C per column, coalesced.  Lane layout of the instruction (checked on the
-// device): lane l supplies a = P[l % 16][l / 16] and b = Q[l / 16][l % 16] of
-// D = P Q and receives D[4 v + l / 16][l % 16] in register v; here P = B^T,
-// so a = B[k0 + l / 16][j + l % 16], and Q = A^T, so b = A[i + l % 16][k0 + l / 16].
-// Each wave owns 32 x 32 output tiles (2 x 2
-// blocks), the four waves of the workgroup take them in turn; operands come
-// straight from global memory (L1 / L2), no LDS.
+// major, no transposes), v_mfma_f64_16x16x4f64, 64 x 64 output tiles per
+// workgroup with k-chunks of 16 staged through LDS (the next chunk prefetched
+// into registers), each wave a 32 x 32 quarter as 2 x 2 blocks of 16 x 16.
+// The product is formed transposed, C^T = B^T A^T, so that the accumulator
+// of lane l, register v, holds C[l % 16][4 v + l / 16] of its block: 16
+// consecutive rows of C per column, coalesced.  Lane layout of the
+// instruction (checked on the device): lane l supplies a = P[l % 16][l / 16]
+// and b = Q[l / 16][l % 16] of D = P Q and receives D[4 v + l / 16][l % 16]
+// in register v; here P = B^T and Q = A^T.  Per 1024 multiply-adds a wave
+// reads 1 KB of operands from LDS, against 4 KB for the FMA tile's 4 x 4
+// register blocks, which makes this tile bound by the matrix cores rather
+// than by LDS bandwidth.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 __device__ inline void wg_gemm_f64m(int m, int n, int k, double alpha, const double* A, int lda, const double* B,
                                     int ldb, double beta, double* C, int ldc) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-  const int tm = (m + 31) / 32, tn = (n + 31) / 32;
-  for (int t = wave; t < tm * tn; t += NT / 64) {
-    const int i0 = 32 * (t % tm), j0 = 32 * (t / tm);
-    f64x4 acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    const int ia0 = i0 + lr, ia1 = i0 + 16 + lr;     // rows of A (and C) this lane loads
-    const int jb0 = j0 + lr, jb1 = j0 + 16 + lr;     // columns of B (and C) this lane loads
-    const bool ra0 = ia0 < m, ra1 = ia1 < m, cb0 = jb0 < n, cb1 = jb1 < n;
-    for (int k0 = 0; k0 < k; k0 += 4) {
-      const int kk = k0 + lk;
-      const bool kin = kk < k;
-      const double a0 = (kin && ra0) ? A[ia0 + (int64_t)kk * lda] : 0.0;
-      const double a1 = (kin && ra1) ? A[ia1 + (int64_t)kk * lda] : 0.0;
-      const double b0 = (kin && cb0) ? B[kk + (int64_t)jb0 * ldb] : 0.0;
-      const double b1 = (kin && cb1) ? B[kk + (int64_t)jb1 * ldb] : 0.0;
-      // block (row half ra, column half cb) of C^T = B^T A^T: a-operand from B, b-operand from A
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
-    }
-    // acc[ri][cj] register v of lane l: C[i0 + 16 ri + l % 16][j0 + 16 cj + 4 v + l / 16]
-#pragma unroll
-    for (int ri = 0; ri < 2; ++ri)
-#pragma unroll
-      for (int cj = 0; cj < 2; ++cj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = i0 + 16 * ri + lr, j = j0 + 16 * cj + 4 * v + lk;
-          if (i < m && j < n) {
-            double* c = C + i + (int64_t)j * ldc;
-            *c = beta == 0.0 ? alpha * acc[ri][cj][v] : alpha * acc[ri][cj][v] + beta * *c;
-          }
-        }
+  __shared__ double lds64[2 * 16 * 68];  // >= 2 x 32 x 33 for the small product
+  if (m <= 32 && n <= 32 && k <= 32) {   // too small for the tiles: the one-pass product
+    wg_gemm_small(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc, lds64);
+    return;
   }
+  double (*fA)[68] = reinterpret_cast<double (*)[68]>(lds64);
+  double (*fB)[68] = reinterpret_cast<double (*)[68]>(lds64 + 16 * 68);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  for (int i0 = 0; i0 < m; i0 += 64) {
+    for (int j0 = 0; j0 < n; j0 += 64) {
+      f64x4 acc[2][2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+      double ra[4], rb[4];
+      // chunk k0..k0+15: A rows i0 + (e & 63), column k0 + (e >> 6); B rows
+      // k0 + (e & 15), column j0 + (e >> 4); e = tid + 256 q
+      auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = tid + q * NT;
+          const int ii = e & 63, kk = e >> 6;
+          const int gi = i0 + ii, gk = k0 + kk;
+          ra[q] = (gi < m && gk < k) ? A[gi + (int64_t)gk * lda] : 0.0;
+          const int kb = e & 15, jb = e >> 4;
+          const int gk2 = k0 + kb, gj = j0 + jb;
+          rb[q] = (gk2 < k && gj < n) ? B[gk2 + (int64_t)gj * ldb] : 0.0;
+        }
+      };
+      auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = tid + q * NT;
+          fA[e >> 6][e & 63] = ra[q];
+          fB[e & 15][e >> 4] = rb[q];
+        }
+      };
+      if (k > 0) {
+        fetch(0);
+        stash();
+      }
+      __syncthreads();
+      for (int k0 = 0; k0 < k; k0 += 16) {
+        const bool more = k0 + 16 < k;
+        if (more) fetch(k0 + 16);
+#pragma unroll
+        for (int ks = 0; ks < 16; ks += 4) {
+          const int kr = ks + lk;
+          const double a0 = fA[kr][wr + lr], a1 = fA[kr][wr + 16 + lr];
+          const double b0 = fB[kr][wc + lr], b1 = fB[kr][wc + 16 + lr];
+          // block (row half ri, column half cj): a-operand from B, b-operand from A
+          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+        if (more) stash();
+        __syncthreads();
+      }
+      // acc[ri][cj] register v of lane l: C[i0 + wr + 16 ri + l % 16][j0 + wc + 16 cj + 4 v + l / 16]
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+        for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = i0 + wr + 16 * ri + lr, j = j0 + wc + 16 * cj + 4 * v + lk;
+            if (i < m && j < n) {
+              double* c = C + i + (int64_t)j * ldc;
+              *c = beta == 0.0 ? alpha * acc[ri][cj][v] : fma(alpha, acc[ri][cj][v], beta * *c);
+            }
+          }
+    }
+  }
+  __syncthreads();
 }
 
 // precision switch of the Schur-complement and basis-change products

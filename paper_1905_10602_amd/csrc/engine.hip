@@ -1410,10 +1410,11 @@ static int colour_phase_a(Handle& h, ColourWork& W, std::string& err) {
     // tile keeps more workgroups resident and measured faster at every level)
     int nmx = 0;
     for (const ElimRec& R : recs) nmx = std::max(nmx, R.n);
-    // tile: FP64 form FMA (0) or matrix cores (1); mixed form lite (0) or
-    // deep (1) FP32 tile.  Built-in choice unless the autotuner has one; a
-    // level it has not seen alternates the two over its colours, timed
-    bool alt = h.precision != 1 ? h.f64_mfma : nmx >= h.deep_n;
+    // FP64 products on the FMA tile (0) or the FP64 matrix cores (1): the
+    // built-in choice unless the autotuner has one; a level it has not seen
+    // alternates the two over its colours, timed.  The mixed form's FP32
+    // products take the deep tile from pivot order h.deep_n on.
+    bool alt = h.f64_mfma;
     bool explore = false;
     std::string tkey;
     if (!h.tune_cache.empty()) {
@@ -1422,9 +1423,10 @@ static int colour_phase_a(Handle& h, ColourWork& W, std::string& err) {
       explore = it == h.tune.end();
       alt = explore ? (c % 2) == 1 : it->second != 0;
     }
+    const bool deep = nmx >= h.deep_n;
     auto ks = h.precision != 1 ? (alt ? k_schur<false, false, true> : k_schur<false, false, false>)
-              : alt ? k_schur<true, true, false>
-                    : k_schur<true, false, false>;
+              : deep ? (alt ? k_schur<true, true, true> : k_schur<true, true, false>)
+                     : (alt ? k_schur<true, false, true> : k_schur<true, false, false>);
     hipEvent_t ta_ = nullptr, tb_ = nullptr;
     if (explore) {
       ta_ = take_event(h);

@@ -198,11 +198,11 @@ struct Handle {
   // IFMM_DEEP_N: pivot order from which the Schur update takes the deep FP32
   // tile; off by default (the lite tile's occupancy wins at every level measured)
   int deep_n = 1 << 30;
-  // IFMM_F64_MFMA=1: FP64 Schur products of blocks >= 16 x 16 on the FP64
-  // matrix cores instead of the LDS-tiled FMA tile.  Off by default: on this
-  // chip the FP64 matrix-core peak equals the vector peak, and the tile without
-  // LDS staging ran no faster at N = 1M (and slowed the mixed-form kernel)
-  bool f64_mfma = false;
+  // FP64 Schur products on the FP64 matrix cores (LDS-staged tile; the FMA
+  // tile with IFMM_F64_MFMA=0).  The matrix-core peak equals the vector peak
+  // on this chip, but the tile reads a quarter of the LDS bytes per
+  // multiply-add: k_schur 2.6 s against 3.1 s (FP64 form, N = 1M)
+  bool f64_mfma = true;
   int sketch_min = 128;     // Gram order from which a sketch is tried (IFMM_SKETCH_MIN)
   double* skbuf = nullptr;
   int64_t skbuf_bytes = 0;

@@ -262,12 +262,10 @@ constexpr int TRD_BIG = 384;  // matrices of at least this order take the multi-
 // Householder vector of x (length m, in place in A's column): sets e / tau of
 // step `k`; returns the vector (normalised, 0 if x[1:] is already zero) in v.
 __device__ inline void trd_reflector(double* x, int m, double* e, double* tau, int k, double* v) {
-  __shared__ double s_sig;
   const int tid = threadIdx.x;
   double part = 0.0;
   for (int i = 1 + tid; i < m; i += NT) part += x[i] * x[i];
   const double sig = wg_sum(part);
-  if (tid == 0) s_sig = sig;
   __syncthreads();
   const double x0 = x[0];
   if (sig == 0.0) {
@@ -1182,84 +1180,105 @@ struct SchurTask {
 // is formed fresh (no cancellation against stored data) and then compressed
 // at relative accuracy eps.  The near blocks are updated in place, M -= L X,
 // where the difference can be far smaller than either term, and stay FP64.
-// FP64 products of blocks of at least 16 x 16 (inner >= 8) go to the FP64
-// matrix cores in the instance with mf set (FP64 form only: the extra tile's
-// registers would halve the occupancy of the mixed-form kernel), smaller ones
-// to the FMA tile.
+// FP64 products go to the FP64 matrix-core tile in the instances with mf set,
+// to the FMA tile without (both take the one-pass product below 32 x 32 x 32).
+// A template parameter, not a runtime switch, so that one tile's registers do
+// not lower the other instances' occupancy.
 template <bool f32, bool deep, bool mf>
 __device__ inline void schur_gemm(int m, int n, int k, double alpha, const double* A, int lda, const double* B,
                                   int ldb, double beta, double* C, int ldc) {
-  if (!f32 && mf && m >= 16 && n >= 16 && k >= 8) wg_gemm_f64m(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  if (!f32 && mf) wg_gemm_f64m(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
   else if (!f32) wg_gemm(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc);
   else if (deep) wg_gemm_f32_deep(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc);
   else wg_gemm_f32(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc);
 }
-template <bool f32, bool deep, bool mf>
-__device__ inline void schur_block(const LevelView& V, const ElimRec& R, const ElimNbr* nbrs, const int32_t* far_idx,
-                                   const FarPair* far, int a, int b) {
-  const int i = R.node, n = R.n, r = R.r, d = R.d, M = R.M;
-  if (a < R.nnb) {
-    const ElimNbr A = nbrs[R.nb_begin + a];
-    const int np = V.n[A.p];
-    const double* La = R.L + A.off;
-    if (b >= 0) {
-      const ElimNbr B = nbrs[R.nb_begin + b];
-      const double* Xb = R.X + (int64_t)B.off * d;
-      const int fi = far_idx[R.far_base + a * R.nnb + b];
-      if (fi < 0)
-        schur_gemm<false, false, mf>(A.m, B.m, n, -1.0, La, M, Xb, d, 1.0, V.arena + near_block(V, A.p, B.p), np);
-      else schur_gemm<f32, deep, mf>(A.m, B.m, n, -1.0, La, M, Xb, d, 0.0, far[fi].F, A.m);
-    } else {
-      // new block (p, i) = L_a F   with [F; H] = D^-1 [0; I]
-      schur_gemm<false, false, mf>(A.m, r, n, 1.0, La, M, R.X + (int64_t)M * d, d, 0.0, V.arena + A.blk_pi, np);
-    }
-  } else {
-    if (b >= 0) {
-      const ElimNbr B = nbrs[R.nb_begin + b];
-      wg_copy(r, B.m, R.X + n + (int64_t)B.off * d, d, V.arena + B.blk_ip, n);
-    } else {
-      wg_copy(r, r, R.X + n + (int64_t)M * d, d, V.arena + near_block(V, i, i), n, -1.0);
-    }
-  }
-}
-// one 64 x 64 output tile of the update of block (a, b), a < nnb
-template <bool f32, bool deep, bool mf>
-__device__ inline void schur_tile(const LevelView& V, const ElimRec& R, const ElimNbr* nbrs, const int32_t* far_idx,
-                                  const FarPair* far, int a, int b, int ti, int tj) {
+// One product of the Schur update, C = alpha A B + beta C: far (a fill-in
+// block, formed fresh) or near (a stored block updated in place).
+struct SchurProd {
+  int m, n, k, lda, ldb, ldc;
+  double alpha, beta;
+  const double* A;
+  const double* B;
+  double* C;
+  bool far;
+};
+// The product of block (a, b) of the update of record R, a < nnb; b = -1 is
+// the new block (p, i) = L_a F with [F; H] = D^-1 [0; I].  With tj >= 0 only
+// the 64 x 64 output tile (ti, tj) of it.
+__device__ inline SchurProd schur_prod(const LevelView& V, const ElimRec& R, const ElimNbr* nbrs,
+                                       const int32_t* far_idx, const FarPair* far, int a, int b, int ti, int tj) {
   const int n = R.n, d = R.d, M = R.M;
   const ElimNbr A = nbrs[R.nb_begin + a];
   const int np = V.n[A.p];
-  const int i0 = 64 * ti, j0 = 64 * tj;
-  const int mt = min(64, A.m - i0);
-  const double* La = R.L + A.off + i0;
+  const int i0 = tj >= 0 ? 64 * ti : 0, j0 = tj >= 0 ? 64 * tj : 0;
+  SchurProd P;
+  P.m = tj >= 0 ? min(64, A.m - i0) : A.m;
+  P.k = n;
+  P.A = R.L + A.off + i0;
+  P.lda = M;
+  P.ldb = d;
   if (b >= 0) {
     const ElimNbr B = nbrs[R.nb_begin + b];
-    const int nt = min(64, B.m - j0);
-    const double* Xb = R.X + (int64_t)(B.off + j0) * d;
+    P.n = tj >= 0 ? min(64, B.m - j0) : B.m;
+    P.B = R.X + (int64_t)(B.off + j0) * d;
+    P.alpha = -1.0;
     const int fi = far_idx[R.far_base + a * R.nnb + b];
-    if (fi < 0)
-      schur_gemm<false, false, mf>(mt, nt, n, -1.0, La, M, Xb, d, 1.0,
-                               V.arena + near_block(V, A.p, B.p) + i0 + (int64_t)j0 * np, np);
-    else schur_gemm<f32, deep, mf>(mt, nt, n, -1.0, La, M, Xb, d, 0.0, far[fi].F + i0 + (int64_t)j0 * A.m, A.m);
+    P.far = fi >= 0;
+    if (fi < 0) {
+      P.C = V.arena + near_block(V, A.p, B.p) + i0 + (int64_t)j0 * np;
+      P.ldc = np;
+      P.beta = 1.0;
+    } else {
+      P.C = far[fi].F + i0 + (int64_t)j0 * A.m;
+      P.ldc = A.m;
+      P.beta = 0.0;
+    }
   } else {
-    const int nt = min(64, R.r - j0);
-    schur_gemm<false, false, mf>(mt, nt, n, 1.0, La, M, R.X + (int64_t)(M + j0) * d, d, 0.0,
-                             V.arena + A.blk_pi + i0 + (int64_t)j0 * np, np);
+    P.n = tj >= 0 ? min(64, R.r - j0) : R.r;
+    P.B = R.X + (int64_t)(M + j0) * d;
+    P.alpha = 1.0;
+    P.beta = 0.0;
+    P.C = V.arena + A.blk_pi + i0 + (int64_t)j0 * np;
+    P.ldc = np;
+    P.far = false;
+  }
+  return P;
+}
+// The row R_z_i of the update (a = nnb): copies of X's rows, no products.
+__device__ inline void schur_copy(const LevelView& V, const ElimRec& R, const ElimNbr* nbrs, int b) {
+  const int n = R.n, r = R.r, d = R.d, M = R.M;
+  if (b >= 0) {
+    const ElimNbr B = nbrs[R.nb_begin + b];
+    wg_copy(r, B.m, R.X + n + (int64_t)B.off * d, d, V.arena + B.blk_ip, n);
+  } else {
+    wg_copy(r, r, R.X + n + (int64_t)M * d, d, V.arena + near_block(V, R.node, R.node), n, -1.0);
   }
 }
 
+// One task per workgroup: a 64 x 64 output tile of block (a, b), a block
+// (a, b), or a whole row block a (b = -2, its blocks one after the other).
+// Every product goes through one of two call sites (far in the mixed form:
+// FP32 tile; otherwise FP64), so each tile is inlined once.
 template <bool f32, bool deep, bool mf>
 __global__ void __launch_bounds__(NT) k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs,
                                               const SchurTask* tasks, const int32_t* far_idx, const FarPair* far) {
   const SchurTask T = tasks[blockIdx.x];
   const ElimRec R = recs[T.rec];
-  if (T.tile >= 0) {
-    schur_tile<f32, deep, mf>(V, R, nbrs, far_idx, far, T.a, T.b, T.tile & 0xffff, T.tile >> 16);
-  } else if (T.b == -2) {
-    for (int b = 0; b < R.nnb; ++b) schur_block<f32, deep, mf>(V, R, nbrs, far_idx, far, T.a, b);
-    schur_block<f32, deep, mf>(V, R, nbrs, far_idx, far, T.a, -1);
-  } else {
-    schur_block<f32, deep, mf>(V, R, nbrs, far_idx, far, T.a, T.b);
+  const int tile = T.tile;
+  // a row block: its blocks 0..nnb-1, then the new block (b = -1)
+  const int nb = T.b == -2 ? R.nnb + 1 : 1;
+  for (int q = 0; q < nb; ++q) {
+    const int b = T.b == -2 ? (q < R.nnb ? q : -1) : T.b;
+    if (T.a >= R.nnb) {
+      schur_copy(V, R, nbrs, b);
+      continue;
+    }
+    const SchurProd P = schur_prod(V, R, nbrs, far_idx, far, T.a, b, tile >= 0 ? (tile & 0xffff) : 0,
+                                   tile >= 0 ? (tile >> 16) : -1);
+    if (f32 && P.far)
+      schur_gemm<true, deep, false>(P.m, P.n, P.k, P.alpha, P.A, P.lda, P.B, P.ldb, P.beta, P.C, P.ldc);
+    else
+      schur_gemm<false, false, mf>(P.m, P.n, P.k, P.alpha, P.A, P.lda, P.B, P.ldb, P.beta, P.C, P.ldc);
   }
 }
 
