@@ -177,7 +177,8 @@ def run_form(name, pts, dg, args, bt, xt, F5, F4, f_dev, max_steps, warmup):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = IFMM(pts, args.eps, args.sigma, diag=dg, leaf_max=64, precision="mixed" if mixed else "fp64",
-                 bottom_level=args.bottom_level, colouring=args.colouring)
+                 bottom_level=args.bottom_level, colouring=args.colouring,
+                 tune_cache=args.tune_path if mixed and args.tune_path else None)
         if theta is not None:
             h.set_rank_model(theta)
         t1 = time.perf_counter()
@@ -227,6 +228,12 @@ def run_form(name, pts, dg, args, bt, xt, F5, F4, f_dev, max_steps, warmup):
                                          (args.anorm * torch.linalg.norm(xt[k]) + torch.linalg.norm(bt[k])))
                                    for k in range(args.nrhs))
         gm["backward_error_over_eps"] = gm["backward_error"] / args.eps
+    # one untimed single-RHS solve: captures its graph (and, with the
+    # autotuner, times the wave counts for one right-hand side) before GMRES
+    # and the latency below use that path
+    x1 = torch.empty_like(bt[0])
+    _check(load_library().ifmm_solve(h._h, _ptr(bt[0]), _ptr(x1), 1, N, 1))
+    torch.cuda.synchronize()
     if F5 is not None:
         y = F5.matvec(xt[0].contiguous())
         gm["solve_residual_on_cheb5_fmm"] = float(torch.linalg.norm(y - bt[0]) / torch.linalg.norm(bt[0]))
@@ -238,9 +245,8 @@ def run_form(name, pts, dg, args, bt, xt, F5, F4, f_dev, max_steps, warmup):
             del xg
         else:
             gm["gmres_skipped"] = f"budget ({left(args):.0f} s left)"
-    # single-RHS latency of the solve
+    # single-RHS latency of the solve (graph-captured)
     t0 = time.perf_counter()
-    x1 = torch.empty_like(bt[0])
     for _ in range(3):
         _check(load_library().ifmm_solve(h._h, _ptr(bt[0]), _ptr(x1), 1, N, 1))
     torch.cuda.synchronize()
@@ -499,6 +505,9 @@ def main():
                     help="IFMM depth: -1 = chosen by the cost model among the depth of leaves of <= 64 points and "
                          "the two coarser ones (default), 0 = leaves of <= 64 points, >= 2 = forced")
     ap.add_argument("--colouring", choices=("stride", "lookback"), default="stride")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="built-in tile and wave choices (default: the autotuner, tuned in the mixed form's warm-up "
+                         "step and reused by the heuristic form; the FP64 form keeps the built-in choices)")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-geometry batch leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -524,6 +533,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     N = args.n
     log(f"workload: ellipsoid N={N}; budget {args.budget_s:.0f} s")
+    args.tune_path = None
+    if not args.no_tune:  # a fresh autotuner cache per run
+        import tempfile
+        fd, args.tune_path = tempfile.mkstemp(prefix="ifmm_tune_", suffix=".txt")
+        os.close(fd)
+        os.unlink(args.tune_path)
     pts, dg = workload(N)
     b = synth.uniform_rhs(N, args.nrhs, 201)
     bt = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()  # (nrhs, N) row-major = (N, nrhs) col-major
@@ -610,7 +625,8 @@ def main():
                                f"{'by the cost model' if args.bottom_level == -1 else args.bottom_level}; leaves of <= 64 "
                                f"points at depth 7), Chebyshev 4^3, {args.nrhs} RHS; value = factor s of the "
                                f"{'mixed-precision learned-rank' if lead == 'mixed' else lead} form",
-                   "parallelism": "single GPU", "bottom_level": args.bottom_level, "colouring": args.colouring},
+                   "parallelism": "single GPU", "bottom_level": args.bottom_level, "colouring": args.colouring,
+                   "autotuner": "off" if args.no_tune else "mixed and heuristic forms (tuned in the warm-up step)"},
         "factor_s": R.get("factor_s"), "solve_ms_per_rhs": R.get("solve_ms_per_rhs"),
         "steps_requested": args.steps, "warmup_requested": args.warmup,
         "forms": res,
@@ -626,6 +642,10 @@ def main():
         out["learned_rank_ablation"] = {
             k: {"mixed": res["mixed"].get(k), "heuristic": res["heuristic"].get(k)}
             for k in ("factor_s", "sketches", "sketches_rejected", "full_decompositions")}
+    if args.tune_path and os.path.exists(args.tune_path):
+        with open(args.tune_path) as fh:
+            out["autotuner_choices"] = [ln.strip() for ln in fh if ln.strip() and not ln.startswith("#")]
+        os.unlink(args.tune_path)
     print(json.dumps(out), flush=True)
 
 

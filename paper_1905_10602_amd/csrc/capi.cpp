@@ -251,15 +251,18 @@ ifmm_status ifmm_stats(const ifmm_handle* H, char* json, int64_t cap) {
                   ",\"levels\":[";
   for (int l = 2; l <= h.tree.depth; ++l) {
     const ifmm::Level& T = h.tree.levels[l];
-    long long rs = 0, rm = 0, ns = 0, nm = 0;
+    long long rs = 0, rm = 0, ns = 0, nm = 0, sg = 0, st = 0;
     if ((int)h.lv.size() > l) {
       const ifmm::DevLevel& L = h.lv[l];
       for (size_t i = 0; i < L.r.size(); ++i) { rs += L.r[i]; rm = std::max<long long>(rm, L.r[i]); }
       for (size_t i = 0; i < L.n.size(); ++i) { ns += L.n[i]; nm = std::max<long long>(nm, L.n[i]); }
+      sg = (long long)L.sg.size();
+      st = (long long)L.st_b.size();
     }
     s += std::string(l > 2 ? "," : "") + "{\"level\":" + std::to_string(l) + ",\"nodes\":" + std::to_string(T.n) +
          ",\"colours\":" + std::to_string(T.ncolour) + ",\"rank_sum\":" + std::to_string(rs) +
          ",\"rank_max\":" + std::to_string(rm) + ",\"n_sum\":" + std::to_string(ns) + ",\"n_max\":" + std::to_string(nm) +
+         ",\"solve_bwd_tasks\":" + std::to_string(st) + ",\"solve_split_tiles\":" + std::to_string(sg) +
          ",\"t_setup\":" + std::to_string((int)h.t_level_setup.size() > l ? h.t_level_setup[l] : 0.0) +
          ",\"t_elim\":" + std::to_string((int)h.t_level_elim.size() > l ? h.t_level_elim[l] : 0.0) + "}";
   }

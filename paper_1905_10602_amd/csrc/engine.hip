@@ -2146,14 +2146,43 @@ static int colour_keep(Handle& h, ColourWork& W, std::string& err) {
     R.nb_begin += nbase;
     R.X = nullptr;
     const int32_t ri = (int32_t)L.recs.size();
-    for (int r0 = 0; r0 < R.d; r0 += 64) L.st_w.push_back({ri, r0});
-    for (int r0 = 0; r0 < R.M; r0 += 64) L.st_u.push_back({ri, r0});
-    for (int r0 = 0; r0 < R.n; r0 += 64) L.st_b.push_back({ri, r0});
+    for (int r0 = 0; r0 < R.d; r0 += 64) L.st_w.push_back({ri, r0, 0, INT32_MAX, -1});
+    for (int r0 = 0; r0 < R.M; r0 += 64) L.st_u.push_back({ri, r0, 0, INT32_MAX, -1});
     L.recs.push_back(R);
+  }
+  // backward step: a colour of few row tiles (the upper levels) splits each
+  // tile's inner dimension (64-column chunks over the neighbours' G blocks,
+  // then E_tb) over several tasks, up to about 1024 tasks in all and at least
+  // 8 chunks per task; their partial sums are added in order by a second
+  // kernel, so the result does not depend on the split's timing
+  {
+    const int rb = (int)L.recs.size() - (int)recs.size();
+    int ntile = 0;
+    for (const ElimRec& R : recs) ntile += (R.n + 63) / 64;
+    int32_t slots = 0;
+    for (int k = 0; k < (int)recs.size(); ++k) {
+      const ElimRec& R = recs[k];
+      int G = (R.r + 63) / 64;
+      for (int q = 0; q < R.nnb; ++q) G += (nbrs[R.nb_begin + q].m + 63) / 64;
+      int ns = 1;
+      if (h.solve_split && ntile > 0 && ntile < 512) ns = std::max(1, std::min((1024 + ntile - 1) / ntile, G / 8));
+      for (int r0 = 0; r0 < R.n; r0 += 64) {
+        if (ns == 1) {
+          L.st_b.push_back({rb + k, r0, 0, INT32_MAX, -1});
+          continue;
+        }
+        L.sg.push_back({rb + k, r0, slots, ns});
+        for (int s = 0; s < ns; ++s)
+          L.st_b.push_back({rb + k, r0, (int32_t)((int64_t)G * s / ns), (int32_t)((int64_t)G * (s + 1) / ns), slots + s});
+        slots += ns;
+      }
+    }
+    L.part_slots = std::max(L.part_slots, slots);
   }
   L.stw_ptr.push_back((int32_t)L.st_w.size());
   L.stu_ptr.push_back((int32_t)L.st_u.size());
   L.stb_ptr.push_back((int32_t)L.st_b.size());
+  L.sg_ptr.push_back((int32_t)L.sg.size());
   L.nbrs.insert(L.nbrs.end(), nbrs.begin(), nbrs.end());
   L.col_ptr.push_back((int32_t)L.recs.size());
   ColourInv ci;
@@ -2265,6 +2294,9 @@ static int finish_level(Handle& h, int l, std::string& err) {
     all.insert(all.end(), L.st_b.begin(), L.st_b.end());
     if ((rc = upload(h, &L.d_st, all, err))) return rc;
   }
+  dfree(h, L.d_sg);
+  L.d_sg = nullptr;
+  if (!L.sg.empty() && (rc = upload(h, &L.d_sg, L.sg, err))) return rc;
   // solve-vector offsets
   L.vx_off.resize(L.nn);
   L.vz_off.resize(L.nn);
@@ -2292,7 +2324,7 @@ static void clear_factor(Handle& h) {
     release_level_work(h, (int)l);
     DevLevel& L = h.lv[l];
     void* ptrs[] = {L.d_recs, L.d_nbrs, L.d_vx_off, L.d_vz_off, L.d_n, L.d_r, L.d_parent, L.d_child_ptr, L.d_child,
-                    L.d_st};
+                    L.d_st, L.d_sg};
     for (void* p : ptrs) dfree(h, p);
     L = DevLevel();
   }
@@ -2342,6 +2374,7 @@ int factor(Handle& h, std::string& err) {
   if (const char* e = std::getenv("IFMM_DEEP_N")) h.deep_n = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("IFMM_F64_MFMA")) h.f64_mfma = std::atoi(e) != 0;
   tune_load(h);
+  if (const char* e = std::getenv("IFMM_SOLVE_SPLIT")) h.solve_split = std::atoi(e) != 0;
   // IFMM_SOLVE32=1 (mixed form): the solve reads FP32 copies of L and G.  It
   // halves the store but ran slower than the FP64 blocks (the conversions
   // sit in the column loop), so it is off by default
@@ -2379,6 +2412,9 @@ int factor(Handle& h, std::string& err) {
     L.cinv.clear();
     L.st_w.clear(); L.st_u.clear(); L.st_b.clear();
     L.stw_ptr.assign(1, 0); L.stu_ptr.assign(1, 0); L.stb_ptr.assign(1, 0);
+    L.sg.clear();
+    L.sg_ptr.assign(1, 0);
+    L.part_slots = 0;
     ta = now_s();
     h.cur_level = l;
     for (int c = 0; c < T.ncolour; ++c)
@@ -2509,7 +2545,7 @@ static SolvePlan solve_plan(const Handle& h, int k, int64_t ld, bool staging) {
     P.ox[l] = tot; tot += L.vx_total * k + 32;
     P.oz[l] = tot; tot += L.vz_total * k + 32;
     P.ow[l] = tot; tot += L.wv_total * k + 32;
-    P.ot[l] = tot; tot += L.wv_total * k + 32;
+    P.ot[l] = tot; tot += (int64_t)L.part_slots * 64 * k + 32;  // partial sums of split backward tiles
   }
   P.otop = tot;
   tot += 2 * (int64_t)std::max(h.top_n, 1) * k + 32;
@@ -2548,7 +2584,7 @@ static void enqueue_solve(Handle& h, const SolvePlan& P, double* B, const double
   const int D = h.tree.depth;
   auto sv = [&](int l) {
     SolveView S;
-    S.X = B + P.ox[l]; S.Z = B + P.oz[l]; S.W = B + P.ow[l]; S.tmp = B + P.ot[l];
+    S.X = B + P.ox[l]; S.Z = B + P.oz[l]; S.W = B + P.ow[l]; S.part = B + P.ot[l];
     S.xo = h.lv[l].d_vx_off; S.zo = h.lv[l].d_vz_off; S.k = k;
     return S;
   };
@@ -2667,6 +2703,10 @@ static void enqueue_solve(Handle& h, const SolvePlan& P, double* B, const double
         IFMM_SOLVE_LAUNCH(k_solve_bwd, float, k, nw, tb1 - tb0, h.stream, L.d_recs, L.d_nbrs, st_b + tb0, S);
       else
         IFMM_SOLVE_LAUNCH(k_solve_bwd, double, k, nw, tb1 - tb0, h.stream, L.d_recs, L.d_nbrs, st_b + tb0, S);
+      const int sg0 = L.sg_ptr[c], sg1 = L.sg_ptr[c + 1];
+      if (sg1 > sg0)  // split tiles: x = w - the partial sums, added in order
+        hipLaunchKernelGGL(k_solve_bwd_sum, dim3((unsigned)(sg1 - sg0)), dim3(NT), 0, h.stream, L.d_recs,
+                           L.d_sg + sg0, S);
       tstop(ev, "solve_bwd", l);
     }
   }

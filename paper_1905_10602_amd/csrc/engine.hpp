@@ -39,6 +39,13 @@ struct ElimRec {
 // One 64-row tile of a stored block in the solve.
 struct STask {
   int32_t rec, r0;  // record (index in the level's elimination order), first row of the tile
+  int32_t g0, g1;   // backward step: the 64-column chunks [g0, g1) of the inner dimension this task sums
+  int32_t slot;     // backward step split over several tasks: partial-sum slot, else -1 (writes x directly)
+};
+// Backward-step tile whose inner dimension is split over `ns` tasks: its
+// partial sums sit in slots slot0 .. slot0 + ns - 1 and are added in order.
+struct SGroup {
+  int32_t rec, r0, slot0, ns;
 };
 
 struct ElimNbr {
@@ -118,6 +125,10 @@ struct DevLevel {
   // holding w, then upd, then b
   std::vector<STask> st_w, st_u, st_b;
   std::vector<int32_t> stw_ptr, stu_ptr, stb_ptr;
+  std::vector<SGroup> sg;          // per colour (sg_ptr) the split backward tiles
+  std::vector<int32_t> sg_ptr;
+  SGroup* d_sg = nullptr;
+  int32_t part_slots = 0;          // most partial-sum slots of one colour
   STask* d_st = nullptr;
   ElimRec* d_recs = nullptr;
   ElimNbr* d_nbrs = nullptr;
@@ -159,6 +170,7 @@ struct Handle {
   float* store32_cur = nullptr;
   int64_t store32_left = 0;
   bool solve32 = false;  // mixed form, IFMM_SOLVE32=1: the solve reads FP32 L and G blocks
+  bool solve_split = true;  // IFMM_SOLVE_SPLIT=0: no split backward tiles (one task per row tile)
   // growable buffers
   double* scratch = nullptr;
   int64_t scratch_bytes = 0;

@@ -1790,9 +1790,10 @@ __global__ void __launch_bounds__(NT) k_lu_inverse(const double* T, int n, const
 
 // ------------------------------------------------------------------ solve
 // Node vectors per level: X (x-part, n_i x k at xo[i] * k) and Z (z-part /
-// later y-part, r_i x k at zo[i] * k); W: w_i (d x k) per elimination.
+// later y-part, r_i x k at zo[i] * k); W: w_i (d x k) per elimination;
+// part: partial sums of split backward tiles (64 x k per slot).
 struct SolveView {
-  double *X, *Z, *W, *tmp;
+  double *X, *Z, *W, *part;
   const int64_t *xo, *zo;
   int k;
 };
@@ -1871,12 +1872,14 @@ __device__ inline void wave_gemv_chunk(const T* A, int64_t lda, bool act, const 
 }
 
 // One segment of a tile's inner dimension, split into 64-column chunks that
-// the NW waves of the workgroup take in turn (g counts chunks over segments).
+// the NW waves of the workgroup take in turn (g counts chunks over segments);
+// only the chunks g0 <= g < g1 are this task's.
 template <int SK, int NW, typename T>
 __device__ inline void seg_gemv(const T* A, int64_t lda, bool act, const double* x, int64_t ldx, int len, int kc,
-                                int lane, int wave, double sign, int& g, double* acc, double* xs) {
+                                int lane, int wave, double sign, int& g, double* acc, double* xs, int g0 = 0,
+                                int g1 = INT32_MAX) {
   for (int j0 = 0; j0 < len; j0 += 64, ++g)
-    if (g % NW == wave)
+    if (g >= g0 && g < g1 && (g - g0) % NW == wave)
       wave_gemv_chunk<SK, T>(A + (int64_t)j0 * lda, lda, act, x + j0, ldx, min(64, len - j0), kc, lane, sign, acc,
                              xs);
 }
@@ -2026,7 +2029,8 @@ __global__ void __launch_bounds__(64 * NW) k_solve_bwd(const ElimRec* recs, cons
         }
         if (len > 0)
           seg_gemv<SK, NW, double>(Ap + (act ? row : 0), lda, act, xq, len, len, kc, lane, wave, sign, g, acc,
-                                   &red[wave][0][0]);
+                                   &red[wave][0][0], T.g0, T.g1);
+        if (g >= T.g1) break;  // the rest of the inner dimension belongs to later tasks
       }
     } else {
       for (int q = 0; q < R.nnb; ++q) {
@@ -2034,17 +2038,43 @@ __global__ void __launch_bounds__(64 * NW) k_solve_bwd(const ElimRec* recs, cons
         if (B.m == 0) continue;
         const double* xq = (B.elim ? S.Z + S.zo[B.p] * k : S.X + S.xo[B.p] * k) + (int64_t)c0 * B.m;
         seg_gemv<SK, NW, E>(solve_U<E>(R) + (act ? row : 0) + (int64_t)B.off * n, n, act, xq, B.m, B.m, kc, lane,
-                            wave, 1.0, g, acc, &red[wave][0][0]);
+                            wave, 1.0, g, acc, &red[wave][0][0], T.g0, T.g1);
       }
       seg_gemv<SK, NW, double>(R.lu + (act ? row : 0) + (int64_t)n * d, d, act, yi + (int64_t)c0 * r, r, r, kc, lane,
-                               wave, -1.0, g, acc, &red[wave][0][0]);
+                               wave, -1.0, g, acc, &red[wave][0][0], T.g0, T.g1);
     }
     if (wg_reduce_acc<SK, NW>(red, lane, wave, acc) && act) {
+      if (T.slot < 0) {
 #pragma unroll
-      for (int c = 0; c < SK; ++c)
-        if (c < kc) xi[row + (int64_t)(c0 + c) * n] = wt[row + (int64_t)(c0 + c) * n] - acc[c];
+        for (int c = 0; c < SK; ++c)
+          if (c < kc) xi[row + (int64_t)(c0 + c) * n] = wt[row + (int64_t)(c0 + c) * n] - acc[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < SK; ++c)
+          if (c < kc) S.part[((int64_t)T.slot * k + c0 + c) * 64 + lane] = acc[c];
+      }
     }
     if (NW > 1) __syncthreads();
+  }
+}
+
+// Split backward tiles: x_i = w - (sum of the tile's partial sums, in slot
+// order).  One workgroup per tile; rows over lanes, right-hand sides over the
+// workgroup's waves.
+__global__ void __launch_bounds__(NT) k_solve_bwd_sum(const ElimRec* recs, const SGroup* groups, SolveView S) {
+  const SGroup G = groups[blockIdx.x];
+  const ElimRec R = recs[G.rec];
+  const int n = R.n, k = S.k;
+  const int rows = min(64, n - G.r0);
+  const double* wt = S.W + R.wv * k;
+  double* xi = S.X + S.xo[R.node] * k;
+  WG_FOR2(64, k, lr, c) {
+    if (lr < rows) {
+      double v = 0.0;
+      for (int s = 0; s < G.ns; ++s) v += S.part[((int64_t)(G.slot0 + s) * k + c) * 64 + lr];
+      const int row = G.r0 + lr;
+      xi[row + (int64_t)c * n] = wt[row + (int64_t)c * n] - v;
+    }
   }
 }
 

@@ -214,6 +214,31 @@ def test_fp64_matrix_core_schur_matches_oracle(monkeypatch):
     assert np.linalg.norm(xm - xf) <= 10 * eps * np.linalg.norm(xf)
 
 
+def test_split_backward_tiles_match_unsplit(monkeypatch):
+    # colours with few backward row tiles split each tile's inner dimension
+    # over several workgroups and add the partial sums in order; against one
+    # task per tile (IFMM_SOLVE_SPLIT=0) only the summation order differs
+    N, eps = 20000, 1e-6
+    print(f"case split backward tiles sphere N={N}", flush=True)
+    pts, dg = _case("sphere", N, 12)
+    b = synth.uniform_rhs(N, 8, 71)
+    out = {}
+    for v in ("1", "0"):
+        monkeypatch.setenv("IFMM_SOLVE_SPLIT", v)
+        h = _gpu(pts, eps, 3, dg, 64)
+        st = h.stats()
+        out[v] = (h.solve(b), h.solve(b[:, :1]), [lv["rank_sum"] for lv in st["levels"]],
+                  sum(lv["solve_split_tiles"] for lv in st["levels"]))
+    (x1, y1, r1, s1), (x0, y0, r0, s0) = out["1"], out["0"]
+    print(f"split tiles: {s1} (split) / {s0} (unsplit)", flush=True)
+    assert s1 > 0 and s0 == 0
+    assert r1 == r0
+    rel = np.linalg.norm(x1 - x0) / np.linalg.norm(x0)
+    rel1 = np.linalg.norm(y1 - y0) / np.linalg.norm(y0)
+    print(f"split vs unsplit: {rel:.2e} (8 RHS), {rel1:.2e} (1 RHS)", flush=True)
+    assert rel <= 1e-12 and rel1 <= 1e-12
+
+
 def test_mixed_solve_reads_fp32_blocks(monkeypatch):
     # mixed form with IFMM_SOLVE32=1: the solve reads FP32 copies of the
     # stored L and G blocks (FP64 vectors and pivot inverses).  Against the
