@@ -59,8 +59,12 @@ HBM_PEAK = 8.0e12               # bytes/s
 FP32_MFMA_PEAK = 157.3e12      # dense FP32 matrix-core peak
 BOUND = {"k_solve_fwd_w": "hbm", "k_solve_fwd_upd": "hbm", "k_solve_bwd": "hbm", "k_gather": "hbm",
          "solve": "hbm"}
-MFMA_F32 = {"k_schur"}          # runs on FP32 matrix cores in the mixed form
-MFMA_F64 = set()                 # kernels on FP64 matrix cores in the FP64 form
+# k_schur: the Schur update's FP64 products (FP64 matrix cores) and, in the
+# mixed form without IFMM_SCHUR_SPLIT, also its far products (FP32 matrix
+# cores; the peak is then blended by the flops share); k_schur_far: the
+# mixed form's far products alone (FP32 matrix cores)
+MFMA_F32 = {"k_schur", "k_schur_far"}
+MFMA_F64 = {"k_schur"}
 
 
 def log(msg):
@@ -326,7 +330,7 @@ def price(name, k, mixed, f32_flops=None):
         peak = FP32_MFMA_PEAK
         if f32_flops is not None and k["flops"] > 0:
             f = min(max(f32_flops / k["flops"], 0.0), 1.0)  # flops share on FP32 matrix cores
-            peak = 1.0 / (f / FP32_MFMA_PEAK + (1.0 - f) / FP64_VECTOR_PEAK)
+            peak = 1.0 / (f / FP32_MFMA_PEAK + (1.0 - f) / FP64_MFMA_PEAK)
             common["fp32_share_of_flops"] = f
         return {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": ach / peak, **common}
@@ -348,8 +352,13 @@ def roofline_of(stats, mixed):
 
 
 def _f32_flops(stats, name):
+    """Flops of `name` on FP32 matrix cores: all of k_schur_far; for k_schur
+    the far products' share unless they ran as their own kernel."""
+    ks = stats.get("kernels", {})
+    if name == "k_schur_far":
+        return ks[name]["flops"]
     if name == "k_schur":
-        return stats.get("aux", {}).get("schur_far_flops")
+        return 0.0 if "k_schur_far" in ks else stats.get("aux", {}).get("schur_far_flops")
     return None
 
 
@@ -358,7 +367,7 @@ def roofline_more(stats, mixed):
     whole captured solve) beside the dominant kernel."""
     ks = stats.get("kernels", {})
     out = {}
-    for n in ("k_schur", "k_eig_values", "k_solve_fwd_w", "k_solve_fwd_upd", "k_solve_bwd"):
+    for n in ("k_schur", "k_schur_far", "k_eig_values", "k_solve_fwd_w", "k_solve_fwd_upd", "k_solve_bwd"):
         if n in ks:
             out[n] = price(n, ks[n], mixed, _f32_flops(stats, n))
     # the three solve steps together: algorithmic bytes over their summed time

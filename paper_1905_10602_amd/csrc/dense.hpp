@@ -14,6 +14,26 @@ namespace ifmm {
 
 constexpr int NT = 256;           // threads per workgroup
 
+// The same address as a global-memory pointer.  Pointers read from task
+// tables are generic to the compiler, and generic (flat) loads count against
+// the LDS counter as well, so a wait for an LDS result also waits for every
+// global load in flight; loads through these pointers are global loads.
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+// Global-memory pointer when G (the operands of the GEMM tiles), else the
+// generic pointer (a caller whose operands may live in LDS).
+template <bool G, class T>
+__device__ inline auto gsel(T* p) {
+  if constexpr (G) return gmem(p);
+  else return p;
+}
+
 // Workgroup-strided loop over an R x C index range, rows fastest (coalesced
 // for column-major data).  One 32-bit division at entry, none per step.
 // Requires R > 0.
@@ -24,9 +44,13 @@ constexpr int NT = 256;           // threads per workgroup
 
 // Small product (m, n, k <= 32): both operands staged whole in LDS (the
 // caller's buffer of at least 2 * 32 * 33 doubles), one pass, no k-chunks.
-__device__ inline void wg_gemm_small(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
-                                     const double* B, int ldb, bool tB, double beta, double* C, int ldc,
+template <bool G = true>
+__device__ inline void wg_gemm_small(int m, int n, int k, double alpha, const double* A_, int lda, bool tA,
+                                     const double* B_, int ldb, bool tB, double beta, double* C_, int ldc,
                                      double* smem) {
+  const auto A = gsel<G>(A_);
+  const auto B = gsel<G>(B_);
+  const auto C = gsel<G>(C_);
   const int tid = threadIdx.x;
   double (*As)[33] = reinterpret_cast<double (*)[33]>(smem);
   double (*Bs)[33] = reinterpret_cast<double (*)[33]>(smem + 32 * 33);
@@ -43,7 +67,7 @@ __device__ inline void wg_gemm_small(int m, int n, int k, double alpha, const do
     const int i = e % m, j = e / m;
     double acc = 0.0;
     for (int q = 0; q < k; ++q) acc = fma(As[i][q], Bs[q][j], acc);
-    double* c = C + i + (int64_t)j * ldc;
+    auto c = C + i + (int64_t)j * ldc;
     *c = (beta == 0.0) ? alpha * acc : fma(alpha, acc, beta * (*c));
   }
   __syncthreads();
@@ -53,14 +77,18 @@ __device__ inline void wg_gemm_small(int m, int n, int k, double alpha, const do
 // op(A) is m x k, op(B) is k x n.  beta == 0 overwrites C (NaNs in C ignored).
 // LDS tiles of 64 x 16 (A) and 16 x 64 (B); each thread owns a 4 x 4 block
 // of the 64 x 64 output tile, rows strided by 16 for coalesced stores.
-__device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
-                               const double* B, int ldb, bool tB, double beta, double* C, int ldc) {
+template <bool G = true>
+__device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* A_, int lda, bool tA,
+                               const double* B_, int ldb, bool tB, double beta, double* C_, int ldc) {
+  const auto A = gsel<G>(A_);
+  const auto B = gsel<G>(B_);
+  const auto C = gsel<G>(C_);
   __shared__ double smem[2 * 16 * 65 + 64];
   double (*sA)[65] = reinterpret_cast<double (*)[65]>(smem);
   double (*sB)[65] = reinterpret_cast<double (*)[65]>(smem + 16 * 65);
   const int tid = threadIdx.x;
   if (m <= 32 && n <= 32 && k <= 32) {
-    wg_gemm_small(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc, smem);
+    wg_gemm_small<G>(m, n, k, alpha, A_, lda, tA, B_, ldb, tB, beta, C_, ldc, smem);
     return;
   }
   const int tr = tid & 15, tc = tid >> 4;
@@ -132,7 +160,7 @@ __device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* 
         for (int a = 0; a < 4; ++a) {
           const int gi = i0 + tr + 16 * a;
           if (gi >= m) continue;
-          double* c = C + gi + (int64_t)gj * ldc;
+          auto c = C + gi + (int64_t)gj * ldc;
           *c = (beta == 0.0) ? alpha * acc[a][b] : fma(alpha, acc[a][b], beta * (*c));
         }
       }
@@ -151,9 +179,13 @@ __device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 // 64 x 64 tiles, k-chunks of 16 through one LDS buffer pair (lds: at least
 // 2 x 16 x 68 floats), the next chunk prefetched into registers.
-__device__ inline void wg_gemm_f32_lite(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
-                                        const double* B, int ldb, bool tB, double beta, double* C, int ldc,
+template <bool G = true>
+__device__ inline void wg_gemm_f32_lite(int m, int n, int k, double alpha, const double* A_, int lda, bool tA,
+                                        const double* B_, int ldb, bool tB, double beta, double* C_, int ldc,
                                         float* lds) {
+  const auto A = gsel<G>(A_);
+  const auto B = gsel<G>(B_);
+  const auto C = gsel<G>(C_);
   float (*fA)[68] = reinterpret_cast<float (*)[68]>(lds);
   float (*fB)[68] = reinterpret_cast<float (*)[68]>(lds + 16 * 68);
   const int tid = threadIdx.x;
@@ -216,7 +248,7 @@ __device__ inline void wg_gemm_f32_lite(int m, int n, int k, double alpha, const
         for (int v = 0; v < 16; ++v) {
           const int gj = j0 + wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
           if (gj < n) {
-            double* c = C + gi + (int64_t)gj * ldc;
+            auto c = C + gi + (int64_t)gj * ldc;
             *c = (beta == 0.0) ? alpha * (double)acc[v] : fma(alpha, (double)acc[v], beta * (*c));
           }
         }
@@ -230,9 +262,13 @@ __device__ inline void wg_gemm_f32_lite(int m, int n, int k, double alpha, const
 // 2 x 2 x 32 x 65 floats): chunk c + 1 is loaded into registers while chunk c
 // is multiplied, then written to the other pair; one barrier per chunk.  Rows
 // padded to 65 floats (conflict-free column writes).  For long inner dimensions.
-__device__ inline void wg_gemm_f32_kc32(int m, int n, int k, double alpha, const double* A, int lda, bool tA,
-                                        const double* B, int ldb, bool tB, double beta, double* C, int ldc,
+template <bool G = true>
+__device__ inline void wg_gemm_f32_kc32(int m, int n, int k, double alpha, const double* A_, int lda, bool tA,
+                                        const double* B_, int ldb, bool tB, double beta, double* C_, int ldc,
                                         float* lds) {
+  const auto A = gsel<G>(A_);
+  const auto B = gsel<G>(B_);
+  const auto C = gsel<G>(C_);
   constexpr int KC = 32;
   float (*fA)[KC][65] = reinterpret_cast<float (*)[KC][65]>(lds);
   float (*fB)[KC][65] = reinterpret_cast<float (*)[KC][65]>(lds + 2 * KC * 65);
@@ -296,7 +332,7 @@ __device__ inline void wg_gemm_f32_kc32(int m, int n, int k, double alpha, const
         for (int v = 0; v < 16; ++v) {
           const int gj = j0 + wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
           if (gj < n) {
-            double* c = C + gi + (int64_t)gj * ldc;
+            auto c = C + gi + (int64_t)gj * ldc;
             *c = (beta == 0.0) ? alpha * (double)acc[v] : fma(alpha, (double)acc[v], beta * (*c));
           }
         }
@@ -346,11 +382,15 @@ __device__ inline void wg_gemm_f32_deep(int m, int n, int k, double alpha, const
 // register blocks, which makes this tile bound by the matrix cores rather
 // than by LDS bandwidth.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-__device__ inline void wg_gemm_f64m(int m, int n, int k, double alpha, const double* A, int lda, const double* B,
-                                    int ldb, double beta, double* C, int ldc) {
+template <bool G = true>
+__device__ inline void wg_gemm_f64m(int m, int n, int k, double alpha, const double* A_, int lda, const double* B_,
+                                    int ldb, double beta, double* C_, int ldc) {
+  const auto A = gsel<G>(A_);
+  const auto B = gsel<G>(B_);
+  const auto C = gsel<G>(C_);
   __shared__ double lds64[2 * 16 * 68];  // >= 2 x 32 x 33 for the small product
   if (m <= 32 && n <= 32 && k <= 32) {   // too small for the tiles: the one-pass product
-    wg_gemm_small(m, n, k, alpha, A, lda, false, B, ldb, false, beta, C, ldc, lds64);
+    wg_gemm_small<G>(m, n, k, alpha, A_, lda, false, B_, ldb, false, beta, C_, ldc, lds64);
     return;
   }
   double (*fA)[68] = reinterpret_cast<double (*)[68]>(lds64);
@@ -421,7 +461,7 @@ __device__ inline void wg_gemm_f64m(int m, int n, int k, double alpha, const dou
           for (int v = 0; v < 4; ++v) {
             const int i = i0 + wr + 16 * ri + lr, j = j0 + wc + 16 * cj + 4 * v + lk;
             if (i < m && j < n) {
-              double* c = C + i + (int64_t)j * ldc;
+              auto c = C + i + (int64_t)j * ldc;
               *c = beta == 0.0 ? alpha * acc[ri][cj][v] : fma(alpha, acc[ri][cj][v], beta * *c);
             }
           }
@@ -774,9 +814,9 @@ __device__ inline void wg_trd_eigenvalues(int n, const double* A, int lda, doubl
 __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const double* W, const double* lam, int k,
                                        double* X, int ldx, double* IW) {
   __shared__ double s_c[NT];
-  const double* d = W;
-  const double* e = W + n;
-  const double* tau = W + 2 * n;
+  const auto d = gmem(W);
+  const auto e = gmem(W + n);
+  const auto tau = gmem(W + 2 * n);
   const int tid = threadIdx.x;
   if (k <= 0) return;
   if (n == 1) {
@@ -788,11 +828,11 @@ __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const do
   const double tiny = 2.2e-16 * nrm;
   for (int j = tid; j < k; j += NT) {
     // interleaved per-thread arrays: element i of vector j at [i * k + j]
-    double* u0 = IW;
-    double* u1 = IW + (int64_t)n * k;
-    double* u2 = IW + 2 * (int64_t)n * k;
-    double* ll = IW + 3 * (int64_t)n * k;
-    double* pv = IW + 4 * (int64_t)n * k;
+    const auto u0 = gmem(IW);
+    const auto u1 = gmem(IW + (int64_t)n * k);
+    const auto u2 = gmem(IW + 2 * (int64_t)n * k);
+    const auto ll = gmem(IW + 3 * (int64_t)n * k);
+    const auto pv = gmem(IW + 4 * (int64_t)n * k);
     const double mu = lam[j];
     double cd = d[0] - mu, cs = e[0];
     for (int i = 0; i + 1 < n; ++i) {
@@ -816,10 +856,10 @@ __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const do
       u0[o] = cd; u1[o] = 0.0; u2[o] = 0.0; ll[o] = 0.0; pv[o] = 0.0;
     }
     for (int i = 0; i < n; ++i) {
-      double& u = u0[(int64_t)i * k + j];
+      auto& u = u0[(int64_t)i * k + j];
       if (fabs(u) < tiny) u = (u < 0.0) ? -tiny : tiny;
     }
-    double* x = X + (int64_t)j * ldx;
+    const auto x = gmem(X + (int64_t)j * ldx);
     // distinct pseudo-random start per vector: within a (near-)degenerate
     // cluster the iterates then span the cluster's eigenspace
     for (int i = 0; i < n; ++i) {

@@ -932,6 +932,7 @@ struct ColourWork {
   const XTask* d_xt = nullptr;
   LevelView V;
   double fl_lu = 0, fl_x = 0, fl_schur = 0, by_gather = 0, by_schur = 0, fl_gram = 0, fl_ev = 0, fl_evec = 0;
+  double fl_far = 0;  // the far fill-in products' share of fl_schur
   // recompression: counts per task, pivot info per record, the tasks that
   // ended with a full decomposition and the accepted sketches
   std::vector<int32_t> cnt, info, full_ids, sk_ids, fe_ids;
@@ -1294,7 +1295,8 @@ static int colour_upload(Handle& h, ColourWork& W, std::string& err) {
   V = view_of(L);
   nchg = (int)chg.size();
   // algorithmic work of the phase-A steps (counted from the block sizes)
-  double fl_far = 0;
+  double& fl_far = W.fl_far;
+  fl_far = 0;
   for (const FarPair& F : far) {  // far fill-in products (FP32 in the mixed form)
     const ElimRec& R = recs[F.rec];
     fl_far += 2.0 * nbrs[R.nb_begin + F.a].m * (double)R.n * nbrs[R.nb_begin + F.b].m;
@@ -1354,6 +1356,7 @@ static int colour_phase_a(Handle& h, ColourWork& W, std::string& err) {
   auto& by_gather = W.by_gather;
   auto& by_schur = W.by_schur;
   auto& fl_gram = W.fl_gram;
+  const double fl_far = W.fl_far;
   int rc = 0;
   // ---- phase A
   {
@@ -1404,7 +1407,6 @@ static int colour_phase_a(Handle& h, ColourWork& W, std::string& err) {
     hipLaunchKernelGGL(k_store_solve, dim3((unsigned)((wmax + 63) / 64), (unsigned)nrec), dim3(NT), 0, h.stream, d_recs);
   }
   {
-    ProfScope ps(h, "k_schur", fl_schur, by_schur);
     // inner dimension of the products = n of the pivot; the double-buffered
     // FP32 tile only from pivot order h.deep_n on (off unless set: the lite
     // tile keeps more workgroups resident and measured faster at every level)
@@ -1424,21 +1426,37 @@ static int colour_phase_a(Handle& h, ColourWork& W, std::string& err) {
       alt = explore ? (c % 2) == 1 : it->second != 0;
     }
     const bool deep = nmx >= h.deep_n;
-    auto ks = h.precision != 1 ? (alt ? k_schur<false, false, true> : k_schur<false, false, false>)
-              : deep ? (alt ? k_schur<true, true, true> : k_schur<true, true, false>)
-                     : (alt ? k_schur<true, false, true> : k_schur<true, false, false>);
-    hipEvent_t ta_ = nullptr, tb_ = nullptr;
-    if (explore) {
-      ta_ = take_event(h);
-      tb_ = take_event(h);
-      HIPCHK(hipEventRecord(ta_, h.stream));
+    // mixed form: the near products (FP64) on the main stream and the far
+    // fill-in products (FP32) on the side stream at the same time, as two
+    // kernels with one tile each (they write disjoint blocks)
+    const bool split = h.precision == 1 && h.schur_split && fl_far > 0;
+    if (split && (rc = fork_side(h, err))) return rc;
+    {
+      ProfScope ps(h, "k_schur", split ? fl_schur - fl_far : fl_schur, by_schur);
+      auto ks = h.precision != 1 ? (alt ? k_schur<false, false, true, 0> : k_schur<false, false, false, 0>)
+                : split ? (alt ? k_schur<true, false, true, 1> : k_schur<true, false, false, 1>)
+                : deep  ? (alt ? k_schur<true, true, true, 0> : k_schur<true, true, false, 0>)
+                        : (alt ? k_schur<true, false, true, 0> : k_schur<true, false, false, 0>);
+      hipEvent_t ta_ = nullptr, tb_ = nullptr;
+      if (explore) {
+        ta_ = take_event(h);
+        tb_ = take_event(h);
+        HIPCHK(hipEventRecord(ta_, h.stream));
+      }
+      hipLaunchKernelGGL(ks, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks, d_fidx,
+                         d_far);
+      if (explore) {
+        HIPCHK(hipEventRecord(tb_, h.stream));
+        h.tune_pending.push_back({ta_, tb_, tkey, alt ? 1 : 0, alt ? 1 : 0, std::max(fl_schur, 1.0)});
+      }
     }
-    hipLaunchKernelGGL(ks, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, V, d_recs, d_nbrs, d_tasks, d_fidx,
-                       d_far);
-    if (explore) {
-      HIPCHK(hipEventRecord(tb_, h.stream));
-      h.tune_pending.push_back({ta_, tb_, tkey, alt ? 1 : 0, alt ? 1 : 0, std::max(fl_schur, 1.0)});
+    if (split) {
+      ProfScope ps(h, "k_schur_far", fl_far, 0, true);
+      auto kf = deep ? k_schur<true, true, false, 2> : k_schur<true, false, false, 2>;
+      hipLaunchKernelGGL(kf, dim3((unsigned)tasks.size()), dim3(NT), 0, h.side_stream, V, d_recs, d_nbrs, d_tasks,
+                         d_fidx, d_far);
     }
+    if (split && (rc = join_side(h, err))) return rc;
   }
   if ((rc = check_arena(h, l, "schur", c, err))) return rc;
   if (nchg) {
@@ -2375,6 +2393,7 @@ int factor(Handle& h, std::string& err) {
   if (const char* e = std::getenv("IFMM_F64_MFMA")) h.f64_mfma = std::atoi(e) != 0;
   tune_load(h);
   if (const char* e = std::getenv("IFMM_SOLVE_SPLIT")) h.solve_split = std::atoi(e) != 0;
+  if (const char* e = std::getenv("IFMM_SCHUR_SPLIT")) h.schur_split = std::atoi(e) != 0;
   // IFMM_SOLVE32=1 (mixed form): the solve reads FP32 copies of L and G.  It
   // halves the store but ran slower than the FP64 blocks (the conversions
   // sit in the column loop), so it is off by default

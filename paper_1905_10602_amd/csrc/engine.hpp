@@ -171,6 +171,10 @@ struct Handle {
   int64_t store32_left = 0;
   bool solve32 = false;  // mixed form, IFMM_SOLVE32=1: the solve reads FP32 L and G blocks
   bool solve_split = true;  // IFMM_SOLVE_SPLIT=0: no split backward tiles (one task per row tile)
+  // IFMM_SCHUR_SPLIT=1: the mixed form's near and far Schur products as two
+  // kernels on two streams (20.9 s against 21.1 s for the factorisation at
+  // N = 1M; off by default, the single kernel's timing stays a clean roofline)
+  bool schur_split = false;
   // growable buffers
   double* scratch = nullptr;
   int64_t scratch_bytes = 0;

@@ -800,8 +800,9 @@ __global__ void __launch_bounds__(NT) k_reduce_m2l_lds(LevelView V, int K, const
     const double* Tl = V.arena + V.T_off[l];
     for (int c0 = 0; c0 < rl; c0 += 64) {
       const int nc = min(64, rl - c0);
-      wg_gemm(K, nc, K, invL, U, K, false, Tl + (int64_t)c0 * K, K, false, 0.0, tl, K);
-      wg_gemm(ri, nc, K, 1.0, S, rci, false, tl, K, false, 0.0, V.il_blk[s] + (int64_t)c0 * V.ilcap[i], V.ilcap[i]);
+      wg_gemm<false>(K, nc, K, invL, U, K, false, Tl + (int64_t)c0 * K, K, false, 0.0, tl, K);  // C in LDS
+      wg_gemm<false>(ri, nc, K, 1.0, S, rci, false, tl, K, false, 0.0, V.il_blk[s] + (int64_t)c0 * V.ilcap[i],
+                     V.ilcap[i]);  // B in LDS
     }
   }
 }
@@ -1258,8 +1259,11 @@ __device__ inline void schur_copy(const LevelView& V, const ElimRec& R, const El
 // One task per workgroup: a 64 x 64 output tile of block (a, b), a block
 // (a, b), or a whole row block a (b = -2, its blocks one after the other).
 // Every product goes through one of two call sites (far in the mixed form:
-// FP32 tile; otherwise FP64), so each tile is inlined once.
-template <bool f32, bool deep, bool mf>
+// FP32 tile; otherwise FP64), so each tile is inlined once.  part: 0 every
+// product, 1 the near products and the copies only, 2 the far products only
+// (the mixed form runs 1 and 2 as two kernels, each with one tile's
+// registers, at the same time on two streams).
+template <bool f32, bool deep, bool mf, int part>
 __global__ void __launch_bounds__(NT) k_schur(LevelView V, const ElimRec* recs, const ElimNbr* nbrs,
                                               const SchurTask* tasks, const int32_t* far_idx, const FarPair* far) {
   const SchurTask T = tasks[blockIdx.x];
@@ -1270,12 +1274,13 @@ __global__ void __launch_bounds__(NT) k_schur(LevelView V, const ElimRec* recs, 
   for (int q = 0; q < nb; ++q) {
     const int b = T.b == -2 ? (q < R.nnb ? q : -1) : T.b;
     if (T.a >= R.nnb) {
-      schur_copy(V, R, nbrs, b);
+      if (part != 2) schur_copy(V, R, nbrs, b);
       continue;
     }
     const SchurProd P = schur_prod(V, R, nbrs, far_idx, far, T.a, b, tile >= 0 ? (tile & 0xffff) : 0,
                                    tile >= 0 ? (tile >> 16) : -1);
-    if (f32 && P.far)
+    if ((part == 1 && P.far) || (part == 2 && !P.far)) continue;
+    if (part == 2 || (part == 0 && f32 && P.far))
       schur_gemm<true, deep, false>(P.m, P.n, P.k, P.alpha, P.A, P.lda, P.B, P.ldb, P.beta, P.C, P.ldc);
     else
       schur_gemm<false, false, mf>(P.m, P.n, P.k, P.alpha, P.A, P.lda, P.B, P.ldb, P.beta, P.C, P.ldc);
@@ -1837,8 +1842,10 @@ __global__ void __launch_bounds__(NT) k_perm_out(double* x, int64_t ld, int k, c
 // 64), for the lane's row (A points at the lane's row; act: the row exists);
 // xs: the wave's LDS slice of 64 * SK doubles.  The whole wave calls it.
 template <int SK, typename T>
-__device__ inline void wave_gemv_chunk(const T* A, int64_t lda, bool act, const double* x, int64_t ldx, int cnt,
+__device__ inline void wave_gemv_chunk(const T* Ag, int64_t lda, bool act, const double* xg, int64_t ldx, int cnt,
                                        int kc, int lane, double sign, double* acc, double* xs) {
+  const auto A = gmem(Ag);
+  const auto x = gmem(xg);
   // the previous chunk's reads of xs are ordered before these writes (LDS
   // operations of one wave complete in order), and the fences keep the
   // compiler from moving LDS accesses across the staging
@@ -1848,25 +1855,19 @@ __device__ inline void wave_gemv_chunk(const T* A, int64_t lda, bool act, const 
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (cnt == 64) {
-    // 16 column loads in flight per wave before their products
-    for (int jb = 0; jb < 64; jb += 16) {
-      double av[16];
+  // 16 column loads in flight per wave before their products; a partial
+  // chunk (cnt < 64, e.g. the blocks of leaf-level neighbours) runs whole
+  // batches too, its missing columns loaded as zeros against zero vector
+  // entries (the products in between are exact no-ops)
+  for (int jb = 0; jb < cnt; jb += 16) {
+    double av[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) av[q] = act ? (double)A[(int64_t)(jb + q) * lda] : 0.0;
+    for (int q = 0; q < 16; ++q) av[q] = (act && jb + q < cnt) ? (double)A[(int64_t)(jb + q) * lda] : 0.0;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const double* xr = xs + (jb + q) * SK;
+    for (int q = 0; q < 16; ++q) {
+      const double* xr = xs + (jb + q) * SK;
 #pragma unroll
-        for (int c = 0; c < SK; ++c) acc[c] = fma(av[q], xr[c], acc[c]);
-      }
-    }
-  } else {
-    for (int jj = 0; jj < cnt; ++jj) {
-      const double a = act ? (double)A[(int64_t)jj * lda] : 0.0;
-      const double* xr = xs + jj * SK;
-#pragma unroll
-      for (int c = 0; c < SK; ++c) acc[c] = fma(a, xr[c], acc[c]);
+      for (int c = 0; c < SK; ++c) acc[c] = fma(av[q], xr[c], acc[c]);
     }
   }
 }

@@ -35,9 +35,17 @@ def test_roofline_picks_the_largest_single_kernel_and_prices_it():
     assert rf["frac"] == pytest.approx(ach / bench.FP32_MFMA_PEAK)
     assert rf["avg_launch_ms"] == pytest.approx(20.0)
     assert rf["algorithmic_bytes_per_launch"] == pytest.approx(1.0e10)
-    # the FP64 form prices the same kernel against the FP64 vector peak
+    # the FP64 form prices the same kernel against the FP64 matrix-core peak
     rf64 = bench.roofline_of(st, mixed=False)
-    assert rf64["bound"] == "alu" and rf64["frac"] == pytest.approx(ach / bench.FP64_VECTOR_PEAK)
+    assert rf64["bound"] == "mfma" and rf64["frac"] == pytest.approx(ach / bench.FP64_MFMA_PEAK)
+    # the mixed form's far products as their own kernel: FP32 matrix cores,
+    # and k_schur then holds FP64 products only
+    st2 = _stats({"k_schur": (2000.0, 100, 4.0e14, 1.0e12), "k_schur_far": (1000.0, 100, 3.0e14, 0.0)})
+    st2["aux"] = {"schur_far_flops": 3.0e14}
+    far = bench.price("k_schur_far", st2["kernels"]["k_schur_far"], True, bench._f32_flops(st2, "k_schur_far"))
+    assert far["peak"] == pytest.approx(bench.FP32_MFMA_PEAK / 1e12)
+    near = bench.price("k_schur", st2["kernels"]["k_schur"], True, bench._f32_flops(st2, "k_schur"))
+    assert near["peak"] == pytest.approx(bench.FP64_MFMA_PEAK / 1e12)
     # a memory-bound kernel is priced in bytes against HBM
     rfh = bench.roofline_of(_stats({"k_solve_fwd_upd": (10.0, 10, 0.0, 8.0e10)}), mixed=True)
     assert rfh["bound"] == "hbm" and rfh["frac"] == pytest.approx(8.0e9 / 1e-3 / bench.HBM_PEAK)

@@ -214,6 +214,22 @@ def test_fp64_matrix_core_schur_matches_oracle(monkeypatch):
     assert np.linalg.norm(xm - xf) <= 10 * eps * np.linalg.norm(xf)
 
 
+def test_schur_near_far_kernels_match_one_kernel(monkeypatch):
+    # IFMM_SCHUR_SPLIT=1: the mixed form's near (FP64) and far (FP32) Schur
+    # products as two kernels on two streams; every product is the same
+    # arithmetic as in the single kernel, so the solutions agree bit for bit
+    N, eps = 6000, 1e-6
+    print(f"case Schur near / far kernels ellipsoid N={N}", flush=True)
+    pts, dg = _case("ellipsoid", N, 13)
+    b = synth.uniform_rhs(N, 2, 81)
+    out = {}
+    for v in ("1", "0"):
+        monkeypatch.setenv("IFMM_SCHUR_SPLIT", v)
+        h = _gpu(pts, eps, 3, dg, 32, precision="mixed")
+        out[v] = h.solve(b)
+    assert np.array_equal(out["1"], out["0"])
+
+
 def test_split_backward_tiles_match_unsplit(monkeypatch):
     # colours with few backward row tiles split each tile's inner dimension
     # over several workgroups and add the partial sums in order; against one
