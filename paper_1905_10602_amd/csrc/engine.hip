@@ -378,7 +378,7 @@ static int check_arena(Handle& h, int l, const char* step, int c, std::string& e
 
 // ------------------------------------------------------------------ eigenvalues
 // Eigenvalues of the matrices of T (device table d_T, counts above eps2 *
-// lam_1 into d_cnt) on stream st: orders below TRD_BIG take the one-workgroup
+// lam_1 into d_cnt) on stream st: orders below h.trd_big take the one-workgroup
 // solver, larger ones the multi-workgroup reduction (their work vectors in a
 // buffer of this stream; the stream is synchronised before it grows).
 static int eig_values(Handle& h, const std::vector<EigTask>& T, const EigTask* d_T, double eps2, int32_t* d_cnt,
@@ -388,7 +388,7 @@ static int eig_values(Handle& h, const std::vector<EigTask>& T, const EigTask* d
   int nmax = 0;
   int64_t need = 0;
   for (size_t a = 0; a < T.size(); ++a)
-    if (!h.eig_jacobi && T[a].n >= TRD_BIG && T[a].n <= TRD_MAXN) {
+    if (!h.eig_jacobi && T[a].n >= h.trd_big && T[a].n <= TRD_MAXN) {
       big.push_back((int32_t)a);
       nmax = std::max(nmax, T[a].n);
       need += 3LL * T[a].n + (int64_t)T[a].n * ((T[a].n + 63) / 64) + 32;
@@ -396,7 +396,7 @@ static int eig_values(Handle& h, const std::vector<EigTask>& T, const EigTask* d
   if (h.eig_jacobi)
     hipLaunchKernelGGL(k_eig_jacobi, dim3((unsigned)T.size()), dim3(NT), 0, st, d_T, eps2, d_cnt);
   else
-    hipLaunchKernelGGL(k_eig_values, dim3((unsigned)T.size()), dim3(NT), 0, st, d_T, eps2, d_cnt, TRD_BIG);
+    hipLaunchKernelGGL(k_eig_values, dim3((unsigned)T.size()), dim3(NT), 0, st, d_T, eps2, d_cnt, h.trd_big);
   if (big.empty()) return 0;
   const bool side = st == h.side_stream && st != nullptr;
   double*& buf = side ? h.trd_buf_side : h.trd_buf;
@@ -2394,6 +2394,7 @@ int factor(Handle& h, std::string& err) {
   tune_load(h);
   if (const char* e = std::getenv("IFMM_SOLVE_SPLIT")) h.solve_split = std::atoi(e) != 0;
   if (const char* e = std::getenv("IFMM_SCHUR_SPLIT")) h.schur_split = std::atoi(e) != 0;
+  if (const char* e = std::getenv("IFMM_TRD_BIG")) h.trd_big = std::max(3, std::atoi(e));
   // IFMM_SOLVE32=1 (mixed form): the solve reads FP32 copies of L and G.  It
   // halves the store but ran slower than the FP64 blocks (the conversions
   // sit in the column loop), so it is off by default
@@ -3125,7 +3126,7 @@ extern "C" int ifmm_internal_syev(const double* A, int count, int n, int k, doub
   if (jacobi) {
     hipLaunchKernelGGL(k_eig_jacobi, dim3(count), dim3(NT), 0, nullptr, dT, 0.0, dC);
   } else {
-    // the factorisation's routing: one workgroup below TRD_BIG, the
+    // the factorisation's routing: one workgroup below the threshold, the
     // multi-workgroup reduction from there on
     Handle hh;
     std::string err;

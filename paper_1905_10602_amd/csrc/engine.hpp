@@ -37,6 +37,11 @@ struct ElimRec {
 };
 
 // One 64-row tile of a stored block in the solve.
+// Default order from which eigenvalues take the multi-workgroup Householder
+// reduction instead of one workgroup per matrix (N = 1M: factorisation 23.8 s
+// in FP64 and 21.3 s mixed with 160, against 25.1 and 21.5 s with 384).
+constexpr int TRD_BIG_DEFAULT = 160;
+
 struct STask {
   int32_t rec, r0;  // record (index in the level's elimination order), first row of the tile
   int32_t g0, g1;   // backward step: the 64-column chunks [g0, g1) of the inner dimension this task sums
@@ -175,6 +180,7 @@ struct Handle {
   // kernels on two streams (20.9 s against 21.1 s for the factorisation at
   // N = 1M; off by default, the single kernel's timing stays a clean roofline)
   bool schur_split = false;
+  int trd_big = TRD_BIG_DEFAULT;  // order from which eigenvalues take the multi-workgroup reduction (IFMM_TRD_BIG)
   // growable buffers
   double* scratch = nullptr;
   int64_t scratch_bytes = 0;

@@ -257,7 +257,6 @@ struct TrdTask {
   double* part;  // n x ceil(n / 64): partial sums of the next product, one column per column tile
   int32_t n, slot;  // order; index of the matrix in the caller's EigTask table and count array
 };
-constexpr int TRD_BIG = 384;  // matrices of at least this order take the multi-workgroup reduction
 
 // Householder vector of x (length m, in place in A's column): sets e / tau of
 // step `k`; returns the vector (normalised, 0 if x[1:] is already zero) in v.
