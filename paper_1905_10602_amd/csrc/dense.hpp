@@ -809,13 +809,16 @@ __device__ inline void wg_trd_eigenvalues(int n, const double* A, int lda, doubl
 
 // Eigenvectors of the k largest eigenvalues (after wg_syev_values): inverse
 // iteration on the tridiagonal (one thread per vector, pivoted LU of T - lam I),
-// two passes of modified Gram-Schmidt, then the Householder back-transform.
+// two passes of modified Gram-Schmidt, then the Householder back-transform
+// (left to the caller when bt is false).
 // X (n x k, ld ldx) receives the vectors; IW holds 5 n k doubles.
+// The substitutions walk each vector in chunks of EV_CH rows: a chunk's loads
+// are issued together before its serial recurrence, the results stored after.
+constexpr int EV_CH = 8;
 __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const double* W, const double* lam, int k,
-                                       double* X, int ldx, double* IW) {
+                                       double* X, int ldx, double* IW, bool bt = true) {
   __shared__ double s_c[NT];
-  const auto d = gmem(W);
-  const auto e = gmem(W + n);
+  __shared__ double s_d[TRD_MAXN], s_e[TRD_MAXN];
   const auto tau = gmem(W + 2 * n);
   const int tid = threadIdx.x;
   if (k <= 0) return;
@@ -824,6 +827,13 @@ __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const do
     __syncthreads();
     return;
   }
+  for (int i = tid; i < n; i += NT) {
+    s_d[i] = W[i];
+    s_e[i] = W[n + i];
+  }
+  __syncthreads();
+  const double* d = s_d;
+  const double* e = s_e;
   const double nrm = fmax(fabs(lam[0]), fabs(lam[n - 1])) + 1e-300;
   const double tiny = 2.2e-16 * nrm;
   for (int j = tid; j < k; j += NT) {
@@ -834,6 +844,8 @@ __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const do
     const auto ll = gmem(IW + 3 * (int64_t)n * k);
     const auto pv = gmem(IW + 4 * (int64_t)n * k);
     const double mu = lam[j];
+    // pivots below tiny in magnitude are stored as +-tiny
+    auto clamp = [&](double u) { return fabs(u) < tiny ? ((u < 0.0) ? -tiny : tiny) : u; };
     double cd = d[0] - mu, cs = e[0];
     for (int i = 0; i + 1 < n; ++i) {
       const double ns = e[i], nd = d[i + 1] - mu, nsp = (i + 2 < n) ? e[i + 1] : 0.0;
@@ -841,23 +853,19 @@ __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const do
       if (fabs(cd) >= fabs(ns)) {
         if (cd == 0.0) cd = tiny;
         const double mlt = ns / cd;
-        u0[o] = cd; u1[o] = cs; u2[o] = 0.0; ll[o] = mlt; pv[o] = 0.0;
+        u0[o] = clamp(cd); u1[o] = cs; u2[o] = 0.0; ll[o] = mlt; pv[o] = 0.0;
         cd = nd - mlt * cs;
         cs = nsp;
       } else {
         const double mlt = cd / ns;
-        u0[o] = ns; u1[o] = nd; u2[o] = nsp; ll[o] = mlt; pv[o] = 1.0;
+        u0[o] = clamp(ns); u1[o] = nd; u2[o] = nsp; ll[o] = mlt; pv[o] = 1.0;
         cd = cs - mlt * nd;
         cs = -mlt * nsp;
       }
     }
     {
       const int64_t o = (int64_t)(n - 1) * k + j;  // last row: only the diagonal is non-zero
-      u0[o] = cd; u1[o] = 0.0; u2[o] = 0.0; ll[o] = 0.0; pv[o] = 0.0;
-    }
-    for (int i = 0; i < n; ++i) {
-      auto& u = u0[(int64_t)i * k + j];
-      if (fabs(u) < tiny) u = (u < 0.0) ? -tiny : tiny;
+      u0[o] = clamp(cd); u1[o] = 0.0; u2[o] = 0.0; ll[o] = 0.0; pv[o] = 0.0;
     }
     const auto x = gmem(X + (int64_t)j * ldx);
     // distinct pseudo-random start per vector: within a (near-)degenerate
@@ -873,23 +881,57 @@ __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const do
     for (int it = 0; it < 3; ++it) {
       // apply L (with the row interchanges), carrying b_i in a register
       double bi = x[0];
-      for (int i = 0; i + 1 < n; ++i) {
-        const int64_t o = (int64_t)i * k + j;
-        double bn = x[i + 1];
-        if (pv[o] != 0.0) { const double t = bi; bi = bn; bn = t; }
-        x[i] = bi;
-        bi = bn - ll[o] * bi;
+      for (int i0 = 0; i0 + 1 < n; i0 += EV_CH) {
+        const int c = min(EV_CH, n - 1 - i0);
+        double xb[EV_CH], pb[EV_CH], lb[EV_CH];
+#pragma unroll
+        for (int q = 0; q < EV_CH; ++q)
+          if (q < c) {
+            const int64_t o = (int64_t)(i0 + q) * k + j;
+            xb[q] = x[i0 + 1 + q];
+            pb[q] = pv[o];
+            lb[q] = ll[o];
+          }
+#pragma unroll
+        for (int q = 0; q < EV_CH; ++q)
+          if (q < c) {
+            double bn = xb[q];
+            if (pb[q] != 0.0) { const double t = bi; bi = bn; bn = t; }
+            xb[q] = bi;
+            bi = bn - lb[q] * bi;
+          }
+#pragma unroll
+        for (int q = 0; q < EV_CH; ++q)
+          if (q < c) x[i0 + q] = xb[q];
       }
       x[n - 1] = bi;
       // back substitution with U (three diagonals)
       double x1 = 0.0, x2 = 0.0, ss = 0.0;
-      for (int i = n - 1; i >= 0; --i) {
-        const int64_t o = (int64_t)i * k + j;
-        const double xi = (x[i] - u1[o] * x1 - u2[o] * x2) / u0[o];
-        x[i] = xi;
-        x2 = x1;
-        x1 = xi;
-        ss += xi * xi;
+      for (int i1 = n; i1 > 0; i1 -= EV_CH) {
+        const int c = min(EV_CH, i1);
+        double xb[EV_CH], a0[EV_CH], a1[EV_CH], a2[EV_CH];
+#pragma unroll
+        for (int q = 0; q < EV_CH; ++q)
+          if (q < c) {
+            const int i = i1 - 1 - q;
+            const int64_t o = (int64_t)i * k + j;
+            xb[q] = x[i];
+            a0[q] = u0[o];
+            a1[q] = u1[o];
+            a2[q] = u2[o];
+          }
+#pragma unroll
+        for (int q = 0; q < EV_CH; ++q)
+          if (q < c) {
+            const double xi = (xb[q] - a1[q] * x1 - a2[q] * x2) / a0[q];
+            xb[q] = xi;
+            x2 = x1;
+            x1 = xi;
+            ss += xi * xi;
+          }
+#pragma unroll
+        for (int q = 0; q < EV_CH; ++q)
+          if (q < c) x[i1 - 1 - q] = xb[q];
       }
       const double sc = 1.0 / sqrt(ss);
       for (int i = 0; i < n; ++i) x[i] *= sc;
@@ -940,6 +982,7 @@ __device__ inline void wg_syev_vectors(int n, const double* A, int lda, const do
       __syncthreads();
     }
   }
+  if (!bt) return;
   // back-transform X <- H_0 H_1 ... H_{n-3} X, H_q = I - tq vq vq^T (tq = 2 or 0):
   // 32 reflectors at a time in compact WY form H_b0 ... H_b1-1 = I - V T V^T
   // (T upper triangular), applied as W = V^T X, W = T W, X -= V W.

@@ -443,9 +443,31 @@ static int eig_values(Handle& h, const std::vector<EigTask>& T, const EigTask* d
     hipLaunchKernelGGL(k_trd_step, dim3(nb), dim3(NT), 0, st, d_trd, k);
     tiles(k);
   }
-  hipLaunchKernelGGL(k_trd_values, dim3(nb), dim3(NT), 0, st, d_trd, d_T, eps2, d_cnt);
+  hipLaunchKernelGGL(k_trd_bisect, dim3((unsigned)((nmax + NT - 1) / NT), nb), dim3(NT), 0, st, d_trd, d_T);
+  hipLaunchKernelGGL(k_trd_count, dim3(nb), dim3(NT), 0, st, d_trd, d_T, eps2, d_cnt);
   HIPCHK(hipGetLastError());
   return 0;
+}
+
+// Eigenvectors of the tasks T (device table d_T, the k of each already set)
+// on stream st: one workgroup per task, except the back-transform of orders
+// from h.trd_big on, which runs over blocks of 64 columns (k_ev_mask,
+// k_ev_apply).
+static void eig_vectors(Handle& h, const std::vector<EigTask>& T, const EigTask* d_T, hipStream_t st) {
+  if (T.empty()) return;
+  const int big = h.trd_big;
+  int nmax = 0, kmax = 0;
+  for (const EigTask& e : T)
+    if (big > 0 && e.n >= big && e.n >= 34 && e.k > 0) {
+      nmax = std::max(nmax, e.n);
+      kmax = std::max(kmax, e.k);
+    }
+  const unsigned nt = (unsigned)T.size();
+  hipLaunchKernelGGL(k_eig_vectors, dim3(nt), dim3(NT), 0, st, d_T, big);
+  if (nmax) {
+    hipLaunchKernelGGL(k_ev_mask, dim3((unsigned)((nmax + 63) / 64), nt), dim3(NT), 0, st, d_T, big);
+    hipLaunchKernelGGL(k_ev_apply, dim3((unsigned)((kmax + 63) / 64), nt), dim3(NT), 0, st, d_T, big);
+  }
 }
 
 // ------------------------------------------------------------------ level set-up
@@ -693,7 +715,7 @@ static int reduce_level(Handle& h, int l, std::string& err) {
   V = view_of(L);
   const double side = 2.0 * h.tree.H / (double)(1LL << l);
   if (nn > 0) {
-    if (!h.eig_jacobi) hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)tasks.size()), dim3(NT), 0, h.stream, d_tasks);
+    if (!h.eig_jacobi) eig_vectors(h, tasks, d_tasks, h.stream);
     hipLaunchKernelGGL(k_reduce_basis, dim3(nn), dim3(NT), 0, h.stream, V, K, work, d_woff, h.d_m2m8, l > 2 ? 1 : 0,
                        sym ? 1 : 0);
     HIPCHK(hipGetLastError());
@@ -1889,7 +1911,7 @@ static int colour_ranks_vectors(Handle& h, ColourWork& W, HostLap& lap, std::str
     if (vside && (rc = fork_side(h, err))) return rc;
     if (!h.eig_jacobi && nf2) {
       ProfScope ps(h, "k_eig_vectors", fl_evec, 0, vside);
-      hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)nf2), dim3(NT), 0, vside ? h.side_stream : h.stream, d_vf);
+      eig_vectors(h, fullT, d_vf, vside ? h.side_stream : h.stream);
     }
     if (ns2) {
       double fl = 0;
@@ -1901,7 +1923,7 @@ static int colour_ranks_vectors(Handle& h, ColourWork& W, HostLap& lap, std::str
         nmx = std::max(nmx, C.n);
       }
       ProfScope ps(h, "group:sketch_vectors", fl, 0);
-      hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)ns2), dim3(NT), 0, h.stream, d_vs);
+      eig_vectors(h, skE, d_vs, h.stream);
       hipLaunchKernelGGL(k_gemm_batch, dim3((unsigned)((nmx + 63) / 64), (unsigned)((rmax + 63) / 64), (unsigned)ns2),
                          dim3(NT), 0, h.stream, d_vg);
     }
@@ -3131,7 +3153,7 @@ extern "C" int ifmm_internal_syev(const double* A, int count, int n, int k, doub
     Handle hh;
     std::string err;
     rc = eig_values(hh, t, dT, 0.0, dC, nullptr, err);
-    if (rc == 0) hipLaunchKernelGGL(k_eig_vectors, dim3(count), dim3(NT), 0, nullptr, dT);
+    if (rc == 0) eig_vectors(hh, t, dT, nullptr);
     if (hipDeviceSynchronize() != hipSuccess) rc = -3;
     for (auto& a : hh.allocs) (void)hipFree(a.first);
   }

@@ -235,10 +235,64 @@ __global__ void __launch_bounds__(NT) k_eig_values(const EigTask* tasks, double 
   }
 }
 
-__global__ void __launch_bounds__(NT) k_eig_vectors(const EigTask* tasks) {
+// Whether task (n, k) leaves its back-transform to k_ev_mask / k_ev_apply
+// (big > 0: orders from big on, with at least one full block of reflectors).
+__device__ inline bool ev_split(int n, int k, int big) { return big > 0 && n >= big && n >= 34 && k > 0; }
+
+__global__ void __launch_bounds__(NT) k_eig_vectors(const EigTask* tasks, int big) {
   const EigTask t = tasks[blockIdx.x];
   if (t.n == 0 || t.k == 0) return;
-  wg_syev_vectors(t.n, t.A, t.n, t.W, t.lam, t.k, t.V, t.n, t.IW);
+  wg_syev_vectors(t.n, t.A, t.n, t.W, t.lam, t.k, t.V, t.n, t.IW, !ev_split(t.n, t.k, big));
+}
+
+// Blocked back-transform of the large tasks, many workgroups per matrix.
+// The reflectors v_q (unit vectors, rows q+1.. of column q of A) are applied
+// 32 at a time in compact WY form, H_b0 ... H_b1-1 = I - V T V^T, where
+// T^-1 = diag(1/2) + (strict upper part of V^T V) for H_q = I - 2 v_q v_q^T
+// (Joffrain, Low, Quintana-Orti, van de Geijn and van Zee, "Accumulating
+// Householder transformations, revisited", 2006).  k_ev_mask first zeroes
+// what V must read as zero: column q on and above the diagonal, and the whole
+// column of a skipped reflector (tau_q = 0).  grid (ceil(n_max / 64), task).
+__global__ void __launch_bounds__(NT) k_ev_mask(const EigTask* tasks, int big) {
+  const EigTask t = tasks[blockIdx.y];
+  const int n = t.n;
+  if (!ev_split(n, t.k, big)) return;
+  const int q0 = blockIdx.x * 64, q1 = min(n - 2, q0 + 64);
+  const double* tau = t.W + 2 * n;
+  for (int q = q0; q < q1; ++q) {
+    const int rend = tau[q] != 0.0 ? q + 1 : n;
+    for (int r = threadIdx.x; r < rend; r += NT) t.A[r + (int64_t)q * n] = 0.0;
+  }
+}
+
+// X <- H_0 ... H_{n-3} X on a block of 64 columns of X (grid (ceil(k_max /
+// 64), task)), reflector blocks from the last to the first: with the rows
+// b0+1.. of the block's columns, G = V^T V and B = V^T X, then T^-1 W = B by
+// back substitution (W = T B) and X -= V W.
+__global__ void __launch_bounds__(NT) k_ev_apply(const EigTask* tasks, int big) {
+  __shared__ double sG[32 * 32], sB[32 * 64];
+  const EigTask t = tasks[blockIdx.y];
+  const int n = t.n, k = t.k;
+  if (!ev_split(n, k, big)) return;
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= k) return;
+  const int kc = min(64, k - c0);
+  double* X = t.V + (int64_t)c0 * n;
+  for (int b1 = n - 2; b1 > 0; b1 -= 32) {
+    const int b0 = max(0, b1 - 32), nb = b1 - b0, mb = n - b0 - 1;
+    const double* Vs = t.A + (b0 + 1) + (int64_t)b0 * n;
+    double* Xs = X + (b0 + 1);
+    wg_gemm<false>(nb, nb, mb, 1.0, Vs, n, true, Vs, n, false, 0.0, sG, 32);
+    wg_gemm<false>(nb, kc, mb, 1.0, Vs, n, true, Xs, n, false, 0.0, sB, 32);
+    for (int j = threadIdx.x; j < kc; j += NT)
+      for (int q = nb - 1; q >= 0; --q) {
+        double acc = sB[q + 32 * j];
+        for (int p = q + 1; p < nb; ++p) acc -= sG[q + 32 * p] * sB[p + 32 * j];
+        sB[q + 32 * j] = 2.0 * acc;
+      }
+    __syncthreads();
+    wg_gemm<false>(mb, kc, nb, -1.0, Vs, n, false, sB, 32, false, 1.0, Xs, n);
+  }
 }
 
 // ---- Householder tridiagonalisation spread over many workgroups (large
@@ -305,9 +359,11 @@ __global__ void __launch_bounds__(NT) k_trd_start(const TrdTask* tasks) {
 // ti (slot tj of part) and S_tile^T vn_I to the rows of block tj (slot ti),
 // so every (row, slot) is written by exactly one tile; a diagonal tile adds
 // both into slot ti.  grid (lower tiles of the largest S, task).
+// Thread (tx, ty) = (tid % 16, tid / 16) owns rows I + tx + 16a and columns
+// J + ty + 16b (a, b < 4): its 16 loads are issued together (16 lanes read
+// 128 contiguous bytes of a column), and the row and column sums meet in LDS.
 __global__ void __launch_bounds__(NT) k_trd_tiles(const TrdTask* tasks, int k) {
-  __shared__ double red[NT / 64][64];
-  __shared__ double colsum[64];
+  __shared__ double rowp[16][64], colp[16][64];
   const TrdTask t = tasks[blockIdx.y];
   const int n = t.n, m = n - k - 2;
   if (n < 3 || k > n - 3 || m <= 0) return;
@@ -320,39 +376,62 @@ __global__ void __launch_bounds__(NT) k_trd_tiles(const TrdTask* tasks, int k) {
   const int tj = tile - ti * (ti + 1) / 2;
   const bool diag = ti == tj;
   const int I = 64 * ti, J = 64 * tj;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double* v = t.vec;
-  const double* w = t.vec + n;
-  const double* vn = t.vec + 2 * n;
-  double* S = t.A + (k + 2) + (int64_t)(k + 2) * n;
-  const int i = I + lane;
-  const bool row_ok = i < m;
-  const double vi = row_ok ? v[i] : 0.0, wi = row_ok ? w[i] : 0.0, vni = row_ok ? vn[i] : 0.0;
-  double acc = 0.0;
-  for (int jj = wave; jj < 64; jj += NT / 64) {
-    const int j = J + jj;
-    if (j >= m) break;  // uniform over the wave
-    double tr = 0.0;    // this lane's term of (S^T vn_I)[j]
-    if (row_ok && (!diag || i >= j)) {
-      double* c = S + i + (int64_t)j * n;
-      const double sv = *c - 2.0 * (vi * w[j] + wi * v[j]);
-      *c = sv;
-      acc += sv * vn[j];
-      if (!diag || i > j) tr = sv * vni;
-    }
-    for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
-    if (lane == 0) colsum[jj] = tr;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const auto v = gmem(t.vec);
+  const auto w = gmem(t.vec + n);
+  const auto vn = gmem(t.vec + 2 * n);
+  const auto S = gmem(t.A + (k + 2) + (int64_t)(k + 2) * n);
+  double vr[4], wr[4], vnr[4], vc[4], wc[4], vnc[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = I + tx + 16 * a, j = J + ty + 16 * a;
+    vr[a] = i < m ? v[i] : 0.0;
+    wr[a] = i < m ? w[i] : 0.0;
+    vnr[a] = i < m ? vn[i] : 0.0;
+    vc[a] = j < m ? v[j] : 0.0;
+    wc[a] = j < m ? w[j] : 0.0;
+    vnc[a] = j < m ? vn[j] : 0.0;
   }
-  red[wave][lane] = acc;
+  double x[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = I + tx + 16 * a, j = J + ty + 16 * b;
+      x[a][b] = (i < m && j < m && (!diag || i >= j)) ? S[i + (int64_t)j * n] : 0.0;
+    }
+  double racc[4] = {0.0, 0.0, 0.0, 0.0}, cacc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = I + tx + 16 * a, j = J + ty + 16 * b;
+      if (i < m && j < m && (!diag || i >= j)) {
+        const double sv = x[a][b] - 2.0 * (vr[a] * wc[b] + wr[a] * vc[b]);
+        S[i + (int64_t)j * n] = sv;
+        racc[a] += sv * vnc[b];
+        if (!diag || i > j) cacc[b] += sv * vnr[a];
+      }
+    }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    rowp[ty][tx + 16 * a] = racc[a];
+    colp[tx][ty + 16 * a] = cacc[a];
+  }
   __syncthreads();
-  if (wave == 0) {
-    double a = 0.0;
-    for (int q = 0; q < NT / 64; ++q) a += red[q][lane];
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    double r = 0.0, c = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      r += rowp[q][l];
+      c += colp[q][l];
+    }
     if (diag) {
-      if (row_ok) t.part[(int64_t)ti * n + i] = a + colsum[lane];
+      if (I + l < m) t.part[(int64_t)ti * n + I + l] = r + c;
     } else {
-      if (row_ok) t.part[(int64_t)tj * n + i] = a;
-      if (J + lane < m) t.part[(int64_t)ti * n + J + lane] = colsum[lane];
+      if (I + l < m) t.part[(int64_t)tj * n + I + l] = r;
+      if (J + l < m) t.part[(int64_t)ti * n + J + l] = c;
     }
   }
 }
@@ -374,6 +453,7 @@ __global__ void __launch_bounds__(NT) k_trd_step(const TrdTask* tasks, int k) {
   double* col = t.A + (k + 1) + (int64_t)k * n;  // reflector v_k, stored by the previous step
   for (int i = tid; i < m; i += NT) {
     double a = 0.0;
+#pragma unroll 8
     for (int c = 0; c < nb; ++c) a += t.part[(int64_t)c * n + i];
     sp[i] = a;
     sv[i] = t.W[2 * n + k] != 0.0 ? col[i] : 0.0;  // tau_k = 0: no reflector at this step
@@ -401,27 +481,82 @@ __global__ void __launch_bounds__(NT) k_trd_step(const TrdTask* tasks, int k) {
   }
 }
 
-// After the last step: d, the last off-diagonal and the eigenvalues.
-__global__ void __launch_bounds__(NT) k_trd_values(const TrdTask* tasks, const EigTask* et, double eps2, int32_t* cnt) {
+// After the last step: the eigenvalues of the tridiagonal matrix by bisection
+// on Sturm counts, spread over workgroups of NT eigenvalues each (grid
+// (ceil(n_max / NT), task)).  Every workgroup stages d and e in LDS (the
+// counts read them n times per bisection step) and forms the Gershgorin
+// interval itself; workgroup 0 also stores d and the last off-diagonal in W.
+// The values are those of the one-workgroup bisection, bit for bit (same
+// interval, same steps; min and max reductions are exact).
+__global__ void __launch_bounds__(NT) k_trd_bisect(const TrdTask* tasks, const EigTask* et) {
+  __shared__ double sd[TRD_MAXN], se[TRD_MAXN];
+  __shared__ double s_lo[NT / 64], s_hi[NT / 64];
+  const TrdTask t = tasks[blockIdx.y];
+  const int n = t.n, j0 = blockIdx.x * NT, tid = threadIdx.x;
+  if (n < 3 || j0 >= n) return;
+  double* lam = et[t.slot].lam;
+  double* d = t.W;
+  double* e = t.W + n;
+  const double e_last = t.A[(n - 1) + (int64_t)(n - 2) * n];
+  for (int i = tid; i < n; i += NT) {
+    const double di = t.A[i + (int64_t)i * n];
+    sd[i] = di;
+    if (blockIdx.x == 0) d[i] = di;
+    if (i + 1 < n) se[i] = i == n - 2 ? e_last : e[i];
+  }
+  if (blockIdx.x == 0 && tid == 0) e[n - 2] = e_last;
+  __syncthreads();
+  double lo = 0.0, hi = 0.0;
+  bool any = false;
+  for (int i = tid; i < n; i += NT) {
+    const double rad = (i > 0 ? fabs(se[i - 1]) : 0.0) + (i + 1 < n ? fabs(se[i]) : 0.0);
+    const double a = sd[i] - rad, b = sd[i] + rad;
+    if (!any || a < lo) lo = a;
+    if (!any || b > hi) hi = b;
+    any = true;
+  }
+  if (!any) { lo = INFINITY; hi = -INFINITY; }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+  }
+  if ((tid & 63) == 0) { s_lo[tid >> 6] = lo; s_hi[tid >> 6] = hi; }
+  __syncthreads();
+  lo = s_lo[0];
+  hi = s_hi[0];
+  for (int w = 1; w < NT / 64; ++w) { lo = fmin(lo, s_lo[w]); hi = fmax(hi, s_hi[w]); }
+  const double nrm = fmax(fabs(lo), fabs(hi));
+  const double tiny = 2.2e-16 * nrm + 1e-300;
+  const int j = j0 + tid;
+  if (j < n) {
+    const int target = n - 1 - j;  // the j-th largest has n-1-j eigenvalues below it
+    double a = lo, b = hi;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (b - a <= 4.4e-16 * nrm || mid <= a || mid >= b) break;
+      if (sturm_count(n, sd, se, mid, tiny) > target) b = mid;
+      else a = mid;
+    }
+    lam[j] = 0.5 * (a + b);
+  }
+}
+
+// Count of eigenvalues above eps2 * lam_0 per task (one workgroup each); the
+// tiny orders the reduction leaves untouched (n < 3) are solved here whole.
+__global__ void __launch_bounds__(NT) k_trd_count(const TrdTask* tasks, const EigTask* et, double eps2, int32_t* cnt) {
   const TrdTask t = tasks[blockIdx.x];
   const EigTask e = et[t.slot];
   if (t.n == 0) {
     if (threadIdx.x == 0) cnt[t.slot] = 0;
     return;
   }
-  if (t.n < 3) {  // nothing reduced: the one-workgroup solver on the tiny matrix
-    wg_syev_values(t.n, t.A, t.n, t.W, e.lam);
-  } else {
-    wg_trd_eigenvalues(t.n, t.A, t.n, t.W, e.lam);
-  }
-  if (threadIdx.x == 0) {
-    const double l0 = e.lam[0];
-    int c = 0;
-    if (l0 > 0.0)
-      for (int q = 0; q < t.n; ++q)
-        if (e.lam[q] > eps2 * l0) ++c;
-    cnt[t.slot] = c;
-  }
+  if (t.n < 3) wg_syev_values(t.n, t.A, t.n, t.W, e.lam);
+  const double l0 = e.lam[0];
+  double c = 0.0;
+  if (l0 > 0.0)
+    for (int q = threadIdx.x; q < t.n; q += NT) c += e.lam[q] > eps2 * l0 ? 1.0 : 0.0;
+  c = wg_sum(c);
+  if (threadIdx.x == 0) cnt[t.slot] = (int32_t)c;
 }
 
 // ------------------------------------------------------------------ batched tiled GEMM
