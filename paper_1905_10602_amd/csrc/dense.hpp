@@ -196,7 +196,9 @@ __device__ inline void wg_gemm_f32_lite(int m, int n, int k, double alpha, const
       f32x16 acc;
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-      float ra[4], rb[4];
+      // prefetched as FP64 and converted when stashed: a conversion next to
+      // its load would wait for each load in turn
+      double ra[4], rb[4];
       auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -204,11 +206,11 @@ __device__ inline void wg_gemm_f32_lite(int m, int n, int k, double alpha, const
           int ii, kk;
           if (!tA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
           const int gi = i0 + ii, gk = k0 + kk;
-          ra[q] = (gi < m && gk < k) ? (float)(tA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda]) : 0.0f;
+          ra[q] = (gi < m && gk < k) ? (tA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda]) : 0.0;
           int kb, jb;
           if (!tB) { kb = e & 15; jb = e >> 4; } else { jb = e & 63; kb = e >> 6; }
           const int gk2 = k0 + kb, gj = j0 + jb;
-          rb[q] = (gk2 < k && gj < n) ? (float)(tB ? B[gj + (int64_t)gk2 * ldb] : B[gk2 + (int64_t)gj * ldb]) : 0.0f;
+          rb[q] = (gk2 < k && gj < n) ? (tB ? B[gj + (int64_t)gk2 * ldb] : B[gk2 + (int64_t)gj * ldb]) : 0.0;
         }
       };
       auto stash = [&]() {
@@ -217,10 +219,10 @@ __device__ inline void wg_gemm_f32_lite(int m, int n, int k, double alpha, const
           const int e = tid + q * NT;
           int ii, kk;
           if (!tA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
-          fA[kk][ii] = ra[q];
+          fA[kk][ii] = (float)ra[q];
           int kb, jb;
           if (!tB) { kb = e & 15; jb = e >> 4; } else { jb = e & 63; kb = e >> 6; }
-          fB[kb][jb] = rb[q];
+          fB[kb][jb] = (float)rb[q];
         }
       };
       if (k > 0) {

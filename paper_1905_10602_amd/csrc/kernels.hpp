@@ -1628,26 +1628,39 @@ __device__ inline void wave_sync_lds() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-// acc += A (m x k, global FP64) B (k x n, global FP64), one wave, m, n, k <= 32
+// acc += A (m x k, global FP64) B (k x n, global FP64), one wave, m, n, k <= 32.
+// All 16 k-steps of a lane are loaded before the first product (as FP64: a
+// conversion next to its load would wait for each load in turn).
 __device__ inline void wave_mm_gg(f32x16& acc, int m, int n, int k, const double* A, int lda, const double* B,
                                   int ldb) {
   const int lane = threadIdx.x & 63, i = lane & 31, kh = lane >> 5;
-  for (int k0 = 0; k0 < k; k0 += 2) {
-    const int kk = k0 + kh;
-    const float a = (i < m && kk < k) ? (float)A[i + (int64_t)kk * lda] : 0.0f;
-    const float b = (i < n && kk < k) ? (float)B[kk + (int64_t)i * ldb] : 0.0f;
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+  double ra[16], rb[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int kk = 2 * s + kh;
+    ra[s] = (i < m && kk < k) ? A[i + (int64_t)kk * lda] : 0.0;
+    rb[s] = (i < n && kk < k) ? B[kk + (int64_t)i * ldb] : 0.0;
   }
+#pragma unroll
+  for (int s = 0; s < 16; ++s)
+    if (2 * s < k) acc = __builtin_amdgcn_mfma_f32_32x32x2f32((float)ra[s], (float)rb[s], acc, 0, 0, 0);
 }
 // acc += A (m x k, global FP64) Bl (k x n, wave LDS tile)
 __device__ inline void wave_mm_gl(f32x16& acc, int m, int n, int k, const double* A, int lda, const float (*Bl)[33]) {
   const int lane = threadIdx.x & 63, i = lane & 31, kh = lane >> 5;
-  for (int k0 = 0; k0 < k; k0 += 2) {
-    const int kk = k0 + kh;
-    const float a = (i < m && kk < k) ? (float)A[i + (int64_t)kk * lda] : 0.0f;
-    const float b = (kk < k) ? Bl[kk][i] : 0.0f;
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+  double ra[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int kk = 2 * s + kh;
+    ra[s] = (i < m && kk < k) ? A[i + (int64_t)kk * lda] : 0.0;
   }
+#pragma unroll
+  for (int s = 0; s < 16; ++s)
+    if (2 * s < k) {
+      const int kk = 2 * s + kh;
+      const float b = (kk < k) ? Bl[kk][i] : 0.0f;
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32((float)ra[s], b, acc, 0, 0, 0);
+    }
 }
 __device__ inline void wave_acc_to_lds(const f32x16& acc, float (*Tl)[33]) {
   const int lane = threadIdx.x & 63;
