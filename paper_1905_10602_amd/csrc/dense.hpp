@@ -370,8 +370,8 @@ __device__ inline void wg_gemm_f32_deep(int m, int n, int k, double alpha, const
   else wg_gemm_f32_kc32(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc, reinterpret_cast<float*>(lbuf));
 }
 
-// FP64 matrix-core product C = alpha A B + beta C (A m x k, B k x n, column
-// major, no transposes), v_mfma_f64_16x16x4f64, 64 x 64 output tiles per
+// FP64 matrix-core product C = alpha op(A) B + beta C (op(A) m x k, A^T when
+// tA; B k x n; column major), v_mfma_f64_16x16x4f64, 64 x 64 output tiles per
 // workgroup with k-chunks of 16 staged through LDS (the next chunk prefetched
 // into registers), each wave a 32 x 32 quarter as 2 x 2 blocks of 16 x 16.
 // The product is formed transposed, C^T = B^T A^T, so that the accumulator
@@ -386,13 +386,13 @@ __device__ inline void wg_gemm_f32_deep(int m, int n, int k, double alpha, const
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <bool G = true>
 __device__ inline void wg_gemm_f64m(int m, int n, int k, double alpha, const double* A_, int lda, const double* B_,
-                                    int ldb, double beta, double* C_, int ldc) {
+                                    int ldb, double beta, double* C_, int ldc, bool tA = false) {
   const auto A = gsel<G>(A_);
   const auto B = gsel<G>(B_);
   const auto C = gsel<G>(C_);
   __shared__ double lds64[2 * 16 * 68];  // >= 2 x 32 x 33 for the small product
   if (m <= 32 && n <= 32 && k <= 32) {   // too small for the tiles: the one-pass product
-    wg_gemm_small<G>(m, n, k, alpha, A_, lda, false, B_, ldb, false, beta, C_, ldc, lds64);
+    wg_gemm_small<G>(m, n, k, alpha, A_, lda, tA, B_, ldb, false, beta, C_, ldc, lds64);
     return;
   }
   double (*fA)[68] = reinterpret_cast<double (*)[68]>(lds64);
@@ -409,15 +409,16 @@ __device__ inline void wg_gemm_f64m(int m, int n, int k, double alpha, const dou
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
       double ra[4], rb[4];
-      // chunk k0..k0+15: A rows i0 + (e & 63), column k0 + (e >> 6); B rows
-      // k0 + (e & 15), column j0 + (e >> 4); e = tid + 256 q
+      // chunk k0..k0+15: A rows i0 + (e & 63), column k0 + (e >> 6) (A
+      // transposed: k0 + (e & 15) of column i0 + (e >> 4)); B rows k0 + (e & 15),
+      // column j0 + (e >> 4); e = tid + 256 q
       auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int e = tid + q * NT;
-          const int ii = e & 63, kk = e >> 6;
+          const int ii = tA ? e >> 4 : e & 63, kk = tA ? e & 15 : e >> 6;
           const int gi = i0 + ii, gk = k0 + kk;
-          ra[q] = (gi < m && gk < k) ? A[gi + (int64_t)gk * lda] : 0.0;
+          ra[q] = (gi < m && gk < k) ? (tA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda]) : 0.0;
           const int kb = e & 15, jb = e >> 4;
           const int gk2 = k0 + kb, gj = j0 + jb;
           rb[q] = (gk2 < k && gj < n) ? B[gk2 + (int64_t)gj * ldb] : 0.0;
@@ -427,7 +428,8 @@ __device__ inline void wg_gemm_f64m(int m, int n, int k, double alpha, const dou
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int e = tid + q * NT;
-          fA[e >> 6][e & 63] = ra[q];
+          if (tA) fA[e & 15][e >> 4] = ra[q];
+          else fA[e >> 6][e & 63] = ra[q];
           fB[e & 15][e >> 4] = rb[q];
         }
       };

@@ -449,6 +449,17 @@ static int eig_values(Handle& h, const std::vector<EigTask>& T, const EigTask* d
   return 0;
 }
 
+// Batched GEMM over `count` tasks (host copy `host`, device table d_tasks):
+// the FP64 matrix-core tile when every task leaves B untransposed, else (or
+// with the matrix cores switched off) the FMA tile.
+static void gemm_batch(Handle& h, dim3 grid, const GemmTask* host, size_t count, const GemmTask* d_tasks,
+                       hipStream_t st) {
+  bool mf = h.f64_mfma;
+  for (size_t a = 0; mf && a < count; ++a) mf = host[a].tB == 0;
+  if (mf) hipLaunchKernelGGL(k_gemm_batch<true>, grid, dim3(NT), 0, st, d_tasks);
+  else hipLaunchKernelGGL(k_gemm_batch<false>, grid, dim3(NT), 0, st, d_tasks);
+}
+
 // Eigenvectors of the tasks T (device table d_T, the k of each already set)
 // on stream st: one workgroup per task, except the back-transform of orders
 // from h.trd_big on, which runs over blocks of 64 columns (k_ev_mask,
@@ -884,9 +895,10 @@ static int sk_orthonormalise(Handle& h, const std::vector<SkTask>& T, const SkTa
     if (b > 0) {
       const unsigned tj = (unsigned)((b * 64 + 63) / 64), tn = (unsigned)((nmax + 63) / 64);
       for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_gemm_batch, dim3(tj, 1, (unsigned)nt), dim3(NT), 0, h.stream, d_g + ((size_t)b * 2) * nt);
-        hipLaunchKernelGGL(k_gemm_batch, dim3(tn, 1, (unsigned)nt), dim3(NT), 0, h.stream,
-                           d_g + ((size_t)b * 2 + 1) * nt);
+        gemm_batch(h, dim3(tj, 1, (unsigned)nt), g.data() + ((size_t)b * 2) * nt, nt, d_g + ((size_t)b * 2) * nt,
+                   h.stream);
+        gemm_batch(h, dim3(tn, 1, (unsigned)nt), g.data() + ((size_t)b * 2 + 1) * nt, nt,
+                   d_g + ((size_t)b * 2 + 1) * nt, h.stream);
       }
     }
     hipLaunchKernelGGL(k_sk_orth_block, dim3((unsigned)nt), dim3(NT), 0, h.stream, d_T, b * 64, drop, n0, ldn0);
@@ -1581,8 +1593,8 @@ static int sketch_batch(Handle& h, const ColourWork& W, const std::vector<int32_
     if ((rc = sk_orthonormalise(h, B.T, B.d_T, drop, err))) return rc;
   }
   ProfScope ps(h, "group:sketch_rr", 0, 0);
-  hipLaunchKernelGGL(k_gemm_batch, dim3(tn, ts, (unsigned)ns), dim3(NT), 0, h.stream, d_G);
-  hipLaunchKernelGGL(k_gemm_batch, dim3(ts, ts, (unsigned)ns), dim3(NT), 0, h.stream, d_G + ns);
+  gemm_batch(h, dim3(tn, ts, (unsigned)ns), g.data(), ns, d_G, h.stream);
+  gemm_batch(h, dim3(ts, ts, (unsigned)ns), g.data() + ns, ns, d_G + ns, h.stream);
   hipLaunchKernelGGL(k_sk_trace, dim3((unsigned)ns), dim3(NT), 0, h.stream, B.d_T);
   if ((rc = eig_values(h, B.E, B.d_E, eps2, B.d_cnt, h.stream, err))) return rc;
   hipLaunchKernelGGL(k_sk_check, dim3((unsigned)((ns + NT - 1) / NT)), dim3(NT), 0, h.stream, B.d_T, B.d_E, B.d_cnt,
@@ -1924,8 +1936,8 @@ static int colour_ranks_vectors(Handle& h, ColourWork& W, HostLap& lap, std::str
       }
       ProfScope ps(h, "group:sketch_vectors", fl, 0);
       eig_vectors(h, skE, d_vs, h.stream);
-      hipLaunchKernelGGL(k_gemm_batch, dim3((unsigned)((nmx + 63) / 64), (unsigned)((rmax + 63) / 64), (unsigned)ns2),
-                         dim3(NT), 0, h.stream, d_vg);
+      gemm_batch(h, dim3((unsigned)((nmx + 63) / 64), (unsigned)((rmax + 63) / 64), (unsigned)ns2), vT.data(), ns2,
+                 d_vg, h.stream);
     }
     if (vside && (rc = join_side(h, err))) return rc;
     lap.mark("plan_vectors");

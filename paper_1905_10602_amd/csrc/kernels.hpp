@@ -569,6 +569,8 @@ struct GemmTask {
   int32_t m, n, k, lda, ldb, ldc, tA, tB;
   double alpha, beta;
 };
+// mf: the FP64 matrix-core tile (every task of the launch with tB == 0).
+template <bool mf>
 __global__ void __launch_bounds__(NT) k_gemm_batch(const GemmTask* tasks) {
   const GemmTask t = tasks[blockIdx.z];
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
@@ -576,8 +578,12 @@ __global__ void __launch_bounds__(NT) k_gemm_batch(const GemmTask* tasks) {
   const int mm = min(64, t.m - i0), nn = min(64, t.n - j0);
   const double* Ab = t.tA ? t.A + (int64_t)i0 * t.lda : t.A + i0;
   const double* Bb = t.tB ? t.B + j0 : t.B + (int64_t)j0 * t.ldb;
-  wg_gemm(mm, nn, t.k, t.alpha, Ab, t.lda, t.tA != 0, Bb, t.ldb, t.tB != 0, t.beta, t.C + i0 + (int64_t)j0 * t.ldc,
-          t.ldc);
+  if constexpr (mf)
+    wg_gemm_f64m(mm, nn, t.k, t.alpha, Ab, t.lda, Bb, t.ldb, t.beta, t.C + i0 + (int64_t)j0 * t.ldc, t.ldc,
+                 t.tA != 0);
+  else
+    wg_gemm(mm, nn, t.k, t.alpha, Ab, t.lda, t.tA != 0, Bb, t.ldb, t.tB != 0, t.beta,
+            t.C + i0 + (int64_t)j0 * t.ldc, t.ldc);
 }
 
 // ------------------------------------------------------------------ sketched recompression
@@ -782,10 +788,10 @@ __global__ void __launch_bounds__(NT) k_sk_orth_block(const SkTask* tasks, int j
   const SkTask t = tasks[blockIdx.x];
   const int n = t.n, j1 = min(t.s, j0 + 64);
   if (j0 >= t.s) return;
-  double* X = t.Y;
+  const auto X = gmem(t.Y);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int j = j0; j < j1; ++j) {
-    double* xj = X + (int64_t)j * n;
+    const auto xj = X + (int64_t)j * n;
     const int cnt = j - j0;
     double part = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
@@ -793,10 +799,25 @@ __global__ void __launch_bounds__(NT) k_sk_orth_block(const SkTask* tasks, int j
         // c_i = q_i^T x_j, four columns per wave at a time
         for (int i0 = 4 * wave; i0 < cnt; i0 += NT / 16) {
           double c[4] = {0.0, 0.0, 0.0, 0.0};
-          const double* xi[4];
+          std::remove_const_t<decltype(X)> xi[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) xi[u] = X + (int64_t)(j0 + min(i0 + u, cnt - 1)) * n;
-          for (int r = lane; r < n; r += 64) {
+          // four rows' loads in flight before their products (same order)
+          int r = lane;
+          for (; r + 192 < n; r += 256) {
+            double xv[4], yv[4][4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              xv[q] = xj[r + 64 * q];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) yv[q][u] = xi[u][r + 64 * q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) c[u] += yv[q][u] * xv[q];
+          }
+          for (; r < n; r += 64) {
             const double v = xj[r];
 #pragma unroll
             for (int u = 0; u < 4; ++u) c[u] += xi[u][r] * v;
@@ -813,7 +834,15 @@ __global__ void __launch_bounds__(NT) k_sk_orth_block(const SkTask* tasks, int j
       // x_j -= sum_i c_i q_i (and, on the second pass, the squared norm)
       for (int r = tid; r < n; r += NT) {
         double v = xj[r];
-        for (int i = 0; i < cnt; ++i) v -= s_c[i] * s_sc[i] * X[r + (int64_t)(j0 + i) * n];
+        int i = 0;
+        for (; i + 8 <= cnt; i += 8) {  // eight loads in flight, then the same sequence of updates
+          double xv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) xv[u] = X[r + (int64_t)(j0 + i + u) * n];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v -= s_c[i + u] * s_sc[i + u] * xv[u];
+        }
+        for (; i < cnt; ++i) v -= s_c[i] * s_sc[i] * X[r + (int64_t)(j0 + i) * n];
         if (cnt > 0) xj[r] = v;
         if (pass == 1) part += v * v;
       }
