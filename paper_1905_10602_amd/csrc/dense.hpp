@@ -152,18 +152,27 @@ __device__ inline void wg_gemm(int m, int n, int k, double alpha, const double* 
         if (more) stash();
         __syncthreads();
       }
+      // epilogue: every C value loaded, then combined, then stored (a wait
+      // for a load issued after a store also waits for the store)
+      double cv[4][4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int gj = j0 + tc + 16 * b;
-        if (gj >= n) continue;
+      for (int b = 0; b < 4; ++b)
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          const int gi = i0 + tr + 16 * a;
-          if (gi >= m) continue;
-          auto c = C + gi + (int64_t)gj * ldc;
-          *c = (beta == 0.0) ? alpha * acc[a][b] : fma(alpha, acc[a][b], beta * (*c));
+          const int gi = i0 + tr + 16 * a, gj = j0 + tc + 16 * b;
+          cv[a][b] = (beta != 0.0 && gi < m && gj < n) ? C[gi + (int64_t)gj * ldc] : 0.0;
         }
-      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) cv[a][b] = (beta == 0.0) ? alpha * acc[a][b] : fma(alpha, acc[a][b], beta * cv[a][b]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int gi = i0 + tr + 16 * a, gj = j0 + tc + 16 * b;
+          if (gi < m && gj < n) C[gi + (int64_t)gj * ldc] = cv[a][b];
+        }
     }
   }
   __syncthreads();
@@ -246,13 +255,20 @@ __device__ inline void wg_gemm_f32_lite(int m, int n, int k, double alpha, const
       }
       const int gi = i0 + wr + (lane & 31);
       if (gi < m) {
+        // every C value loaded, then combined, then stored
+        double cv[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int gj = j0 + wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-          if (gj < n) {
-            auto c = C + gi + (int64_t)gj * ldc;
-            *c = (beta == 0.0) ? alpha * (double)acc[v] : fma(alpha, (double)acc[v], beta * (*c));
-          }
+          cv[v] = (beta != 0.0 && gj < n) ? C[gi + (int64_t)gj * ldc] : 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          cv[v] = (beta == 0.0) ? alpha * (double)acc[v] : fma(alpha, (double)acc[v], beta * cv[v]);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int gj = j0 + wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          if (gj < n) C[gi + (int64_t)gj * ldc] = cv[v];
         }
       }
     }
@@ -330,13 +346,20 @@ __device__ inline void wg_gemm_f32_kc32(int m, int n, int k, double alpha, const
       }
       const int gi = i0 + wr + (lane & 31);
       if (gi < m) {
+        // every C value loaded, then combined, then stored
+        double cv[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int gj = j0 + wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-          if (gj < n) {
-            auto c = C + gi + (int64_t)gj * ldc;
-            *c = (beta == 0.0) ? alpha * (double)acc[v] : fma(alpha, (double)acc[v], beta * (*c));
-          }
+          cv[v] = (beta != 0.0 && gj < n) ? C[gi + (int64_t)gj * ldc] : 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          cv[v] = (beta == 0.0) ? alpha * (double)acc[v] : fma(alpha, (double)acc[v], beta * cv[v]);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int gj = j0 + wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          if (gj < n) C[gi + (int64_t)gj * ldc] = cv[v];
         }
       }
     }
@@ -457,6 +480,9 @@ __device__ inline void wg_gemm_f64m(int m, int n, int k, double alpha, const dou
         __syncthreads();
       }
       // acc[ri][cj] register v of lane l: C[i0 + wr + 16 ri + l % 16][j0 + wc + 16 cj + 4 v + l / 16]
+      // every C value loaded, then combined, then stored (a wait for a load
+      // issued after a store also waits for the store)
+      double cv[2][2][4];
 #pragma unroll
       for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
@@ -464,10 +490,23 @@ __device__ inline void wg_gemm_f64m(int m, int n, int k, double alpha, const dou
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int i = i0 + wr + 16 * ri + lr, j = j0 + wc + 16 * cj + 4 * v + lk;
-            if (i < m && j < n) {
-              auto c = C + i + (int64_t)j * ldc;
-              *c = beta == 0.0 ? alpha * acc[ri][cj][v] : fma(alpha, acc[ri][cj][v], beta * *c);
-            }
+            cv[ri][cj][v] = (beta != 0.0 && i < m && j < n) ? C[i + (int64_t)j * ldc] : 0.0;
+          }
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+        for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            cv[ri][cj][v] = beta == 0.0 ? alpha * acc[ri][cj][v] : fma(alpha, acc[ri][cj][v], beta * cv[ri][cj][v]);
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+        for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = i0 + wr + 16 * ri + lr, j = j0 + wc + 16 * cj + 4 * v + lk;
+            if (i < m && j < n) C[i + (int64_t)j * ldc] = cv[ri][cj][v];
           }
     }
   }

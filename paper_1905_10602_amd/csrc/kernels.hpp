@@ -408,10 +408,19 @@ __global__ void __launch_bounds__(NT) k_trd_tiles(const TrdTask* tasks, int k) {
       const int i = I + tx + 16 * a, j = J + ty + 16 * b;
       if (i < m && j < m && (!diag || i >= j)) {
         const double sv = x[a][b] - 2.0 * (vr[a] * wc[b] + wr[a] * vc[b]);
-        S[i + (int64_t)j * n] = sv;
+        x[a][b] = sv;
         racc[a] += sv * vnc[b];
         if (!diag || i > j) cacc[b] += sv * vnr[a];
       }
+    }
+  // the stores after every result (a wait for a load after a store would
+  // also wait for the store)
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = I + tx + 16 * a, j = J + ty + 16 * b;
+      if (i < m && j < m && (!diag || i >= j)) S[i + (int64_t)j * n] = x[a][b];
     }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -1166,18 +1175,26 @@ __global__ void __launch_bounds__(NT) k_blu_xinit(const BluTask* tasks, const El
   }
 }
 
+// Panel LU of columns j0 .. j0+nb-1 over rows j0 .. d-1, one workgroup per
+// task.  Per column: the pivot (largest magnitude, first on ties), the row
+// interchange inside the panel, the scaling of the column and the rank-1
+// update of the panel columns to its right.  The scaling and the update go
+// through their elements four per thread at a time, loads first, then the
+// arithmetic, then the stores, so that a batch of loads is in flight at once
+// (a wait for a load issued after a store also waits for the store).
 __global__ void __launch_bounds__(NT) k_blu_panel(const BluTask* tasks, int j0) {
   const BluTask t = tasks[blockIdx.x];
   const int d = t.d;
   if (j0 >= d) return;
   const int nb = min(BLU_NB, d - j0);
   double* T = t.lu;
+  const auto Tg = gmem(T);
   const int tid = threadIdx.x;
   for (int j = j0; j < j0 + nb; ++j) {
     double best = -1.0;
     int bi = j;  // in range even for a NaN column
     for (int i = j + tid; i < d; i += NT) {
-      const double v = fabs(T[i + (int64_t)j * d]);
+      const double v = fabs(Tg[i + (int64_t)j * d]);
       if (v > best) { best = v; bi = i; }
     }
     wg_argmax(best, bi);
@@ -1196,12 +1213,53 @@ __global__ void __launch_bounds__(NT) k_blu_panel(const BluTask* tasks, int j0) 
     __syncthreads();
     const double dj = T[j + (int64_t)j * d];
     if (dj != 0.0)
-      for (int i = j + 1 + tid; i < d; i += NT) T[i + (int64_t)j * d] /= dj;
+      for (int i0 = j + 1; i0 < d; i0 += 4 * NT) {
+        double x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + tid + NT * q;
+          x[q] = i < d ? Tg[i + (int64_t)j * d] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] /= dj;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + tid + NT * q;
+          if (i < d) Tg[i + (int64_t)j * d] = x[q];
+        }
+      }
     __syncthreads();
     const int rem = d - j - 1, w = j0 + nb - j - 1;
     if (rem > 0 && w > 0) {
-      WG_FOR2(rem, w, ii, cc) T[j + 1 + ii + (int64_t)(j + 1 + cc) * d] -=
-          T[j + 1 + ii + (int64_t)j * d] * T[j + (int64_t)(j + 1 + cc) * d];
+      // element e = ii + rem * cc of the rem x w block, e = tid + NT * step;
+      // (ii, cc) advance by NT per step without a division
+      const int di = NT % rem, dc = NT / rem;
+      int ii = tid % rem, cc = tid / rem;
+      while (cc < w) {
+        int ri[4], ci[4];
+        double x[4], l[4], u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ri[q] = ii;
+          ci[q] = cc;
+          ii += di;
+          cc += dc;
+          if (ii >= rem) { ii -= rem; ++cc; }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool ok = ci[q] < w;
+          const int64_t col = (int64_t)(j + 1 + (ok ? ci[q] : 0)) * d;
+          x[q] = ok ? Tg[j + 1 + ri[q] + col] : 0.0;
+          l[q] = ok ? Tg[j + 1 + ri[q] + (int64_t)j * d] : 0.0;
+          u[q] = ok ? Tg[j + col] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] -= l[q] * u[q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (ci[q] < w) Tg[j + 1 + ri[q] + (int64_t)(j + 1 + ci[q]) * d] = x[q];
+      }
     }
     __syncthreads();
   }
