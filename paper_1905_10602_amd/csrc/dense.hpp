@@ -520,12 +520,56 @@ __device__ inline void wg_gemm_p(bool f32, int m, int n, int k, double alpha, co
   else wg_gemm(m, n, k, alpha, A, lda, tA, B, ldb, tB, beta, C, ldc);
 }
 
-// dst(m x n) = alpha * src
-__device__ inline void wg_copy(int m, int n, const double* src, int lds, double* dst, int ldd, double alpha = 1.0) {
-  if (m > 0) {
-    WG_FOR2(m, n, i, j) dst[i + (int64_t)j * ldd] = alpha * src[i + (int64_t)j * lds];
+// Element-wise pass over an R x C index range (rows fastest, the order of
+// WG_FOR2), EW_B elements per thread at a time: ld(i, c) for all of them
+// (the loads), then st(i, c, value) (the arithmetic and the stores).  A wait
+// for a load issued after a store also waits for that store, so a loop that
+// loads and stores one element at a time pays a memory latency per element.
+// No barrier at the end.
+constexpr int EW_B = 8;
+template <class Ld, class St>
+__device__ inline void wg_each2(int R, int C, Ld ld, St st) {
+  if (R <= 0 || C <= 0) return;
+  const int di = (int)((unsigned)NT % (unsigned)R), dc = (int)((unsigned)NT / (unsigned)R);
+  int i = (int)(threadIdx.x % (unsigned)R), c = (int)(threadIdx.x / (unsigned)R);
+  while (c < C) {
+    int ri[EW_B], ci[EW_B];
+    decltype(ld(0, 0)) v[EW_B];
+#pragma unroll
+    for (int q = 0; q < EW_B; ++q) {
+      ri[q] = i;
+      ci[q] = c;
+      i += di;
+      c += dc;
+      if (i >= R) {
+        i -= R;
+        ++c;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < EW_B; ++q)
+      if (ci[q] < C) v[q] = ld(ri[q], ci[q]);
+#pragma unroll
+    for (int q = 0; q < EW_B; ++q)
+      if (ci[q] < C) st(ri[q], ci[q], v[q]);
   }
+}
+
+// dst(m x n) = alpha * src (global memory, no overlap)
+__device__ inline void wg_copy(int m, int n, const double* src, int lds, double* dst, int ldd, double alpha = 1.0) {
+  const auto S = gmem(src);
+  const auto D = gmem(dst);
+  wg_each2(m, n, [&](int i, int j) { return S[i + (int64_t)j * lds]; },
+           [&](int i, int j, double v) { D[i + (int64_t)j * ldd] = alpha * v; });
   __syncthreads();
+}
+
+// dst(m x n) += src (global memory, no overlap)
+__device__ inline void wg_add(int m, int n, const double* src, int lds, double* dst, int ldd) {
+  const auto S = gmem(src);
+  const auto D = gmem(dst);
+  wg_each2(m, n, [&](int i, int j) { return make_double2(D[i + (int64_t)j * ldd], S[i + (int64_t)j * lds]); },
+           [&](int i, int j, double2 v) { D[i + (int64_t)j * ldd] = v.x + v.y; });
 }
 
 __device__ inline void wg_fill(int m, int n, double* dst, int ldd, double v) {

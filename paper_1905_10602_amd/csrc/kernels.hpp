@@ -1523,10 +1523,12 @@ __global__ void __launch_bounds__(NT) k_gram_prep(LevelView V, const Changed* ch
   if (r == 0 || n == 0) return;
   if (side == 0) {
     const double* P2M = V.arena + V.p2m_off[p];
-    WG_FOR2(r, n, a, j) { t[a + (int64_t)j * r] = sig[a] * P2M[a + (int64_t)j * rc]; }
+    wg_each2(r, n, [&](int a, int j) { return make_double2(sig[a], P2M[a + (int64_t)j * rc]); },
+             [&](int a, int j, double2 v) { t[a + (int64_t)j * r] = v.x * v.y; });
   } else {
     const double* L2P = V.arena + V.l2p_off[p];
-    WG_FOR2(n, r, j, a) { t[j + (int64_t)a * n] = L2P[j + (int64_t)a * n] * sig[rc + a]; }
+    wg_each2(n, r, [&](int j, int a) { return make_double2(L2P[j + (int64_t)a * n], sig[rc + a]); },
+             [&](int j, int a, double2 v) { t[j + (int64_t)a * n] = v.x * v.y; });
   }
 }
 
@@ -1568,7 +1570,9 @@ __global__ void __launch_bounds__(NT) k_gram(LevelView V, const Changed* chg, co
     }
   }
   if (ti != tj) {
-    WG_FOR2(mi, mj, a, b) { G[J + b + (int64_t)(I + a) * n] = G[I + a + (int64_t)(J + b) * n]; }
+    const auto Gg = gmem(G);
+    wg_each2(mi, mj, [&](int a, int b) { return Gg[I + a + (int64_t)(J + b) * n]; },
+             [&](int a, int b, double v) { Gg[J + b + (int64_t)(I + a) * n] = v; });
   }
 }
 
@@ -1582,12 +1586,10 @@ __global__ void __launch_bounds__(NT) k_basis(LevelView V, const Changed* chg) {
   double* sig = V.arena + V.sig_off[p];
   wg_gemm(r, rn, n, 1.0, P2M, rc, false, C.vs, n, false, 0.0, C.T, r > 0 ? r : 1);
   wg_gemm(rn, r, n, 1.0, C.vt, n, true, L2P, n, false, 0.0, C.S, rn > 0 ? rn : 1);
-  if (rn > 0) WG_FOR2(rn, n, a, j) {
-    P2M[a + (int64_t)j * rc] = C.vs[j + (int64_t)a * n];
-  }
-  if (n > 0) WG_FOR2(n, rn, j, a) {
-    L2P[j + (int64_t)a * n] = C.vt[j + (int64_t)a * n];
-  }
+  wg_each2(rn, n, [&](int a, int j) { return C.vs[j + (int64_t)a * n]; },
+           [&](int a, int j, double v) { P2M[a + (int64_t)j * rc] = v; });
+  wg_each2(n, rn, [&](int j, int a) { return C.vt[j + (int64_t)a * n]; },
+           [&](int j, int a, double v) { L2P[j + (int64_t)a * n] = v; });
   for (int a = threadIdx.x; a < rn; a += NT) {
     sig[a] = sqrt(fmax(C.ls[a], 0.0));
     sig[rc + a] = sqrt(fmax(C.lt[a], 0.0));
@@ -1607,9 +1609,7 @@ __global__ void __launch_bounds__(NT) k_project(LevelView V, const FarPair* far,
   const ElimNbr A = nbrs[R.nb_begin + P.a], B = nbrs[R.nb_begin + P.b];
   if (P.direct) {
     double* dst = P.dst;
-    if (A.m > 0) WG_FOR2(A.m, B.m, x, y) {
-      dst[x + (int64_t)y * P.dst_ld] += P.F[x + (int64_t)y * A.m];
-    }
+    wg_add(A.m, B.m, P.F, A.m, dst, P.dst_ld);
     return;
   }
   const int ra = A.elim ? A.m : chg[V.chg[A.p]].rnew;
@@ -1665,9 +1665,7 @@ __global__ void __launch_bounds__(NT) k_phase_b(LevelView V, int K, const Change
     const int k = find_ref(refs, C.far_begin, C.far_count, l);
     if (k >= 0) {
       const double* Dm = far[refs[k].ab].F;
-      if (rn > 0) WG_FOR2(rn, rln, x, y) {
-        M[x + (int64_t)y * ldn] += Dm[x + (int64_t)y * rn];
-      }
+      wg_add(rn, rln, Dm, rn, M, ldn);
       __syncthreads();
     }
   }
@@ -1684,9 +1682,7 @@ __global__ void __launch_bounds__(NT) k_phase_b(LevelView V, int K, const Change
     const int k = find_ref(refs, C.far_begin, C.far_count, l);
     if (k >= 0) {
       const double* Dm = far[refs[k].ba].F;
-      if (rl > 0) WG_FOR2(rl, rn, x, y) {
-        M[x + (int64_t)y * ldn] += Dm[x + (int64_t)y * rl];
-      }
+      wg_add(rl, rn, Dm, rl, M, ldn);
       __syncthreads();
     }
   }
@@ -1850,7 +1846,7 @@ __global__ void __launch_bounds__(NT) k_phase_b_blocks(LevelView V, int K, const
     const int k = find_ref(refs, C.far_begin, C.far_count, l);
     if (k >= 0) {
       const double* Dm = far[refs[k].ab].F;
-      if (rn > 0) WG_FOR2(rn, rln, x, y) { M[x + (int64_t)y * ldn] += Dm[x + (int64_t)y * rn]; }
+      wg_add(rn, rln, Dm, rn, M, ldn);
     }
   } else if (task.kind == 1) {
     const int s = task.slot;  // slot of p in I_l
@@ -1864,7 +1860,7 @@ __global__ void __launch_bounds__(NT) k_phase_b_blocks(LevelView V, int K, const
     const int k = find_ref(refs, C.far_begin, C.far_count, ln);
     if (k >= 0) {
       const double* Dm = far[refs[k].ba].F;
-      if (rl > 0) WG_FOR2(rl, rn, x, y) { M[x + (int64_t)y * ldn] += Dm[x + (int64_t)y * rl]; }
+      wg_add(rl, rn, Dm, rl, M, ldn);
     }
   } else {
     double* M2M = V.arena + V.m2m_off[p];
