@@ -729,7 +729,9 @@ __device__ inline void wg_trd_eigenvalues(int n, const double* A, int lda, doubl
 // The rank-2 update of step k and the product S v of step k + 1 share one
 // pass over the trailing matrix.
 __device__ inline void wg_syev_values(int n, double* A, int lda, double* W, double* lam) {
-  __shared__ double sv[TRD_MAXN], sw[TRD_MAXN], sp[TRD_MAXN];  // 48 KiB
+  // sq takes the next product during the fused pass (sp holds the next
+  // reflector then)
+  __shared__ double sv[TRD_MAXN], sw[TRD_MAXN], sp[TRD_MAXN], sq[TRD_MAXN];  // 64 KiB
   double* d = W;
   double* e = W + n;
   double* tau = W + 2 * n;
@@ -800,18 +802,30 @@ __device__ inline void wg_syev_values(int n, double* A, int lda, double* W, doub
       double* vn = sp;  // reuse: p of this step is no longer needed
       for (int i = tid; i < m2; i += NT) vn[i] = sig2 != 0.0 ? (i == 0 ? v02 : x2[i]) * inv2 : 0.0;
       __syncthreads();
-      // fused pass over S[1:, 1:]: update and accumulate S' v' (rows of this
-      // thread: i = tid + NT t, at most TRD_MAXN / NT of them)
+      // fused pass over S[1:, 1:]: update and accumulate S' v' into sq (rows
+      // of this thread: i = tid + NT t, at most TRD_MAXN / NT of them)
       double* S2 = S + 1 + lda;
-      double pacc[TRD_MAXN / NT];
-#pragma unroll
       for (int t = 0; t < TRD_MAXN / NT; ++t) {
-        pacc[t] = 0.0;
         const int i = tid + NT * t;
-        if (i >= m2) continue;
+        if (i >= m2) break;
         const double vi = sv[i + 1], wi = sw[i + 1];
         double a0 = 0.0, a1 = 0.0;
         int j = 0;
+        // four columns per batch: their loads, then the updates (even
+        // columns into a0, odd into a1, as below), then the stores
+        for (; j + 3 < m2; j += 4) {
+          double x[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) x[q] = gmem(S2)[i + (int64_t)(j + q) * lda];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            x[q] = x[q] - 2.0 * (vi * sw[j + q + 1] + wi * sv[j + q + 1]);
+            if (q & 1) a1 += x[q] * vn[j + q];
+            else a0 += x[q] * vn[j + q];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) gmem(S2)[i + (int64_t)(j + q) * lda] = x[q];
+        }
         for (; j + 1 < m2; j += 2) {
           double* c0 = S2 + i + (int64_t)j * lda;
           double* c1 = S2 + i + (int64_t)(j + 1) * lda;
@@ -828,17 +842,13 @@ __device__ inline void wg_syev_values(int n, double* A, int lda, double* W, doub
           *c0 = s0;
           a0 += s0 * vn[j];
         }
-        pacc[t] = a0 + a1;
+        sq[i] = a0 + a1;
       }
       __syncthreads();
       // the next step recomputes its v from the same column; its p is S'' v'
       // (only when that reflector is non-trivial)
       if (sig2 != 0.0) {
-#pragma unroll
-        for (int t = 0; t < TRD_MAXN / NT; ++t) {
-          const int i = tid + NT * t;
-          if (i < m2) sp[i] = pacc[t];
-        }
+        for (int i = tid; i < m2; i += NT) sp[i] = sq[i];
         have_p = true;
       } else {
         have_p = false;
