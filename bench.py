@@ -12,9 +12,11 @@ points (7 here) and the two coarser ones (Sec. 5.2 tunes it the same way).
 Forms on the same GPU:
   mixed      FP32 matrix-core Schur and basis products, sketched recompression
              sized by the trained rank network: gives `value`;
-  fp64       every step FP64, full eigen-decompositions (one step);
+  fp64       every step FP64, full eigen-decompositions;
   heuristic  the mixed form without the network (sketch width from the node's
-             current rank; one step): the ablation of the learned part.
+             current rank): the ablation of the learned part.
+The comparison forms take up to three timed steps each (no warm-up of their
+own: the lead form's run has loaded the kernels), factor time the median.
 For each form: e_res = ||A~ x - b|| / ||b|| with A~ applied through the
 Chebyshev 4^3 FMM on the IFMM's own tree (exactly the matrix the IFMM
 factorises), and FGMRES(50) on the Chebyshev 5^3 FMM operator with the form's
@@ -22,8 +24,8 @@ factorisation as right preconditioner (iterations at tolerance 1e-8).
 
 The whole run keeps to a wall-clock budget (--budget-s, counted from the
 start of the process): warm-up is at most one step, the timed mixed steps are
-as many of --steps as fit, the comparison forms run once, and the GMRES and
-CPU legs are skipped, with a note, when they no longer fit.  `steps` reports
+as many of --steps as fit, the comparison forms up to three steps each, and the
+GMRES and CPU legs are skipped, with a note, when they no longer fit.  `steps` reports
 the count actually timed.  The JSON line is always printed.
 
 `roofline` covers the single kernel with the largest device time in the lead
@@ -69,6 +71,9 @@ MFMA_F64 = {"k_schur"}
 
 def log(msg):
     print(f"[bench {time.time() - T_START:6.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+CMP_STEPS = 3  # timed steps of each comparison form (fp64, heuristic), when they fit
 
 
 def left(args):
@@ -590,8 +595,12 @@ def main():
                                        bt, xt, F5, F4, f_dev, max(args.steps, 1), min(args.warmup, 1))
                 est_step = out["step_s"]
             else:
-                out, st, x0 = run_form(fm, pts, dg, argparse.Namespace(**{**vars(args), "reserve_s": 0.0}),
-                                       bt, xt, F5, F4, f_dev, 1, 0)
+                # up to CMP_STEPS steps, keeping time for the legs still to come
+                rest = forms[forms.index(fm) + 1:]
+                keep = sum((est_step or 60.0) * (2.0 if r == "fp64" else 1.2) + 15 for r in rest)
+                keep += (0.0 if args.no_batch else 90.0) + (0.0 if args.no_cpu_baseline else 80.0)
+                out, st, x0 = run_form(fm, pts, dg, argparse.Namespace(**{**vars(args), "reserve_s": keep}),
+                                       bt, xt, F5, F4, f_dev, CMP_STEPS, 0)
         except Exception as e:  # keep the line: report the failure of this form
             traceback.print_exc()
             notes.append(f"form {fm} failed: {e}")
@@ -660,22 +669,22 @@ def main():
 
 def _reserve(args, forms):
     """Seconds to keep free after the lead form's timed steps: the comparison
-    forms (one step each, the FP64 one about twice as long), GMRES and the CPU
-    sample.  Estimated before the first step from the workload size."""
+    forms (CMP_STEPS steps each), GMRES, the batch leg and the CPU sample.
+    Estimated before the first step from the workload size."""
     if args.reserve_s >= 0:
         return args.reserve_s
     scale = args.n / float(1 << 20)
     est = 0.0
     if "fp64" in forms:
-        est += 60.0 * scale + 10
+        est += 20.0 * CMP_STEPS * scale + 10
     if "heuristic" in forms:
-        est += 35.0 * scale + 10
+        est += 18.0 * CMP_STEPS * scale + 10
     if not args.no_gmres:
-        est += 10.0 * len(forms)
+        est += 5.0 * len(forms)
     if not args.no_cpu_baseline:
         est += 80.0
     if not args.no_batch:
-        est += 90.0
+        est += 45.0
     return est
 
 
