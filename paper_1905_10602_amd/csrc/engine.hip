@@ -2512,22 +2512,24 @@ int factor(Handle& h, std::string& err) {
     const int n = h.top_n;
     HIPCHK(hipMemsetAsync(d_info, 0, 4, h.stream));
     hipLaunchKernelGGL(k_top_assemble, dim3(L2.nn), dim3(NT), 0, h.stream, V2, L2.nn, d_toff, h.d_top, n);
-    // blocked LU: panel, swaps, triangular solve, trailing update
-    for (int j0 = 0; j0 < n; j0 += TOP_NB) {
-      const int nb = std::min(TOP_NB, n - j0);
-      hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(NT), 0, h.stream, h.d_top, n, j0, nb, h.d_top_piv, d_info);
-      hipLaunchKernelGGL(k_lu_swap, dim3((n + NT - 1) / NT), dim3(NT), 0, h.stream, h.d_top, n, j0, nb, h.d_top_piv);
-      const int rest = n - j0 - nb;
-      if (rest > 0) {
-        hipLaunchKernelGGL(k_lu_trsm, dim3((rest + 63) / 64), dim3(NT), 0, h.stream, h.d_top, n, j0, nb);
-        hipLaunchKernelGGL(k_gemm_tiles, dim3((rest + 63) / 64, (rest + 63) / 64), dim3(NT), 0, h.stream, rest, rest,
-                           nb, -1.0, h.d_top + (j0 + nb) + (int64_t)j0 * n, n, h.d_top + j0 + (int64_t)(j0 + nb) * n,
-                           n, 1.0, h.d_top + (j0 + nb) + (int64_t)(j0 + nb) * n, n);
-      }
-    }
+    // T^-1 from the blocked LU of [T | I] (Sec. 2.3: the top system is solved
+    // densely): the pivots' machinery with one task, every step one launch
+    // over many workgroups; T keeps its LU factors
     if ((rc = dalloc(h, &h.d_top_inv, (int64_t)n * n, err))) return rc;
-    hipLaunchKernelGGL(k_lu_inverse, dim3((n + 63) / 64), dim3(NT), 0, h.stream, h.d_top, n, h.d_top_piv,
-                       h.d_top_inv);
+    const unsigned nt = (unsigned)((n + 63) / 64);
+    hipLaunchKernelGGL(k_eye, dim3(nt, nt), dim3(NT), 0, h.stream, h.d_top_inv, n);
+    double* d_dinv = nullptr;
+    const int64_t nsteps = (n + BLU_NB - 1) / BLU_NB;
+    if ((rc = dalloc(h, &d_dinv, nsteps * 2 * 4096, err))) return rc;
+    BluTask* d_bt = nullptr;
+    if ((rc = dalloc(h, &d_bt, 1, err))) return rc;
+    const BluTask bt{h.d_top, h.d_top_inv, h.d_top_piv, d_info, d_dinv, n, n};
+    H2D(h, d_bt, held(h, std::vector<BluTask>{bt}), sizeof(BluTask));
+    enqueue_blocked_lu(d_bt, 1, n, n, h.stream);
+    HIPCHK(hipGetLastError());
+    HSYNC(h);
+    dfree(h, d_dinv);
+    dfree(h, d_bt);
   }
   HIPCHK(hipGetLastError());
   // every stored factor block and the top inverse must be finite (an overflow

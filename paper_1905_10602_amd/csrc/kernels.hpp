@@ -1926,8 +1926,8 @@ __global__ void __launch_bounds__(NT) k_top_assemble(LevelView V, int nn, const 
   }
 }
 
-// ---- blocked right-looking LU of the dense top matrix (many workgroups)
-constexpr int TOP_NB = 64;
+// ---- dense top level: its inverse comes from the blocked LU of [T | I]
+// (k_blu_*, one task), the top solve is a GEMM with it.
 
 // C tile (64 x 64 at blockIdx) of C = alpha A B + beta C.
 __global__ void __launch_bounds__(NT) k_gemm_tiles(int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
@@ -1939,88 +1939,13 @@ __global__ void __launch_bounds__(NT) k_gemm_tiles(int m, int n, int k, double a
           ldc);
 }
 
-// Panel T[j0:n, j0:j0+nb]: unblocked LU with partial pivoting over rows j0..n-1
-// (swaps applied inside the panel only); piv[j] = global row swapped with j.
-__global__ void __launch_bounds__(NT) k_lu_panel(double* T, int n, int j0, int nb, int32_t* piv, int32_t* info) {
-  const int tid = threadIdx.x;
-  for (int j = j0; j < j0 + nb; ++j) {
-    double best = -1.0;
-    int bi = j;  // in range even for a NaN column
-    for (int i = j + tid; i < n; i += NT) {
-      const double v = fabs(T[i + (int64_t)j * n]);
-      if (v > best) { best = v; bi = i; }
-    }
-    wg_argmax(best, bi);
-    const int p = bi;
-    const double pv = best;
-    if (tid == 0) {
-      piv[j] = p;
-      if (pv == 0.0 && *info == 0) *info = j + 1;
-    }
-    if (p != j)
-      for (int c = j0 + tid; c < j0 + nb; c += NT) {
-        const double t = T[j + (int64_t)c * n];
-        T[j + (int64_t)c * n] = T[p + (int64_t)c * n];
-        T[p + (int64_t)c * n] = t;
-      }
-    __syncthreads();
-    const double dj = T[j + (int64_t)j * n];
-    if (dj != 0.0)
-      for (int i = j + 1 + tid; i < n; i += NT) T[i + (int64_t)j * n] /= dj;
-    __syncthreads();
-    const int rem = n - j - 1, w = j0 + nb - j - 1;
-    if (rem > 0 && w > 0) {
-      WG_FOR2(rem, w, ii, cc) T[j + 1 + ii + (int64_t)(j + 1 + cc) * n] -=
-          T[j + 1 + ii + (int64_t)j * n] * T[j + (int64_t)(j + 1 + cc) * n];
-    }
-    __syncthreads();
+// X (n x n) = I, grid (ceil(n / 64), ceil(n / 64)): one 64 x 64 tile each.
+__global__ void __launch_bounds__(NT) k_eye(double* X, int n) {
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = i0 + (e & 63), j = j0 + (e >> 6);
+    if (i < n && j < n) X[i + (int64_t)j * n] = i == j ? 1.0 : 0.0;
   }
-}
-
-// Row interchanges of the panel applied to the columns outside it.
-__global__ void __launch_bounds__(NT) k_lu_swap(double* T, int n, int j0, int nb, const int32_t* piv) {
-  const int c = blockIdx.x * NT + threadIdx.x;
-  if (c >= n || (c >= j0 && c < j0 + nb)) return;
-  for (int j = j0; j < j0 + nb; ++j) {
-    const int p = piv[j];
-    if (p != j) {
-      const double t = T[j + (int64_t)c * n];
-      T[j + (int64_t)c * n] = T[p + (int64_t)c * n];
-      T[p + (int64_t)c * n] = t;
-    }
-  }
-}
-
-// U12 = L11^-1 A12 for 64 columns per workgroup (L11 unit lower, in LDS).
-__global__ void __launch_bounds__(NT) k_lu_trsm(double* T, int n, int j0, int nb) {
-  __shared__ double L[TOP_NB][TOP_NB + 1];
-  const int c0 = j0 + nb + blockIdx.x * 64;
-  for (int e = threadIdx.x; e < nb * nb; e += NT) L[e % nb][e / nb] = T[j0 + e % nb + (int64_t)(j0 + e / nb) * n];
-  __syncthreads();
-  const int c = c0 + (threadIdx.x & 63);
-  const int part = threadIdx.x >> 6;  // 4 threads share a column: rows split by 4
-  const bool act = c < n;
-  double* col = T + j0 + (int64_t)(act ? c : 0) * n;
-  for (int j = 0; j < nb; ++j) {
-    if (act) {
-      const double xj = col[j];
-      for (int i = j + 1 + part; i < nb; i += 4) col[i] -= L[i][j] * xj;
-    }
-    // row j + 1 must be final before the next step reads it (uniform barrier)
-    __syncthreads();
-  }
-}
-
-// Inverse columns: X[:, c0:c0+64] = T^-1 I[:, c0:c0+64] with the LU factors.
-__global__ void __launch_bounds__(NT) k_lu_inverse(const double* T, int n, const int32_t* piv, double* X) {
-  const int c0 = blockIdx.x * 64;
-  const int nc = min(64, n - c0);
-  double* B = X + (int64_t)c0 * n;
-  if (n > 0) {
-    WG_FOR2(n, nc, i, c) B[i + (int64_t)c * n] = (i == c0 + c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  wg_getrs(n, T, n, piv, B, n, nc);
 }
 
 // ------------------------------------------------------------------ solve
