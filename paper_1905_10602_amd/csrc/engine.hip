@@ -1419,8 +1419,10 @@ static int colour_phase_a(Handle& h, ColourWork& W, std::string& err) {
     int dmx = 0;
     for (const ElimRec& R : recs)
       if (R.d < h.big_d) dmx = std::max(dmx, R.d);
-    hipLaunchKernelGGL(dmx <= 64 ? k_xsolve<64> : k_xsolve<256>, dim3((unsigned)xtasks.size()), dim3(NT), 0, sa, d_recs,
-                       d_xt);
+    // one row per thread up to order NT (every small pivot with the default
+    // threshold), else the slice in LDS or in place
+    auto kx = dmx <= NT ? k_xsolve_rows : dmx <= 64 ? k_xsolve<64> : k_xsolve<256>;
+    hipLaunchKernelGGL(kx, dim3((unsigned)xtasks.size()), dim3(NT), 0, sa, d_recs, d_xt);
   }
   if (!blu.empty()) {
     const BluTask* d_blu = (const BluTask*)(M + o_blu);

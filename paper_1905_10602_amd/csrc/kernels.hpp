@@ -1101,6 +1101,92 @@ __global__ void __launch_bounds__(NT) k_xsolve(const ElimRec* recs, const XTask*
   }
 }
 
+// The same solve for pivots of order d <= NT with one row per thread: thread i
+// keeps row i of its 32-column slice in registers through both substitutions.
+// The row interchanges become one permutation first (row i of P B is row
+// perm[i] of B); per pivot row j the row goes through LDS to the others, and
+// each thread's multiplier of the next step is loaded during the current one.
+// Every element sees the same operations in the same order as in wg_getrs.
+__global__ void __launch_bounds__(NT) k_xsolve_rows(const ElimRec* recs, const XTask* xt) {
+  __shared__ double rowj[XCOLS];
+  __shared__ int32_t perm[NT], spiv[NT];
+  const XTask t = xt[blockIdx.x];
+  const ElimRec R = recs[t.rec];
+  const int n = R.n, d = R.d, M = R.M, r = R.r;
+  const int nc = min(XCOLS, M + r + n - t.c0);
+  if (d == 0 || nc <= 0) return;
+  const int i = threadIdx.x;
+  const bool own = i < d;
+  const auto LU = gmem(R.lu);
+  if (own) {
+    perm[i] = i;
+    spiv[i] = R.piv[i];
+  }
+  __syncthreads();
+  if (i == 0)
+    for (int j = 0; j < d; ++j) {
+      const int p = spiv[j];
+      if (p != j) {
+        const int a = perm[j];
+        perm[j] = perm[p];
+        perm[p] = a;
+      }
+    }
+  __syncthreads();
+  // row perm[i] of X0 = [[U, 0, I_n], [0, I_r, 0]] in columns c0 .. c0+nc-1
+  const int row = own ? perm[i] : 0;
+  double x[XCOLS];
+#pragma unroll
+  for (int c = 0; c < XCOLS; ++c) {
+    const int col = t.c0 + c;
+    double v = 0.0;
+    if (own && c < nc) {
+      if (col < M) v = row < n ? R.U[row + (int64_t)col * n] : 0.0;
+      else if (col < M + r) v = (row >= n && row - n == col - M) ? 1.0 : 0.0;
+      else v = (row == col - M - r) ? 1.0 : 0.0;
+    }
+    x[c] = v;
+  }
+  // forward: unit lower, x_i -= L[i][j] x_j for i > j
+  double l_next = (own && i > 0) ? LU[i] : 0.0;
+  for (int j = 0; j + 1 < d; ++j) {
+    const double l = l_next;
+    if (i == j)
+#pragma unroll
+      for (int c = 0; c < XCOLS; ++c) rowj[c] = x[c];
+    __syncthreads();
+    l_next = (own && i > j + 1) ? LU[i + (int64_t)(j + 1) * d] : 0.0;
+    if (own && i > j)
+#pragma unroll
+      for (int c = 0; c < XCOLS; ++c) x[c] -= l * rowj[c];
+    __syncthreads();
+  }
+  // backward: upper, x_j /= U[j][j], then x_i -= U[i][j] x_j for i < j
+  double u_next = (own && i < d - 1) ? LU[i + (int64_t)(d - 1) * d] : 0.0;
+  const double dii = own ? LU[i + (int64_t)i * d] : 1.0;  // this row's pivot, loaded ahead
+  for (int j = d - 1; j >= 0; --j) {
+    const double u = u_next;
+    if (i == j) {
+#pragma unroll
+      for (int c = 0; c < XCOLS; ++c) x[c] /= dii;
+#pragma unroll
+      for (int c = 0; c < XCOLS; ++c) rowj[c] = x[c];
+    }
+    __syncthreads();
+    u_next = (own && j > 0 && i < j - 1) ? LU[i + (int64_t)(j - 1) * d] : 0.0;
+    if (own && i < j)
+#pragma unroll
+      for (int c = 0; c < XCOLS; ++c) x[c] -= u * rowj[c];
+    __syncthreads();
+  }
+  if (own) {
+    const auto X = gmem(R.X + (int64_t)t.c0 * d);
+#pragma unroll
+    for (int c = 0; c < XCOLS; ++c)
+      if (c < nc) X[i + (int64_t)c * d] = x[c];
+  }
+}
+
 // ---- large pivots: right-looking blocked LU of the augmented matrix
 // [D | X0] (d x (d + W)), X0 = [[U, 0], [0, I]], pivoting over the columns of
 // D only.  The trailing updates carry L^-1 P X0 along in the X columns; a
